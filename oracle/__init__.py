@@ -1,0 +1,288 @@
+"""FP64 CPU oracle of the registration operator and of the series prefix scan.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline leg of the
+benchmark may use it; the product path never does. It shares no code with the GPU path.
+
+The C source (pprs_oracle.c) is compiled with gcc on first use (or by build()). Arrays cross
+the boundary as C-contiguous float64 NumPy arrays. Frames are nodal grids (2^L+1)^2 and
+displacements are [2, n, n] in domain units ([0,1]^2), unless a function says otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+from dataclasses import dataclass, asdict
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pprs_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+TRACE_W = 8
+SCAN_KINDS = {"sequential": 0, "brent_kung": 1}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, FP64, no fast-math)."""
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math",
+           "-o", tmp, _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if (not os.path.exists(_LIB)) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        D = ctypes.POINTER(ctypes.c_double)
+        I = ctypes.POINTER(ctypes.c_int)
+        P = ctypes.POINTER(_CParams)
+        S = ctypes.POINTER(_CStats)
+        sigs = {
+            "or_restrict": (None, [D, ctypes.c_int, D]),
+            "or_prolong": (None, [D, ctypes.c_int, D]),
+            "or_bilinear": (ctypes.c_double, [D, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                              D, D]),
+            "or_mass_apply": (None, [D, ctypes.c_int, D]),
+            "or_stiff_apply": (None, [D, ctypes.c_int, D]),
+            "or_normalize": (ctypes.c_int, [D, ctypes.c_int, D, D, D]),
+            "or_smooth": (None, [D, ctypes.c_int, ctypes.c_double, D]),
+            "or_energy": (ctypes.c_double, [D, D, ctypes.c_int, D, ctypes.c_double, D]),
+            "or_gradient": (ctypes.c_int, [D, D, ctypes.c_int, D, ctypes.c_double, D]),
+            "or_gradient_flow": (ctypes.c_int, [D, D, ctypes.c_int, D, P, I, I, D, D,
+                                                ctypes.c_int, I]),
+            "or_register": (ctypes.c_int, [D, D, ctypes.c_int, D, P, D, S, D, ctypes.c_int, I]),
+            "or_compose": (None, [D, D, ctypes.c_int, D]),
+            "or_series": (ctypes.c_int, [D, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, D, S,
+                                         S, I, ctypes.c_int]),
+        }
+        for name, (res, args) in sigs.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+        return lib
+
+
+class _CParams(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int), ("lam", ctypes.c_double), ("beta", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("ladder_k", ctypes.c_int), ("cap", ctypes.c_double),
+                ("tau_min_rel", ctypes.c_double), ("eps", ctypes.c_double),
+                ("iter_max", ctypes.c_int)]
+
+
+class _CStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int * 16), ("trials", ctypes.c_int * 16),
+                ("energy", ctypes.c_double), ("ncc", ctypes.c_double), ("flags", ctypes.c_int)]
+
+
+@dataclass
+class Params:
+    """Parameters of operator A. Field meanings follow the C struct in pprs_oracle.c."""
+    levels: int = 2
+    lam: float = 0.1
+    beta: float = 1.0
+    sigma: float = 0.5
+    ladder_k: int = 1
+    cap: float = 1.0
+    tau_min_rel: float = 1e-4
+    eps: float = 1e-7
+    iter_max: int = 500
+
+    def c(self) -> _CParams:
+        return _CParams(**asdict(self))
+
+
+def _d(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ------------------------------------------------------------------------------------------ #
+# Elementary operators
+
+def restrict(f) -> np.ndarray:
+    f = _f64(f)
+    n = f.shape[-1]
+    nc = (n - 1) // 2 + 1
+    out = np.empty((nc, nc))
+    _load().or_restrict(_d(f), n, _d(out))
+    return out
+
+
+def prolong(c) -> np.ndarray:
+    c = _f64(c)
+    nc = c.shape[-1]
+    nf = 2 * (nc - 1) + 1
+    out = np.empty((nf, nf))
+    _load().or_prolong(_d(c), nc, _d(out))
+    return out
+
+
+def bilinear(g, px: float, py: float):
+    g = _f64(g)
+    gx = ctypes.c_double()
+    gy = ctypes.c_double()
+    v = _load().or_bilinear(_d(g), g.shape[-1], px, py, ctypes.byref(gx), ctypes.byref(gy))
+    return v, gx.value, gy.value
+
+
+def mass_apply(f) -> np.ndarray:
+    f = _f64(f)
+    out = np.empty_like(f)
+    _load().or_mass_apply(_d(f), f.shape[-1], _d(out))
+    return out
+
+
+def stiff_apply(f) -> np.ndarray:
+    f = _f64(f)
+    out = np.empty_like(f)
+    _load().or_stiff_apply(_d(f), f.shape[-1], _d(out))
+    return out
+
+
+def normalize(f):
+    """Returns (F~, mean, sigma); F~ is None when sigma == 0."""
+    f = _f64(f)
+    out = np.empty_like(f)
+    m = ctypes.c_double()
+    s = ctypes.c_double()
+    rc = _load().or_normalize(_d(f), f.shape[-1], _d(out), ctypes.byref(m), ctypes.byref(s))
+    return (out if rc == 0 else None), m.value, s.value
+
+
+def smooth(g, beta: float) -> np.ndarray:
+    g = _f64(g)
+    out = np.empty_like(g)
+    _load().or_smooth(_d(g), g.shape[-1], beta, _d(out))
+    return out
+
+
+def energy(R, T, u, lam: float):
+    """Returns (E, NCC) for raw reference R, template T and displacement u [2, n, n]."""
+    R, T, u = _f64(R), _f64(T), _f64(u)
+    ncc = ctypes.c_double()
+    e = _load().or_energy(_d(R), _d(T), R.shape[-1], _d(u), lam, ctypes.byref(ncc))
+    return e, ncc.value
+
+
+def gradient(R, T, u, lam: float) -> np.ndarray:
+    R, T, u = _f64(R), _f64(T), _f64(u)
+    G = np.empty_like(u)
+    rc = _load().or_gradient(_d(R), _d(T), R.shape[-1], _d(u), lam, _d(G))
+    if rc != 0:
+        raise ValueError("constant reference")
+    return G
+
+
+def gradient_flow(R, T, u0, params: Params, trace_cap: int = 4096):
+    """One level of gradient flow. Returns (u, steps, passes, energy, trace[len, 8], flags)."""
+    R, T = _f64(R), _f64(T)
+    u = _f64(u0).copy()
+    steps = ctypes.c_int()
+    passes = ctypes.c_int()
+    e = ctypes.c_double()
+    tr = np.zeros((trace_cap, TRACE_W))
+    tl = ctypes.c_int()
+    cp = params.c()
+    flags = _load().or_gradient_flow(_d(R), _d(T), R.shape[-1], _d(u), ctypes.byref(cp),
+                                     ctypes.byref(steps), ctypes.byref(passes), ctypes.byref(e),
+                                     _d(tr), trace_cap, ctypes.byref(tl))
+    if flags < 0:
+        raise ValueError("constant reference")
+    return u, steps.value, passes.value, e.value, tr[: tl.value], flags
+
+
+@dataclass
+class RegStats:
+    iters: list
+    trials: list
+    energy: float
+    ncc: float
+    flags: int
+
+
+def _stats(st: _CStats, levels: int) -> RegStats:
+    return RegStats(list(st.iters[:levels]), list(st.trials[:levels]), st.energy, st.ncc,
+                    st.flags)
+
+
+def register(R, T, params: Params, u0=None, trace_cap: int = 0):
+    """Operator A on finest-level nodal frames. Returns (u [2,n,n] domain units, RegStats,
+    trace)."""
+    R, T = _f64(R), _f64(T)
+    n = R.shape[-1]
+    u = np.empty((2, n, n))
+    st = _CStats()
+    cp = params.c()
+    tr = np.zeros((max(trace_cap, 1), TRACE_W))
+    tl = ctypes.c_int()
+    u0p = _d(_f64(u0)) if u0 is not None else None
+    keep = _f64(u0) if u0 is not None else None
+    if keep is not None:
+        u0p = _d(keep)
+    rc = _load().or_register(_d(R), _d(T), n, u0p, ctypes.byref(cp), _d(u), ctypes.byref(st),
+                             _d(tr), trace_cap, ctypes.byref(tl))
+    if rc == -1:
+        raise ValueError("constant reference on some level")
+    if rc != 0:
+        raise ValueError("invalid sizes or levels")
+    return u, _stats(st, params.levels), tr[: tl.value]
+
+
+def compose(uij, ujk) -> np.ndarray:
+    uij, ujk = _f64(uij), _f64(ujk)
+    out = np.empty_like(uij)
+    _load().or_compose(_d(uij), _d(ujk), uij.shape[-1], _d(out))
+    return out
+
+
+def series(frames_nodal, params: Params, scan: str = "brent_kung", threads: int = 0):
+    """Series registration as an inclusive scan with operator B.
+
+    frames_nodal: [N, n, n]. Returns (u [N, 2, n, n] domain units with u[0] = 0, a_stats,
+    b_stats, b_pairs [(i, j, k)] in execution order)."""
+    fr = _f64(frames_nodal)
+    N, n = fr.shape[0], fr.shape[-1]
+    u = np.zeros((N, 2, n, n))
+    a_st = (_CStats * max(N - 1, 1))()
+    b_st = (_CStats * max(2 * N, 1))()
+    pairs = np.zeros(3 * max(2 * N, 1), dtype=np.int32)
+    cp = params.c()
+    rc = _load().or_series(_d(fr), N, n, ctypes.byref(cp), SCAN_KINDS[scan], _d(u), a_st, b_st,
+                           pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), threads)
+    if rc < 0:
+        raise ValueError("oracle series failed with %d" % rc)
+    a = [_stats(a_st[m], params.levels) for m in range(N - 1)]
+    b = [_stats(b_st[m], params.levels) for m in range(rc)]
+    return u, a, b, [tuple(pairs[3 * m: 3 * m + 3]) for m in range(rc)]
+
+
+# ------------------------------------------------------------------------------------------ #
+# Pixel frames <-> nodal grids (the API works in pixels of 2^L x 2^L frames)
+
+def frame_to_nodes(frame) -> np.ndarray:
+    """2^L x 2^L pixels -> (2^L+1)^2 nodes by replicating the last row and column."""
+    f = _f64(frame)
+    return np.pad(f, ((0, 1), (0, 1)), mode="edge") if (f.shape[-1] & (f.shape[-1] - 1)) == 0 \
+        else f
+
+
+def u_to_pixels(u_dom, side: int) -> np.ndarray:
+    """Domain-unit displacement on (side+1)^2 nodes -> pixels on side x side."""
+    return np.asarray(u_dom)[..., :side, :side] * side

@@ -1,0 +1,772 @@
+/*
+ * FP64 CPU oracle of the multilevel gradient-flow registration operator and of the series
+ * prefix scan (Copik 2017, "Image registration" and "Prefix sum" chapters).
+ *
+ * TEST INFRASTRUCTURE ONLY. It is plain, slow and written to be checked against the paper by
+ * eye: every step follows the formula it implements, with no blocking, fusion or reordering.
+ * Only the test suite, the smoke check and the CPU-baseline leg of the benchmark may load it;
+ * the product path never calls it and shares no code with it.
+ *
+ * Grids (Multilevel section): level l has n = 2^l + 1 nodes per axis, spacing h = 1/(n-1),
+ * node (a, b) (row a, column b) at the point (x, y) = (b h, a h) of the unit square. Nodal
+ * arrays are row-major [a][b]. A displacement u = phi - id is stored as two planes (x then y)
+ * in domain units.
+ *
+ * Readings taken where the paper is silent or garbled (each one is listed in the design notes):
+ *  - restriction at the border: the full-weighting stencil truncated to in-range nodes and
+ *    renormalised;
+ *  - prolongation: the standard vertex-centred bilinear rule (the figure caption says bilinear;
+ *    the printed case table is garbled);
+ *  - sampling outside the domain: clamp (replicate), derivative of the clamped function;
+ *  - mass matrix: the consistent Q1 matrix M = M1 (x) M1; stiffness K = K1 (x) M1 + M1 (x) K1;
+ *  - metric of the gradient flow: A = S1 (x) S1 with S1 = M1 + (beta h)^2 K1;
+ *  - Armijo rule: Phi(tau) <= Phi(0) + sigma tau Phi'(0) with Phi'(0) = -G.d, evaluated on a
+ *    ladder of 2K+1 step sizes top * 2^-j, j = 0..2K, top = min(2^K tau_prev, tau_max),
+ *    tau_max = cap h / max|d|; the largest passing step is taken; if none passes the ladder
+ *    moves 2K+1 halvings down; below tau_min_rel * tau_max the level stops;
+ *  - stopping: E_k - E_{k+1} < eps, or iter_max accepted steps, or a failed line search, or
+ *    G.d <= 0.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+  int levels;          /* number of grid levels m1 - m0 + 1 */
+  double lambda;       /* Dirichlet weight */
+  double beta;         /* smoother width in cells */
+  double sigma;        /* Armijo constant */
+  int ladder_k;        /* K: 2K+1 step sizes per line-search pass */
+  double cap;          /* largest step, in cells of the current level */
+  double tau_min_rel;  /* line search gives up below tau_min_rel * tau_max */
+  double eps;          /* energy-decrease stopping threshold */
+  int iter_max;        /* accepted steps per level */
+} or_params;
+
+#define OR_MAX_LEVELS 16
+typedef struct {
+  int iters[OR_MAX_LEVELS];   /* accepted steps per level, index 0 = coarsest */
+  int trials[OR_MAX_LEVELS];  /* line-search passes per level */
+  double energy;              /* final energy at the finest level */
+  double ncc;                 /* final NCC at the finest level */
+  int flags;                  /* OR_FLAG_* */
+} or_stats;
+
+enum { OR_FLAG_NONCONV = 1, OR_FLAG_NAN = 2 };
+#define OR_TRACE_W 8
+
+/* ----------------------------------------------------------------------------------------- */
+/* Restriction and prolongation (Multilevel section)                                           */
+
+static double fw_weight(int p) { return p == 0 ? 2.0 : 1.0; }
+
+/* Full weighting 1/16 [1 2 1; 2 4 2; 1 2 1]; coarse node (A, B) sits on fine node (2A, 2B). */
+void or_restrict(const double* f, int nf, double* g) {
+  int nc = (nf - 1) / 2 + 1;
+  for (int A = 0; A < nc; ++A)
+    for (int B = 0; B < nc; ++B) {
+      double s = 0.0, w = 0.0;
+      for (int p = -1; p <= 1; ++p)
+        for (int q = -1; q <= 1; ++q) {
+          int a = 2 * A + p, b = 2 * B + q;
+          if (a < 0 || a >= nf || b < 0 || b >= nf) continue;
+          double wt = fw_weight(p) * fw_weight(q);
+          s += wt * f[a * nf + b];
+          w += wt;
+        }
+      g[A * nc + B] = s / w;
+    }
+}
+
+/* Bilinear prolongation: copy coarse nodes, average 2 neighbours on edges, 4 on cell centres. */
+void or_prolong(const double* c, int nc, double* f) {
+  int nf = 2 * (nc - 1) + 1;
+  for (int a = 0; a < nf; ++a)
+    for (int b = 0; b < nf; ++b) {
+      int A = a / 2, B = b / 2;
+      double v;
+      if (a % 2 == 0 && b % 2 == 0) v = c[A * nc + B];
+      else if (a % 2 == 0) v = 0.5 * (c[A * nc + B] + c[A * nc + B + 1]);
+      else if (b % 2 == 0) v = 0.5 * (c[A * nc + B] + c[(A + 1) * nc + B]);
+      else v = 0.25 * (c[A * nc + B] + c[A * nc + B + 1] + c[(A + 1) * nc + B] +
+                       c[(A + 1) * nc + B + 1]);
+      f[a * nf + b] = v;
+    }
+}
+
+/* ----------------------------------------------------------------------------------------- */
+/* Clamped bilinear evaluation of a nodal function and its gradient at a point (domain units). */
+
+double or_bilinear(const double* g, int n, double px, double py, double* gx, double* gy) {
+  double h = 1.0 / (n - 1);
+  double s = px / h, t = py / h;
+  int outx = (s < 0.0 || s > n - 1), outy = (t < 0.0 || t > n - 1);
+  if (s < 0.0) s = 0.0;
+  if (s > n - 1) s = n - 1;
+  if (t < 0.0) t = 0.0;
+  if (t > n - 1) t = n - 1;
+  int b0 = (int)floor(s), a0 = (int)floor(t);
+  if (b0 > n - 2) b0 = n - 2;
+  if (a0 > n - 2) a0 = n - 2;
+  double fx = s - b0, fy = t - a0;
+  double v00 = g[a0 * n + b0], v01 = g[a0 * n + b0 + 1];
+  double v10 = g[(a0 + 1) * n + b0], v11 = g[(a0 + 1) * n + b0 + 1];
+  if (gx) *gx = outx ? 0.0 : ((1.0 - fy) * (v01 - v00) + fy * (v11 - v10)) / h;
+  if (gy) *gy = outy ? 0.0 : ((1.0 - fx) * (v10 - v00) + fx * (v11 - v01)) / h;
+  return (1.0 - fy) * ((1.0 - fx) * v00 + fx * v01) + fy * ((1.0 - fx) * v10 + fx * v11);
+}
+
+/* ----------------------------------------------------------------------------------------- */
+/* FE matrices (Spatial discretization section).                                              */
+/* A symmetric tridiagonal 1-D matrix with end diagonal de, interior diagonal di, off-diagonal  */
+/* o, applied along one axis of a 2-D nodal array (axis 0: along x within rows; 1: along y).    */
+
+static void tri_apply(const double* f, double* g, int n, int axis, double de, double di,
+                      double o) {
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      int i = axis == 0 ? b : a;
+      int st = axis == 0 ? 1 : n;
+      int idx = a * n + b;
+      double d = (i == 0 || i == n - 1) ? de : di;
+      double v = d * f[idx];
+      if (i > 0) v += o * f[idx - st];
+      if (i < n - 1) v += o * f[idx + st];
+      g[idx] = v;
+    }
+}
+
+/* 1-D P1 mass matrix M1 = (h/6) tridiag(1, [2 4 ... 4 2], 1). */
+static void m1_apply(const double* f, double* g, int n, int axis) {
+  double h = 1.0 / (n - 1);
+  tri_apply(f, g, n, axis, h / 3.0, 2.0 * h / 3.0, h / 6.0);
+}
+/* 1-D P1 stiffness matrix K1 = (1/h) tridiag(-1, [1 2 ... 2 1], -1). */
+static void k1_apply(const double* f, double* g, int n, int axis) {
+  double h = 1.0 / (n - 1);
+  tri_apply(f, g, n, axis, 1.0 / h, 2.0 / h, -1.0 / h);
+}
+
+/* M F with M = M1 (x) M1 (bilinear mass matrix). */
+void or_mass_apply(const double* f, int n, double* out) {
+  double* t = malloc(sizeof(double) * n * n);
+  m1_apply(f, t, n, 0);
+  m1_apply(t, out, n, 1);
+  free(t);
+}
+
+/* K F with K = K1 (x) M1 + M1 (x) K1 (bilinear stiffness matrix, int |grad f|^2 = F^T K F). */
+void or_stiff_apply(const double* f, int n, double* out) {
+  size_t nn = (size_t)n * n;
+  double* t1 = malloc(sizeof(double) * nn);
+  double* t2 = malloc(sizeof(double) * nn);
+  m1_apply(f, t1, n, 0);
+  k1_apply(t1, out, n, 1);  /* derivative across rows (y), mass along x */
+  k1_apply(f, t1, n, 0);
+  m1_apply(t1, t2, n, 1);   /* derivative along x, mass across rows */
+  for (size_t i = 0; i < nn; ++i) out[i] += t2[i];
+  free(t1);
+  free(t2);
+}
+
+static double dot(const double* a, const double* b, size_t n) {
+  double s = 0.0;
+  for (size_t i = 0; i < n; ++i) s += a[i] * b[i];
+  return s;
+}
+
+/* Mean 1^T M F and standard deviation sqrt(F_c^T M F_c), F_c = F - mean (|Omega| = 1).
+   Writes the normalised F~ = F_c / sigma when out != NULL and sigma > 0.
+   Returns -1 if sigma == 0 (sigma <= 1e-12 max(1, |mean|) counts as 0). */
+int or_normalize(const double* f, int n, double* out, double* mean, double* sigma) {
+  size_t nn = (size_t)n * n;
+  double* mf = malloc(sizeof(double) * nn);
+  double* fc = malloc(sizeof(double) * nn);
+  or_mass_apply(f, n, mf);
+  double m = 0.0;
+  for (size_t i = 0; i < nn; ++i) m += mf[i];  /* 1^T M F */
+  for (size_t i = 0; i < nn; ++i) fc[i] = f[i] - m;
+  or_mass_apply(fc, n, mf);
+  double var = dot(fc, mf, nn);
+  double s = var > 0.0 ? sqrt(var) : 0.0;
+  /* a frame counts as constant when sigma is at rounding level relative to its mean */
+  if (s <= 1e-12 * fmax(1.0, fabs(m))) s = 0.0;
+  if (mean) *mean = m;
+  if (sigma) *sigma = s;
+  if (out && s > 0.0)
+    for (size_t i = 0; i < nn; ++i) out[i] = fc[i] / s;
+  free(mf);
+  free(fc);
+  return s > 0.0 ? 0 : -1;
+}
+
+/* ----------------------------------------------------------------------------------------- */
+/* Energy and gradient (NCC + Dirichlet energy, E[phi] and its first variation).               */
+/* The similarity integrals are evaluated with the 2x2 Gauss rule on every element, the rule   */
+/* that integrates the Q1 mass matrix exactly (so for Q1 integrands they equal the F^T M G     */
+/* forms). The template is composed with phi at the quadrature points:                          */
+/*   q = element point, u(q) = sum_corners psi(q) u_corner, T_phi(q) = T(q + u(q)),             */
+/*   mean = sum_q w T_phi(q), sigma^2 = sum_q w (T_phi(q) - mean)^2,                            */
+/*   NCC = sum_q w R~(q) (T_phi(q) - mean) / sigma, w = h^2 / 4.                                 */
+
+typedef struct {
+  int n;
+  const double* Rn;  /* normalised reference R~ (nodal) */
+  const double* T;   /* template (nodal) */
+} level_data;
+
+static const double GP[2] = {0.21132486540518711775, 0.78867513459481288225};  /* (1 -+ 1/sqrt3)/2 */
+
+/* Quadrature point (element (a, b), local point (p, q)) -> flat index. */
+static size_t qidx(int n, int a, int b, int p, int q) {
+  return ((((size_t)a * (n - 1) + b) * 2 + p) * 2 + q);
+}
+
+/* Bilinear basis weights of the 4 element corners at local point (xi, eta):
+   corners ordered (a,b), (a,b+1), (a+1,b), (a+1,b+1). */
+static void basis(double xi, double eta, double psi[4]) {
+  psi[0] = (1.0 - xi) * (1.0 - eta);
+  psi[1] = xi * (1.0 - eta);
+  psi[2] = (1.0 - xi) * eta;
+  psi[3] = xi * eta;
+}
+
+/* Sample T_phi, its gradient and R~ at every quadrature point. */
+static void warp_q(const level_data* L, const double* u, double* Tq, double* dTx, double* dTy,
+                   double* Rq) {
+  int n = L->n;
+  double h = 1.0 / (n - 1);
+  size_t nn = (size_t)n * n;
+  for (int a = 0; a < n - 1; ++a)
+    for (int b = 0; b < n - 1; ++b) {
+      size_t c[4] = {(size_t)a * n + b, (size_t)a * n + b + 1, (size_t)(a + 1) * n + b,
+                     (size_t)(a + 1) * n + b + 1};
+      for (int p = 0; p < 2; ++p)
+        for (int q = 0; q < 2; ++q) {
+          double psi[4];
+          basis(GP[q], GP[p], psi);
+          double ux = 0.0, uy = 0.0, r = 0.0;
+          for (int k = 0; k < 4; ++k) {
+            ux += psi[k] * u[c[k]];
+            uy += psi[k] * u[nn + c[k]];
+            r += psi[k] * L->Rn[c[k]];
+          }
+          double px = (b + GP[q]) * h + ux, py = (a + GP[p]) * h + uy;
+          double gx, gy;
+          size_t qi = qidx(n, a, b, p, q);
+          Tq[qi] = or_bilinear(L->T, n, px, py, &gx, &gy);
+          if (dTx) dTx[qi] = gx;
+          if (dTy) dTy[qi] = gy;
+          if (Rq) Rq[qi] = r;
+        }
+    }
+}
+
+/* Mean, sigma and NCC of the sampled template against R~ (all by the quadrature rule).
+   Returns sigma (0 when the warped template is constant; NCC is then 0). */
+static double ncc_q(int n, const double* Tq, const double* Rq, double* mean, double* ncc) {
+  double h = 1.0 / (n - 1);
+  double w = h * h / 4.0;
+  size_t nq = (size_t)4 * (n - 1) * (n - 1);
+  double m = 0.0;
+  for (size_t i = 0; i < nq; ++i) m += w * Tq[i];
+  double var = 0.0;
+  for (size_t i = 0; i < nq; ++i) var += w * (Tq[i] - m) * (Tq[i] - m);
+  double s = var > 0.0 ? sqrt(var) : 0.0;
+  double c = 0.0;
+  if (s > 0.0)
+    for (size_t i = 0; i < nq; ++i) c += w * Rq[i] * (Tq[i] - m) / s;
+  *mean = m;
+  *ncc = c;
+  return s;
+}
+
+static double regulariser(const double* u, int n) {
+  size_t nn = (size_t)n * n;
+  double* Ku = malloc(sizeof(double) * nn);
+  double reg = 0.0;
+  for (int c = 0; c < 2; ++c) {
+    or_stiff_apply(u + c * nn, n, Ku);
+    reg += dot(u + c * nn, Ku, nn);
+  }
+  free(Ku);
+  return reg;
+}
+
+/* E(u) = -NCC[R, T o phi] + (lambda/2) sum_c u_c^T K u_c. */
+static double energy_level(const level_data* L, const double* u, double lambda, double* ncc_out) {
+  int n = L->n;
+  size_t nq = (size_t)4 * (n - 1) * (n - 1);
+  double* Tq = malloc(sizeof(double) * nq);
+  double* Rq = malloc(sizeof(double) * nq);
+  warp_q(L, u, Tq, NULL, NULL, Rq);
+  double m, ncc;
+  ncc_q(n, Tq, Rq, &m, &ncc);
+  free(Tq);
+  free(Rq);
+  if (ncc_out) *ncc_out = ncc;
+  return -ncc + 0.5 * lambda * regulariser(u, n);
+}
+
+/* dE/du_i = -sum_q w (R~(q) - NCC T~_phi(q)) / sigma * grad T(q + u(q)) psi_i(q)
+             + lambda (K u)_i, summed over the quadrature points of the elements around i. */
+static void gradient_level(const level_data* L, const double* u, double lambda, double* G) {
+  int n = L->n;
+  double h = 1.0 / (n - 1);
+  double w = h * h / 4.0;
+  size_t nn = (size_t)n * n;
+  size_t nq = (size_t)4 * (n - 1) * (n - 1);
+  double* Tq = malloc(sizeof(double) * nq);
+  double* dTx = malloc(sizeof(double) * nq);
+  double* dTy = malloc(sizeof(double) * nq);
+  double* Rq = malloc(sizeof(double) * nq);
+  double* Ku = malloc(sizeof(double) * nn);
+  warp_q(L, u, Tq, dTx, dTy, Rq);
+  double m, ncc;
+  double s = ncc_q(n, Tq, Rq, &m, &ncc);
+  memset(G, 0, sizeof(double) * 2 * nn);
+  if (s > 0.0) {
+    for (int a = 0; a < n - 1; ++a)
+      for (int b = 0; b < n - 1; ++b) {
+        size_t c[4] = {(size_t)a * n + b, (size_t)a * n + b + 1, (size_t)(a + 1) * n + b,
+                       (size_t)(a + 1) * n + b + 1};
+        for (int p = 0; p < 2; ++p)
+          for (int q = 0; q < 2; ++q) {
+            size_t qi = qidx(n, a, b, p, q);
+            double f = -w * (Rq[qi] - ncc * (Tq[qi] - m) / s) / s;  /* d(-NCC)/dT_phi(q) */
+            double psi[4];
+            basis(GP[q], GP[p], psi);
+            for (int k = 0; k < 4; ++k) {
+              G[c[k]] += f * dTx[qi] * psi[k];
+              G[nn + c[k]] += f * dTy[qi] * psi[k];
+            }
+          }
+      }
+  }
+  for (int cc = 0; cc < 2; ++cc) {
+    or_stiff_apply(u + cc * nn, n, Ku);
+    for (size_t i = 0; i < nn; ++i) G[cc * nn + i] += lambda * Ku[i];
+  }
+  free(Tq);
+  free(dTx);
+  free(dTy);
+  free(Rq);
+  free(Ku);
+}
+
+/* ----------------------------------------------------------------------------------------- */
+/* Metric of the gradient flow: d = A^{-1} G, A = S1 (x) S1, S1 = M1 + (beta h)^2 K1.          */
+
+/* Thomas algorithm for a symmetric tridiagonal system along one line of a 2-D array. */
+static void thomas_line(double* x, int n, size_t stride, double de, double di, double o,
+                        double* cp, double* dp) {
+  for (int i = 0; i < n; ++i) {
+    double d = (i == 0 || i == n - 1) ? de : di;
+    double rhs = x[i * stride];
+    if (i == 0) {
+      cp[0] = o / d;
+      dp[0] = rhs / d;
+    } else {
+      double den = d - o * cp[i - 1];
+      cp[i] = o / den;
+      dp[i] = (rhs - o * dp[i - 1]) / den;
+    }
+  }
+  x[(n - 1) * stride] = dp[n - 1];
+  for (int i = n - 2; i >= 0; --i) x[i * stride] = dp[i] - cp[i] * x[(i + 1) * stride];
+}
+
+void or_smooth(const double* g, int n, double beta, double* out) {
+  double h = 1.0 / (n - 1);
+  double c = beta * beta * h * h;
+  double de = h / 3.0 + c / h, di = 2.0 * h / 3.0 + 2.0 * c / h, o = h / 6.0 - c / h;
+  double* cp = malloc(sizeof(double) * n);
+  double* dp = malloc(sizeof(double) * n);
+  memcpy(out, g, sizeof(double) * n * n);
+  for (int b = 0; b < n; ++b) thomas_line(out + b, n, n, de, di, o, cp, dp);  /* along y */
+  for (int a = 0; a < n; ++a) thomas_line(out + (size_t)a * n, n, 1, de, di, o, cp, dp); /* x */
+  free(cp);
+  free(dp);
+}
+
+/* ----------------------------------------------------------------------------------------- */
+/* Public energy / gradient on raw frames (normalises the reference itself).                  */
+
+double or_energy(const double* R, const double* T, int n, const double* u, double lambda,
+                 double* ncc) {
+  size_t nn = (size_t)n * n;
+  double* Rn = malloc(sizeof(double) * nn);
+  if (or_normalize(R, n, Rn, NULL, NULL) != 0) {
+    free(Rn);
+    return NAN;
+  }
+  level_data L = {n, Rn, T};
+  double e = energy_level(&L, u, lambda, ncc);
+  free(Rn);
+  return e;
+}
+
+int or_gradient(const double* R, const double* T, int n, const double* u, double lambda,
+                double* G) {
+  size_t nn = (size_t)n * n;
+  double* Rn = malloc(sizeof(double) * nn);
+  if (or_normalize(R, n, Rn, NULL, NULL) != 0) {
+    free(Rn);
+    return -1;
+  }
+  level_data L = {n, Rn, T};
+  gradient_level(&L, u, lambda, G);
+  free(Rn);
+  return 0;
+}
+
+/* ----------------------------------------------------------------------------------------- */
+/* Gradient flow on one level: forward Euler steps u <- u - tau A^{-1} E'(u) with the Armijo  */
+/* ladder described in the header. Returns the number of accepted steps; writes trace records  */
+/* [level, step, tau, E_before, E_after, G.d, tau_max, passes] when trace != NULL.             */
+
+typedef struct {
+  double* buf;
+  int cap;
+  int len;
+} trace_t;
+
+static void trace_put(trace_t* tr, int level, int step, double tau, double e0, double e1,
+                      double gtd, double tmax, int passes) {
+  if (!tr || !tr->buf || tr->len >= tr->cap) return;
+  double* r = tr->buf + (size_t)tr->len * OR_TRACE_W;
+  r[0] = level;
+  r[1] = step;
+  r[2] = tau;
+  r[3] = e0;
+  r[4] = e1;
+  r[5] = gtd;
+  r[6] = tmax;
+  r[7] = passes;
+  tr->len++;
+}
+
+static int gradient_flow(const level_data* L, double* u, const or_params* p, int level,
+                         int* trials, int* flags, double* e_out, double* ncc_out,
+                         trace_t* tr) {
+  int n = L->n;
+  size_t nn = (size_t)n * n;
+  double h = 1.0 / (n - 1);
+  double* G = malloc(sizeof(double) * 2 * nn);
+  double* d = malloc(sizeof(double) * 2 * nn);
+  double* ut = malloc(sizeof(double) * 2 * nn);
+  int K = p->ladder_k;
+  double ncc;
+  double E = energy_level(L, u, p->lambda, &ncc);
+  double tau_prev = INFINITY;
+  int steps = 0, passes_total = 0;
+  if (!isfinite(E)) *flags |= OR_FLAG_NAN;
+  while (isfinite(E) && steps < p->iter_max) {
+    gradient_level(L, u, p->lambda, G);
+    or_smooth(G, n, p->beta, d);
+    or_smooth(G + nn, n, p->beta, d + nn);
+    double gtd = dot(G, d, 2 * nn);
+    double dmax = 0.0;
+    for (size_t i = 0; i < 2 * nn; ++i) dmax = fmax(dmax, fabs(d[i]));
+    if (!(gtd > 0.0) || !(dmax > 0.0)) break;           /* stationary */
+    double tau_max = p->cap * h / dmax;
+    double top = fmin(ldexp(tau_prev, K), tau_max);
+    double tau_acc = 0.0, e_acc = E, ncc_acc = ncc;
+    int passes = 0;
+    while (top >= p->tau_min_rel * tau_max) {
+      passes++;
+      for (int j = 0; j <= 2 * K; ++j) {                  /* largest step first */
+        double tau = ldexp(top, -j);
+        for (size_t i = 0; i < 2 * nn; ++i) ut[i] = u[i] - tau * d[i];
+        double nc;
+        double e = energy_level(L, ut, p->lambda, &nc);
+        if (e <= E - p->sigma * tau * gtd) {              /* Armijo, sufficient decrease */
+          tau_acc = tau;
+          e_acc = e;
+          ncc_acc = nc;
+          break;
+        }
+      }
+      if (tau_acc > 0.0) break;
+      top = ldexp(top, -(2 * K + 1));
+    }
+    passes_total += passes;
+    trace_put(tr, level, steps, tau_acc, E, e_acc, gtd, tau_max, passes);
+    if (tau_acc == 0.0) break;                            /* line search exhausted */
+    for (size_t i = 0; i < 2 * nn; ++i) u[i] -= tau_acc * d[i];
+    double dec = E - e_acc;
+    E = e_acc;
+    ncc = ncc_acc;
+    tau_prev = tau_acc;
+    steps++;
+    if (dec < p->eps) break;                              /* converged */
+    if (steps >= p->iter_max) *flags |= OR_FLAG_NONCONV;
+  }
+  if (trials) *trials = passes_total;
+  if (e_out) *e_out = E;
+  if (ncc_out) *ncc_out = ncc;
+  free(G);
+  free(d);
+  free(ut);
+  return steps;
+}
+
+/* One level of gradient flow on raw frames (normalises the reference). */
+int or_gradient_flow(const double* R, const double* T, int n, double* u, const or_params* p,
+                     int* steps, int* passes, double* energy, double* trace, int trace_cap,
+                     int* trace_len) {
+  size_t nn = (size_t)n * n;
+  double* Rn = malloc(sizeof(double) * nn);
+  if (or_normalize(R, n, Rn, NULL, NULL) != 0) {
+    free(Rn);
+    return -1;
+  }
+  level_data L = {n, Rn, T};
+  trace_t tr = {trace, trace_cap, 0};
+  int flags = 0;
+  int s = gradient_flow(&L, u, p, 0, passes, &flags, energy, NULL, &tr);
+  if (steps) *steps = s;
+  if (trace_len) *trace_len = tr.len;
+  free(Rn);
+  return flags;
+}
+
+/* ----------------------------------------------------------------------------------------- */
+/* Function A: multilevel gradient flow (Algorithm "multigrid_gradient").                      */
+/* R, T are finest-level nodal frames (nf = 2^L + 1); u0 (finest, domain units) may be NULL    */
+/* for the identity; u_out receives the finest-level displacement. Returns 0, or -1 when the  */
+/* reference is constant on some level, or -2 on bad sizes.                                     */
+
+static int log2_exact(int m) {
+  int l = 0;
+  while ((1 << l) < m) ++l;
+  return (1 << l) == m ? l : -1;
+}
+
+int or_register(const double* R, const double* T, int nf, const double* u0, const or_params* p,
+                double* u_out, or_stats* st, double* trace, int trace_cap, int* trace_len) {
+  int L = log2_exact(nf - 1);
+  if (L < 1 || p->levels < 1 || p->levels > L || p->levels > OR_MAX_LEVELS) return -2;
+  int m0 = L - p->levels + 1;
+  double* Rl[OR_MAX_LEVELS + 1];
+  double* Tl[OR_MAX_LEVELS + 1];
+  double* Rn[OR_MAX_LEVELS + 1];
+  int rc = 0;
+  for (int l = L; l >= m0; --l) {
+    int n = (1 << l) + 1;
+    size_t nn = (size_t)n * n;
+    Rl[l] = malloc(sizeof(double) * nn);
+    Tl[l] = malloc(sizeof(double) * nn);
+    Rn[l] = malloc(sizeof(double) * nn);
+    if (l == L) {
+      memcpy(Rl[l], R, sizeof(double) * nn);
+      memcpy(Tl[l], T, sizeof(double) * nn);
+    } else {
+      or_restrict(Rl[l + 1], (1 << (l + 1)) + 1, Rl[l]);
+      or_restrict(Tl[l + 1], (1 << (l + 1)) + 1, Tl[l]);
+    }
+    if (or_normalize(Rl[l], n, Rn[l], NULL, NULL) != 0) rc = -1;
+  }
+  if (rc != 0) goto done;
+  {
+    /* Initial guess on the coarsest level: restrict u0 down to m0 (identity if NULL). */
+    int n0 = (1 << m0) + 1;
+    double* u = calloc((size_t)2 * n0 * n0, sizeof(double));
+    if (u0) {
+      int n = nf;
+      double* cur = malloc(sizeof(double) * 2 * nf * nf);
+      memcpy(cur, u0, sizeof(double) * 2 * nf * nf);
+      for (int l = L; l > m0; --l) {
+        int nc = (1 << (l - 1)) + 1;
+        double* nxt = malloc(sizeof(double) * 2 * nc * nc);
+        for (int c = 0; c < 2; ++c)
+          or_restrict(cur + (size_t)c * n * n, n, nxt + (size_t)c * nc * nc);
+        free(cur);
+        cur = nxt;
+        n = nc;
+      }
+      memcpy(u, cur, sizeof(double) * 2 * n0 * n0);
+      free(cur);
+    }
+    trace_t tr = {trace, trace_cap, 0};
+    if (st) memset(st, 0, sizeof(*st));
+    int flags = 0;
+    double e = 0.0, ncc = 0.0;
+    for (int l = m0; l <= L; ++l) {
+      int n = (1 << l) + 1;
+      level_data LD = {n, Rn[l], Tl[l]};
+      int passes = 0;
+      int steps = gradient_flow(&LD, u, p, l, &passes, &flags, &e, &ncc, &tr);
+      if (st) {
+        st->iters[l - m0] = steps;
+        st->trials[l - m0] = passes;
+      }
+      if (l < L) {
+        int nn2 = (1 << (l + 1)) + 1;
+        double* uf = malloc(sizeof(double) * 2 * nn2 * nn2);
+        for (int c = 0; c < 2; ++c)
+          or_prolong(u + (size_t)c * n * n, n, uf + (size_t)c * nn2 * nn2);
+        free(u);
+        u = uf;
+      }
+    }
+    memcpy(u_out, u, sizeof(double) * 2 * nf * nf);
+    free(u);
+    if (st) {
+      st->energy = e;
+      st->ncc = ncc;
+      st->flags = flags;
+    }
+    if (trace_len) *trace_len = tr.len;
+  }
+done:
+  for (int l = L; l >= m0; --l) {
+    free(Rl[l]);
+    free(Tl[l]);
+    free(Rn[l]);
+  }
+  return rc;
+}
+
+/* ----------------------------------------------------------------------------------------- */
+/* Composition (Registration for series of images): (phi_jk o phi_ij)(x) = phi_jk(phi_ij(x)),  */
+/* i.e. w(x) = u_ij(x) + u_jk(x + u_ij(x)), bilinear and clamped. out may alias u_ij.          */
+
+void or_compose(const double* uij, const double* ujk, int n, double* out) {
+  double h = 1.0 / (n - 1);
+  size_t nn = (size_t)n * n;
+  double* w = malloc(sizeof(double) * 2 * nn);
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      size_t i = (size_t)a * n + b;
+      double px = b * h + uij[i], py = a * h + uij[nn + i];
+      w[i] = uij[i] + or_bilinear(ujk, n, px, py, NULL, NULL);
+      w[nn + i] = uij[nn + i] + or_bilinear(ujk + nn, n, px, py, NULL, NULL);
+    }
+  memcpy(out, w, sizeof(double) * 2 * nn);
+  free(w);
+}
+
+/* ----------------------------------------------------------------------------------------- */
+/* Series registration as an inclusive prefix scan with operator B (def. of image series       */
+/* registration; eq. of the prefix sum with B).                                                */
+/* Elements x_m = (m, m+1, A(f_m, f_{m+1}, id)), m = 0..N-2; y_m = x_0 (.) ... (.) x_m.        */
+/* (i, j, u) (.) (j, k, v) = (i, k, A(f_i, f_k, v o u)).                                         */
+
+enum { OR_SCAN_SEQUENTIAL = 0, OR_SCAN_BRENT_KUNG = 1 };
+
+typedef struct {
+  int i, k;
+  double* u;
+} elem_t;
+
+typedef struct {
+  const double* frames;
+  int nf;
+  const or_params* p;
+  or_stats* op_stats;  /* per op, in execution order; may be NULL */
+  int* op_pairs;       /* (i, j, k) per op in execution order; may be NULL */
+  int n_ops;
+  int err;
+} series_ctx;
+
+static void apply_b(series_ctx* S, const elem_t* left, elem_t* right, int op_index) {
+  size_t nn = (size_t)S->nf * S->nf;
+  if (left->k != right->i) {
+    S->err = -4;
+    return;
+  }
+  double* w = malloc(sizeof(double) * 2 * nn);
+  or_compose(left->u, right->u, S->nf, w);
+  or_stats st;
+  int rc = or_register(S->frames + (size_t)left->i * nn, S->frames + (size_t)right->k * nn,
+                       S->nf, w, S->p, right->u, &st, NULL, 0, NULL);
+  if (rc != 0) S->err = rc;
+  if (S->op_stats) S->op_stats[op_index] = st;
+  if (S->op_pairs) {
+    S->op_pairs[3 * op_index] = left->i;
+    S->op_pairs[3 * op_index + 1] = left->k;
+    S->op_pairs[3 * op_index + 2] = right->k;
+  }
+  right->i = left->i;
+  free(w);
+}
+
+/* frames: N finest-level nodal frames; u_out: N x 2 x nf x nf, u_out[0] = 0.
+   a_stats: N-1 entries (may be NULL); b_stats / b_pairs: up to 2N entries (may be NULL).
+   Returns the number of B ops, or a negative error. */
+int or_series(const double* frames, int N, int nf, const or_params* p, int scan,
+              double* u_out, or_stats* a_stats, or_stats* b_stats, int* b_pairs,
+              int threads) {
+  if (N < 1) return -1;
+  size_t nn = (size_t)nf * nf;
+  memset(u_out, 0, sizeof(double) * 2 * nn);
+  int M = N - 1;
+  if (M == 0) return 0;
+  elem_t* x = malloc(sizeof(elem_t) * M);
+  int err = 0;
+#ifdef _OPENMP
+  if (threads > 0) omp_set_num_threads(threads);
+#else
+  (void)threads;
+#endif
+  for (int m = 0; m < M; ++m) {
+    x[m].i = m;
+    x[m].k = m + 1;
+    x[m].u = u_out + (size_t)(m + 1) * 2 * nn;
+  }
+  /* Preprocessing: neighbour registrations are independent. */
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int m = 0; m < M; ++m) {
+    or_stats st;
+    int rc = or_register(frames + (size_t)m * nn, frames + (size_t)(m + 1) * nn, nf, NULL, p,
+                         x[m].u, &st, NULL, 0, NULL);
+    if (rc != 0) err = rc;
+    if (a_stats) a_stats[m] = st;
+  }
+  if (err) {
+    free(x);
+    return err;
+  }
+  series_ctx S = {frames, nf, p, b_stats, b_pairs, 0, 0};
+  int ops = 0;
+  if (scan == OR_SCAN_SEQUENTIAL) {
+    /* y_0 = x_0, y_m = y_{m-1} (.) x_m */
+    for (int m = 1; m < M; ++m) apply_b(&S, &x[m - 1], &x[m], ops++);
+  } else if (scan == OR_SCAN_BRENT_KUNG) {
+    /* Up-sweep: x_j <- x_{j-d} (.) x_j for j = 2d-1, 4d-1, ... */
+    for (int d = 1; d < M; d *= 2) {
+      int cnt = 0;
+      for (int j = 2 * d - 1; j < M; j += 2 * d) ++cnt;
+#pragma omp parallel for schedule(dynamic, 1)
+      for (int q = 0; q < cnt; ++q) {
+        int j = 2 * d - 1 + q * 2 * d;
+        apply_b(&S, &x[j - d], &x[j], ops + q);
+      }
+      ops += cnt;
+    }
+    /* Down-sweep: x_j <- x_{j-d} (.) x_j for j = 3d-1, 5d-1, ..., d halving to 1. */
+    int dtop = 1;
+    while (dtop * 2 < M) dtop *= 2;
+    for (int d = dtop; d >= 1; d /= 2) {
+      int cnt = 0;
+      for (int j = 3 * d - 1; j < M; j += 2 * d) ++cnt;
+#pragma omp parallel for schedule(dynamic, 1)
+      for (int q = 0; q < cnt; ++q) {
+        int j = 3 * d - 1 + q * 2 * d;
+        apply_b(&S, &x[j - d], &x[j], ops + q);
+      }
+      ops += cnt;
+    }
+  } else {
+    free(x);
+    return -1;
+  }
+  for (int m = 0; m < M; ++m)
+    if (x[m].i != 0 || x[m].k != m + 1) S.err = -4;
+  free(x);
+  return S.err ? S.err : ops;
+}

@@ -1,0 +1,416 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix (no GPU).
+
+Every test checks the oracle against something other than itself: closed-form integrals,
+library routines (scipy's bilinear interpolation with edge replication, dense numpy solves,
+numerically integrated hat functions), invariants (NCC bounds, Armijo decrease, monotone
+energy), values printed in the paper (tests/golden/paper_values.json) and the analytic ground
+truth of the synthetic generator.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import oracle as O
+from synth import SeriesSpec, ground_truth, make_series
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+GP = np.array([(1 - 1 / np.sqrt(3)) / 2, (1 + 1 / np.sqrt(3)) / 2])
+
+
+def grid(n):
+    x = np.linspace(0.0, 1.0, n)
+    X, Y = np.meshgrid(x, x)  # X varies along columns (x), Y along rows (y)
+    return X, Y
+
+
+# ------------------------------------------------------------------------------------------
+# Restriction / prolongation (Multilevel section)
+
+@pytest.mark.parametrize("n", [5, 9, 17, 33])
+def test_restriction_constants_and_affine_interior(n):
+    X, Y = grid(n)
+    c = np.full((n, n), 3.25)
+    assert np.allclose(O.restrict(c), 3.25, atol=1e-14)
+    f = 0.7 * X - 1.3 * Y + 0.2
+    r = O.restrict(f)
+    Xc, Yc = grid((n - 1) // 2 + 1)
+    assert np.abs(r - (0.7 * Xc - 1.3 * Yc + 0.2))[1:-1, 1:-1].max() < 1e-13
+
+
+def test_restriction_interior_matches_library_correlation():
+    rng = np.random.default_rng(1)
+    f = rng.normal(size=(17, 17))
+    k = np.outer([1, 2, 1], [1, 2, 1]) / 16.0
+    full = ndimage.correlate(f, k, mode="constant")
+    ref = full[::2, ::2]
+    assert np.abs(O.restrict(f) - ref)[1:-1, 1:-1].max() < 1e-13
+
+
+@pytest.mark.parametrize("nc", [3, 5, 9, 17])
+def test_prolongation_exact_for_affine_and_inverse_of_restriction(nc):
+    Xc, Yc = grid(nc)
+    nf = 2 * (nc - 1) + 1
+    Xf, Yf = grid(nf)
+    f = -0.4 * Xc + 2.1 * Yc + 0.5
+    p = O.prolong(f)
+    assert np.abs(p - (-0.4 * Xf + 2.1 * Yf + 0.5)).max() < 1e-13
+    assert np.abs(O.restrict(p) - f)[1:-1, 1:-1].max() < 1e-13
+
+
+def test_prolongation_matches_library_bilinear_zoom():
+    rng = np.random.default_rng(2)
+    c = rng.normal(size=(9, 9))
+    ref = ndimage.zoom(c, (17 - 1) / (9 - 1) + 1e-12, order=1, grid_mode=False)
+    ref = ndimage.map_coordinates(c, np.mgrid[0:17, 0:17] / 2.0, order=1)
+    assert np.abs(O.prolong(c) - ref).max() < 1e-13
+
+
+# ------------------------------------------------------------------------------------------
+# Clamped bilinear evaluation
+
+def test_bilinear_affine_exact_and_nodes_and_clamp():
+    n = 9
+    X, Y = grid(n)
+    g = 1.5 * X - 0.25 * Y + 0.125
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        px, py = rng.uniform(0, 1, 2)
+        v, gx, gy = O.bilinear(g, px, py)
+        assert abs(v - (1.5 * px - 0.25 * py + 0.125)) < 1e-13
+        assert abs(gx - 1.5) < 1e-12 and abs(gy + 0.25) < 1e-12
+    h = 1.0 / (n - 1)
+    f = rng.normal(size=(n, n))
+    for a in range(n):
+        for b in range(n):
+            assert O.bilinear(f, b * h, a * h)[0] == f[a, b]
+    # outside the domain: replicated value, zero derivative across the violated axis
+    v, gx, gy = O.bilinear(g, 1.7, 0.5)
+    assert abs(v - (1.5 - 0.125 + 0.125)) < 1e-13 and gx == 0.0 and abs(gy + 0.25) < 1e-12
+    v, gx, gy = O.bilinear(g, 0.5, -0.3)
+    assert abs(v - (0.75 + 0.125)) < 1e-13 and gy == 0.0
+
+
+def test_bilinear_matches_library_with_edge_replication():
+    rng = np.random.default_rng(4)
+    n = 17
+    f = rng.normal(size=(n, n))
+    pts = rng.uniform(-0.2, 1.2, size=(200, 2))
+    h = 1.0 / (n - 1)
+    ref = ndimage.map_coordinates(f, [np.clip(pts[:, 1] / h, 0, n - 1),
+                                      np.clip(pts[:, 0] / h, 0, n - 1)], order=1, mode="nearest")
+    got = np.array([O.bilinear(f, px, py)[0] for px, py in pts])
+    assert np.abs(got - ref).max() < 1e-12
+
+
+# ------------------------------------------------------------------------------------------
+# FE matrices (Spatial discretization section)
+
+def _hat_matrices_1d(n):
+    """M1, K1 by numerical integration of the 1-D hat functions (5-point Gauss per cell)."""
+    h = 1.0 / (n - 1)
+    xg, wg = np.polynomial.legendre.leggauss(5)
+    M = np.zeros((n, n))
+    K = np.zeros((n, n))
+    for c in range(n - 1):
+        x = c * h + (xg + 1) / 2 * h
+        w = wg / 2 * h
+        phi = {c: 1 - (x - c * h) / h, c + 1: (x - c * h) / h}
+        dphi = {c: -1 / h, c + 1: 1 / h}
+        for i in phi:
+            for j in phi:
+                M[i, j] += np.sum(w * phi[i] * phi[j])
+                K[i, j] += np.sum(w * dphi[i] * dphi[j])
+    return M, K
+
+
+@pytest.mark.parametrize("n", [3, 5, 9])
+def test_mass_and_stiffness_match_integrated_basis(n):
+    M1, K1 = _hat_matrices_1d(n)
+    M = np.kron(M1, M1)
+    K = np.kron(K1, M1) + np.kron(M1, K1)
+    rng = np.random.default_rng(5)
+    f = rng.normal(size=(n, n))
+    assert np.abs(O.mass_apply(f).ravel() - M @ f.ravel()).max() < 1e-13
+    assert np.abs(O.stiff_apply(f).ravel() - K @ f.ravel()).max() < 1e-12
+
+
+def test_fe_integrals_closed_forms():
+    n = 17
+    X, Y = grid(n)
+    one = np.ones((n, n))
+    assert abs(O.mass_apply(one).sum() - 1.0) < 1e-14           # |Omega| = 1
+    assert abs((O.mass_apply(X) * one).sum() - 0.5) < 1e-14     # int x = 1/2
+    xy = X * Y
+    assert abs((xy * O.mass_apply(xy)).sum() - 1.0 / 9.0) < 1e-14  # int (xy)^2 = 1/9
+    u = 2.0 * X + 3.0 * Y
+    assert abs((u * O.stiff_apply(u)).sum() - 13.0) < 1e-11     # int |grad u|^2
+    assert abs((xy * O.stiff_apply(xy)).sum() - 2.0 / 3.0) < 1e-12
+    assert np.abs(O.stiff_apply(one)).max() < 1e-11             # constants have no energy
+
+
+# ------------------------------------------------------------------------------------------
+# Normalisation, NCC, energy
+
+def _frames(side=16, seed=7, drift=1.0, noise=0.0):
+    s = make_series(SeriesSpec(2, side, drift, 0.0, noise, seed))
+    return s, O.frame_to_nodes(s.frames[0]), O.frame_to_nodes(s.frames[1])
+
+
+def _energy_numpy(R, T, u, lam):
+    """Independent quadrature energy with scipy's bilinear interpolation (edge replication)."""
+    n = R.shape[0]
+    h = 1.0 / (n - 1)
+    Rn, m, sg = O.normalize(R)
+    a, b, p, q = np.meshgrid(np.arange(n - 1), np.arange(n - 1), [0, 1], [0, 1], indexing="ij")
+    rows = a + GP[p]
+    cols = b + GP[q]
+    ux = ndimage.map_coordinates(u[0], [rows, cols], order=1)
+    uy = ndimage.map_coordinates(u[1], [rows, cols], order=1)
+    rq = ndimage.map_coordinates(Rn, [rows, cols], order=1)
+    tr = np.clip(rows + uy / h, 0, n - 1)
+    tc = np.clip(cols + ux / h, 0, n - 1)
+    tq = ndimage.map_coordinates(T, [tr, tc], order=1, mode="nearest")
+    w = h * h / 4
+    mean = w * tq.sum()
+    sig = np.sqrt(w * ((tq - mean) ** 2).sum())
+    ncc = w * (rq * (tq - mean)).sum() / sig
+    M1, K1 = _hat_matrices_1d(n)
+    K = np.kron(K1, M1) + np.kron(M1, K1)
+    reg = sum(u[c].ravel() @ K @ u[c].ravel() for c in range(2))
+    return -ncc + 0.5 * lam * reg, ncc
+
+
+def test_energy_matches_independent_quadrature():
+    _, R, T = _frames()
+    n = R.shape[0]
+    rng = np.random.default_rng(8)
+    for trial in range(3):
+        u = rng.normal(0, 1.5 / (n - 1), size=(2, n, n))
+        e, ncc = O.energy(R, T, u, 0.37)
+        e2, ncc2 = _energy_numpy(R, T, u, 0.37)
+        assert abs(ncc - ncc2) < 1e-12 and abs(e - e2) < 1e-11
+
+
+def test_ncc_invariants_and_bounds():
+    _, R, T = _frames()
+    n = R.shape[0]
+    z = np.zeros((2, n, n))
+    assert abs(O.energy(R, R, z, 1.0)[1] - 1.0) < 1e-13            # perfect match
+    assert abs(O.energy(R, 3.0 * R + 7.0, z, 1.0)[1] - 1.0) < 1e-13
+    assert abs(O.energy(R, -2.0 * R + 1.0, z, 1.0)[1] + 1.0) < 1e-13  # sign(a)
+    rng = np.random.default_rng(9)
+    for _ in range(5):
+        u = rng.normal(0, 2.0 / (n - 1), size=(2, n, n))
+        ncc = O.energy(R, T, u, 0.0)[1]
+        assert GOLD["ncc_bounds"]["min"] <= ncc <= GOLD["ncc_bounds"]["max"]
+    # at u = 0 the 2x2 Gauss rule is exact for Q1 x Q1: NCC = R~^T M T~ (mass-matrix form)
+    M1, _ = _hat_matrices_1d(n)
+    M = np.kron(M1, M1)
+    Rn = O.normalize(R)[0].ravel()
+    Tn = O.normalize(T)[0].ravel()
+    assert abs(O.energy(R, T, z, 0.0)[1] - Rn @ M @ Tn) < 1e-13
+    # constant displacements carry no Dirichlet energy
+    e0 = O.energy(R, T, np.full((2, n, n), 0.013), 5.0)
+    e1 = O.energy(R, T, np.full((2, n, n), 0.013), 0.0)
+    assert abs(e0[0] - e1[0]) < 1e-13
+
+
+def _rectangle(n, cx, sigma_px=1.5):
+    """Smoothed 0.5 x 0.5 rectangle with its lower-left corner at (cx, 0.25)."""
+    X, Y = grid(n)
+    side = n - 1
+    inside = ((X >= cx) & (X <= cx + 0.5) & (Y >= 0.25) & (Y <= 0.75)).astype(float)
+    return ndimage.gaussian_filter(inside, sigma_px, mode="nearest")
+
+
+def test_rectangle_worked_example_sign_convention():
+    """f1(x + G) = f0(x) with G = (0.25, 0) for the centred / right-shifted rectangle."""
+    ex = GOLD["rectangle_example"]
+    n = 65
+    f0 = _rectangle(n, ex["lower_left_f0"][0])
+    f1 = _rectangle(n, ex["lower_left_f1"][0])
+    G = np.array(ex["G"])
+    up = np.stack([np.full((n, n), G[0]), np.full((n, n), G[1])])
+    e_plus, ncc_plus = O.energy(f0, f1, up, 1.0)
+    e_minus, _ = O.energy(f0, f1, -up, 1.0)
+    assert e_plus < e_minus
+    # along the x-translation line the energy is lowest at +G (sign convention f1(x+G) = f0(x));
+    # the rectangle of f1 touches the right border, so the clamped sample is not a perfect match
+    ts = np.linspace(-0.4, 0.4, 65)
+    es = [O.energy(f0, f1, np.stack([np.full((n, n), t), np.zeros((n, n))]), 1.0)[0] for t in ts]
+    assert abs(ts[int(np.argmin(es))] - G[0]) <= 1.0 / (n - 1) + 1e-12
+    u, st, _ = O.register(f0, f1, O.Params(levels=4, lam=10.0, eps=1e-6))
+    X, Y = grid(n)
+    inside = (X >= 0.3) & (X <= 0.7) & (Y >= 0.3) & (Y <= 0.7)
+    # registering from the identity finds +G inside the rectangle (within 2 of its 16 px; the
+    # rectangle of f1 touches the border, where clamped sampling pulls the field)
+    assert abs(u[0][inside].mean() - G[0]) < 2.0 / (n - 1)
+    assert abs(u[1][inside].mean() - G[1]) < 2.0 / (n - 1)
+
+
+# ------------------------------------------------------------------------------------------
+# Gradient and metric
+
+def test_gradient_matches_central_differences():
+    _, R, T = _frames(side=16, seed=3)
+    n = R.shape[0]
+    rng = np.random.default_rng(0)
+    u = rng.normal(0, 0.3 / (n - 1), size=(2, n, n))
+    lam = 0.7
+    G = O.gradient(R, T, u, lam)
+    fd = np.zeros_like(u)
+    eps = 1e-7
+    for c in range(2):
+        for i in range(n):
+            for j in range(n):
+                up = u.copy()
+                up[c, i, j] += eps
+                um = u.copy()
+                um[c, i, j] -= eps
+                fd[c, i, j] = (O.energy(R, T, up, lam)[0] - O.energy(R, T, um, lam)[0]) / (2 * eps)
+    assert np.abs(G - fd).max() < 1e-6 * np.abs(G).max()
+
+
+@pytest.mark.parametrize("n,beta", [(5, 0.0), (9, 1.0), (9, 3.0)])
+def test_metric_solve_matches_dense(n, beta):
+    M1, K1 = _hat_matrices_1d(n)
+    h = 1.0 / (n - 1)
+    S1 = M1 + (beta * h) ** 2 * K1
+    A = np.kron(S1, S1)
+    rng = np.random.default_rng(11)
+    g = rng.normal(size=(n, n))
+    d = O.smooth(g, beta)
+    assert np.abs(d.ravel() - np.linalg.solve(A, g.ravel())).max() < 1e-10 * np.abs(d).max()
+    assert g.ravel() @ d.ravel() > 0
+
+
+# ------------------------------------------------------------------------------------------
+# Gradient flow and operator A
+
+def test_armijo_and_monotone_energy_trace():
+    s, R, T = _frames(side=32, seed=5, drift=1.5, noise=20.0)
+    p = O.Params(levels=2, lam=10.0, eps=1e-6)
+    _, st, tr = O.register(R, T, p, trace_cap=4000)
+    assert len(tr) > 3
+    sigma = GOLD["armijo_sigma"]["value"]
+    for level, step, tau, e0, e1, gtd, tmax, passes in tr:
+        if tau > 0:
+            assert e1 <= e0 - sigma * tau * gtd + 1e-15        # sufficient decrease
+            assert tau <= tmax * (1 + 1e-12)
+        else:
+            assert e1 == e0
+    # energy never increases within a level
+    for lv in np.unique(tr[:, 0]):
+        t = tr[tr[:, 0] == lv]
+        assert np.all(np.diff(np.concatenate([t[:1, 3], t[:, 4]])) <= 1e-15)
+
+
+def test_identical_frames_give_identity():
+    _, R, _ = _frames(side=32, seed=6, noise=20.0)
+    u, st, _ = O.register(R, R, O.Params(levels=3))
+    assert np.all(u == 0.0)
+
+
+@pytest.mark.parametrize("seed", [100, 101, 102])
+def test_known_translation_recovered(seed):
+    spec = SeriesSpec(2, 64, 1.5, 0.0, 0.0, seed)
+    s = make_series(spec)
+    u, st, _ = O.register(O.frame_to_nodes(s.frames[0]), O.frame_to_nodes(s.frames[1]),
+                          O.Params(levels=3, lam=10.0, eps=3e-4))
+    gt = ground_truth(s, 1)
+    err = O.u_to_pixels(u, 64) - gt
+    b = 8
+    assert np.sqrt((err[:, b:-b, b:-b] ** 2).mean()) < 0.05
+
+
+@pytest.mark.parametrize("seed", [200, 201])
+def test_smooth_nonrigid_field_recovered(seed):
+    spec = SeriesSpec(2, 128, 1.0, 1.0, 0.0, seed)
+    s = make_series(spec)
+    u, st, _ = O.register(O.frame_to_nodes(s.frames[0]), O.frame_to_nodes(s.frames[1]),
+                          O.Params(levels=3, lam=1.0, eps=1e-6))
+    gt = ground_truth(s, 1)
+    err = O.u_to_pixels(u, 128) - gt
+    b = int(np.abs(gt).max() + 3 * 1.5 + 2)
+    assert np.sqrt((err[:, b:-b, b:-b] ** 2).mean()) < 0.05
+
+
+def test_constant_reference_rejected():
+    n = 17
+    with pytest.raises(ValueError):
+        O.register(np.ones((n, n)), np.random.default_rng(0).normal(size=(n, n)), O.Params(levels=2))
+
+
+# ------------------------------------------------------------------------------------------
+# Composition
+
+def test_composition_identity_constants_affine():
+    n = 17
+    X, Y = grid(n)
+    rng = np.random.default_rng(12)
+    u = rng.normal(0, 0.01, size=(2, n, n))
+    z = np.zeros((2, n, n))
+    assert np.array_equal(O.compose(u, z), u)
+    assert np.abs(O.compose(z, u) - u).max() < 1e-15
+    a = np.stack([np.full((n, n), 0.03), np.full((n, n), -0.02)])
+    b = np.stack([np.full((n, n), -0.01), np.full((n, n), 0.05)])
+    assert np.abs(O.compose(a, b) - (a + b)).max() < 1e-15
+    # affine o affine: u1 = A1 x + c1, u2 = A2 x + c2 -> w = u1 + A2 (x + u1) + c2
+    A1 = np.array([[0.01, -0.02], [0.015, 0.005]])
+    A2 = np.array([[-0.01, 0.02], [0.01, 0.01]])
+    c1 = np.array([0.02, 0.01])
+    c2 = np.array([-0.01, 0.03])
+    P = np.stack([X, Y])
+    u1 = np.einsum("ij,jab->iab", A1, P) + c1[:, None, None]
+    u2 = np.einsum("ij,jab->iab", A2, P) + c2[:, None, None]
+    w = u1 + np.einsum("ij,jab->iab", A2, P + u1) + c2[:, None, None]
+    got = O.compose(u1, u2)
+    q = P + u1
+    inside = (q[0] >= 0) & (q[0] <= 1) & (q[1] >= 0) & (q[1] <= 1)
+    assert np.abs(got - w)[:, inside].max() < 1e-14
+
+
+# ------------------------------------------------------------------------------------------
+# Series registration (scan with operator B)
+
+def test_series_identical_frames_all_zero():
+    s = make_series(SeriesSpec(1, 32, 0.0, 0.0, 20.0, 13))
+    fr = np.stack([O.frame_to_nodes(s.frames[0])] * 5)
+    for scan in ("sequential", "brent_kung"):
+        u, a, b, pairs = O.series(fr, O.Params(levels=2), scan=scan)
+        assert np.all(u == 0.0)
+
+
+@pytest.mark.parametrize("M,ops", [(8, 11), (7, 8), (1, 0), (2, 1), (5, 5), (16, 26)])
+def test_series_bk_schedule_counts_and_pairs(M, ops):
+    """Brent-Kung over M elements: 2M - log2(M) - 2 ops for M a power of two (table), and every
+    op combines (i, j) with (j, k)."""
+    s = make_series(SeriesSpec(M + 1, 16, 0.5, 0.0, 0.0, 14))
+    fr = np.stack([O.frame_to_nodes(f) for f in s.frames])
+    u, a, b, pairs = O.series(fr, O.Params(levels=1, iter_max=0), scan="brent_kung")
+    assert len(pairs) == ops
+    if M == 8:
+        assert ops == GOLD["scan_figures_N8"]["brent_kung"]["ops"]
+    for i, j, k in pairs:
+        assert i < j < k
+
+
+def test_series_translation_chain_and_bk_vs_sequential():
+    spec = SeriesSpec(6, 64, 1.0, 0.0, 0.0, 15)
+    s = make_series(spec)
+    fr = np.stack([O.frame_to_nodes(f) for f in s.frames])
+    p = O.Params(levels=3, lam=10.0, eps=3e-4)
+    useq, _, _, _ = O.series(fr, p, scan="sequential")
+    ubk, _, _, _ = O.series(fr, p, scan="brent_kung")
+    b = 8
+    for k in range(1, 6):
+        gt = ground_truth(s, k)
+        e = O.u_to_pixels(useq[k], 64) - gt
+        assert np.sqrt((e[:, b:-b, b:-b] ** 2).mean()) < 0.1
+        d = O.u_to_pixels(ubk[k] - useq[k], 64)
+        # approximate associativity (definition in the associativity section)
+        assert np.sqrt((d[:, b:-b, b:-b] ** 2).mean()) < 0.05
+    assert np.all(useq[0] == 0) and np.all(ubk[0] == 0)
