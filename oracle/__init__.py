@@ -66,6 +66,7 @@ def _load():
             "or_compose": (None, [D, D, ctypes.c_int, D]),
             "or_series": (ctypes.c_int, [D, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, D, S,
                                          S, I, ctypes.c_int]),
+            "or_set_u_storage_f32": (None, [ctypes.c_int]),
         }
         for name, (res, args) in sigs.items():
             fn = getattr(lib, name)
@@ -243,6 +244,11 @@ def register(R, T, params: Params, u0=None, trace_cap: int = 0):
     if rc != 0:
         raise ValueError("invalid sizes or levels")
     return u, _stats(st, params.levels), tr[: tl.value]
+
+
+def set_u_storage_f32(on: bool) -> None:
+    """Test switch: round the displacement to FP32 after every accepted step (process-wide)."""
+    _load().or_set_u_storage_f32(1 if on else 0)
 
 
 def compose(uij, ujk) -> np.ndarray:

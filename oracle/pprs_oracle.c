@@ -428,6 +428,12 @@ int or_gradient(const double* R, const double* T, int n, const double* u, double
 /* ladder described in the header. Returns the number of accepted steps; writes trace records  */
 /* [level, step, tau, E_before, E_after, G.d, tau_max, passes] when trace != NULL.             */
 
+/* Test switch: round u to FP32 after every accepted step (off by default). It measures how
+   far FP32 storage of the displacement alone moves the result, which bounds the agreement any
+   FP32 implementation can reach with this FP64 oracle. */
+static int g_u_storage_f32 = 0;
+void or_set_u_storage_f32(int on) { g_u_storage_f32 = on != 0; }
+
 typedef struct {
   double* buf;
   int cap;
@@ -497,6 +503,8 @@ static int gradient_flow(const level_data* L, double* u, const or_params* p, int
     trace_put(tr, level, steps, tau_acc, E, e_acc, gtd, tau_max, passes);
     if (tau_acc == 0.0) break;                            /* line search exhausted */
     for (size_t i = 0; i < 2 * nn; ++i) u[i] -= tau_acc * d[i];
+    if (g_u_storage_f32)
+      for (size_t i = 0; i < 2 * nn; ++i) u[i] = (double)(float)u[i];
     double dec = E - e_acc;
     E = e_acc;
     ncc = ncc_acc;
