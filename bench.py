@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Benchmark: series registration (512 frames of 512 x 512, 4 levels, Brent-Kung scan) on one
+MI355X. A step is one complete series registration: frame pyramids, the N-1 neighbour
+registrations and every B application of the scan, with the frames already in HBM.
+
+Prints one JSON line: registrations/s (A + B applications per second), the series time, the
+roofline of the dominant kernel (algorithmic bytes / HIP-event time of its launches in the
+timed steps) and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "frame-pair registrations/s and series scan time (512², N=512), warm vs cold"
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    "c3": dict(name="512 frames of 512x512, drift<=8 px, non-rigid<=1.5 px, 5 counts; "
+                    "4 levels; Brent-Kung scan; cold start",
+               spec=("c3",)),
+    "c2": dict(name="64 frames of 256x256, drift<=4 px, non-rigid<=1 px, 10 counts; "
+                    "3 levels; Brent-Kung scan; cold start", spec=("c2",)),
+    "c1": dict(name="8 frames of 64x64, drift<=2 px, 20 counts; 2 levels; sequential scan",
+               spec=("c1",)),
+}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def traffic_from_profiles(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, when it
+    was taken for the current kernel source (its recorded source hash matches)."""
+    path = os.path.join(ROOT, "profiles", "counters_%s.json" % kernel)
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        import hashlib
+        src = open(os.path.join(ROOT, "paper_1712_02533_amd", "csrc", "kernels.hip"), "rb").read()
+        if rec.get("kernels_hip_sha256") != hashlib.sha256(src).hexdigest():
+            return None
+        return rec.get("hbm_bytes_per_launch")
+    except Exception:
+        return None
+
+
+def cpu_baseline(series, cfg, n_ops, threads):
+    """The FP64 oracle on `n_ops` neighbour registrations of the same series, run on `threads`
+    host threads (one registration per thread at a time)."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle as O
+    import paper_1712_02533_amd as P
+    gp = P.Params(levels=cfg["levels"], scan=cfg["scan"])
+    op = O.Params(levels=gp.levels, lam=gp.lam, beta=gp.beta, sigma=gp.armijo_sigma,
+                  ladder_k=gp.ladder_k, cap=gp.step_cap, tau_min_rel=gp.tau_min_rel, eps=gp.eps,
+                  iter_max=gp.iter_max)
+    frames = series.frames
+    n_ops = min(n_ops, len(frames) - 1)
+
+    def one(m):
+        O.register(O.frame_to_nodes(frames[m]), O.frame_to_nodes(frames[m + 1]), op)
+
+    O._load()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(one, range(n_ops)))
+    dt = time.perf_counter() - t0
+    return dict(value=n_ops / dt, unit="registrations/s", cores=threads, kind="oracle",
+                sample="%d neighbour registrations (frames m, m+1 for m < %d) of the same "
+                       "series, FP64, %d threads, %.1f s" % (n_ops, n_ops, threads, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--frames", type=int, default=0, help="override the series length")
+    ap.add_argument("--cpu-ops", type=int, default=0, help="oracle sample size (0 = auto)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1712_02533_amd as P
+    from synth import CONFIGS, make_series
+    from dataclasses import replace
+
+    cfg = CONFIGS[args.config]
+    spec = cfg["spec"]
+    if args.frames:
+        spec = replace(spec, n_frames=args.frames)
+    nthreads = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    series = make_series(spec, workers=nthreads)
+    log("generated %d frames of %dx%d in %.1f s" % (spec.n_frames, spec.side, spec.side,
+                                                     time.perf_counter() - t0))
+    dev = torch.device("cuda", 0)
+    frames = torch.tensor(series.frames, device=dev)
+    out = torch.empty((spec.n_frames, 2, spec.side, spec.side), device=dev)
+    params = P.Params(levels=cfg["levels"], scan=cfg["scan"])
+    for w in range(args.warmup):
+        _, st, _ = P.prefix_register_series(frames, params=params, out=out)
+        log("warmup %d: %.1f ms, %d A + %d B ops" % (w, st.ms_total, st.n_ops_a, st.n_ops_b))
+    timing = not args.no_timing
+    P.set_kernel_timing(timing, dev)
+    P.kernel_timing(reset=True, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(args.steps):
+        _, st, _ = P.prefix_register_series(frames, params=params, out=out)
+        stats.append(st)
+        log("step %d: %.1f ms (prepare %.1f, preprocess %.1f, scan %.1f), flags %d" %
+            (k, st.ms_total, st.ms_prepare, st.ms_preprocess, st.ms_scan, st.flags_or))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kt = P.kernel_timing(reset=True, device=dev)
+    P.set_kernel_timing(False, dev)
+    regs = sum(s.n_ops_a + s.n_ops_b for s in stats)
+    value = regs / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    roofline = None
+    kernels = {}
+    if timing:
+        for name, (ms, launches, byts) in kt.items():
+            if launches:
+                kernels[name] = dict(ms=round(ms, 3), launches=launches,
+                                     gbs=round(byts / (ms * 1e-3) / 1e9, 1) if ms > 0 else None)
+        cand = {k: v for k, v in kt.items() if v[2] > 0}
+        dom = max(cand, key=lambda k: cand[k][0])
+        ms, launches, byts = kt[dom]
+        achieved = byts / (ms * 1e-3) / 1e9
+        tr = traffic_from_profiles(dom)
+        roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                        unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                        traffic=tr, launches=launches, avg_launch_us=round(1e3 * ms / launches, 2),
+                        bytes_per_launch=byts / launches)
+    result = dict(
+        metric=METRIC, value=round(value, 3), unit="registrations/s", n_gpus=1,
+        steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_per_step, 1),
+        higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+        data="synthetic",
+        config=dict(workload=WORKLOADS[args.config]["name"], frames=spec.n_frames,
+                    side=spec.side, levels=cfg["levels"], scan=cfg["scan"], start="cold",
+                    registrations_per_step=stats[0].n_ops_a + stats[0].n_ops_b),
+        series_scan_s=round(ms_per_step / 1e3, 3),
+        roofline=roofline, kernels=kernels,
+        node_steps=stats[0].node_steps, node_passes=stats[0].node_passes,
+    )
+    if not args.no_cpu:
+        ops = args.cpu_ops or max(4, nthreads)
+        log("cpu baseline: oracle on %d registrations, %d threads" % (ops, nthreads))
+        result["cpu_baseline"] = cpu_baseline(series, cfg, ops, nthreads)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,148 @@
+/*
+ * pprs — prefix-scan registration of micrograph series on AMD Instinct MI355X (gfx950).
+ *
+ * The method (Copik 2017): every frame f_i of a series is aligned to f_0 by an inclusive
+ * prefix scan whose binary operator is a pairwise non-rigid registration. Function A (end of
+ * the "Image registration for electron microscopy" section) registers a template to a
+ * reference by a multilevel gradient flow on -NCC + Dirichlet energy; function B (section
+ * "Registration for series of images") composes two deformations and refines the composition
+ * with A; the series registration (definition "Image series registration") runs A on all
+ * neighbour pairs, then scans them with B (section "Prefix sum for registration problem").
+ *
+ * Conventions shared by every entry point:
+ *  - Frames are float32, row-major [H][W], with H == W and either H == 2^L (pixels; the grid
+ *    gets one replicated row and column) or H == 2^L + 1 (grid nodes). 2 <= L <= 11.
+ *  - A displacement u = phi - id is float32 [2][H][W]: plane 0 is the x (column) component,
+ *    plane 1 the y (row) component, in pixels of the finest level. phi maps reference
+ *    coordinates to template coordinates: template(x + u(x)) ~ reference(x).
+ *  - Unless a comment says "host", pointers are device pointers in the context's device
+ *    memory. The caller owns every array it passes; the library never frees them.
+ *  - Calls are ordered on the context's stream and return after the work has completed.
+ *  - No call throws; each returns a pprs_status. pprs_last_error() describes the last
+ *    non-OK status of the calling thread.
+ *  - A context is not thread-safe: calls on one context must not overlap.
+ */
+#ifndef PPRS_H
+#define PPRS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PPRS_OK = 0,
+  PPRS_NOT_CONVERGED = 1, /* warning: some level hit iter_max; the result is valid */
+  PPRS_EINVAL = -1,       /* bad size, null pointer, bad parameter, constant reference */
+  PPRS_ENOMEM = -2,       /* device allocation failed */
+  PPRS_EHIP = -3,         /* a HIP runtime call failed */
+  PPRS_EINDEX = -4,       /* scan operands do not share their middle frame */
+  PPRS_ESTATE = -5,       /* context used after a fatal error, or wrong device */
+  PPRS_ENAN = -6          /* a registration produced a non-finite energy */
+} pprs_status;
+
+enum { PPRS_SCAN_SEQUENTIAL = 0, PPRS_SCAN_BRENT_KUNG = 1 };
+
+enum { PPRS_FLAG_NONCONV = 1, PPRS_FLAG_NAN = 2 };
+
+#define PPRS_MAX_LEVELS 16
+
+/* Parameters of operator A. The paper leaves lambda, the metric, the line-search details,
+   eps and iter_max to the user; pprs_default_params() fills the values this library uses. */
+typedef struct {
+  int levels;           /* number of grid levels m1 - m0 + 1 (multilevel section); 1..L */
+  double lambda;        /* weight of the Dirichlet regulariser (energy E[phi]) */
+  double beta;          /* metric A = S1 (x) S1, S1 = M1 + (beta h)^2 K1 (gradient flow) */
+  double armijo_sigma;  /* Armijo constant, 0 < sigma < 1 (the paper uses 0.5) */
+  int ladder_k;         /* one line-search pass tries 2K+1 steps top * 2^-j, j = 0..2K */
+  double step_cap;      /* tau_max = step_cap * h / max|d| (largest step in cells) */
+  double tau_min_rel;   /* line search gives up when top < tau_min_rel * tau_max */
+  double eps;           /* stop a level when E_k - E_{k+1} < eps (stopping criteria) */
+  int iter_max;         /* accepted steps per level (stopping criteria) */
+  int scan;             /* PPRS_SCAN_* schedule of the series step */
+} pprs_params;
+
+/* Statistics of one A or B application. Level index 0 is the coarsest level. */
+typedef struct {
+  int iters[PPRS_MAX_LEVELS];   /* accepted gradient-flow steps per level */
+  int passes[PPRS_MAX_LEVELS];  /* line-search passes per level */
+  double energy;                /* final energy at the finest level */
+  double ncc;                   /* final NCC at the finest level */
+  int flags;                    /* PPRS_FLAG_* */
+} pprs_pair_stats;
+
+typedef struct {
+  int n_ops_a;            /* neighbour registrations (preprocessing) */
+  int n_ops_b;            /* B applications of the scan */
+  int n_scan_levels;      /* batches of mutually independent B applications */
+  int flags_or;           /* OR of all pair flags */
+  double ms_total;        /* wall time of the call on the device (ms) */
+  double ms_prepare;      /* frame pyramids and normalisation */
+  double ms_preprocess;   /* the N-1 neighbour registrations */
+  double ms_scan;         /* all B applications */
+  long long node_steps;   /* sum over ops and levels of accepted steps x grid nodes */
+  long long node_passes;  /* sum over ops and levels of line-search passes x grid nodes */
+} pprs_series_stats;
+
+typedef struct pprs_ctx pprs_ctx;
+
+/* Fills *p with the library defaults (levels = 4, scan = Brent-Kung). Host pointer. */
+void pprs_default_params(pprs_params* p);
+
+/* Creates a context on HIP device `device`. `stream` is a hipStream_t to order work on, or
+   NULL for a stream the context creates and owns. The context allocates its device workspace
+   lazily and keeps it until pprs_destroy. */
+pprs_status pprs_create(pprs_ctx** ctx, int device, void* stream);
+void pprs_destroy(pprs_ctx* ctx);
+
+/* Thread-local description of the last non-OK status; never NULL. */
+const char* pprs_last_error(void);
+
+/* Function A: registers f_tmpl to f_ref (reference f_i, template f_k: f_k o phi ~ f_i).
+   f_ref, f_tmpl: [H][W]. u_init: [2][H][W] initial guess (NULL = identity); it is restricted
+   to the coarsest level only, as the multilevel algorithm prescribes. u_out: [2][H][W].
+   stats: host pointer, may be NULL. Returns PPRS_NOT_CONVERGED when some level hit iter_max,
+   PPRS_EINVAL when the reference is constant on some level. */
+pprs_status pprs_register_pair(pprs_ctx* ctx, const float* f_ref, const float* f_tmpl, int H,
+                               int W, const float* u_init, float* u_out,
+                               const pprs_params* params, pprs_pair_stats* stats);
+
+/* Composition of deformations (section "Registration for series of images"):
+   (phi_jk o phi_ij)(x) = phi_jk(phi_ij(x)), i.e. u_ik(x) = u_ij(x) + u_jk(x + u_ij(x)) with
+   u_jk interpolated bilinearly and clamped to the domain. All [2][H][W]; u_ik may alias u_ij
+   or u_jk. */
+pprs_status pprs_compose_deformations(pprs_ctx* ctx, const float* u_ij, const float* u_jk,
+                                      float* u_ik, int H, int W);
+
+/* Series registration (definition "Image series registration"): frames [N][H][W];
+   u_out [N][2][H][W] receives u_out[0] = 0 and u_out[i] = phi_{0,i}, so that
+   f_i o phi_{0,i} ~ f_0. The neighbour registrations run as one batch; the scan runs the B
+   applications of each schedule level as one batch. stats and op_stats are host pointers and
+   may be NULL; op_stats receives N-1 A entries followed by the B entries in schedule order
+   (at most 2N). */
+pprs_status pprs_prefix_register_series(pprs_ctx* ctx, const float* frames, int N, int H,
+                                        int W, float* u_out, const pprs_params* params,
+                                        pprs_series_stats* stats, pprs_pair_stats* op_stats);
+
+/* Host-only: the scan schedule over M = N-1 elements (algorithms "serial" and "brent_kung").
+   ops (host, capacity `cap` triples) receives (left, right, level) per B application in
+   execution order: x[right] <- x[left] (.) x[right]; ops of one level are independent.
+   Writes the op count and level count. Returns PPRS_EINVAL for bad arguments or a too small
+   capacity (then *n_ops holds the needed count). Makes no HIP call. */
+pprs_status pprs_scan_plan(int kind, int M, int* ops, int cap, int* n_ops, int* n_levels);
+
+/* Kernel timing (HIP events around the launches of each kernel kind on the context stream).
+   Enabling costs a few microseconds per launch. Kinds are listed by pprs_kernel_name(). */
+pprs_status pprs_set_kernel_timing(pprs_ctx* ctx, int enable);
+/* Host arrays of `cap` entries: total ms, launch count, algorithmic bytes per kind since the
+   last reset. Returns the number of kinds in *n_kinds. */
+pprs_status pprs_get_kernel_timing(pprs_ctx* ctx, double* ms, long long* launches,
+                                   double* bytes, int cap, int* n_kinds, int reset);
+const char* pprs_kernel_name(int kind);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPRS_H */

@@ -1,0 +1,13 @@
+"""pprs: prefix-scan registration of micrograph series on MI355X (gfx950).
+
+The work runs in libpprs.so (HIP kernels behind a C ABI, include/pprs.h). This package only
+marshals arguments: torch tensors supply device memory and the stream. Importing it does not
+load the library; the first call does, and fails loudly if it has not been built.
+"""
+from .api import (Params, PairStats, SeriesStats, compose_deformations, default_params,
+                  kernel_names, kernel_timing, prefix_register_series, register_pair,
+                  scan_plan, set_kernel_timing, Context)
+
+__all__ = ["Params", "PairStats", "SeriesStats", "compose_deformations", "default_params",
+           "kernel_names", "kernel_timing", "prefix_register_series", "register_pair",
+           "scan_plan", "set_kernel_timing", "Context"]

@@ -1,0 +1,292 @@
+"""ctypes binding of libpprs (include/pprs.h). Argument marshalling only.
+
+Every function takes and returns torch tensors in device memory; the work happens in the HIP
+kernels of libpprs.so on the caller's current HIP stream. Displacements are [2, H, W] float32
+in pixels (plane 0: x/column, plane 1: y/row); frames are [H, W] float32 with H == W == 2^L
+(or 2^L + 1).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from dataclasses import asdict, dataclass, field
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpprs.so")
+
+PPRS_OK = 0
+PPRS_NOT_CONVERGED = 1
+SCAN_KINDS = {"sequential": 0, "brent_kung": 1}
+MAX_LEVELS = 16
+
+
+class PprsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("pprs status %d: %s" % (status, message))
+        self.status = status
+
+
+class _CParams(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int), ("lam", ctypes.c_double), ("beta", ctypes.c_double),
+                ("armijo_sigma", ctypes.c_double), ("ladder_k", ctypes.c_int),
+                ("step_cap", ctypes.c_double), ("tau_min_rel", ctypes.c_double),
+                ("eps", ctypes.c_double), ("iter_max", ctypes.c_int), ("scan", ctypes.c_int)]
+
+
+class _CPairStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int * MAX_LEVELS), ("passes", ctypes.c_int * MAX_LEVELS),
+                ("energy", ctypes.c_double), ("ncc", ctypes.c_double), ("flags", ctypes.c_int)]
+
+
+class _CSeriesStats(ctypes.Structure):
+    _fields_ = [("n_ops_a", ctypes.c_int), ("n_ops_b", ctypes.c_int),
+                ("n_scan_levels", ctypes.c_int), ("flags_or", ctypes.c_int),
+                ("ms_total", ctypes.c_double), ("ms_prepare", ctypes.c_double),
+                ("ms_preprocess", ctypes.c_double), ("ms_scan", ctypes.c_double),
+                ("node_steps", ctypes.c_longlong), ("node_passes", ctypes.c_longlong)]
+
+
+@dataclass
+class Params:
+    """Mirror of pprs_params; defaults are pprs_default_params()."""
+    levels: int = 4
+    lam: float = 10.0
+    beta: float = 1.0
+    armijo_sigma: float = 0.5
+    ladder_k: int = 1
+    step_cap: float = 1.0
+    tau_min_rel: float = 1e-4
+    eps: float = 3e-4
+    iter_max: int = 500
+    scan: str = "brent_kung"
+
+    def c(self) -> _CParams:
+        d = asdict(self)
+        d["scan"] = SCAN_KINDS[d["scan"]]
+        return _CParams(**d)
+
+
+@dataclass
+class PairStats:
+    iters: list
+    passes: list
+    energy: float
+    ncc: float
+    flags: int
+
+
+@dataclass
+class SeriesStats:
+    n_ops_a: int
+    n_ops_b: int
+    n_scan_levels: int
+    flags_or: int
+    ms_total: float
+    ms_prepare: float
+    ms_preprocess: float
+    ms_scan: float
+    node_steps: int
+    node_passes: int
+
+
+_lib_lock = threading.Lock()
+_lib_obj = None
+
+
+def _lib():
+    global _lib_obj
+    with _lib_lock:
+        if _lib_obj is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError("libpprs.so is not built (%s); run __graft_entry__.build()"
+                                   % LIB_PATH)
+            lib = ctypes.CDLL(LIB_PATH)
+            vp = ctypes.c_void_p
+            i = ctypes.c_int
+            sigs = {
+                "pprs_default_params": (None, [ctypes.POINTER(_CParams)]),
+                "pprs_create": (i, [ctypes.POINTER(vp), i, vp]),
+                "pprs_destroy": (None, [vp]),
+                "pprs_last_error": (ctypes.c_char_p, []),
+                "pprs_register_pair": (i, [vp, vp, vp, i, i, vp, vp, ctypes.POINTER(_CParams),
+                                           ctypes.POINTER(_CPairStats)]),
+                "pprs_compose_deformations": (i, [vp, vp, vp, vp, i, i]),
+                "pprs_prefix_register_series": (i, [vp, vp, i, i, i, vp,
+                                                    ctypes.POINTER(_CParams),
+                                                    ctypes.POINTER(_CSeriesStats),
+                                                    ctypes.POINTER(_CPairStats)]),
+                "pprs_scan_plan": (i, [i, i, ctypes.POINTER(ctypes.c_int), i,
+                                       ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_int)]),
+                "pprs_set_kernel_timing": (i, [vp, i]),
+                "pprs_get_kernel_timing": (i, [vp, ctypes.POINTER(ctypes.c_double),
+                                               ctypes.POINTER(ctypes.c_longlong),
+                                               ctypes.POINTER(ctypes.c_double), i,
+                                               ctypes.POINTER(ctypes.c_int), i]),
+                "pprs_kernel_name": (ctypes.c_char_p, [i]),
+            }
+            for name, (res, args) in sigs.items():
+                fn = getattr(lib, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib_obj = lib
+        return _lib_obj
+
+
+def _check(status: int) -> int:
+    if status < 0:
+        raise PprsError(status, _lib().pprs_last_error().decode())
+    return status
+
+
+def default_params() -> Params:
+    cp = _CParams()
+    _lib().pprs_default_params(ctypes.byref(cp))
+    scan = {v: k for k, v in SCAN_KINDS.items()}[cp.scan]
+    return Params(cp.levels, cp.lam, cp.beta, cp.armijo_sigma, cp.ladder_k, cp.step_cap,
+                  cp.tau_min_rel, cp.eps, cp.iter_max, scan)
+
+
+def scan_plan(kind: str, M: int):
+    """Host-only schedule: list of (left, right, level) and the number of levels."""
+    lib = _lib()
+    n = ctypes.c_int()
+    lv = ctypes.c_int()
+    lib.pprs_scan_plan(SCAN_KINDS[kind], M, None, 0, ctypes.byref(n), ctypes.byref(lv))
+    buf = (ctypes.c_int * max(3 * n.value, 1))()
+    _check(lib.pprs_scan_plan(SCAN_KINDS[kind], M, buf, n.value, ctypes.byref(n),
+                              ctypes.byref(lv)))
+    return [(buf[3 * k], buf[3 * k + 1], buf[3 * k + 2]) for k in range(n.value)], lv.value
+
+
+class Context:
+    """A libpprs context bound to one device and one HIP stream."""
+
+    def __init__(self, device: int, stream_ptr: int):
+        self.device = device
+        self.stream_ptr = stream_ptr
+        h = ctypes.c_void_p()
+        _check(_lib().pprs_create(ctypes.byref(h), device, ctypes.c_void_p(stream_ptr)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            _lib().pprs_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_ctx_cache = {}
+
+
+def _ctx(device) -> Context:
+    import torch
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    stream = torch.cuda.current_stream(idx).cuda_stream
+    key = (idx, stream)
+    c = _ctx_cache.get(key)
+    if c is None:
+        c = Context(idx, stream)
+        _ctx_cache[key] = c
+    return c
+
+
+def _dev_f32(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError("%s must be a torch tensor on a HIP device" % name)
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError("%s must be contiguous float32" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _pair_stats(s: _CPairStats, levels: int) -> PairStats:
+    return PairStats(list(s.iters[:levels]), list(s.passes[:levels]), s.energy, s.ncc, s.flags)
+
+
+def register_pair(f_ref, f_tmpl, u_init=None, params: Params | None = None, out=None):
+    """Function A: returns (u [2, H, W] pixels, PairStats)."""
+    import torch
+    params = params or Params()
+    H, W = f_ref.shape[-2:]
+    if out is None:
+        out = torch.empty((2, H, W), device=f_ref.device, dtype=torch.float32)
+    st = _CPairStats()
+    cp = params.c()
+    c = _ctx(f_ref.device)
+    _check(_lib().pprs_register_pair(
+        c.handle, _dev_f32(f_ref, "f_ref"), _dev_f32(f_tmpl, "f_tmpl"), H, W,
+        _dev_f32(u_init, "u_init") if u_init is not None else None, _dev_f32(out, "out"),
+        ctypes.byref(cp), ctypes.byref(st)))
+    return out, _pair_stats(st, params.levels)
+
+
+def compose_deformations(u_ij, u_jk, out=None):
+    """(phi_jk o phi_ij) as a displacement [2, H, W] in pixels."""
+    import torch
+    H, W = u_ij.shape[-2:]
+    if out is None:
+        out = torch.empty_like(u_ij)
+    c = _ctx(u_ij.device)
+    _check(_lib().pprs_compose_deformations(c.handle, _dev_f32(u_ij, "u_ij"),
+                                            _dev_f32(u_jk, "u_jk"), _dev_f32(out, "out"), H, W))
+    return out
+
+
+def prefix_register_series(frames, params: Params | None = None, out=None,
+                           want_op_stats: bool = False):
+    """Series registration: returns (u [N, 2, H, W] pixels with u[0] = 0, SeriesStats,
+    op stats list or None)."""
+    import torch
+    params = params or Params()
+    N, H, W = frames.shape
+    if out is None:
+        out = torch.empty((N, 2, H, W), device=frames.device, dtype=torch.float32)
+    ss = _CSeriesStats()
+    ops = None
+    if want_op_stats:
+        ops = (_CPairStats * max(2 * N, 1))()
+    cp = params.c()
+    c = _ctx(frames.device)
+    _check(_lib().pprs_prefix_register_series(
+        c.handle, _dev_f32(frames, "frames"), N, H, W, _dev_f32(out, "out"), ctypes.byref(cp),
+        ctypes.byref(ss), ops))
+    stats = SeriesStats(ss.n_ops_a, ss.n_ops_b, ss.n_scan_levels, ss.flags_or, ss.ms_total,
+                        ss.ms_prepare, ss.ms_preprocess, ss.ms_scan, ss.node_steps,
+                        ss.node_passes)
+    op_list = None
+    if want_op_stats:
+        op_list = [_pair_stats(ops[k], params.levels) for k in range(ss.n_ops_a + ss.n_ops_b)]
+    return out, stats, op_list
+
+
+def set_kernel_timing(enable: bool, device=None):
+    import torch
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    _check(_lib().pprs_set_kernel_timing(_ctx(dev).handle, 1 if enable else 0))
+
+
+def kernel_names():
+    lib = _lib()
+    return [lib.pprs_kernel_name(k).decode() for k in range(7)]
+
+
+def kernel_timing(reset: bool = False, device=None):
+    """{kernel kind: (total ms, launches, algorithmic bytes)} since the last reset."""
+    import torch
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    cap = 16
+    ms = (ctypes.c_double * cap)()
+    la = (ctypes.c_longlong * cap)()
+    by = (ctypes.c_double * cap)()
+    nk = ctypes.c_int()
+    _check(_lib().pprs_get_kernel_timing(_ctx(dev).handle, ms, la, by, cap, ctypes.byref(nk),
+                                         1 if reset else 0))
+    names = kernel_names()
+    return {names[k]: (ms[k], la[k], by[k]) for k in range(nk.value)}

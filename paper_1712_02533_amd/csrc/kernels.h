@@ -1,0 +1,34 @@
+// Launch wrappers of the HIP kernels (kernels.hip). All take the context stream.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "pprs_internal.h"
+
+namespace pprs_k {
+hipError_t plan(BatchDesc* d, hipStream_t st);
+hipError_t prolong(BatchDesc* d, int grid, hipStream_t st);
+hipError_t energy(BatchDesc* d, int mode, int ladder_k, int grid, hipStream_t st);
+hipError_t grad(BatchDesc* d, int grid, hipStream_t st);
+hipError_t smooth(BatchDesc* d, int dir, int grid, size_t lds_bytes, hipStream_t st);
+hipError_t set_smooth_lds(size_t bytes);
+hipError_t restrict_planes(const float* src, long long s_outer, long long s_inner, float* dst,
+                           long long d_outer, long long d_inner, int inner, int nf, int planes,
+                           hipStream_t st);
+hipError_t to_nodes(const float* src, int H, long long s_plane, float* dst, int n,
+                    long long d_plane, int planes, float scale, hipStream_t st);
+hipError_t from_nodes(const float* src, int n, long long s_plane, float* dst, int H,
+                      long long d_plane, int planes, float scale, hipStream_t st);
+hipError_t fill(float* p, long long count, float v, hipStream_t st);
+hipError_t fill_strided(float* p, long long outer, long long per, int n_outer, float v,
+                        hipStream_t st);
+hipError_t elem_sums(const float* src, long long plane_stride, int n, int bands, int planes,
+                     double* partial, hipStream_t st);
+hipError_t elem_final(const double* partial, int bands, int planes, int mode, double* ms,
+                      double* rsum, int rs_stride, int rs_off, hipStream_t st);
+hipError_t normalize(float* f, long long plane_stride, long long per_plane, int planes,
+                     const double* ms, hipStream_t st);
+hipError_t compose(const float* elems, long long estride, const int* left_idx,
+                   const int* right_idx, float* out_base, long long ostride, int n, int ops,
+                   hipStream_t st);
+hipError_t finish(BatchDesc* d, const int* out_idx, float* elems, long long estride,
+                  long long work, hipStream_t st);
+}  // namespace pprs_k

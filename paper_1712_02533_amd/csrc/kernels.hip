@@ -1,0 +1,1128 @@
+// HIP kernels of libpprs for gfx950 (MI355X): 64-wide wavefronts, LDS-staged stencils,
+// FP32 arithmetic with FP64 reductions, deterministic fixed-order sums.
+//
+// Per-step kernels (one "step" advances every active registration by one phase):
+//   k_plan     - builds per-kind item lists from the slot phases (one workgroup)
+//   k_prolong  - bilinear prolongation of a finished level's u to the next level
+//   k_energy   - energy at a set of step sizes (line-search pass) or at the current u
+//   k_grad     - applies the accepted step and computes the gradient G
+//   k_smooth   - metric solve d = (S1^-1 (x) S1^-1) G, one direction per launch
+// A per-slot "finaliser" runs in the last workgroup that finishes a slot's items of a kind
+// (atomic ticket), sums the tile partials in a fixed order and advances the slot's state.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include "pprs_internal.h"
+#include "kernels.h"
+
+#define FLAG_NONCONV 1
+#define FLAG_NAN 2
+
+__constant__ float c_gp[2] = {0.21132486540518711775f, 0.78867513459481288225f};
+
+// ------------------------------------------------------------------------------------------
+// Helpers
+
+__device__ __forceinline__ int lvl_n(int l) { return (1 << l) + 1; }
+
+// Clamped bilinear sample of nodal g (n x n) at column bi + tx, row ai + ty (cells).
+// Returns value; writes the gradient in domain units when grad is true.
+template <bool GRAD>
+__device__ __forceinline__ float sample_bil(const float* __restrict__ g, int n, int bi,
+                                            float tx, int ai, float ty, float inv_h,
+                                            float* gx, float* gy) {
+  float flx = floorf(tx), fly = floorf(ty);
+  int b0 = bi + (int)flx, a0 = ai + (int)fly;
+  float fx = tx - flx, fy = ty - fly;
+  bool outx = false, outy = false;
+  if (b0 < 0) { b0 = 0; fx = 0.f; outx = true; }
+  else if (b0 >= n - 1) { outx = (b0 > n - 1) || (fx > 0.f); b0 = n - 2; fx = 1.f; }
+  if (a0 < 0) { a0 = 0; fy = 0.f; outy = true; }
+  else if (a0 >= n - 1) { outy = (a0 > n - 1) || (fy > 0.f); a0 = n - 2; fy = 1.f; }
+  const float* p = g + (size_t)a0 * n + b0;
+  float v00 = p[0], v01 = p[1], v10 = p[n], v11 = p[n + 1];
+  float top = fmaf(fx, v01 - v00, v00);
+  float bot = fmaf(fx, v11 - v10, v10);
+  if (GRAD) {
+    *gx = outx ? 0.f : fmaf(fy, (v11 - v10) - (v01 - v00), v01 - v00) * inv_h;
+    *gy = outy ? 0.f : (bot - top) * inv_h;
+  }
+  return fmaf(fy, bot - top, top);
+}
+
+// Wave-level (64 lanes) sum of a double, fixed shuffle order.
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+  return v;
+}
+
+// Deterministic block reduction of NV doubles per thread (blockDim.x == BLOCK).
+// Result valid in thread 0. scratch: BLOCK/64 * NV doubles.
+template <int NV>
+__device__ void block_sum(double (&v)[NV], double* scratch, bool is_max_last = false) {
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = (is_max_last && k == NV - 1) ? wave_max(v[k]) : wave_sum(v[k]);
+    if (lane == 0) scratch[w * NV + k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = scratch[k];
+      for (int ww = 1; ww < BLOCK / 64; ++ww)
+        s = (is_max_last && k == NV - 1) ? fmax(s, scratch[ww * NV + k]) : s + scratch[ww * NV + k];
+      v[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ float* slot_u(const BatchDesc* D, int s, int l, int buf) {
+  int n = lvl_n(l);
+  return D->ubuf + (size_t)s * D->slot_u_stride + D->u_off[l] + (size_t)buf * 2 * n * n;
+}
+
+__device__ __forceinline__ void level_done(SlotState& st) {
+  st.phase = st.level < st.finest ? PH_PROLONG : PH_DONE;
+}
+
+// Items of a kind for a slot whose effective level is l.
+__device__ __forceinline__ int kind_items(const BatchDesc* D, int kind, int l) {
+  const LevelGeom& g = D->geom[l];
+  switch (kind) {
+    case WK_PROLONG: return g.tiles_prol;
+    case WK_EVAL: return g.tiles_elem;
+    case WK_LADDER: return g.tiles_elem;
+    case WK_GRAD: return g.tiles_grad;
+    default: return 2 * g.sm_items;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Work distribution: workgroup b handles the contiguous item range
+// [b * chunk, min((b+1) * chunk, total)); item -> (list position, local index).
+
+struct ItemCursor {
+  int item, end, pos;
+};
+
+__device__ bool cursor_begin(const BatchDesc* D, int kind, ItemCursor& c, int* s_pos) {
+  const WorkList wl = D->lists[kind];
+  int total = wl.total;
+  if (total <= 0) return false;
+  int chunk = (total + gridDim.x - 1) / gridDim.x;
+  c.item = blockIdx.x * chunk;
+  c.end = min(c.item + chunk, total);
+  if (c.item >= c.end) return false;
+  if (threadIdx.x == 0) {
+    const int* off = D->list_off + (size_t)kind * (D->max_slots + 1);
+    int lo = 0, hi = wl.n_slots - 1;
+    while (lo < hi) {  // largest pos with off[pos] <= item
+      int mid = (lo + hi + 1) >> 1;
+      if (off[mid] <= c.item) lo = mid; else hi = mid - 1;
+    }
+    *s_pos = lo;
+  }
+  __syncthreads();
+  c.pos = *s_pos;
+  __syncthreads();
+  return true;
+}
+
+__device__ __forceinline__ void cursor_slot(const BatchDesc* D, int kind, ItemCursor& c,
+                                            int& slot, int& local) {
+  const int* off = D->list_off + (size_t)kind * (D->max_slots + 1);
+  while (c.item >= off[c.pos + 1]) c.pos++;
+  slot = D->list_slots[(size_t)kind * D->max_slots + c.pos];
+  local = c.item - off[c.pos];
+}
+
+// Ticket: returns true in every thread of the workgroup that completed the slot's last item.
+__device__ bool last_ticket(const BatchDesc* D, int slot, int kind, int n_items, int* s_flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    int* cnt = D->counters + (size_t)slot * WK_COUNT + kind;
+    int t = atomicAdd(cnt, 1);
+    int last = (t == n_items - 1);
+    if (last) {
+      *cnt = 0;
+      __threadfence();
+    }
+    *s_flag = last;
+  }
+  __syncthreads();
+  bool last = *s_flag != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+__device__ __forceinline__ double* slot_partial(const BatchDesc* D, int s, int kind, int item) {
+  return D->partial + (size_t)s * D->part_slot_stride + (size_t)kind * D->part_kind_stride +
+         (size_t)item * PW;
+}
+
+// Fixed-order sum of NV columns over n_items partial records; result in thread 0's out[].
+template <int NV>
+__device__ void sum_partials(const BatchDesc* D, int s, int kind, int n_items, int nv,
+                             double (&out)[NV], double* scratch, bool max_last) {
+  for (int k = 0; k < NV; ++k) out[k] = 0.0;
+  for (int it = threadIdx.x; it < n_items; it += BLOCK) {
+    const double* p = slot_partial(D, s, kind, it);
+    for (int k = 0; k < nv; ++k) {
+      double x = p[k];
+      if (max_last && k == NV - 1) out[k] = fmax(out[k], x);
+      else out[k] += x;
+    }
+  }
+  block_sum<NV>(out, scratch, max_last);
+}
+
+// ------------------------------------------------------------------------------------------
+// Planning kernel: one workgroup of 1024 threads.
+
+#define PLAN_T 1024
+
+__device__ int block_excl_scan(int v, int* s, int& total) {
+  int tid = threadIdx.x;
+  s[tid] = v;
+  __syncthreads();
+  for (int o = 1; o < PLAN_T; o <<= 1) {
+    int x = tid >= o ? s[tid - o] : 0;
+    __syncthreads();
+    s[tid] += x;
+    __syncthreads();
+  }
+  int incl = s[tid];
+  total = s[PLAN_T - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void __launch_bounds__(PLAN_T) k_plan(BatchDesc* D) {
+  __shared__ int s_scan[PLAN_T];
+  __shared__ int s_red[PLAN_T / 64];
+  int carry_cnt[WK_COUNT], carry_items[WK_COUNT];
+  for (int k = 0; k < WK_COUNT; ++k) carry_cnt[k] = carry_items[k] = 0;
+  int n_slots = D->n_slots;
+  int active = 0;
+  for (int base = 0; base < n_slots; base += PLAN_T) {
+    int s = base + threadIdx.x;
+    int ph = PH_DONE, eff = 0;
+    if (s < n_slots) {
+      SlotState* st = D->state + s;
+      ph = st->phase;
+      eff = ph == PH_PROLONG ? st->level + 1 : st->level;
+    }
+    active += ph != PH_DONE;
+    for (int k = 0; k < WK_COUNT; ++k) {
+      bool m;
+      switch (k) {
+        case WK_PROLONG: m = ph == PH_PROLONG; break;
+        case WK_EVAL: m = ph == PH_PROLONG || ph == PH_INIT; break;
+        case WK_LADDER: m = ph != PH_DONE; break;
+        default: m = ph == PH_PROLONG || ph == PH_INIT || ph == PH_GRAD; break;
+      }
+      int items = m ? kind_items(D, k, eff) : 0;
+      int tc, ti;
+      int pc = block_excl_scan(m ? 1 : 0, s_scan, tc);
+      int pi = block_excl_scan(items, s_scan, ti);
+      if (m) {
+        D->list_slots[(size_t)k * D->max_slots + carry_cnt[k] + pc] = s;
+        D->list_off[(size_t)k * (D->max_slots + 1) + carry_cnt[k] + pc] = carry_items[k] + pi;
+      }
+      carry_cnt[k] += tc;
+      carry_items[k] += ti;
+    }
+  }
+  // active count
+  int a = active;
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_down(a, o, 64);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int w = 0; w < PLAN_T / 64; ++w) tot += s_red[w];
+    D->active = tot;
+    if (D->active_host) *(volatile int*)D->active_host = tot;
+    for (int k = 0; k < WK_COUNT; ++k) {
+      D->list_off[(size_t)k * (D->max_slots + 1) + carry_cnt[k]] = carry_items[k];
+      D->lists[k].n_slots = carry_cnt[k];
+      D->lists[k].total = carry_items[k];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Prolongation of u (level l -> l+1) with the pending step applied: u_l - tau_pend d.
+
+__global__ void __launch_bounds__(BLOCK) k_prolong(BatchDesc* D) {
+  __shared__ int s_pos;
+  ItemCursor c;
+  if (!cursor_begin(D, WK_PROLONG, c, &s_pos)) return;
+  for (; c.item < c.end; ++c.item) {
+    int s, t;
+    cursor_slot(D, WK_PROLONG, c, s, t);
+    const SlotState& st = D->state[s];
+    if (st.phase != PH_PROLONG) continue;
+    int lc = st.level, lf = lc + 1;
+    int nc = lvl_n(lc), nf = lvl_n(lf);
+    const float* uc = slot_u(D, s, lc, st.ub);
+    const float* dd = D->dbuf + (size_t)s * D->slot_f_stride;
+    float tau = (float)st.tau_pend;
+    float* uf = slot_u(D, s, lf, 0);
+    int ntx = (nf + PT_X - 1) / PT_X;
+    int x0 = (t % ntx) * PT_X, y0 = (t / ntx) * PT_Y;
+    size_t ncc = (size_t)nc * nc, nff = (size_t)nf * nf;
+    for (int k = threadIdx.x; k < PT_X * PT_Y; k += BLOCK) {
+      int a = y0 + k / PT_X, b = x0 + k % PT_X;
+      if (a >= nf || b >= nf) continue;
+      int A = a >> 1, B = b >> 1;
+      int A1 = (a & 1) ? A + 1 : A, B1 = (b & 1) ? B + 1 : B;
+      for (int comp = 0; comp < 2; ++comp) {
+        const float* u = uc + comp * ncc;
+        const float* d = dd + comp * ncc;
+        size_t i00 = (size_t)A * nc + B, i01 = (size_t)A * nc + B1;
+        size_t i10 = (size_t)A1 * nc + B, i11 = (size_t)A1 * nc + B1;
+        float v00 = u[i00], v01 = u[i01], v10 = u[i10], v11 = u[i11];
+        if (tau != 0.f) {
+          v00 -= tau * d[i00];
+          v01 -= tau * d[i01];
+          v10 -= tau * d[i10];
+          v11 -= tau * d[i11];
+        }
+        uf[comp * nff + (size_t)a * nf + b] = 0.25f * ((v00 + v01) + (v10 + v11));
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Energy kernel. MODE 0: energy of the starting u of a level (slots in INIT or PROLONG).
+// MODE 1: one line-search pass at 2K+1 step sizes (slots in LADDER).
+// Per element tile: quadrature sums S1 = sum w T, S2 = sum w T^2, S3 = sum w R~ T for each
+// candidate, and the Dirichlet terms u^T K u, d^T K u, d^T K d via element matrices.
+
+// Element stiffness (Q1, h-independent in 2-D), corners ordered 00, 01, 10, 11: diagonal 2/3,
+// edge pairs -1/6, opposite pairs -1/3. Its rows sum to zero, so the bilinear form is written
+// with node differences, which keeps FP32 free of cancellation for nearly constant fields:
+//   a^T K_e b = 1/6 sum_edges (a_i - a_j)(b_i - b_j) + 1/3 sum_opposite (a_i - a_j)(b_i - b_j).
+__device__ __forceinline__ float ke_form(float a0, float a1, float a2, float a3, float b0,
+                                         float b1, float b2, float b3) {
+  float edge = (a0 - a1) * (b0 - b1) + (a0 - a2) * (b0 - b2) + (a1 - a3) * (b1 - b3) +
+               (a2 - a3) * (b2 - b3);
+  float opp = (a0 - a3) * (b0 - b3) + (a1 - a2) * (b1 - b2);
+  return (1.f / 6.f) * edge + (1.f / 3.f) * opp;
+}
+
+// (K_e u)_k = 1/6 sum over edge neighbours j of (u_k - u_j) + 1/3 (u_k - u_opposite).
+__device__ __forceinline__ void ke_apply(const float u[4], float out[4]) {
+  float d01 = u[0] - u[1], d02 = u[0] - u[2], d13 = u[1] - u[3], d23 = u[2] - u[3];
+  float d03 = u[0] - u[3], d12 = u[1] - u[2];
+  out[0] = (1.f / 6.f) * (d01 + d02) + (1.f / 3.f) * d03;
+  out[1] = (1.f / 6.f) * (d13 - d01) + (1.f / 3.f) * d12;
+  out[2] = (1.f / 6.f) * (d23 - d02) - (1.f / 3.f) * d12;
+  out[3] = (1.f / 6.f) * (-d13 - d23) - (1.f / 3.f) * d03;
+}
+
+template <int MODE, int NC>
+__global__ void __launch_bounds__(BLOCK) k_energy(BatchDesc* D) {
+  constexpr int NN = (ET_X + 1) * (ET_Y + 1);
+  __shared__ float s_ux[NN], s_uy[NN], s_dx[MODE ? NN : 1], s_dy[MODE ? NN : 1], s_r[NN];
+  __shared__ double s_red[(BLOCK / 64) * PW];
+  __shared__ int s_pos, s_flag;
+  const int kind = MODE ? WK_LADDER : WK_EVAL;
+  ItemCursor c;
+  if (!cursor_begin(D, kind, c, &s_pos)) return;
+  for (; c.item < c.end; ++c.item) {
+    int s, t;
+    cursor_slot(D, kind, c, s, t);
+    SlotState* stp = D->state + s;
+    int ph = stp->phase;
+    if (MODE == 0 && !(ph == PH_INIT || ph == PH_PROLONG)) continue;
+    if (MODE == 1 && ph != PH_LADDER) continue;
+    int l = (ph == PH_PROLONG) ? stp->level + 1 : stp->level;
+    int ub = (ph == PH_PROLONG) ? 0 : stp->ub;
+    int n = lvl_n(l);
+    size_t nn = (size_t)n * n;
+    const float* u = slot_u(D, s, l, ub);
+    const float* d = D->dbuf + (size_t)s * D->slot_f_stride;
+    const float* R = D->frames[l] + (size_t)stp->ref * nn;
+    const float* T = D->frames[l] + (size_t)stp->tmpl * nn;
+    int K = D->ladder_k;
+    constexpr int ncand = NC;
+    double top = MODE ? stp->top : 0.0;
+    float taus[NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) taus[j] = MODE ? (float)ldexp(top, -j) : 0.f;
+    int ntx = (n - 1 + ET_X - 1) / ET_X;
+    int e0x = (t % ntx) * ET_X, e0y = (t / ntx) * ET_Y;
+    // stage nodes [e0y, e0y+ET_Y] x [e0x, e0x+ET_X] (clipped)
+    for (int k = threadIdx.x; k < NN; k += BLOCK) {
+      int a = e0y + k / (ET_X + 1), b = e0x + k % (ET_X + 1);
+      float ux = 0.f, uy = 0.f, dx = 0.f, dy = 0.f, r = 0.f;
+      if (a < n && b < n) {
+        size_t i = (size_t)a * n + b;
+        ux = u[i];
+        uy = u[nn + i];
+        r = R[i];
+        if (MODE) {
+          dx = d[i];
+          dy = d[nn + i];
+        }
+      }
+      s_ux[k] = ux;
+      s_uy[k] = uy;
+      s_r[k] = r;
+      if (MODE) {
+        s_dx[k] = dx;
+        s_dy[k] = dy;
+      }
+    }
+    __syncthreads();
+    constexpr int NV = 3 * NC + 3;
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    float inv_h = (float)(n - 1);
+    float w = 0.25f / ((float)(n - 1) * (float)(n - 1));
+    for (int e = threadIdx.x; e < ET_X * ET_Y; e += BLOCK) {
+      int ey = e / ET_X, ex = e % ET_X;
+      int a = e0y + ey, b = e0x + ex;
+      if (a >= n - 1 || b >= n - 1) continue;
+      int k00 = ey * (ET_X + 1) + ex;
+      float ux[4] = {s_ux[k00], s_ux[k00 + 1], s_ux[k00 + ET_X + 1], s_ux[k00 + ET_X + 2]};
+      float uy[4] = {s_uy[k00], s_uy[k00 + 1], s_uy[k00 + ET_X + 1], s_uy[k00 + ET_X + 2]};
+      float rr[4] = {s_r[k00], s_r[k00 + 1], s_r[k00 + ET_X + 1], s_r[k00 + ET_X + 2]};
+      float dx[4] = {0, 0, 0, 0}, dy[4] = {0, 0, 0, 0};
+      if (MODE) {
+        dx[0] = s_dx[k00]; dx[1] = s_dx[k00 + 1]; dx[2] = s_dx[k00 + ET_X + 1]; dx[3] = s_dx[k00 + ET_X + 2];
+        dy[0] = s_dy[k00]; dy[1] = s_dy[k00 + 1]; dy[2] = s_dy[k00 + ET_X + 1]; dy[3] = s_dy[k00 + ET_X + 2];
+      }
+      // Dirichlet terms
+      acc[3 * NC + 0] += (double)(ke_form(ux[0], ux[1], ux[2], ux[3], ux[0], ux[1], ux[2], ux[3]) +
+                                        ke_form(uy[0], uy[1], uy[2], uy[3], uy[0], uy[1], uy[2], uy[3]));
+      if (MODE) {
+        acc[3 * NC + 1] += (double)(ke_form(dx[0], dx[1], dx[2], dx[3], ux[0], ux[1], ux[2], ux[3]) +
+                                          ke_form(dy[0], dy[1], dy[2], dy[3], uy[0], uy[1], uy[2], uy[3]));
+        acc[3 * NC + 2] += (double)(ke_form(dx[0], dx[1], dx[2], dx[3], dx[0], dx[1], dx[2], dx[3]) +
+                                          ke_form(dy[0], dy[1], dy[2], dy[3], dy[0], dy[1], dy[2], dy[3]));
+      }
+      // quadrature points
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          float xi = c_gp[q], eta = c_gp[p];
+          float p0 = (1.f - xi) * (1.f - eta), p1 = xi * (1.f - eta), p2 = (1.f - xi) * eta, p3 = xi * eta;
+          float uqx = p0 * ux[0] + p1 * ux[1] + p2 * ux[2] + p3 * ux[3];
+          float uqy = p0 * uy[0] + p1 * uy[1] + p2 * uy[2] + p3 * uy[3];
+          float rq = p0 * rr[0] + p1 * rr[1] + p2 * rr[2] + p3 * rr[3];
+          float dqx = 0.f, dqy = 0.f;
+          if (MODE) {
+            dqx = p0 * dx[0] + p1 * dx[1] + p2 * dx[2] + p3 * dx[3];
+            dqy = p0 * dy[0] + p1 * dy[1] + p2 * dy[2] + p3 * dy[3];
+          }
+#pragma unroll
+          for (int j = 0; j < NC; ++j) {
+            float tx = xi + (uqx - taus[j] * dqx) * inv_h;
+            float ty = eta + (uqy - taus[j] * dqy) * inv_h;
+            float tv = sample_bil<false>(T, n, b, tx, a, ty, inv_h, nullptr, nullptr);
+            float wt = w * tv;
+            acc[3 * j + 0] += (double)wt;
+            acc[3 * j + 1] += (double)(wt * tv);
+            acc[3 * j + 2] += (double)(wt * rq);
+          }
+        }
+      }
+    }
+    // block reduction -> partial record
+    {
+      block_sum<NV>(acc, s_red);
+      if (threadIdx.x == 0) {
+        double* pr = slot_partial(D, s, kind, t);
+        for (int k = 0; k < NV; ++k) pr[k] = acc[k];
+      }
+    }
+    int n_items = D->geom[l].tiles_elem;
+    if (last_ticket(D, s, kind, n_items, &s_flag)) {
+      double tot[NV];
+      sum_partials<NV>(D, s, kind, n_items, NV, tot, s_red, false);
+      if (threadIdx.x == 0) {
+        SlotState& st = *stp;
+        double rs = D->rsum[(size_t)st.ref * PPRS_MAXL + l];
+        double h = 1.0 / (n - 1);
+        double e_j[MAX_CAND], ncc_j[MAX_CAND], m_j[MAX_CAND], sg_j[MAX_CAND];
+        for (int j = 0; j < ncand; ++j) {
+          double m = tot[3 * j], var = tot[3 * j + 1] - m * m;
+          double sg = var > 0.0 ? sqrt(var) : 0.0;
+          double ncc = sg > 0.0 ? (tot[3 * j + 2] - m * rs) / sg : 0.0;
+          double tj = MODE ? ldexp(top, -j) : 0.0;
+          double reg = tot[3 * NC] - 2.0 * tj * tot[3 * NC + 1] + tj * tj * tot[3 * NC + 2];
+          e_j[j] = -ncc + 0.5 * D->lambda * reg;
+          ncc_j[j] = ncc;
+          m_j[j] = m;
+          sg_j[j] = sg;
+        }
+        (void)h;
+        long long* nc_s = D->node_count + (size_t)s * WK_COUNT;
+        nc_s[kind] += (long long)n * n;
+        if (MODE == 0 && ph == PH_PROLONG) nc_s[WK_PROLONG] += (long long)n * n;
+        if (MODE == 0) {
+          if (ph == PH_PROLONG) {
+            st.level = l;
+            st.ub = 0;
+          }
+          st.iter = 0;
+          st.tau_prev = INFINITY;
+          st.tau_pend = 0.0;
+          st.E = e_j[0];
+          st.ncc = ncc_j[0];
+          st.mean = m_j[0];
+          st.sigma = sg_j[0];
+          if (!isfinite(st.E)) {
+            st.flags |= FLAG_NAN;
+            st.phase = PH_DONE;
+          } else if (D->iter_max <= 0) {
+            level_done(st);
+          } else {
+            st.phase = PH_GRAD;
+          }
+        } else {
+          int li = st.level - st.coarsest;
+          st.passes[li]++;
+          int acc_j = -1;
+          for (int j = 0; j < ncand; ++j) {
+            double tj = ldexp(top, -j);
+            if (e_j[j] <= st.E - D->sigma * tj * st.gtd) {
+              acc_j = j;
+              break;
+            }
+          }
+          if (acc_j >= 0) {
+            double tj = ldexp(top, -acc_j);
+            double dec = st.E - e_j[acc_j];
+            st.E = e_j[acc_j];
+            st.ncc = ncc_j[acc_j];
+            st.mean = m_j[acc_j];
+            st.sigma = sg_j[acc_j];
+            st.tau_pend = tj;
+            st.tau_prev = tj;
+            st.iter++;
+            st.iters[li] = st.iter;
+            if (dec < D->eps) {
+              level_done(st);
+            } else if (st.iter >= D->iter_max) {
+              st.flags |= FLAG_NONCONV;
+              level_done(st);
+            } else {
+              st.phase = PH_GRAD;
+            }
+          } else {
+            st.top = ldexp(top, -(2 * K + 1));
+            if (st.top < D->tau_min_rel * st.tau_max) level_done(st);
+            else st.phase = PH_LADDER;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Gradient kernel (slots in GRAD): u_new = u - tau_pend d, written to the other u buffer;
+// G_i = sum over the elements around node i of
+//       sum_q psi_i(q) f_q grad T(q + u(q)) + lambda (K_e u_e)_i,
+//       f_q = -w (R~(q) - NCC (T(q) - mean) / sigma) / sigma.
+
+__global__ void __launch_bounds__(BLOCK) k_grad(BatchDesc* D) {
+  constexpr int NX = GT_X + 2, NY = GT_Y + 2;       // staged nodes
+  constexpr int EX = GT_X + 1, EY = GT_Y + 1;       // elements touching the tile
+  __shared__ float s_ux[NX * NY], s_uy[NX * NY], s_r[NX * NY];
+  __shared__ float s_c[8][EX * EY];                 // per element, per corner, (x, y)
+  __shared__ int s_pos;
+  ItemCursor c;
+  if (!cursor_begin(D, WK_GRAD, c, &s_pos)) return;
+  for (; c.item < c.end; ++c.item) {
+    int s, t;
+    cursor_slot(D, WK_GRAD, c, s, t);
+    const SlotState* stp = D->state + s;
+    if (stp->phase != PH_GRAD) continue;
+    int l = stp->level;
+    int n = lvl_n(l);
+    size_t nn = (size_t)n * n;
+    const float* u = slot_u(D, s, l, stp->ub);
+    float* un = slot_u(D, s, l, stp->ub ^ 1);
+    const float* d = D->dbuf + (size_t)s * D->slot_f_stride;
+    float* G = D->gbuf + (size_t)s * D->slot_f_stride;
+    const float* R = D->frames[l] + (size_t)stp->ref * nn;
+    const float* T = D->frames[l] + (size_t)stp->tmpl * nn;
+    float tau = (float)stp->tau_pend;
+    double sg = stp->sigma;
+    float inv_sig = sg > 0.0 ? (float)(1.0 / sg) : 0.f;
+    float ncc = (float)stp->ncc, mean = (float)stp->mean;
+    float lam = (float)D->lambda;
+    float inv_h = (float)(n - 1);
+    float w = 0.25f / ((float)(n - 1) * (float)(n - 1));
+    int ntx = (n + GT_X - 1) / GT_X;
+    int x0 = (t % ntx) * GT_X, y0 = (t / ntx) * GT_Y;
+    __syncthreads();
+    for (int k = threadIdx.x; k < NX * NY; k += BLOCK) {
+      int a = y0 - 1 + k / NX, b = x0 - 1 + k % NX;
+      float ux = 0.f, uy = 0.f, r = 0.f;
+      if (a >= 0 && a < n && b >= 0 && b < n) {
+        size_t i = (size_t)a * n + b;
+        ux = u[i];
+        uy = u[nn + i];
+        if (tau != 0.f) {
+          ux -= tau * d[i];
+          uy -= tau * d[nn + i];
+        }
+        r = R[i];
+      }
+      s_ux[k] = ux;
+      s_uy[k] = uy;
+      s_r[k] = r;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < EX * EY; e += BLOCK) {
+      int ey = e / EX, ex = e % EX;
+      int a = y0 - 1 + ey, b = x0 - 1 + ex;
+      float cx[4] = {0, 0, 0, 0}, cy[4] = {0, 0, 0, 0};
+      if (a >= 0 && a < n - 1 && b >= 0 && b < n - 1) {
+        int k00 = ey * NX + ex;
+        float ux[4] = {s_ux[k00], s_ux[k00 + 1], s_ux[k00 + NX], s_ux[k00 + NX + 1]};
+        float uy[4] = {s_uy[k00], s_uy[k00 + 1], s_uy[k00 + NX], s_uy[k00 + NX + 1]};
+        float rr[4] = {s_r[k00], s_r[k00 + 1], s_r[k00 + NX], s_r[k00 + NX + 1]};
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            float xi = c_gp[q], eta = c_gp[p];
+            float ps[4] = {(1.f - xi) * (1.f - eta), xi * (1.f - eta), (1.f - xi) * eta, xi * eta};
+            float uqx = ps[0] * ux[0] + ps[1] * ux[1] + ps[2] * ux[2] + ps[3] * ux[3];
+            float uqy = ps[0] * uy[0] + ps[1] * uy[1] + ps[2] * uy[2] + ps[3] * uy[3];
+            float rq = ps[0] * rr[0] + ps[1] * rr[1] + ps[2] * rr[2] + ps[3] * rr[3];
+            float gx, gy;
+            float tv = sample_bil<true>(T, n, b, xi + uqx * inv_h, a, eta + uqy * inv_h, inv_h, &gx, &gy);
+            float f = -w * (rq - ncc * (tv - mean) * inv_sig) * inv_sig;
+            float fx = f * gx, fy = f * gy;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              cx[k] += ps[k] * fx;
+              cy[k] += ps[k] * fy;
+            }
+          }
+        }
+        // lambda K_e u_e
+        float kx[4], ky[4];
+        ke_apply(ux, kx);
+        ke_apply(uy, ky);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          cx[k] += lam * kx[k];
+          cy[k] += lam * ky[k];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        s_c[2 * k][e] = cx[k];
+        s_c[2 * k + 1][e] = cy[k];
+      }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < GT_X * GT_Y; k += BLOCK) {
+      int ty = k / GT_X, tx = k % GT_X;
+      int a = y0 + ty, b = x0 + tx;
+      if (a >= n || b >= n) continue;
+      // elements (local coords): (ty, tx) is element (a-1, b-1) -> corner 3, etc.
+      int e11 = ty * EX + tx, e10 = ty * EX + tx + 1, e01 = (ty + 1) * EX + tx,
+          e00 = (ty + 1) * EX + tx + 1;
+      float gx = (s_c[6][e11] + s_c[4][e10]) + (s_c[2][e01] + s_c[0][e00]);
+      float gy = (s_c[7][e11] + s_c[5][e10]) + (s_c[3][e01] + s_c[1][e00]);
+      size_t i = (size_t)a * n + b;
+      int kn = (ty + 1) * NX + tx + 1;
+      G[i] = gx;
+      G[nn + i] = gy;
+      un[i] = s_ux[kn];
+      un[nn + i] = s_uy[kn];
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Metric solve along one axis: S1 x = g on every line, S1 symmetric tridiagonal with the
+// level's precomputed LU (a_i = -o / den_i, inv_den_i, c'_i). Lines of a workgroup are staged
+// in LDS; each line is split into chunks whose affine maps are composed, scanned across
+// chunks, then re-applied (forward and backward substitution).
+// DIR 0: lines are columns (solve along y), reads G writes Z.
+// DIR 1: lines are rows (solve along x), reads Z writes D, partial G.d and max |d|.
+
+template <int DIR>
+__global__ void __launch_bounds__(SM_THREADS) k_smooth(BatchDesc* D) {
+  extern __shared__ float s_buf[];
+  __shared__ float s_A[SM_THREADS], s_B[SM_THREADS], s_in[SM_THREADS];
+  __shared__ double s_red[(BLOCK / 64) * 2];
+  __shared__ int s_pos, s_flag;
+  const int kind = DIR ? WK_SMX : WK_SMY;
+  ItemCursor c;
+  if (!cursor_begin(D, kind, c, &s_pos)) return;
+  for (; c.item < c.end; ++c.item) {
+    int s, t;
+    cursor_slot(D, kind, c, s, t);
+    const SlotState* stp = D->state + s;
+    if (stp->phase != PH_GRAD) continue;
+    int l = stp->level;
+    int n = lvl_n(l);
+    size_t nn = (size_t)n * n;
+    const LevelGeom& g = D->geom[l];
+    int SL = g.sm_lines;
+    int comp = t / g.sm_items;
+    int line0 = (t % g.sm_items) * SL;
+    int nl = min(SL, n - line0);
+    const float* src = (DIR ? D->zbuf : D->gbuf) + (size_t)s * D->slot_f_stride + comp * nn;
+    float* dst = (DIR ? D->dbuf : D->zbuf) + (size_t)s * D->slot_f_stride + comp * nn;
+    const float* Gp = D->gbuf + (size_t)s * D->slot_f_stride + comp * nn;
+    const float* ca = D->coef + g.coef_off;           // a_i
+    const float* cinv = ca + n;                       // inv_den_i
+    const float* ccp = ca + 2 * n;                    // c'_i
+    // LDS layout: element (line L, index i) at L * ls + i * is
+    int ls, is;
+    if (DIR == 0) { is = SL + 1; ls = 1; }             // [i][line]
+    else { ls = n + 1; is = 1; }                       // [line][i]
+    __syncthreads();
+    // load
+    if (DIR == 0) {
+      for (int k = threadIdx.x; k < n * SL; k += SM_THREADS) {
+        int i = k / SL, L = k % SL;
+        s_buf[i * is + L] = L < nl ? src[(size_t)i * n + line0 + L] : 0.f;
+      }
+    } else {
+      for (int L = 0; L < nl; ++L)
+        for (int i = threadIdx.x; i < n; i += SM_THREADS)
+          s_buf[L * ls + i] = src[(size_t)(line0 + L) * n + i];
+    }
+    __syncthreads();
+    int tpl = SM_THREADS / SL;                         // threads per line
+    int L = threadIdx.x % SL, ck = threadIdx.x / SL;   // line, chunk
+    int C = (n + tpl - 1) / tpl;
+    int i0 = min(ck * C, n), i1 = min(i0 + C, n);
+    float* line = s_buf + L * ls;
+    // forward: y_i = a_i y_{i-1} + inv_den_i g_i
+    {
+      float A = 1.f, B = 0.f;
+      for (int i = i0; i < i1; ++i) {
+        float ai = ca[i];
+        A = ai * A;
+        B = fmaf(ai, B, cinv[i] * line[i * is]);
+      }
+      s_A[ck * SL + L] = A;
+      s_B[ck * SL + L] = B;
+    }
+    __syncthreads();
+    if (ck == 0) {
+      float y = 0.f;
+      for (int k = 0; k < tpl; ++k) {
+        s_in[k * SL + L] = y;
+        y = fmaf(s_A[k * SL + L], y, s_B[k * SL + L]);
+      }
+    }
+    __syncthreads();
+    {
+      float y = s_in[ck * SL + L];
+      for (int i = i0; i < i1; ++i) {
+        y = fmaf(ca[i], y, cinv[i] * line[i * is]);
+        line[i * is] = y;
+      }
+    }
+    __syncthreads();
+    // backward: x_i = y_i - c'_i x_{i+1}
+    {
+      float A = 1.f, B = 0.f;
+      for (int i = i1 - 1; i >= i0; --i) {
+        float m = -ccp[i];
+        A = m * A;
+        B = fmaf(m, B, line[i * is]);
+      }
+      s_A[ck * SL + L] = A;
+      s_B[ck * SL + L] = B;
+    }
+    __syncthreads();
+    if (ck == 0) {
+      float x = 0.f;
+      for (int k = tpl - 1; k >= 0; --k) {
+        s_in[k * SL + L] = x;
+        x = fmaf(s_A[k * SL + L], x, s_B[k * SL + L]);
+      }
+    }
+    __syncthreads();
+    {
+      float x = s_in[ck * SL + L];
+      for (int i = i1 - 1; i >= i0; --i) {
+        x = fmaf(-ccp[i], x, line[i * is]);
+        line[i * is] = x;
+      }
+    }
+    __syncthreads();
+    // store
+    if (DIR == 0) {
+      for (int k = threadIdx.x; k < n * SL; k += SM_THREADS) {
+        int i = k / SL, LL = k % SL;
+        if (LL < nl) dst[(size_t)i * n + line0 + LL] = s_buf[i * is + LL];
+      }
+    } else {
+      double gd = 0.0, dm = 0.0;
+      for (int LL = 0; LL < nl; ++LL)
+        for (int i = threadIdx.x; i < n; i += SM_THREADS) {
+          size_t gi = (size_t)(line0 + LL) * n + i;
+          float v = s_buf[LL * ls + i];
+          dst[gi] = v;
+          gd += (double)(Gp[gi] * v);
+          dm = fmax(dm, (double)fabsf(v));
+        }
+      double acc[2] = {gd, dm};
+      block_sum<2>(acc, s_red, true);
+      if (threadIdx.x == 0) {
+        double* pr = slot_partial(D, s, kind, t);
+        pr[0] = acc[0];
+        pr[1] = acc[1];
+      }
+      int n_items = 2 * g.sm_items;
+      if (last_ticket(D, s, kind, n_items, &s_flag)) {
+        double tot[2];
+        sum_partials<2>(D, s, kind, n_items, 2, tot, s_red, true);
+        if (threadIdx.x == 0) {
+          SlotState& st = D->state[s];
+          long long* nc_s = D->node_count + (size_t)s * WK_COUNT;
+          nc_s[WK_GRAD] += (long long)n * n;
+          nc_s[WK_SMY] += (long long)n * n;
+          nc_s[WK_SMX] += (long long)n * n;
+          st.ub ^= 1;          // the gradient kernel wrote u - tau_pend d to the other buffer
+          st.tau_pend = 0.0;
+          st.gtd = tot[0];
+          st.dmax = tot[1];
+          if (!(st.gtd > 0.0) || !(st.dmax > 0.0)) {
+            level_done(st);
+          } else {
+            double h = 1.0 / (n - 1);
+            st.tau_max = D->step_cap * h / st.dmax;
+            st.top = fmin(ldexp(st.tau_prev, D->ladder_k), st.tau_max);
+            st.phase = PH_LADDER;
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Setup / finish kernels (one launch per batch)
+
+// Full-weighting restriction of planes: dst(A,B) = sum w_p w_q src(2A+p, 2B+q) / sum w over
+// in-range fine nodes. Plane p lives at base + (p / inner) * outer + (p % inner) * innerst.
+__global__ void __launch_bounds__(BLOCK) k_restrict(const float* src, long long s_outer,
+                                                    long long s_inner, float* dst,
+                                                    long long d_outer, long long d_inner,
+                                                    int inner, int nf, int planes) {
+  int nc = (nf - 1) / 2 + 1;
+  long long total = (long long)planes * nc * nc;
+  for (long long k = blockIdx.x * (long long)BLOCK + threadIdx.x; k < total;
+       k += (long long)gridDim.x * BLOCK) {
+    int p = (int)(k / ((long long)nc * nc));
+    int rem = (int)(k % ((long long)nc * nc));
+    int A = rem / nc, B = rem % nc;
+    const float* f = src + (p / inner) * s_outer + (p % inner) * s_inner;
+    float sum = 0.f, ws = 0.f;
+    for (int dp = -1; dp <= 1; ++dp) {
+      int a = 2 * A + dp;
+      if (a < 0 || a >= nf) continue;
+      float wa = dp == 0 ? 2.f : 1.f;
+      float row = 0.f, rw = 0.f;
+      for (int dq = -1; dq <= 1; ++dq) {
+        int b = 2 * B + dq;
+        if (b < 0 || b >= nf) continue;
+        float wb = dq == 0 ? 2.f : 1.f;
+        row = fmaf(wb, f[(size_t)a * nf + b], row);
+        rw += wb;
+      }
+      sum = fmaf(wa, row, sum);
+      ws += wa * rw;
+    }
+    dst[(p / inner) * d_outer + (p % inner) * d_inner + (size_t)A * nc + B] = sum / ws;
+  }
+}
+
+// Pixel frames [N][H][W] (H == 2^L or 2^L + 1) -> nodal grids [N][n][n], replicating the last
+// row/column when H == 2^L. scale multiplies every value.
+__global__ void __launch_bounds__(BLOCK) k_to_nodes(const float* src, int H, long long s_plane,
+                                                    float* dst, int n, long long d_plane,
+                                                    int planes, float scale) {
+  long long total = (long long)planes * n * n;
+  for (long long k = blockIdx.x * (long long)BLOCK + threadIdx.x; k < total;
+       k += (long long)gridDim.x * BLOCK) {
+    int p = (int)(k / ((long long)n * n));
+    int rem = (int)(k % ((long long)n * n));
+    int a = min(rem / n, H - 1), b = min(rem % n, H - 1);
+    dst[p * d_plane + rem] = scale * src[p * s_plane + (size_t)a * H + b];
+  }
+}
+
+// Nodal [planes][n][n] -> pixels [planes][H][H] (crop), times scale.
+__global__ void __launch_bounds__(BLOCK) k_from_nodes(const float* src, int n, long long s_plane,
+                                                      float* dst, int H, long long d_plane,
+                                                      int planes, float scale) {
+  long long total = (long long)planes * H * H;
+  for (long long k = blockIdx.x * (long long)BLOCK + threadIdx.x; k < total;
+       k += (long long)gridDim.x * BLOCK) {
+    int p = (int)(k / ((long long)H * H));
+    int rem = (int)(k % ((long long)H * H));
+    int a = rem / H, b = rem % H;
+    dst[p * d_plane + rem] = scale * src[p * s_plane + (size_t)a * n + b];
+  }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_fill_strided(float* p, long long outer, long long per,
+                                                        int n_outer, float v) {
+  long long total = (long long)n_outer * per;
+  for (long long k = blockIdx.x * (long long)BLOCK + threadIdx.x; k < total;
+       k += (long long)gridDim.x * BLOCK)
+    p[(k / per) * outer + (k % per)] = v;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_fill(float* p, long long count, float v) {
+  for (long long k = blockIdx.x * (long long)BLOCK + threadIdx.x; k < count;
+       k += (long long)gridDim.x * BLOCK)
+    p[k] = v;
+}
+
+// Element sums of planes for normalisation: per (plane, row band) partials of
+// S1 = sum_e h^2/4 sum_corners F and S2 = sum_e F_e^T M_e F_e (FP64).
+__global__ void __launch_bounds__(BLOCK) k_elem_sums(const float* src, long long plane_stride,
+                                                     int n, int bands, double* partial) {
+  __shared__ double s_red[(BLOCK / 64) * 2];
+  int p = blockIdx.x / bands, band = blockIdx.x % bands;
+  const float* f = src + p * plane_stride;
+  int ne = n - 1;
+  int rows = (ne + bands - 1) / bands;
+  int a0 = band * rows, a1 = min(a0 + rows, ne);
+  double h2 = 1.0 / ((double)ne * ne);
+  double s1 = 0.0, s2 = 0.0;
+  for (int a = a0; a < a1; ++a)
+    for (int b = threadIdx.x; b < ne; b += BLOCK) {
+      double f0 = f[(size_t)a * n + b], f1 = f[(size_t)a * n + b + 1];
+      double f2 = f[(size_t)(a + 1) * n + b], f3 = f[(size_t)(a + 1) * n + b + 1];
+      s1 += (f0 + f1 + f2 + f3);
+      double sq = f0 * f0 + f1 * f1 + f2 * f2 + f3 * f3;
+      double edge = f0 * f1 + f0 * f2 + f1 * f3 + f2 * f3;
+      double opp = f0 * f3 + f1 * f2;
+      s2 += 4.0 * sq + 4.0 * edge + 2.0 * opp;
+    }
+  double acc[2] = {s1 * h2 * 0.25, s2 * h2 / 36.0};
+  block_sum<2>(acc, s_red);
+  if (threadIdx.x == 0) {
+    partial[(size_t)blockIdx.x * 2] = acc[0];
+    partial[(size_t)blockIdx.x * 2 + 1] = acc[1];
+  }
+}
+
+// Per plane: mean = S1, sigma = sqrt(S2 - S1^2) from the band partials (fixed order).
+// mode 0: writes mean/sigma to ms[2 * p]; mode 1: writes S1 to rsum[p * rs_stride + rs_off].
+__global__ void k_elem_final(const double* partial, int bands, int planes, int mode, double* ms,
+                             double* rsum, int rs_stride, int rs_off) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= planes) return;
+  double s1 = 0.0, s2 = 0.0;
+  for (int b = 0; b < bands; ++b) {
+    s1 += partial[((size_t)p * bands + b) * 2];
+    s2 += partial[((size_t)p * bands + b) * 2 + 1];
+  }
+  if (mode == 0) {
+    double var = s2 - s1 * s1;
+    ms[2 * p] = s1;
+    ms[2 * p + 1] = var > 0.0 ? sqrt(var) : 0.0;
+  } else {
+    rsum[(size_t)p * rs_stride + rs_off] = s1;
+  }
+}
+
+// F <- (F - mean) / sigma per plane (sigma == 0 leaves the plane, the host reports EINVAL).
+__global__ void __launch_bounds__(BLOCK) k_normalize(float* f, long long plane_stride,
+                                                     long long per_plane, int planes,
+                                                     const double* ms) {
+  long long total = (long long)planes * per_plane;
+  for (long long k = blockIdx.x * (long long)BLOCK + threadIdx.x; k < total;
+       k += (long long)gridDim.x * BLOCK) {
+    int p = (int)(k / per_plane);
+    long long i = k % per_plane;
+    double m = ms[2 * p], sg = ms[2 * p + 1];
+    if (sg > 0.0) f[p * plane_stride + i] = (float)((f[p * plane_stride + i] - m) / sg);
+  }
+}
+
+// Composition (phi_jk o phi_ij): w = u_ij + u_jk(x + u_ij), clamped bilinear, domain units.
+// For op k: left = elems + left_idx[k] * estride, right = elems + right_idx[k] * estride,
+// out = out_base + k * ostride. Index -1 means "use the explicit pointer" (single op).
+__global__ void __launch_bounds__(BLOCK) k_compose(const float* elems, long long estride,
+                                                   const int* left_idx, const int* right_idx,
+                                                   float* out_base, long long ostride, int n,
+                                                   int ops) {
+  size_t nn = (size_t)n * n;
+  long long total = (long long)ops * nn;
+  float inv_h = (float)(n - 1);
+  for (long long k = blockIdx.x * (long long)BLOCK + threadIdx.x; k < total;
+       k += (long long)gridDim.x * BLOCK) {
+    int op = (int)(k / nn);
+    int i = (int)(k % nn);
+    const float* ul = elems + left_idx[op] * estride;
+    const float* ur = elems + right_idx[op] * estride;
+    float* w = out_base + op * ostride;
+    int a = i / n, b = i % n;
+    float ux = ul[i], uy = ul[nn + i];
+    float tx = ux * inv_h, ty = uy * inv_h;
+    float vx = sample_bil<false>(ur, n, b, tx, a, ty, inv_h, nullptr, nullptr);
+    float vy = sample_bil<false>(ur + nn, n, b, tx, a, ty, inv_h, nullptr, nullptr);
+    w[i] = ux + vx;
+    w[nn + i] = uy + vy;
+  }
+}
+
+// Finished slots: element[out_idx[s]] = u_L[ub] - tau_pend d.
+__global__ void __launch_bounds__(BLOCK) k_finish(BatchDesc* D, const int* out_idx,
+                                                  float* elems, long long estride) {
+  int L = D->finest;
+  int n = lvl_n(L);
+  size_t per = 2 * (size_t)n * n;
+  long long total = (long long)D->n_slots * per;
+  for (long long k = blockIdx.x * (long long)BLOCK + threadIdx.x; k < total;
+       k += (long long)gridDim.x * BLOCK) {
+    int s = (int)(k / per);
+    size_t i = k % per;
+    const SlotState& st = D->state[s];
+    if (st.level != L) continue;  // aborted before the finest level: leave the element
+    const float* u = slot_u(D, s, L, st.ub);
+    const float* d = D->dbuf + (size_t)s * D->slot_f_stride;
+    float tau = (float)st.tau_pend;
+    elems[out_idx[s] * estride + i] = tau != 0.f ? u[i] - tau * d[i] : u[i];
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Host launch wrappers
+
+namespace pprs_k {
+
+static int grid_for(long long work, int cap = 8192) {
+  long long g = (work + BLOCK - 1) / BLOCK;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+hipError_t plan(BatchDesc* d, hipStream_t st) {
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(PLAN_T), 0, st, d);
+  return hipGetLastError();
+}
+hipError_t prolong(BatchDesc* d, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_prolong, dim3(grid), dim3(BLOCK), 0, st, d);
+  return hipGetLastError();
+}
+hipError_t energy(BatchDesc* d, int mode, int ladder_k, int grid, hipStream_t st) {
+  if (mode == 0) {
+    hipLaunchKernelGGL((k_energy<0, 1>), dim3(grid), dim3(BLOCK), 0, st, d);
+  } else {
+    switch (ladder_k) {
+      case 0: hipLaunchKernelGGL((k_energy<1, 1>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+      case 1: hipLaunchKernelGGL((k_energy<1, 3>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+      case 2: hipLaunchKernelGGL((k_energy<1, 5>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+      default: hipLaunchKernelGGL((k_energy<1, 7>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    }
+  }
+  return hipGetLastError();
+}
+hipError_t grad(BatchDesc* d, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_grad, dim3(grid), dim3(BLOCK), 0, st, d);
+  return hipGetLastError();
+}
+hipError_t smooth(BatchDesc* d, int dir, int grid, size_t lds_bytes, hipStream_t st) {
+  if (dir == 0) hipLaunchKernelGGL(k_smooth<0>, dim3(grid), dim3(SM_THREADS), lds_bytes, st, d);
+  else hipLaunchKernelGGL(k_smooth<1>, dim3(grid), dim3(SM_THREADS), lds_bytes, st, d);
+  return hipGetLastError();
+}
+hipError_t set_smooth_lds(size_t bytes) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_smooth<0>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_smooth<1>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+hipError_t restrict_planes(const float* src, long long s_outer, long long s_inner, float* dst,
+                           long long d_outer, long long d_inner, int inner, int nf, int planes,
+                           hipStream_t st) {
+  int nc = (nf - 1) / 2 + 1;
+  hipLaunchKernelGGL(k_restrict, dim3(grid_for((long long)planes * nc * nc)), dim3(BLOCK), 0,
+                     st, src, s_outer, s_inner, dst, d_outer, d_inner, inner, nf, planes);
+  return hipGetLastError();
+}
+hipError_t to_nodes(const float* src, int H, long long s_plane, float* dst, int n,
+                    long long d_plane, int planes, float scale, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_nodes, dim3(grid_for((long long)planes * n * n)), dim3(BLOCK), 0, st,
+                     src, H, s_plane, dst, n, d_plane, planes, scale);
+  return hipGetLastError();
+}
+hipError_t from_nodes(const float* src, int n, long long s_plane, float* dst, int H,
+                      long long d_plane, int planes, float scale, hipStream_t st) {
+  hipLaunchKernelGGL(k_from_nodes, dim3(grid_for((long long)planes * H * H)), dim3(BLOCK), 0,
+                     st, src, n, s_plane, dst, H, d_plane, planes, scale);
+  return hipGetLastError();
+}
+hipError_t fill(float* p, long long count, float v, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(count)), dim3(BLOCK), 0, st, p, count, v);
+  return hipGetLastError();
+}
+hipError_t fill_strided(float* p, long long outer, long long per, int n_outer, float v,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_strided, dim3(grid_for((long long)n_outer * per)), dim3(BLOCK), 0,
+                     st, p, outer, per, n_outer, v);
+  return hipGetLastError();
+}
+hipError_t elem_sums(const float* src, long long plane_stride, int n, int bands, int planes,
+                     double* partial, hipStream_t st) {
+  hipLaunchKernelGGL(k_elem_sums, dim3(planes * bands), dim3(BLOCK), 0, st, src, plane_stride,
+                     n, bands, partial);
+  return hipGetLastError();
+}
+hipError_t elem_final(const double* partial, int bands, int planes, int mode, double* ms,
+                      double* rsum, int rs_stride, int rs_off, hipStream_t st) {
+  hipLaunchKernelGGL(k_elem_final, dim3((planes + 255) / 256), dim3(256), 0, st, partial, bands,
+                     planes, mode, ms, rsum, rs_stride, rs_off);
+  return hipGetLastError();
+}
+hipError_t normalize(float* f, long long plane_stride, long long per_plane, int planes,
+                     const double* ms, hipStream_t st) {
+  hipLaunchKernelGGL(k_normalize, dim3(grid_for((long long)planes * per_plane)), dim3(BLOCK), 0,
+                     st, f, plane_stride, per_plane, planes, ms);
+  return hipGetLastError();
+}
+hipError_t compose(const float* elems, long long estride, const int* left_idx,
+                   const int* right_idx, float* out_base, long long ostride, int n, int ops,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_compose, dim3(grid_for((long long)ops * n * n)), dim3(BLOCK), 0, st,
+                     elems, estride, left_idx, right_idx, out_base, ostride, n, ops);
+  return hipGetLastError();
+}
+hipError_t finish(BatchDesc* d, const int* out_idx, float* elems, long long estride,
+                  long long work, hipStream_t st) {
+  hipLaunchKernelGGL(k_finish, dim3(grid_for(work)), dim3(BLOCK), 0, st, d, out_idx, elems,
+                     estride);
+  return hipGetLastError();
+}
+
+}  // namespace pprs_k

@@ -1,0 +1,764 @@
+// Host runtime and C-ABI of libpprs: context, device workspace, batched execution of
+// registrations (one slot per A or B application), the series scan, and kernel timing.
+//
+// A batch runs as a sequence of identical "steps" (plan, prolong, eval, grad, smooth y,
+// smooth x, line search). The device decides per slot what happens next; the host only
+// launches steps and polls one counter of active slots between groups of steps, so slots
+// retire independently and a batch mixes slots that are on different grid levels.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/pprs.h"
+#include "kernels.h"
+#include "pprs_internal.h"
+
+static thread_local std::string g_err = "no error";
+
+static pprs_status fail(pprs_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail(PPRS_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                                  \
+  } while (0)
+
+#define STCHK(expr)                 \
+  do {                              \
+    pprs_status s_ = (expr);        \
+    if (s_ < 0) return s_;          \
+  } while (0)
+
+namespace {
+
+const int kGridItems = 2048;   // workgroups of the per-step item kernels
+const int kGridSmooth = 1024;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+enum { TK_PLAN = 0, TK_PROLONG, TK_EVAL, TK_GRAD, TK_SMY, TK_SMX, TK_LADDER, TK_COUNT };
+const char* kTkName[TK_COUNT] = {"plan", "prolong", "energy_eval", "grad", "smooth_y",
+                                 "smooth_x", "energy_ladder"};
+// algorithmic HBM bytes per grid node (both displacement components) of one launch per kind
+const double kBytesPerNode[TK_COUNT] = {0.0, 12.0, 16.0, 40.0, 16.0, 24.0, 24.0};
+
+int level_n(int l) { return (1 << l) + 1; }
+
+}  // namespace
+
+struct pprs_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  // frames
+  DevBuf frames, rsum, fr_ms, fr_part;
+  // slots
+  DevBuf state, ubuf, dbuf, gbuf, zbuf, partial, counters, nodecount, coef, list_slots, list_off,
+      lists, desc, opidx;
+  // scan elements [M][2][nL^2] and staging
+  DevBuf elems;
+  int* active_host = nullptr;
+  BatchDesc hd;
+  int slots_cap = 0, slots_L = -1, slots_m0 = -1;
+  double coef_beta = -1.0;
+  int coef_L = -1, coef_m0 = -1;
+  // kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev;   // pairs
+  std::vector<int> ev_kind;
+  double t_ms[TK_COUNT] = {0};
+  long long t_launch[TK_COUNT] = {0};
+  double t_bytes[TK_COUNT] = {0};
+  long long nodes_acc[WK_COUNT] = {0};
+};
+
+namespace {
+
+pprs_status ensure(DevBuf& b, size_t bytes, bool zero = false) {
+  if (b.bytes >= bytes && b.p) return PPRS_OK;
+  if (b.p) {
+    (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  if (bytes == 0) return PPRS_OK;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(PPRS_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  b.bytes = bytes;
+  if (zero) {
+    e = hipMemset(b.p, 0, bytes);
+    if (e != hipSuccess) return fail(PPRS_EHIP, "hipMemset failed: %s", hipGetErrorString(e));
+  }
+  return PPRS_OK;
+}
+
+template <class T>
+T* P(DevBuf& b) {
+  return reinterpret_cast<T*>(b.p);
+}
+
+pprs_status check_params(const pprs_params* p, int L) {
+  if (!p) return fail(PPRS_EINVAL, "params is NULL");
+  if (p->levels < 1 || p->levels > L || L - p->levels + 1 < 1)
+    return fail(PPRS_EINVAL, "levels must be in [1, %d] for this frame size", L);
+  if (!(p->lambda >= 0.0) || !(p->beta >= 0.0))
+    return fail(PPRS_EINVAL, "lambda and beta must be >= 0");
+  if (!(p->armijo_sigma > 0.0 && p->armijo_sigma < 1.0))
+    return fail(PPRS_EINVAL, "armijo_sigma must be in (0, 1)");
+  if (p->ladder_k < 0 || p->ladder_k > 3) return fail(PPRS_EINVAL, "ladder_k must be in [0, 3]");
+  if (!(p->step_cap > 0.0)) return fail(PPRS_EINVAL, "step_cap must be > 0");
+  if (!(p->tau_min_rel > 0.0 && p->tau_min_rel < 1.0))
+    return fail(PPRS_EINVAL, "tau_min_rel must be in (0, 1)");
+  if (!(p->eps >= 0.0)) return fail(PPRS_EINVAL, "eps must be >= 0");
+  if (p->iter_max < 0) return fail(PPRS_EINVAL, "iter_max must be >= 0");
+  if (p->scan != PPRS_SCAN_SEQUENTIAL && p->scan != PPRS_SCAN_BRENT_KUNG)
+    return fail(PPRS_EINVAL, "unknown scan kind %d", p->scan);
+  return PPRS_OK;
+}
+
+// H is 2^L pixels or 2^L + 1 nodes; returns L or -1.
+int frame_level(int H, int W) {
+  if (H != W || H < 4) return -1;
+  for (int L = 2; L <= 11; ++L)
+    if (H == (1 << L) || H == (1 << L) + 1) return L;
+  return -1;
+}
+
+void fill_geom(LevelGeom& g, int l, int coef_off) {
+  int n = level_n(l);
+  g.n = n;
+  g.tiles_grad = ((n + GT_X - 1) / GT_X) * ((n + GT_Y - 1) / GT_Y);
+  g.tiles_elem = ((n - 1 + ET_X - 1) / ET_X) * ((n - 1 + ET_Y - 1) / ET_Y);
+  g.tiles_prol = ((n + PT_X - 1) / PT_X) * ((n + PT_Y - 1) / PT_Y);
+  int lines = 32;
+  while (lines > 1 && (long long)n * (lines + 1) > SM_LDS_MAX_FLOATS) lines /= 2;
+  g.sm_lines = lines;
+  g.sm_items = (n + lines - 1) / lines;
+  g.coef_off = coef_off;
+  g.pad = 0;
+}
+
+size_t smooth_lds_bytes(const BatchDesc& hd) {
+  size_t mx = 0;
+  for (int l = hd.coarsest; l <= hd.finest; ++l) {
+    const LevelGeom& g = hd.geom[l];
+    size_t a = (size_t)g.n * (g.sm_lines + 1), b = (size_t)g.sm_lines * (g.n + 1);
+    mx = std::max(mx, std::max(a, b));
+  }
+  return mx * sizeof(float);
+}
+
+// Workspace for up to `cap` slots on levels m0..L, and the metric coefficients for beta.
+pprs_status ensure_slots(pprs_ctx* c, int cap, int L, int m0, double beta) {
+  BatchDesc& hd = c->hd;
+  if (cap > c->slots_cap || L != c->slots_L || m0 != c->slots_m0) {
+    cap = std::max(cap, c->slots_cap);
+    hd.finest = L;
+    hd.coarsest = m0;
+    int coef_off = 0;
+    long long uoff = 0;
+    int max_items = 1;
+    for (int l = 0; l < PPRS_MAXL; ++l) hd.u_off[l] = 0;
+    for (int l = m0; l <= L; ++l) {
+      fill_geom(hd.geom[l], l, coef_off);
+      coef_off += 3 * hd.geom[l].n;
+      hd.u_off[l] = uoff;
+      uoff += 4LL * hd.geom[l].n * hd.geom[l].n;
+      max_items = std::max(max_items, std::max(hd.geom[l].tiles_elem, 2 * hd.geom[l].sm_items));
+    }
+    int nL = level_n(L);
+    hd.slot_u_stride = uoff;
+    hd.slot_f_stride = 2LL * nL * nL;
+    hd.part_kind_stride = (long long)max_items * PW;
+    hd.part_slot_stride = hd.part_kind_stride * WK_COUNT;
+    hd.max_slots = cap;
+    STCHK(ensure(c->state, sizeof(SlotState) * cap));
+    STCHK(ensure(c->ubuf, sizeof(float) * hd.slot_u_stride * cap));
+    STCHK(ensure(c->dbuf, sizeof(float) * hd.slot_f_stride * cap, true));
+    STCHK(ensure(c->gbuf, sizeof(float) * hd.slot_f_stride * cap));
+    STCHK(ensure(c->zbuf, sizeof(float) * hd.slot_f_stride * cap));
+    STCHK(ensure(c->partial, sizeof(double) * hd.part_slot_stride * cap));
+    // counters must start at zero; the finalisers reset them after use
+    if (c->counters.bytes < sizeof(int) * WK_COUNT * cap) {
+      STCHK(ensure(c->counters, sizeof(int) * WK_COUNT * cap, true));
+    } else {
+      HIPCHK(hipMemset(c->counters.p, 0, c->counters.bytes));
+    }
+    STCHK(ensure(c->nodecount, sizeof(long long) * WK_COUNT * cap));
+    STCHK(ensure(c->coef, sizeof(float) * coef_off));
+    STCHK(ensure(c->list_slots, sizeof(int) * WK_COUNT * cap));
+    STCHK(ensure(c->list_off, sizeof(int) * WK_COUNT * (cap + 1)));
+    STCHK(ensure(c->lists, sizeof(WorkList) * WK_COUNT));
+    STCHK(ensure(c->desc, sizeof(BatchDesc)));
+    STCHK(ensure(c->opidx, sizeof(int) * 3 * cap));
+    hd.state = P<SlotState>(c->state);
+    hd.ubuf = P<float>(c->ubuf);
+    hd.dbuf = P<float>(c->dbuf);
+    hd.gbuf = P<float>(c->gbuf);
+    hd.zbuf = P<float>(c->zbuf);
+    hd.partial = P<double>(c->partial);
+    hd.counters = P<int>(c->counters);
+    hd.node_count = P<long long>(c->nodecount);
+    hd.coef = P<float>(c->coef);
+    hd.list_slots = P<int>(c->list_slots);
+    hd.list_off = P<int>(c->list_off);
+    hd.lists = P<WorkList>(c->lists);
+    hd.active_host = nullptr;  // the host polls the device word instead
+    c->slots_cap = cap;
+    c->slots_L = L;
+    c->slots_m0 = m0;
+    c->coef_beta = -1.0;
+  }
+  if (beta != c->coef_beta || c->coef_L != L || c->coef_m0 != m0) {
+    // LU of S1 = M1 + (beta h)^2 K1 per level, in FP64, stored as FP32 a_i, 1/den_i, c'_i.
+    std::vector<float> host;
+    for (int l = m0; l <= L; ++l) {
+      int n = level_n(l);
+      double h = 1.0 / (n - 1), cc = beta * beta * h * h;
+      double de = h / 3.0 + cc / h, di = 2.0 * h / 3.0 + 2.0 * cc / h, o = h / 6.0 - cc / h;
+      std::vector<double> den(n), cp(n);
+      for (int i = 0; i < n; ++i) {
+        double dd = (i == 0 || i == n - 1) ? de : di;
+        den[i] = i == 0 ? dd : dd - o * cp[i - 1];
+        cp[i] = o / den[i];
+      }
+      size_t base = host.size();
+      host.resize(base + 3 * n);
+      for (int i = 0; i < n; ++i) {
+        host[base + i] = i == 0 ? 0.f : (float)(-o / den[i]);
+        host[base + n + i] = (float)(1.0 / den[i]);
+        host[base + 2 * n + i] = i == n - 1 ? 0.f : (float)cp[i];
+      }
+    }
+    HIPCHK(hipMemcpy(c->coef.p, host.data(), host.size() * sizeof(float),
+                     hipMemcpyHostToDevice));
+    c->coef_beta = beta;
+    c->coef_L = L;
+    c->coef_m0 = m0;
+  }
+  return PPRS_OK;
+}
+
+// Normalised frame pyramids for N frames (device [N][H][H]) on levels m0..L. Fails with
+// EINVAL if a frame with index < n_ref_frames is constant on some level.
+pprs_status prepare_frames(pprs_ctx* c, const float* frames, int N, int H, int L, int m0,
+                           int n_ref_frames) {
+  BatchDesc& hd = c->hd;
+  size_t total = 0;
+  size_t off[PPRS_MAXL] = {0};
+  for (int l = m0; l <= L; ++l) {
+    off[l] = total;
+    total += (size_t)N * level_n(l) * level_n(l);
+  }
+  STCHK(ensure(c->frames, sizeof(float) * total));
+  STCHK(ensure(c->rsum, sizeof(double) * (size_t)N * PPRS_MAXL));
+  const int bands = 16;
+  STCHK(ensure(c->fr_part, sizeof(double) * 2 * (size_t)N * bands));
+  STCHK(ensure(c->fr_ms, sizeof(double) * 2 * (size_t)N * PPRS_MAXL));
+  float* base = P<float>(c->frames);
+  for (int l = 0; l < PPRS_MAXL; ++l) hd.frames[l] = nullptr;
+  for (int l = m0; l <= L; ++l) hd.frames[l] = base + off[l];
+  hd.rsum = P<double>(c->rsum);
+  int nL = level_n(L);
+  HIPCHK(pprs_k::to_nodes(frames, H, (long long)H * H, hd.frames[L], nL, (long long)nL * nL, N,
+                          1.0f, c->stream));
+  for (int l = L; l > m0; --l) {
+    int nf = level_n(l), nc = level_n(l - 1);
+    HIPCHK(pprs_k::restrict_planes(hd.frames[l], (long long)nf * nf, 0, hd.frames[l - 1],
+                                   (long long)nc * nc, 0, 1, nf, N, c->stream));
+  }
+  std::vector<double> ms(2 * (size_t)N);
+  for (int l = m0; l <= L; ++l) {
+    int n = level_n(l);
+    double* msd = P<double>(c->fr_ms) + 2 * (size_t)N * l;
+    HIPCHK(pprs_k::elem_sums(hd.frames[l], (long long)n * n, n, bands, N, P<double>(c->fr_part),
+                             c->stream));
+    HIPCHK(pprs_k::elem_final(P<double>(c->fr_part), bands, N, 0, msd, nullptr, 0, 0,
+                              c->stream));
+    HIPCHK(hipMemcpyAsync(ms.data(), msd, sizeof(double) * 2 * N, hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int f = 0; f < N; ++f) {
+      double m = ms[2 * f], s = ms[2 * f + 1];
+      if (s <= 1e-12 * std::max(1.0, fabs(m)) && f < n_ref_frames)
+        return fail(PPRS_EINVAL, "reference frame %d is constant on level %d", f, l);
+    }
+    HIPCHK(pprs_k::normalize(hd.frames[l], (long long)n * n, (long long)n * n, N, msd,
+                             c->stream));
+    HIPCHK(pprs_k::elem_sums(hd.frames[l], (long long)n * n, n, bands, N, P<double>(c->fr_part),
+                             c->stream));
+    HIPCHK(pprs_k::elem_final(P<double>(c->fr_part), bands, N, 1, nullptr, P<double>(c->rsum),
+                              PPRS_MAXL, l, c->stream));
+  }
+  return PPRS_OK;
+}
+
+// ---- kernel timing -----------------------------------------------------------------------
+
+pprs_status tk_begin(pprs_ctx* c, int kind, hipEvent_t* stop) {
+  *stop = nullptr;
+  if (!c->timing) return PPRS_OK;
+  hipEvent_t a, b;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  HIPCHK(hipEventRecord(a, c->stream));
+  c->ev.push_back(a);
+  c->ev.push_back(b);
+  c->ev_kind.push_back(kind);
+  *stop = b;
+  return PPRS_OK;
+}
+pprs_status tk_end(pprs_ctx* c, hipEvent_t stop) {
+  if (stop) HIPCHK(hipEventRecord(stop, c->stream));
+  return PPRS_OK;
+}
+pprs_status tk_collect(pprs_ctx* c) {
+  for (size_t i = 0; i < c->ev_kind.size(); ++i) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
+    c->t_ms[c->ev_kind[i]] += ms;
+    c->t_launch[c->ev_kind[i]] += 1;
+    (void)hipEventDestroy(c->ev[2 * i]);
+    (void)hipEventDestroy(c->ev[2 * i + 1]);
+  }
+  c->ev.clear();
+  c->ev_kind.clear();
+  return PPRS_OK;
+}
+
+#define TIMED(kind, call)                 \
+  do {                                    \
+    hipEvent_t stop_;                     \
+    STCHK(tk_begin(c, kind, &stop_));     \
+    HIPCHK(call);                         \
+    STCHK(tk_end(c, stop_));              \
+  } while (0)
+
+pprs_status launch_step(pprs_ctx* c, BatchDesc* d, int ladder_k, size_t lds) {
+  TIMED(TK_PLAN, pprs_k::plan(d, c->stream));
+  TIMED(TK_PROLONG, pprs_k::prolong(d, kGridItems, c->stream));
+  TIMED(TK_EVAL, pprs_k::energy(d, 0, ladder_k, kGridItems, c->stream));
+  TIMED(TK_GRAD, pprs_k::grad(d, kGridItems, c->stream));
+  TIMED(TK_SMY, pprs_k::smooth(d, 0, kGridSmooth, lds, c->stream));
+  TIMED(TK_SMX, pprs_k::smooth(d, 1, kGridSmooth, lds, c->stream));
+  TIMED(TK_LADDER, pprs_k::energy(d, 1, ladder_k, kGridItems, c->stream));
+  return PPRS_OK;
+}
+
+enum InitKind { INIT_IDENTITY = 0, INIT_COMPOSE = 1, INIT_GIVEN = 2 };
+
+// Runs n slots (reference ref[s], template tmpl[s]) to completion and writes each result
+// (domain units, [2][nL][nL]) to elems[out_idx[s]]. INIT_COMPOSE composes elems[left[s]]
+// and elems[right[s]]; INIT_GIVEN takes the finest-level guess already in slot 0's buffer.
+pprs_status run_batch(pprs_ctx* c, int n, const int* ref, const int* tmpl, InitKind init,
+                      const int* left, const int* right, const int* out_idx, float* elems,
+                      const pprs_params* p, pprs_pair_stats* stats, long long* node_steps,
+                      long long* node_passes, int* flags_or) {
+  if (n <= 0) return PPRS_OK;
+  BatchDesc& hd = c->hd;
+  int L = hd.finest, m0 = hd.coarsest;
+  int nL = level_n(L);
+  hd.n_slots = n;
+  hd.ladder_k = p->ladder_k;
+  hd.lambda = p->lambda;
+  hd.sigma = p->armijo_sigma;
+  hd.step_cap = p->step_cap;
+  hd.tau_min_rel = p->tau_min_rel;
+  hd.eps = p->eps;
+  hd.iter_max = p->iter_max;
+  BatchDesc* d = P<BatchDesc>(c->desc);
+  HIPCHK(hipMemcpyAsync(d, &hd, sizeof(BatchDesc), hipMemcpyHostToDevice, c->stream));
+  std::vector<SlotState> st(n);
+  for (int s = 0; s < n; ++s) {
+    memset(&st[s], 0, sizeof(SlotState));
+    st[s].phase = PH_INIT;
+    st[s].level = m0;
+    st[s].ref = ref[s];
+    st[s].tmpl = tmpl[s];
+    st[s].finest = L;
+    st[s].coarsest = m0;
+    st[s].tau_prev = INFINITY;
+  }
+  HIPCHK(hipMemcpyAsync(hd.state, st.data(), sizeof(SlotState) * n, hipMemcpyHostToDevice,
+                        c->stream));
+  HIPCHK(hipMemsetAsync(hd.node_count, 0, sizeof(long long) * WK_COUNT * n, c->stream));
+  std::vector<int> idx(3 * (size_t)n);
+  for (int s = 0; s < n; ++s) {
+    idx[s] = left ? left[s] : 0;
+    idx[n + s] = right ? right[s] : 0;
+    idx[2 * n + s] = out_idx[s];
+  }
+  int* didx = P<int>(c->opidx);
+  HIPCHK(hipMemcpyAsync(didx, idx.data(), sizeof(int) * 3 * n, hipMemcpyHostToDevice,
+                        c->stream));
+  long long est = 2LL * nL * nL;
+  // initial guess on the coarsest level
+  if (init == INIT_IDENTITY) {
+    int n0 = level_n(m0);
+    HIPCHK(pprs_k::fill_strided(hd.ubuf + hd.u_off[m0], hd.slot_u_stride, 2LL * n0 * n0, n,
+                                0.f, c->stream));
+  } else {
+    if (init == INIT_COMPOSE)
+      HIPCHK(pprs_k::compose(elems, est, didx, didx + n, hd.ubuf + hd.u_off[L],
+                             hd.slot_u_stride, nL, n, c->stream));
+    for (int l = L; l > m0; --l) {
+      int nf = level_n(l), nc = level_n(l - 1);
+      HIPCHK(pprs_k::restrict_planes(hd.ubuf + hd.u_off[l], hd.slot_u_stride, (long long)nf * nf,
+                                     hd.ubuf + hd.u_off[l - 1], hd.slot_u_stride,
+                                     (long long)nc * nc, 2, nf, 2 * n, c->stream));
+    }
+  }
+  // steps
+  size_t lds = smooth_lds_bytes(hd);
+  int K = p->ladder_k;
+  long long passes_per_iter = 2 + (long long)ceil(log2(1.0 / p->tau_min_rel) / (2 * K + 1));
+  long long max_steps =
+      (long long)p->levels * ((long long)p->iter_max + 2) * (passes_per_iter + 2) + 64;
+  long long done_steps = 0;
+  int group = 4;
+  while (true) {
+    for (int k = 0; k < group; ++k) STCHK(launch_step(c, d, K, lds));
+    done_steps += group;
+    int active = 0;
+    HIPCHK(hipMemcpyAsync(&active, &d->active, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->timing) STCHK(tk_collect(c));
+    if (active == 0) break;
+    if (done_steps > max_steps)
+      return fail(PPRS_ESTATE, "batch did not finish within %lld steps", max_steps);
+    group = std::min(group * 2, 32);
+  }
+  HIPCHK(pprs_k::finish(d, didx + 2 * n, elems, est, (long long)n * est, c->stream));
+  // statistics
+  HIPCHK(hipMemcpyAsync(st.data(), hd.state, sizeof(SlotState) * n, hipMemcpyDeviceToHost,
+                        c->stream));
+  std::vector<long long> nodes((size_t)n * WK_COUNT);
+  HIPCHK(hipMemcpyAsync(nodes.data(), hd.node_count, sizeof(long long) * WK_COUNT * n,
+                        hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int s = 0; s < n; ++s) {
+    if (flags_or) *flags_or |= st[s].flags;
+    for (int k = 0; k < WK_COUNT; ++k) c->nodes_acc[k] += nodes[(size_t)s * WK_COUNT + k];
+    for (int l = m0; l <= L; ++l) {
+      long long nn = (long long)level_n(l) * level_n(l);
+      if (node_steps) *node_steps += nn * st[s].iters[l - m0];
+      if (node_passes) *node_passes += nn * st[s].passes[l - m0];
+    }
+    if (stats) {
+      pprs_pair_stats& o = stats[s];
+      memset(&o, 0, sizeof o);
+      for (int l = m0; l <= L; ++l) {
+        o.iters[l - m0] = st[s].iters[l - m0];
+        o.passes[l - m0] = st[s].passes[l - m0];
+      }
+      o.energy = st[s].E;
+      o.ncc = st[s].ncc;
+      o.flags = st[s].flags;
+    }
+  }
+  return PPRS_OK;
+}
+
+pprs_status status_from_flags(int flags) {
+  if (flags & PPRS_FLAG_NAN) return fail(PPRS_ENAN, "a registration produced a non-finite energy");
+  if (flags & PPRS_FLAG_NONCONV) return PPRS_NOT_CONVERGED;
+  return PPRS_OK;
+}
+
+pprs_status enter(pprs_ctx* c) {
+  if (!c) return fail(PPRS_EINVAL, "ctx is NULL");
+  HIPCHK(hipSetDevice(c->device));
+  return PPRS_OK;
+}
+
+}  // namespace
+
+// ---- C-ABI ---------------------------------------------------------------------------------
+
+extern "C" {
+
+void pprs_default_params(pprs_params* p) {
+  if (!p) return;
+  p->levels = 4;
+  p->lambda = 10.0;
+  p->beta = 1.0;
+  p->armijo_sigma = 0.5;
+  p->ladder_k = 1;
+  p->step_cap = 1.0;
+  p->tau_min_rel = 1e-4;
+  p->eps = 3e-4;
+  p->iter_max = 500;
+  p->scan = PPRS_SCAN_BRENT_KUNG;
+}
+
+const char* pprs_last_error(void) { return g_err.c_str(); }
+
+pprs_status pprs_create(pprs_ctx** out, int device, void* stream) {
+  if (!out) return fail(PPRS_EINVAL, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  HIPCHK(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count)
+    return fail(PPRS_EINVAL, "device %d out of range (%d devices)", device, count);
+  HIPCHK(hipSetDevice(device));
+  pprs_ctx* c = new pprs_ctx();
+  memset(&c->hd, 0, sizeof(BatchDesc));
+  c->device = device;
+  if (stream) {
+    c->stream = (hipStream_t)stream;
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete c;
+      return fail(PPRS_EHIP, "hipStreamCreate failed: %s", hipGetErrorString(e));
+    }
+    c->own_stream = true;
+  }
+  hipError_t e = hipHostMalloc((void**)&c->active_host, sizeof(int), hipHostMallocDefault);
+  if (e != hipSuccess) c->active_host = nullptr;
+  *out = c;
+  return PPRS_OK;
+}
+
+void pprs_destroy(pprs_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  DevBuf* bufs[] = {&c->frames, &c->rsum, &c->fr_ms, &c->fr_part, &c->state, &c->ubuf,
+                    &c->dbuf, &c->gbuf, &c->zbuf, &c->partial, &c->counters, &c->nodecount,
+                    &c->coef, &c->list_slots, &c->list_off, &c->lists, &c->desc, &c->opidx,
+                    &c->elems};
+  for (DevBuf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  if (c->active_host) (void)hipHostFree(c->active_host);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+pprs_status pprs_register_pair(pprs_ctx* c, const float* f_ref, const float* f_tmpl, int H,
+                               int W, const float* u_init, float* u_out,
+                               const pprs_params* params, pprs_pair_stats* stats) {
+  STCHK(enter(c));
+  int L = frame_level(H, W);
+  if (L < 0) return fail(PPRS_EINVAL, "frames must be square with side 2^L or 2^L+1, L in [2,11]");
+  if (!f_ref || !f_tmpl || !u_out) return fail(PPRS_EINVAL, "NULL frame or output pointer");
+  STCHK(check_params(params, L));
+  int m0 = L - params->levels + 1;
+  int nL = level_n(L);
+  size_t plane = (size_t)H * W;
+  // stage both frames contiguously, then build the pyramids
+  STCHK(ensure(c->elems, sizeof(float) * std::max(2 * plane, (size_t)2 * nL * nL)));
+  float* stage = P<float>(c->elems);
+  HIPCHK(hipMemcpyAsync(stage, f_ref, sizeof(float) * plane, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(stage + plane, f_tmpl, sizeof(float) * plane, hipMemcpyDeviceToDevice,
+                        c->stream));
+  STCHK(prepare_frames(c, stage, 2, H, L, m0, 1));
+  STCHK(ensure_slots(c, 1, L, m0, params->beta));
+  InitKind init = INIT_IDENTITY;
+  if (u_init) {
+    init = INIT_GIVEN;
+    HIPCHK(pprs_k::to_nodes(u_init, H, (long long)plane, c->hd.ubuf + c->hd.u_off[L], nL,
+                            (long long)nL * nL, 2, 1.0f / (float)(nL - 1), c->stream));
+  }
+  int ref = 0, tmpl = 1, out = 0;
+  int flags = 0;
+  STCHK(run_batch(c, 1, &ref, &tmpl, init, nullptr, nullptr, &out, stage, params, stats,
+                  nullptr, nullptr, &flags));
+  HIPCHK(pprs_k::from_nodes(stage, nL, (long long)nL * nL, u_out, H, (long long)plane, 2,
+                            (float)(nL - 1), c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return status_from_flags(flags);
+}
+
+pprs_status pprs_compose_deformations(pprs_ctx* c, const float* u_ij, const float* u_jk,
+                                      float* u_ik, int H, int W) {
+  STCHK(enter(c));
+  int L = frame_level(H, W);
+  if (L < 0) return fail(PPRS_EINVAL, "fields must be square with side 2^L or 2^L+1");
+  if (!u_ij || !u_jk || !u_ik) return fail(PPRS_EINVAL, "NULL field pointer");
+  int nL = level_n(L);
+  long long est = 2LL * nL * nL;
+  size_t plane = (size_t)H * W;
+  STCHK(ensure(c->elems, sizeof(float) * 3 * est));
+  STCHK(ensure(c->opidx, sizeof(int) * 3));
+  float* e = P<float>(c->elems);
+  float s = 1.0f / (float)(nL - 1);
+  HIPCHK(pprs_k::to_nodes(u_ij, H, (long long)plane, e, nL, (long long)nL * nL, 2, s, c->stream));
+  HIPCHK(pprs_k::to_nodes(u_jk, H, (long long)plane, e + est, nL, (long long)nL * nL, 2, s,
+                          c->stream));
+  int idx[3] = {0, 1, 0};
+  int* didx = P<int>(c->opidx);
+  HIPCHK(hipMemcpyAsync(didx, idx, sizeof idx, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(pprs_k::compose(e, est, didx, didx + 1, e + 2 * est, est, nL, 1, c->stream));
+  HIPCHK(pprs_k::from_nodes(e + 2 * est, nL, (long long)nL * nL, u_ik, H, (long long)plane, 2,
+                            (float)(nL - 1), c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return PPRS_OK;
+}
+
+pprs_status pprs_prefix_register_series(pprs_ctx* c, const float* frames, int N, int H, int W,
+                                        float* u_out, const pprs_params* params,
+                                        pprs_series_stats* stats, pprs_pair_stats* op_stats) {
+  STCHK(enter(c));
+  int L = frame_level(H, W);
+  if (L < 0) return fail(PPRS_EINVAL, "frames must be square with side 2^L or 2^L+1, L in [2,11]");
+  if (N < 1) return fail(PPRS_EINVAL, "N must be >= 1");
+  if (!frames || !u_out) return fail(PPRS_EINVAL, "NULL frames or output pointer");
+  STCHK(check_params(params, L));
+  int m0 = L - params->levels + 1;
+  int nL = level_n(L);
+  int M = N - 1;
+  size_t plane = (size_t)H * W;
+  hipEvent_t e0, e1, e2, e3;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventCreate(&e2));
+  HIPCHK(hipEventCreate(&e3));
+  HIPCHK(hipEventRecord(e0, c->stream));
+  pprs_series_stats S;
+  memset(&S, 0, sizeof S);
+  HIPCHK(pprs_k::fill(u_out, 2LL * (long long)plane, 0.f, c->stream));
+  if (M >= 1) {
+    STCHK(prepare_frames(c, frames, N, H, L, m0, N - 1));
+  }
+  HIPCHK(hipEventRecord(e1, c->stream));
+  // schedule
+  std::vector<int> ops;
+  int n_ops = 0, n_levels = 0;
+  pprs_scan_plan(params->scan, std::max(M, 0), nullptr, 0, &n_ops, &n_levels);  // sizes only
+  ops.resize(3 * (size_t)std::max(n_ops, 1));
+  if (pprs_scan_plan(params->scan, std::max(M, 0), ops.data(), n_ops, &n_ops, &n_levels) != PPRS_OK)
+    return fail(PPRS_EINVAL, "scan planning failed");
+  int widest = M;
+  for (int lv = 0, i = 0; lv < n_levels; ++lv) {
+    int cnt = 0;
+    while (i < n_ops && ops[3 * i + 2] == lv) ++cnt, ++i;
+    widest = std::max(widest, cnt);
+  }
+  int flags = 0;
+  if (M >= 1) {
+    long long est = 2LL * nL * nL;
+    STCHK(ensure(c->elems, sizeof(float) * est * M));
+    STCHK(ensure_slots(c, widest, L, m0, params->beta));
+    float* elems = P<float>(c->elems);
+    // preprocessing: A on all neighbour pairs (one batch)
+    std::vector<int> ref(M), tmpl(M), out(M), ei(M), ek(M);
+    for (int m = 0; m < M; ++m) {
+      ref[m] = m;
+      tmpl[m] = m + 1;
+      out[m] = m;
+      ei[m] = m;
+      ek[m] = m + 1;
+    }
+    STCHK(run_batch(c, M, ref.data(), tmpl.data(), INIT_IDENTITY, nullptr, nullptr, out.data(),
+                    elems, params, op_stats, &S.node_steps, &S.node_passes, &flags));
+    HIPCHK(hipEventRecord(e2, c->stream));
+    // scan: every level of the schedule is one batch of B applications
+    int done = 0;
+    for (int lv = 0, i = 0; lv < n_levels; ++lv) {
+      std::vector<int> lft, rgt, r2, t2;
+      while (i < n_ops && ops[3 * i + 2] == lv) {
+        int a = ops[3 * i], b = ops[3 * i + 1];
+        if (ek[a] != ei[b])
+          return fail(PPRS_EINDEX, "scan operands (%d,%d) and (%d,%d) do not share a frame",
+                      ei[a], ek[a], ei[b], ek[b]);
+        lft.push_back(a);
+        rgt.push_back(b);
+        r2.push_back(ei[a]);
+        t2.push_back(ek[b]);
+        ++i;
+      }
+      int cnt = (int)lft.size();
+      STCHK(run_batch(c, cnt, r2.data(), t2.data(), INIT_COMPOSE, lft.data(), rgt.data(),
+                      rgt.data(), elems, params, op_stats ? op_stats + M + done : nullptr,
+                      &S.node_steps, &S.node_passes, &flags));
+      for (int k = 0; k < cnt; ++k) ei[rgt[k]] = ei[lft[k]];
+      done += cnt;
+    }
+    for (int m = 0; m < M; ++m)
+      if (ei[m] != 0 || ek[m] != m + 1)
+        return fail(PPRS_EINDEX, "element %d ends as (%d,%d)", m, ei[m], ek[m]);
+    HIPCHK(pprs_k::from_nodes(elems, nL, (long long)nL * nL, u_out + 2 * plane, H,
+                              (long long)plane, 2 * M, (float)(nL - 1), c->stream));
+  } else {
+    HIPCHK(hipEventRecord(e2, c->stream));
+  }
+  HIPCHK(hipEventRecord(e3, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
+  (void)hipEventElapsedTime(&t01, e0, e1);
+  (void)hipEventElapsedTime(&t12, e1, e2);
+  (void)hipEventElapsedTime(&t23, e2, e3);
+  (void)hipEventElapsedTime(&t03, e0, e3);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
+  (void)hipEventDestroy(e3);
+  S.n_ops_a = M;
+  S.n_ops_b = n_ops;
+  S.n_scan_levels = n_levels;
+  S.flags_or = flags;
+  S.ms_total = t03;
+  S.ms_prepare = t01;
+  S.ms_preprocess = t12;
+  S.ms_scan = t23;
+  if (stats) *stats = S;
+  return status_from_flags(flags);
+}
+
+pprs_status pprs_set_kernel_timing(pprs_ctx* c, int enable) {
+  STCHK(enter(c));
+  c->timing = enable != 0;
+  return PPRS_OK;
+}
+
+pprs_status pprs_get_kernel_timing(pprs_ctx* c, double* ms, long long* launches, double* bytes,
+                                   int cap, int* n_kinds, int reset) {
+  if (!c) return fail(PPRS_EINVAL, "ctx is NULL");
+  if (n_kinds) *n_kinds = TK_COUNT;
+  // node counts per work kind -> bytes per timing kind
+  const int wk_of_tk[TK_COUNT] = {-1, WK_PROLONG, WK_EVAL, WK_GRAD, WK_SMY, WK_SMX, WK_LADDER};
+  for (int k = 0; k < TK_COUNT && k < cap; ++k) {
+    if (ms) ms[k] = c->t_ms[k];
+    if (launches) launches[k] = c->t_launch[k];
+    if (bytes) bytes[k] = wk_of_tk[k] < 0 ? 0.0 : kBytesPerNode[k] * c->nodes_acc[wk_of_tk[k]];
+  }
+  if (reset) {
+    for (int k = 0; k < TK_COUNT; ++k) {
+      c->t_ms[k] = 0;
+      c->t_launch[k] = 0;
+    }
+    for (int k = 0; k < WK_COUNT; ++k) c->nodes_acc[k] = 0;
+  }
+  return PPRS_OK;
+}
+
+const char* pprs_kernel_name(int kind) {
+  if (kind < 0 || kind >= TK_COUNT) return "unknown";
+  return kTkName[kind];
+}
+
+}  // extern "C"

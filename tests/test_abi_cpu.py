@@ -1,0 +1,98 @@
+"""Host-side tests of libpprs (no GPU): the library loads and exports every symbol declared in
+include/pprs.h, and the scan planner (pure host logic) produces correct schedules."""
+import json
+import math
+import os
+import re
+import ctypes
+
+import numpy as np
+import pytest
+
+import paper_1712_02533_amd as P
+from paper_1712_02533_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLD = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_values.json")))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "pprs.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pprs_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(api.LIB_PATH)
+    syms = declared_symbols()
+    assert len(syms) >= 11
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+def test_default_params_match_binding_defaults():
+    assert P.default_params() == P.Params()
+
+
+def _apply(plan, xs, op):
+    xs = list(xs)
+    for left, right, _ in plan:
+        xs[right] = op(xs[left], xs[right])
+    return xs
+
+
+def _interval(a, b):
+    assert a[1] == b[0], "operands do not share their middle index"
+    return (a[0], b[1])
+
+
+@pytest.mark.parametrize("kind", ["sequential", "brent_kung"])
+@pytest.mark.parametrize("M", [0, 1, 2, 3, 7, 8, 9, 63, 64, 100, 511])
+def test_plan_matches_sequential_scan_with_associative_ops(kind, M):
+    plan, levels = P.scan_plan(kind, M)
+    # interval concatenation: exactly associative, non-commutative, checks index matching
+    xs = [(m, m + 1) for m in range(M)]
+    assert _apply(plan, xs, _interval) == [(0, m + 1) for m in range(M)]
+    # 2x2 integer matrix products (exact, non-commutative)
+    rng = np.random.default_rng(M)
+    mats = [rng.integers(-2, 3, size=(2, 2)) for _ in range(M)]
+    got = _apply(plan, mats, lambda a, b: a @ b)
+    acc = None
+    for m in range(M):
+        acc = mats[m] if acc is None else acc @ mats[m]
+        assert np.array_equal(got[m], acc)
+    # ops of one level are independent: no op reads an element written in the same level
+    by_level = {}
+    for left, right, lv in plan:
+        by_level.setdefault(lv, []).append((left, right))
+    for ops in by_level.values():
+        written = {r for _, r in ops}
+        assert not any(l in written for l, _ in ops)
+        assert len(written) == len(ops)
+    assert len(by_level) == levels
+
+
+def test_plan_counts_match_paper_figures_and_table():
+    fig = GOLD["scan_figures_N8"]
+    for kind in ("sequential", "brent_kung"):
+        plan, levels = P.scan_plan(kind, 8)
+        assert len(plan) == fig[kind]["ops"] and levels == fig[kind]["steps"]
+    for k in range(1, 11):
+        N = 2 ** k
+        plan, levels = P.scan_plan("brent_kung", N)
+        assert len(plan) == 2 * N - k - 2                 # work, Brent-Kung row of the table
+        assert levels == max(2 * k - 1, 1) if N > 1 else True  # span
+        assert len(plan) + levels >= 2 * N - 2            # Snir: size + depth >= 2N - 2
+        plan, levels = P.scan_plan("sequential", N)
+        assert len(plan) == N - 1 and levels == N - 1
+
+
+def test_plan_rejects_bad_arguments():
+    n = ctypes.c_int()
+    lv = ctypes.c_int()
+    lib = api._lib()
+    assert lib.pprs_scan_plan(7, 8, None, 0, ctypes.byref(n), ctypes.byref(lv)) == -1
+    assert lib.pprs_scan_plan(1, -1, None, 0, ctypes.byref(n), ctypes.byref(lv)) == -1
+    buf = (ctypes.c_int * 3)()
+    assert lib.pprs_scan_plan(1, 8, buf, 1, ctypes.byref(n), ctypes.byref(lv)) == -1
+    assert n.value == 11
