@@ -120,7 +120,7 @@ pprs_status pprs_compose_deformations(pprs_ctx* ctx, const float* u_ij, const fl
    f_i o phi_{0,i} ~ f_0. The neighbour registrations run as one batch; the scan runs the B
    applications of each schedule level as one batch. stats and op_stats are host pointers and
    may be NULL; op_stats receives N-1 A entries followed by the B entries in schedule order
-   (at most 2N). */
+   (pprs_scan_plan gives their count, at most 2(N-1)), so 3N entries always suffice. */
 pprs_status pprs_prefix_register_series(pprs_ctx* ctx, const float* frames, int N, int H,
                                         int W, float* u_out, const pprs_params* params,
                                         pprs_series_stats* stats, pprs_pair_stats* op_stats);

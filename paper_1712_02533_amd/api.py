@@ -251,7 +251,7 @@ def prefix_register_series(frames, params: Params | None = None, out=None,
     ss = _CSeriesStats()
     ops = None
     if want_op_stats:
-        ops = (_CPairStats * max(2 * N, 1))()
+        ops = (_CPairStats * max(3 * N, 1))()   # N-1 A entries + at most 2(N-1) B entries
     cp = params.c()
     c = _ctx(frames.device)
     _check(_lib().pprs_prefix_register_series(

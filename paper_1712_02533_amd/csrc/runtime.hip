@@ -9,6 +9,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -77,6 +78,7 @@ struct pprs_ctx {
   // scan elements [M][2][nL^2] and staging
   DevBuf elems;
   int* active_host = nullptr;
+  bool log = false;  // one progress line per batch on stderr (environment PPRS_LOG=1)
   BatchDesc hd;
   int slots_cap = 0, slots_L = -1, slots_m0 = -1;
   double coef_beta = -1.0;
@@ -451,6 +453,11 @@ pprs_status run_batch(pprs_ctx* c, int n, const int* ref, const int* tmpl, InitK
     group = std::min(group * 2, 32);
   }
   HIPCHK(pprs_k::finish(d, didx + 2 * n, elems, est, (long long)n * est, c->stream));
+  if (c->log) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    fprintf(stderr, "[pprs] batch of %d registrations done after %lld steps\n", n, done_steps);
+    fflush(stderr);
+  }
   // statistics
   HIPCHK(hipMemcpyAsync(st.data(), hd.state, sizeof(SlotState) * n, hipMemcpyDeviceToHost,
                         c->stream));
@@ -526,6 +533,8 @@ pprs_status pprs_create(pprs_ctx** out, int device, void* stream) {
   pprs_ctx* c = new pprs_ctx();
   memset(&c->hd, 0, sizeof(BatchDesc));
   c->device = device;
+  const char* lg = getenv("PPRS_LOG");
+  c->log = lg && lg[0] && lg[0] != '0';
   if (stream) {
     c->stream = (hipStream_t)stream;
   } else {
