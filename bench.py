@@ -34,18 +34,24 @@ def log(*a):
 
 
 def traffic_from_profiles(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, when it
-    was taken for the current kernel source (its recorded source hash matches)."""
-    path = os.path.join(ROOT, "profiles", "counters_%s.json" % kernel)
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (profiles/counters_<kernel>.md), if it was taken for the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "counters_%s.md" % kernel)
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path))
         import hashlib
+        rec = {}
+        for line in open(path):
+            line = line.strip()
+            if ":" in line and line.split(":")[0] in ("kernel", "kernels_hip_sha256",
+                                                      "hbm_bytes_per_launch"):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
         src = open(os.path.join(ROOT, "paper_1712_02533_amd", "csrc", "kernels.hip"), "rb").read()
         if rec.get("kernels_hip_sha256") != hashlib.sha256(src).hexdigest():
             return None
-        return rec.get("hbm_bytes_per_launch")
+        return float(rec["hbm_bytes_per_launch"])
     except Exception:
         return None
 
