@@ -11,7 +11,7 @@
  *
  * Conventions shared by every entry point:
  *  - Frames are float32, row-major [H][W], with H == W and either H == 2^L (pixels; the grid
- *    gets one replicated row and column) or H == 2^L + 1 (grid nodes). 2 <= L <= 11.
+ *    gets one replicated row and column) or H == 2^L + 1 (grid nodes). 2 <= L <= 10.
  *  - A displacement u = phi - id is float32 [2][H][W]: plane 0 is the x (column) component,
  *    plane 1 the y (row) component, in pixels of the finest level. phi maps reference
  *    coordinates to template coordinates: template(x + u(x)) ~ reference(x).

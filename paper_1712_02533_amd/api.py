@@ -274,7 +274,7 @@ def set_kernel_timing(enable: bool, device=None):
 
 def kernel_names():
     lib = _lib()
-    return [lib.pprs_kernel_name(k).decode() for k in range(7)]
+    return [lib.pprs_kernel_name(k).decode() for k in range(8)]
 
 
 def kernel_timing(reset: bool = False, device=None):

@@ -7,6 +7,8 @@ namespace pprs_k {
 hipError_t plan(BatchDesc* d, hipStream_t st);
 hipError_t prolong(BatchDesc* d, int grid, hipStream_t st);
 hipError_t energy(BatchDesc* d, int mode, int ladder_k, int grid, hipStream_t st);
+hipError_t energy_fin(BatchDesc* d, int mode, int ladder_k, int grid, hipStream_t st);
+hipError_t smooth_fin(BatchDesc* d, int grid, hipStream_t st);
 hipError_t grad(BatchDesc* d, int grid, hipStream_t st);
 hipError_t smooth(BatchDesc* d, int dir, int grid, size_t lds_bytes, hipStream_t st);
 hipError_t set_smooth_lds(size_t bytes);

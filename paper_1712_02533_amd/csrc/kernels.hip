@@ -142,26 +142,6 @@ __device__ __forceinline__ void cursor_slot(const BatchDesc* D, int kind, ItemCu
   local = c.item - off[c.pos];
 }
 
-// Ticket: returns true in every thread of the workgroup that completed the slot's last item.
-__device__ bool last_ticket(const BatchDesc* D, int slot, int kind, int n_items, int* s_flag) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    int* cnt = D->counters + (size_t)slot * WK_COUNT + kind;
-    int t = atomicAdd(cnt, 1);
-    int last = (t == n_items - 1);
-    if (last) {
-      *cnt = 0;
-      __threadfence();
-    }
-    *s_flag = last;
-  }
-  __syncthreads();
-  bool last = *s_flag != 0;
-  if (last) __threadfence();
-  return last;
-}
-
 __device__ __forceinline__ double* slot_partial(const BatchDesc* D, int s, int kind, int item) {
   return D->partial + (size_t)s * D->part_slot_stride + (size_t)kind * D->part_kind_stride +
          (size_t)item * PW;
@@ -187,39 +167,31 @@ __device__ void sum_partials(const BatchDesc* D, int s, int kind, int n_items, i
 // Planning kernel: one workgroup of 1024 threads.
 
 #define PLAN_T 1024
+#define PLAN_V (2 * WK_COUNT)
 
-__device__ int block_excl_scan(int v, int* s, int& total) {
-  int tid = threadIdx.x;
-  s[tid] = v;
-  __syncthreads();
-  for (int o = 1; o < PLAN_T; o <<= 1) {
-    int x = tid >= o ? s[tid - o] : 0;
-    __syncthreads();
-    s[tid] += x;
-    __syncthreads();
-  }
-  int incl = s[tid];
-  total = s[PLAN_T - 1];
-  __syncthreads();
-  return incl - v;
-}
-
+// One workgroup: per kind, the compacted list of member slots and the prefix sum of their
+// item counts. Wave-level shuffle scans, then a scan over the 16 wave totals.
 __global__ void __launch_bounds__(PLAN_T) k_plan(BatchDesc* D) {
-  __shared__ int s_scan[PLAN_T];
-  __shared__ int s_red[PLAN_T / 64];
-  int carry_cnt[WK_COUNT], carry_items[WK_COUNT];
-  for (int k = 0; k < WK_COUNT; ++k) carry_cnt[k] = carry_items[k] = 0;
+  __shared__ int s_wtot[PLAN_T / 64][PLAN_V];
+  __shared__ int s_woff[PLAN_T / 64][PLAN_V];
+  __shared__ int s_carry[PLAN_V];
+  __shared__ int s_active[PLAN_T / 64];
+  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (threadIdx.x < PLAN_V) s_carry[threadIdx.x] = 0;
   int n_slots = D->n_slots;
   int active = 0;
+  __syncthreads();
   for (int base = 0; base < n_slots; base += PLAN_T) {
     int s = base + threadIdx.x;
     int ph = PH_DONE, eff = 0;
     if (s < n_slots) {
-      SlotState* st = D->state + s;
+      const SlotState* st = D->state + s;
       ph = st->phase;
       eff = ph == PH_PROLONG ? st->level + 1 : st->level;
     }
     active += ph != PH_DONE;
+    int val[PLAN_V];
+#pragma unroll
     for (int k = 0; k < WK_COUNT; ++k) {
       bool m;
       switch (k) {
@@ -228,33 +200,57 @@ __global__ void __launch_bounds__(PLAN_T) k_plan(BatchDesc* D) {
         case WK_LADDER: m = ph != PH_DONE; break;
         default: m = ph == PH_PROLONG || ph == PH_INIT || ph == PH_GRAD; break;
       }
-      int items = m ? kind_items(D, k, eff) : 0;
-      int tc, ti;
-      int pc = block_excl_scan(m ? 1 : 0, s_scan, tc);
-      int pi = block_excl_scan(items, s_scan, ti);
-      if (m) {
-        D->list_slots[(size_t)k * D->max_slots + carry_cnt[k] + pc] = s;
-        D->list_off[(size_t)k * (D->max_slots + 1) + carry_cnt[k] + pc] = carry_items[k] + pi;
-      }
-      carry_cnt[k] += tc;
-      carry_items[k] += ti;
+      val[2 * k] = m ? 1 : 0;
+      val[2 * k + 1] = m ? kind_items(D, k, eff) : 0;
     }
+    int inc[PLAN_V];
+#pragma unroll
+    for (int v = 0; v < PLAN_V; ++v) inc[v] = val[v];
+    for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+      for (int v = 0; v < PLAN_V; ++v) {
+        int x = __shfl_up(inc[v], off, 64);
+        if (lane >= off) inc[v] += x;
+      }
+    }
+    if (lane == 63)
+#pragma unroll
+      for (int v = 0; v < PLAN_V; ++v) s_wtot[wv][v] = inc[v];
+    __syncthreads();
+    if (threadIdx.x < PLAN_V) {
+      int v = threadIdx.x, acc = s_carry[v];
+      for (int w = 0; w < PLAN_T / 64; ++w) {
+        s_woff[w][v] = acc;
+        acc += s_wtot[w][v];
+      }
+      s_carry[v] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < WK_COUNT; ++k) {
+      if (val[2 * k]) {
+        int pos = s_woff[wv][2 * k] + inc[2 * k] - 1;
+        int off = s_woff[wv][2 * k + 1] + inc[2 * k + 1] - val[2 * k + 1];
+        D->list_slots[(size_t)k * D->max_slots + pos] = s;
+        D->list_off[(size_t)k * (D->max_slots + 1) + pos] = off;
+      }
+    }
+    __syncthreads();
   }
-  // active count
-  int a = active;
-  for (int o = 32; o > 0; o >>= 1) a += __shfl_down(a, o, 64);
-  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = a;
+  for (int o = 32; o > 0; o >>= 1) active += __shfl_down(active, o, 64);
+  if (lane == 0) s_active[wv] = active;
   __syncthreads();
   if (threadIdx.x == 0) {
     int tot = 0;
-    for (int w = 0; w < PLAN_T / 64; ++w) tot += s_red[w];
+    for (int w = 0; w < PLAN_T / 64; ++w) tot += s_active[w];
     D->active = tot;
-    if (D->active_host) *(volatile int*)D->active_host = tot;
-    for (int k = 0; k < WK_COUNT; ++k) {
-      D->list_off[(size_t)k * (D->max_slots + 1) + carry_cnt[k]] = carry_items[k];
-      D->lists[k].n_slots = carry_cnt[k];
-      D->lists[k].total = carry_items[k];
-    }
+  }
+  if (threadIdx.x < WK_COUNT) {
+    int k = threadIdx.x;
+    int cnt = s_carry[2 * k], items = s_carry[2 * k + 1];
+    D->list_off[(size_t)k * (D->max_slots + 1) + cnt] = items;
+    D->lists[k].n_slots = cnt;
+    D->lists[k].total = items;
   }
 }
 
@@ -302,12 +298,6 @@ __global__ void __launch_bounds__(BLOCK) k_prolong(BatchDesc* D) {
   }
 }
 
-// ------------------------------------------------------------------------------------------
-// Energy kernel. MODE 0: energy of the starting u of a level (slots in INIT or PROLONG).
-// MODE 1: one line-search pass at 2K+1 step sizes (slots in LADDER).
-// Per element tile: quadrature sums S1 = sum w T, S2 = sum w T^2, S3 = sum w R~ T for each
-// candidate, and the Dirichlet terms u^T K u, d^T K u, d^T K d via element matrices.
-
 // Element stiffness (Q1, h-independent in 2-D), corners ordered 00, 01, 10, 11: diagonal 2/3,
 // edge pairs -1/6, opposite pairs -1/3. Its rows sum to zero, so the bilinear form is written
 // with node differences, which keeps FP32 free of cancellation for nearly constant fields:
@@ -330,12 +320,99 @@ __device__ __forceinline__ void ke_apply(const float u[4], float out[4]) {
   out[3] = (1.f / 6.f) * (-d13 - d23) - (1.f / 3.f) * d03;
 }
 
+// ------------------------------------------------------------------------------------------
+// Energy kernel. MODE 0: energy of the starting u of a level (slots in INIT or PROLONG).
+// MODE 1: one line-search pass at NC = 2K+1 step sizes (slots in LADDER).
+// Per element tile: quadrature sums S1 = sum w T, S2 = sum w T^2, S3 = sum w R~ T for each
+// step size, and the Dirichlet terms u^T K u, d^T K u, d^T K d via element matrices.
+
 template <int MODE, int NC>
-__global__ void __launch_bounds__(BLOCK) k_energy(BatchDesc* D) {
-  constexpr int NN = (ET_X + 1) * (ET_Y + 1);
+__device__ __noinline__ void energy_finalize(BatchDesc* D, SlotState* stp, int s, int l, int n, int ph,
+                                double top, const double* tot) {
+  SlotState& st = *stp;
+  const int kind = MODE ? WK_LADDER : WK_EVAL;
+  int K = D->ladder_k;
+  double rs = D->rsum[(size_t)st.ref * PPRS_MAXL + l];
+  double e_j[NC], ncc_j[NC], m_j[NC], sg_j[NC];
+  for (int j = 0; j < NC; ++j) {
+    double m = tot[3 * j], var = tot[3 * j + 1] - m * m;
+    double sg = var > 0.0 ? sqrt(var) : 0.0;
+    double ncc = sg > 0.0 ? (tot[3 * j + 2] - m * rs) / sg : 0.0;
+    double tj = MODE ? ldexp(top, -j) : 0.0;
+    double reg = tot[3 * NC] - 2.0 * tj * tot[3 * NC + 1] + tj * tj * tot[3 * NC + 2];
+    e_j[j] = -ncc + 0.5 * D->lambda * reg;
+    ncc_j[j] = ncc;
+    m_j[j] = m;
+    sg_j[j] = sg;
+  }
+  long long* nc_s = D->node_count + (size_t)s * WK_COUNT;
+  nc_s[kind] += (long long)n * n;
+  if (MODE == 0 && ph == PH_PROLONG) nc_s[WK_PROLONG] += (long long)n * n;
+  if (MODE == 0) {
+    if (ph == PH_PROLONG) {
+      st.level = l;
+      st.ub = 0;
+    }
+    st.iter = 0;
+    st.tau_prev = INFINITY;
+    st.tau_pend = 0.0;
+    st.E = e_j[0];
+    st.ncc = ncc_j[0];
+    st.mean = m_j[0];
+    st.sigma = sg_j[0];
+    if (!isfinite(st.E)) {
+      st.flags |= FLAG_NAN;
+      st.phase = PH_DONE;
+    } else if (D->iter_max <= 0) {
+      level_done(st);
+    } else {
+      st.phase = PH_GRAD;
+    }
+  } else {
+    int li = st.level - st.coarsest;
+    st.passes[li]++;
+    int acc_j = -1;
+    for (int j = 0; j < NC; ++j) {
+      double tj = ldexp(top, -j);
+      if (e_j[j] <= st.E - D->sigma * tj * st.gtd) {
+        acc_j = j;
+        break;
+      }
+    }
+    if (acc_j >= 0) {
+      double tj = ldexp(top, -acc_j);
+      double dec = st.E - e_j[acc_j];
+      st.E = e_j[acc_j];
+      st.ncc = ncc_j[acc_j];
+      st.mean = m_j[acc_j];
+      st.sigma = sg_j[acc_j];
+      st.tau_pend = tj;
+      st.tau_prev = tj;
+      st.iter++;
+      st.iters[li] = st.iter;
+      if (dec < D->eps) {
+        level_done(st);
+      } else if (st.iter >= D->iter_max) {
+        st.flags |= FLAG_NONCONV;
+        level_done(st);
+      } else {
+        st.phase = PH_GRAD;
+      }
+    } else {
+      st.top = ldexp(top, -(2 * K + 1));
+      if (st.top < D->tau_min_rel * st.tau_max) level_done(st);
+      else st.phase = PH_LADDER;
+    }
+  }
+}
+
+template <int MODE, int NC>
+__global__ void __launch_bounds__(BLOCK, 4) k_energy(BatchDesc* D) {
+  constexpr int NXN = ET_X + 1, NYN = ET_Y + 1, NN = NXN * NYN;
+  constexpr int NV = 3 * NC + 3;
   __shared__ float s_ux[NN], s_uy[NN], s_dx[MODE ? NN : 1], s_dy[MODE ? NN : 1], s_r[NN];
-  __shared__ double s_red[(BLOCK / 64) * PW];
-  __shared__ int s_pos, s_flag;
+  __shared__ double s_red[(BLOCK / 64) * NV];
+  __shared__ int s_pos;
   const int kind = MODE ? WK_LADDER : WK_EVAL;
   ItemCursor c;
   if (!cursor_begin(D, kind, c, &s_pos)) return;
@@ -354,17 +431,17 @@ __global__ void __launch_bounds__(BLOCK) k_energy(BatchDesc* D) {
     const float* d = D->dbuf + (size_t)s * D->slot_f_stride;
     const float* R = D->frames[l] + (size_t)stp->ref * nn;
     const float* T = D->frames[l] + (size_t)stp->tmpl * nn;
-    int K = D->ladder_k;
-    constexpr int ncand = NC;
     double top = MODE ? stp->top : 0.0;
     float taus[NC];
 #pragma unroll
     for (int j = 0; j < NC; ++j) taus[j] = MODE ? (float)ldexp(top, -j) : 0.f;
+    float inv_h = (float)(n - 1);
     int ntx = (n - 1 + ET_X - 1) / ET_X;
     int e0x = (t % ntx) * ET_X, e0y = (t / ntx) * ET_Y;
-    // stage nodes [e0y, e0y+ET_Y] x [e0x, e0x+ET_X] (clipped)
+    // stage the nodes of the tile's elements
+    __syncthreads();
     for (int k = threadIdx.x; k < NN; k += BLOCK) {
-      int a = e0y + k / (ET_X + 1), b = e0x + k % (ET_X + 1);
+      int a = e0y + k / NXN, b = e0x + k % NXN;
       float ux = 0.f, uy = 0.f, dx = 0.f, dy = 0.f, r = 0.f;
       if (a < n && b < n) {
         size_t i = (size_t)a * n + b;
@@ -385,38 +462,38 @@ __global__ void __launch_bounds__(BLOCK) k_energy(BatchDesc* D) {
       }
     }
     __syncthreads();
-    constexpr int NV = 3 * NC + 3;
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    float inv_h = (float)(n - 1);
     float w = 0.25f / ((float)(n - 1) * (float)(n - 1));
     for (int e = threadIdx.x; e < ET_X * ET_Y; e += BLOCK) {
       int ey = e / ET_X, ex = e % ET_X;
       int a = e0y + ey, b = e0x + ex;
       if (a >= n - 1 || b >= n - 1) continue;
-      int k00 = ey * (ET_X + 1) + ex;
-      float ux[4] = {s_ux[k00], s_ux[k00 + 1], s_ux[k00 + ET_X + 1], s_ux[k00 + ET_X + 2]};
-      float uy[4] = {s_uy[k00], s_uy[k00 + 1], s_uy[k00 + ET_X + 1], s_uy[k00 + ET_X + 2]};
-      float rr[4] = {s_r[k00], s_r[k00 + 1], s_r[k00 + ET_X + 1], s_r[k00 + ET_X + 2]};
+      int k00 = ey * NXN + ex;
+      float ux[4] = {s_ux[k00], s_ux[k00 + 1], s_ux[k00 + NXN], s_ux[k00 + NXN + 1]};
+      float uy[4] = {s_uy[k00], s_uy[k00 + 1], s_uy[k00 + NXN], s_uy[k00 + NXN + 1]};
+      float rr[4] = {s_r[k00], s_r[k00 + 1], s_r[k00 + NXN], s_r[k00 + NXN + 1]};
       float dx[4] = {0, 0, 0, 0}, dy[4] = {0, 0, 0, 0};
       if (MODE) {
-        dx[0] = s_dx[k00]; dx[1] = s_dx[k00 + 1]; dx[2] = s_dx[k00 + ET_X + 1]; dx[3] = s_dx[k00 + ET_X + 2];
-        dy[0] = s_dy[k00]; dy[1] = s_dy[k00 + 1]; dy[2] = s_dy[k00 + ET_X + 1]; dy[3] = s_dy[k00 + ET_X + 2];
+        dx[0] = s_dx[k00]; dx[1] = s_dx[k00 + 1]; dx[2] = s_dx[k00 + NXN]; dx[3] = s_dx[k00 + NXN + 1];
+        dy[0] = s_dy[k00]; dy[1] = s_dy[k00 + 1]; dy[2] = s_dy[k00 + NXN]; dy[3] = s_dy[k00 + NXN + 1];
       }
       // Dirichlet terms
       acc[3 * NC + 0] += (double)(ke_form(ux[0], ux[1], ux[2], ux[3], ux[0], ux[1], ux[2], ux[3]) +
-                                        ke_form(uy[0], uy[1], uy[2], uy[3], uy[0], uy[1], uy[2], uy[3]));
+                                  ke_form(uy[0], uy[1], uy[2], uy[3], uy[0], uy[1], uy[2], uy[3]));
       if (MODE) {
         acc[3 * NC + 1] += (double)(ke_form(dx[0], dx[1], dx[2], dx[3], ux[0], ux[1], ux[2], ux[3]) +
-                                          ke_form(dy[0], dy[1], dy[2], dy[3], uy[0], uy[1], uy[2], uy[3]));
+                                    ke_form(dy[0], dy[1], dy[2], dy[3], uy[0], uy[1], uy[2], uy[3]));
         acc[3 * NC + 2] += (double)(ke_form(dx[0], dx[1], dx[2], dx[3], dx[0], dx[1], dx[2], dx[3]) +
-                                          ke_form(dy[0], dy[1], dy[2], dy[3], dy[0], dy[1], dy[2], dy[3]));
+                                    ke_form(dy[0], dy[1], dy[2], dy[3], dy[0], dy[1], dy[2], dy[3]));
       }
-      // quadrature points
+      float es[3 * NC];
 #pragma unroll
+      for (int k = 0; k < 3 * NC; ++k) es[k] = 0.f;
+#pragma unroll 1
       for (int p = 0; p < 2; ++p) {
-#pragma unroll
+#pragma unroll 1
         for (int q = 0; q < 2; ++q) {
           float xi = c_gp[q], eta = c_gp[p];
           float p0 = (1.f - xi) * (1.f - eta), p1 = xi * (1.f - eta), p2 = (1.f - xi) * eta, p3 = xi * eta;
@@ -433,105 +510,44 @@ __global__ void __launch_bounds__(BLOCK) k_energy(BatchDesc* D) {
             float tx = xi + (uqx - taus[j] * dqx) * inv_h;
             float ty = eta + (uqy - taus[j] * dqy) * inv_h;
             float tv = sample_bil<false>(T, n, b, tx, a, ty, inv_h, nullptr, nullptr);
-            float wt = w * tv;
-            acc[3 * j + 0] += (double)wt;
-            acc[3 * j + 1] += (double)(wt * tv);
-            acc[3 * j + 2] += (double)(wt * rq);
+            es[3 * j + 0] += tv;
+            es[3 * j + 1] += tv * tv;
+            es[3 * j + 2] += tv * rq;
           }
         }
       }
+#pragma unroll
+      for (int k = 0; k < 3 * NC; ++k) acc[k] += (double)(w * es[k]);
     }
-    // block reduction -> partial record
-    {
-      block_sum<NV>(acc, s_red);
-      if (threadIdx.x == 0) {
-        double* pr = slot_partial(D, s, kind, t);
-        for (int k = 0; k < NV; ++k) pr[k] = acc[k];
-      }
+    block_sum<NV>(acc, s_red);
+    if (threadIdx.x == 0) {
+      double* pr = slot_partial(D, s, kind, t);
+      for (int k = 0; k < NV; ++k) pr[k] = acc[k];
     }
-    int n_items = D->geom[l].tiles_elem;
-    if (last_ticket(D, s, kind, n_items, &s_flag)) {
-      double tot[NV];
-      sum_partials<NV>(D, s, kind, n_items, NV, tot, s_red, false);
-      if (threadIdx.x == 0) {
-        SlotState& st = *stp;
-        double rs = D->rsum[(size_t)st.ref * PPRS_MAXL + l];
-        double h = 1.0 / (n - 1);
-        double e_j[MAX_CAND], ncc_j[MAX_CAND], m_j[MAX_CAND], sg_j[MAX_CAND];
-        for (int j = 0; j < ncand; ++j) {
-          double m = tot[3 * j], var = tot[3 * j + 1] - m * m;
-          double sg = var > 0.0 ? sqrt(var) : 0.0;
-          double ncc = sg > 0.0 ? (tot[3 * j + 2] - m * rs) / sg : 0.0;
-          double tj = MODE ? ldexp(top, -j) : 0.0;
-          double reg = tot[3 * NC] - 2.0 * tj * tot[3 * NC + 1] + tj * tj * tot[3 * NC + 2];
-          e_j[j] = -ncc + 0.5 * D->lambda * reg;
-          ncc_j[j] = ncc;
-          m_j[j] = m;
-          sg_j[j] = sg;
-        }
-        (void)h;
-        long long* nc_s = D->node_count + (size_t)s * WK_COUNT;
-        nc_s[kind] += (long long)n * n;
-        if (MODE == 0 && ph == PH_PROLONG) nc_s[WK_PROLONG] += (long long)n * n;
-        if (MODE == 0) {
-          if (ph == PH_PROLONG) {
-            st.level = l;
-            st.ub = 0;
-          }
-          st.iter = 0;
-          st.tau_prev = INFINITY;
-          st.tau_pend = 0.0;
-          st.E = e_j[0];
-          st.ncc = ncc_j[0];
-          st.mean = m_j[0];
-          st.sigma = sg_j[0];
-          if (!isfinite(st.E)) {
-            st.flags |= FLAG_NAN;
-            st.phase = PH_DONE;
-          } else if (D->iter_max <= 0) {
-            level_done(st);
-          } else {
-            st.phase = PH_GRAD;
-          }
-        } else {
-          int li = st.level - st.coarsest;
-          st.passes[li]++;
-          int acc_j = -1;
-          for (int j = 0; j < ncand; ++j) {
-            double tj = ldexp(top, -j);
-            if (e_j[j] <= st.E - D->sigma * tj * st.gtd) {
-              acc_j = j;
-              break;
-            }
-          }
-          if (acc_j >= 0) {
-            double tj = ldexp(top, -acc_j);
-            double dec = st.E - e_j[acc_j];
-            st.E = e_j[acc_j];
-            st.ncc = ncc_j[acc_j];
-            st.mean = m_j[acc_j];
-            st.sigma = sg_j[acc_j];
-            st.tau_pend = tj;
-            st.tau_prev = tj;
-            st.iter++;
-            st.iters[li] = st.iter;
-            if (dec < D->eps) {
-              level_done(st);
-            } else if (st.iter >= D->iter_max) {
-              st.flags |= FLAG_NONCONV;
-              level_done(st);
-            } else {
-              st.phase = PH_GRAD;
-            }
-          } else {
-            st.top = ldexp(top, -(2 * K + 1));
-            if (st.top < D->tau_min_rel * st.tau_max) level_done(st);
-            else st.phase = PH_LADDER;
-          }
-        }
-      }
-      __syncthreads();
-    }
+  }
+}
+
+// Per-slot finalisation of an energy pass: one workgroup per listed slot sums the tile
+// partials in tile order and advances the slot (the kernel boundary orders it after the pass).
+template <int MODE, int NC>
+__global__ void __launch_bounds__(BLOCK) k_energy_fin(BatchDesc* D) {
+  constexpr int NV = 3 * NC + 3;
+  __shared__ double s_red[(BLOCK / 64) * NV];
+  const int kind = MODE ? WK_LADDER : WK_EVAL;
+  const WorkList wl = D->lists[kind];
+  for (int pos = blockIdx.x; pos < wl.n_slots; pos += gridDim.x) {
+    int s = D->list_slots[(size_t)kind * D->max_slots + pos];
+    SlotState* stp = D->state + s;
+    int ph = stp->phase;
+    if (MODE == 0 && !(ph == PH_INIT || ph == PH_PROLONG)) continue;
+    if (MODE == 1 && ph != PH_LADDER) continue;
+    int l = (ph == PH_PROLONG) ? stp->level + 1 : stp->level;
+    int n = lvl_n(l);
+    double top = MODE ? stp->top : 0.0;
+    double tot[NV];
+    sum_partials<NV>(D, s, kind, D->geom[l].tiles_elem, NV, tot, s_red, false);
+    if (threadIdx.x == 0) energy_finalize<MODE, NC>(D, stp, s, l, n, ph, top, tot);
+    __syncthreads();
   }
 }
 
@@ -541,7 +557,7 @@ __global__ void __launch_bounds__(BLOCK) k_energy(BatchDesc* D) {
 //       sum_q psi_i(q) f_q grad T(q + u(q)) + lambda (K_e u_e)_i,
 //       f_q = -w (R~(q) - NCC (T(q) - mean) / sigma) / sigma.
 
-__global__ void __launch_bounds__(BLOCK) k_grad(BatchDesc* D) {
+__global__ void __launch_bounds__(BLOCK, 4) k_grad(BatchDesc* D) {
   constexpr int NX = GT_X + 2, NY = GT_Y + 2;       // staged nodes
   constexpr int EX = GT_X + 1, EY = GT_Y + 1;       // elements touching the tile
   __shared__ float s_ux[NX * NY], s_uy[NX * NY], s_r[NX * NY];
@@ -610,7 +626,8 @@ __global__ void __launch_bounds__(BLOCK) k_grad(BatchDesc* D) {
             float uqy = ps[0] * uy[0] + ps[1] * uy[1] + ps[2] * uy[2] + ps[3] * uy[3];
             float rq = ps[0] * rr[0] + ps[1] * rr[1] + ps[2] * rr[2] + ps[3] * rr[3];
             float gx, gy;
-            float tv = sample_bil<true>(T, n, b, xi + uqx * inv_h, a, eta + uqy * inv_h, inv_h, &gx, &gy);
+            float tv = sample_bil<true>(T, n, b, xi + uqx * inv_h, a, eta + uqy * inv_h, inv_h,
+                                        &gx, &gy);
             float f = -w * (rq - ncc * (tv - mean) * inv_sig) * inv_sig;
             float fx = f * gx, fy = f * gy;
 #pragma unroll
@@ -659,18 +676,212 @@ __global__ void __launch_bounds__(BLOCK) k_grad(BatchDesc* D) {
 
 // ------------------------------------------------------------------------------------------
 // Metric solve along one axis: S1 x = g on every line, S1 symmetric tridiagonal with the
-// level's precomputed LU (a_i = -o / den_i, inv_den_i, c'_i). Lines of a workgroup are staged
-// in LDS; each line is split into chunks whose affine maps are composed, scanned across
-// chunks, then re-applied (forward and backward substitution).
-// DIR 0: lines are columns (solve along y), reads G writes Z.
+// level's precomputed LU (a_i = -o / den_i, inv_den_i, c'_i). One wavefront solves one line:
+// lane j holds nodes j*C .. j*C+C-1 in registers, composes the affine maps of the forward
+// (y_i = a_i y_{i-1} + g_i / den_i) and backward (x_i = y_i - c'_i x_{i+1}) substitutions over
+// its chunk, scans them across the 64 lanes with shuffles, and re-applies them.
+// DIR 0: lines are columns of a strip staged in LDS (solve along y), reads G writes Z.
 // DIR 1: lines are rows (solve along x), reads Z writes D, partial G.d and max |d|.
 
+template <int R, int C>
+__device__ __forceinline__ void solve_lines(float (&v)[R][C], int n, int lane,
+                                            const float* __restrict__ coef) {
+  const float* ca = coef;            // a_i
+  const float* ci = coef + n;        // 1 / den_i
+  const float* cp = coef + 2 * n;    // c'_i
+  int base = lane * C;
+  float A[R], B[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    A[r] = 1.f;
+    B[r] = 0.f;
+  }
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    int i = base + k;
+    if (i < n) {
+      float a = ca[i], c = ci[i];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        A[r] = a * A[r];
+        B[r] = fmaf(a, B[r], c * v[r][k]);
+      }
+    }
+  }
+  for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      float Ap = __shfl_up(A[r], off, 64), Bp = __shfl_up(B[r], off, 64);
+      if (lane >= off) {
+        B[r] = fmaf(A[r], Bp, B[r]);
+        A[r] = A[r] * Ap;
+      }
+    }
+  }
+  float y[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    y[r] = __shfl_up(B[r], 1, 64);
+    if (lane == 0) y[r] = 0.f;
+  }
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    int i = base + k;
+    if (i < n) {
+      float a = ca[i], c = ci[i];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        y[r] = fmaf(a, y[r], c * v[r][k]);
+        v[r][k] = y[r];
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    A[r] = 1.f;
+    B[r] = 0.f;
+  }
+#pragma unroll
+  for (int k = C - 1; k >= 0; --k) {
+    int i = base + k;
+    if (i < n) {
+      float mm = -cp[i];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        A[r] = mm * A[r];
+        B[r] = fmaf(mm, B[r], v[r][k]);
+      }
+    }
+  }
+  for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      float Ag = __shfl_down(A[r], off, 64), Bg = __shfl_down(B[r], off, 64);
+      if (lane + off < 64) {
+        B[r] = fmaf(A[r], Bg, B[r]);
+        A[r] = A[r] * Ag;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    y[r] = __shfl_down(B[r], 1, 64);
+    if (lane == 63) y[r] = 0.f;
+  }
+#pragma unroll
+  for (int k = C - 1; k >= 0; --k) {
+    int i = base + k;
+    if (i < n) {
+      float mm = -cp[i];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        y[r] = fmaf(mm, y[r], v[r][k]);
+        v[r][k] = y[r];
+      }
+    }
+  }
+}
+
+// Orders LDS accesses of one wavefront (lanes exchange data through LDS).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Lines solved together by one wavefront for C nodes per lane (LDS per wave stays <= 10 KB).
+template <int C>
+struct SmoothR {
+  static constexpr int value = C <= 9 ? 4 : 2;
+};
+
+// One smoother item: lines [line0, line0 + nl) of one component.
+template <int DIR, int C>
+__device__ void smooth_item(const float* src, float* dst, const float* Gp, const float* coef,
+                            int n, int line0, int nl, int SL, float* s_buf, double& gd,
+                            double& dm) {
+  constexpr int R = SmoothR<C>::value;
+  constexpr int NW = BLOCK / 64;
+  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  float v[R][C];
+  if (DIR == 0) {
+    // strip [n][SL] with pitch SL + 1; wave wv solves columns g .. g+R-1, g = R wv + R NW j
+    int pitch = SL + 1;
+    for (int k = threadIdx.x; k < n * SL; k += BLOCK) {
+      int i = k / SL, L = k - i * SL;
+      s_buf[i * pitch + L] = L < nl ? src[(size_t)i * n + line0 + L] : 0.f;
+    }
+    __syncthreads();
+    for (int g = wv * R; g < nl; g += R * NW) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+          int i = lane * C + k, L = min(g + r, SL - 1);
+          v[r][k] = i < n ? s_buf[i * pitch + L] : 0.f;
+        }
+      solve_lines<R, C>(v, n, lane, coef);
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+          int i = lane * C + k;
+          if (i < n && g + r < nl) s_buf[i * pitch + g + r] = v[r][k];
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < n * SL; k += BLOCK) {
+      int i = k / SL, L = k - i * SL;
+      if (L < nl) dst[(size_t)i * n + line0 + L] = s_buf[i * pitch + L];
+    }
+  } else {
+    // each wave stages R rows in its own LDS area (row pitch 64 C + 1)
+    int pitch = 64 * C + 1;
+    float* rows = s_buf + wv * R * pitch;
+    for (int g = wv * R; g < nl; g += R * NW) {
+      int nr = min(R, nl - g);
+      for (int r = 0; r < nr; ++r) {
+        const float* sr = src + (size_t)(line0 + g + r) * n;
+        for (int i = lane; i < n; i += 64) rows[r * pitch + i] = sr[i];
+      }
+      wave_sync();
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+          int i = lane * C + k;
+          v[r][k] = (i < n && r < nr) ? rows[r * pitch + i] : 0.f;
+        }
+      wave_sync();
+      solve_lines<R, C>(v, n, lane, coef);
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+          int i = lane * C + k;
+          if (i < n && r < nr) rows[r * pitch + i] = v[r][k];
+        }
+      wave_sync();
+      for (int r = 0; r < nr; ++r) {
+        float* dr = dst + (size_t)(line0 + g + r) * n;
+        const float* gr = Gp + (size_t)(line0 + g + r) * n;
+        for (int i = lane; i < n; i += 64) {
+          float x = rows[r * pitch + i];
+          dr[i] = x;
+          gd += (double)(gr[i] * x);
+          dm = fmax(dm, (double)fabsf(x));
+        }
+      }
+      wave_sync();
+    }
+  }
+}
+
 template <int DIR>
-__global__ void __launch_bounds__(SM_THREADS) k_smooth(BatchDesc* D) {
+__global__ void __launch_bounds__(BLOCK, 3) k_smooth(BatchDesc* D) {
   extern __shared__ float s_buf[];
-  __shared__ float s_A[SM_THREADS], s_B[SM_THREADS], s_in[SM_THREADS];
   __shared__ double s_red[(BLOCK / 64) * 2];
-  __shared__ int s_pos, s_flag;
+  __shared__ int s_pos;
   const int kind = DIR ? WK_SMX : WK_SMY;
   ItemCursor c;
   if (!cursor_begin(D, kind, c, &s_pos)) return;
@@ -690,103 +901,17 @@ __global__ void __launch_bounds__(SM_THREADS) k_smooth(BatchDesc* D) {
     const float* src = (DIR ? D->zbuf : D->gbuf) + (size_t)s * D->slot_f_stride + comp * nn;
     float* dst = (DIR ? D->dbuf : D->zbuf) + (size_t)s * D->slot_f_stride + comp * nn;
     const float* Gp = D->gbuf + (size_t)s * D->slot_f_stride + comp * nn;
-    const float* ca = D->coef + g.coef_off;           // a_i
-    const float* cinv = ca + n;                       // inv_den_i
-    const float* ccp = ca + 2 * n;                    // c'_i
-    // LDS layout: element (line L, index i) at L * ls + i * is
-    int ls, is;
-    if (DIR == 0) { is = SL + 1; ls = 1; }             // [i][line]
-    else { ls = n + 1; is = 1; }                       // [line][i]
+    const float* coef = D->coef + g.coef_off;
+    double gd = 0.0, dm = 0.0;
     __syncthreads();
-    // load
-    if (DIR == 0) {
-      for (int k = threadIdx.x; k < n * SL; k += SM_THREADS) {
-        int i = k / SL, L = k % SL;
-        s_buf[i * is + L] = L < nl ? src[(size_t)i * n + line0 + L] : 0.f;
-      }
-    } else {
-      for (int L = 0; L < nl; ++L)
-        for (int i = threadIdx.x; i < n; i += SM_THREADS)
-          s_buf[L * ls + i] = src[(size_t)(line0 + L) * n + i];
-    }
-    __syncthreads();
-    int tpl = SM_THREADS / SL;                         // threads per line
-    int L = threadIdx.x % SL, ck = threadIdx.x / SL;   // line, chunk
-    int C = (n + tpl - 1) / tpl;
-    int i0 = min(ck * C, n), i1 = min(i0 + C, n);
-    float* line = s_buf + L * ls;
-    // forward: y_i = a_i y_{i-1} + inv_den_i g_i
-    {
-      float A = 1.f, B = 0.f;
-      for (int i = i0; i < i1; ++i) {
-        float ai = ca[i];
-        A = ai * A;
-        B = fmaf(ai, B, cinv[i] * line[i * is]);
-      }
-      s_A[ck * SL + L] = A;
-      s_B[ck * SL + L] = B;
-    }
-    __syncthreads();
-    if (ck == 0) {
-      float y = 0.f;
-      for (int k = 0; k < tpl; ++k) {
-        s_in[k * SL + L] = y;
-        y = fmaf(s_A[k * SL + L], y, s_B[k * SL + L]);
-      }
-    }
-    __syncthreads();
-    {
-      float y = s_in[ck * SL + L];
-      for (int i = i0; i < i1; ++i) {
-        y = fmaf(ca[i], y, cinv[i] * line[i * is]);
-        line[i * is] = y;
-      }
-    }
-    __syncthreads();
-    // backward: x_i = y_i - c'_i x_{i+1}
-    {
-      float A = 1.f, B = 0.f;
-      for (int i = i1 - 1; i >= i0; --i) {
-        float m = -ccp[i];
-        A = m * A;
-        B = fmaf(m, B, line[i * is]);
-      }
-      s_A[ck * SL + L] = A;
-      s_B[ck * SL + L] = B;
-    }
-    __syncthreads();
-    if (ck == 0) {
-      float x = 0.f;
-      for (int k = tpl - 1; k >= 0; --k) {
-        s_in[k * SL + L] = x;
-        x = fmaf(s_A[k * SL + L], x, s_B[k * SL + L]);
-      }
-    }
-    __syncthreads();
-    {
-      float x = s_in[ck * SL + L];
-      for (int i = i1 - 1; i >= i0; --i) {
-        x = fmaf(-ccp[i], x, line[i * is]);
-        line[i * is] = x;
-      }
-    }
-    __syncthreads();
-    // store
-    if (DIR == 0) {
-      for (int k = threadIdx.x; k < n * SL; k += SM_THREADS) {
-        int i = k / SL, LL = k % SL;
-        if (LL < nl) dst[(size_t)i * n + line0 + LL] = s_buf[i * is + LL];
-      }
-    } else {
-      double gd = 0.0, dm = 0.0;
-      for (int LL = 0; LL < nl; ++LL)
-        for (int i = threadIdx.x; i < n; i += SM_THREADS) {
-          size_t gi = (size_t)(line0 + LL) * n + i;
-          float v = s_buf[LL * ls + i];
-          dst[gi] = v;
-          gd += (double)(Gp[gi] * v);
-          dm = fmax(dm, (double)fabsf(v));
-        }
+    int Cn = (n + 63) / 64;
+    if (Cn <= 1) smooth_item<DIR, 1>(src, dst, Gp, coef, n, line0, nl, SL, s_buf, gd, dm);
+    else if (Cn <= 2) smooth_item<DIR, 2>(src, dst, Gp, coef, n, line0, nl, SL, s_buf, gd, dm);
+    else if (Cn <= 3) smooth_item<DIR, 3>(src, dst, Gp, coef, n, line0, nl, SL, s_buf, gd, dm);
+    else if (Cn <= 5) smooth_item<DIR, 5>(src, dst, Gp, coef, n, line0, nl, SL, s_buf, gd, dm);
+    else if (Cn <= 9) smooth_item<DIR, 9>(src, dst, Gp, coef, n, line0, nl, SL, s_buf, gd, dm);
+    else smooth_item<DIR, 17>(src, dst, Gp, coef, n, line0, nl, SL, s_buf, gd, dm);
+    if (DIR == 1) {
       double acc[2] = {gd, dm};
       block_sum<2>(acc, s_red, true);
       if (threadIdx.x == 0) {
@@ -794,32 +919,41 @@ __global__ void __launch_bounds__(SM_THREADS) k_smooth(BatchDesc* D) {
         pr[0] = acc[0];
         pr[1] = acc[1];
       }
-      int n_items = 2 * g.sm_items;
-      if (last_ticket(D, s, kind, n_items, &s_flag)) {
-        double tot[2];
-        sum_partials<2>(D, s, kind, n_items, 2, tot, s_red, true);
-        if (threadIdx.x == 0) {
-          SlotState& st = D->state[s];
-          long long* nc_s = D->node_count + (size_t)s * WK_COUNT;
-          nc_s[WK_GRAD] += (long long)n * n;
-          nc_s[WK_SMY] += (long long)n * n;
-          nc_s[WK_SMX] += (long long)n * n;
-          st.ub ^= 1;          // the gradient kernel wrote u - tau_pend d to the other buffer
-          st.tau_pend = 0.0;
-          st.gtd = tot[0];
-          st.dmax = tot[1];
-          if (!(st.gtd > 0.0) || !(st.dmax > 0.0)) {
-            level_done(st);
-          } else {
-            double h = 1.0 / (n - 1);
-            st.tau_max = D->step_cap * h / st.dmax;
-            st.top = fmin(ldexp(st.tau_prev, D->ladder_k), st.tau_max);
-            st.phase = PH_LADDER;
-          }
-        }
-        __syncthreads();
+    }
+  }
+}
+
+// Per-slot finalisation of the metric solve: G.d, max |d|, step bound and first ladder top.
+__global__ void __launch_bounds__(BLOCK) k_smooth_fin(BatchDesc* D) {
+  __shared__ double s_red[(BLOCK / 64) * 2];
+  const WorkList wl = D->lists[WK_SMX];
+  for (int pos = blockIdx.x; pos < wl.n_slots; pos += gridDim.x) {
+    int s = D->list_slots[(size_t)WK_SMX * D->max_slots + pos];
+    SlotState& st = D->state[s];
+    if (st.phase != PH_GRAD) continue;
+    int l = st.level;
+    int n = lvl_n(l);
+    double tot[2];
+    sum_partials<2>(D, s, WK_SMX, 2 * D->geom[l].sm_items, 2, tot, s_red, true);
+    if (threadIdx.x == 0) {
+      long long* nc_s = D->node_count + (size_t)s * WK_COUNT;
+      nc_s[WK_GRAD] += (long long)n * n;
+      nc_s[WK_SMY] += (long long)n * n;
+      nc_s[WK_SMX] += (long long)n * n;
+      st.ub ^= 1;          // the gradient kernel wrote u - tau_pend d to the other buffer
+      st.tau_pend = 0.0;
+      st.gtd = tot[0];
+      st.dmax = tot[1];
+      if (!(st.gtd > 0.0) || !(st.dmax > 0.0)) {
+        level_done(st);
+      } else {
+        double h = 1.0 / (n - 1);
+        st.tau_max = D->step_cap * h / st.dmax;
+        st.top = fmin(ldexp(st.tau_prev, D->ladder_k), st.tau_max);
+        st.phase = PH_LADDER;
       }
     }
+    __syncthreads();
   }
 }
 
@@ -1045,6 +1179,23 @@ hipError_t energy(BatchDesc* d, int mode, int ladder_k, int grid, hipStream_t st
       default: hipLaunchKernelGGL((k_energy<1, 7>), dim3(grid), dim3(BLOCK), 0, st, d); break;
     }
   }
+  return hipGetLastError();
+}
+hipError_t energy_fin(BatchDesc* d, int mode, int ladder_k, int grid, hipStream_t st) {
+  if (mode == 0) {
+    hipLaunchKernelGGL((k_energy_fin<0, 1>), dim3(grid), dim3(BLOCK), 0, st, d);
+  } else {
+    switch (ladder_k) {
+      case 0: hipLaunchKernelGGL((k_energy_fin<1, 1>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+      case 1: hipLaunchKernelGGL((k_energy_fin<1, 3>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+      case 2: hipLaunchKernelGGL((k_energy_fin<1, 5>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+      default: hipLaunchKernelGGL((k_energy_fin<1, 7>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    }
+  }
+  return hipGetLastError();
+}
+hipError_t smooth_fin(BatchDesc* d, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_smooth_fin, dim3(grid), dim3(BLOCK), 0, st, d);
   return hipGetLastError();
 }
 hipError_t grad(BatchDesc* d, int grid, hipStream_t st) {

@@ -28,7 +28,7 @@ enum { WK_PROLONG = 0, WK_EVAL = 1, WK_GRAD = 2, WK_SMY = 3, WK_SMX = 4, WK_LADD
 // Tile geometry (compile-time).
 #define GT_X 32   // gradient kernel: nodes per tile along x
 #define GT_Y 16   //                  nodes per tile along y
-#define ET_X 32   // energy kernel: elements per tile along x
+#define ET_X 64   // energy kernel: elements per tile along x
 #define ET_Y 16   //                elements per tile along y
 #define PT_X 64   // prolongation: fine nodes per tile along x
 #define PT_Y 8

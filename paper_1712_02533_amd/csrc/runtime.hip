@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <string>
 #include <vector>
 
@@ -50,17 +51,18 @@ namespace {
 
 const int kGridItems = 2048;   // workgroups of the per-step item kernels
 const int kGridSmooth = 1024;
+const int kGridFin = 512;       // finalisation: one workgroup per listed slot (grid-stride)
 
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
 };
 
-enum { TK_PLAN = 0, TK_PROLONG, TK_EVAL, TK_GRAD, TK_SMY, TK_SMX, TK_LADDER, TK_COUNT };
+enum { TK_PLAN = 0, TK_PROLONG, TK_EVAL, TK_GRAD, TK_SMY, TK_SMX, TK_LADDER, TK_FIN, TK_COUNT };
 const char* kTkName[TK_COUNT] = {"plan", "prolong", "energy_eval", "grad", "smooth_y",
-                                 "smooth_x", "energy_ladder"};
+                                 "smooth_x", "energy_ladder", "finalize"};
 // algorithmic HBM bytes per grid node (both displacement components) of one launch per kind
-const double kBytesPerNode[TK_COUNT] = {0.0, 12.0, 16.0, 40.0, 16.0, 24.0, 24.0};
+const double kBytesPerNode[TK_COUNT] = {0.0, 12.0, 16.0, 40.0, 16.0, 24.0, 24.0, 0.0};
 
 int level_n(int l) { return (1 << l) + 1; }
 
@@ -143,7 +145,7 @@ pprs_status check_params(const pprs_params* p, int L) {
 // H is 2^L pixels or 2^L + 1 nodes; returns L or -1.
 int frame_level(int H, int W) {
   if (H != W || H < 4) return -1;
-  for (int L = 2; L <= 11; ++L)
+  for (int L = 2; L <= 10; ++L)
     if (H == (1 << L) || H == (1 << L) + 1) return L;
   return -1;
 }
@@ -166,7 +168,9 @@ size_t smooth_lds_bytes(const BatchDesc& hd) {
   size_t mx = 0;
   for (int l = hd.coarsest; l <= hd.finest; ++l) {
     const LevelGeom& g = hd.geom[l];
-    size_t a = (size_t)g.n * (g.sm_lines + 1), b = (size_t)g.sm_lines * (g.n + 1);
+    size_t C = (g.n + 63) / 64;
+    size_t Rw = C <= 9 ? 4 : 2;  // lines per wavefront (SmoothR in kernels.hip)
+    size_t a = (size_t)g.n * (g.sm_lines + 1), b = (BLOCK / 64) * Rw * (64 * C + 1);
     mx = std::max(mx, std::max(a, b));
   }
   return mx * sizeof(float);
@@ -362,10 +366,13 @@ pprs_status launch_step(pprs_ctx* c, BatchDesc* d, int ladder_k, size_t lds) {
   TIMED(TK_PLAN, pprs_k::plan(d, c->stream));
   TIMED(TK_PROLONG, pprs_k::prolong(d, kGridItems, c->stream));
   TIMED(TK_EVAL, pprs_k::energy(d, 0, ladder_k, kGridItems, c->stream));
+  TIMED(TK_FIN, pprs_k::energy_fin(d, 0, ladder_k, kGridFin, c->stream));
   TIMED(TK_GRAD, pprs_k::grad(d, kGridItems, c->stream));
   TIMED(TK_SMY, pprs_k::smooth(d, 0, kGridSmooth, lds, c->stream));
   TIMED(TK_SMX, pprs_k::smooth(d, 1, kGridSmooth, lds, c->stream));
+  TIMED(TK_FIN, pprs_k::smooth_fin(d, kGridFin, c->stream));
   TIMED(TK_LADDER, pprs_k::energy(d, 1, ladder_k, kGridItems, c->stream));
+  TIMED(TK_FIN, pprs_k::energy_fin(d, 1, ladder_k, kGridFin, c->stream));
   return PPRS_OK;
 }
 
@@ -379,6 +386,7 @@ pprs_status run_batch(pprs_ctx* c, int n, const int* ref, const int* tmpl, InitK
                       const pprs_params* p, pprs_pair_stats* stats, long long* node_steps,
                       long long* node_passes, int* flags_or) {
   if (n <= 0) return PPRS_OK;
+  auto t_start = std::chrono::steady_clock::now();
   BatchDesc& hd = c->hd;
   int L = hd.finest, m0 = hd.coarsest;
   int nL = level_n(L);
@@ -455,7 +463,9 @@ pprs_status run_batch(pprs_ctx* c, int n, const int* ref, const int* tmpl, InitK
   HIPCHK(pprs_k::finish(d, didx + 2 * n, elems, est, (long long)n * est, c->stream));
   if (c->log) {
     HIPCHK(hipStreamSynchronize(c->stream));
-    fprintf(stderr, "[pprs] batch of %d registrations done after %lld steps\n", n, done_steps);
+    double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    fprintf(stderr, "[pprs] batch of %d registrations done after %lld steps, %.2f ms\n", n,
+            done_steps, ms);
     fflush(stderr);
   }
   // statistics
@@ -572,7 +582,7 @@ pprs_status pprs_register_pair(pprs_ctx* c, const float* f_ref, const float* f_t
                                const pprs_params* params, pprs_pair_stats* stats) {
   STCHK(enter(c));
   int L = frame_level(H, W);
-  if (L < 0) return fail(PPRS_EINVAL, "frames must be square with side 2^L or 2^L+1, L in [2,11]");
+  if (L < 0) return fail(PPRS_EINVAL, "frames must be square with side 2^L or 2^L+1, L in [2,10]");
   if (!f_ref || !f_tmpl || !u_out) return fail(PPRS_EINVAL, "NULL frame or output pointer");
   STCHK(check_params(params, L));
   int m0 = L - params->levels + 1;
@@ -633,7 +643,7 @@ pprs_status pprs_prefix_register_series(pprs_ctx* c, const float* frames, int N,
                                         pprs_series_stats* stats, pprs_pair_stats* op_stats) {
   STCHK(enter(c));
   int L = frame_level(H, W);
-  if (L < 0) return fail(PPRS_EINVAL, "frames must be square with side 2^L or 2^L+1, L in [2,11]");
+  if (L < 0) return fail(PPRS_EINVAL, "frames must be square with side 2^L or 2^L+1, L in [2,10]");
   if (N < 1) return fail(PPRS_EINVAL, "N must be >= 1");
   if (!frames || !u_out) return fail(PPRS_EINVAL, "NULL frames or output pointer");
   STCHK(check_params(params, L));
@@ -749,7 +759,8 @@ pprs_status pprs_get_kernel_timing(pprs_ctx* c, double* ms, long long* launches,
   if (!c) return fail(PPRS_EINVAL, "ctx is NULL");
   if (n_kinds) *n_kinds = TK_COUNT;
   // node counts per work kind -> bytes per timing kind
-  const int wk_of_tk[TK_COUNT] = {-1, WK_PROLONG, WK_EVAL, WK_GRAD, WK_SMY, WK_SMX, WK_LADDER};
+  const int wk_of_tk[TK_COUNT] = {-1, WK_PROLONG, WK_EVAL, WK_GRAD, WK_SMY, WK_SMX, WK_LADDER,
+                                  -1};
   for (int k = 0; k < TK_COUNT && k < cap; ++k) {
     if (ms) ms[k] = c->t_ms[k];
     if (launches) launches[k] = c->t_launch[k];
