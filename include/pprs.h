@@ -44,7 +44,7 @@ typedef enum {
 
 enum { PPRS_SCAN_SEQUENTIAL = 0, PPRS_SCAN_BRENT_KUNG = 1 };
 
-enum { PPRS_FLAG_NONCONV = 1, PPRS_FLAG_NAN = 2 };
+enum { PPRS_FLAG_NONCONV = 1, PPRS_FLAG_NAN = 2, PPRS_FLAG_FALLBACK = 4 };
 
 #define PPRS_MAX_LEVELS 16
 
@@ -140,6 +140,47 @@ pprs_status pprs_set_kernel_timing(pprs_ctx* ctx, int enable);
 pprs_status pprs_get_kernel_timing(pprs_ctx* ctx, double* ms, long long* launches,
                                    double* bytes, int cap, int* n_kinds, int reset);
 const char* pprs_kernel_name(int kind);
+
+/* ---- Learned warm start (not in the paper: a small BF16 CNN predicts the level-7
+   displacement of a frame pair; the gradient flow then refines levels 7..L) ------------------ */
+
+typedef struct pprs_cnn pprs_cnn;
+
+/* Creates the network on `device`, ordered on `stream` (NULL = the default stream), with
+   He-normal weights drawn from `seed`. Inputs are [B][128][128][2] float32 (channel 0 the
+   reference, 1 the template: level-7 frames normalised to mean 0, sigma 1), outputs
+   [B][128][128][2] float32 displacements in level-7 cells (x then y). */
+pprs_status pprs_cnn_create(pprs_cnn** cnn, int device, void* stream, unsigned long long seed);
+void pprs_cnn_destroy(pprs_cnn* cnn);
+const char* pprs_cnn_last_error(void);
+/* Number of float32 parameters (FP32 master weights, layer by layer: weights then bias). */
+size_t pprs_cnn_param_count(const pprs_cnn* cnn);
+/* Host buffers of pprs_cnn_param_count floats. set also resets the optimiser state. */
+pprs_status pprs_cnn_set_params(pprs_cnn* cnn, const float* host, size_t count);
+pprs_status pprs_cnn_get_params(pprs_cnn* cnn, float* host, size_t count);
+/* Inference on B samples (device pointers). */
+pprs_status pprs_cnn_forward(pprs_cnn* cnn, const float* x, int B, float* y);
+/* Mean squared error over the interior (a border of `margin` pixels left out) and its gradient
+   with respect to every parameter; grad_host (host, may be NULL) receives it. */
+pprs_status pprs_cnn_gradients(pprs_cnn* cnn, const float* x, const float* target, int B,
+                               int margin, double* loss, float* grad_host);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) with learning rate lr on that loss. */
+pprs_status pprs_cnn_train_step(pprs_cnn* cnn, const float* x, const float* target, int B,
+                                int margin, float lr, double* loss);
+
+/* Network inputs for P frame pairs of a series: frames [N][H][W] as in
+   pprs_prefix_register_series (side >= 128); ref and tmpl are host arrays of P frame indices;
+   out [P][128][128][2]. */
+pprs_status pprs_pair_inputs(pprs_ctx* ctx, const float* frames, int N, int H, int W,
+                             const int* ref, const int* tmpl, int P, float* out);
+/* Network targets: displacements u [P][2][H][W] (pixels) restricted to level 7 and expressed in
+   level-7 cells, out [P][128][128][2]. */
+pprs_status pprs_level7_targets(pprs_ctx* ctx, const float* u, int P, int H, int W, float* out);
+/* Enables (cnn != NULL) or disables the warm start for later series calls on ctx: the
+   neighbour registrations start at level 7 from the network's prediction, B applications at
+   level 7 from the composition. A prediction that is not finite or exceeds max_cells level-7
+   cells falls back to the cold start from the coarsest level. */
+pprs_status pprs_set_warm_start(pprs_ctx* ctx, pprs_cnn* cnn, double max_cells);
 
 #ifdef __cplusplus
 }

@@ -290,3 +290,146 @@ def kernel_timing(reset: bool = False, device=None):
                                          1 if reset else 0))
     names = kernel_names()
     return {names[k]: (ms[k], la[k], by[k]) for k in range(nk.value)}
+
+
+# ------------------------------------------------------------------------------------------ #
+# Learned warm start
+
+def _cnn_sigs(lib):
+    vp = ctypes.c_void_p
+    i = ctypes.c_int
+    sigs = {
+        "pprs_cnn_create": (i, [ctypes.POINTER(vp), i, vp, ctypes.c_ulonglong]),
+        "pprs_cnn_destroy": (None, [vp]),
+        "pprs_cnn_last_error": (ctypes.c_char_p, []),
+        "pprs_cnn_param_count": (ctypes.c_size_t, [vp]),
+        "pprs_cnn_set_params": (i, [vp, vp, ctypes.c_size_t]),
+        "pprs_cnn_get_params": (i, [vp, vp, ctypes.c_size_t]),
+        "pprs_cnn_forward": (i, [vp, vp, i, vp]),
+        "pprs_cnn_gradients": (i, [vp, vp, vp, i, i, ctypes.POINTER(ctypes.c_double), vp]),
+        "pprs_cnn_train_step": (i, [vp, vp, vp, i, i, ctypes.c_float,
+                                    ctypes.POINTER(ctypes.c_double)]),
+        "pprs_pair_inputs": (i, [vp, vp, i, i, i, vp, vp, i, vp]),
+        "pprs_level7_targets": (i, [vp, vp, i, i, i, vp]),
+        "pprs_set_warm_start": (i, [vp, vp, ctypes.c_double]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+def _cnn_check(status: int):
+    if status < 0:
+        lib = _lib()
+        msg = lib.pprs_cnn_last_error().decode() or lib.pprs_last_error().decode()
+        raise PprsError(status, msg)
+    return status
+
+
+class WarmStartNet:
+    """The BF16 encoder-decoder of the warm start (weights live on the device)."""
+
+    def __init__(self, seed: int = 0, device=None):
+        import torch
+        dev = device or torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        lib = _cnn_sigs(_lib())
+        h = ctypes.c_void_p()
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        _cnn_check(lib.pprs_cnn_create(ctypes.byref(h), dev.index or 0, ctypes.c_void_p(stream),
+                                       seed))
+        self.handle = h
+        self.n_params = lib.pprs_cnn_param_count(h)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib().pprs_cnn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        import numpy as np
+        out = np.empty(self.n_params, dtype=np.float32)
+        _cnn_check(_lib().pprs_cnn_get_params(self.handle, out.ctypes.data, out.size))
+        return out
+
+    def set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _cnn_check(_lib().pprs_cnn_set_params(self.handle, p.ctypes.data, p.size))
+
+    def forward(self, x):
+        """x [B, 128, 128, 2] float32 on the device -> [B, 128, 128, 2]."""
+        import torch
+        y = torch.empty_like(x)
+        _cnn_check(_lib().pprs_cnn_forward(self.handle, _dev_f32(x, "x"), x.shape[0],
+                                           _dev_f32(y, "y")))
+        return y
+
+    def gradients(self, x, target, margin: int = 4):
+        import numpy as np
+        g = np.empty(self.n_params, dtype=np.float32)
+        loss = ctypes.c_double()
+        _cnn_check(_lib().pprs_cnn_gradients(self.handle, _dev_f32(x, "x"),
+                                             _dev_f32(target, "target"), x.shape[0], margin,
+                                             ctypes.byref(loss), g.ctypes.data))
+        return loss.value, g
+
+    def train_step(self, x, target, lr: float, margin: int = 4) -> float:
+        loss = ctypes.c_double()
+        _cnn_check(_lib().pprs_cnn_train_step(self.handle, _dev_f32(x, "x"),
+                                              _dev_f32(target, "target"), x.shape[0], margin,
+                                              lr, ctypes.byref(loss)))
+        return loss.value
+
+    def save(self, path: str):
+        from safetensors.numpy import save_file
+        save_file({"params": self.get_params()}, path)
+
+    def load(self, path: str):
+        from safetensors.numpy import load_file
+        self.set_params(load_file(path)["params"])
+
+
+def pair_inputs(frames, ref, tmpl):
+    """Network inputs [P, 128, 128, 2] for frame pairs (ref[p], tmpl[p]) of frames [N, H, W]."""
+    import numpy as np
+    import torch
+    _cnn_sigs(_lib())
+    ref = np.ascontiguousarray(ref, dtype=np.int32)
+    tmpl = np.ascontiguousarray(tmpl, dtype=np.int32)
+    N, H, W = frames.shape
+    out = torch.empty((len(ref), 128, 128, 2), device=frames.device, dtype=torch.float32)
+    c = _ctx(frames.device)
+    _check(_lib().pprs_pair_inputs(c.handle, _dev_f32(frames, "frames"), N, H, W,
+                                   ref.ctypes.data, tmpl.ctypes.data, len(ref),
+                                   _dev_f32(out, "out")))
+    return out
+
+
+def level7_targets(u):
+    """Displacements u [P, 2, H, W] (pixels) -> level-7 targets [P, 128, 128, 2] (cells)."""
+    import torch
+    _cnn_sigs(_lib())
+    P, _, H, W = u.shape
+    out = torch.empty((P, 128, 128, 2), device=u.device, dtype=torch.float32)
+    c = _ctx(u.device)
+    _check(_lib().pprs_level7_targets(c.handle, _dev_f32(u, "u"), P, H, W,
+                                      _dev_f32(out, "out")))
+    return out
+
+
+def set_warm_start(net, max_cells: float = 8.0, device=None):
+    """Use `net` (or None) to warm-start later series calls on the current stream's context."""
+    import torch
+    _cnn_sigs(_lib())
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    _check(_lib().pprs_set_warm_start(_ctx(dev).handle, net.handle if net else None,
+                                      max_cells))

@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpprs.so")
-SOURCES = ["kernels.hip", "runtime.hip", "plan.cpp"]
+SOURCES = ["kernels.hip", "runtime.hip", "cnn.hip", "plan.cpp"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
          # no packed FP32 instructions (v_pk_*_f32) anywhere
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

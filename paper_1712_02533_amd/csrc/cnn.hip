@@ -1,0 +1,888 @@
+// Learned warm start: a 6-layer convolutional encoder-decoder (BF16 weights and activations,
+// FP32 accumulation) that maps a pair of level-7 frames (2 x 128 x 128, normalised) to the
+// level-7 displacement (2 x 128 x 128, in level-7 cells). Trained on this GPU by the kernels in
+// this file (forward, backward, Adam) on pairs registered by the plain method.
+//
+// Network (3x3 convolutions, padding 1; ReLU after every layer but the last):
+//   L1 2->64 stride 2 (64^2)   L2 64->128 stride 2 (32^2)   L3 128->256 stride 2 (16^2)
+//   L4 [up2(L3), L2] 384->128 (32^2)   L5 [up2(L4), L1] 192->64 (64^2)
+//   L6 [up2(L5), input] 66->2 (128^2, linear)
+// Activations are NHWC. A convolution is im2col + an MFMA GEMM (v_mfma_f32_16x16x32_bf16);
+// its weights are [Cout][Kp] with k = (dy * 3 + dx) * Cin + ci, Kp = 9 Cin rounded up to 32
+// (L1 to 64), padded with zeros. L6 (2 output channels) uses direct FP32 kernels.
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/pprs.h"
+
+typedef __bf16 bf16;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+namespace {
+
+const int kBlock = 256;
+
+int grid1d(long long work, int cap = 16384) {
+  long long g = (work + kBlock - 1) / kBlock;
+  return (int)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+// ------------------------------------------------------------------------------------------
+// GEMM: C[m][n] = sum_k A(m,k) B(n,k), bf16 operands, fp32 result.
+// A(m,k) = AK ? A[k * lda + m] : A[m * lda + k]; B(n,k) = BK ? B[k * ldb + n] : B[n * ldb + k].
+// 64 x 64 tiles, 32-deep K steps, 4 wavefronts each owning a 32 x 32 quarter (2 x 2 MFMA).
+// Requires M % 64 == 0, N % 64 == 0, (K range of a split) % 32 == 0, lda, ldb % 8 == 0.
+// blockIdx.z selects a K split; split s writes C + s * split_stride.
+
+template <bool AK, bool BK>
+__global__ void __launch_bounds__(256) k_gemm(const bf16* __restrict__ A, int lda,
+                                              const bf16* __restrict__ B, int ldb,
+                                              float* __restrict__ C, int ldc, int K,
+                                              int k_per_split, long long split_stride) {
+  constexpr int PADK = 40;  // LDS row of 32 k plus 8 (keeps 16-byte alignment)
+  __shared__ __attribute__((aligned(16))) bf16 sA[64 * PADK];
+  __shared__ __attribute__((aligned(16))) bf16 sB[64 * PADK];
+  int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  int n0 = blockIdx.x * 64, m0 = blockIdx.y * 64;
+  int kb = blockIdx.z * k_per_split, ke = min(K, kb + k_per_split);
+  int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  f32x4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int k0 = kb; k0 < ke; k0 += 32) {
+    if (!AK) {
+      int m = tid >> 2, kk = (tid & 3) * 8;
+      *(uint4*)&sA[m * PADK + kk] = *(const uint4*)&A[(size_t)(m0 + m) * lda + k0 + kk];
+    } else {
+      int kk = tid >> 3, mm = (tid & 7) * 8;
+      uint4 v = *(const uint4*)&A[(size_t)(k0 + kk) * lda + m0 + mm];
+      const bf16* e = (const bf16*)&v;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) sA[(mm + i) * PADK + kk] = e[i];
+    }
+    if (!BK) {
+      int n = tid >> 2, kk = (tid & 3) * 8;
+      *(uint4*)&sB[n * PADK + kk] = *(const uint4*)&B[(size_t)(n0 + n) * ldb + k0 + kk];
+    } else {
+      int kk = tid >> 3, nn = (tid & 7) * 8;
+      uint4 v = *(const uint4*)&B[(size_t)(k0 + kk) * ldb + n0 + nn];
+      const bf16* e = (const bf16*)&v;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) sB[(nn + i) * PADK + kk] = e[i];
+    }
+    __syncthreads();
+    bf16x8 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      a[i] = *(const bf16x8*)&sA[(wm + i * 16 + (lane & 15)) * PADK + 8 * (lane >> 4)];
+      b[i] = *(const bf16x8*)&sB[(wn + i * 16 + (lane & 15)) * PADK + 8 * (lane >> 4)];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+  float* Co = C + (size_t)blockIdx.z * split_stride;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        int col = n0 + wn + j * 16 + (lane & 15);
+        Co[(size_t)row * ldc + col] = acc[i][j][r];
+      }
+}
+
+// Sum of `splits` partial results in split order.
+__global__ void k_split_sum(const float* __restrict__ part, long long stride, int splits,
+                            float* __restrict__ out, long long count) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int k = 0; k < splits; ++k) s += part[k * stride + i];
+    out[i] = s;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Layout kernels
+
+// col[(b, oy, ox)][(dy * 3 + dx) * C + c] = X[b][oy*s + dy - 1][ox*s + dx - 1][c] (0 outside),
+// zero for k >= 9 C up to Kp.
+__global__ void k_im2col(const bf16* __restrict__ X, int Bn, int H, int W, int C, int s,
+                         int Kp, bf16* __restrict__ col) {
+  int Ho = H / s, Wo = W / s;
+  long long total = (long long)Bn * Ho * Wo * Kp;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    int k = (int)(i % Kp);
+    long long p = i / Kp;
+    int ox = (int)(p % Wo), oy = (int)((p / Wo) % Ho), b = (int)(p / ((long long)Wo * Ho));
+    bf16 v = (bf16)0.f;
+    if (k < 9 * C) {
+      int tap = k / C, c = k - tap * C;
+      int y = oy * s + tap / 3 - 1, x = ox * s + tap % 3 - 1;
+      if (y >= 0 && y < H && x >= 0 && x < W) v = X[(((size_t)b * H + y) * W + x) * C + c];
+    }
+    col[i] = v;
+  }
+}
+
+// dX[b][y][x][c] = sum of dcol over the output positions whose patch covers (y, x).
+__global__ void k_col2im(const float* __restrict__ dcol, int Bn, int H, int W, int C, int s,
+                         int ldk, float* __restrict__ dX, int accumulate) {
+  int Ho = H / s, Wo = W / s;
+  long long total = (long long)Bn * H * W * C;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    int c = (int)(i % C);
+    long long p = i / C;
+    int x = (int)(p % W), y = (int)((p / W) % H), b = (int)(p / ((long long)W * H));
+    float sum = 0.f;
+    for (int dy = 0; dy < 3; ++dy) {
+      int ty = y + 1 - dy;
+      if (ty < 0 || ty % s) continue;
+      int oy = ty / s;
+      if (oy >= Ho) continue;
+      for (int dx = 0; dx < 3; ++dx) {
+        int tx = x + 1 - dx;
+        if (tx < 0 || tx % s) continue;
+        int ox = tx / s;
+        if (ox >= Wo) continue;
+        sum += dcol[(((size_t)b * Ho + oy) * Wo + ox) * ldk + (dy * 3 + dx) * C + c];
+      }
+    }
+    dX[i] = accumulate ? dX[i] + sum : sum;
+  }
+}
+
+// U = [up2(lo) (C1 channels), skip (C2 channels)] at H x W (lo is H/2 x W/2).
+__global__ void k_upcat(const bf16* __restrict__ lo, int C1, const bf16* __restrict__ skip,
+                        int C2, int Bn, int H, int W, bf16* __restrict__ U) {
+  int C = C1 + C2;
+  long long total = (long long)Bn * H * W * C;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    int c = (int)(i % C);
+    long long p = i / C;
+    int x = (int)(p % W), y = (int)((p / W) % H), b = (int)(p / ((long long)W * H));
+    U[i] = c < C1 ? lo[(((size_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C1 + c]
+                  : skip[(((size_t)b * H + y) * W + x) * C2 + (c - C1)];
+  }
+}
+
+// Backward of k_upcat: d_lo = 2x2 sums of the first C1 channels; d_skip (+)= the rest.
+__global__ void k_upcat_bwd(const float* __restrict__ dU, int C1, int C2, int Bn, int H, int W,
+                            float* __restrict__ dlo, float* __restrict__ dskip,
+                            int skip_accumulate) {
+  int C = C1 + C2;
+  long long nlo = (long long)Bn * (H / 2) * (W / 2) * C1;
+  long long nsk = dskip ? (long long)Bn * H * W * C2 : 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nlo + nsk;
+       i += (long long)gridDim.x * blockDim.x) {
+    if (i < nlo) {
+      int c = (int)(i % C1);
+      long long p = i / C1;
+      int X = (int)(p % (W / 2)), Y = (int)((p / (W / 2)) % (H / 2));
+      int b = (int)(p / ((long long)(W / 2) * (H / 2)));
+      float s = 0.f;
+      for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx)
+          s += dU[(((size_t)b * H + 2 * Y + dy) * W + 2 * X + dx) * C + c];
+      dlo[i] = s;
+    } else {
+      long long j = i - nlo;
+      int c = (int)(j % C2);
+      long long p = j / C2;
+      float v = dU[p * C + C1 + c];
+      dskip[j] = skip_accumulate ? dskip[j] + v : v;
+    }
+  }
+}
+
+// out_bf16[m][n] = relu(Z[m][n] + bias[n]) (N columns).
+__global__ void k_bias_relu(const float* __restrict__ Z, const float* __restrict__ bias,
+                            long long M, int N, bf16* __restrict__ out) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < M * N;
+       i += (long long)gridDim.x * blockDim.x) {
+    float v = Z[i] + bias[i % N];
+    out[i] = (bf16)(v > 0.f ? v : 0.f);
+  }
+}
+
+// dZ = dA * (A > 0) as bf16 (A is the layer's ReLU output).
+__global__ void k_relu_bwd(const float* __restrict__ dA, const bf16* __restrict__ A,
+                           long long count, bf16* __restrict__ dZ) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x)
+    dZ[i] = (bf16)((float)A[i] > 0.f ? dA[i] : 0.f);
+}
+
+// Column sums of a bf16 matrix [M][N] (bias gradients): per (column, chunk) partials.
+__global__ void k_colsum_part(const bf16* __restrict__ G, long long M, int N, int chunks,
+                              float* __restrict__ part) {
+  __shared__ float red[kBlock];
+  int n = blockIdx.x, ch = blockIdx.y;
+  long long rows = (M + chunks - 1) / chunks;
+  long long r0 = ch * rows, r1 = r0 + rows < M ? r0 + rows : M;
+  float s = 0.f;
+  for (long long r = r0 + threadIdx.x; r < r1; r += blockDim.x) s += (float)G[r * N + n];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(size_t)ch * N + n] = red[0];
+}
+
+__global__ void k_colsum_final(const float* __restrict__ part, int N, int chunks,
+                               float* __restrict__ out) {
+  int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.f;
+  for (int c = 0; c < chunks; ++c) s += part[(size_t)c * N + n];
+  out[n] = s;
+}
+
+__global__ void k_f32_to_bf16(const float* __restrict__ x, long long count,
+                              bf16* __restrict__ y) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = (bf16)x[i];
+}
+
+// ------------------------------------------------------------------------------------------
+// Last layer (66 -> 2 channels, stride 1), FP32 direct kernels. W6 is [2][9][66] fp32 (from the
+// bf16 copy), bias b6[2].
+
+__global__ void k_l6_fwd(const bf16* __restrict__ U, const float* __restrict__ W6,
+                         const float* __restrict__ b6, int Bn, int H, int Wd, int C,
+                         float* __restrict__ Y) {
+  long long total = (long long)Bn * H * Wd;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < total;
+       p += (long long)gridDim.x * blockDim.x) {
+    int x = (int)(p % Wd), y = (int)((p / Wd) % H), b = (int)(p / ((long long)Wd * H));
+    float s0 = b6[0], s1 = b6[1];
+    for (int tap = 0; tap < 9; ++tap) {
+      int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+      if (yy < 0 || yy >= H || xx < 0 || xx >= Wd) continue;
+      const bf16* u = U + (((size_t)b * H + yy) * Wd + xx) * C;
+      const float* w0 = W6 + tap * C;
+      const float* w1 = W6 + 9 * C + tap * C;
+      for (int c = 0; c < C; ++c) {
+        float v = (float)u[c];
+        s0 = fmaf(w0[c], v, s0);
+        s1 = fmaf(w1[c], v, s1);
+      }
+    }
+    Y[p * 2] = s0;
+    Y[p * 2 + 1] = s1;
+  }
+}
+
+// dU[b][y][x][c] = sum over taps of W6[o][tap][c] dY at the output whose patch holds (y, x).
+__global__ void k_l6_bwd_data(const float* __restrict__ dY, const float* __restrict__ W6,
+                              int Bn, int H, int Wd, int C, float* __restrict__ dU) {
+  long long total = (long long)Bn * H * Wd * C;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    int c = (int)(i % C);
+    long long p = i / C;
+    int x = (int)(p % Wd), y = (int)((p / Wd) % H), b = (int)(p / ((long long)Wd * H));
+    float s = 0.f;
+    for (int tap = 0; tap < 9; ++tap) {
+      int oy = y + 1 - tap / 3, ox = x + 1 - tap % 3;
+      if (oy < 0 || oy >= H || ox < 0 || ox >= Wd) continue;
+      const float* g = dY + (((size_t)b * H + oy) * Wd + ox) * 2;
+      s = fmaf(W6[tap * C + c], g[0], s);
+      s = fmaf(W6[9 * C + tap * C + c], g[1], s);
+    }
+    dU[i] = s;
+  }
+}
+
+// dW6[o][tap][c] and db6[o]: per (weight, chunk) partial sums over pixels.
+__global__ void k_l6_bwd_w_part(const float* __restrict__ dY, const bf16* __restrict__ U,
+                                int Bn, int H, int Wd, int C, int chunks,
+                                float* __restrict__ part) {
+  __shared__ float red[kBlock];
+  int widx = blockIdx.x;  // 0 .. 2*9*C + 2 - 1
+  int ch = blockIdx.y;
+  int nw = 2 * 9 * C;
+  long long total = (long long)Bn * H * Wd;
+  long long rows = (total + chunks - 1) / chunks;
+  long long p0 = ch * rows, p1 = p0 + rows < total ? p0 + rows : total;
+  float s = 0.f;
+  if (widx < nw) {
+    int o = widx / (9 * C), tap = (widx / C) % 9, c = widx % C;
+    for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+      int x = (int)(p % Wd), y = (int)((p / Wd) % H), b = (int)(p / ((long long)Wd * H));
+      int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+      if (yy < 0 || yy >= H || xx < 0 || xx >= Wd) continue;
+      s = fmaf(dY[p * 2 + o], (float)U[(((size_t)b * H + yy) * Wd + xx) * C + c], s);
+    }
+  } else {
+    int o = widx - nw;
+    for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) s += dY[p * 2 + o];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(size_t)ch * gridDim.x + widx] = red[0];
+}
+
+// ------------------------------------------------------------------------------------------
+// Loss: mean squared error over the interior (a border of `margin` pixels is left out).
+// Writes per-block partial sums of squares and dY = 2 (Y - T) / count (0 in the border).
+
+__global__ void k_mse(const float* __restrict__ Y, const float* __restrict__ T, int Bn, int H,
+                      int Wd, int margin, float inv_count, float* __restrict__ dY,
+                      double* __restrict__ part) {
+  __shared__ double red[kBlock];
+  long long total = (long long)Bn * H * Wd * 2;
+  double s = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    long long p = i / 2;
+    int x = (int)(p % Wd), y = (int)((p / Wd) % H);
+    bool in = x >= margin && x < Wd - margin && y >= margin && y < H - margin;
+    float d = in ? Y[i] - T[i] : 0.f;
+    s += (double)d * d;
+    if (dY) dY[i] = 2.f * d * inv_count;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Adam on FP32 master weights; refreshes the bf16 copy. Gradient g is the full fp32 gradient.
+__global__ void k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, long long count, float lr, float b1,
+                       float b2, float eps, float c1, float c2, bf16* __restrict__ wb) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x) {
+    float gi = g[i];
+    float mi = b1 * m[i] + (1.f - b1) * gi;
+    float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    if (wb) wb[i] = (bf16)wi;
+  }
+}
+
+// Pack level-7 normalised frames of pairs into the network input [P][128][128][2] (fp32):
+// channel 0 = reference, 1 = template; the 129^2 grid is cropped to 128^2.
+__global__ void k_pack_pairs(const float* __restrict__ lvl, int n, const int* __restrict__ ref,
+                             const int* __restrict__ tmpl, int P, float* __restrict__ out) {
+  int S = n - 1;
+  long long total = (long long)P * S * S;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    int x = (int)(i % S), y = (int)((i / S) % S), p = (int)(i / ((long long)S * S));
+    out[i * 2] = lvl[(size_t)ref[p] * n * n + (size_t)y * n + x];
+    out[i * 2 + 1] = lvl[(size_t)tmpl[p] * n * n + (size_t)y * n + x];
+  }
+}
+
+// Level-7 displacement planes [P][2][n][n] (domain units) -> [P][n-1][n-1][2] in cells.
+__global__ void k_planes_to_nhwc(const float* __restrict__ src, int n, long long pstride, int P,
+                                 float scale, float* __restrict__ out) {
+  int S = n - 1;
+  long long total = (long long)P * S * S;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    int x = (int)(i % S), y = (int)((i / S) % S), p = (int)(i / ((long long)S * S));
+    const float* s = src + p * pstride;
+    out[i * 2] = scale * s[(size_t)y * n + x];
+    out[i * 2 + 1] = scale * s[(size_t)n * n + (size_t)y * n + x];
+  }
+}
+
+// Network output [P][S][S][2] (cells) -> slot planes [2][S+1][S+1] (domain units), replicating
+// the last row and column; dst of slot p = base + p * stride.
+__global__ void k_nhwc_to_planes(const float* __restrict__ y, int S, int P, float scale,
+                                 float* __restrict__ base, long long stride) {
+  int n = S + 1;
+  long long total = (long long)P * n * n;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    int x = (int)(i % n), yy = (int)((i / n) % n), p = (int)(i / ((long long)n * n));
+    int xs = min(x, S - 1), ys = min(yy, S - 1);
+    const float* src = y + (((size_t)p * S + ys) * S + xs) * 2;
+    float* d = base + p * stride;
+    d[(size_t)yy * n + x] = scale * src[0];
+    d[(size_t)n * n + (size_t)yy * n + x] = scale * src[1];
+  }
+}
+
+// bad[p] = 1 when sample p of y [P][n_per] has a non-finite value or one with |v| > limit.
+__global__ void k_check_pred(const float* __restrict__ y, long long n_per, float limit,
+                             int* __restrict__ bad) {
+  __shared__ int red[kBlock];
+  const float* s = y + blockIdx.x * n_per;
+  int b = 0;
+  for (long long i = threadIdx.x; i < n_per; i += blockDim.x) {
+    float v = s[i];
+    if (!(fabsf(v) <= limit)) b = 1;
+  }
+  red[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] |= red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bad[blockIdx.x] = red[0];
+}
+
+}  // namespace
+
+// ==========================================================================================
+// Model
+
+namespace pprs_cnn_impl {
+
+struct Layer {
+  int cin, cout, stride, kp;    // kp: padded K (columns of the weight matrix)
+  int hin, hout;                // spatial size of input / output (square)
+  long long woff, boff;         // offsets into the flat parameter vector
+};
+
+struct Model {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  Layer L[6];
+  long long n_params = 0;
+  float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;  // fp32 master, Adam, grad
+  bf16* wb = nullptr;                                            // bf16 copy of w
+  long long step = 0;
+  int cap_b = 0;
+  // activations and workspaces (sized for cap_b)
+  bf16 *x0 = nullptr, *a[5] = {nullptr}, *u4 = nullptr, *u5 = nullptr, *u6 = nullptr,
+       *col = nullptr, *dzb = nullptr;
+  float *z = nullptr, *y = nullptr, *dy = nullptr, *dcol = nullptr, *du = nullptr,
+        *da[5] = {nullptr}, *part = nullptr, *w6 = nullptr;
+  double* lpart = nullptr;
+  size_t part_floats = 0;
+};
+
+}  // namespace pprs_cnn_impl
+
+struct pprs_cnn {
+  pprs_cnn_impl::Model M;
+};
+
+using pprs_cnn_impl::Layer;
+using pprs_cnn_impl::Model;
+
+static thread_local std::string g_cnn_err;
+
+static pprs_status cfail(pprs_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_cnn_err = buf;
+  return s;
+}
+
+#define CHK(expr)                                                                     \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return cfail(PPRS_EHIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                   __LINE__);                                                         \
+  } while (0)
+
+static pprs_status gemm(Model& M, bool ak, bool bk, const bf16* A, int lda, const bf16* B,
+                        int ldb, float* C, int ldc, int Mr, int Nc, int K, int splits) {
+  if (Mr % 64 || Nc % 64 || K % 32 || lda % 8 || ldb % 8)
+    return cfail(PPRS_EINVAL, "gemm shape %d x %d x %d not tileable", Mr, Nc, K);
+  int kps = ((K / 32 + splits - 1) / splits) * 32;
+  splits = (K + kps - 1) / kps;
+  float* out = C;
+  long long stride = (long long)Mr * ldc;
+  if (splits > 1) {
+    if ((size_t)splits * stride > M.part_floats)
+      return cfail(PPRS_EINVAL, "split-K workspace too small");
+    out = M.part;
+  }
+  dim3 grid(Nc / 64, Mr / 64, splits);
+  if (!ak && !bk) hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, M.stream, A, lda, B, ldb, out, ldc, K, kps, stride);
+  else if (!ak && bk) hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, M.stream, A, lda, B, ldb, out, ldc, K, kps, stride);
+  else if (ak && !bk) hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, M.stream, A, lda, B, ldb, out, ldc, K, kps, stride);
+  else hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, M.stream, A, lda, B, ldb, out, ldc, K, kps, stride);
+  CHK(hipGetLastError());
+  if (splits > 1) {
+    hipLaunchKernelGGL(k_split_sum, dim3(grid1d(stride)), dim3(kBlock), 0, M.stream, M.part,
+                       stride, splits, C, stride);
+    CHK(hipGetLastError());
+  }
+  return PPRS_OK;
+}
+
+static void define_layers(Model& M) {
+  const int cin[6] = {2, 64, 128, 384, 192, 66}, cout[6] = {64, 128, 256, 128, 64, 2};
+  const int stride[6] = {2, 2, 2, 1, 1, 1}, hin[6] = {128, 64, 32, 32, 64, 128};
+  long long off = 0;
+  for (int l = 0; l < 6; ++l) {
+    Layer& y = M.L[l];
+    y.cin = cin[l];
+    y.cout = cout[l];
+    y.stride = stride[l];
+    y.hin = hin[l];
+    y.hout = hin[l] / stride[l];
+    int k = 9 * cin[l];
+    y.kp = l == 0 ? 64 : (l == 5 ? k : ((k + 31) / 32) * 32);
+    y.woff = off;
+    off += (long long)y.cout * y.kp;
+    y.boff = off;
+    off += y.cout;
+  }
+  M.n_params = off;
+}
+
+static pprs_status alloc_batch(Model& M, int B) {
+  if (B <= M.cap_b) return PPRS_OK;
+  void* ptrs[] = {M.x0, M.a[0], M.a[1], M.a[2], M.a[3], M.a[4], M.u4, M.u5, M.u6, M.col, M.dzb,
+                  M.z, M.y, M.dy, M.dcol, M.du, M.da[0], M.da[1], M.da[2], M.da[3], M.da[4],
+                  M.part, M.lpart};
+  for (void* p : ptrs)
+    if (p) CHK(hipFree(p));
+  long long P128 = (long long)B * 128 * 128, P64 = P128 / 4, P32 = P128 / 16, P16 = P128 / 64;
+  long long col_max = 0, z_max = 0;
+  for (int l = 0; l < 5; ++l) {
+    long long pix = (long long)B * M.L[l].hout * M.L[l].hout;
+    col_max = std::max(col_max, pix * M.L[l].kp);
+    z_max = std::max(z_max, pix * (long long)M.L[l].cout);
+  }
+  CHK(hipMalloc(&M.x0, sizeof(bf16) * P128 * 2));
+  CHK(hipMalloc(&M.a[0], sizeof(bf16) * P64 * 64));
+  CHK(hipMalloc(&M.a[1], sizeof(bf16) * P32 * 128));
+  CHK(hipMalloc(&M.a[2], sizeof(bf16) * P16 * 256));
+  CHK(hipMalloc(&M.a[3], sizeof(bf16) * P32 * 128));
+  CHK(hipMalloc(&M.a[4], sizeof(bf16) * P64 * 64));
+  CHK(hipMalloc(&M.u4, sizeof(bf16) * P32 * 384));
+  CHK(hipMalloc(&M.u5, sizeof(bf16) * P64 * 192));
+  CHK(hipMalloc(&M.u6, sizeof(bf16) * P128 * 66));
+  CHK(hipMalloc(&M.col, sizeof(bf16) * col_max));
+  CHK(hipMalloc(&M.dzb, sizeof(bf16) * z_max));
+  CHK(hipMalloc(&M.z, sizeof(float) * z_max));
+  CHK(hipMalloc(&M.y, sizeof(float) * P128 * 2));
+  CHK(hipMalloc(&M.dy, sizeof(float) * P128 * 2));
+  CHK(hipMalloc(&M.dcol, sizeof(float) * col_max));
+  CHK(hipMalloc(&M.du, sizeof(float) * P128 * 66));
+  CHK(hipMalloc(&M.da[0], sizeof(float) * P64 * 64));
+  CHK(hipMalloc(&M.da[1], sizeof(float) * P32 * 128));
+  CHK(hipMalloc(&M.da[2], sizeof(float) * P16 * 256));
+  CHK(hipMalloc(&M.da[3], sizeof(float) * P32 * 128));
+  CHK(hipMalloc(&M.da[4], sizeof(float) * P64 * 64));
+  // split-K partials: weight gradients (<= 64 splits of the largest weight) or layer outputs
+  long long wmax = 0;
+  for (int l = 0; l < 5; ++l) wmax = std::max(wmax, (long long)M.L[l].cout * M.L[l].kp);
+  M.part_floats = (size_t)std::max(64 * wmax, 4 * (long long)(2 * 9 * 66 + 2) * 64);
+  CHK(hipMalloc(&M.part, sizeof(float) * M.part_floats));
+  CHK(hipMalloc(&M.lpart, sizeof(double) * 1024));
+  M.cap_b = B;
+  return PPRS_OK;
+}
+
+// Forward pass for B samples; input x [B][128][128][2] fp32; output in M.y.
+static pprs_status forward(Model& M, const float* x, int B) {
+  hipStream_t st = M.stream;
+  long long P128 = (long long)B * 128 * 128;
+  hipLaunchKernelGGL(k_f32_to_bf16, dim3(grid1d(P128 * 2)), dim3(kBlock), 0, st, x, P128 * 2, M.x0);
+  const bf16* in[5] = {M.x0, M.a[0], M.a[1], M.u4, M.u5};
+  for (int l = 0; l < 5; ++l) {
+    const Layer& y = M.L[l];
+    long long pix = (long long)B * y.hout * y.hout;
+    if (l == 3)
+      hipLaunchKernelGGL(k_upcat, dim3(grid1d(pix * 384)), dim3(kBlock), 0, st, M.a[2], 256, M.a[1], 128, B, 32, 32, M.u4);
+    if (l == 4)
+      hipLaunchKernelGGL(k_upcat, dim3(grid1d(pix * 192)), dim3(kBlock), 0, st, M.a[3], 128, M.a[0], 64, B, 64, 64, M.u5);
+    hipLaunchKernelGGL(k_im2col, dim3(grid1d(pix * y.kp)), dim3(kBlock), 0, st, in[l], B, y.hin, y.hin, y.cin, y.stride, y.kp, M.col);
+    pprs_status s = gemm(M, false, false, M.col, y.kp, M.wb + y.woff, y.kp, M.z, y.cout, (int)pix, y.cout, y.kp, 1);
+    if (s != PPRS_OK) return s;
+    hipLaunchKernelGGL(k_bias_relu, dim3(grid1d(pix * y.cout)), dim3(kBlock), 0, st, M.z, M.w + y.boff, pix, y.cout, M.a[l]);
+  }
+  // L6
+  const Layer& y6 = M.L[5];
+  hipLaunchKernelGGL(k_upcat, dim3(grid1d(P128 * 66)), dim3(kBlock), 0, st, M.a[4], 64, M.x0, 2, B, 128, 128, M.u6);
+  hipLaunchKernelGGL(k_l6_fwd, dim3(grid1d(P128)), dim3(kBlock), 0, st, M.u6, M.w6, M.w + y6.boff, B, 128, 128, 66, M.y);
+  CHK(hipGetLastError());
+  return PPRS_OK;
+}
+
+// fp32 view of the L6 weights from the bf16 copy (so every layer computes with bf16 weights).
+static pprs_status refresh_w6(Model& M) {
+  const Layer& y6 = M.L[5];
+  std::vector<uint16_t> hb((size_t)y6.cout * y6.kp);
+  CHK(hipMemcpyAsync(hb.data(), M.wb + y6.woff, hb.size() * 2, hipMemcpyDeviceToHost, M.stream));
+  CHK(hipStreamSynchronize(M.stream));
+  std::vector<float> hf(hb.size());
+  for (size_t i = 0; i < hb.size(); ++i) {
+    uint32_t u = (uint32_t)hb[i] << 16;
+    memcpy(&hf[i], &u, 4);
+  }
+  CHK(hipMemcpyAsync(M.w6, hf.data(), hf.size() * 4, hipMemcpyHostToDevice, M.stream));
+  CHK(hipStreamSynchronize(M.stream));
+  return PPRS_OK;
+}
+
+// Loss and full gradient into M.g (uses M.y from forward). Returns the mean squared error.
+static pprs_status backward(Model& M, const float* target, int B, int margin, double* loss) {
+  hipStream_t st = M.stream;
+  long long P128 = (long long)B * 128 * 128;
+  int interior = 128 - 2 * margin;
+  float inv_count = 1.f / ((float)B * interior * interior * 2);
+  int blocks = 1024;
+  hipLaunchKernelGGL(k_mse, dim3(blocks), dim3(kBlock), 0, st, M.y, target, B, 128, 128, margin, inv_count, M.dy, M.lpart);
+  std::vector<double> hp(blocks);
+  CHK(hipMemcpyAsync(hp.data(), M.lpart, sizeof(double) * blocks, hipMemcpyDeviceToHost, st));
+  CHK(hipMemsetAsync(M.g, 0, sizeof(float) * M.n_params, st));
+  // L6: dW6, db6, dU6
+  const Layer& y6 = M.L[5];
+  {
+    int nw = 2 * 9 * 66 + 2, chunks = 64;
+    hipLaunchKernelGGL(k_l6_bwd_w_part, dim3(nw, chunks), dim3(kBlock), 0, st, M.dy, M.u6, B, 128, 128, 66, chunks, M.part);
+    // weights [2][9*66] then bias [2] are contiguous at woff: columns 0..nw-1 map to them
+    hipLaunchKernelGGL(k_colsum_final, dim3((nw + 255) / 256), dim3(256), 0, st, M.part, nw, chunks, M.g + y6.woff);
+    hipLaunchKernelGGL(k_l6_bwd_data, dim3(grid1d(P128 * 66)), dim3(kBlock), 0, st, M.dy, M.w6, B, 128, 128, 66, M.du);
+    // split dU6 into d a[4] (upsampled part); the input part needs no gradient
+    hipLaunchKernelGGL(k_upcat_bwd, dim3(grid1d(P128 / 4 * 64)), dim3(kBlock), 0, st, M.du, 64, 2, B, 128, 128, M.da[4], (float*)nullptr, 0);
+  }
+  CHK(hipGetLastError());
+  // L5 .. L1
+  const bf16* in[5] = {M.x0, M.a[0], M.a[1], M.u4, M.u5};
+  for (int l = 4; l >= 0; --l) {
+    const Layer& y = M.L[l];
+    long long pix = (long long)B * y.hout * y.hout;
+    // dZ = dA * relu'(A)
+    hipLaunchKernelGGL(k_relu_bwd, dim3(grid1d(pix * y.cout)), dim3(kBlock), 0, st, M.da[l], M.a[l], pix * y.cout, M.dzb);
+    // bias gradient
+    int chunks = 64;
+    hipLaunchKernelGGL(k_colsum_part, dim3(y.cout, chunks), dim3(kBlock), 0, st, M.dzb, pix, y.cout, chunks, M.part);
+    hipLaunchKernelGGL(k_colsum_final, dim3((y.cout + 255) / 256), dim3(256), 0, st, M.part, y.cout, chunks, M.g + y.boff);
+    // weight gradient: dW[co][k] = sum_pix dZ[pix][co] col[pix][k]
+    hipLaunchKernelGGL(k_im2col, dim3(grid1d(pix * y.kp)), dim3(kBlock), 0, st, in[l], B, y.hin, y.hin, y.cin, y.stride, y.kp, M.col);
+    int splits = (int)std::min<long long>(64, pix / 256);
+    if (splits < 1) splits = 1;
+    pprs_status s = gemm(M, true, true, M.dzb, y.cout, M.col, y.kp, M.g + y.woff, y.kp, y.cout, y.kp, (int)pix, splits);
+    if (s != PPRS_OK) return s;
+    if (l == 0) break;
+    // data gradient: dcol[pix][k] = sum_co dZ[pix][co] W[co][k]; then col2im into the input
+    s = gemm(M, false, true, M.dzb, y.cout, M.wb + y.woff, y.kp, M.dcol, y.kp, (int)pix, y.kp, y.cout, 1);
+    if (s != PPRS_OK) return s;
+    if (l == 4) {
+      // input u5 = [up2(a4) 128, a1 64] at 64^2
+      hipLaunchKernelGGL(k_col2im, dim3(grid1d((long long)B * 64 * 64 * 192)), dim3(kBlock), 0, st, M.dcol, B, 64, 64, 192, 1, y.kp, M.du, 0);
+      hipLaunchKernelGGL(k_upcat_bwd, dim3(grid1d((long long)B * 64 * 64 * 64 + (long long)B * 32 * 32 * 128)), dim3(kBlock), 0, st, M.du, 128, 64, B, 64, 64, M.da[3], M.da[0], 0);
+    } else if (l == 3) {
+      // input u4 = [up2(a3) 256, a2 128] at 32^2
+      hipLaunchKernelGGL(k_col2im, dim3(grid1d((long long)B * 32 * 32 * 384)), dim3(kBlock), 0, st, M.dcol, B, 32, 32, 384, 1, y.kp, M.du, 0);
+      hipLaunchKernelGGL(k_upcat_bwd, dim3(grid1d((long long)B * 16 * 16 * 256 + (long long)B * 32 * 32 * 128)), dim3(kBlock), 0, st, M.du, 256, 128, B, 32, 32, M.da[2], M.da[1], 0);
+    } else if (l == 2) {
+      // input a2 (32^2 x 128), stride 2; a2 already holds the skip gradient from L4
+      hipLaunchKernelGGL(k_col2im, dim3(grid1d((long long)B * 32 * 32 * 128)), dim3(kBlock), 0, st, M.dcol, B, 32, 32, 128, 2, y.kp, M.da[1], 1);
+    } else if (l == 1) {
+      // input a1 (64^2 x 64), stride 2; a1 already holds the skip gradient from L5
+      hipLaunchKernelGGL(k_col2im, dim3(grid1d((long long)B * 64 * 64 * 64)), dim3(kBlock), 0, st, M.dcol, B, 64, 64, 64, 2, y.kp, M.da[0], 1);
+    }
+    CHK(hipGetLastError());
+  }
+  CHK(hipStreamSynchronize(st));
+  double sum = 0.0;
+  for (int i = 0; i < blocks; ++i) sum += hp[i];
+  if (loss) *loss = sum / ((double)B * interior * interior * 2);
+  return PPRS_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// C-ABI
+
+extern "C" {
+
+const char* pprs_cnn_last_error(void) { return g_cnn_err.c_str(); }
+
+pprs_status pprs_cnn_create(pprs_cnn** out, int device, void* stream, unsigned long long seed) {
+  if (!out) return cfail(PPRS_EINVAL, "out is NULL");
+  *out = nullptr;
+  CHK(hipSetDevice(device));
+  pprs_cnn* c = new pprs_cnn();
+  Model& M = c->M;
+  M.device = device;
+  M.stream = (hipStream_t)stream;
+  define_layers(M);
+  // He-normal initialisation from a counter-based hash (SplitMix64) of (seed, index)
+  std::vector<float> hw(M.n_params, 0.f);
+  auto mix = [](unsigned long long x) {
+    x += 0x9E3779B97F4A7C15ULL;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+    return x ^ (x >> 31);
+  };
+  for (int l = 0; l < 6; ++l) {
+    const Layer& y = M.L[l];
+    int k = 9 * y.cin;
+    double sd = sqrt(2.0 / k) * (l == 5 ? 0.1 : 1.0);
+    for (int co = 0; co < y.cout; ++co)
+      for (int j = 0; j < k; ++j) {
+        long long i = y.woff + (long long)co * y.kp + j;
+        unsigned long long r1 = mix(seed * 0x100000001B3ULL + 2 * (unsigned long long)i);
+        unsigned long long r2 = mix(seed * 0x100000001B3ULL + 2 * (unsigned long long)i + 1);
+        double u1 = ((r1 >> 11) + 0.5) / 9007199254740992.0, u2 = (r2 >> 11) / 9007199254740992.0;
+        hw[i] = (float)(sd * sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
+      }
+  }
+  hipError_t e = hipSuccess;
+  e = hipMalloc(&M.w, sizeof(float) * M.n_params);
+  if (e == hipSuccess) e = hipMalloc(&M.m, sizeof(float) * M.n_params);
+  if (e == hipSuccess) e = hipMalloc(&M.v, sizeof(float) * M.n_params);
+  if (e == hipSuccess) e = hipMalloc(&M.g, sizeof(float) * M.n_params);
+  if (e == hipSuccess) e = hipMalloc(&M.wb, sizeof(bf16) * M.n_params);
+  if (e == hipSuccess) e = hipMalloc(&M.w6, sizeof(float) * M.L[5].cout * M.L[5].kp);
+  if (e != hipSuccess) {
+    delete c;
+    return cfail(PPRS_ENOMEM, "cnn allocation failed");
+  }
+  *out = c;
+  pprs_status s = pprs_cnn_set_params(c, hw.data(), (size_t)M.n_params);
+  return s;
+}
+
+void pprs_cnn_destroy(pprs_cnn* c) {
+  if (!c) return;
+  Model& M = c->M;
+  (void)hipSetDevice(M.device);
+  (void)hipStreamSynchronize(M.stream);
+  void* ptrs[] = {M.w, M.m, M.v, M.g, M.wb, M.w6, M.x0, M.a[0], M.a[1], M.a[2], M.a[3], M.a[4],
+                  M.u4, M.u5, M.u6, M.col, M.dzb, M.z, M.y, M.dy, M.dcol, M.du, M.da[0],
+                  M.da[1], M.da[2], M.da[3], M.da[4], M.part, M.lpart};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete c;
+}
+
+size_t pprs_cnn_param_count(const pprs_cnn* c) { return c ? (size_t)c->M.n_params : 0; }
+
+pprs_status pprs_cnn_set_params(pprs_cnn* c, const float* host, size_t count) {
+  if (!c || !host) return cfail(PPRS_EINVAL, "NULL argument");
+  Model& M = c->M;
+  if (count != (size_t)M.n_params) return cfail(PPRS_EINVAL, "expected %lld parameters", M.n_params);
+  CHK(hipSetDevice(M.device));
+  CHK(hipMemcpyAsync(M.w, host, sizeof(float) * count, hipMemcpyHostToDevice, M.stream));
+  CHK(hipMemsetAsync(M.m, 0, sizeof(float) * count, M.stream));
+  CHK(hipMemsetAsync(M.v, 0, sizeof(float) * count, M.stream));
+  hipLaunchKernelGGL(k_f32_to_bf16, dim3(grid1d(count)), dim3(kBlock), 0, M.stream, M.w, (long long)count, M.wb);
+  CHK(hipGetLastError());
+  M.step = 0;
+  return refresh_w6(M);
+}
+
+pprs_status pprs_cnn_get_params(pprs_cnn* c, float* host, size_t count) {
+  if (!c || !host) return cfail(PPRS_EINVAL, "NULL argument");
+  Model& M = c->M;
+  if (count != (size_t)M.n_params) return cfail(PPRS_EINVAL, "expected %lld parameters", M.n_params);
+  CHK(hipSetDevice(M.device));
+  CHK(hipMemcpyAsync(host, M.w, sizeof(float) * count, hipMemcpyDeviceToHost, M.stream));
+  CHK(hipStreamSynchronize(M.stream));
+  return PPRS_OK;
+}
+
+pprs_status pprs_cnn_forward(pprs_cnn* c, const float* x, int B, float* y) {
+  if (!c || !x || !y || B < 1) return cfail(PPRS_EINVAL, "bad arguments");
+  Model& M = c->M;
+  CHK(hipSetDevice(M.device));
+  pprs_status s = alloc_batch(M, B);
+  if (s != PPRS_OK) return s;
+  s = forward(M, x, B);
+  if (s != PPRS_OK) return s;
+  CHK(hipMemcpyAsync(y, M.y, sizeof(float) * (size_t)B * 128 * 128 * 2, hipMemcpyDeviceToDevice, M.stream));
+  CHK(hipStreamSynchronize(M.stream));
+  return PPRS_OK;
+}
+
+pprs_status pprs_cnn_gradients(pprs_cnn* c, const float* x, const float* target, int B,
+                               int margin, double* loss, float* grad_host) {
+  if (!c || !x || !target || B < 1 || margin < 0 || margin >= 64)
+    return cfail(PPRS_EINVAL, "bad arguments");
+  Model& M = c->M;
+  CHK(hipSetDevice(M.device));
+  pprs_status s = alloc_batch(M, B);
+  if (s != PPRS_OK) return s;
+  if ((s = forward(M, x, B)) != PPRS_OK) return s;
+  if ((s = backward(M, target, B, margin, loss)) != PPRS_OK) return s;
+  if (grad_host) {
+    CHK(hipMemcpyAsync(grad_host, M.g, sizeof(float) * M.n_params, hipMemcpyDeviceToHost, M.stream));
+    CHK(hipStreamSynchronize(M.stream));
+  }
+  return PPRS_OK;
+}
+
+pprs_status pprs_cnn_train_step(pprs_cnn* c, const float* x, const float* target, int B,
+                                int margin, float lr, double* loss) {
+  pprs_status s = pprs_cnn_gradients(c, x, target, B, margin, loss, nullptr);
+  if (s != PPRS_OK) return s;
+  Model& M = c->M;
+  M.step++;
+  const float b1 = 0.9f, b2 = 0.999f;
+  float c1 = 1.f - powf(b1, (float)M.step), c2 = 1.f - powf(b2, (float)M.step);
+  hipLaunchKernelGGL(k_adam, dim3(grid1d(M.n_params)), dim3(kBlock), 0, M.stream, M.w, M.m, M.v, M.g, M.n_params, lr, b1, b2, 1e-8f, c1, c2, M.wb);
+  CHK(hipGetLastError());
+  return refresh_w6(M);
+}
+
+}  // extern "C"
+
+// Used by the runtime: pack pairs of level-7 frames and run the network.
+namespace pprs_cnn_api {
+hipError_t pack_pairs(const float* lvl, int n, const int* ref, const int* tmpl, int P,
+                      float* out, hipStream_t st) {
+  long long work = (long long)P * (n - 1) * (n - 1);
+  hipLaunchKernelGGL(k_pack_pairs, dim3(grid1d(work)), dim3(kBlock), 0, st, lvl, n, ref, tmpl, P, out);
+  return hipGetLastError();
+}
+pprs_status forward_into(pprs_cnn* c, const float* x, int B, float* y) {
+  return pprs_cnn_forward(c, x, B, y);
+}
+hipError_t planes_to_nhwc(const float* src, int n, long long pstride, int P, float scale,
+                          float* out, hipStream_t st) {
+  long long work = (long long)P * (n - 1) * (n - 1);
+  hipLaunchKernelGGL(k_planes_to_nhwc, dim3(grid1d(work)), dim3(kBlock), 0, st, src, n, pstride, P, scale, out);
+  return hipGetLastError();
+}
+hipError_t nhwc_to_planes(const float* y, int S, int P, float scale, float* base,
+                          long long stride, hipStream_t st) {
+  long long work = (long long)P * (S + 1) * (S + 1);
+  hipLaunchKernelGGL(k_nhwc_to_planes, dim3(grid1d(work)), dim3(kBlock), 0, st, y, S, P, scale, base, stride);
+  return hipGetLastError();
+}
+int cnn_device(const pprs_cnn* c) { return c->M.device; }
+hipError_t check_pred(const float* y, int P, long long n_per, float limit, int* bad,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_check_pred, dim3(P), dim3(kBlock), 0, st, y, n_per, limit, bad);
+  return hipGetLastError();
+}
+}  // namespace pprs_cnn_api

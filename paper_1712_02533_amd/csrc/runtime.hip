@@ -21,6 +21,19 @@
 #include "kernels.h"
 #include "pprs_internal.h"
 
+namespace pprs_cnn_api {
+hipError_t pack_pairs(const float* lvl, int n, const int* ref, const int* tmpl, int P,
+                      float* out, hipStream_t st);
+pprs_status forward_into(pprs_cnn* c, const float* x, int B, float* y);
+hipError_t planes_to_nhwc(const float* src, int n, long long pstride, int P, float scale,
+                          float* out, hipStream_t st);
+hipError_t nhwc_to_planes(const float* y, int S, int P, float scale, float* base,
+                          long long stride, hipStream_t st);
+int cnn_device(const pprs_cnn* c);
+hipError_t check_pred(const float* y, int P, long long n_per, float limit, int* bad,
+                      hipStream_t st);
+}  // namespace pprs_cnn_api
+
 static thread_local std::string g_err = "no error";
 
 static pprs_status fail(pprs_status s, const char* fmt, ...) {
@@ -81,6 +94,9 @@ struct pprs_ctx {
   DevBuf elems;
   int* active_host = nullptr;
   bool log = false;  // one progress line per batch on stderr (environment PPRS_LOG=1)
+  pprs_cnn* cnn = nullptr;  // warm start network (not owned)
+  double warm_max_cells = 8.0;
+  DevBuf cnn_in, cnn_out, tmp, badflags;
   BatchDesc hd;
   int slots_cap = 0, slots_L = -1, slots_m0 = -1;
   double coef_beta = -1.0;
@@ -376,7 +392,7 @@ pprs_status launch_step(pprs_ctx* c, BatchDesc* d, int ladder_k, size_t lds) {
   return PPRS_OK;
 }
 
-enum InitKind { INIT_IDENTITY = 0, INIT_COMPOSE = 1, INIT_GIVEN = 2 };
+enum InitKind { INIT_IDENTITY = 0, INIT_COMPOSE = 1, INIT_GIVEN = 2, INIT_PREPARED = 3 };
 
 // Runs n slots (reference ref[s], template tmpl[s]) to completion and writes each result
 // (domain units, [2][nL][nL]) to elems[out_idx[s]]. INIT_COMPOSE composes elems[left[s]]
@@ -384,7 +400,8 @@ enum InitKind { INIT_IDENTITY = 0, INIT_COMPOSE = 1, INIT_GIVEN = 2 };
 pprs_status run_batch(pprs_ctx* c, int n, const int* ref, const int* tmpl, InitKind init,
                       const int* left, const int* right, const int* out_idx, float* elems,
                       const pprs_params* p, pprs_pair_stats* stats, long long* node_steps,
-                      long long* node_passes, int* flags_or) {
+                      long long* node_passes, int* flags_or, int start = -1,
+                      const int* start_level = nullptr, const int* extra_flags = nullptr) {
   if (n <= 0) return PPRS_OK;
   auto t_start = std::chrono::steady_clock::now();
   BatchDesc& hd = c->hd;
@@ -400,16 +417,19 @@ pprs_status run_batch(pprs_ctx* c, int n, const int* ref, const int* tmpl, InitK
   hd.iter_max = p->iter_max;
   BatchDesc* d = P<BatchDesc>(c->desc);
   HIPCHK(hipMemcpyAsync(d, &hd, sizeof(BatchDesc), hipMemcpyHostToDevice, c->stream));
+  if (start < m0 || start > L) start = m0;
   std::vector<SlotState> st(n);
   for (int s = 0; s < n; ++s) {
+    int lv = start_level ? start_level[s] : start;
     memset(&st[s], 0, sizeof(SlotState));
     st[s].phase = PH_INIT;
-    st[s].level = m0;
+    st[s].level = lv;
     st[s].ref = ref[s];
     st[s].tmpl = tmpl[s];
     st[s].finest = L;
-    st[s].coarsest = m0;
+    st[s].coarsest = lv;
     st[s].tau_prev = INFINITY;
+    st[s].flags = extra_flags ? extra_flags[s] : 0;
   }
   HIPCHK(hipMemcpyAsync(hd.state, st.data(), sizeof(SlotState) * n, hipMemcpyHostToDevice,
                         c->stream));
@@ -424,16 +444,16 @@ pprs_status run_batch(pprs_ctx* c, int n, const int* ref, const int* tmpl, InitK
   HIPCHK(hipMemcpyAsync(didx, idx.data(), sizeof(int) * 3 * n, hipMemcpyHostToDevice,
                         c->stream));
   long long est = 2LL * nL * nL;
-  // initial guess on the coarsest level
+  // initial guess on the start level (INIT_PREPARED: the caller filled it)
   if (init == INIT_IDENTITY) {
-    int n0 = level_n(m0);
-    HIPCHK(pprs_k::fill_strided(hd.ubuf + hd.u_off[m0], hd.slot_u_stride, 2LL * n0 * n0, n,
+    int n0 = level_n(start);
+    HIPCHK(pprs_k::fill_strided(hd.ubuf + hd.u_off[start], hd.slot_u_stride, 2LL * n0 * n0, n,
                                 0.f, c->stream));
-  } else {
+  } else if (init != INIT_PREPARED) {
     if (init == INIT_COMPOSE)
       HIPCHK(pprs_k::compose(elems, est, didx, didx + n, hd.ubuf + hd.u_off[L],
                              hd.slot_u_stride, nL, n, c->stream));
-    for (int l = L; l > m0; --l) {
+    for (int l = L; l > start; --l) {
       int nf = level_n(l), nc = level_n(l - 1);
       HIPCHK(pprs_k::restrict_planes(hd.ubuf + hd.u_off[l], hd.slot_u_stride, (long long)nf * nf,
                                      hd.ubuf + hd.u_off[l - 1], hd.slot_u_stride,
@@ -478,23 +498,60 @@ pprs_status run_batch(pprs_ctx* c, int n, const int* ref, const int* tmpl, InitK
   for (int s = 0; s < n; ++s) {
     if (flags_or) *flags_or |= st[s].flags;
     for (int k = 0; k < WK_COUNT; ++k) c->nodes_acc[k] += nodes[(size_t)s * WK_COUNT + k];
-    for (int l = m0; l <= L; ++l) {
+    for (int l = st[s].coarsest; l <= L; ++l) {
       long long nn = (long long)level_n(l) * level_n(l);
-      if (node_steps) *node_steps += nn * st[s].iters[l - m0];
-      if (node_passes) *node_passes += nn * st[s].passes[l - m0];
+      if (node_steps) *node_steps += nn * st[s].iters[l - st[s].coarsest];
+      if (node_passes) *node_passes += nn * st[s].passes[l - st[s].coarsest];
     }
     if (stats) {
       pprs_pair_stats& o = stats[s];
       memset(&o, 0, sizeof o);
-      for (int l = m0; l <= L; ++l) {
-        o.iters[l - m0] = st[s].iters[l - m0];
-        o.passes[l - m0] = st[s].passes[l - m0];
+      for (int l = st[s].coarsest; l <= L; ++l) {
+        o.iters[l - st[s].coarsest] = st[s].iters[l - st[s].coarsest];
+        o.passes[l - st[s].coarsest] = st[s].passes[l - st[s].coarsest];
       }
       o.energy = st[s].E;
       o.ncc = st[s].ncc;
       o.flags = st[s].flags;
     }
   }
+  return PPRS_OK;
+}
+
+const int kWarmLevel = 7;     // the network works on 128^2 frames (level 7)
+const int kWarmChunk = 64;    // pairs per network call
+
+// Network predictions for n pairs (ref[s], tmpl[s]) written as level-7 guesses into slot s's
+// first u buffer; bad[s] = 1 for predictions that are not finite or exceed the bound.
+pprs_status warm_predict(pprs_ctx* c, int n, const int* ref, const int* tmpl,
+                         std::vector<int>& bad) {
+  BatchDesc& hd = c->hd;
+  int S = 1 << kWarmLevel;
+  size_t per = (size_t)S * S * 2;
+  int chunk = std::min(n, kWarmChunk);
+  STCHK(ensure(c->cnn_in, sizeof(float) * per * chunk));
+  STCHK(ensure(c->cnn_out, sizeof(float) * per * chunk));
+  STCHK(ensure(c->badflags, sizeof(int) * 3 * (size_t)n));
+  int* dref = P<int>(c->badflags);
+  int* dtmpl = dref + n;
+  int* dbad = dtmpl + n;
+  HIPCHK(hipMemcpyAsync(dref, ref, sizeof(int) * n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(dtmpl, tmpl, sizeof(int) * n, hipMemcpyHostToDevice, c->stream));
+  for (int p0 = 0; p0 < n; p0 += chunk) {
+    int np = std::min(chunk, n - p0);
+    HIPCHK(pprs_cnn_api::pack_pairs(hd.frames[kWarmLevel], S + 1, dref + p0, dtmpl + p0, np,
+                                    P<float>(c->cnn_in), c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    STCHK(pprs_cnn_api::forward_into(c->cnn, P<float>(c->cnn_in), np, P<float>(c->cnn_out)));
+    HIPCHK(pprs_cnn_api::check_pred(P<float>(c->cnn_out), np, (long long)per,
+                                    (float)c->warm_max_cells, dbad + p0, c->stream));
+    HIPCHK(pprs_cnn_api::nhwc_to_planes(P<float>(c->cnn_out), S, np, 1.0f / S,
+                                        hd.ubuf + hd.u_off[kWarmLevel] + (size_t)p0 * hd.slot_u_stride,
+                                        hd.slot_u_stride, c->stream));
+  }
+  bad.assign(n, 0);
+  HIPCHK(hipMemcpyAsync(bad.data(), dbad, sizeof(int) * n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
   return PPRS_OK;
 }
 
@@ -568,7 +625,7 @@ void pprs_destroy(pprs_ctx* c) {
   DevBuf* bufs[] = {&c->frames, &c->rsum, &c->fr_ms, &c->fr_part, &c->state, &c->ubuf,
                     &c->dbuf, &c->gbuf, &c->zbuf, &c->partial, &c->counters, &c->nodecount,
                     &c->coef, &c->list_slots, &c->list_off, &c->lists, &c->desc, &c->opidx,
-                    &c->elems};
+                    &c->elems, &c->cnn_in, &c->cnn_out, &c->tmp, &c->badflags};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -660,6 +717,7 @@ pprs_status pprs_prefix_register_series(pprs_ctx* c, const float* frames, int N,
   pprs_series_stats S;
   memset(&S, 0, sizeof S);
   HIPCHK(pprs_k::fill(u_out, 2LL * (long long)plane, 0.f, c->stream));
+  bool warm = c->cnn != nullptr && m0 <= kWarmLevel && kWarmLevel <= L;
   if (M >= 1) {
     STCHK(prepare_frames(c, frames, N, H, L, m0, N - 1));
   }
@@ -692,8 +750,24 @@ pprs_status pprs_prefix_register_series(pprs_ctx* c, const float* frames, int N,
       ei[m] = m;
       ek[m] = m + 1;
     }
-    STCHK(run_batch(c, M, ref.data(), tmpl.data(), INIT_IDENTITY, nullptr, nullptr, out.data(),
-                    elems, params, op_stats, &S.node_steps, &S.node_passes, &flags));
+    if (warm) {
+      std::vector<int> bad, lv(M), fl(M);
+      STCHK(warm_predict(c, M, ref.data(), tmpl.data(), bad));
+      int n0 = level_n(m0);
+      HIPCHK(pprs_k::fill_strided(c->hd.ubuf + c->hd.u_off[m0], c->hd.slot_u_stride,
+                                  2LL * n0 * n0, M, 0.f, c->stream));
+      for (int m = 0; m < M; ++m) {
+        lv[m] = bad[m] ? m0 : kWarmLevel;
+        fl[m] = bad[m] ? PPRS_FLAG_FALLBACK : 0;
+      }
+      STCHK(run_batch(c, M, ref.data(), tmpl.data(), INIT_PREPARED, nullptr, nullptr,
+                      out.data(), elems, params, op_stats, &S.node_steps, &S.node_passes, &flags,
+                      m0, lv.data(), fl.data()));
+    } else {
+      STCHK(run_batch(c, M, ref.data(), tmpl.data(), INIT_IDENTITY, nullptr, nullptr,
+                      out.data(), elems, params, op_stats, &S.node_steps, &S.node_passes,
+                      &flags));
+    }
     HIPCHK(hipEventRecord(e2, c->stream));
     // scan: every level of the schedule is one batch of B applications
     int done = 0;
@@ -713,7 +787,7 @@ pprs_status pprs_prefix_register_series(pprs_ctx* c, const float* frames, int N,
       int cnt = (int)lft.size();
       STCHK(run_batch(c, cnt, r2.data(), t2.data(), INIT_COMPOSE, lft.data(), rgt.data(),
                       rgt.data(), elems, params, op_stats ? op_stats + M + done : nullptr,
-                      &S.node_steps, &S.node_passes, &flags));
+                      &S.node_steps, &S.node_passes, &flags, warm ? kWarmLevel : m0));
       for (int k = 0; k < cnt; ++k) ei[rgt[k]] = ei[lft[k]];
       done += cnt;
     }
@@ -746,6 +820,70 @@ pprs_status pprs_prefix_register_series(pprs_ctx* c, const float* frames, int N,
   S.ms_scan = t23;
   if (stats) *stats = S;
   return status_from_flags(flags);
+}
+
+pprs_status pprs_set_warm_start(pprs_ctx* c, pprs_cnn* cnn, double max_cells) {
+  STCHK(enter(c));
+  if (cnn && pprs_cnn_api::cnn_device(cnn) != c->device)
+    return fail(PPRS_EINVAL, "network and context are on different devices");
+  if (!(max_cells > 0.0)) return fail(PPRS_EINVAL, "max_cells must be > 0");
+  c->cnn = cnn;
+  c->warm_max_cells = max_cells;
+  return PPRS_OK;
+}
+
+pprs_status pprs_pair_inputs(pprs_ctx* c, const float* frames, int N, int H, int W,
+                             const int* ref, const int* tmpl, int P, float* out) {
+  STCHK(enter(c));
+  int L = frame_level(H, W);
+  if (L < kWarmLevel) return fail(PPRS_EINVAL, "frames must have a side of at least 128");
+  if (!frames || !ref || !tmpl || !out || N < 1 || P < 1) return fail(PPRS_EINVAL, "bad arguments");
+  for (int p = 0; p < P; ++p)
+    if (ref[p] < 0 || ref[p] >= N || tmpl[p] < 0 || tmpl[p] >= N)
+      return fail(PPRS_EINVAL, "pair %d has a frame index out of range", p);
+  STCHK(prepare_frames(c, frames, N, H, L, kWarmLevel, 0));
+  STCHK(ensure(c->badflags, sizeof(int) * 2 * (size_t)P));
+  int* dref = ::P<int>(c->badflags);
+  HIPCHK(hipMemcpyAsync(dref, ref, sizeof(int) * P, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(dref + P, tmpl, sizeof(int) * P, hipMemcpyHostToDevice, c->stream));
+  int S = 1 << kWarmLevel;
+  HIPCHK(pprs_cnn_api::pack_pairs(c->hd.frames[kWarmLevel], S + 1, dref, dref + P, P, out,
+                                  c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return PPRS_OK;
+}
+
+pprs_status pprs_level7_targets(pprs_ctx* c, const float* u, int P, int H, int W, float* out) {
+  STCHK(enter(c));
+  int L = frame_level(H, W);
+  if (L < kWarmLevel) return fail(PPRS_EINVAL, "fields must have a side of at least 128");
+  if (!u || !out || P < 1) return fail(PPRS_EINVAL, "bad arguments");
+  int nL = level_n(L);
+  const int chunk = 256;
+  // per chunk: level L planes, then the restrictions down to level 7 (ping-pong)
+  size_t a = (size_t)2 * chunk * nL * nL, b = (size_t)2 * chunk * level_n(L - 1) * level_n(L - 1);
+  STCHK(ensure(c->tmp, sizeof(float) * (a + b)));
+  float* bufA = ::P<float>(c->tmp);
+  float* bufB = bufA + a;
+  size_t plane = (size_t)H * W;
+  int S = 1 << kWarmLevel;
+  for (int p0 = 0; p0 < P; p0 += chunk) {
+    int np = std::min(chunk, P - p0);
+    HIPCHK(pprs_k::to_nodes(u + (size_t)p0 * 2 * plane, H, (long long)plane, bufA, nL,
+                            (long long)nL * nL, 2 * np, 1.0f / (float)(nL - 1), c->stream));
+    float* cur = bufA;
+    float* nxt = bufB;
+    for (int l = L; l > kWarmLevel; --l) {
+      int nf = level_n(l), nc = level_n(l - 1);
+      HIPCHK(pprs_k::restrict_planes(cur, (long long)nf * nf, 0, nxt, (long long)nc * nc, 0, 1,
+                                     nf, 2 * np, c->stream));
+      std::swap(cur, nxt);
+    }
+    HIPCHK(pprs_cnn_api::planes_to_nhwc(cur, S + 1, 2LL * (S + 1) * (S + 1), np, (float)S,
+                                        out + (size_t)p0 * S * S * 2, c->stream));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return PPRS_OK;
 }
 
 pprs_status pprs_set_kernel_timing(pprs_ctx* c, int enable) {
