@@ -65,7 +65,8 @@ typedef struct {
 
 /* Statistics of one A or B application. Level index 0 is the coarsest level. */
 typedef struct {
-  int iters[PPRS_MAX_LEVELS];   /* accepted gradient-flow steps per level */
+  int iters[PPRS_MAX_LEVELS];   /* accepted gradient-flow steps per level (0 for levels a
+                                   warm start skipped) */
   int passes[PPRS_MAX_LEVELS];  /* line-search passes per level */
   double energy;                /* final energy at the finest level */
   double ncc;                   /* final NCC at the finest level */
@@ -107,6 +108,17 @@ const char* pprs_last_error(void);
 pprs_status pprs_register_pair(pprs_ctx* ctx, const float* f_ref, const float* f_tmpl, int H,
                                int W, const float* u_init, float* u_out,
                                const pprs_params* params, pprs_pair_stats* stats);
+
+/* Function A over a batch: for p < P registers frames[tmpl[p]] to frames[ref[p]] (as
+   pprs_register_pair with the identity start, or the learned warm start when it is enabled on
+   ctx). frames: device [N][H][W]; ref, tmpl: host arrays of P indices in [0, N);
+   u_out: device [P][2][H][W] in pixels; stats: host array of P entries or NULL. The pairs run
+   as batches of up to 512 concurrent registrations; each result is independent of the batch it
+   ran in. Returns PPRS_EINVAL for an index out of range or a constant reference frame,
+   PPRS_NOT_CONVERGED when some registration hit iter_max. */
+pprs_status pprs_register_pairs(pprs_ctx* ctx, const float* frames, int N, int H, int W,
+                                const int* ref, const int* tmpl, int P, float* u_out,
+                                const pprs_params* params, pprs_pair_stats* stats);
 
 /* Composition of deformations (section "Registration for series of images"):
    (phi_jk o phi_ij)(x) = phi_jk(phi_ij(x)), i.e. u_ik(x) = u_ij(x) + u_jk(x + u_ij(x)) with
@@ -176,11 +188,19 @@ pprs_status pprs_pair_inputs(pprs_ctx* ctx, const float* frames, int N, int H, i
 /* Network targets: displacements u [P][2][H][W] (pixels) restricted to level 7 and expressed in
    level-7 cells, out [P][128][128][2]. */
 pprs_status pprs_level7_targets(pprs_ctx* ctx, const float* u, int P, int H, int W, float* out);
-/* Enables (cnn != NULL) or disables the warm start for later series calls on ctx: the
-   neighbour registrations start at level 7 from the network's prediction, B applications at
-   level 7 from the composition. A prediction that is not finite or exceeds max_cells level-7
-   cells falls back to the cold start from the coarsest level. */
-pprs_status pprs_set_warm_start(pprs_ctx* ctx, pprs_cnn* cnn, double max_cells);
+/* Warm-start modes. REFINE: the prediction, restricted to the coarsest level, replaces the
+   identity as the initial guess and every level runs (B applications are unchanged).
+   SKIP: the neighbour registrations start on level 7 from the prediction and B applications
+   on level 7 from the composition; the coarser levels are skipped. */
+#define PPRS_WARM_REFINE 0
+#define PPRS_WARM_SKIP 1
+
+/* Enables (cnn != NULL) or disables the warm start for later pprs_prefix_register_series and
+   pprs_register_pairs calls on ctx (it needs levels m0 <= 7 <= L). A prediction that is not
+   finite or exceeds max_cells level-7 cells is rejected: that pair runs the cold start and its
+   stats carry PPRS_FLAG_FALLBACK. ctx keeps the pointer: cnn must outlive its use. Returns
+   PPRS_EINVAL for max_cells <= 0, an unknown mode or a network on another device. */
+pprs_status pprs_set_warm_start(pprs_ctx* ctx, pprs_cnn* cnn, double max_cells, int mode);
 
 #ifdef __cplusplus
 }

@@ -63,6 +63,8 @@ def _load():
             "or_gradient_flow": (ctypes.c_int, [D, D, ctypes.c_int, D, P, I, I, D, D,
                                                 ctypes.c_int, I]),
             "or_register": (ctypes.c_int, [D, D, ctypes.c_int, D, P, D, S, D, ctypes.c_int, I]),
+            "or_register_from": (ctypes.c_int, [D, D, ctypes.c_int, ctypes.c_int, D, P, D, S, D,
+                                                ctypes.c_int, I]),
             "or_compose": (None, [D, D, ctypes.c_int, D]),
             "or_series": (ctypes.c_int, [D, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, D, S,
                                          S, I, ctypes.c_int]),
@@ -243,6 +245,28 @@ def register(R, T, params: Params, u0=None, trace_cap: int = 0):
         raise ValueError("constant reference on some level")
     if rc != 0:
         raise ValueError("invalid sizes or levels")
+    return u, _stats(st, params.levels), tr[: tl.value]
+
+
+def register_from(R, T, start: int, u_start, params: Params, trace_cap: int = 0):
+    """Operator A started on level `start` from u_start ([2, n, n] on that level, domain units);
+    the coarser levels are skipped. Returns (u [2, nf, nf], RegStats, trace)."""
+    R, T = _f64(R), _f64(T)
+    n = R.shape[-1]
+    us = _f64(u_start)
+    u = np.empty((2, n, n))
+    st = _CStats()
+    cp = params.c()
+    tr = np.zeros((max(trace_cap, 1), TRACE_W))
+    tl = ctypes.c_int()
+    if us.shape != (2, (1 << start) + 1, (1 << start) + 1):
+        raise ValueError("u_start must be [2, 2^start+1, 2^start+1]")
+    rc = _load().or_register_from(_d(R), _d(T), n, start, _d(us), ctypes.byref(cp), _d(u),
+                                  ctypes.byref(st), _d(tr), trace_cap, ctypes.byref(tl))
+    if rc == -1:
+        raise ValueError("constant reference on some level")
+    if rc != 0:
+        raise ValueError("invalid sizes, levels or start level")
     return u, _stats(st, params.levels), tr[: tl.value]
 
 

@@ -554,32 +554,91 @@ static int log2_exact(int m) {
   return (1 << l) == m ? l : -1;
 }
 
+/* Levels m0..L of the pyramid of R and T: raw restrictions, then the normalised reference
+   (zero mean, unit standard deviation). Returns -1 when the reference is constant on a level. */
+typedef struct {
+  double* Rl[OR_MAX_LEVELS + 1];
+  double* Tl[OR_MAX_LEVELS + 1];
+  double* Rn[OR_MAX_LEVELS + 1];
+  int m0, L;
+} pyramid_t;
+
+static int pyramid_build(pyramid_t* py, const double* R, const double* T, int L, int m0) {
+  int rc = 0;
+  py->m0 = m0;
+  py->L = L;
+  for (int l = L; l >= m0; --l) {
+    int n = (1 << l) + 1;
+    size_t nn = (size_t)n * n;
+    py->Rl[l] = malloc(sizeof(double) * nn);
+    py->Tl[l] = malloc(sizeof(double) * nn);
+    py->Rn[l] = malloc(sizeof(double) * nn);
+    if (l == L) {
+      memcpy(py->Rl[l], R, sizeof(double) * nn);
+      memcpy(py->Tl[l], T, sizeof(double) * nn);
+    } else {
+      or_restrict(py->Rl[l + 1], (1 << (l + 1)) + 1, py->Rl[l]);
+      or_restrict(py->Tl[l + 1], (1 << (l + 1)) + 1, py->Tl[l]);
+    }
+    if (or_normalize(py->Rl[l], n, py->Rn[l], NULL, NULL) != 0) rc = -1;
+  }
+  return rc;
+}
+
+static void pyramid_free(pyramid_t* py) {
+  for (int l = py->L; l >= py->m0; --l) {
+    free(py->Rl[l]);
+    free(py->Tl[l]);
+    free(py->Rn[l]);
+  }
+}
+
+/* Gradient flow on levels start..L from the guess u (level `start`, owned: freed here), each
+   result prolongated as the next level's start. Statistics are indexed from level m0. */
+static void run_levels(const pyramid_t* py, int start, double* u, const or_params* p,
+                       double* u_out, or_stats* st, double* trace, int trace_cap,
+                       int* trace_len) {
+  int L = py->L, m0 = py->m0, nf = (1 << L) + 1;
+  trace_t tr = {trace, trace_cap, 0};
+  if (st) memset(st, 0, sizeof(*st));
+  int flags = 0;
+  double e = 0.0, ncc = 0.0;
+  for (int l = start; l <= L; ++l) {
+    int n = (1 << l) + 1;
+    level_data LD = {n, py->Rn[l], py->Tl[l]};
+    int passes = 0;
+    int steps = gradient_flow(&LD, u, p, l, &passes, &flags, &e, &ncc, &tr);
+    if (st) {
+      st->iters[l - m0] = steps;
+      st->trials[l - m0] = passes;
+    }
+    if (l < L) {
+      int nn2 = (1 << (l + 1)) + 1;
+      double* uf = malloc(sizeof(double) * 2 * nn2 * nn2);
+      for (int c = 0; c < 2; ++c)
+        or_prolong(u + (size_t)c * n * n, n, uf + (size_t)c * nn2 * nn2);
+      free(u);
+      u = uf;
+    }
+  }
+  memcpy(u_out, u, sizeof(double) * 2 * nf * nf);
+  free(u);
+  if (st) {
+    st->energy = e;
+    st->ncc = ncc;
+    st->flags = flags;
+  }
+  if (trace_len) *trace_len = tr.len;
+}
+
 int or_register(const double* R, const double* T, int nf, const double* u0, const or_params* p,
                 double* u_out, or_stats* st, double* trace, int trace_cap, int* trace_len) {
   int L = log2_exact(nf - 1);
   if (L < 1 || p->levels < 1 || p->levels > L || p->levels > OR_MAX_LEVELS) return -2;
   int m0 = L - p->levels + 1;
-  double* Rl[OR_MAX_LEVELS + 1];
-  double* Tl[OR_MAX_LEVELS + 1];
-  double* Rn[OR_MAX_LEVELS + 1];
-  int rc = 0;
-  for (int l = L; l >= m0; --l) {
-    int n = (1 << l) + 1;
-    size_t nn = (size_t)n * n;
-    Rl[l] = malloc(sizeof(double) * nn);
-    Tl[l] = malloc(sizeof(double) * nn);
-    Rn[l] = malloc(sizeof(double) * nn);
-    if (l == L) {
-      memcpy(Rl[l], R, sizeof(double) * nn);
-      memcpy(Tl[l], T, sizeof(double) * nn);
-    } else {
-      or_restrict(Rl[l + 1], (1 << (l + 1)) + 1, Rl[l]);
-      or_restrict(Tl[l + 1], (1 << (l + 1)) + 1, Tl[l]);
-    }
-    if (or_normalize(Rl[l], n, Rn[l], NULL, NULL) != 0) rc = -1;
-  }
-  if (rc != 0) goto done;
-  {
+  pyramid_t py;
+  int rc = pyramid_build(&py, R, T, L, m0);
+  if (rc == 0) {
     /* Initial guess on the coarsest level: restrict u0 down to m0 (identity if NULL). */
     int n0 = (1 << m0) + 1;
     double* u = calloc((size_t)2 * n0 * n0, sizeof(double));
@@ -599,43 +658,31 @@ int or_register(const double* R, const double* T, int nf, const double* u0, cons
       memcpy(u, cur, sizeof(double) * 2 * n0 * n0);
       free(cur);
     }
-    trace_t tr = {trace, trace_cap, 0};
-    if (st) memset(st, 0, sizeof(*st));
-    int flags = 0;
-    double e = 0.0, ncc = 0.0;
-    for (int l = m0; l <= L; ++l) {
-      int n = (1 << l) + 1;
-      level_data LD = {n, Rn[l], Tl[l]};
-      int passes = 0;
-      int steps = gradient_flow(&LD, u, p, l, &passes, &flags, &e, &ncc, &tr);
-      if (st) {
-        st->iters[l - m0] = steps;
-        st->trials[l - m0] = passes;
-      }
-      if (l < L) {
-        int nn2 = (1 << (l + 1)) + 1;
-        double* uf = malloc(sizeof(double) * 2 * nn2 * nn2);
-        for (int c = 0; c < 2; ++c)
-          or_prolong(u + (size_t)c * n * n, n, uf + (size_t)c * nn2 * nn2);
-        free(u);
-        u = uf;
-      }
-    }
-    memcpy(u_out, u, sizeof(double) * 2 * nf * nf);
-    free(u);
-    if (st) {
-      st->energy = e;
-      st->ncc = ncc;
-      st->flags = flags;
-    }
-    if (trace_len) *trace_len = tr.len;
+    run_levels(&py, m0, u, p, u_out, st, trace, trace_cap, trace_len);
   }
-done:
-  for (int l = L; l >= m0; --l) {
-    free(Rl[l]);
-    free(Tl[l]);
-    free(Rn[l]);
+  pyramid_free(&py);
+  return rc;
+}
+
+/* Function A started on level `start` (m0 <= start <= L) from the guess u_start given on that
+   level ([2][n_start][n_start], domain units): the coarser levels are skipped, as a warm start
+   from a predicted displacement does. The reference is still checked on levels m0..L. */
+int or_register_from(const double* R, const double* T, int nf, int start,
+                     const double* u_start, const or_params* p, double* u_out, or_stats* st,
+                     double* trace, int trace_cap, int* trace_len) {
+  int L = log2_exact(nf - 1);
+  if (L < 1 || p->levels < 1 || p->levels > L || p->levels > OR_MAX_LEVELS) return -2;
+  int m0 = L - p->levels + 1;
+  if (start < m0 || start > L || !u_start) return -2;
+  pyramid_t py;
+  int rc = pyramid_build(&py, R, T, L, m0);
+  if (rc == 0) {
+    int ns = (1 << start) + 1;
+    double* u = malloc(sizeof(double) * 2 * ns * ns);
+    memcpy(u, u_start, sizeof(double) * 2 * ns * ns);
+    run_levels(&py, start, u, p, u_out, st, trace, trace_cap, trace_len);
   }
+  pyramid_free(&py);
   return rc;
 }
 

@@ -111,6 +111,9 @@ def _lib():
                 "pprs_last_error": (ctypes.c_char_p, []),
                 "pprs_register_pair": (i, [vp, vp, vp, i, i, vp, vp, ctypes.POINTER(_CParams),
                                            ctypes.POINTER(_CPairStats)]),
+                "pprs_register_pairs": (i, [vp, vp, i, i, i, vp, vp, i, vp,
+                                            ctypes.POINTER(_CParams),
+                                            ctypes.POINTER(_CPairStats)]),
                 "pprs_compose_deformations": (i, [vp, vp, vp, vp, i, i]),
                 "pprs_prefix_register_series": (i, [vp, vp, i, i, i, vp,
                                                     ctypes.POINTER(_CParams),
@@ -227,6 +230,29 @@ def register_pair(f_ref, f_tmpl, u_init=None, params: Params | None = None, out=
     return out, _pair_stats(st, params.levels)
 
 
+def register_pairs(frames, ref, tmpl, params: Params | None = None, out=None):
+    """Function A on pairs (frames[ref[p]], frames[tmpl[p]]) of frames [N, H, W]: returns
+    (u [P, 2, H, W] pixels, [PairStats])."""
+    import numpy as np
+    import torch
+    params = params or Params()
+    ref = np.ascontiguousarray(ref, dtype=np.int32)
+    tmpl = np.ascontiguousarray(tmpl, dtype=np.int32)
+    if ref.shape != tmpl.shape or ref.ndim != 1:
+        raise ValueError("ref and tmpl must be 1-D index arrays of one length")
+    N, H, W = frames.shape
+    P = len(ref)
+    if out is None:
+        out = torch.empty((P, 2, H, W), device=frames.device, dtype=torch.float32)
+    st = (_CPairStats * max(P, 1))()
+    cp = params.c()
+    c = _ctx(frames.device)
+    _check(_lib().pprs_register_pairs(
+        c.handle, _dev_f32(frames, "frames"), N, H, W, ref.ctypes.data, tmpl.ctypes.data, P,
+        _dev_f32(out, "out"), ctypes.byref(cp), st))
+    return out, [_pair_stats(st[k], params.levels) for k in range(P)]
+
+
 def compose_deformations(u_ij, u_jk, out=None):
     """(phi_jk o phi_ij) as a displacement [2, H, W] in pixels."""
     import torch
@@ -311,7 +337,7 @@ def _cnn_sigs(lib):
                                     ctypes.POINTER(ctypes.c_double)]),
         "pprs_pair_inputs": (i, [vp, vp, i, i, i, vp, vp, i, vp]),
         "pprs_level7_targets": (i, [vp, vp, i, i, i, vp]),
-        "pprs_set_warm_start": (i, [vp, vp, ctypes.c_double]),
+        "pprs_set_warm_start": (i, [vp, vp, ctypes.c_double, i]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -426,10 +452,17 @@ def level7_targets(u):
     return out
 
 
-def set_warm_start(net, max_cells: float = 8.0, device=None):
-    """Use `net` (or None) to warm-start later series calls on the current stream's context."""
+WARM_MODES = {"refine": 0, "skip": 1}
+
+
+def set_warm_start(net, max_cells: float = 8.0, mode: str = "refine", device=None):
+    """Use `net` (or None) to warm-start later series and pair-batch calls on the current
+    stream's context. mode "refine": the prediction becomes the coarsest-level initial guess;
+    "skip": registrations start on level 7 from it and skip the coarser levels."""
     import torch
     _cnn_sigs(_lib())
     dev = device or torch.device("cuda", torch.cuda.current_device())
-    _check(_lib().pprs_set_warm_start(_ctx(dev).handle, net.handle if net else None,
-                                      max_cells))
+    c = _ctx(dev)
+    _check(_lib().pprs_set_warm_start(c.handle, net.handle if net else None, max_cells,
+                                      WARM_MODES[mode]))
+    c.warm_net = net  # the context refers to the network's device memory: keep it alive

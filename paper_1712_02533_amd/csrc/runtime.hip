@@ -96,6 +96,7 @@ struct pprs_ctx {
   bool log = false;  // one progress line per batch on stderr (environment PPRS_LOG=1)
   pprs_cnn* cnn = nullptr;  // warm start network (not owned)
   double warm_max_cells = 8.0;
+  int warm_mode = PPRS_WARM_REFINE;
   DevBuf cnn_in, cnn_out, tmp, badflags;
   BatchDesc hd;
   int slots_cap = 0, slots_L = -1, slots_m0 = -1;
@@ -285,8 +286,10 @@ pprs_status ensure_slots(pprs_ctx* c, int cap, int L, int m0, double beta) {
 
 // Normalised frame pyramids for N frames (device [N][H][H]) on levels m0..L. Fails with
 // EINVAL if a frame with index < n_ref_frames is constant on some level.
+// Pyramids of N frames (levels m0..L), normalised per level. Frame f is checked for being
+// constant when f < n_ref_frames or, given ref_mask, when ref_mask[f] != 0.
 pprs_status prepare_frames(pprs_ctx* c, const float* frames, int N, int H, int L, int m0,
-                           int n_ref_frames) {
+                           int n_ref_frames, const std::vector<char>* ref_mask = nullptr) {
   BatchDesc& hd = c->hd;
   size_t total = 0;
   size_t off[PPRS_MAXL] = {0};
@@ -324,7 +327,8 @@ pprs_status prepare_frames(pprs_ctx* c, const float* frames, int N, int H, int L
     HIPCHK(hipStreamSynchronize(c->stream));
     for (int f = 0; f < N; ++f) {
       double m = ms[2 * f], s = ms[2 * f + 1];
-      if (s <= 1e-12 * std::max(1.0, fabs(m)) && f < n_ref_frames)
+      bool is_ref = ref_mask ? (*ref_mask)[f] != 0 : f < n_ref_frames;
+      if (s <= 1e-12 * std::max(1.0, fabs(m)) && is_ref)
         return fail(PPRS_EINVAL, "reference frame %d is constant on level %d", f, l);
     }
     HIPCHK(pprs_k::normalize(hd.frames[l], (long long)n * n, (long long)n * n, N, msd,
@@ -504,11 +508,12 @@ pprs_status run_batch(pprs_ctx* c, int n, const int* ref, const int* tmpl, InitK
       if (node_passes) *node_passes += nn * st[s].passes[l - st[s].coarsest];
     }
     if (stats) {
+      // indexed from the batch's coarsest level; levels a warm start skipped report 0
       pprs_pair_stats& o = stats[s];
       memset(&o, 0, sizeof o);
       for (int l = st[s].coarsest; l <= L; ++l) {
-        o.iters[l - st[s].coarsest] = st[s].iters[l - st[s].coarsest];
-        o.passes[l - st[s].coarsest] = st[s].passes[l - st[s].coarsest];
+        o.iters[l - m0] = st[s].iters[l - st[s].coarsest];
+        o.passes[l - m0] = st[s].passes[l - st[s].coarsest];
       }
       o.energy = st[s].E;
       o.ncc = st[s].ncc;
@@ -520,6 +525,7 @@ pprs_status run_batch(pprs_ctx* c, int n, const int* ref, const int* tmpl, InitK
 
 const int kWarmLevel = 7;     // the network works on 128^2 frames (level 7)
 const int kWarmChunk = 64;    // pairs per network call
+const int kPairChunk = 512;   // pairs per batch of pprs_register_pairs
 
 // Network predictions for n pairs (ref[s], tmpl[s]) written as level-7 guesses into slot s's
 // first u buffer; bad[s] = 1 for predictions that are not finite or exceed the bound.
@@ -552,6 +558,40 @@ pprs_status warm_predict(pprs_ctx* c, int n, const int* ref, const int* tmpl,
   bad.assign(n, 0);
   HIPCHK(hipMemcpyAsync(bad.data(), dbad, sizeof(int) * n, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+  return PPRS_OK;
+}
+
+// Initial guesses of n slots (pairs ref[s], tmpl[s]) from the network. PPRS_WARM_REFINE:
+// the level-7 prediction is restricted to the coarsest level m0 and every level runs;
+// PPRS_WARM_SKIP: the prediction is the start on level 7 and the coarser levels are skipped.
+// A rejected prediction starts from the identity on m0 and is flagged PPRS_FLAG_FALLBACK.
+// lv[s] and fl[s] receive each slot's start level and flags for run_batch (INIT_PREPARED).
+pprs_status warm_init(pprs_ctx* c, int n, const int* ref, const int* tmpl, int m0,
+                      std::vector<int>& lv, std::vector<int>& fl) {
+  BatchDesc& hd = c->hd;
+  std::vector<int> bad;
+  STCHK(warm_predict(c, n, ref, tmpl, bad));
+  int n0 = level_n(m0);
+  long long per0 = 2LL * n0 * n0;
+  lv.assign(n, m0);
+  fl.assign(n, 0);
+  if (c->warm_mode == PPRS_WARM_SKIP) {
+    HIPCHK(pprs_k::fill_strided(hd.ubuf + hd.u_off[m0], hd.slot_u_stride, per0, n, 0.f,
+                                c->stream));
+    for (int s = 0; s < n; ++s) lv[s] = bad[s] ? m0 : kWarmLevel;
+  } else {
+    for (int l = kWarmLevel; l > m0; --l) {
+      int nf = level_n(l), nc = level_n(l - 1);
+      HIPCHK(pprs_k::restrict_planes(hd.ubuf + hd.u_off[l], hd.slot_u_stride, (long long)nf * nf,
+                                     hd.ubuf + hd.u_off[l - 1], hd.slot_u_stride,
+                                     (long long)nc * nc, 2, nf, 2 * n, c->stream));
+    }
+    for (int s = 0; s < n; ++s)
+      if (bad[s])
+        HIPCHK(pprs_k::fill_strided(hd.ubuf + hd.u_off[m0] + (size_t)s * hd.slot_u_stride,
+                                    hd.slot_u_stride, per0, 1, 0.f, c->stream));
+  }
+  for (int s = 0; s < n; ++s) fl[s] = bad[s] ? PPRS_FLAG_FALLBACK : 0;
   return PPRS_OK;
 }
 
@@ -669,6 +709,54 @@ pprs_status pprs_register_pair(pprs_ctx* c, const float* f_ref, const float* f_t
   return status_from_flags(flags);
 }
 
+pprs_status pprs_register_pairs(pprs_ctx* c, const float* frames, int N, int H, int W,
+                                const int* ref, const int* tmpl, int P, float* u_out,
+                                const pprs_params* params, pprs_pair_stats* stats) {
+  STCHK(enter(c));
+  int L = frame_level(H, W);
+  if (L < 0) return fail(PPRS_EINVAL, "frames must be square with side 2^L or 2^L+1, L in [2,10]");
+  if (!frames || !ref || !tmpl || !u_out || N < 1 || P < 0)
+    return fail(PPRS_EINVAL, "bad arguments");
+  STCHK(check_params(params, L));
+  if (P == 0) return PPRS_OK;
+  std::vector<char> is_ref(N, 0);
+  for (int p = 0; p < P; ++p) {
+    if (ref[p] < 0 || ref[p] >= N || tmpl[p] < 0 || tmpl[p] >= N)
+      return fail(PPRS_EINVAL, "pair %d has a frame index out of range", p);
+    is_ref[ref[p]] = 1;
+  }
+  int m0 = L - params->levels + 1;
+  int nL = level_n(L);
+  long long est = 2LL * nL * nL;
+  size_t plane = (size_t)H * W;
+  bool warm = c->cnn != nullptr && m0 <= kWarmLevel && kWarmLevel <= L;
+  STCHK(prepare_frames(c, frames, N, H, L, m0, 0, &is_ref));
+  int chunk = std::min(P, kPairChunk);
+  STCHK(ensure(c->elems, sizeof(float) * est * chunk));
+  STCHK(ensure_slots(c, chunk, L, m0, params->beta));
+  float* elems = ::P<float>(c->elems);
+  int flags = 0;
+  for (int p0 = 0; p0 < P; p0 += chunk) {
+    int np = std::min(chunk, P - p0);
+    std::vector<int> out(np);
+    for (int k = 0; k < np; ++k) out[k] = k;
+    pprs_pair_stats* ps = stats ? stats + p0 : nullptr;
+    if (warm) {
+      std::vector<int> lv, fl;
+      STCHK(warm_init(c, np, ref + p0, tmpl + p0, m0, lv, fl));
+      STCHK(run_batch(c, np, ref + p0, tmpl + p0, INIT_PREPARED, nullptr, nullptr, out.data(),
+                      elems, params, ps, nullptr, nullptr, &flags, m0, lv.data(), fl.data()));
+    } else {
+      STCHK(run_batch(c, np, ref + p0, tmpl + p0, INIT_IDENTITY, nullptr, nullptr, out.data(),
+                      elems, params, ps, nullptr, nullptr, &flags));
+    }
+    HIPCHK(pprs_k::from_nodes(elems, nL, (long long)nL * nL, u_out + (size_t)p0 * 2 * plane, H,
+                              (long long)plane, 2 * np, (float)(nL - 1), c->stream));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return status_from_flags(flags);
+}
+
 pprs_status pprs_compose_deformations(pprs_ctx* c, const float* u_ij, const float* u_jk,
                                       float* u_ik, int H, int W) {
   STCHK(enter(c));
@@ -751,15 +839,8 @@ pprs_status pprs_prefix_register_series(pprs_ctx* c, const float* frames, int N,
       ek[m] = m + 1;
     }
     if (warm) {
-      std::vector<int> bad, lv(M), fl(M);
-      STCHK(warm_predict(c, M, ref.data(), tmpl.data(), bad));
-      int n0 = level_n(m0);
-      HIPCHK(pprs_k::fill_strided(c->hd.ubuf + c->hd.u_off[m0], c->hd.slot_u_stride,
-                                  2LL * n0 * n0, M, 0.f, c->stream));
-      for (int m = 0; m < M; ++m) {
-        lv[m] = bad[m] ? m0 : kWarmLevel;
-        fl[m] = bad[m] ? PPRS_FLAG_FALLBACK : 0;
-      }
+      std::vector<int> lv, fl;
+      STCHK(warm_init(c, M, ref.data(), tmpl.data(), m0, lv, fl));
       STCHK(run_batch(c, M, ref.data(), tmpl.data(), INIT_PREPARED, nullptr, nullptr,
                       out.data(), elems, params, op_stats, &S.node_steps, &S.node_passes, &flags,
                       m0, lv.data(), fl.data()));
@@ -787,7 +868,8 @@ pprs_status pprs_prefix_register_series(pprs_ctx* c, const float* frames, int N,
       int cnt = (int)lft.size();
       STCHK(run_batch(c, cnt, r2.data(), t2.data(), INIT_COMPOSE, lft.data(), rgt.data(),
                       rgt.data(), elems, params, op_stats ? op_stats + M + done : nullptr,
-                      &S.node_steps, &S.node_passes, &flags, warm ? kWarmLevel : m0));
+                      &S.node_steps, &S.node_passes, &flags,
+                      warm && c->warm_mode == PPRS_WARM_SKIP ? kWarmLevel : m0));
       for (int k = 0; k < cnt; ++k) ei[rgt[k]] = ei[lft[k]];
       done += cnt;
     }
@@ -822,13 +904,16 @@ pprs_status pprs_prefix_register_series(pprs_ctx* c, const float* frames, int N,
   return status_from_flags(flags);
 }
 
-pprs_status pprs_set_warm_start(pprs_ctx* c, pprs_cnn* cnn, double max_cells) {
+pprs_status pprs_set_warm_start(pprs_ctx* c, pprs_cnn* cnn, double max_cells, int mode) {
   STCHK(enter(c));
+  if (mode != PPRS_WARM_REFINE && mode != PPRS_WARM_SKIP)
+    return fail(PPRS_EINVAL, "unknown warm-start mode %d", mode);
   if (cnn && pprs_cnn_api::cnn_device(cnn) != c->device)
     return fail(PPRS_EINVAL, "network and context are on different devices");
   if (!(max_cells > 0.0)) return fail(PPRS_EINVAL, "max_cells must be > 0");
   c->cnn = cnn;
   c->warm_max_cells = max_cells;
+  c->warm_mode = mode;
   return PPRS_OK;
 }
 

@@ -338,6 +338,59 @@ def test_smooth_nonrigid_field_recovered(seed):
     assert np.sqrt((err[:, b:-b, b:-b] ** 2).mean()) < 0.05
 
 
+def test_start_level_variant_reduces_to_multilevel_and_skips_levels():
+    """Started on the coarsest level with the restricted guess, the start-level variant is the
+    multilevel algorithm itself; started on a finer level from the true (constant) shift it
+    recovers the translation with no work on the skipped levels."""
+    spec = SeriesSpec(2, 64, 1.5, 0.0, 0.0, 103)
+    s = make_series(spec)
+    R, T = O.frame_to_nodes(s.frames[0]), O.frame_to_nodes(s.frames[1])
+    p = O.Params(levels=3, lam=10.0, eps=3e-4)
+    u0 = np.zeros((2, 65, 65))
+    u0[0], u0[1] = 0.4 / 64, -0.3 / 64
+    ua, sa, _ = O.register(R, T, p, u0=u0)
+    c = np.stack([O.restrict(O.restrict(u0[k])) for k in range(2)])
+    ub, sb, _ = O.register_from(R, T, 4, c, p)
+    assert np.array_equal(ua, ub) and sa.iters == sb.iters
+    gt = ground_truth(s, 1)
+    shift = gt[:, 32, 32]
+    us = np.zeros((2, 33, 33))
+    us[0], us[1] = shift[0] / 64, shift[1] / 64
+    u, st, _ = O.register_from(R, T, 5, us, p)
+    assert st.iters[0] == 0 and st.iters[1] >= 0
+    err = O.u_to_pixels(u, 64) - gt
+    assert np.sqrt((err[:, 8:-8, 8:-8] ** 2).mean()) < 0.05
+    # identical frames from the identity on any start level stay exactly at the identity
+    z, _, _ = O.register_from(R, R, 5, np.zeros((2, 33, 33)), p)
+    assert np.all(z == 0)
+    with pytest.raises(ValueError):
+        O.register_from(R, T, 3, np.zeros((2, 9, 9)), p)
+
+
+def test_long_registration_sensitivity_to_fp32_level_perturbation():
+    """Derived tolerance for long registrations: a pair four frames' drift apart (about 230
+    accepted steps over 3 levels) is sensitive to perturbations at the level of FP32 rounding.
+    Relative noise of 1e-6 on the template leaves every line-search decision unchanged and the
+    RMS change below 1e-4 px, but moves isolated nodes by more than 1e-3 px (a sample point
+    crossing a cell edge switches the one-sided bilinear gradient there)."""
+    s = make_series(SeriesSpec(n_frames=4, side=256, drift=4.0, warp_amp=1.0,
+                               mean_counts=10.0, seed=51))
+    p = O.Params(levels=3, lam=10.0, beta=1.0, sigma=0.5, ladder_k=1, cap=1.0,
+                 tau_min_rel=1e-4, eps=3e-4, iter_max=500)
+    R, T = O.frame_to_nodes(s.frames[3]), O.frame_to_nodes(s.frames[0])
+    u0, s0, _ = O.register(R, T, p)
+    rng = np.random.default_rng(0)
+    worst = 0.0
+    for _ in range(2):
+        up, sp, _ = O.register(R, T * (1 + 1e-6 * rng.standard_normal(T.shape)), p)
+        d = np.abs(O.u_to_pixels(u0, 256) - O.u_to_pixels(up, 256))
+        assert sp.iters == s0.iters and sp.trials == s0.trials
+        assert np.sqrt((d ** 2).mean()) < 1e-4
+        assert np.percentile(d, 99.9) < 1e-3
+        worst = max(worst, d.max())
+    assert 1e-3 < worst < 0.05
+
+
 def test_constant_reference_rejected():
     n = 17
     with pytest.raises(ValueError):
