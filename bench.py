@@ -4,8 +4,10 @@ MI355X. A step is one complete series registration: frame pyramids, the N-1 neig
 registrations and every B application of the scan, with the frames already in HBM.
 
 Prints one JSON line: registrations/s (A + B applications per second), the series time, the
-roofline of the dominant kernel (algorithmic bytes / HIP-event time of its launches in the
-timed steps) and the FP64 CPU oracle timed on a bounded sample of the same workload.
+roofline of the dominant kernel (algorithmic bytes / HIP-event time of its launches, taken in
+extra steps after the timed ones because events around every launch slow the series), the
+same series with the learned warm start (both modes, with the network's MFMA throughput) and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -83,6 +85,65 @@ def cpu_baseline(series, cfg, n_ops, threads):
                        "series, FP64, %d threads, %.1f s" % (n_ops, n_ops, threads, dt))
 
 
+# multiply-adds x 2 of one forward pass of the warm-start network (3x3 convolutions)
+CNN_LAYERS = [(64, 64, 2), (32, 128, 64), (16, 256, 128), (32, 128, 384), (64, 64, 192),
+              (128, 2, 66)]  # (output side, Cout, Cin)
+CNN_FLOP_PER_PAIR = sum(2 * h * h * co * 9 * ci for h, co, ci in CNN_LAYERS)
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def warm_runs(P, frames, out, params, args, regs_per_step):
+    """The same series with the learned warm start (both modes): throughput, difference to the
+    cold result and the network's forward throughput on the series' neighbour pairs."""
+    import numpy as np
+    import torch
+    cold = out.clone()
+    net = P.WarmStartNet()
+    net.load(args.weights)
+    res = {}
+    for mode in ("refine", "skip"):
+        P.set_warm_start(net, mode=mode)
+        try:
+            w = torch.empty_like(out)
+            P.prefix_register_series(frames, params=params, out=w)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, st, ops = P.prefix_register_series(frames, params=params, out=w,
+                                                      want_op_stats=True)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / args.steps
+        finally:
+            P.set_warm_start(None)
+        d = (w - cold)[:, :, 16:-16, 16:-16]
+        res[mode] = dict(value=round(regs_per_step / dt, 3), ms_per_step=round(1e3 * dt, 1),
+                         rms_vs_cold_px=round(float(d.pow(2).mean().sqrt()), 4),
+                         max_vs_cold_px=round(float(d.abs().max()), 3),
+                         fallbacks=sum(1 for o in ops if o.flags & 4))
+        log("warm (%s): %.1f ms per series, RMS vs cold %.4f px" %
+            (mode, 1e3 * dt, res[mode]["rms_vs_cold_px"]))
+    # network forward on the series' neighbour pairs, as the warm start runs it (64 per call)
+    n = frames.shape[0] - 1
+    ref = np.arange(n, dtype=np.int32)
+    x = P.pair_inputs(frames, ref, ref + 1)
+    for b0 in range(0, n, 64):
+        net.forward(x[b0:b0 + 64])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for b0 in range(0, n, 64):
+        net.forward(x[b0:b0 + 64])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    tf = CNN_FLOP_PER_PAIR * n / (ms * 1e-3) / 1e12
+    res["cnn_forward"] = dict(pairs=n, ms=round(ms, 2), flop_per_pair=CNN_FLOP_PER_PAIR,
+                              tflops=round(tf, 1), peak_tflops=MFMA_BF16_PEAK_TFLOPS,
+                              frac=round(tf / MFMA_BF16_PEAK_TFLOPS, 4))
+    log("cnn forward: %d pairs in %.2f ms, %.1f TFLOP/s" % (n, ms, tf))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +154,9 @@ def main():
     ap.add_argument("--cpu-ops", type=int, default=0, help="oracle sample size (0 = auto)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
+    ap.add_argument("--no-warm", action="store_true", help="skip the warm-start runs")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1712_02533_amd", "weights",
+                                                      "warmstart_512.safetensors"))
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -126,9 +190,6 @@ def main():
     for w in range(args.warmup):
         _, st, _ = P.prefix_register_series(frames, params=params, out=out)
         log("warmup %d: %.1f ms, %d A + %d B ops" % (w, st.ms_total, st.n_ops_a, st.n_ops_b))
-    timing = not args.no_timing
-    P.set_kernel_timing(timing, dev)
-    P.kernel_timing(reset=True, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
@@ -139,11 +200,20 @@ def main():
             (k, st.ms_total, st.ms_prepare, st.ms_preprocess, st.ms_scan, st.flags_or))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    kt = P.kernel_timing(reset=True, device=dev)
-    P.set_kernel_timing(False, dev)
     regs = sum(s.n_ops_a + s.n_ops_b for s in stats)
     value = regs / elapsed
     ms_per_step = 1e3 * elapsed / args.steps
+    # per-kernel HIP events bracket every launch, which slows the series: they run in steps of
+    # their own after the timed ones (same work, same launches)
+    timing = not args.no_timing
+    if timing:
+        P.set_kernel_timing(True, dev)
+        P.kernel_timing(reset=True, device=dev)
+        for k in range(max(1, min(args.steps, 2))):
+            P.prefix_register_series(frames, params=params, out=out)
+        torch.cuda.synchronize()
+        kt = P.kernel_timing(reset=True, device=dev)
+        P.set_kernel_timing(False, dev)
 
     roofline = None
     kernels = {}
@@ -173,6 +243,8 @@ def main():
         roofline=roofline, kernels=kernels,
         node_steps=stats[0].node_steps, node_passes=stats[0].node_passes,
     )
+    if not args.no_warm and os.path.exists(args.weights) and spec.side >= 128:
+        result["warm"] = warm_runs(P, frames, out, params, args, stats[0].n_ops_a + stats[0].n_ops_b)
     if not args.no_cpu:
         ops = args.cpu_ops or max(4, nthreads)
         log("cpu baseline: oracle on %d registrations, %d threads" % (ops, nthreads))

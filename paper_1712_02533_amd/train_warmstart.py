@@ -170,7 +170,7 @@ def main():
     _save(args.out, best[1], meta)
     log("saved %s (best val RMS %.4f cells)" % (args.out, best[0]))
     net.set_params(best[1])
-    meta["warm_vs_cold"] = warm_vs_cold(net, val_frames, params)
+    meta["warm_vs_cold"] = warm_vs_cold(net, val_frames, params)[0]
     _save(args.out, best[1], meta)
 
 
@@ -200,7 +200,7 @@ def warm_vs_cold(net, frames, params, border=16):
                          fallbacks=sum(1 for s in out[mode][1] if s.flags & 4),
                          iters=np.sum([s.iters for s in out[mode][1]], axis=0).tolist())
     log("warm vs cold on %d validation pairs: %s" % (len(ref), json.dumps(res)))
-    return res
+    return res, out
 
 
 def evaluate_only(args):
@@ -212,7 +212,8 @@ def evaluate_only(args):
     dev = torch.device("cuda", 0)
     params = P.Params(levels=4, scan="brent_kung")
     spec = replace(CONFIGS["c3"]["spec"], n_frames=args.frames, seed=args.seed0)
-    frames = torch.tensor(make_series(spec, workers=args.workers).frames, device=dev)
+    series = make_series(spec, workers=args.workers)
+    frames = torch.tensor(series.frames, device=dev)
     net = P.WarmStartNet(device=dev)
     net.load(args.init)
     ref = np.arange(args.frames - 1, dtype=np.int32)
@@ -221,8 +222,26 @@ def evaluate_only(args):
     rms, good = evaluate(net, X, P.level7_targets(u), 64)
     log("seed %d: prediction RMS %.4f cells, %.1f%% within 0.5 cell" % (args.seed0, rms,
                                                                       100 * good))
-    res = warm_vs_cold(net, frames, params)
+    res, out = warm_vs_cold(net, frames, params)
     res.update(seed=args.seed0, prediction_rms_cells=rms, prediction_within_half_cell=good)
+    # against the generator's analytic displacement: the pairs where warm and cold differ most,
+    # and pairs spread over the series
+    from synth import ground_truth_pair
+    b = 24
+    diff = (out["refine"][0] - out["cold"][0])[:, :, b:-b, b:-b].pow(2).mean(dim=(1, 2, 3))
+    worst = torch.argsort(diff, descending=True)[:12].cpu().numpy().tolist()
+    spread = list(range(0, len(ref), max(1, len(ref) // 12)))[:12]
+    gt_rows = []
+    for m in worst + spread:
+        g = torch.tensor(ground_truth_pair(series, m, m + 1), device=dev, dtype=torch.float32)
+        row = dict(pair=m)
+        for mode in ("cold", "refine", "skip"):
+            e = (out[mode][0][m] - g)[:, b:-b, b:-b]
+            row[mode] = round(float(e.pow(2).mean().sqrt()), 4)
+        gt_rows.append(row)
+        log("pair %d: RMS error vs truth (px) cold %.4f refine %.4f skip %.4f" %
+            (m, row["cold"], row["refine"], row["skip"]))
+    res["ground_truth_rms_px"] = gt_rows
     if args.out:
         with open(args.out, "w") as f:
             json.dump(res, f, indent=1)

@@ -3,6 +3,8 @@
 This module only produces inputs and their analytic ground truth. It holds none of the
 registration arithmetic, so both the FP64 oracle and the GPU path can draw from it.
 """
-from .blobs import SeriesSpec, make_series, ground_truth, CONFIGS, config_spec
+from .blobs import (SeriesSpec, make_series, ground_truth, ground_truth_pair, CONFIGS,
+                    config_spec)
 
-__all__ = ["SeriesSpec", "make_series", "ground_truth", "CONFIGS", "config_spec"]
+__all__ = ["SeriesSpec", "make_series", "ground_truth", "ground_truth_pair", "CONFIGS",
+           "config_spec"]

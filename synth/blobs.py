@@ -169,6 +169,23 @@ def ground_truth(series: Series, k: int, iters: int = 60) -> np.ndarray:
     return np.stack([yx - c, yy - r])
 
 
+def ground_truth_pair(series: Series, i: int, k: int, iters: int = 60) -> np.ndarray:
+    """Analytic u_{i,k} in pixels, [2, side, side]: y = x + t_k - t_i - s_i(x) + s_k(y), so that
+    frame k sampled at x + u(x) shows what frame i shows at x (same fixed point as above)."""
+    side = series.spec.side
+    r, c = np.meshgrid(np.arange(side, dtype=np.float64), np.arange(side, dtype=np.float64),
+                       indexing="ij")
+    t = series.shifts
+    six, siy = _warp(series.sines[i], c, r)
+    bx = c + t[k, 0] - t[i, 0] - six
+    by = r + t[k, 1] - t[i, 1] - siy
+    yx, yy = bx.copy(), by.copy()
+    for _ in range(iters):
+        skx, sky = _warp(series.sines[k], yx, yy)
+        yx, yy = bx + skx, by + sky
+    return np.stack([yx - c, yy - r])
+
+
 # Workload recipes. Levels are listed finest first; "scan" is the schedule of the series step.
 CONFIGS = {
     "c1": dict(spec=SeriesSpec(8, 64, 2.0, 0.0, 20.0, 0), levels=2, scan="sequential"),
