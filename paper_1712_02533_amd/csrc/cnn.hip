@@ -105,6 +105,130 @@ __global__ void __launch_bounds__(256) k_gemm(const bf16* __restrict__ A, int ld
       }
 }
 
+// ------------------------------------------------------------------------------------------
+// Fused 3x3 convolution (implicit GEMM) for layers whose input channels come in multiples of
+// 64: out[m][n] = relu(bias[n] + sum_k A(m,k) W[n][k]) as bf16, with m = (b, oy, ox) and
+// k = tap * Cin + c. A(m,k) is read straight from the NHWC input (no im2col copy): channels
+// [0, C0) from src0 (at half resolution when UP, i.e. the nearest 2x upsampling of the decoder),
+// channels [C0, C0 + C1) from src1 (the skip connection), zero outside the frame.
+// Tiles: 128 pixels x BN output channels x 64-deep K chunks (one tap, one source per chunk),
+// 4 wavefronts in 2 x 2, each owning 64 x BN/2 with 16x16x32 MFMAs; the next chunk is fetched
+// into registers while the current one is multiplied out of LDS (double buffer).
+// Requires C0 % 64 == 0, C1 % 64 == 0, BN | Cout, (B * Hout^2) % 128 == 0, Kp % 8 == 0.
+
+constexpr int CV_BM = 128, CV_BK = 64, CV_LD = CV_BK + 8;
+
+template <int BN, bool UP>
+__global__ void __launch_bounds__(256, 2) k_conv_fwd(
+    const bf16* __restrict__ src0, int C0, const bf16* __restrict__ src1, int C1, int Hin,
+    int stride, const bf16* __restrict__ Wt, int Kp, const float* __restrict__ bias, int Cout,
+    bf16* __restrict__ out) {
+  constexpr int WN = BN / 2;          // columns per wave
+  constexpr int TN = WN / 16;         // 16-wide MFMA tiles per wave along n
+  constexpr int B_PIECES = BN * 8 / 256;
+  __shared__ __attribute__((aligned(16))) bf16 sA[2][CV_BM * CV_LD];
+  __shared__ __attribute__((aligned(16))) bf16 sB[2][BN * CV_LD];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int Cin = C0 + C1, Hout = Hin / stride;
+  const int K = 9 * Cin, nchunks = K / CV_BK;
+  const long long m0 = (long long)blockIdx.x * CV_BM;
+  const int n0 = blockIdx.y * BN;
+  const int Hs0 = UP ? Hin / 2 : Hin;
+  // this thread's 4 A rows (pixels) and its 16-byte piece within a 64-wide chunk
+  const int a_piece = tid & 7;
+  int a_b[4], a_oy[4], a_ox[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    long long m = m0 + (tid >> 3) + 32 * r;
+    a_ox[r] = (int)(m % Hout);
+    a_oy[r] = (int)((m / Hout) % Hout);
+    a_b[r] = (int)(m / ((long long)Hout * Hout));
+  }
+  uint4 ra[4], rb[B_PIECES];
+  auto fetch = [&](int chunk) {
+    int k0 = chunk * CV_BK;
+    int tap = k0 / Cin, c0 = k0 - tap * Cin;
+    int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    bool first = c0 < C0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int iy = a_oy[r] * stride + dy, ix = a_ox[r] * stride + dx;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (iy >= 0 && iy < Hin && ix >= 0 && ix < Hin) {
+        const bf16* p;
+        if (first) {
+          int sy = UP ? iy >> 1 : iy, sx = UP ? ix >> 1 : ix;
+          p = src0 + (((size_t)a_b[r] * Hs0 + sy) * Hs0 + sx) * C0 + c0;
+        } else {
+          p = src1 + (((size_t)a_b[r] * Hin + iy) * Hin + ix) * C1 + (c0 - C0);
+        }
+        v = *(const uint4*)(p + a_piece * 8);
+      }
+      ra[r] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < B_PIECES; ++r) {
+      int e = tid + 256 * r;
+      int n = e >> 3, pc = e & 7;
+      rb[r] = *(const uint4*)(Wt + (size_t)(n0 + n) * Kp + k0 + pc * 8);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      *(uint4*)&sA[buf][((tid >> 3) + 32 * r) * CV_LD + a_piece * 8] = ra[r];
+#pragma unroll
+    for (int r = 0; r < B_PIECES; ++r) {
+      int e = tid + 256 * r;
+      *(uint4*)&sB[buf][(e >> 3) * CV_LD + (e & 7) * 8] = rb[r];
+    }
+  };
+  f32x4 acc[4][TN];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * WN;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int chunk = 0; chunk < nchunks; ++chunk) {
+    int buf = chunk & 1;
+    if (chunk + 1 < nchunks) fetch(chunk + 1);
+#pragma unroll
+    for (int ks = 0; ks < CV_BK; ks += 32) {
+      bf16x8 a[4], b[TN];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        a[i] = *(const bf16x8*)&sA[buf][(wm + 16 * i + (lane & 15)) * CV_LD + ks + 8 * (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        b[j] = *(const bf16x8*)&sB[buf][(wn + 16 * j + (lane & 15)) * CV_LD + ks + 8 * (lane >> 4)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (chunk + 1 < nchunks) stash(buf ^ 1);
+    __syncthreads();
+  }
+  // epilogue: bias, ReLU, bf16 NHWC
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    int col = n0 + wn + 16 * j + (lane & 15);
+    float bv = bias[col];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        long long row = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+        float v = acc[i][j][r] + bv;
+        out[row * Cout + col] = (bf16)(v > 0.f ? v : 0.f);
+      }
+  }
+}
+
 // Sum of `splits` partial results in split order.
 __global__ void k_split_sum(const float* __restrict__ part, long long stride, int splits,
                             float* __restrict__ out, long long count) {
@@ -609,23 +733,56 @@ static pprs_status alloc_batch(Model& M, int B) {
   return PPRS_OK;
 }
 
-// Forward pass for B samples; input x [B][128][128][2] fp32; output in M.y.
-static pprs_status forward(Model& M, const float* x, int B) {
+// Fused convolution of layer l (L2..L5) into M.a[l].
+static pprs_status conv_fused(Model& M, int l, int B) {
+  const Layer& y = M.L[l];
+  const bf16* s0 = l == 1 ? M.a[0] : l == 2 ? M.a[1] : l == 3 ? M.a[2] : M.a[3];
+  const bf16* s1 = l == 3 ? M.a[1] : l == 4 ? M.a[0] : nullptr;
+  int c0 = l == 1 ? 64 : l == 2 ? 128 : l == 3 ? 256 : 128;
+  int c1 = y.cin - c0;
+  bool up = l >= 3;
+  long long pix = (long long)B * y.hout * y.hout;
+  if (pix % CV_BM || c0 % 64 || c1 % 64 || y.kp != 9 * y.cin)
+    return cfail(PPRS_EINVAL, "layer %d does not fit the fused convolution", l + 1);
+  int bn = y.cout % 128 == 0 ? 128 : 64;
+  dim3 grid((unsigned)(pix / CV_BM), y.cout / bn);
+  const bf16* w = M.wb + y.woff;
+  const float* b = M.w + y.boff;
+  if (bn == 128 && up)
+    hipLaunchKernelGGL((k_conv_fwd<128, true>), grid, dim3(256), 0, M.stream, s0, c0, s1, c1, y.hin, y.stride, w, y.kp, b, y.cout, M.a[l]);
+  else if (bn == 128)
+    hipLaunchKernelGGL((k_conv_fwd<128, false>), grid, dim3(256), 0, M.stream, s0, c0, s1, c1, y.hin, y.stride, w, y.kp, b, y.cout, M.a[l]);
+  else if (up)
+    hipLaunchKernelGGL((k_conv_fwd<64, true>), grid, dim3(256), 0, M.stream, s0, c0, s1, c1, y.hin, y.stride, w, y.kp, b, y.cout, M.a[l]);
+  else
+    hipLaunchKernelGGL((k_conv_fwd<64, false>), grid, dim3(256), 0, M.stream, s0, c0, s1, c1, y.hin, y.stride, w, y.kp, b, y.cout, M.a[l]);
+  CHK(hipGetLastError());
+  return PPRS_OK;
+}
+
+// Forward pass for B samples; input x [B][128][128][2] fp32; output in M.y. With `train`, the
+// decoder inputs (upsampled + concatenated) are also kept for the weight gradients.
+static pprs_status forward(Model& M, const float* x, int B, bool train) {
   hipStream_t st = M.stream;
   long long P128 = (long long)B * 128 * 128;
   hipLaunchKernelGGL(k_f32_to_bf16, dim3(grid1d(P128 * 2)), dim3(kBlock), 0, st, x, P128 * 2, M.x0);
-  const bf16* in[5] = {M.x0, M.a[0], M.a[1], M.u4, M.u5};
-  for (int l = 0; l < 5; ++l) {
-    const Layer& y = M.L[l];
+  {
+    // L1 (2 input channels): im2col + GEMM
+    const Layer& y = M.L[0];
     long long pix = (long long)B * y.hout * y.hout;
-    if (l == 3)
-      hipLaunchKernelGGL(k_upcat, dim3(grid1d(pix * 384)), dim3(kBlock), 0, st, M.a[2], 256, M.a[1], 128, B, 32, 32, M.u4);
-    if (l == 4)
-      hipLaunchKernelGGL(k_upcat, dim3(grid1d(pix * 192)), dim3(kBlock), 0, st, M.a[3], 128, M.a[0], 64, B, 64, 64, M.u5);
-    hipLaunchKernelGGL(k_im2col, dim3(grid1d(pix * y.kp)), dim3(kBlock), 0, st, in[l], B, y.hin, y.hin, y.cin, y.stride, y.kp, M.col);
+    hipLaunchKernelGGL(k_im2col, dim3(grid1d(pix * y.kp)), dim3(kBlock), 0, st, M.x0, B, y.hin, y.hin, y.cin, y.stride, y.kp, M.col);
     pprs_status s = gemm(M, false, false, M.col, y.kp, M.wb + y.woff, y.kp, M.z, y.cout, (int)pix, y.cout, y.kp, 1);
     if (s != PPRS_OK) return s;
-    hipLaunchKernelGGL(k_bias_relu, dim3(grid1d(pix * y.cout)), dim3(kBlock), 0, st, M.z, M.w + y.boff, pix, y.cout, M.a[l]);
+    hipLaunchKernelGGL(k_bias_relu, dim3(grid1d(pix * y.cout)), dim3(kBlock), 0, st, M.z, M.w + y.boff, pix, y.cout, M.a[0]);
+  }
+  for (int l = 1; l < 5; ++l) {
+    pprs_status s = conv_fused(M, l, B);
+    if (s != PPRS_OK) return s;
+  }
+  if (train) {
+    long long p32 = (long long)B * 32 * 32, p64 = (long long)B * 64 * 64;
+    hipLaunchKernelGGL(k_upcat, dim3(grid1d(p32 * 384)), dim3(kBlock), 0, st, M.a[2], 256, M.a[1], 128, B, 32, 32, M.u4);
+    hipLaunchKernelGGL(k_upcat, dim3(grid1d(p64 * 192)), dim3(kBlock), 0, st, M.a[3], 128, M.a[0], 64, B, 64, 64, M.u5);
   }
   // L6
   const Layer& y6 = M.L[5];
@@ -817,7 +974,7 @@ pprs_status pprs_cnn_forward(pprs_cnn* c, const float* x, int B, float* y) {
   CHK(hipSetDevice(M.device));
   pprs_status s = alloc_batch(M, B);
   if (s != PPRS_OK) return s;
-  s = forward(M, x, B);
+  s = forward(M, x, B, false);
   if (s != PPRS_OK) return s;
   CHK(hipMemcpyAsync(y, M.y, sizeof(float) * (size_t)B * 128 * 128 * 2, hipMemcpyDeviceToDevice, M.stream));
   CHK(hipStreamSynchronize(M.stream));
@@ -832,7 +989,7 @@ pprs_status pprs_cnn_gradients(pprs_cnn* c, const float* x, const float* target,
   CHK(hipSetDevice(M.device));
   pprs_status s = alloc_batch(M, B);
   if (s != PPRS_OK) return s;
-  if ((s = forward(M, x, B)) != PPRS_OK) return s;
+  if ((s = forward(M, x, B, true)) != PPRS_OK) return s;
   if ((s = backward(M, target, B, margin, loss)) != PPRS_OK) return s;
   if (grad_host) {
     CHK(hipMemcpyAsync(grad_host, M.g, sizeof(float) * M.n_params, hipMemcpyDeviceToHost, M.stream));
