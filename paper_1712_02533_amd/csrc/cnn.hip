@@ -392,25 +392,48 @@ __global__ void k_f32_to_bf16(const float* __restrict__ x, long long count,
 // Last layer (66 -> 2 channels, stride 1), FP32 direct kernels. W6 is [2][9][66] fp32 (from the
 // bf16 copy), bias b6[2].
 
-__global__ void k_l6_fwd(const bf16* __restrict__ U, const float* __restrict__ W6,
-                         const float* __restrict__ b6, int Bn, int H, int Wd, int C,
-                         float* __restrict__ Y) {
-  long long total = (long long)Bn * H * Wd;
+// Last layer read straight from its sources: input channels 0..63 are the 2x upsampled L5
+// output a5 [B][64][64][64], channels 64, 65 the network input x0 [B][128][128][2]; the
+// 66 x 9 x 2 weights sit in LDS. One thread per output pixel, 16-byte loads of a5.
+__global__ void __launch_bounds__(256) k_l6_fused(const bf16* __restrict__ a5,
+                                                  const bf16* __restrict__ x0,
+                                                  const float* __restrict__ W6,
+                                                  const float* __restrict__ b6, int Bn,
+                                                  float* __restrict__ Y) {
+  constexpr int C = 66;
+  __shared__ float w[2 * 9 * C];
+  for (int i = threadIdx.x; i < 2 * 9 * C; i += blockDim.x) w[i] = W6[i];
+  __syncthreads();
+  long long total = (long long)Bn * 128 * 128;
   for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < total;
        p += (long long)gridDim.x * blockDim.x) {
-    int x = (int)(p % Wd), y = (int)((p / Wd) % H), b = (int)(p / ((long long)Wd * H));
+    int x = (int)(p & 127), y = (int)((p >> 7) & 127), b = (int)(p >> 14);
     float s0 = b6[0], s1 = b6[1];
     for (int tap = 0; tap < 9; ++tap) {
       int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
-      if (yy < 0 || yy >= H || xx < 0 || xx >= Wd) continue;
-      const bf16* u = U + (((size_t)b * H + yy) * Wd + xx) * C;
-      const float* w0 = W6 + tap * C;
-      const float* w1 = W6 + 9 * C + tap * C;
-      for (int c = 0; c < C; ++c) {
-        float v = (float)u[c];
-        s0 = fmaf(w0[c], v, s0);
-        s1 = fmaf(w1[c], v, s1);
+      if (yy < 0 || yy >= 128 || xx < 0 || xx >= 128) continue;
+      const uint4* u = (const uint4*)(a5 + (((size_t)b * 64 + (yy >> 1)) * 64 + (xx >> 1)) * 64);
+      const float* w0 = w + tap * C;
+      const float* w1 = w + 9 * C + tap * C;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        uint4 v = u[q];
+        unsigned int h[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float lo = __uint_as_float(h[i] << 16), hi = __uint_as_float(h[i] & 0xffff0000u);
+          s0 = fmaf(w0[8 * q + 2 * i], lo, s0);
+          s1 = fmaf(w1[8 * q + 2 * i], lo, s1);
+          s0 = fmaf(w0[8 * q + 2 * i + 1], hi, s0);
+          s1 = fmaf(w1[8 * q + 2 * i + 1], hi, s1);
+        }
       }
+      const bf16* xi = x0 + (((size_t)b * 128 + yy) * 128 + xx) * 2;
+      float f0 = (float)xi[0], f1 = (float)xi[1];
+      s0 = fmaf(w0[64], f0, s0);
+      s1 = fmaf(w1[64], f0, s1);
+      s0 = fmaf(w0[65], f1, s0);
+      s1 = fmaf(w1[65], f1, s1);
     }
     Y[p * 2] = s0;
     Y[p * 2 + 1] = s1;
@@ -786,8 +809,9 @@ static pprs_status forward(Model& M, const float* x, int B, bool train) {
   }
   // L6
   const Layer& y6 = M.L[5];
-  hipLaunchKernelGGL(k_upcat, dim3(grid1d(P128 * 66)), dim3(kBlock), 0, st, M.a[4], 64, M.x0, 2, B, 128, 128, M.u6);
-  hipLaunchKernelGGL(k_l6_fwd, dim3(grid1d(P128)), dim3(kBlock), 0, st, M.u6, M.w6, M.w + y6.boff, B, 128, 128, 66, M.y);
+  if (train)
+    hipLaunchKernelGGL(k_upcat, dim3(grid1d(P128 * 66)), dim3(kBlock), 0, st, M.a[4], 64, M.x0, 2, B, 128, 128, M.u6);
+  hipLaunchKernelGGL(k_l6_fused, dim3(grid1d(P128)), dim3(kBlock), 0, st, M.a[4], M.x0, M.w6, M.w + y6.boff, B, M.y);
   CHK(hipGetLastError());
   return PPRS_OK;
 }
