@@ -80,8 +80,8 @@ typedef struct {
   int flags_or;           /* OR of all pair flags */
   double ms_total;        /* wall time of the call on the device (ms) */
   double ms_prepare;      /* frame pyramids and normalisation */
-  double ms_preprocess;   /* the N-1 neighbour registrations */
-  double ms_scan;         /* all B applications */
+  double ms_preprocess;   /* the warm start's network predictions (0 when cold) */
+  double ms_scan;         /* all A and B applications (they overlap in the slot pool) */
   long long node_steps;   /* sum over ops and levels of accepted steps x grid nodes */
   long long node_passes;  /* sum over ops and levels of line-search passes x grid nodes */
 } pprs_series_stats;
@@ -92,8 +92,10 @@ typedef struct pprs_ctx pprs_ctx;
 void pprs_default_params(pprs_params* p);
 
 /* Creates a context on HIP device `device`. `stream` is a hipStream_t to order work on, or
-   NULL for a stream the context creates and owns. The context allocates its device workspace
-   lazily and keeps it until pprs_destroy. */
+   NULL for a blocking stream the context creates and owns (ordered with the legacy default
+   stream, as work the caller issues there). The stream must not be the legacy default stream
+   itself: the series step loop is replayed from a captured graph. The context allocates its
+   device workspace lazily and keeps it until pprs_destroy. */
 pprs_status pprs_create(pprs_ctx** ctx, int device, void* stream);
 void pprs_destroy(pprs_ctx* ctx);
 
@@ -129,13 +131,22 @@ pprs_status pprs_compose_deformations(pprs_ctx* ctx, const float* u_ij, const fl
 
 /* Series registration (definition "Image series registration"): frames [N][H][W];
    u_out [N][2][H][W] receives u_out[0] = 0 and u_out[i] = phi_{0,i}, so that
-   f_i o phi_{0,i} ~ f_0. The neighbour registrations run as one batch; the scan runs the B
-   applications of each schedule level as one batch. stats and op_stats are host pointers and
+   f_i o phi_{0,i} ~ f_0. The neighbour registrations and the scan's B applications run in one
+   pool of concurrent registrations (pprs_set_pool), each B application as soon as its inputs
+   exist. stats and op_stats are host pointers and
    may be NULL; op_stats receives N-1 A entries followed by the B entries in schedule order
    (pprs_scan_plan gives their count, at most 2(N-1)), so 3N entries always suffice. */
 pprs_status pprs_prefix_register_series(pprs_ctx* ctx, const float* frames, int N, int H,
                                         int W, float* u_out, const pprs_params* params,
                                         pprs_series_stats* stats, pprs_pair_stats* op_stats);
+
+/* Execution of pprs_prefix_register_series: all its operator applications (the N-1 neighbour
+   registrations and every B application) run in one pool of `slots` concurrent registrations
+   (0 = 512). An application starts as soon as the applications producing its two inputs have
+   finished and a slot is free (in schedule order); the host retires finished registrations and
+   starts new ones every `group_steps` steps (0 = 8). Results do not depend on either value.
+   Returns PPRS_EINVAL for values out of range (slots > 65536, group_steps > 1024). */
+pprs_status pprs_set_pool(pprs_ctx* ctx, int slots, int group_steps);
 
 /* Host-only: the scan schedule over M = N-1 elements (algorithms "serial" and "brent_kung").
    ops (host, capacity `cap` triples) receives (left, right, level) per B application in

@@ -128,6 +128,7 @@ def _lib():
                                                ctypes.POINTER(ctypes.c_double), i,
                                                ctypes.POINTER(ctypes.c_int), i]),
                 "pprs_kernel_name": (ctypes.c_char_p, [i]),
+                "pprs_set_pool": (i, [vp, i, i]),
             }
             for name, (res, args) in sigs.items():
                 fn = getattr(lib, name)
@@ -290,6 +291,13 @@ def prefix_register_series(frames, params: Params | None = None, out=None,
     if want_op_stats:
         op_list = [_pair_stats(ops[k], params.levels) for k in range(ss.n_ops_a + ss.n_ops_b)]
     return out, stats, op_list
+
+
+def set_pool(slots: int = 0, group_steps: int = 0, device=None):
+    """Slot-pool shape of later series calls on the current stream's context (0 = default)."""
+    import torch
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    _check(_lib().pprs_set_pool(_ctx(dev).handle, slots, group_steps))
 
 
 def set_kernel_timing(enable: bool, device=None):

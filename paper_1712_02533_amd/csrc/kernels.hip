@@ -1149,6 +1149,144 @@ __global__ void __launch_bounds__(BLOCK) k_finish(BatchDesc* D, const int* out_i
 }
 
 // ------------------------------------------------------------------------------------------
+// Slot-pool kernels: a registration is started in whichever slot is free, so these address
+// slots through index lists (slots[k] is the slot of the k-th listed registration).
+
+// D->state[slots[k]] = staged[k]; the slots' node counters restart at zero.
+__global__ void __launch_bounds__(BLOCK) k_pool_assign(BatchDesc* D, const SlotState* staged,
+                                                       const int* slots, int ops) {
+  constexpr int W = sizeof(SlotState) / 4;
+  long long total = (long long)ops * W;
+  for (long long i = blockIdx.x * (long long)BLOCK + threadIdx.x; i < total;
+       i += (long long)gridDim.x * BLOCK) {
+    int k = (int)(i / W), w = (int)(i % W);
+    reinterpret_cast<int*>(D->state + slots[k])[w] = reinterpret_cast<const int*>(staged + k)[w];
+  }
+  for (long long i = blockIdx.x * (long long)BLOCK + threadIdx.x; i < (long long)ops * WK_COUNT;
+       i += (long long)gridDim.x * BLOCK)
+    D->node_count[(size_t)slots[i / WK_COUNT] * WK_COUNT + i % WK_COUNT] = 0;
+}
+
+// Identity start: both components of listed slots' first u buffer on level l are zero.
+__global__ void __launch_bounds__(BLOCK) k_pool_zero(BatchDesc* D, int l, const int* slots,
+                                                     int ops) {
+  int n = lvl_n(l);
+  long long per = 2LL * n * n;
+  for (long long i = blockIdx.x * (long long)BLOCK + threadIdx.x; i < (long long)ops * per;
+       i += (long long)gridDim.x * BLOCK)
+    slot_u(D, slots[i / per], l, 0)[i % per] = 0.f;
+}
+
+// Composition start: the finest-level u of slot slots[k] = vbuf[in0[k]] (.) vbuf[in1[k]]
+// (w = u_ij + u_jk(x + u_ij), clamped bilinear, domain units).
+__global__ void __launch_bounds__(BLOCK) k_pool_compose(BatchDesc* D, const float* vbuf,
+                                                        long long est, const int* in0,
+                                                        const int* in1, const int* slots,
+                                                        int ops) {
+  int L = D->finest, n = lvl_n(L);
+  size_t nn = (size_t)n * n;
+  float inv_h = (float)(n - 1);
+  for (long long k = blockIdx.x * (long long)BLOCK + threadIdx.x; k < (long long)ops * nn;
+       k += (long long)gridDim.x * BLOCK) {
+    int op = (int)(k / nn);
+    int i = (int)(k % nn);
+    const float* ul = vbuf + in0[op] * est;
+    const float* ur = vbuf + in1[op] * est;
+    float* w = slot_u(D, slots[op], L, 0);
+    int a = i / n, b = i % n;
+    float ux = ul[i], uy = ul[nn + i];
+    float tx = ux * inv_h, ty = uy * inv_h;
+    float vx = sample_bil<false>(ur, n, b, tx, a, ty, inv_h, nullptr, nullptr);
+    float vy = sample_bil<false>(ur + nn, n, b, tx, a, ty, inv_h, nullptr, nullptr);
+    w[i] = ux + vx;
+    w[nn + i] = uy + vy;
+  }
+}
+
+// Full-weighting restriction of listed slots' first u buffer from level l to level l - 1.
+__global__ void __launch_bounds__(BLOCK) k_pool_restrict(BatchDesc* D, int l, const int* slots,
+                                                         int ops) {
+  int nf = lvl_n(l), nc = lvl_n(l - 1);
+  long long per = (long long)nc * nc;
+  for (long long k = blockIdx.x * (long long)BLOCK + threadIdx.x; k < (long long)ops * 2 * per;
+       k += (long long)gridDim.x * BLOCK) {
+    int p = (int)(k / per), rem = (int)(k % per);
+    int op = p >> 1, comp = p & 1;
+    int A = rem / nc, B = rem % nc;
+    const float* f = slot_u(D, slots[op], l, 0) + (size_t)comp * nf * nf;
+    float sum = 0.f, ws = 0.f;
+    for (int dp = -1; dp <= 1; ++dp) {
+      int a = 2 * A + dp;
+      if (a < 0 || a >= nf) continue;
+      float wa = dp == 0 ? 2.f : 1.f;
+      float row = 0.f, rw = 0.f;
+      for (int dq = -1; dq <= 1; ++dq) {
+        int b = 2 * B + dq;
+        if (b < 0 || b >= nf) continue;
+        float wb = dq == 0 ? 2.f : 1.f;
+        row = fmaf(wb, f[(size_t)a * nf + b], row);
+        rw += wb;
+      }
+      sum = fmaf(wa, row, sum);
+      ws += wa * rw;
+    }
+    slot_u(D, slots[op], l - 1, 0)[(size_t)comp * nc * nc + (size_t)A * nc + B] = sum / ws;
+  }
+}
+
+// Staged guesses on level l (src + src_idx[k] * sstride, [2][n_l^2]) into listed slots.
+__global__ void __launch_bounds__(BLOCK) k_pool_copy(BatchDesc* D, int l, const float* src,
+                                                     long long sstride, const int* src_idx,
+                                                     const int* slots, int ops) {
+  int n = lvl_n(l);
+  long long per = 2LL * n * n;
+  for (long long i = blockIdx.x * (long long)BLOCK + threadIdx.x; i < (long long)ops * per;
+       i += (long long)gridDim.x * BLOCK) {
+    int k = (int)(i / per);
+    slot_u(D, slots[k], l, 0)[i % per] = src[src_idx[k] * sstride + i % per];
+  }
+}
+
+// Finished listed slots: vbuf[outs[k]] = u_L[ub] - tau_pend d of slot slots[k] (a slot that
+// stopped before the finest level leaves its output untouched).
+__global__ void __launch_bounds__(BLOCK) k_pool_finish(BatchDesc* D, const int* slots,
+                                                       const int* outs, int ops, float* vbuf,
+                                                       long long est) {
+  int L = D->finest;
+  int n = lvl_n(L);
+  size_t per = 2 * (size_t)n * n;
+  for (long long k = blockIdx.x * (long long)BLOCK + threadIdx.x; k < (long long)ops * per;
+       k += (long long)gridDim.x * BLOCK) {
+    int op = (int)(k / per);
+    size_t i = k % per;
+    int s = slots[op];
+    const SlotState& st = D->state[s];
+    if (st.level != L) continue;
+    const float* u = slot_u(D, s, L, st.ub);
+    const float* d = D->dbuf + (size_t)s * D->slot_f_stride;
+    float tau = (float)st.tau_pend;
+    vbuf[outs[op] * est + i] = tau != 0.f ? u[i] - tau * d[i] : u[i];
+  }
+}
+
+// Nodal fields vbuf[idx[e]] ([2][n][n], domain units) -> pixels dst + e * 2 * d_plane.
+__global__ void __launch_bounds__(BLOCK) k_from_nodes_idx(const float* vbuf, long long est,
+                                                          const int* idx, int n, float* dst,
+                                                          int H, long long d_plane, int elems,
+                                                          float scale) {
+  long long per = (long long)H * H;
+  for (long long k = blockIdx.x * (long long)BLOCK + threadIdx.x; k < (long long)elems * 2 * per;
+       k += (long long)gridDim.x * BLOCK) {
+    int p = (int)(k / per);
+    int e = p >> 1, comp = p & 1;
+    int i = (int)(k % per);
+    int a = i / H, b = i % H;
+    dst[(size_t)e * 2 * d_plane + (size_t)comp * d_plane + i] =
+        scale * vbuf[idx[e] * est + (size_t)comp * n * n + (size_t)a * n + b];
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // Host launch wrappers
 
 namespace pprs_k {
@@ -1273,6 +1411,48 @@ hipError_t finish(BatchDesc* d, const int* out_idx, float* elems, long long estr
                   long long work, hipStream_t st) {
   hipLaunchKernelGGL(k_finish, dim3(grid_for(work)), dim3(BLOCK), 0, st, d, out_idx, elems,
                      estride);
+  return hipGetLastError();
+}
+
+hipError_t pool_assign(BatchDesc* d, const SlotState* staged, const int* slots, int ops,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_pool_assign, dim3(grid_for((long long)ops * sizeof(SlotState) / 4)),
+                     dim3(BLOCK), 0, st, d, staged, slots, ops);
+  return hipGetLastError();
+}
+hipError_t pool_zero(BatchDesc* d, int l, int n_l, const int* slots, int ops, hipStream_t st) {
+  hipLaunchKernelGGL(k_pool_zero, dim3(grid_for((long long)ops * 2 * n_l * n_l)), dim3(BLOCK), 0,
+                     st, d, l, slots, ops);
+  return hipGetLastError();
+}
+hipError_t pool_compose(BatchDesc* d, int nL, const float* vbuf, long long est, const int* in0,
+                        const int* in1, const int* slots, int ops, hipStream_t st) {
+  hipLaunchKernelGGL(k_pool_compose, dim3(grid_for((long long)ops * nL * nL)), dim3(BLOCK), 0,
+                     st, d, vbuf, est, in0, in1, slots, ops);
+  return hipGetLastError();
+}
+hipError_t pool_restrict(BatchDesc* d, int l, int n_c, const int* slots, int ops,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_pool_restrict, dim3(grid_for((long long)ops * 2 * n_c * n_c)),
+                     dim3(BLOCK), 0, st, d, l, slots, ops);
+  return hipGetLastError();
+}
+hipError_t pool_copy(BatchDesc* d, int l, int n_l, const float* src, long long sstride,
+                     const int* src_idx, const int* slots, int ops, hipStream_t st) {
+  hipLaunchKernelGGL(k_pool_copy, dim3(grid_for((long long)ops * 2 * n_l * n_l)), dim3(BLOCK), 0,
+                     st, d, l, src, sstride, src_idx, slots, ops);
+  return hipGetLastError();
+}
+hipError_t pool_finish(BatchDesc* d, int nL, const int* slots, const int* outs, int ops,
+                       float* vbuf, long long est, hipStream_t st) {
+  hipLaunchKernelGGL(k_pool_finish, dim3(grid_for((long long)ops * 2 * nL * nL)), dim3(BLOCK), 0,
+                     st, d, slots, outs, ops, vbuf, est);
+  return hipGetLastError();
+}
+hipError_t from_nodes_idx(const float* vbuf, long long est, const int* idx, int n, float* dst,
+                          int H, long long d_plane, int elems, float scale, hipStream_t st) {
+  hipLaunchKernelGGL(k_from_nodes_idx, dim3(grid_for((long long)elems * 2 * H * H)), dim3(BLOCK),
+                     0, st, vbuf, est, idx, n, dst, H, d_plane, elems, scale);
   return hipGetLastError();
 }
 

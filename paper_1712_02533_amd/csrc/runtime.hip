@@ -16,6 +16,8 @@
 #include <chrono>
 #include <string>
 #include <vector>
+#include <queue>
+#include <functional>
 
 #include "../../include/pprs.h"
 #include "kernels.h"
@@ -97,7 +99,11 @@ struct pprs_ctx {
   pprs_cnn* cnn = nullptr;  // warm start network (not owned)
   double warm_max_cells = 8.0;
   int warm_mode = PPRS_WARM_REFINE;
-  DevBuf cnn_in, cnn_out, tmp, badflags;
+  DevBuf cnn_in, cnn_out, tmp, badflags, warm_stage;
+  // slot pool: per-round index lists and staged slot states
+  DevBuf pool_idx, pool_states;
+  int pool_group = 8;    // steps between polls of the slot pool
+  int pool_slots = 512;  // concurrent registrations of a series
   BatchDesc hd;
   int slots_cap = 0, slots_L = -1, slots_m0 = -1;
   double coef_beta = -1.0;
@@ -527,10 +533,11 @@ const int kWarmLevel = 7;     // the network works on 128^2 frames (level 7)
 const int kWarmChunk = 64;    // pairs per network call
 const int kPairChunk = 512;   // pairs per batch of pprs_register_pairs
 
-// Network predictions for n pairs (ref[s], tmpl[s]) written as level-7 guesses into slot s's
-// first u buffer; bad[s] = 1 for predictions that are not finite or exceed the bound.
-pprs_status warm_predict(pprs_ctx* c, int n, const int* ref, const int* tmpl,
-                         std::vector<int>& bad) {
+// Network predictions for n pairs (ref[s], tmpl[s]) written as level-7 guesses (domain units,
+// [2][129][129]) to dst + s * dst_stride; bad[s] = 1 for predictions that are not finite or
+// exceed the bound.
+pprs_status warm_predict(pprs_ctx* c, int n, const int* ref, const int* tmpl, float* dst,
+                         long long dst_stride, std::vector<int>& bad) {
   BatchDesc& hd = c->hd;
   int S = 1 << kWarmLevel;
   size_t per = (size_t)S * S * 2;
@@ -552,8 +559,7 @@ pprs_status warm_predict(pprs_ctx* c, int n, const int* ref, const int* tmpl,
     HIPCHK(pprs_cnn_api::check_pred(P<float>(c->cnn_out), np, (long long)per,
                                     (float)c->warm_max_cells, dbad + p0, c->stream));
     HIPCHK(pprs_cnn_api::nhwc_to_planes(P<float>(c->cnn_out), S, np, 1.0f / S,
-                                        hd.ubuf + hd.u_off[kWarmLevel] + (size_t)p0 * hd.slot_u_stride,
-                                        hd.slot_u_stride, c->stream));
+                                        dst + (size_t)p0 * dst_stride, dst_stride, c->stream));
   }
   bad.assign(n, 0);
   HIPCHK(hipMemcpyAsync(bad.data(), dbad, sizeof(int) * n, hipMemcpyDeviceToHost, c->stream));
@@ -570,7 +576,7 @@ pprs_status warm_init(pprs_ctx* c, int n, const int* ref, const int* tmpl, int m
                       std::vector<int>& lv, std::vector<int>& fl) {
   BatchDesc& hd = c->hd;
   std::vector<int> bad;
-  STCHK(warm_predict(c, n, ref, tmpl, bad));
+  STCHK(warm_predict(c, n, ref, tmpl, hd.ubuf + hd.u_off[kWarmLevel], hd.slot_u_stride, bad));
   int n0 = level_n(m0);
   long long per0 = 2LL * n0 * n0;
   lv.assign(n, m0);
@@ -592,6 +598,267 @@ pprs_status warm_init(pprs_ctx* c, int n, const int* ref, const int* tmpl, int m
                                     hd.slot_u_stride, per0, 1, 0.f, c->stream));
   }
   for (int s = 0; s < n; ++s) fl[s] = bad[s] ? PPRS_FLAG_FALLBACK : 0;
+  return PPRS_OK;
+}
+
+// ---- slot pool ---------------------------------------------------------------------------
+// A registration ("op") reads frames ref/tmpl, starts from the identity, a composition of two
+// finished results or a staged guess, and writes its finest-level result (nodal, domain units)
+// to its own version buffer vbuf[out]. Ops become ready when the ops producing their inputs
+// have finished; ready ops are started in free slots in op order, and the slots keep stepping
+// (early retirement: a finished slot takes the next ready op at the following poll).
+
+struct PoolOp {
+  int ref, tmpl;
+  InitKind init;   // INIT_IDENTITY, INIT_COMPOSE or INIT_PREPARED (staged guess)
+  int in0, in1;    // INIT_COMPOSE: versions composed (in1 o in0)
+  int out;         // version written
+  int start;       // start level
+  int flags;       // initial flags (e.g. PPRS_FLAG_FALLBACK)
+  int stage;       // INIT_PREPARED: index of the staged level-stage_level guess
+};
+
+struct GraphExec {
+  hipGraphExec_t exec = nullptr;
+  ~GraphExec() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+  }
+};
+
+struct PoolSpec {
+  const float* stage = nullptr;   // staged guesses [count][2][n^2] on stage_level
+  long long stage_stride = 0;
+  int stage_level = -1;
+};
+
+pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf, long long est,
+                     const pprs_params* p, const PoolSpec& spec, pprs_pair_stats* stats,
+                     long long* node_steps, long long* node_passes, int* flags_or) {
+  const int n_ops = (int)ops.size();
+  if (n_ops == 0) return PPRS_OK;
+  auto t_start = std::chrono::steady_clock::now();
+  BatchDesc& hd = c->hd;
+  int L = hd.finest, m0 = hd.coarsest;
+  int nL = level_n(L);
+  S = std::max(1, std::min(S, std::min(n_ops, hd.max_slots)));
+  hd.n_slots = S;
+  hd.ladder_k = p->ladder_k;
+  hd.lambda = p->lambda;
+  hd.sigma = p->armijo_sigma;
+  hd.step_cap = p->step_cap;
+  hd.tau_min_rel = p->tau_min_rel;
+  hd.eps = p->eps;
+  hd.iter_max = p->iter_max;
+  BatchDesc* d = P<BatchDesc>(c->desc);
+  HIPCHK(hipMemcpyAsync(d, &hd, sizeof(BatchDesc), hipMemcpyHostToDevice, c->stream));
+  // dependencies: producers are the ops whose out is read
+  std::vector<int> producer(n_ops + 1, -1);  // version -> op (versions are op outputs)
+  int max_ver = 0;
+  for (const PoolOp& o : ops) max_ver = std::max(max_ver, o.out);
+  producer.assign(max_ver + 1, -1);
+  for (int i = 0; i < n_ops; ++i) producer[ops[i].out] = i;
+  std::vector<int> remaining(n_ops, 0);
+  std::vector<std::vector<int>> dependents(n_ops);
+  for (int i = 0; i < n_ops; ++i) {
+    if (ops[i].init != INIT_COMPOSE) continue;
+    for (int v : {ops[i].in0, ops[i].in1}) {
+      int q = v >= 0 && v <= max_ver ? producer[v] : -1;
+      if (q < 0 || q >= i) return fail(PPRS_EINDEX, "op %d reads a version no earlier op writes", i);
+      remaining[i]++;
+      dependents[q].push_back(i);
+    }
+  }
+  std::priority_queue<int, std::vector<int>, std::greater<int>> ready;
+  for (int i = 0; i < n_ops; ++i)
+    if (remaining[i] == 0) ready.push(i);
+  // empty slots
+  std::vector<SlotState> st(S);
+  for (int s = 0; s < S; ++s) {
+    memset(&st[s], 0, sizeof(SlotState));
+    st[s].phase = PH_DONE;
+    st[s].level = m0;
+  }
+  HIPCHK(hipMemcpyAsync(hd.state, st.data(), sizeof(SlotState) * S, hipMemcpyHostToDevice,
+                        c->stream));
+  STCHK(ensure(c->pool_idx, sizeof(int) * 6 * (size_t)S));
+  STCHK(ensure(c->pool_states, sizeof(SlotState) * (size_t)S));
+  int* didx = P<int>(c->pool_idx);
+  SlotState* dstates = P<SlotState>(c->pool_states);
+  std::vector<int> slot_op(S, -1), free_slots;
+  for (int s = S - 1; s >= 0; --s) free_slots.push_back(s);
+  std::vector<long long> nodes((size_t)S * WK_COUNT);
+  size_t lds = smooth_lds_bytes(hd);
+  int K = p->ladder_k;
+  long long passes_per_iter = 2 + (long long)ceil(log2(1.0 / p->tau_min_rel) / (2 * K + 1));
+  long long per_op_steps =
+      (long long)p->levels * ((long long)p->iter_max + 2) * (passes_per_iter + 2) + 64;
+  long long max_steps = per_op_steps * (long long)(n_ops / S + 2) + 64;
+  long long done_steps = 0;
+  int done_ops = 0;
+  // host copies of the per-round lists (they must outlive the asynchronous uploads)
+  std::vector<int> h_idx(6 * (size_t)S);
+  std::vector<SlotState> h_states(S);
+  int G = std::max(1, c->pool_group);
+  // the G steps between polls always launch the same kernels with the same arguments (all
+  // per-slot state lives on the device): one captured graph replays them, unless per-launch
+  // timing events are wanted
+  GraphExec graph;
+  if (!c->timing) {
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    pprs_status cs = PPRS_OK;
+    for (int k = 0; k < G && cs == PPRS_OK; ++k) cs = launch_step(c, d, K, lds);
+    hipError_t ce = hipStreamEndCapture(c->stream, &g);
+    if (cs != PPRS_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return cs;
+    }
+    if (ce != hipSuccess) return fail(PPRS_EHIP, "graph capture failed: %s", hipGetErrorString(ce));
+    hipError_t ie = hipGraphInstantiate(&graph.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess)
+      return fail(PPRS_EHIP, "graph instantiation failed: %s", hipGetErrorString(ie));
+  }
+  while (done_ops < n_ops) {
+    // 1. start ready ops in free slots
+    int na = 0;
+    std::vector<int> a_slot, a_op;
+    while (!free_slots.empty() && !ready.empty()) {
+      int i = ready.top();
+      ready.pop();
+      int s = free_slots.back();
+      free_slots.pop_back();
+      slot_op[s] = i;
+      a_slot.push_back(s);
+      a_op.push_back(i);
+      const PoolOp& o = ops[i];
+      SlotState& x = h_states[na];
+      memset(&x, 0, sizeof(SlotState));
+      x.phase = PH_INIT;
+      x.level = o.start;
+      x.ref = o.ref;
+      x.tmpl = o.tmpl;
+      x.finest = L;
+      x.coarsest = o.start;
+      x.tau_prev = INFINITY;
+      x.flags = o.flags;
+      ++na;
+    }
+    if (na > 0) {
+      // lists: [0] slots, [1] in0, [2] in1 / stage index, grouped by init kind
+      for (int k = 0; k < na; ++k) h_idx[k] = a_slot[k];
+      HIPCHK(hipMemcpyAsync(dstates, h_states.data(), sizeof(SlotState) * na,
+                            hipMemcpyHostToDevice, c->stream));
+      HIPCHK(hipMemcpyAsync(didx, h_idx.data(), sizeof(int) * na, hipMemcpyHostToDevice,
+                            c->stream));
+      HIPCHK(pprs_k::pool_assign(d, dstates, didx, na, c->stream));
+      // initial guesses per kind and start level
+      for (int kind : {(int)INIT_IDENTITY, (int)INIT_COMPOSE, (int)INIT_PREPARED}) {
+        for (int lv = m0; lv <= L; ++lv) {
+          int cnt = 0;
+          int* hs = h_idx.data() + S;            // slots
+          int* h0 = h_idx.data() + 2 * S;        // in0 / stage index
+          int* h1 = h_idx.data() + 3 * S;        // in1
+          for (int k = 0; k < na; ++k) {
+            const PoolOp& o = ops[a_op[k]];
+            if ((int)o.init != kind || o.start != lv) continue;
+            hs[cnt] = a_slot[k];
+            h0[cnt] = kind == INIT_PREPARED ? o.stage : o.in0;
+            h1[cnt] = o.in1;
+            ++cnt;
+          }
+          if (cnt == 0) continue;
+          int* ds = didx + S;
+          int* d0 = didx + 2 * S;
+          int* d1 = didx + 3 * S;
+          HIPCHK(hipMemcpyAsync(ds, hs, sizeof(int) * cnt, hipMemcpyHostToDevice, c->stream));
+          HIPCHK(hipMemcpyAsync(d0, h0, sizeof(int) * cnt, hipMemcpyHostToDevice, c->stream));
+          if (kind == INIT_COMPOSE)
+            HIPCHK(hipMemcpyAsync(d1, h1, sizeof(int) * cnt, hipMemcpyHostToDevice, c->stream));
+          int top = L;
+          if (kind == INIT_IDENTITY) {
+            HIPCHK(pprs_k::pool_zero(d, lv, level_n(lv), ds, cnt, c->stream));
+            top = lv;
+          } else if (kind == INIT_COMPOSE) {
+            HIPCHK(pprs_k::pool_compose(d, nL, vbuf, est, d0, d1, ds, cnt, c->stream));
+          } else {
+            if (!spec.stage || spec.stage_level < lv || spec.stage_level > L)
+              return fail(PPRS_ESTATE, "staged guesses on level %d cannot start level %d",
+                          spec.stage_level, lv);
+            HIPCHK(pprs_k::pool_copy(d, spec.stage_level, level_n(spec.stage_level), spec.stage,
+                                     spec.stage_stride, d0, ds, cnt, c->stream));
+            top = spec.stage_level;
+          }
+          for (int l = top; l > lv; --l)
+            HIPCHK(pprs_k::pool_restrict(d, l, level_n(l - 1), ds, cnt, c->stream));
+          // the lists are reused by the next group: wait for the uploads to be consumed
+          HIPCHK(hipStreamSynchronize(c->stream));
+        }
+      }
+    }
+    // 2. step every slot G times
+    if (graph.exec) {
+      HIPCHK(hipGraphLaunch(graph.exec, c->stream));
+    } else {
+      for (int k = 0; k < G; ++k) STCHK(launch_step(c, d, K, lds));
+    }
+    done_steps += G;
+    // 3. poll: retire finished slots, release their dependents
+    HIPCHK(hipMemcpyAsync(st.data(), hd.state, sizeof(SlotState) * S, hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(nodes.data(), hd.node_count, sizeof(long long) * WK_COUNT * S,
+                          hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->timing) STCHK(tk_collect(c));
+    int nf = 0;
+    int* fs = h_idx.data() + 4 * S;
+    int* fo = h_idx.data() + 5 * S;
+    for (int s = 0; s < S; ++s) {
+      int i = slot_op[s];
+      if (i < 0 || st[s].phase != PH_DONE) continue;
+      fs[nf] = s;
+      fo[nf] = ops[i].out;
+      ++nf;
+      if (flags_or) *flags_or |= st[s].flags;
+      for (int k = 0; k < WK_COUNT; ++k) c->nodes_acc[k] += nodes[(size_t)s * WK_COUNT + k];
+      for (int l = st[s].coarsest; l <= L; ++l) {
+        long long nn = (long long)level_n(l) * level_n(l);
+        if (node_steps) *node_steps += nn * st[s].iters[l - st[s].coarsest];
+        if (node_passes) *node_passes += nn * st[s].passes[l - st[s].coarsest];
+      }
+      if (stats) {
+        pprs_pair_stats& o = stats[i];
+        memset(&o, 0, sizeof o);
+        for (int l = st[s].coarsest; l <= L; ++l) {
+          o.iters[l - m0] = st[s].iters[l - st[s].coarsest];
+          o.passes[l - m0] = st[s].passes[l - st[s].coarsest];
+        }
+        o.energy = st[s].E;
+        o.ncc = st[s].ncc;
+        o.flags = st[s].flags;
+      }
+      for (int q : dependents[i])
+        if (--remaining[q] == 0) ready.push(q);
+      slot_op[s] = -1;
+      free_slots.push_back(s);
+      ++done_ops;
+    }
+    if (nf > 0) {
+      HIPCHK(hipMemcpyAsync(didx + 4 * S, fs, sizeof(int) * 2 * S, hipMemcpyHostToDevice,
+                            c->stream));
+      HIPCHK(pprs_k::pool_finish(d, nL, didx + 4 * S, didx + 5 * S, nf, vbuf, est, c->stream));
+      // mark the retired slots empty (their state stays DONE; the lists drop them)
+    }
+    if (done_steps > max_steps)
+      return fail(PPRS_ESTATE, "slot pool did not finish within %lld steps", max_steps);
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->log) {
+    double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    fprintf(stderr, "[pprs] pool of %d slots ran %d registrations in %lld steps, %.2f ms\n", S,
+            n_ops, done_steps, ms);
+    fflush(stderr);
+  }
   return PPRS_OK;
 }
 
@@ -645,7 +912,8 @@ pprs_status pprs_create(pprs_ctx** out, int device, void* stream) {
   if (stream) {
     c->stream = (hipStream_t)stream;
   } else {
-    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    // a blocking stream: ordered with the legacy default stream like the caller's work
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamDefault);
     if (e != hipSuccess) {
       delete c;
       return fail(PPRS_EHIP, "hipStreamCreate failed: %s", hipGetErrorString(e));
@@ -783,6 +1051,15 @@ pprs_status pprs_compose_deformations(pprs_ctx* c, const float* u_ij, const floa
   return PPRS_OK;
 }
 
+// RAII for the series timing events.
+struct EventSet {
+  hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+  ~EventSet() {
+    for (hipEvent_t x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+};
+
 pprs_status pprs_prefix_register_series(pprs_ctx* c, const float* frames, int N, int H, int W,
                                         float* u_out, const pprs_params* params,
                                         pprs_series_stats* stats, pprs_pair_stats* op_stats) {
@@ -796,102 +1073,100 @@ pprs_status pprs_prefix_register_series(pprs_ctx* c, const float* frames, int N,
   int nL = level_n(L);
   int M = N - 1;
   size_t plane = (size_t)H * W;
-  hipEvent_t e0, e1, e2, e3;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  HIPCHK(hipEventCreate(&e2));
-  HIPCHK(hipEventCreate(&e3));
-  HIPCHK(hipEventRecord(e0, c->stream));
+  EventSet ev;
+  for (int k = 0; k < 4; ++k) HIPCHK(hipEventCreate(&ev.e[k]));
+  HIPCHK(hipEventRecord(ev.e[0], c->stream));
   pprs_series_stats S;
   memset(&S, 0, sizeof S);
   HIPCHK(pprs_k::fill(u_out, 2LL * (long long)plane, 0.f, c->stream));
   bool warm = c->cnn != nullptr && m0 <= kWarmLevel && kWarmLevel <= L;
-  if (M >= 1) {
-    STCHK(prepare_frames(c, frames, N, H, L, m0, N - 1));
-  }
-  HIPCHK(hipEventRecord(e1, c->stream));
+  bool skip = warm && c->warm_mode == PPRS_WARM_SKIP;
+  if (M >= 1) STCHK(prepare_frames(c, frames, N, H, L, m0, N - 1));
+  HIPCHK(hipEventRecord(ev.e[1], c->stream));
   // schedule
-  std::vector<int> ops;
+  std::vector<int> plan;
   int n_ops = 0, n_levels = 0;
   pprs_scan_plan(params->scan, std::max(M, 0), nullptr, 0, &n_ops, &n_levels);  // sizes only
-  ops.resize(3 * (size_t)std::max(n_ops, 1));
-  if (pprs_scan_plan(params->scan, std::max(M, 0), ops.data(), n_ops, &n_ops, &n_levels) != PPRS_OK)
+  plan.resize(3 * (size_t)std::max(n_ops, 1));
+  if (pprs_scan_plan(params->scan, std::max(M, 0), plan.data(), n_ops, &n_ops, &n_levels) != PPRS_OK)
     return fail(PPRS_EINVAL, "scan planning failed");
-  int widest = M;
-  for (int lv = 0, i = 0; lv < n_levels; ++lv) {
-    int cnt = 0;
-    while (i < n_ops && ops[3 * i + 2] == lv) ++cnt, ++i;
-    widest = std::max(widest, cnt);
-  }
   int flags = 0;
   if (M >= 1) {
     long long est = 2LL * nL * nL;
-    STCHK(ensure(c->elems, sizeof(float) * est * M));
-    STCHK(ensure_slots(c, widest, L, m0, params->beta));
-    float* elems = P<float>(c->elems);
-    // preprocessing: A on all neighbour pairs (one batch)
-    std::vector<int> ref(M), tmpl(M), out(M), ei(M), ek(M);
+    int slots = std::min(M, c->pool_slots);
+    // one result buffer ("version") per operator application: no result is overwritten while
+    // a later application may still read it
+    STCHK(ensure(c->elems, sizeof(float) * est * (size_t)(M + n_ops)));
+    STCHK(ensure_slots(c, slots, L, m0, params->beta));
+    float* vbuf = P<float>(c->elems);
+    std::vector<PoolOp> ops;
+    ops.reserve(M + n_ops);
+    std::vector<int> ref(M), tmpl(M), ver(M), ei(M), ek(M);
     for (int m = 0; m < M; ++m) {
       ref[m] = m;
       tmpl[m] = m + 1;
-      out[m] = m;
+      ver[m] = m;
       ei[m] = m;
       ek[m] = m + 1;
     }
+    // preprocessing: A on every neighbour pair, from the identity or the network's guess
+    PoolSpec spec;
+    std::vector<int> bad(M, 0);
     if (warm) {
-      std::vector<int> lv, fl;
-      STCHK(warm_init(c, M, ref.data(), tmpl.data(), m0, lv, fl));
-      STCHK(run_batch(c, M, ref.data(), tmpl.data(), INIT_PREPARED, nullptr, nullptr,
-                      out.data(), elems, params, op_stats, &S.node_steps, &S.node_passes, &flags,
-                      m0, lv.data(), fl.data()));
-    } else {
-      STCHK(run_batch(c, M, ref.data(), tmpl.data(), INIT_IDENTITY, nullptr, nullptr,
-                      out.data(), elems, params, op_stats, &S.node_steps, &S.node_passes,
-                      &flags));
+      int n7 = level_n(kWarmLevel);
+      long long per7 = 2LL * n7 * n7;
+      STCHK(ensure(c->warm_stage, sizeof(float) * per7 * M));
+      STCHK(warm_predict(c, M, ref.data(), tmpl.data(), P<float>(c->warm_stage), per7, bad));
+      spec.stage = P<float>(c->warm_stage);
+      spec.stage_stride = per7;
+      spec.stage_level = kWarmLevel;
     }
-    HIPCHK(hipEventRecord(e2, c->stream));
-    // scan: every level of the schedule is one batch of B applications
-    int done = 0;
-    for (int lv = 0, i = 0; lv < n_levels; ++lv) {
-      std::vector<int> lft, rgt, r2, t2;
-      while (i < n_ops && ops[3 * i + 2] == lv) {
-        int a = ops[3 * i], b = ops[3 * i + 1];
-        if (ek[a] != ei[b])
-          return fail(PPRS_EINDEX, "scan operands (%d,%d) and (%d,%d) do not share a frame",
-                      ei[a], ek[a], ei[b], ek[b]);
-        lft.push_back(a);
-        rgt.push_back(b);
-        r2.push_back(ei[a]);
-        t2.push_back(ek[b]);
-        ++i;
+    HIPCHK(hipEventRecord(ev.e[2], c->stream));
+    for (int m = 0; m < M; ++m) {
+      PoolOp o{m, m + 1, INIT_IDENTITY, -1, -1, m, m0, 0, -1};
+      if (warm) {
+        if (bad[m]) {
+          o.flags = PPRS_FLAG_FALLBACK;
+        } else {
+          o.init = INIT_PREPARED;
+          o.stage = m;
+          o.start = skip ? kWarmLevel : m0;
+        }
       }
-      int cnt = (int)lft.size();
-      STCHK(run_batch(c, cnt, r2.data(), t2.data(), INIT_COMPOSE, lft.data(), rgt.data(),
-                      rgt.data(), elems, params, op_stats ? op_stats + M + done : nullptr,
-                      &S.node_steps, &S.node_passes, &flags,
-                      warm && c->warm_mode == PPRS_WARM_SKIP ? kWarmLevel : m0));
-      for (int k = 0; k < cnt; ++k) ei[rgt[k]] = ei[lft[k]];
-      done += cnt;
+      ops.push_back(o);
+    }
+    // scan: x[right] <- x[left] (.) x[right], i.e. B(x[left], x[right]) registers frame
+    // ek[right] to frame ei[left] from the composition of the two results
+    for (int i = 0; i < n_ops; ++i) {
+      int a = plan[3 * i], b = plan[3 * i + 1];
+      if (ek[a] != ei[b])
+        return fail(PPRS_EINDEX, "scan operands (%d,%d) and (%d,%d) do not share a frame", ei[a],
+                    ek[a], ei[b], ek[b]);
+      PoolOp o{ei[a], ek[b], INIT_COMPOSE, ver[a], ver[b], M + i, skip ? kWarmLevel : m0, 0, -1};
+      ops.push_back(o);
+      ver[b] = M + i;
+      ei[b] = ei[a];
     }
     for (int m = 0; m < M; ++m)
       if (ei[m] != 0 || ek[m] != m + 1)
         return fail(PPRS_EINDEX, "element %d ends as (%d,%d)", m, ei[m], ek[m]);
-    HIPCHK(pprs_k::from_nodes(elems, nL, (long long)nL * nL, u_out + 2 * plane, H,
-                              (long long)plane, 2 * M, (float)(nL - 1), c->stream));
+    STCHK(run_pool(c, ops, slots, vbuf, est, params, spec, op_stats, &S.node_steps,
+                   &S.node_passes, &flags));
+    STCHK(ensure(c->opidx, sizeof(int) * (size_t)std::max(M, 3 * c->slots_cap)));
+    HIPCHK(hipMemcpyAsync(P<int>(c->opidx), ver.data(), sizeof(int) * M, hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(pprs_k::from_nodes_idx(vbuf, est, P<int>(c->opidx), nL, u_out + 2 * plane, H,
+                                  (long long)plane, M, (float)(nL - 1), c->stream));
   } else {
-    HIPCHK(hipEventRecord(e2, c->stream));
+    HIPCHK(hipEventRecord(ev.e[2], c->stream));
   }
-  HIPCHK(hipEventRecord(e3, c->stream));
+  HIPCHK(hipEventRecord(ev.e[3], c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
-  (void)hipEventElapsedTime(&t01, e0, e1);
-  (void)hipEventElapsedTime(&t12, e1, e2);
-  (void)hipEventElapsedTime(&t23, e2, e3);
-  (void)hipEventElapsedTime(&t03, e0, e3);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipEventDestroy(e2);
-  (void)hipEventDestroy(e3);
+  (void)hipEventElapsedTime(&t01, ev.e[0], ev.e[1]);
+  (void)hipEventElapsedTime(&t12, ev.e[1], ev.e[2]);
+  (void)hipEventElapsedTime(&t23, ev.e[2], ev.e[3]);
+  (void)hipEventElapsedTime(&t03, ev.e[0], ev.e[3]);
   S.n_ops_a = M;
   S.n_ops_b = n_ops;
   S.n_scan_levels = n_levels;
@@ -902,6 +1177,15 @@ pprs_status pprs_prefix_register_series(pprs_ctx* c, const float* frames, int N,
   S.ms_scan = t23;
   if (stats) *stats = S;
   return status_from_flags(flags);
+}
+
+pprs_status pprs_set_pool(pprs_ctx* c, int slots, int group_steps) {
+  STCHK(enter(c));
+  if (slots < 0 || group_steps < 0 || slots > 65536 || group_steps > 1024)
+    return fail(PPRS_EINVAL, "slots must be in [0, 65536] and group_steps in [0, 1024]");
+  c->pool_slots = slots ? slots : 512;
+  c->pool_group = group_steps ? group_steps : 8;
+  return PPRS_OK;
 }
 
 pprs_status pprs_set_warm_start(pprs_ctx* c, pprs_cnn* cnn, double max_cells, int mode) {

@@ -168,3 +168,44 @@ def test_invalid_inputs_raise():
         P.register_pair(t[:60, :60].contiguous(), t[:60, :60].contiguous(), params=_gpu_params(2))
     with pytest.raises(PprsError):
         P.register_pair(t, t, params=_gpu_params(9))
+
+
+def test_series_pool_shape_does_not_change_results():
+    """Every application's result is independent of the slot it ran in and of what ran beside
+    it: a pool of 3 slots polled every 2 steps gives the default pool's bits."""
+    torch = _torch()
+    import paper_1712_02533_amd as P
+    s = make_series(SeriesSpec(12, 128, 4.0, 1.0, 10.0, 21))
+    frames = torch.tensor(s.frames, device="cuda")
+    params = _gpu_params(3, scan="brent_kung")
+    say("series 12 x 128, default pool")
+    u1, st1, ops1 = P.prefix_register_series(frames, params=params, want_op_stats=True)
+    P.set_pool(slots=3, group_steps=2)
+    try:
+        say("series 12 x 128, pool of 3 slots")
+        u2, st2, ops2 = P.prefix_register_series(frames, params=params, want_op_stats=True)
+    finally:
+        P.set_pool()
+    assert torch.equal(u1, u2)
+    assert [o.iters for o in ops1] == [o.iters for o in ops2]
+    assert st1.node_steps == st2.node_steps
+
+
+def test_series_graph_replay_matches_eager_launches():
+    """The pool's step groups replay a captured graph; with per-launch timing events the same
+    steps launch eagerly. Both give the same bits, over many replays and two calls."""
+    torch = _torch()
+    import paper_1712_02533_amd as P
+    s = make_series(SeriesSpec(10, 128, 4.0, 1.0, 10.0, 22))
+    frames = torch.tensor(s.frames, device="cuda")
+    params = _gpu_params(3, scan="brent_kung")
+    say("series 10 x 128, graph replays")
+    g1, _, _ = P.prefix_register_series(frames, params=params)
+    g2, _, _ = P.prefix_register_series(frames, params=params)
+    P.set_kernel_timing(True)
+    try:
+        say("series 10 x 128, eager launches")
+        e1, _, _ = P.prefix_register_series(frames, params=params)
+    finally:
+        P.set_kernel_timing(False)
+    assert torch.equal(g1, g2) and torch.equal(g1, e1)
