@@ -155,6 +155,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start runs")
+    ap.add_argument("--no-tune", action="store_true", help="default launch shape, no autotuning")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1712_02533_amd", "weights",
                                                       "warmstart_512.safetensors"))
     args = ap.parse_args()
@@ -187,6 +188,13 @@ def main():
     calib = torch.empty(64 << 20, device=dev)
     calib.copy_(torch.ones_like(calib))
     del calib
+    tuning = None
+    if not args.no_tune:
+        from paper_1712_02533_amd import autotune
+        t0 = time.perf_counter()
+        tuning = autotune.tune(frames, params, cache=os.path.join(
+            os.environ.get("TMPDIR", "/tmp"), "pprs_tuning_bench.json"), log=log)
+        log("autotuned launch shape in %.1f s: %s" % (time.perf_counter() - t0, tuning))
     for w in range(args.warmup):
         _, st, _ = P.prefix_register_series(frames, params=params, out=out)
         log("warmup %d: %.1f ms, %d A + %d B ops" % (w, st.ms_total, st.n_ops_a, st.n_ops_b))
@@ -238,6 +246,7 @@ def main():
         data="synthetic",
         config=dict(workload=WORKLOADS[args.config]["name"], frames=spec.n_frames,
                     side=spec.side, levels=cfg["levels"], scan=cfg["scan"], start="cold",
+                    tuning=tuning,
                     registrations_per_step=stats[0].n_ops_a + stats[0].n_ops_b),
         series_scan_s=round(ms_per_step / 1e3, 3),
         roofline=roofline, kernels=kernels,

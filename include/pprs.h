@@ -148,6 +148,24 @@ pprs_status pprs_prefix_register_series(pprs_ctx* ctx, const float* frames, int 
    Returns PPRS_EINVAL for values out of range (slots > 65536, group_steps > 1024). */
 pprs_status pprs_set_pool(pprs_ctx* ctx, int slots, int group_steps);
 
+/* Launch shape of the registration kernels; 0 selects the default. Every value only changes
+   how work is spread over the GPU, never a result (each tile's partial sums and each slot's
+   decisions are the same for any shape): the autotuner (paper_1712_02533_amd.autotune) times
+   candidates and keeps the fastest. */
+typedef struct {
+  int pool_slots;    /* concurrent registrations of a series (default 512, at most 65536) */
+  int pool_group;    /* steps between polls of the slot pool (default 8, at most 1024) */
+  int grid_energy;   /* workgroups of the energy kernels (default 2048) */
+  int grid_grad;     /* workgroups of the gradient kernel (default 2048) */
+  int grid_smooth;   /* workgroups of the metric-solve kernels (default 1024) */
+  int grid_prolong;  /* workgroups of the prolongation kernel (default 2048) */
+} pprs_tuning;
+
+/* Reads / replaces the launch shape of ctx (host struct). PPRS_EINVAL for out-of-range
+   values. */
+pprs_status pprs_get_tuning(pprs_ctx* ctx, pprs_tuning* t);
+pprs_status pprs_set_tuning(pprs_ctx* ctx, const pprs_tuning* t);
+
 /* Host-only: the scan schedule over M = N-1 elements (algorithms "serial" and "brent_kung").
    ops (host, capacity `cap` triples) receives (left, right, level) per B application in
    execution order: x[right] <- x[left] (.) x[right]; ops of one level are independent.

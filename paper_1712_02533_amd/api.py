@@ -48,6 +48,14 @@ class _CSeriesStats(ctypes.Structure):
 
 
 @dataclass
+class _CTuning(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int) for n in ("pool_slots", "pool_group", "grid_energy",
+                                            "grid_grad", "grid_smooth", "grid_prolong")]
+
+
+TUNING_KEYS = [n for n, _ in _CTuning._fields_]
+
+
 class Params:
     """Mirror of pprs_params; defaults are pprs_default_params()."""
     levels: int = 4
@@ -129,6 +137,8 @@ def _lib():
                                                ctypes.POINTER(ctypes.c_int), i]),
                 "pprs_kernel_name": (ctypes.c_char_p, [i]),
                 "pprs_set_pool": (i, [vp, i, i]),
+                "pprs_get_tuning": (i, [vp, ctypes.POINTER(_CTuning)]),
+                "pprs_set_tuning": (i, [vp, ctypes.POINTER(_CTuning)]),
             }
             for name, (res, args) in sigs.items():
                 fn = getattr(lib, name)
@@ -298,6 +308,25 @@ def set_pool(slots: int = 0, group_steps: int = 0, device=None):
     import torch
     dev = device or torch.device("cuda", torch.cuda.current_device())
     _check(_lib().pprs_set_pool(_ctx(dev).handle, slots, group_steps))
+
+
+def get_tuning(device=None) -> dict:
+    """Launch shape of the current stream's context (see pprs_tuning)."""
+    import torch
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    t = _CTuning()
+    _check(_lib().pprs_get_tuning(_ctx(dev).handle, ctypes.byref(t)))
+    return {k: getattr(t, k) for k in TUNING_KEYS}
+
+
+def set_tuning(tuning: dict, device=None):
+    """Sets the launch shape (missing keys keep their value; 0 means the default)."""
+    import torch
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    cur = get_tuning(dev)
+    cur.update({k: int(v) for k, v in tuning.items() if k in TUNING_KEYS})
+    t = _CTuning(**cur)
+    _check(_lib().pprs_set_tuning(_ctx(dev).handle, ctypes.byref(t)))
 
 
 def set_kernel_timing(enable: bool, device=None):

@@ -64,8 +64,6 @@ static pprs_status fail(pprs_status s, const char* fmt, ...) {
 
 namespace {
 
-const int kGridItems = 2048;   // workgroups of the per-step item kernels
-const int kGridSmooth = 1024;
 const int kGridFin = 512;       // finalisation: one workgroup per listed slot (grid-stride)
 
 struct DevBuf {
@@ -104,6 +102,8 @@ struct pprs_ctx {
   DevBuf pool_idx, pool_states;
   int pool_group = 8;    // steps between polls of the slot pool
   int pool_slots = 512;  // concurrent registrations of a series
+  // workgroups of the per-step item kernels (results do not depend on them)
+  int grid_energy = 2048, grid_grad = 2048, grid_smooth = 1024, grid_prolong = 2048;
   BatchDesc hd;
   int slots_cap = 0, slots_L = -1, slots_m0 = -1;
   double coef_beta = -1.0;
@@ -390,14 +390,14 @@ pprs_status tk_collect(pprs_ctx* c) {
 
 pprs_status launch_step(pprs_ctx* c, BatchDesc* d, int ladder_k, size_t lds) {
   TIMED(TK_PLAN, pprs_k::plan(d, c->stream));
-  TIMED(TK_PROLONG, pprs_k::prolong(d, kGridItems, c->stream));
-  TIMED(TK_EVAL, pprs_k::energy(d, 0, ladder_k, kGridItems, c->stream));
+  TIMED(TK_PROLONG, pprs_k::prolong(d, c->grid_prolong, c->stream));
+  TIMED(TK_EVAL, pprs_k::energy(d, 0, ladder_k, c->grid_energy, c->stream));
   TIMED(TK_FIN, pprs_k::energy_fin(d, 0, ladder_k, kGridFin, c->stream));
-  TIMED(TK_GRAD, pprs_k::grad(d, kGridItems, c->stream));
-  TIMED(TK_SMY, pprs_k::smooth(d, 0, kGridSmooth, lds, c->stream));
-  TIMED(TK_SMX, pprs_k::smooth(d, 1, kGridSmooth, lds, c->stream));
+  TIMED(TK_GRAD, pprs_k::grad(d, c->grid_grad, c->stream));
+  TIMED(TK_SMY, pprs_k::smooth(d, 0, c->grid_smooth, lds, c->stream));
+  TIMED(TK_SMX, pprs_k::smooth(d, 1, c->grid_smooth, lds, c->stream));
   TIMED(TK_FIN, pprs_k::smooth_fin(d, kGridFin, c->stream));
-  TIMED(TK_LADDER, pprs_k::energy(d, 1, ladder_k, kGridItems, c->stream));
+  TIMED(TK_LADDER, pprs_k::energy(d, 1, ladder_k, c->grid_energy, c->stream));
   TIMED(TK_FIN, pprs_k::energy_fin(d, 1, ladder_k, kGridFin, c->stream));
   return PPRS_OK;
 }
@@ -1177,6 +1177,33 @@ pprs_status pprs_prefix_register_series(pprs_ctx* c, const float* frames, int N,
   S.ms_scan = t23;
   if (stats) *stats = S;
   return status_from_flags(flags);
+}
+
+pprs_status pprs_get_tuning(pprs_ctx* c, pprs_tuning* t) {
+  if (!c || !t) return fail(PPRS_EINVAL, "NULL argument");
+  t->pool_slots = c->pool_slots;
+  t->pool_group = c->pool_group;
+  t->grid_energy = c->grid_energy;
+  t->grid_grad = c->grid_grad;
+  t->grid_smooth = c->grid_smooth;
+  t->grid_prolong = c->grid_prolong;
+  return PPRS_OK;
+}
+
+pprs_status pprs_set_tuning(pprs_ctx* c, const pprs_tuning* t) {
+  if (!c || !t) return fail(PPRS_EINVAL, "NULL argument");
+  const int v[6] = {t->pool_slots, t->pool_group, t->grid_energy, t->grid_grad, t->grid_smooth,
+                    t->grid_prolong};
+  const int hi[6] = {65536, 1024, 65536, 65536, 65536, 65536};
+  for (int k = 0; k < 6; ++k)
+    if (v[k] < 0 || v[k] > hi[k]) return fail(PPRS_EINVAL, "tuning value %d out of range", k);
+  c->pool_slots = t->pool_slots ? t->pool_slots : 512;
+  c->pool_group = t->pool_group ? t->pool_group : 8;
+  c->grid_energy = t->grid_energy ? t->grid_energy : 2048;
+  c->grid_grad = t->grid_grad ? t->grid_grad : 2048;
+  c->grid_smooth = t->grid_smooth ? t->grid_smooth : 1024;
+  c->grid_prolong = t->grid_prolong ? t->grid_prolong : 2048;
+  return PPRS_OK;
 }
 
 pprs_status pprs_set_pool(pprs_ctx* c, int slots, int group_steps) {

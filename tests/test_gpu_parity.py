@@ -209,3 +209,24 @@ def test_series_graph_replay_matches_eager_launches():
     finally:
         P.set_kernel_timing(False)
     assert torch.equal(g1, g2) and torch.equal(g1, e1)
+
+
+def test_launch_shape_does_not_change_results():
+    """Grid sizes only spread tiles over workgroups: any shape gives the same bits."""
+    torch = _torch()
+    import paper_1712_02533_amd as P
+    s = make_series(SeriesSpec(8, 128, 4.0, 1.0, 10.0, 23))
+    frames = torch.tensor(s.frames, device="cuda")
+    params = _gpu_params(3, scan="brent_kung")
+    base = P.get_tuning()
+    u1, _, _ = P.prefix_register_series(frames, params=params)
+    try:
+        P.set_tuning(dict(grid_energy=333, grid_grad=97, grid_smooth=61, grid_prolong=5,
+                          pool_group=5))
+        say("series 8 x 128 with odd grid sizes", P.get_tuning())
+        u2, _, _ = P.prefix_register_series(frames, params=params)
+    finally:
+        P.set_tuning(base)
+    assert torch.equal(u1, u2)
+    with pytest.raises(P.PprsError):
+        P.set_tuning(dict(pool_group=-1))
