@@ -47,7 +47,6 @@ class _CSeriesStats(ctypes.Structure):
                 ("node_steps", ctypes.c_longlong), ("node_passes", ctypes.c_longlong)]
 
 
-@dataclass
 class _CTuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int) for n in ("pool_slots", "pool_group", "grid_energy",
                                             "grid_grad", "grid_smooth", "grid_prolong")]
@@ -56,6 +55,7 @@ class _CTuning(ctypes.Structure):
 TUNING_KEYS = [n for n, _ in _CTuning._fields_]
 
 
+@dataclass
 class Params:
     """Mirror of pprs_params; defaults are pprs_default_params()."""
     levels: int = 4
