@@ -137,6 +137,7 @@ def _lib():
                                                ctypes.POINTER(ctypes.c_int), i]),
                 "pprs_kernel_name": (ctypes.c_char_p, [i]),
                 "pprs_set_pool": (i, [vp, i, i]),
+                "pprs_set_metric_solve": (i, [vp, i]),
                 "pprs_get_tuning": (i, [vp, ctypes.POINTER(_CTuning)]),
                 "pprs_set_tuning": (i, [vp, ctypes.POINTER(_CTuning)]),
             }
@@ -310,6 +311,13 @@ def set_pool(slots: int = 0, group_steps: int = 0, device=None):
     _check(_lib().pprs_set_pool(_ctx(dev).handle, slots, group_steps))
 
 
+def set_metric_solve(mode: str = "auto", device=None):
+    """"auto": windowed one-pass metric solve where beta allows it; "exact": line solves."""
+    import torch
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    _check(_lib().pprs_set_metric_solve(_ctx(dev).handle, {"auto": 0, "exact": 1}[mode]))
+
+
 def get_tuning(device=None) -> dict:
     """Launch shape of the current stream's context (see pprs_tuning)."""
     import torch
@@ -337,7 +345,12 @@ def set_kernel_timing(enable: bool, device=None):
 
 def kernel_names():
     lib = _lib()
-    return [lib.pprs_kernel_name(k).decode() for k in range(8)]
+    names = []
+    while True:
+        nm = lib.pprs_kernel_name(len(names)).decode()
+        if nm == "unknown":
+            return names
+        names.append(nm)
 
 
 def kernel_timing(reset: bool = False, device=None):

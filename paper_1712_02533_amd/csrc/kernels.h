@@ -12,6 +12,8 @@ hipError_t smooth_fin(BatchDesc* d, int grid, hipStream_t st);
 hipError_t grad(BatchDesc* d, int grid, hipStream_t st);
 hipError_t smooth(BatchDesc* d, int dir, int grid, size_t lds_bytes, hipStream_t st);
 hipError_t set_smooth_lds(size_t bytes);
+// windowed metric solve (both axes in one launch); halo 16 or 24
+hipError_t smooth_win(BatchDesc* d, int halo, int grid, hipStream_t st);
 hipError_t restrict_planes(const float* src, long long s_outer, long long s_inner, float* dst,
                            long long d_outer, long long d_inner, int inner, int nf, int planes,
                            hipStream_t st);

@@ -99,7 +99,8 @@ __device__ __forceinline__ int kind_items(const BatchDesc* D, int kind, int l) {
     case WK_EVAL: return g.tiles_elem;
     case WK_LADDER: return g.tiles_elem;
     case WK_GRAD: return g.tiles_grad;
-    default: return 2 * g.sm_items;
+    case WK_SMY: return D->smooth_halo ? 0 : 2 * g.sm_items;
+    default: return D->smooth_halo ? 2 * g.sw_tiles * g.sw_tiles : 2 * g.sm_items;
   }
 }
 
@@ -923,6 +924,133 @@ __global__ void __launch_bounds__(BLOCK, 3) k_smooth(BatchDesc* D) {
   }
 }
 
+// Windowed metric solve: d = (S1^-1 (x) S1^-1) G for one SW_T x SW_T tile of one component in
+// one pass. The LU recurrences of S1 contract by a factor rho(beta) per node (0.35 for
+// beta = 1), so a node's solution depends on G within a few nodes only: each tile solves the
+// columns of its window (tile plus H nodes of halo on every side, clipped to the domain, with
+// the LU coefficients of the global rows) and then the rows of its output nodes. The host picks
+// H with rho^H below FP32 resolution; where the window reaches the domain edge the solve is the
+// exact one. Reads G once (halo re-reads hit the cache) and writes d: 16 B per node instead of
+// the 40 of two full passes through an intermediate. Partials: G.d and max |d| per tile.
+template <int H>
+__global__ void __launch_bounds__(SW_THREADS) k_smooth_win(BatchDesc* D) {
+  constexpr int WM = SW_T + 1 + 2 * H;  // largest window extent (last tile holds SW_T + 1)
+  constexpr int PITCH = WM + 1;
+  __shared__ float s[WM * PITCH];
+  __shared__ double s_red[2][SW_THREADS / 64];
+  __shared__ int s_pos;
+  const int tid = threadIdx.x;
+  ItemCursor c;
+  if (!cursor_begin(D, WK_SMX, c, &s_pos)) return;
+  for (; c.item < c.end; ++c.item) {
+    int sl, t;
+    cursor_slot(D, WK_SMX, c, sl, t);
+    const SlotState* stp = D->state + sl;
+    if (stp->phase != PH_GRAD) continue;
+    int l = stp->level;
+    int n = lvl_n(l);
+    size_t nn = (size_t)n * n;
+    const LevelGeom& g = D->geom[l];
+    int nt = g.sw_tiles;
+    int comp = t / (nt * nt), tile = t - comp * nt * nt;
+    int ty = tile / nt, tx = tile - ty * nt;
+    int oy0 = ty * SW_T, oy1 = ty == nt - 1 ? n : oy0 + SW_T;
+    int ox0 = tx * SW_T, ox1 = tx == nt - 1 ? n : ox0 + SW_T;
+    int wy0 = max(0, oy0 - H), wy1 = min(n, oy1 + H);
+    int wx0 = max(0, ox0 - H), wx1 = min(n, ox1 + H);
+    int hy = wy1 - wy0, hx = wx1 - wx0;
+    const float* G = D->gbuf + (size_t)sl * D->slot_f_stride + comp * nn;
+    float* dst = D->dbuf + (size_t)sl * D->slot_f_stride + comp * nn;
+    const float* ca = D->coef + g.coef_off;  // a_i
+    const float* ci = ca + n;                // 1 / den_i
+    const float* cp = ca + 2 * n;            // c'_i
+    __syncthreads();
+    for (int k = tid; k < hy * hx; k += SW_THREADS) {
+      int r = k / hx, q = k - r * hx;
+      s[r * PITCH + q] = G[(size_t)(wy0 + r) * n + wx0 + q];
+    }
+    __syncthreads();
+    if (tid < hx) {  // column tid of the window, rows wy0 .. wy1 - 1
+      float v[WM];
+#pragma unroll
+      for (int r = 0; r < WM; ++r) v[r] = r < hy ? s[r * PITCH + tid] : 0.f;
+      float y = 0.f;
+#pragma unroll
+      for (int r = 0; r < WM; ++r)
+        if (r < hy) {
+          int i = wy0 + r;
+          y = fmaf(ca[i], y, ci[i] * v[r]);
+          v[r] = y;
+        }
+      float x = 0.f;
+#pragma unroll
+      for (int r = WM - 1; r >= 0; --r)
+        if (r < hy) {
+          int i = wy0 + r;
+          x = fmaf(-cp[i], x, v[r]);
+          v[r] = x;
+        }
+#pragma unroll
+      for (int r = 0; r < WM; ++r)
+        if (r < hy) s[r * PITCH + tid] = v[r];
+    }
+    __syncthreads();
+    int rows = oy1 - oy0, cols = ox1 - ox0;
+    if (tid < rows) {  // output row tid, columns wx0 .. wx1 - 1
+      float* row = s + (oy0 - wy0 + tid) * PITCH;
+      float v[WM];
+#pragma unroll
+      for (int q = 0; q < WM; ++q) v[q] = q < hx ? row[q] : 0.f;
+      float y = 0.f;
+#pragma unroll
+      for (int q = 0; q < WM; ++q)
+        if (q < hx) {
+          int i = wx0 + q;
+          y = fmaf(ca[i], y, ci[i] * v[q]);
+          v[q] = y;
+        }
+      float x = 0.f;
+#pragma unroll
+      for (int q = WM - 1; q >= 0; --q)
+        if (q < hx) {
+          int i = wx0 + q;
+          x = fmaf(-cp[i], x, v[q]);
+          v[q] = x;
+        }
+#pragma unroll
+      for (int q = 0; q < WM; ++q)
+        if (q < hx) row[q] = v[q];
+    }
+    __syncthreads();
+    double gd = 0.0, dm = 0.0;
+    for (int k = tid; k < rows * cols; k += SW_THREADS) {
+      int j = k / cols, q = k - j * cols;
+      float xv = s[(oy0 - wy0 + j) * PITCH + (ox0 - wx0) + q];
+      size_t gi = (size_t)(oy0 + j) * n + ox0 + q;
+      dst[gi] = xv;
+      gd += (double)(G[gi] * xv);
+      dm = fmax(dm, (double)fabsf(xv));
+    }
+    gd = wave_sum(gd);
+    dm = wave_max(dm);
+    if ((tid & 63) == 0) {
+      s_red[0][tid >> 6] = gd;
+      s_red[1][tid >> 6] = dm;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double a = s_red[0][0], b = s_red[1][0];
+      for (int w = 1; w < SW_THREADS / 64; ++w) {
+        a += s_red[0][w];
+        b = fmax(b, s_red[1][w]);
+      }
+      double* pr = slot_partial(D, sl, WK_SMX, t);
+      pr[0] = a;
+      pr[1] = b;
+    }
+  }
+}
+
 // Per-slot finalisation of the metric solve: G.d, max |d|, step bound and first ladder top.
 __global__ void __launch_bounds__(BLOCK) k_smooth_fin(BatchDesc* D) {
   __shared__ double s_red[(BLOCK / 64) * 2];
@@ -934,11 +1062,11 @@ __global__ void __launch_bounds__(BLOCK) k_smooth_fin(BatchDesc* D) {
     int l = st.level;
     int n = lvl_n(l);
     double tot[2];
-    sum_partials<2>(D, s, WK_SMX, 2 * D->geom[l].sm_items, 2, tot, s_red, true);
+    sum_partials<2>(D, s, WK_SMX, kind_items(D, WK_SMX, l), 2, tot, s_red, true);
     if (threadIdx.x == 0) {
       long long* nc_s = D->node_count + (size_t)s * WK_COUNT;
       nc_s[WK_GRAD] += (long long)n * n;
-      nc_s[WK_SMY] += (long long)n * n;
+      if (!D->smooth_halo) nc_s[WK_SMY] += (long long)n * n;
       nc_s[WK_SMX] += (long long)n * n;
       st.ub ^= 1;          // the gradient kernel wrote u - tau_pend d to the other buffer
       st.tau_pend = 0.0;
@@ -1343,6 +1471,12 @@ hipError_t grad(BatchDesc* d, int grid, hipStream_t st) {
 hipError_t smooth(BatchDesc* d, int dir, int grid, size_t lds_bytes, hipStream_t st) {
   if (dir == 0) hipLaunchKernelGGL(k_smooth<0>, dim3(grid), dim3(SM_THREADS), lds_bytes, st, d);
   else hipLaunchKernelGGL(k_smooth<1>, dim3(grid), dim3(SM_THREADS), lds_bytes, st, d);
+  return hipGetLastError();
+}
+hipError_t smooth_win(BatchDesc* d, int halo, int grid, hipStream_t st) {
+  if (halo == 16) hipLaunchKernelGGL(k_smooth_win<16>, dim3(grid), dim3(SW_THREADS), 0, st, d);
+  else if (halo == 24) hipLaunchKernelGGL(k_smooth_win<24>, dim3(grid), dim3(SW_THREADS), 0, st, d);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 hipError_t set_smooth_lds(size_t bytes) {

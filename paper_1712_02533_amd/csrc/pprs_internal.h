@@ -34,6 +34,8 @@ enum { WK_PROLONG = 0, WK_EVAL = 1, WK_GRAD = 2, WK_SMY = 3, WK_SMX = 4, WK_LADD
 #define PT_Y 8
 // smoother: lines per workgroup, chosen per level so one strip stays under 40 KB of LDS
 #define SM_LDS_MAX_FLOATS 9728
+#define SW_T 64          // windowed metric solve: output nodes per tile along each axis
+#define SW_THREADS 128
 #define SM_THREADS 256
 #define BLOCK 256
 #define MAX_CAND 7      // 2K+1 with K <= 3
@@ -73,7 +75,7 @@ struct LevelGeom {
   int sm_lines;     // lines per smoother workgroup
   int sm_items;     // ceil(n / sm_lines) per component
   int coef_off;     // offset of this level's smoother coefficients
-  int pad;
+  int sw_tiles;     // windowed metric solve: tiles per axis (max(1, (n-1) / SW_T))
 };
 
 // Per-kind item list built by the planning kernel each step.
@@ -94,7 +96,7 @@ struct BatchDesc {
   double tau_min_rel;
   double eps;
   int iter_max;
-  int pad;
+  int smooth_halo;         // windowed metric solve halo in nodes; 0: exact two-pass line solves
   LevelGeom geom[PPRS_MAXL];
   // frames: normalised pyramids, frame f at level l: frames[l] + f * n_l^2
   float* frames[PPRS_MAXL];

@@ -71,11 +71,12 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
-enum { TK_PLAN = 0, TK_PROLONG, TK_EVAL, TK_GRAD, TK_SMY, TK_SMX, TK_LADDER, TK_FIN, TK_COUNT };
+enum { TK_PLAN = 0, TK_PROLONG, TK_EVAL, TK_GRAD, TK_SMY, TK_SMX, TK_LADDER, TK_FIN, TK_SMW,
+       TK_COUNT };
 const char* kTkName[TK_COUNT] = {"plan", "prolong", "energy_eval", "grad", "smooth_y",
-                                 "smooth_x", "energy_ladder", "finalize"};
+                                 "smooth_x", "energy_ladder", "finalize", "smooth_window"};
 // algorithmic HBM bytes per grid node (both displacement components) of one launch per kind
-const double kBytesPerNode[TK_COUNT] = {0.0, 12.0, 16.0, 40.0, 16.0, 24.0, 24.0, 0.0};
+const double kBytesPerNode[TK_COUNT] = {0.0, 12.0, 16.0, 40.0, 16.0, 24.0, 24.0, 0.0, 16.0};
 
 int level_n(int l) { return (1 << l) + 1; }
 
@@ -104,6 +105,7 @@ struct pprs_ctx {
   int pool_slots = 512;  // concurrent registrations of a series
   // workgroups of the per-step item kernels (results do not depend on them)
   int grid_energy = 2048, grid_grad = 2048, grid_smooth = 1024, grid_prolong = 2048;
+  bool smooth_window = true;  // windowed one-pass metric solve where beta allows it
   BatchDesc hd;
   int slots_cap = 0, slots_L = -1, slots_m0 = -1;
   double coef_beta = -1.0;
@@ -184,7 +186,7 @@ void fill_geom(LevelGeom& g, int l, int coef_off) {
   g.sm_lines = lines;
   g.sm_items = (n + lines - 1) / lines;
   g.coef_off = coef_off;
-  g.pad = 0;
+  g.sw_tiles = std::max(1, (n - 1) / SW_T);
 }
 
 size_t smooth_lds_bytes(const BatchDesc& hd) {
@@ -197,6 +199,23 @@ size_t smooth_lds_bytes(const BatchDesc& hd) {
     mx = std::max(mx, std::max(a, b));
   }
   return mx * sizeof(float);
+}
+
+// Halo of the windowed metric solve for beta: the LU recurrences of S1 = M1 + (beta h)^2 K1
+// contract by rho per node, the smaller root of r^2 - q r + 1 with q = |diag / offdiag| =
+// (2/3 + 2 beta^2) / |1/6 - beta^2| (h cancels). The smallest compiled halo H with
+// rho^H <= 2^-24 (FP32 resolution) is used; 0 selects the exact two-pass line solves.
+int window_halo(double beta) {
+  double di = 2.0 / 3.0 + 2.0 * beta * beta, o = fabs(1.0 / 6.0 - beta * beta);
+  double rho = 0.0;
+  if (o > 0.0) {
+    double q = di / o;
+    rho = 0.5 * (q - sqrt(q * q - 4.0));
+  }
+  const double eps = ldexp(1.0, -24);
+  for (int h : {16, 24})
+    if (pow(rho, h) <= eps) return h;
+  return 0;
 }
 
 // Workspace for up to `cap` slots on levels m0..L, and the metric coefficients for beta.
@@ -216,6 +235,7 @@ pprs_status ensure_slots(pprs_ctx* c, int cap, int L, int m0, double beta) {
       hd.u_off[l] = uoff;
       uoff += 4LL * hd.geom[l].n * hd.geom[l].n;
       max_items = std::max(max_items, std::max(hd.geom[l].tiles_elem, 2 * hd.geom[l].sm_items));
+      max_items = std::max(max_items, 2 * hd.geom[l].sw_tiles * hd.geom[l].sw_tiles);
     }
     int nL = level_n(L);
     hd.slot_u_stride = uoff;
@@ -283,6 +303,7 @@ pprs_status ensure_slots(pprs_ctx* c, int cap, int L, int m0, double beta) {
     }
     HIPCHK(hipMemcpy(c->coef.p, host.data(), host.size() * sizeof(float),
                      hipMemcpyHostToDevice));
+    hd.smooth_halo = c->smooth_window ? window_halo(beta) : 0;
     c->coef_beta = beta;
     c->coef_L = L;
     c->coef_m0 = m0;
@@ -394,8 +415,12 @@ pprs_status launch_step(pprs_ctx* c, BatchDesc* d, int ladder_k, size_t lds) {
   TIMED(TK_EVAL, pprs_k::energy(d, 0, ladder_k, c->grid_energy, c->stream));
   TIMED(TK_FIN, pprs_k::energy_fin(d, 0, ladder_k, kGridFin, c->stream));
   TIMED(TK_GRAD, pprs_k::grad(d, c->grid_grad, c->stream));
-  TIMED(TK_SMY, pprs_k::smooth(d, 0, c->grid_smooth, lds, c->stream));
-  TIMED(TK_SMX, pprs_k::smooth(d, 1, c->grid_smooth, lds, c->stream));
+  if (c->hd.smooth_halo) {
+    TIMED(TK_SMW, pprs_k::smooth_win(d, c->hd.smooth_halo, c->grid_smooth, c->stream));
+  } else {
+    TIMED(TK_SMY, pprs_k::smooth(d, 0, c->grid_smooth, lds, c->stream));
+    TIMED(TK_SMX, pprs_k::smooth(d, 1, c->grid_smooth, lds, c->stream));
+  }
   TIMED(TK_FIN, pprs_k::smooth_fin(d, kGridFin, c->stream));
   TIMED(TK_LADDER, pprs_k::energy(d, 1, ladder_k, c->grid_energy, c->stream));
   TIMED(TK_FIN, pprs_k::energy_fin(d, 1, ladder_k, kGridFin, c->stream));
@@ -1179,6 +1204,18 @@ pprs_status pprs_prefix_register_series(pprs_ctx* c, const float* frames, int N,
   return status_from_flags(flags);
 }
 
+pprs_status pprs_set_metric_solve(pprs_ctx* c, int mode) {
+  if (!c) return fail(PPRS_EINVAL, "ctx is NULL");
+  if (mode != PPRS_METRIC_AUTO && mode != PPRS_METRIC_EXACT)
+    return fail(PPRS_EINVAL, "unknown metric-solve mode %d", mode);
+  bool w = mode == PPRS_METRIC_AUTO;
+  if (w != c->smooth_window) {
+    c->smooth_window = w;
+    c->coef_beta = -1.0;  // recompute the coefficients and the halo on the next call
+  }
+  return PPRS_OK;
+}
+
 pprs_status pprs_get_tuning(pprs_ctx* c, pprs_tuning* t) {
   if (!c || !t) return fail(PPRS_EINVAL, "NULL argument");
   t->pool_slots = c->pool_slots;
@@ -1294,11 +1331,15 @@ pprs_status pprs_get_kernel_timing(pprs_ctx* c, double* ms, long long* launches,
   if (n_kinds) *n_kinds = TK_COUNT;
   // node counts per work kind -> bytes per timing kind
   const int wk_of_tk[TK_COUNT] = {-1, WK_PROLONG, WK_EVAL, WK_GRAD, WK_SMY, WK_SMX, WK_LADDER,
-                                  -1};
+                                  -1, WK_SMX};
   for (int k = 0; k < TK_COUNT && k < cap; ++k) {
     if (ms) ms[k] = c->t_ms[k];
     if (launches) launches[k] = c->t_launch[k];
-    if (bytes) bytes[k] = wk_of_tk[k] < 0 ? 0.0 : kBytesPerNode[k] * c->nodes_acc[wk_of_tk[k]];
+    // the metric solve counts its nodes under WK_SMX in both forms: bytes go to the form
+    // that ran
+    if (bytes)
+      bytes[k] = wk_of_tk[k] < 0 || c->t_launch[k] == 0
+                     ? 0.0 : kBytesPerNode[k] * c->nodes_acc[wk_of_tk[k]];
   }
   if (reset) {
     for (int k = 0; k < TK_COUNT; ++k) {

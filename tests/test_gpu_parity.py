@@ -230,3 +230,28 @@ def test_launch_shape_does_not_change_results():
     assert torch.equal(u1, u2)
     with pytest.raises(P.PprsError):
         P.set_tuning(dict(pool_group=-1))
+
+
+def test_windowed_metric_solve_matches_exact_line_solves():
+    """The one-pass windowed metric solve (halo chosen from beta) against the exact two-pass
+    line solves on the same series: FP32-rounding-level differences, the same decisions on
+    (nearly) every application, and both within the oracle bar of each other."""
+    torch = _torch()
+    import paper_1712_02533_amd as P
+    s = make_series(SeriesSpec(10, 256, 4.0, 1.0, 10.0, 24))
+    frames = torch.tensor(s.frames, device="cuda")
+    params = _gpu_params(3, scan="brent_kung")
+    P.set_metric_solve("exact")
+    try:
+        say("series 10 x 256, exact line solves")
+        ue, _, oe = P.prefix_register_series(frames, params=params, want_op_stats=True)
+    finally:
+        P.set_metric_solve("auto")
+    say("series 10 x 256, windowed metric solve")
+    uw, _, ow = P.prefix_register_series(frames, params=params, want_op_stats=True)
+    same = sum(1 for a, b in zip(oe, ow) if a.iters == b.iters)
+    d = (uw - ue).abs()
+    say("  identical decisions on %d of %d applications, max %.2e px" % (same, len(oe),
+                                                                        float(d.max())))
+    assert same >= len(oe) - 1
+    assert float(d.pow(2).mean().sqrt()) < 1e-4 and float(d.max()) < 0.05
