@@ -168,6 +168,8 @@ typedef struct {
   int grid_grad;     /* workgroups of the gradient kernel (default 2048) */
   int grid_smooth;   /* workgroups of the metric-solve kernels (default 1024) */
   int grid_prolong;  /* workgroups of the prolongation kernel (default 2048) */
+  int tile_grad;     /* gradient tile shape: 0 = 32x16 (default), 1 = 64x8, 2 = 128x4,
+                        3 = 64x16 nodes */
 } pprs_tuning;
 
 /* Reads / replaces the launch shape of ctx (host struct). PPRS_EINVAL for out-of-range

@@ -16,6 +16,7 @@ import os
 import time
 
 CANDIDATES = {
+    "tile_grad": [1, 2, 3, 0],
     "pool_group": [4, 8, 16, 32],
     "grid_grad": [1024, 2048, 4096],
     "grid_energy": [1024, 2048, 4096],

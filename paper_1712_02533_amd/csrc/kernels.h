@@ -9,7 +9,9 @@ hipError_t prolong(BatchDesc* d, int grid, hipStream_t st);
 hipError_t energy(BatchDesc* d, int mode, int ladder_k, int grid, hipStream_t st);
 hipError_t energy_fin(BatchDesc* d, int mode, int ladder_k, int grid, hipStream_t st);
 hipError_t smooth_fin(BatchDesc* d, int grid, hipStream_t st);
-hipError_t grad(BatchDesc* d, int grid, hipStream_t st);
+// gradient tile variants: 0 = 32x16, 1 = 64x8, 2 = 128x4, 3 = 64x16 nodes
+void grad_tile(int variant, int* tx, int* ty);
+hipError_t grad(BatchDesc* d, int variant, int grid, hipStream_t st);
 hipError_t smooth(BatchDesc* d, int dir, int grid, size_t lds_bytes, hipStream_t st);
 hipError_t set_smooth_lds(size_t bytes);
 // windowed metric solve (both axes in one launch); halo 16 or 24

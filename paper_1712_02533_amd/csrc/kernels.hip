@@ -558,7 +558,11 @@ __global__ void __launch_bounds__(BLOCK) k_energy_fin(BatchDesc* D) {
 //       sum_q psi_i(q) f_q grad T(q + u(q)) + lambda (K_e u_e)_i,
 //       f_q = -w (R~(q) - NCC (T(q) - mean) / sigma) / sigma.
 
+// Tile shape TX x TY nodes (a launch-shape choice: every node's G is the same sum of the same
+// element terms whatever the tile, so the shape never changes a result).
+template <int TX, int TY>
 __global__ void __launch_bounds__(BLOCK, 4) k_grad(BatchDesc* D) {
+  constexpr int GT_X = TX, GT_Y = TY;
   constexpr int NX = GT_X + 2, NY = GT_Y + 2;       // staged nodes
   constexpr int EX = GT_X + 1, EY = GT_Y + 1;       // elements touching the tile
   __shared__ float s_ux[NX * NY], s_uy[NX * NY], s_r[NX * NY];
@@ -1464,8 +1468,19 @@ hipError_t smooth_fin(BatchDesc* d, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_smooth_fin, dim3(grid), dim3(BLOCK), 0, st, d);
   return hipGetLastError();
 }
-hipError_t grad(BatchDesc* d, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_grad, dim3(grid), dim3(BLOCK), 0, st, d);
+const int kGradTiles[4][2] = {{32, 16}, {64, 8}, {128, 4}, {64, 16}};
+void grad_tile(int variant, int* tx, int* ty) {
+  if (variant < 0 || variant > 3) variant = 0;
+  *tx = kGradTiles[variant][0];
+  *ty = kGradTiles[variant][1];
+}
+hipError_t grad(BatchDesc* d, int variant, int grid, hipStream_t st) {
+  switch (variant) {
+    case 1: hipLaunchKernelGGL((k_grad<64, 8>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    case 2: hipLaunchKernelGGL((k_grad<128, 4>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    case 3: hipLaunchKernelGGL((k_grad<64, 16>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    default: hipLaunchKernelGGL((k_grad<32, 16>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+  }
   return hipGetLastError();
 }
 hipError_t smooth(BatchDesc* d, int dir, int grid, size_t lds_bytes, hipStream_t st) {

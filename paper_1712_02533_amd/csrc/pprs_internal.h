@@ -26,8 +26,6 @@ enum { WK_PROLONG = 0, WK_EVAL = 1, WK_GRAD = 2, WK_SMY = 3, WK_SMX = 4, WK_LADD
        WK_COUNT = 6 };
 
 // Tile geometry (compile-time).
-#define GT_X 32   // gradient kernel: nodes per tile along x
-#define GT_Y 16   //                  nodes per tile along y
 #define ET_X 64   // energy kernel: elements per tile along x
 #define ET_Y 16   //                elements per tile along y
 #define PT_X 64   // prolongation: fine nodes per tile along x
@@ -69,7 +67,7 @@ struct SlotState {
 // Geometry of one level (host-filled, device-read).
 struct LevelGeom {
   int n;
-  int tiles_grad;   // ceil(n/GT_X) * ceil(n/GT_Y)
+  int tiles_grad;   // gradient tiles of the chosen tile shape (tile_grad variant)
   int tiles_elem;   // ceil((n-1)/ET_X) * ceil((n-1)/ET_Y)
   int tiles_prol;   // ceil(n/PT_X) * ceil(n/PT_Y) (fine-level tiles when this is the target)
   int sm_lines;     // lines per smoother workgroup

@@ -106,6 +106,7 @@ struct pprs_ctx {
   // workgroups of the per-step item kernels (results do not depend on them)
   int grid_energy = 2048, grid_grad = 2048, grid_smooth = 1024, grid_prolong = 2048;
   bool smooth_window = true;  // windowed one-pass metric solve where beta allows it
+  int tile_grad = 0;          // gradient kernel tile shape (pprs_k::grad_tile variant)
   BatchDesc hd;
   int slots_cap = 0, slots_L = -1, slots_m0 = -1;
   double coef_beta = -1.0;
@@ -178,7 +179,7 @@ int frame_level(int H, int W) {
 void fill_geom(LevelGeom& g, int l, int coef_off) {
   int n = level_n(l);
   g.n = n;
-  g.tiles_grad = ((n + GT_X - 1) / GT_X) * ((n + GT_Y - 1) / GT_Y);
+  g.tiles_grad = 0;  // set per run from the gradient tile shape (set_grad_tiles)
   g.tiles_elem = ((n - 1 + ET_X - 1) / ET_X) * ((n - 1 + ET_Y - 1) / ET_Y);
   g.tiles_prol = ((n + PT_X - 1) / PT_X) * ((n + PT_Y - 1) / PT_Y);
   int lines = 32;
@@ -199,6 +200,17 @@ size_t smooth_lds_bytes(const BatchDesc& hd) {
     mx = std::max(mx, std::max(a, b));
   }
   return mx * sizeof(float);
+}
+
+// Gradient tiles per level for the context's tile shape (before each batch is uploaded).
+void set_grad_tiles(pprs_ctx* c) {
+  int tx, ty;
+  pprs_k::grad_tile(c->tile_grad, &tx, &ty);
+  BatchDesc& hd = c->hd;
+  for (int l = hd.coarsest; l <= hd.finest; ++l) {
+    int n = level_n(l);
+    hd.geom[l].tiles_grad = ((n + tx - 1) / tx) * ((n + ty - 1) / ty);
+  }
 }
 
 // Halo of the windowed metric solve for beta: the LU recurrences of S1 = M1 + (beta h)^2 K1
@@ -414,7 +426,7 @@ pprs_status launch_step(pprs_ctx* c, BatchDesc* d, int ladder_k, size_t lds) {
   TIMED(TK_PROLONG, pprs_k::prolong(d, c->grid_prolong, c->stream));
   TIMED(TK_EVAL, pprs_k::energy(d, 0, ladder_k, c->grid_energy, c->stream));
   TIMED(TK_FIN, pprs_k::energy_fin(d, 0, ladder_k, kGridFin, c->stream));
-  TIMED(TK_GRAD, pprs_k::grad(d, c->grid_grad, c->stream));
+  TIMED(TK_GRAD, pprs_k::grad(d, c->tile_grad, c->grid_grad, c->stream));
   if (c->hd.smooth_halo) {
     TIMED(TK_SMW, pprs_k::smooth_win(d, c->hd.smooth_halo, c->grid_smooth, c->stream));
   } else {
@@ -450,6 +462,7 @@ pprs_status run_batch(pprs_ctx* c, int n, const int* ref, const int* tmpl, InitK
   hd.tau_min_rel = p->tau_min_rel;
   hd.eps = p->eps;
   hd.iter_max = p->iter_max;
+  set_grad_tiles(c);
   BatchDesc* d = P<BatchDesc>(c->desc);
   HIPCHK(hipMemcpyAsync(d, &hd, sizeof(BatchDesc), hipMemcpyHostToDevice, c->stream));
   if (start < m0 || start > L) start = m0;
@@ -674,6 +687,7 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf, 
   hd.tau_min_rel = p->tau_min_rel;
   hd.eps = p->eps;
   hd.iter_max = p->iter_max;
+  set_grad_tiles(c);
   BatchDesc* d = P<BatchDesc>(c->desc);
   HIPCHK(hipMemcpyAsync(d, &hd, sizeof(BatchDesc), hipMemcpyHostToDevice, c->stream));
   // dependencies: producers are the ops whose out is read
@@ -1224,15 +1238,16 @@ pprs_status pprs_get_tuning(pprs_ctx* c, pprs_tuning* t) {
   t->grid_grad = c->grid_grad;
   t->grid_smooth = c->grid_smooth;
   t->grid_prolong = c->grid_prolong;
+  t->tile_grad = c->tile_grad;
   return PPRS_OK;
 }
 
 pprs_status pprs_set_tuning(pprs_ctx* c, const pprs_tuning* t) {
   if (!c || !t) return fail(PPRS_EINVAL, "NULL argument");
-  const int v[6] = {t->pool_slots, t->pool_group, t->grid_energy, t->grid_grad, t->grid_smooth,
-                    t->grid_prolong};
-  const int hi[6] = {65536, 1024, 65536, 65536, 65536, 65536};
-  for (int k = 0; k < 6; ++k)
+  const int v[7] = {t->pool_slots, t->pool_group, t->grid_energy, t->grid_grad, t->grid_smooth,
+                    t->grid_prolong, t->tile_grad};
+  const int hi[7] = {65536, 1024, 65536, 65536, 65536, 65536, 3};
+  for (int k = 0; k < 7; ++k)
     if (v[k] < 0 || v[k] > hi[k]) return fail(PPRS_EINVAL, "tuning value %d out of range", k);
   c->pool_slots = t->pool_slots ? t->pool_slots : 512;
   c->pool_group = t->pool_group ? t->pool_group : 8;
@@ -1240,6 +1255,7 @@ pprs_status pprs_set_tuning(pprs_ctx* c, const pprs_tuning* t) {
   c->grid_grad = t->grid_grad ? t->grid_grad : 2048;
   c->grid_smooth = t->grid_smooth ? t->grid_smooth : 1024;
   c->grid_prolong = t->grid_prolong ? t->grid_prolong : 2048;
+  c->tile_grad = t->tile_grad;
   return PPRS_OK;
 }
 

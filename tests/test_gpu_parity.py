@@ -212,7 +212,8 @@ def test_series_graph_replay_matches_eager_launches():
 
 
 def test_launch_shape_does_not_change_results():
-    """Grid sizes only spread tiles over workgroups: any shape gives the same bits."""
+    """Grid sizes only spread tiles over workgroups and the gradient tile shape only regroups
+    the same per-node sums: any shape gives the same bits."""
     torch = _torch()
     import paper_1712_02533_amd as P
     s = make_series(SeriesSpec(8, 128, 4.0, 1.0, 10.0, 23))
@@ -222,7 +223,7 @@ def test_launch_shape_does_not_change_results():
     u1, _, _ = P.prefix_register_series(frames, params=params)
     try:
         P.set_tuning(dict(grid_energy=333, grid_grad=97, grid_smooth=61, grid_prolong=5,
-                          pool_group=5))
+                          pool_group=5, tile_grad=2))
         say("series 8 x 128 with odd grid sizes", P.get_tuning())
         u2, _, _ = P.prefix_register_series(frames, params=params)
     finally:
