@@ -148,13 +148,14 @@ pprs_status pprs_prefix_register_series(pprs_ctx* ctx, const float* frames, int 
    Returns PPRS_EINVAL for values out of range (slots > 65536, group_steps > 1024). */
 pprs_status pprs_set_pool(pprs_ctx* ctx, int slots, int group_steps);
 
-/* Metric solve d = A^-1 G, A = S1 (x) S1 (section "Gradient flow"). AUTO: one windowed pass
-   per step when beta allows it (the LU recurrences of S1 contract so fast that a tile plus a
-   halo of 16 or 24 nodes reproduces the full line solves to FP32 resolution; beta up to about
-   1.6), else the exact two-pass line solves. EXACT: always the two-pass line solves. The two
+/* Metric solve d = A^-1 G, A = S1 (x) S1 (section "Gradient flow"). EXACT (default): two
+   passes of line solves (columns, then rows). WINDOW: one windowed pass per step where beta
+   allows it (the LU recurrences of S1 contract so fast that a 64x64 tile plus a halo of 16 or 24
+   nodes reproduces the line solves to FP32 resolution; beta up to about 1.4), else EXACT. WINDOW
+   moves 16 instead of 40 bytes per node but, VALU-latency bound, runs slower on gfx950. The two
    differ by FP32 rounding only. PPRS_EINVAL for another mode. */
-#define PPRS_METRIC_AUTO 0
-#define PPRS_METRIC_EXACT 1
+#define PPRS_METRIC_EXACT 0
+#define PPRS_METRIC_WINDOW 1
 pprs_status pprs_set_metric_solve(pprs_ctx* ctx, int mode);
 
 /* Launch shape of the registration kernels; 0 selects the default. Every value only changes

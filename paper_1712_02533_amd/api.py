@@ -312,11 +312,12 @@ def set_pool(slots: int = 0, group_steps: int = 0, device=None):
     _check(_lib().pprs_set_pool(_ctx(dev).handle, slots, group_steps))
 
 
-def set_metric_solve(mode: str = "auto", device=None):
-    """"auto": windowed one-pass metric solve where beta allows it; "exact": line solves."""
+def set_metric_solve(mode: str = "exact", device=None):
+    """"exact": two passes of line solves (default); "window": one windowed pass where beta
+    allows it."""
     import torch
     dev = device or torch.device("cuda", torch.cuda.current_device())
-    _check(_lib().pprs_set_metric_solve(_ctx(dev).handle, {"auto": 0, "exact": 1}[mode]))
+    _check(_lib().pprs_set_metric_solve(_ctx(dev).handle, {"exact": 0, "window": 1}[mode]))
 
 
 def get_tuning(device=None) -> dict:

@@ -105,7 +105,7 @@ struct pprs_ctx {
   int pool_slots = 512;  // concurrent registrations of a series
   // workgroups of the per-step item kernels (results do not depend on them)
   int grid_energy = 2048, grid_grad = 2048, grid_smooth = 1024, grid_prolong = 2048;
-  bool smooth_window = true;  // windowed one-pass metric solve where beta allows it
+  bool smooth_window = false;  // windowed one-pass metric solve (opt-in, where beta allows)
   int tile_grad = 0;          // gradient kernel tile shape (pprs_k::grad_tile variant)
   BatchDesc hd;
   int slots_cap = 0, slots_L = -1, slots_m0 = -1;
@@ -1220,9 +1220,9 @@ pprs_status pprs_prefix_register_series(pprs_ctx* c, const float* frames, int N,
 
 pprs_status pprs_set_metric_solve(pprs_ctx* c, int mode) {
   if (!c) return fail(PPRS_EINVAL, "ctx is NULL");
-  if (mode != PPRS_METRIC_AUTO && mode != PPRS_METRIC_EXACT)
+  if (mode != PPRS_METRIC_EXACT && mode != PPRS_METRIC_WINDOW)
     return fail(PPRS_EINVAL, "unknown metric-solve mode %d", mode);
-  bool w = mode == PPRS_METRIC_AUTO;
+  bool w = mode == PPRS_METRIC_WINDOW;
   if (w != c->smooth_window) {
     c->smooth_window = w;
     c->coef_beta = -1.0;  // recompute the coefficients and the halo on the next call

@@ -242,14 +242,14 @@ def test_windowed_metric_solve_matches_exact_line_solves():
     s = make_series(SeriesSpec(10, 256, 4.0, 1.0, 10.0, 24))
     frames = torch.tensor(s.frames, device="cuda")
     params = _gpu_params(3, scan="brent_kung")
-    P.set_metric_solve("exact")
+    say("series 10 x 256, exact line solves")
+    ue, _, oe = P.prefix_register_series(frames, params=params, want_op_stats=True)
+    P.set_metric_solve("window")
     try:
-        say("series 10 x 256, exact line solves")
-        ue, _, oe = P.prefix_register_series(frames, params=params, want_op_stats=True)
+        say("series 10 x 256, windowed metric solve")
+        uw, _, ow = P.prefix_register_series(frames, params=params, want_op_stats=True)
     finally:
-        P.set_metric_solve("auto")
-    say("series 10 x 256, windowed metric solve")
-    uw, _, ow = P.prefix_register_series(frames, params=params, want_op_stats=True)
+        P.set_metric_solve("exact")
     same = sum(1 for a, b in zip(oe, ow) if a.iters == b.iters)
     d = (uw - ue).abs()
     say("  identical decisions on %d of %d applications, max %.2e px" % (same, len(oe),
