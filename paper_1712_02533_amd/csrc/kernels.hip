@@ -24,6 +24,17 @@ __constant__ float c_gp[2] = {0.21132486540518711775f, 0.78867513459481288225f};
 
 __device__ __forceinline__ int lvl_n(int l) { return (1 << l) + 1; }
 
+typedef float f32x2u __attribute__((ext_vector_type(2), aligned(4)));
+
+// Global-address-space access. Pointers read out of the batch descriptor are generic to the
+// compiler, which then emits flat loads: those also count against the LDS counter, so every
+// wait for a gather drained the LDS traffic too. All device buffers here are global memory.
+#define GAS __attribute__((address_space(1)))
+__device__ __forceinline__ float gld(const float* p, size_t i) {
+  return ((const GAS float*)p)[i];
+}
+__device__ __forceinline__ void gst(float* p, size_t i, float v) { ((GAS float*)p)[i] = v; }
+
 // Clamped bilinear sample of nodal g (n x n) at column bi + tx, row ai + ty (cells).
 // Returns value; writes the gradient in domain units when grad is true.
 template <bool GRAD>
@@ -38,8 +49,11 @@ __device__ __forceinline__ float sample_bil(const float* __restrict__ g, int n, 
   else if (b0 >= n - 1) { outx = (b0 > n - 1) || (fx > 0.f); b0 = n - 2; fx = 1.f; }
   if (a0 < 0) { a0 = 0; fy = 0.f; outy = true; }
   else if (a0 >= n - 1) { outy = (a0 > n - 1) || (fy > 0.f); a0 = n - 2; fy = 1.f; }
-  const float* p = g + (size_t)a0 * n + b0;
-  float v00 = p[0], v01 = p[1], v10 = p[n], v11 = p[n + 1];
+  const GAS float* p = (const GAS float*)g + (size_t)a0 * n + b0;
+  // the two corners of a row in one 8-byte load (rows are only 4-byte aligned)
+  f32x2u r0 = *reinterpret_cast<const GAS f32x2u*>(p);
+  f32x2u r1 = *reinterpret_cast<const GAS f32x2u*>(p + n);
+  float v00 = r0.x, v01 = r0.y, v10 = r1.x, v11 = r1.y;
   float top = fmaf(fx, v01 - v00, v00);
   float bot = fmaf(fx, v11 - v10, v10);
   if (GRAD) {
@@ -446,12 +460,12 @@ __global__ void __launch_bounds__(BLOCK, 4) k_energy(BatchDesc* D) {
       float ux = 0.f, uy = 0.f, dx = 0.f, dy = 0.f, r = 0.f;
       if (a < n && b < n) {
         size_t i = (size_t)a * n + b;
-        ux = u[i];
-        uy = u[nn + i];
-        r = R[i];
+        ux = gld(u, i);
+        uy = gld(u, nn + i);
+        r = gld(R, i);
         if (MODE) {
-          dx = d[i];
-          dy = d[nn + i];
+          dx = gld(d, i);
+          dy = gld(d, nn + i);
         }
       }
       s_ux[k] = ux;
@@ -599,13 +613,13 @@ __global__ void __launch_bounds__(BLOCK, 4) k_grad(BatchDesc* D) {
       float ux = 0.f, uy = 0.f, r = 0.f;
       if (a >= 0 && a < n && b >= 0 && b < n) {
         size_t i = (size_t)a * n + b;
-        ux = u[i];
-        uy = u[nn + i];
+        ux = gld(u, i);
+        uy = gld(u, nn + i);
         if (tau != 0.f) {
-          ux -= tau * d[i];
-          uy -= tau * d[nn + i];
+          ux -= tau * gld(d, i);
+          uy -= tau * gld(d, nn + i);
         }
-        r = R[i];
+        r = gld(R, i);
       }
       s_ux[k] = ux;
       s_uy[k] = uy;
@@ -670,10 +684,10 @@ __global__ void __launch_bounds__(BLOCK, 4) k_grad(BatchDesc* D) {
       float gy = (s_c[7][e11] + s_c[5][e10]) + (s_c[3][e01] + s_c[1][e00]);
       size_t i = (size_t)a * n + b;
       int kn = (ty + 1) * NX + tx + 1;
-      G[i] = gx;
-      G[nn + i] = gy;
-      un[i] = s_ux[kn];
-      un[nn + i] = s_uy[kn];
+      gst(G, i, gx);
+      gst(G, nn + i, gy);
+      gst(un, i, s_ux[kn]);
+      gst(un, nn + i, s_uy[kn]);
     }
     __syncthreads();
   }
@@ -691,9 +705,9 @@ __global__ void __launch_bounds__(BLOCK, 4) k_grad(BatchDesc* D) {
 template <int R, int C>
 __device__ __forceinline__ void solve_lines(float (&v)[R][C], int n, int lane,
                                             const float* __restrict__ coef) {
-  const float* ca = coef;            // a_i
-  const float* ci = coef + n;        // 1 / den_i
-  const float* cp = coef + 2 * n;    // c'_i
+  const GAS float* ca = (const GAS float*)coef;  // a_i
+  const GAS float* ci = ca + n;                   // 1 / den_i
+  const GAS float* cp = ca + 2 * n;               // c'_i
   int base = lane * C;
   float A[R], B[R];
 #pragma unroll
@@ -814,7 +828,7 @@ __device__ void smooth_item(const float* src, float* dst, const float* Gp, const
     int pitch = SL + 1;
     for (int k = threadIdx.x; k < n * SL; k += BLOCK) {
       int i = k / SL, L = k - i * SL;
-      s_buf[i * pitch + L] = L < nl ? src[(size_t)i * n + line0 + L] : 0.f;
+      s_buf[i * pitch + L] = L < nl ? gld(src, (size_t)i * n + line0 + L) : 0.f;
     }
     __syncthreads();
     for (int g = wv * R; g < nl; g += R * NW) {
@@ -837,7 +851,7 @@ __device__ void smooth_item(const float* src, float* dst, const float* Gp, const
     __syncthreads();
     for (int k = threadIdx.x; k < n * SL; k += BLOCK) {
       int i = k / SL, L = k - i * SL;
-      if (L < nl) dst[(size_t)i * n + line0 + L] = s_buf[i * pitch + L];
+      if (L < nl) gst(dst, (size_t)i * n + line0 + L, s_buf[i * pitch + L]);
     }
   } else {
     // each wave stages R rows in its own LDS area (row pitch 64 C + 1)
@@ -847,7 +861,7 @@ __device__ void smooth_item(const float* src, float* dst, const float* Gp, const
       int nr = min(R, nl - g);
       for (int r = 0; r < nr; ++r) {
         const float* sr = src + (size_t)(line0 + g + r) * n;
-        for (int i = lane; i < n; i += 64) rows[r * pitch + i] = sr[i];
+        for (int i = lane; i < n; i += 64) rows[r * pitch + i] = gld(sr, i);
       }
       wave_sync();
 #pragma unroll
@@ -872,8 +886,8 @@ __device__ void smooth_item(const float* src, float* dst, const float* Gp, const
         const float* gr = Gp + (size_t)(line0 + g + r) * n;
         for (int i = lane; i < n; i += 64) {
           float x = rows[r * pitch + i];
-          dr[i] = x;
-          gd += (double)(gr[i] * x);
+          gst(dr, i, x);
+          gd += (double)(gld(gr, i) * x);
           dm = fmax(dm, (double)fabsf(x));
         }
       }
