@@ -178,6 +178,21 @@ typedef struct {
 pprs_status pprs_get_tuning(pprs_ctx* ctx, pprs_tuning* t);
 pprs_status pprs_set_tuning(pprs_ctx* ctx, const pprs_tuning* t);
 
+/* Several independent series in one run (segmented scan): series j has N[j] frames of
+   side[j] x side[j] (each 2^L or 2^L+1, L may differ between series) at frames[j] (device) and
+   receives u_out[j] ([N[j]][2][side][side], as pprs_prefix_register_series). All neighbour
+   registrations and B applications of all series share one slot pool (pprs_set_pool), so a
+   short series does not wait for a long one and no series waits at another's scan levels.
+   params apply to every series; levels (host, S entries, or NULL for params->levels) gives
+   each series' level count (<= its L). stats (S entries) and latency_ms (S entries: from the
+   start of the call to the series' last result) are host arrays or NULL. Each series' result
+   equals its pprs_prefix_register_series result bit for bit. The warm start, when enabled,
+   applies to every series with m0 <= 7 <= L. Host arrays: frames, N, side, levels, u_out. */
+pprs_status pprs_register_series_batch(pprs_ctx* ctx, int S, const float* const* frames,
+                                       const int* N, const int* side, const int* levels,
+                                       float* const* u_out, const pprs_params* params,
+                                       pprs_series_stats* stats, double* latency_ms);
+
 /* Host-only: the scan schedule over M = N-1 elements (algorithms "serial" and "brent_kung").
    ops (host, capacity `cap` triples) receives (left, right, level) per B application in
    execution order: x[right] <- x[left] (.) x[right]; ops of one level are independent.

@@ -139,6 +139,13 @@ def _lib():
                 "pprs_kernel_name": (ctypes.c_char_p, [i]),
                 "pprs_set_pool": (i, [vp, i, i]),
                 "pprs_set_metric_solve": (i, [vp, i]),
+                "pprs_register_series_batch": (i, [vp, i, ctypes.POINTER(vp),
+                                                   ctypes.POINTER(ctypes.c_int),
+                                                   ctypes.POINTER(ctypes.c_int),
+                                                   ctypes.POINTER(ctypes.c_int),
+                                                   ctypes.POINTER(vp), ctypes.POINTER(_CParams),
+                                                   ctypes.POINTER(_CSeriesStats),
+                                                   ctypes.POINTER(ctypes.c_double)]),
                 "pprs_get_tuning": (i, [vp, ctypes.POINTER(_CTuning)]),
                 "pprs_set_tuning": (i, [vp, ctypes.POINTER(_CTuning)]),
             }
@@ -337,6 +344,33 @@ def set_tuning(tuning: dict, device=None):
     cur.update({k: int(v) for k, v in tuning.items() if k in TUNING_KEYS})
     t = _CTuning(**cur)
     _check(_lib().pprs_set_tuning(_ctx(dev).handle, ctypes.byref(t)))
+
+
+def register_series_batch(series, params: Params | None = None, levels=None, outs=None):
+    """Several independent series (a list of device tensors [N_j, side_j, side_j]) in one run
+    of the slot pool; `levels` optionally gives each series' level count. Returns (list of
+    u [N_j, 2, side_j, side_j], list of SeriesStats, list of per-series latencies in ms)."""
+    import torch
+    params = params or Params()
+    S = len(series)
+    if outs is None:
+        outs = [torch.empty((f.shape[0], 2, f.shape[1], f.shape[2]), device=f.device,
+                            dtype=torch.float32) for f in series]
+    fr = (ctypes.c_void_p * S)(*[_dev_f32(f, "frames").value for f in series])
+    uo = (ctypes.c_void_p * S)(*[_dev_f32(u, "out").value for u in outs])
+    ns = (ctypes.c_int * S)(*[int(f.shape[0]) for f in series])
+    sd = (ctypes.c_int * S)(*[int(f.shape[1]) for f in series])
+    st = (_CSeriesStats * S)()
+    lat = (ctypes.c_double * S)()
+    cp = params.c()
+    c = _ctx(series[0].device)
+    lv = (ctypes.c_int * S)(*[int(x) for x in levels]) if levels is not None else None
+    _check(_lib().pprs_register_series_batch(c.handle, S, fr, ns, sd, lv, uo, ctypes.byref(cp),
+                                             st, lat))
+    stats = [SeriesStats(x.n_ops_a, x.n_ops_b, x.n_scan_levels, x.flags_or, x.ms_total,
+                         x.ms_prepare, x.ms_preprocess, x.ms_scan, x.node_steps, x.node_passes)
+             for x in st]
+    return outs, stats, list(lat)
 
 
 def set_kernel_timing(enable: bool, device=None):

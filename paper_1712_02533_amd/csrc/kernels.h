@@ -41,14 +41,14 @@ hipError_t finish(BatchDesc* d, const int* out_idx, float* elems, long long estr
 hipError_t pool_assign(BatchDesc* d, const SlotState* staged, const int* slots, int ops,
                        hipStream_t st);
 hipError_t pool_zero(BatchDesc* d, int l, int n_l, const int* slots, int ops, hipStream_t st);
-hipError_t pool_compose(BatchDesc* d, int nL, const float* vbuf, long long est, const int* in0,
-                        const int* in1, const int* slots, int ops, hipStream_t st);
+hipError_t pool_compose(BatchDesc* d, int L, const float* vbuf, const long long* off0,
+                        const long long* off1, const int* slots, int ops, hipStream_t st);
 hipError_t pool_restrict(BatchDesc* d, int l, int n_c, const int* slots, int ops,
                          hipStream_t st);
 hipError_t pool_copy(BatchDesc* d, int l, int n_l, const float* src, long long sstride,
                      const int* src_idx, const int* slots, int ops, hipStream_t st);
-hipError_t pool_finish(BatchDesc* d, int nL, const int* slots, const int* outs, int ops,
-                       float* vbuf, long long est, hipStream_t st);
-hipError_t from_nodes_idx(const float* vbuf, long long est, const int* idx, int n, float* dst,
-                          int H, long long d_plane, int elems, float scale, hipStream_t st);
+hipError_t pool_finish(BatchDesc* d, int L, const int* slots, const long long* outs, int ops,
+                       float* vbuf, hipStream_t st);
+hipError_t from_nodes_idx(const float* vbuf, const long long* offs, int n, float* dst, int H,
+                          long long d_plane, int elems, float scale, hipStream_t st);
 }  // namespace pprs_k

@@ -444,8 +444,8 @@ __global__ void __launch_bounds__(BLOCK, 4) k_energy(BatchDesc* D) {
     size_t nn = (size_t)n * n;
     const float* u = slot_u(D, s, l, ub);
     const float* d = D->dbuf + (size_t)s * D->slot_f_stride;
-    const float* R = D->frames[l] + (size_t)stp->ref * nn;
-    const float* T = D->frames[l] + (size_t)stp->tmpl * nn;
+    const float* R = D->pyr + D->frame_off[(size_t)stp->ref * PPRS_MAXL + l];
+    const float* T = D->pyr + D->frame_off[(size_t)stp->tmpl * PPRS_MAXL + l];
     double top = MODE ? stp->top : 0.0;
     float taus[NC];
 #pragma unroll
@@ -596,8 +596,8 @@ __global__ void __launch_bounds__(BLOCK, 4) k_grad(BatchDesc* D) {
     float* un = slot_u(D, s, l, stp->ub ^ 1);
     const float* d = D->dbuf + (size_t)s * D->slot_f_stride;
     float* G = D->gbuf + (size_t)s * D->slot_f_stride;
-    const float* R = D->frames[l] + (size_t)stp->ref * nn;
-    const float* T = D->frames[l] + (size_t)stp->tmpl * nn;
+    const float* R = D->pyr + D->frame_off[(size_t)stp->ref * PPRS_MAXL + l];
+    const float* T = D->pyr + D->frame_off[(size_t)stp->tmpl * PPRS_MAXL + l];
     float tau = (float)stp->tau_pend;
     double sg = stp->sigma;
     float inv_sig = sg > 0.0 ? (float)(1.0 / sg) : 0.f;
@@ -1323,21 +1323,21 @@ __global__ void __launch_bounds__(BLOCK) k_pool_zero(BatchDesc* D, int l, const 
     slot_u(D, slots[i / per], l, 0)[i % per] = 0.f;
 }
 
-// Composition start: the finest-level u of slot slots[k] = vbuf[in0[k]] (.) vbuf[in1[k]]
-// (w = u_ij + u_jk(x + u_ij), clamped bilinear, domain units).
-__global__ void __launch_bounds__(BLOCK) k_pool_compose(BatchDesc* D, const float* vbuf,
-                                                        long long est, const int* in0,
-                                                        const int* in1, const int* slots,
+// Composition start on level L: the level-L u of slot slots[k] = (vbuf + off1[k]) (.)
+// (vbuf + off0[k]) (w = u_ij + u_jk(x + u_ij), clamped bilinear, domain units).
+__global__ void __launch_bounds__(BLOCK) k_pool_compose(BatchDesc* D, int L, const float* vbuf,
+                                                        const long long* off0,
+                                                        const long long* off1, const int* slots,
                                                         int ops) {
-  int L = D->finest, n = lvl_n(L);
+  int n = lvl_n(L);
   size_t nn = (size_t)n * n;
   float inv_h = (float)(n - 1);
   for (long long k = blockIdx.x * (long long)BLOCK + threadIdx.x; k < (long long)ops * nn;
        k += (long long)gridDim.x * BLOCK) {
     int op = (int)(k / nn);
     int i = (int)(k % nn);
-    const float* ul = vbuf + in0[op] * est;
-    const float* ur = vbuf + in1[op] * est;
+    const float* ul = vbuf + off0[op];
+    const float* ur = vbuf + off1[op];
     float* w = slot_u(D, slots[op], L, 0);
     int a = i / n, b = i % n;
     float ux = ul[i], uy = ul[nn + i];
@@ -1393,12 +1393,11 @@ __global__ void __launch_bounds__(BLOCK) k_pool_copy(BatchDesc* D, int l, const 
   }
 }
 
-// Finished listed slots: vbuf[outs[k]] = u_L[ub] - tau_pend d of slot slots[k] (a slot that
-// stopped before the finest level leaves its output untouched).
-__global__ void __launch_bounds__(BLOCK) k_pool_finish(BatchDesc* D, const int* slots,
-                                                       const int* outs, int ops, float* vbuf,
-                                                       long long est) {
-  int L = D->finest;
+// Finished listed slots whose finest level is L: vbuf + outs[k] = u_L[ub] - tau_pend d of slot
+// slots[k] (a slot that stopped before level L leaves its output untouched).
+__global__ void __launch_bounds__(BLOCK) k_pool_finish(BatchDesc* D, int L, const int* slots,
+                                                       const long long* outs, int ops,
+                                                       float* vbuf) {
   int n = lvl_n(L);
   size_t per = 2 * (size_t)n * n;
   for (long long k = blockIdx.x * (long long)BLOCK + threadIdx.x; k < (long long)ops * per;
@@ -1411,15 +1410,15 @@ __global__ void __launch_bounds__(BLOCK) k_pool_finish(BatchDesc* D, const int* 
     const float* u = slot_u(D, s, L, st.ub);
     const float* d = D->dbuf + (size_t)s * D->slot_f_stride;
     float tau = (float)st.tau_pend;
-    vbuf[outs[op] * est + i] = tau != 0.f ? u[i] - tau * d[i] : u[i];
+    vbuf[outs[op] + i] = tau != 0.f ? u[i] - tau * d[i] : u[i];
   }
 }
 
-// Nodal fields vbuf[idx[e]] ([2][n][n], domain units) -> pixels dst + e * 2 * d_plane.
-__global__ void __launch_bounds__(BLOCK) k_from_nodes_idx(const float* vbuf, long long est,
-                                                          const int* idx, int n, float* dst,
-                                                          int H, long long d_plane, int elems,
-                                                          float scale) {
+// Nodal fields at vbuf + offs[e] ([2][n][n], domain units) -> pixels dst + e * 2 * d_plane.
+__global__ void __launch_bounds__(BLOCK) k_from_nodes_idx(const float* vbuf,
+                                                          const long long* offs, int n,
+                                                          float* dst, int H, long long d_plane,
+                                                          int elems, float scale) {
   long long per = (long long)H * H;
   for (long long k = blockIdx.x * (long long)BLOCK + threadIdx.x; k < (long long)elems * 2 * per;
        k += (long long)gridDim.x * BLOCK) {
@@ -1428,7 +1427,7 @@ __global__ void __launch_bounds__(BLOCK) k_from_nodes_idx(const float* vbuf, lon
     int i = (int)(k % per);
     int a = i / H, b = i % H;
     dst[(size_t)e * 2 * d_plane + (size_t)comp * d_plane + i] =
-        scale * vbuf[idx[e] * est + (size_t)comp * n * n + (size_t)a * n + b];
+        scale * vbuf[offs[e] + (size_t)comp * n * n + (size_t)a * n + b];
   }
 }
 
@@ -1588,10 +1587,11 @@ hipError_t pool_zero(BatchDesc* d, int l, int n_l, const int* slots, int ops, hi
                      st, d, l, slots, ops);
   return hipGetLastError();
 }
-hipError_t pool_compose(BatchDesc* d, int nL, const float* vbuf, long long est, const int* in0,
-                        const int* in1, const int* slots, int ops, hipStream_t st) {
-  hipLaunchKernelGGL(k_pool_compose, dim3(grid_for((long long)ops * nL * nL)), dim3(BLOCK), 0,
-                     st, d, vbuf, est, in0, in1, slots, ops);
+hipError_t pool_compose(BatchDesc* d, int L, const float* vbuf, const long long* off0,
+                        const long long* off1, const int* slots, int ops, hipStream_t st) {
+  long long n = (1LL << L) + 1;
+  hipLaunchKernelGGL(k_pool_compose, dim3(grid_for((long long)ops * n * n)), dim3(BLOCK), 0, st,
+                     d, L, vbuf, off0, off1, slots, ops);
   return hipGetLastError();
 }
 hipError_t pool_restrict(BatchDesc* d, int l, int n_c, const int* slots, int ops,
@@ -1606,16 +1606,17 @@ hipError_t pool_copy(BatchDesc* d, int l, int n_l, const float* src, long long s
                      st, d, l, src, sstride, src_idx, slots, ops);
   return hipGetLastError();
 }
-hipError_t pool_finish(BatchDesc* d, int nL, const int* slots, const int* outs, int ops,
-                       float* vbuf, long long est, hipStream_t st) {
-  hipLaunchKernelGGL(k_pool_finish, dim3(grid_for((long long)ops * 2 * nL * nL)), dim3(BLOCK), 0,
-                     st, d, slots, outs, ops, vbuf, est);
+hipError_t pool_finish(BatchDesc* d, int L, const int* slots, const long long* outs, int ops,
+                       float* vbuf, hipStream_t st) {
+  long long n = (1LL << L) + 1;
+  hipLaunchKernelGGL(k_pool_finish, dim3(grid_for((long long)ops * 2 * n * n)), dim3(BLOCK), 0,
+                     st, d, L, slots, outs, ops, vbuf);
   return hipGetLastError();
 }
-hipError_t from_nodes_idx(const float* vbuf, long long est, const int* idx, int n, float* dst,
-                          int H, long long d_plane, int elems, float scale, hipStream_t st) {
+hipError_t from_nodes_idx(const float* vbuf, const long long* offs, int n, float* dst, int H,
+                          long long d_plane, int elems, float scale, hipStream_t st) {
   hipLaunchKernelGGL(k_from_nodes_idx, dim3(grid_for((long long)elems * 2 * H * H)), dim3(BLOCK),
-                     0, st, vbuf, est, idx, n, dst, H, d_plane, elems, scale);
+                     0, st, vbuf, offs, n, dst, H, d_plane, elems, scale);
   return hipGetLastError();
 }
 

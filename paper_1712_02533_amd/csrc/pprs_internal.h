@@ -96,8 +96,9 @@ struct BatchDesc {
   int iter_max;
   int smooth_halo;         // windowed metric solve halo in nodes; 0: exact two-pass line solves
   LevelGeom geom[PPRS_MAXL];
-  // frames: normalised pyramids, frame f at level l: frames[l] + f * n_l^2
-  float* frames[PPRS_MAXL];
+  // frames: normalised pyramids; frame f at level l starts at pyr + frame_off[f][l]
+  float* pyr;
+  const long long* frame_off;  // [frame][PPRS_MAXL] offsets in floats (-1: level not built)
   double* rsum;            // [frame][PPRS_MAXL]: quadrature integral of the normalised frame
   // slots
   SlotState* state;        // [n_slots]

@@ -87,7 +87,8 @@ struct pprs_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   // frames
-  DevBuf frames, rsum, fr_ms, fr_part;
+  DevBuf frames, frame_off, rsum, fr_ms, fr_part;
+  std::vector<long long> frame_off_host;
   // slots
   DevBuf state, ubuf, dbuf, gbuf, zbuf, partial, counters, nodecount, coef, list_slots, list_off,
       lists, desc, opidx;
@@ -100,7 +101,7 @@ struct pprs_ctx {
   int warm_mode = PPRS_WARM_REFINE;
   DevBuf cnn_in, cnn_out, tmp, badflags, warm_stage;
   // slot pool: per-round index lists and staged slot states
-  DevBuf pool_idx, pool_states;
+  DevBuf pool_idx, pool_off, pool_states;
   int pool_group = 8;    // steps between polls of the slot pool
   int pool_slots = 512;  // concurrent registrations of a series
   // workgroups of the per-step item kernels (results do not depend on them)
@@ -323,61 +324,93 @@ pprs_status ensure_slots(pprs_ctx* c, int cap, int L, int m0, double beta) {
   return PPRS_OK;
 }
 
-// Normalised frame pyramids for N frames (device [N][H][H]) on levels m0..L. Fails with
-// EINVAL if a frame with index < n_ref_frames is constant on some level.
-// Pyramids of N frames (levels m0..L), normalised per level. Frame f is checked for being
-// constant when f < n_ref_frames or, given ref_mask, when ref_mask[f] != 0.
-pprs_status prepare_frames(pprs_ctx* c, const float* frames, int N, int H, int L, int m0,
-                           int n_ref_frames, const std::vector<char>* ref_mask = nullptr) {
+// One series' frames for prepare_series: device [N][H][H], levels m0..L, global index of its
+// first frame f0. Frame f is checked for being constant when it serves as a reference:
+// f < n_ref, or ref_mask[f] != 0 when a mask is given.
+struct SeriesIn {
+  const float* frames;
+  int N, H, L, m0, f0, n_ref;
+  const std::vector<char>* ref_mask;
+};
+
+// Normalised frame pyramids of several series in one buffer: series s, level l is a block of
+// N_s frames; the offset table maps (global frame, level) to the frame's first node.
+pprs_status prepare_series(pprs_ctx* c, const std::vector<SeriesIn>& ser) {
   BatchDesc& hd = c->hd;
+  int NT = 0, Nmax = 1;
+  for (const SeriesIn& x : ser) {
+    NT = std::max(NT, x.f0 + x.N);
+    Nmax = std::max(Nmax, x.N);
+  }
+  std::vector<long long>& off = c->frame_off_host;
+  off.assign((size_t)NT * PPRS_MAXL, -1);
   size_t total = 0;
-  size_t off[PPRS_MAXL] = {0};
-  for (int l = m0; l <= L; ++l) {
-    off[l] = total;
-    total += (size_t)N * level_n(l) * level_n(l);
-  }
-  STCHK(ensure(c->frames, sizeof(float) * total));
-  STCHK(ensure(c->rsum, sizeof(double) * (size_t)N * PPRS_MAXL));
-  const int bands = 16;
-  STCHK(ensure(c->fr_part, sizeof(double) * 2 * (size_t)N * bands));
-  STCHK(ensure(c->fr_ms, sizeof(double) * 2 * (size_t)N * PPRS_MAXL));
-  float* base = P<float>(c->frames);
-  for (int l = 0; l < PPRS_MAXL; ++l) hd.frames[l] = nullptr;
-  for (int l = m0; l <= L; ++l) hd.frames[l] = base + off[l];
-  hd.rsum = P<double>(c->rsum);
-  int nL = level_n(L);
-  HIPCHK(pprs_k::to_nodes(frames, H, (long long)H * H, hd.frames[L], nL, (long long)nL * nL, N,
-                          1.0f, c->stream));
-  for (int l = L; l > m0; --l) {
-    int nf = level_n(l), nc = level_n(l - 1);
-    HIPCHK(pprs_k::restrict_planes(hd.frames[l], (long long)nf * nf, 0, hd.frames[l - 1],
-                                   (long long)nc * nc, 0, 1, nf, N, c->stream));
-  }
-  std::vector<double> ms(2 * (size_t)N);
-  for (int l = m0; l <= L; ++l) {
-    int n = level_n(l);
-    double* msd = P<double>(c->fr_ms) + 2 * (size_t)N * l;
-    HIPCHK(pprs_k::elem_sums(hd.frames[l], (long long)n * n, n, bands, N, P<double>(c->fr_part),
-                             c->stream));
-    HIPCHK(pprs_k::elem_final(P<double>(c->fr_part), bands, N, 0, msd, nullptr, 0, 0,
-                              c->stream));
-    HIPCHK(hipMemcpyAsync(ms.data(), msd, sizeof(double) * 2 * N, hipMemcpyDeviceToHost,
-                          c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    for (int f = 0; f < N; ++f) {
-      double m = ms[2 * f], s = ms[2 * f + 1];
-      bool is_ref = ref_mask ? (*ref_mask)[f] != 0 : f < n_ref_frames;
-      if (s <= 1e-12 * std::max(1.0, fabs(m)) && is_ref)
-        return fail(PPRS_EINVAL, "reference frame %d is constant on level %d", f, l);
+  for (const SeriesIn& x : ser)
+    for (int l = x.m0; l <= x.L; ++l) {
+      size_t nn = (size_t)level_n(l) * level_n(l);
+      for (int f = 0; f < x.N; ++f) off[(size_t)(x.f0 + f) * PPRS_MAXL + l] = total + f * nn;
+      total += (size_t)x.N * nn;
     }
-    HIPCHK(pprs_k::normalize(hd.frames[l], (long long)n * n, (long long)n * n, N, msd,
-                             c->stream));
-    HIPCHK(pprs_k::elem_sums(hd.frames[l], (long long)n * n, n, bands, N, P<double>(c->fr_part),
-                             c->stream));
-    HIPCHK(pprs_k::elem_final(P<double>(c->fr_part), bands, N, 1, nullptr, P<double>(c->rsum),
-                              PPRS_MAXL, l, c->stream));
+  STCHK(ensure(c->frames, sizeof(float) * std::max<size_t>(total, 1)));
+  STCHK(ensure(c->frame_off, sizeof(long long) * off.size()));
+  STCHK(ensure(c->rsum, sizeof(double) * (size_t)NT * PPRS_MAXL));
+  const int bands = 16;
+  STCHK(ensure(c->fr_part, sizeof(double) * 2 * (size_t)Nmax * bands));
+  STCHK(ensure(c->fr_ms, sizeof(double) * 2 * (size_t)Nmax * PPRS_MAXL));
+  HIPCHK(hipMemcpyAsync(c->frame_off.p, off.data(), sizeof(long long) * off.size(),
+                        hipMemcpyHostToDevice, c->stream));
+  hd.pyr = P<float>(c->frames);
+  hd.frame_off = P<long long>(c->frame_off);
+  hd.rsum = P<double>(c->rsum);
+  for (const SeriesIn& x : ser) {
+    int N = x.N;
+    auto lvl = [&](int l) { return hd.pyr + off[(size_t)x.f0 * PPRS_MAXL + l]; };
+    int nL = level_n(x.L);
+    HIPCHK(pprs_k::to_nodes(x.frames, x.H, (long long)x.H * x.H, lvl(x.L), nL,
+                            (long long)nL * nL, N, 1.0f, c->stream));
+    for (int l = x.L; l > x.m0; --l) {
+      int nf = level_n(l), nc = level_n(l - 1);
+      HIPCHK(pprs_k::restrict_planes(lvl(l), (long long)nf * nf, 0, lvl(l - 1),
+                                     (long long)nc * nc, 0, 1, nf, N, c->stream));
+    }
+    std::vector<double> ms(2 * (size_t)N);
+    double* rs = P<double>(c->rsum) + (size_t)x.f0 * PPRS_MAXL;
+    for (int l = x.m0; l <= x.L; ++l) {
+      int n = level_n(l);
+      double* msd = P<double>(c->fr_ms) + 2 * (size_t)N * l;
+      HIPCHK(pprs_k::elem_sums(lvl(l), (long long)n * n, n, bands, N, P<double>(c->fr_part),
+                               c->stream));
+      HIPCHK(pprs_k::elem_final(P<double>(c->fr_part), bands, N, 0, msd, nullptr, 0, 0,
+                                c->stream));
+      HIPCHK(hipMemcpyAsync(ms.data(), msd, sizeof(double) * 2 * N, hipMemcpyDeviceToHost,
+                            c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+      for (int f = 0; f < N; ++f) {
+        double m = ms[2 * f], sg = ms[2 * f + 1];
+        bool is_ref = x.ref_mask ? (*x.ref_mask)[f] != 0 : f < x.n_ref;
+        if (sg <= 1e-12 * std::max(1.0, fabs(m)) && is_ref)
+          return fail(PPRS_EINVAL, "reference frame %d is constant on level %d", f, l);
+      }
+      HIPCHK(pprs_k::normalize(lvl(l), (long long)n * n, (long long)n * n, N, msd, c->stream));
+      HIPCHK(pprs_k::elem_sums(lvl(l), (long long)n * n, n, bands, N, P<double>(c->fr_part),
+                               c->stream));
+      HIPCHK(pprs_k::elem_final(P<double>(c->fr_part), bands, N, 1, nullptr, rs, PPRS_MAXL, l,
+                                c->stream));
+    }
   }
   return PPRS_OK;
+}
+
+// Pyramids of one series of N frames (global frames 0 .. N-1).
+pprs_status prepare_frames(pprs_ctx* c, const float* frames, int N, int H, int L, int m0,
+                           int n_ref_frames, const std::vector<char>* ref_mask = nullptr) {
+  std::vector<SeriesIn> one{SeriesIn{frames, N, H, L, m0, 0, n_ref_frames, ref_mask}};
+  return prepare_series(c, one);
+}
+
+// First node of level l of global frame f (host-side pointer arithmetic on device memory).
+float* frame_level_ptr(pprs_ctx* c, int f, int l) {
+  return c->hd.pyr + c->frame_off_host[(size_t)f * PPRS_MAXL + l];
 }
 
 // ---- kernel timing -----------------------------------------------------------------------
@@ -574,8 +607,8 @@ const int kPairChunk = 512;   // pairs per batch of pprs_register_pairs
 // Network predictions for n pairs (ref[s], tmpl[s]) written as level-7 guesses (domain units,
 // [2][129][129]) to dst + s * dst_stride; bad[s] = 1 for predictions that are not finite or
 // exceed the bound.
-pprs_status warm_predict(pprs_ctx* c, int n, const int* ref, const int* tmpl, float* dst,
-                         long long dst_stride, std::vector<int>& bad) {
+pprs_status warm_predict(pprs_ctx* c, int f0, int n, const int* ref, const int* tmpl,
+                         float* dst, long long dst_stride, std::vector<int>& bad) {
   BatchDesc& hd = c->hd;
   int S = 1 << kWarmLevel;
   size_t per = (size_t)S * S * 2;
@@ -590,7 +623,8 @@ pprs_status warm_predict(pprs_ctx* c, int n, const int* ref, const int* tmpl, fl
   HIPCHK(hipMemcpyAsync(dtmpl, tmpl, sizeof(int) * n, hipMemcpyHostToDevice, c->stream));
   for (int p0 = 0; p0 < n; p0 += chunk) {
     int np = std::min(chunk, n - p0);
-    HIPCHK(pprs_cnn_api::pack_pairs(hd.frames[kWarmLevel], S + 1, dref + p0, dtmpl + p0, np,
+    HIPCHK(pprs_cnn_api::pack_pairs(frame_level_ptr(c, f0, kWarmLevel), S + 1, dref + p0,
+                                    dtmpl + p0, np,
                                     P<float>(c->cnn_in), c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     STCHK(pprs_cnn_api::forward_into(c->cnn, P<float>(c->cnn_in), np, P<float>(c->cnn_out)));
@@ -614,7 +648,8 @@ pprs_status warm_init(pprs_ctx* c, int n, const int* ref, const int* tmpl, int m
                       std::vector<int>& lv, std::vector<int>& fl) {
   BatchDesc& hd = c->hd;
   std::vector<int> bad;
-  STCHK(warm_predict(c, n, ref, tmpl, hd.ubuf + hd.u_off[kWarmLevel], hd.slot_u_stride, bad));
+  STCHK(warm_predict(c, 0, n, ref, tmpl, hd.ubuf + hd.u_off[kWarmLevel], hd.slot_u_stride,
+                     bad));
   int n0 = level_n(m0);
   long long per0 = 2LL * n0 * n0;
   lv.assign(n, m0);
@@ -642,18 +677,27 @@ pprs_status warm_init(pprs_ctx* c, int n, const int* ref, const int* tmpl, int m
 // ---- slot pool ---------------------------------------------------------------------------
 // A registration ("op") reads frames ref/tmpl, starts from the identity, a composition of two
 // finished results or a staged guess, and writes its finest-level result (nodal, domain units)
-// to its own version buffer vbuf[out]. Ops become ready when the ops producing their inputs
-// have finished; ready ops are started in free slots in op order, and the slots keep stepping
-// (early retirement: a finished slot takes the next ready op at the following poll).
+// to its own version buffer vbuf + ver_off[out]. Ops become ready when the ops producing their
+// inputs have finished; ready ops are started in free slots in op order, and the slots keep
+// stepping (early retirement: a finished slot takes the next ready op at the following poll).
+// Ops of different series may have different finest levels L (slots are sized for the
+// largest).
 
 struct PoolOp {
-  int ref, tmpl;
+  int ref, tmpl;   // global frame indices
   InitKind init;   // INIT_IDENTITY, INIT_COMPOSE or INIT_PREPARED (staged guess)
   int in0, in1;    // INIT_COMPOSE: versions composed (in1 o in0)
   int out;         // version written
   int start;       // start level
   int flags;       // initial flags (e.g. PPRS_FLAG_FALLBACK)
-  int stage;       // INIT_PREPARED: index of the staged level-stage_level guess
+  int stage;       // INIT_PREPARED: index of the staged guess
+  int L, m0;       // finest level of the op's frames; its series' coarsest level (statistics)
+};
+
+struct PoolSpec {
+  const float* stage = nullptr;   // staged guesses [count][2][n^2] on stage_level
+  long long stage_stride = 0;
+  int stage_level = -1;
 };
 
 struct GraphExec {
@@ -663,21 +707,16 @@ struct GraphExec {
   }
 };
 
-struct PoolSpec {
-  const float* stage = nullptr;   // staged guesses [count][2][n^2] on stage_level
-  long long stage_stride = 0;
-  int stage_level = -1;
-};
-
-pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf, long long est,
-                     const pprs_params* p, const PoolSpec& spec, pprs_pair_stats* stats,
-                     long long* node_steps, long long* node_passes, int* flags_or) {
+pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
+                     const std::vector<long long>& ver_off, const pprs_params* p,
+                     const PoolSpec& spec, pprs_pair_stats* stats, long long* node_steps,
+                     long long* node_passes, int* flags_or,
+                     std::vector<double>* finish_ms = nullptr) {
   const int n_ops = (int)ops.size();
   if (n_ops == 0) return PPRS_OK;
   auto t_start = std::chrono::steady_clock::now();
   BatchDesc& hd = c->hd;
-  int L = hd.finest, m0 = hd.coarsest;
-  int nL = level_n(L);
+  int Lmax = hd.finest, m0min = hd.coarsest;
   S = std::max(1, std::min(S, std::min(n_ops, hd.max_slots)));
   hd.n_slots = S;
   hd.ladder_k = p->ladder_k;
@@ -690,18 +729,19 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf, 
   set_grad_tiles(c);
   BatchDesc* d = P<BatchDesc>(c->desc);
   HIPCHK(hipMemcpyAsync(d, &hd, sizeof(BatchDesc), hipMemcpyHostToDevice, c->stream));
+  for (const PoolOp& o : ops)
+    if (o.L > Lmax || o.start < m0min || o.start > o.L || o.m0 > o.start ||
+        o.out < 0 || o.out >= (int)ver_off.size())
+      return fail(PPRS_ESTATE, "pool op outside the slot geometry");
   // dependencies: producers are the ops whose out is read
-  std::vector<int> producer(n_ops + 1, -1);  // version -> op (versions are op outputs)
-  int max_ver = 0;
-  for (const PoolOp& o : ops) max_ver = std::max(max_ver, o.out);
-  producer.assign(max_ver + 1, -1);
+  std::vector<int> producer(ver_off.size(), -1);
   for (int i = 0; i < n_ops; ++i) producer[ops[i].out] = i;
   std::vector<int> remaining(n_ops, 0);
   std::vector<std::vector<int>> dependents(n_ops);
   for (int i = 0; i < n_ops; ++i) {
     if (ops[i].init != INIT_COMPOSE) continue;
     for (int v : {ops[i].in0, ops[i].in1}) {
-      int q = v >= 0 && v <= max_ver ? producer[v] : -1;
+      int q = v >= 0 && v < (int)producer.size() ? producer[v] : -1;
       if (q < 0 || q >= i) return fail(PPRS_EINDEX, "op %d reads a version no earlier op writes", i);
       remaining[i]++;
       dependents[q].push_back(i);
@@ -715,13 +755,15 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf, 
   for (int s = 0; s < S; ++s) {
     memset(&st[s], 0, sizeof(SlotState));
     st[s].phase = PH_DONE;
-    st[s].level = m0;
+    st[s].level = m0min;
   }
   HIPCHK(hipMemcpyAsync(hd.state, st.data(), sizeof(SlotState) * S, hipMemcpyHostToDevice,
                         c->stream));
-  STCHK(ensure(c->pool_idx, sizeof(int) * 6 * (size_t)S));
+  STCHK(ensure(c->pool_idx, sizeof(int) * 4 * (size_t)S));
+  STCHK(ensure(c->pool_off, sizeof(long long) * 3 * (size_t)S));
   STCHK(ensure(c->pool_states, sizeof(SlotState) * (size_t)S));
   int* didx = P<int>(c->pool_idx);
+  long long* doff = P<long long>(c->pool_off);
   SlotState* dstates = P<SlotState>(c->pool_states);
   std::vector<int> slot_op(S, -1), free_slots;
   for (int s = S - 1; s >= 0; --s) free_slots.push_back(s);
@@ -730,12 +772,13 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf, 
   int K = p->ladder_k;
   long long passes_per_iter = 2 + (long long)ceil(log2(1.0 / p->tau_min_rel) / (2 * K + 1));
   long long per_op_steps =
-      (long long)p->levels * ((long long)p->iter_max + 2) * (passes_per_iter + 2) + 64;
+      (long long)(Lmax - m0min + 1) * ((long long)p->iter_max + 2) * (passes_per_iter + 2) + 64;
   long long max_steps = per_op_steps * (long long)(n_ops / S + 2) + 64;
   long long done_steps = 0;
   int done_ops = 0;
   // host copies of the per-round lists (they must outlive the asynchronous uploads)
-  std::vector<int> h_idx(6 * (size_t)S);
+  std::vector<int> h_idx(4 * (size_t)S);
+  std::vector<long long> h_off(3 * (size_t)S);
   std::vector<SlotState> h_states(S);
   int G = std::max(1, c->pool_group);
   // the G steps between polls always launch the same kernels with the same arguments (all
@@ -777,61 +820,67 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf, 
       x.level = o.start;
       x.ref = o.ref;
       x.tmpl = o.tmpl;
-      x.finest = L;
+      x.finest = o.L;
       x.coarsest = o.start;
       x.tau_prev = INFINITY;
       x.flags = o.flags;
       ++na;
     }
     if (na > 0) {
-      // lists: [0] slots, [1] in0, [2] in1 / stage index, grouped by init kind
       for (int k = 0; k < na; ++k) h_idx[k] = a_slot[k];
       HIPCHK(hipMemcpyAsync(dstates, h_states.data(), sizeof(SlotState) * na,
                             hipMemcpyHostToDevice, c->stream));
       HIPCHK(hipMemcpyAsync(didx, h_idx.data(), sizeof(int) * na, hipMemcpyHostToDevice,
                             c->stream));
       HIPCHK(pprs_k::pool_assign(d, dstates, didx, na, c->stream));
-      // initial guesses per kind and start level
+      // initial guesses per kind, finest level and start level
       for (int kind : {(int)INIT_IDENTITY, (int)INIT_COMPOSE, (int)INIT_PREPARED}) {
-        for (int lv = m0; lv <= L; ++lv) {
-          int cnt = 0;
-          int* hs = h_idx.data() + S;            // slots
-          int* h0 = h_idx.data() + 2 * S;        // in0 / stage index
-          int* h1 = h_idx.data() + 3 * S;        // in1
-          for (int k = 0; k < na; ++k) {
-            const PoolOp& o = ops[a_op[k]];
-            if ((int)o.init != kind || o.start != lv) continue;
-            hs[cnt] = a_slot[k];
-            h0[cnt] = kind == INIT_PREPARED ? o.stage : o.in0;
-            h1[cnt] = o.in1;
-            ++cnt;
+        for (int Lv = m0min; Lv <= Lmax; ++Lv) {
+          for (int lv = m0min; lv <= Lv; ++lv) {
+            int cnt = 0;
+            int* hs = h_idx.data() + S;        // slots
+            int* h0 = h_idx.data() + 2 * S;    // stage index
+            long long* o0 = h_off.data();      // composed versions
+            long long* o1 = h_off.data() + S;
+            for (int k = 0; k < na; ++k) {
+              const PoolOp& o = ops[a_op[k]];
+              if ((int)o.init != kind || o.start != lv || o.L != Lv) continue;
+              hs[cnt] = a_slot[k];
+              h0[cnt] = o.stage;
+              if (kind == INIT_COMPOSE) {
+                o0[cnt] = ver_off[o.in0];
+                o1[cnt] = ver_off[o.in1];
+              }
+              ++cnt;
+            }
+            if (cnt == 0) continue;
+            int* ds = didx + S;
+            int* d0 = didx + 2 * S;
+            HIPCHK(hipMemcpyAsync(ds, hs, sizeof(int) * cnt, hipMemcpyHostToDevice, c->stream));
+            int top = Lv;
+            if (kind == INIT_IDENTITY) {
+              HIPCHK(pprs_k::pool_zero(d, lv, level_n(lv), ds, cnt, c->stream));
+              top = lv;
+            } else if (kind == INIT_COMPOSE) {
+              HIPCHK(hipMemcpyAsync(doff, o0, sizeof(long long) * cnt, hipMemcpyHostToDevice,
+                                    c->stream));
+              HIPCHK(hipMemcpyAsync(doff + S, o1, sizeof(long long) * cnt,
+                                    hipMemcpyHostToDevice, c->stream));
+              HIPCHK(pprs_k::pool_compose(d, Lv, vbuf, doff, doff + S, ds, cnt, c->stream));
+            } else {
+              if (!spec.stage || spec.stage_level < lv || spec.stage_level > Lv)
+                return fail(PPRS_ESTATE, "staged guesses on level %d cannot start level %d",
+                            spec.stage_level, lv);
+              HIPCHK(hipMemcpyAsync(d0, h0, sizeof(int) * cnt, hipMemcpyHostToDevice, c->stream));
+              HIPCHK(pprs_k::pool_copy(d, spec.stage_level, level_n(spec.stage_level),
+                                       spec.stage, spec.stage_stride, d0, ds, cnt, c->stream));
+              top = spec.stage_level;
+            }
+            for (int l = top; l > lv; --l)
+              HIPCHK(pprs_k::pool_restrict(d, l, level_n(l - 1), ds, cnt, c->stream));
+            // the lists are reused by the next group: wait for the uploads to be consumed
+            HIPCHK(hipStreamSynchronize(c->stream));
           }
-          if (cnt == 0) continue;
-          int* ds = didx + S;
-          int* d0 = didx + 2 * S;
-          int* d1 = didx + 3 * S;
-          HIPCHK(hipMemcpyAsync(ds, hs, sizeof(int) * cnt, hipMemcpyHostToDevice, c->stream));
-          HIPCHK(hipMemcpyAsync(d0, h0, sizeof(int) * cnt, hipMemcpyHostToDevice, c->stream));
-          if (kind == INIT_COMPOSE)
-            HIPCHK(hipMemcpyAsync(d1, h1, sizeof(int) * cnt, hipMemcpyHostToDevice, c->stream));
-          int top = L;
-          if (kind == INIT_IDENTITY) {
-            HIPCHK(pprs_k::pool_zero(d, lv, level_n(lv), ds, cnt, c->stream));
-            top = lv;
-          } else if (kind == INIT_COMPOSE) {
-            HIPCHK(pprs_k::pool_compose(d, nL, vbuf, est, d0, d1, ds, cnt, c->stream));
-          } else {
-            if (!spec.stage || spec.stage_level < lv || spec.stage_level > L)
-              return fail(PPRS_ESTATE, "staged guesses on level %d cannot start level %d",
-                          spec.stage_level, lv);
-            HIPCHK(pprs_k::pool_copy(d, spec.stage_level, level_n(spec.stage_level), spec.stage,
-                                     spec.stage_stride, d0, ds, cnt, c->stream));
-            top = spec.stage_level;
-          }
-          for (int l = top; l > lv; --l)
-            HIPCHK(pprs_k::pool_restrict(d, l, level_n(l - 1), ds, cnt, c->stream));
-          // the lists are reused by the next group: wait for the uploads to be consumed
-          HIPCHK(hipStreamSynchronize(c->stream));
         }
       }
     }
@@ -849,18 +898,15 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf, 
                           hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     if (c->timing) STCHK(tk_collect(c));
-    int nf = 0;
-    int* fs = h_idx.data() + 4 * S;
-    int* fo = h_idx.data() + 5 * S;
+    std::vector<int> fin;
     for (int s = 0; s < S; ++s) {
       int i = slot_op[s];
       if (i < 0 || st[s].phase != PH_DONE) continue;
-      fs[nf] = s;
-      fo[nf] = ops[i].out;
-      ++nf;
+      fin.push_back(s);
+      const PoolOp& op = ops[i];
       if (flags_or) *flags_or |= st[s].flags;
       for (int k = 0; k < WK_COUNT; ++k) c->nodes_acc[k] += nodes[(size_t)s * WK_COUNT + k];
-      for (int l = st[s].coarsest; l <= L; ++l) {
+      for (int l = st[s].coarsest; l <= op.L; ++l) {
         long long nn = (long long)level_n(l) * level_n(l);
         if (node_steps) *node_steps += nn * st[s].iters[l - st[s].coarsest];
         if (node_passes) *node_passes += nn * st[s].passes[l - st[s].coarsest];
@@ -868,25 +914,43 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf, 
       if (stats) {
         pprs_pair_stats& o = stats[i];
         memset(&o, 0, sizeof o);
-        for (int l = st[s].coarsest; l <= L; ++l) {
-          o.iters[l - m0] = st[s].iters[l - st[s].coarsest];
-          o.passes[l - m0] = st[s].passes[l - st[s].coarsest];
+        for (int l = st[s].coarsest; l <= op.L; ++l) {
+          o.iters[l - op.m0] = st[s].iters[l - st[s].coarsest];
+          o.passes[l - op.m0] = st[s].passes[l - st[s].coarsest];
         }
         o.energy = st[s].E;
         o.ncc = st[s].ncc;
         o.flags = st[s].flags;
       }
+      if (finish_ms)
+        (*finish_ms)[i] = std::chrono::duration<double, std::milli>(
+                              std::chrono::steady_clock::now() - t_start).count();
       for (int q : dependents[i])
         if (--remaining[q] == 0) ready.push(q);
-      slot_op[s] = -1;
-      free_slots.push_back(s);
       ++done_ops;
     }
-    if (nf > 0) {
-      HIPCHK(hipMemcpyAsync(didx + 4 * S, fs, sizeof(int) * 2 * S, hipMemcpyHostToDevice,
+    // copy the finished results out (grouped by finest level) before their slots are reused
+    for (int Lv = m0min; Lv <= Lmax && !fin.empty(); ++Lv) {
+      int cnt = 0;
+      int* fs = h_idx.data() + 3 * S;
+      long long* fo = h_off.data() + 2 * S;
+      for (int s : fin)
+        if (ops[slot_op[s]].L == Lv) {
+          fs[cnt] = s;
+          fo[cnt] = ver_off[ops[slot_op[s]].out];
+          ++cnt;
+        }
+      if (cnt == 0) continue;
+      HIPCHK(hipMemcpyAsync(didx + 3 * S, fs, sizeof(int) * cnt, hipMemcpyHostToDevice,
                             c->stream));
-      HIPCHK(pprs_k::pool_finish(d, nL, didx + 4 * S, didx + 5 * S, nf, vbuf, est, c->stream));
-      // mark the retired slots empty (their state stays DONE; the lists drop them)
+      HIPCHK(hipMemcpyAsync(doff + 2 * S, fo, sizeof(long long) * cnt, hipMemcpyHostToDevice,
+                            c->stream));
+      HIPCHK(pprs_k::pool_finish(d, Lv, didx + 3 * S, doff + 2 * S, cnt, vbuf, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    for (int s : fin) {
+      slot_op[s] = -1;
+      free_slots.push_back(s);
     }
     if (done_steps > max_steps)
       return fail(PPRS_ESTATE, "slot pool did not finish within %lld steps", max_steps);
@@ -1099,6 +1163,211 @@ struct EventSet {
   }
 };
 
+// One series of a (possibly multi-series) registration run.
+struct SeriesJob {
+  const float* frames;  // device [N][H][H]
+  int N, H, L, m0;
+  float* u_out;         // device [N][2][H][H]
+  pprs_series_stats* stats;
+  pprs_pair_stats* op_stats;  // 3N entries, may be NULL
+  double* latency_ms;   // time from the start of the run to the series' last result, or NULL
+};
+
+// Registers every series of `jobs` in one slot pool: the N-1 neighbour registrations and the
+// scan's B applications of all series share the pool, each starting when its inputs exist.
+pprs_status run_series_set(pprs_ctx* c, std::vector<SeriesJob>& jobs, const pprs_params* params) {
+  EventSet ev;
+  for (int k = 0; k < 4; ++k) HIPCHK(hipEventCreate(&ev.e[k]));
+  HIPCHK(hipEventRecord(ev.e[0], c->stream));
+  int Lmax = 0, m0min = PPRS_MAXL, f0 = 0, total_M = 0;
+  std::vector<SeriesIn> sin;
+  std::vector<int> first(jobs.size());
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    SeriesJob& x = jobs[j];
+    size_t plane = (size_t)x.H * x.H;
+    HIPCHK(pprs_k::fill(x.u_out, 2LL * (long long)plane, 0.f, c->stream));
+    Lmax = std::max(Lmax, x.L);
+    m0min = std::min(m0min, x.m0);
+    first[j] = f0;
+    if (x.N > 1) sin.push_back(SeriesIn{x.frames, x.N, x.H, x.L, x.m0, f0, x.N - 1, nullptr});
+    f0 += x.N;
+    total_M += std::max(0, x.N - 1);
+  }
+  if (!sin.empty()) STCHK(prepare_series(c, sin));
+  HIPCHK(hipEventRecord(ev.e[1], c->stream));
+  bool any_warm = c->cnn != nullptr;
+  // schedules and ops
+  std::vector<PoolOp> ops;
+  std::vector<long long> ver_off;
+  std::vector<std::vector<int>> final_ver(jobs.size());
+  std::vector<std::pair<int, int>> job_ops(jobs.size());  // [first op, end)
+  std::vector<int> n_ops_b(jobs.size(), 0), n_lv(jobs.size(), 0);
+  long long vtotal = 0;
+  int slots_needed = 1;
+  // warm guesses: staged per neighbour pair of every warm-capable series
+  int n7 = level_n(kWarmLevel);
+  long long per7 = 2LL * n7 * n7;
+  PoolSpec spec;
+  std::vector<int> stage_base(jobs.size(), -1);
+  if (any_warm) {
+    int nstage = 0;
+    for (size_t j = 0; j < jobs.size(); ++j)
+      if (jobs[j].m0 <= kWarmLevel && kWarmLevel <= jobs[j].L && jobs[j].N > 1) {
+        stage_base[j] = nstage;
+        nstage += jobs[j].N - 1;
+      }
+    if (nstage > 0) {
+      STCHK(ensure(c->warm_stage, sizeof(float) * per7 * nstage));
+      spec.stage = P<float>(c->warm_stage);
+      spec.stage_stride = per7;
+      spec.stage_level = kWarmLevel;
+    }
+  }
+  // the network runs before the registrations (its time is the "preprocess" figure)
+  std::vector<std::vector<int>> bad(jobs.size());
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    if (stage_base[j] < 0) continue;
+    int M = jobs[j].N - 1;
+    std::vector<int> ref(M), tmpl(M);
+    for (int m = 0; m < M; ++m) {
+      ref[m] = m;
+      tmpl[m] = m + 1;
+    }
+    STCHK(warm_predict(c, first[j], M, ref.data(), tmpl.data(),
+                       P<float>(c->warm_stage) + (size_t)stage_base[j] * per7, per7, bad[j]));
+  }
+  HIPCHK(hipEventRecord(ev.e[2], c->stream));
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    SeriesJob& x = jobs[j];
+    int M = x.N - 1;
+    int nL = level_n(x.L);
+    long long est = 2LL * nL * nL;
+    job_ops[j].first = (int)ops.size();
+    if (M < 1) {
+      job_ops[j].second = (int)ops.size();
+      continue;
+    }
+    std::vector<int> plan;
+    int n_ops = 0, n_levels = 0;
+    pprs_scan_plan(params->scan, M, nullptr, 0, &n_ops, &n_levels);  // sizes only
+    plan.resize(3 * (size_t)std::max(n_ops, 1));
+    if (pprs_scan_plan(params->scan, M, plan.data(), n_ops, &n_ops, &n_levels) != PPRS_OK)
+      return fail(PPRS_EINVAL, "scan planning failed");
+    n_ops_b[j] = n_ops;
+    n_lv[j] = n_levels;
+    int widest = M;
+    for (int lv = 0, i = 0; lv < n_levels; ++lv) {
+      int cnt = 0;
+      while (i < n_ops && plan[3 * i + 2] == lv) ++cnt, ++i;
+      widest = std::max(widest, cnt);
+    }
+    slots_needed = std::max(slots_needed, widest);
+    bool warm = stage_base[j] >= 0;
+    bool skip = warm && c->warm_mode == PPRS_WARM_SKIP;
+    int vb = (int)ver_off.size();
+    for (int k = 0; k < M + n_ops; ++k) ver_off.push_back(vtotal + (long long)k * est);
+    vtotal += (long long)(M + n_ops) * est;
+    std::vector<int> ver(M), ei(M), ek(M);
+    int g0 = first[j];
+    for (int m = 0; m < M; ++m) {
+      ver[m] = vb + m;
+      ei[m] = m;
+      ek[m] = m + 1;
+      PoolOp o{g0 + m, g0 + m + 1, INIT_IDENTITY, -1, -1, vb + m, x.m0, 0, -1, x.L, x.m0};
+      if (warm) {
+        if (bad[j][m]) {
+          o.flags = PPRS_FLAG_FALLBACK;
+        } else {
+          o.init = INIT_PREPARED;
+          o.stage = stage_base[j] + m;
+          o.start = skip ? kWarmLevel : x.m0;
+        }
+      }
+      ops.push_back(o);
+    }
+    // x[right] <- x[left] (.) x[right]: B registers frame ek[right] to frame ei[left], starting
+    // from the composition of the two results
+    for (int i = 0; i < n_ops; ++i) {
+      int a = plan[3 * i], b = plan[3 * i + 1];
+      if (ek[a] != ei[b])
+        return fail(PPRS_EINDEX, "scan operands (%d,%d) and (%d,%d) do not share a frame", ei[a],
+                    ek[a], ei[b], ek[b]);
+      PoolOp o{g0 + ei[a], g0 + ek[b], INIT_COMPOSE, ver[a], ver[b], vb + M + i,
+               skip ? kWarmLevel : x.m0, 0, -1, x.L, x.m0};
+      ops.push_back(o);
+      ver[b] = vb + M + i;
+      ei[b] = ei[a];
+    }
+    for (int m = 0; m < M; ++m)
+      if (ei[m] != 0 || ek[m] != m + 1)
+        return fail(PPRS_EINDEX, "element %d ends as (%d,%d)", m, ei[m], ek[m]);
+    final_ver[j] = ver;
+    job_ops[j].second = (int)ops.size();
+  }
+  int flags = 0;
+  long long node_steps = 0, node_passes = 0;
+  std::vector<pprs_pair_stats> all_stats(ops.size());
+  std::vector<double> fin_ms(ops.size(), 0.0);
+  if (!ops.empty()) {
+    int slots = std::min(slots_needed * (int)jobs.size(), c->pool_slots);
+    STCHK(ensure(c->elems, sizeof(float) * std::max<long long>(vtotal, 1)));
+    STCHK(ensure_slots(c, slots, Lmax, m0min, params->beta));
+    float* vbuf = P<float>(c->elems);
+    STCHK(run_pool(c, ops, slots, vbuf, ver_off, params, spec, all_stats.data(), &node_steps,
+                   &node_passes, &flags, &fin_ms));
+    for (size_t j = 0; j < jobs.size(); ++j) {
+      SeriesJob& x = jobs[j];
+      int M = x.N - 1;
+      if (M < 1) continue;
+      std::vector<long long> offs(M);
+      for (int m = 0; m < M; ++m) offs[m] = ver_off[final_ver[j][m]];
+      STCHK(ensure(c->tmp, sizeof(long long) * M));
+      HIPCHK(hipMemcpyAsync(c->tmp.p, offs.data(), sizeof(long long) * M, hipMemcpyHostToDevice,
+                            c->stream));
+      size_t plane = (size_t)x.H * x.H;
+      int nL = level_n(x.L);
+      HIPCHK(pprs_k::from_nodes_idx(P<float>(c->elems), P<long long>(c->tmp), nL,
+                                    x.u_out + 2 * plane, x.H, (long long)plane, M,
+                                    (float)(nL - 1), c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+    }
+  }
+  HIPCHK(hipEventRecord(ev.e[3], c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
+  (void)hipEventElapsedTime(&t01, ev.e[0], ev.e[1]);
+  (void)hipEventElapsedTime(&t12, ev.e[1], ev.e[2]);
+  (void)hipEventElapsedTime(&t23, ev.e[2], ev.e[3]);
+  (void)hipEventElapsedTime(&t03, ev.e[0], ev.e[3]);
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    SeriesJob& x = jobs[j];
+    int a = job_ops[j].first, b = job_ops[j].second;
+    pprs_series_stats S;
+    memset(&S, 0, sizeof S);
+    S.n_ops_a = std::max(0, x.N - 1);
+    S.n_ops_b = n_ops_b[j];
+    S.n_scan_levels = n_lv[j];
+    double last = 0.0;
+    for (int i = a; i < b; ++i) {
+      S.flags_or |= all_stats[i].flags;
+      last = std::max(last, fin_ms[i]);
+      for (int l = 0; l <= x.L - x.m0; ++l) {
+        long long nn = (long long)level_n(x.m0 + l) * level_n(x.m0 + l);
+        S.node_steps += nn * all_stats[i].iters[l];
+        S.node_passes += nn * all_stats[i].passes[l];
+      }
+      if (x.op_stats) x.op_stats[i - a] = all_stats[i];
+    }
+    S.ms_total = t03;
+    S.ms_prepare = t01;
+    S.ms_preprocess = t12;
+    S.ms_scan = t23;
+    if (x.stats) *x.stats = S;
+    if (x.latency_ms) *x.latency_ms = t01 + t12 + last;
+  }
+  return status_from_flags(flags);
+}
+
 pprs_status pprs_prefix_register_series(pprs_ctx* c, const float* frames, int N, int H, int W,
                                         float* u_out, const pprs_params* params,
                                         pprs_series_stats* stats, pprs_pair_stats* op_stats) {
@@ -1108,114 +1377,31 @@ pprs_status pprs_prefix_register_series(pprs_ctx* c, const float* frames, int N,
   if (N < 1) return fail(PPRS_EINVAL, "N must be >= 1");
   if (!frames || !u_out) return fail(PPRS_EINVAL, "NULL frames or output pointer");
   STCHK(check_params(params, L));
-  int m0 = L - params->levels + 1;
-  int nL = level_n(L);
-  int M = N - 1;
-  size_t plane = (size_t)H * W;
-  EventSet ev;
-  for (int k = 0; k < 4; ++k) HIPCHK(hipEventCreate(&ev.e[k]));
-  HIPCHK(hipEventRecord(ev.e[0], c->stream));
-  pprs_series_stats S;
-  memset(&S, 0, sizeof S);
-  HIPCHK(pprs_k::fill(u_out, 2LL * (long long)plane, 0.f, c->stream));
-  bool warm = c->cnn != nullptr && m0 <= kWarmLevel && kWarmLevel <= L;
-  bool skip = warm && c->warm_mode == PPRS_WARM_SKIP;
-  if (M >= 1) STCHK(prepare_frames(c, frames, N, H, L, m0, N - 1));
-  HIPCHK(hipEventRecord(ev.e[1], c->stream));
-  // schedule
-  std::vector<int> plan;
-  int n_ops = 0, n_levels = 0;
-  pprs_scan_plan(params->scan, std::max(M, 0), nullptr, 0, &n_ops, &n_levels);  // sizes only
-  plan.resize(3 * (size_t)std::max(n_ops, 1));
-  if (pprs_scan_plan(params->scan, std::max(M, 0), plan.data(), n_ops, &n_ops, &n_levels) != PPRS_OK)
-    return fail(PPRS_EINVAL, "scan planning failed");
-  int flags = 0;
-  if (M >= 1) {
-    long long est = 2LL * nL * nL;
-    int slots = std::min(M, c->pool_slots);
-    // one result buffer ("version") per operator application: no result is overwritten while
-    // a later application may still read it
-    STCHK(ensure(c->elems, sizeof(float) * est * (size_t)(M + n_ops)));
-    STCHK(ensure_slots(c, slots, L, m0, params->beta));
-    float* vbuf = P<float>(c->elems);
-    std::vector<PoolOp> ops;
-    ops.reserve(M + n_ops);
-    std::vector<int> ref(M), tmpl(M), ver(M), ei(M), ek(M);
-    for (int m = 0; m < M; ++m) {
-      ref[m] = m;
-      tmpl[m] = m + 1;
-      ver[m] = m;
-      ei[m] = m;
-      ek[m] = m + 1;
-    }
-    // preprocessing: A on every neighbour pair, from the identity or the network's guess
-    PoolSpec spec;
-    std::vector<int> bad(M, 0);
-    if (warm) {
-      int n7 = level_n(kWarmLevel);
-      long long per7 = 2LL * n7 * n7;
-      STCHK(ensure(c->warm_stage, sizeof(float) * per7 * M));
-      STCHK(warm_predict(c, M, ref.data(), tmpl.data(), P<float>(c->warm_stage), per7, bad));
-      spec.stage = P<float>(c->warm_stage);
-      spec.stage_stride = per7;
-      spec.stage_level = kWarmLevel;
-    }
-    HIPCHK(hipEventRecord(ev.e[2], c->stream));
-    for (int m = 0; m < M; ++m) {
-      PoolOp o{m, m + 1, INIT_IDENTITY, -1, -1, m, m0, 0, -1};
-      if (warm) {
-        if (bad[m]) {
-          o.flags = PPRS_FLAG_FALLBACK;
-        } else {
-          o.init = INIT_PREPARED;
-          o.stage = m;
-          o.start = skip ? kWarmLevel : m0;
-        }
-      }
-      ops.push_back(o);
-    }
-    // scan: x[right] <- x[left] (.) x[right], i.e. B(x[left], x[right]) registers frame
-    // ek[right] to frame ei[left] from the composition of the two results
-    for (int i = 0; i < n_ops; ++i) {
-      int a = plan[3 * i], b = plan[3 * i + 1];
-      if (ek[a] != ei[b])
-        return fail(PPRS_EINDEX, "scan operands (%d,%d) and (%d,%d) do not share a frame", ei[a],
-                    ek[a], ei[b], ek[b]);
-      PoolOp o{ei[a], ek[b], INIT_COMPOSE, ver[a], ver[b], M + i, skip ? kWarmLevel : m0, 0, -1};
-      ops.push_back(o);
-      ver[b] = M + i;
-      ei[b] = ei[a];
-    }
-    for (int m = 0; m < M; ++m)
-      if (ei[m] != 0 || ek[m] != m + 1)
-        return fail(PPRS_EINDEX, "element %d ends as (%d,%d)", m, ei[m], ek[m]);
-    STCHK(run_pool(c, ops, slots, vbuf, est, params, spec, op_stats, &S.node_steps,
-                   &S.node_passes, &flags));
-    STCHK(ensure(c->opidx, sizeof(int) * (size_t)std::max(M, 3 * c->slots_cap)));
-    HIPCHK(hipMemcpyAsync(P<int>(c->opidx), ver.data(), sizeof(int) * M, hipMemcpyHostToDevice,
-                          c->stream));
-    HIPCHK(pprs_k::from_nodes_idx(vbuf, est, P<int>(c->opidx), nL, u_out + 2 * plane, H,
-                                  (long long)plane, M, (float)(nL - 1), c->stream));
-  } else {
-    HIPCHK(hipEventRecord(ev.e[2], c->stream));
+  std::vector<SeriesJob> jobs{SeriesJob{frames, N, H, L, L - params->levels + 1, u_out, stats,
+                                        op_stats, nullptr}};
+  return run_series_set(c, jobs, params);
+}
+
+pprs_status pprs_register_series_batch(pprs_ctx* c, int S, const float* const* frames,
+                                       const int* N, const int* side, const int* levels,
+                                       float* const* u_out, const pprs_params* params,
+                                       pprs_series_stats* stats, double* latency_ms) {
+  STCHK(enter(c));
+  if (S < 1 || !frames || !N || !side || !u_out || !params)
+    return fail(PPRS_EINVAL, "bad arguments");
+  std::vector<SeriesJob> jobs;
+  for (int j = 0; j < S; ++j) {
+    int L = frame_level(side[j], side[j]);
+    if (L < 0) return fail(PPRS_EINVAL, "series %d: side must be 2^L or 2^L+1, L in [2,10]", j);
+    if (N[j] < 1 || !frames[j] || !u_out[j]) return fail(PPRS_EINVAL, "series %d: bad arguments", j);
+    pprs_params pj = *params;
+    if (levels) pj.levels = levels[j];
+    STCHK(check_params(&pj, L));
+    jobs.push_back(SeriesJob{frames[j], N[j], side[j], L, L - pj.levels + 1, u_out[j],
+                             stats ? stats + j : nullptr, nullptr,
+                             latency_ms ? latency_ms + j : nullptr});
   }
-  HIPCHK(hipEventRecord(ev.e[3], c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
-  (void)hipEventElapsedTime(&t01, ev.e[0], ev.e[1]);
-  (void)hipEventElapsedTime(&t12, ev.e[1], ev.e[2]);
-  (void)hipEventElapsedTime(&t23, ev.e[2], ev.e[3]);
-  (void)hipEventElapsedTime(&t03, ev.e[0], ev.e[3]);
-  S.n_ops_a = M;
-  S.n_ops_b = n_ops;
-  S.n_scan_levels = n_levels;
-  S.flags_or = flags;
-  S.ms_total = t03;
-  S.ms_prepare = t01;
-  S.ms_preprocess = t12;
-  S.ms_scan = t23;
-  if (stats) *stats = S;
-  return status_from_flags(flags);
+  return run_series_set(c, jobs, params);
 }
 
 pprs_status pprs_set_metric_solve(pprs_ctx* c, int mode) {
@@ -1296,7 +1482,7 @@ pprs_status pprs_pair_inputs(pprs_ctx* c, const float* frames, int N, int H, int
   HIPCHK(hipMemcpyAsync(dref, ref, sizeof(int) * P, hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(dref + P, tmpl, sizeof(int) * P, hipMemcpyHostToDevice, c->stream));
   int S = 1 << kWarmLevel;
-  HIPCHK(pprs_cnn_api::pack_pairs(c->hd.frames[kWarmLevel], S + 1, dref, dref + P, P, out,
+  HIPCHK(pprs_cnn_api::pack_pairs(frame_level_ptr(c, 0, kWarmLevel), S + 1, dref, dref + P, P, out,
                                   c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return PPRS_OK;

@@ -256,3 +256,24 @@ def test_windowed_metric_solve_matches_exact_line_solves():
                                                                         float(d.max())))
     assert same >= len(oe) - 1
     assert float(d.pow(2).mean().sqrt()) < 1e-4 and float(d.max()) < 0.05
+
+
+def test_series_batch_equals_each_series_alone():
+    """Segmented run: three series of different sides and level counts in one slot pool give
+    each series' single-series result bit for bit (no op depends on what ran beside it)."""
+    torch = _torch()
+    import paper_1712_02533_amd as P
+    specs = [(SeriesSpec(9, 64, 2.0, 0.0, 20.0, 31), 2), (SeriesSpec(7, 128, 4.0, 1.0, 10.0, 32), 3),
+             (SeriesSpec(6, 256, 4.0, 1.0, 10.0, 33), 3)]
+    frames = [torch.tensor(make_series(sp).frames, device="cuda") for sp, _ in specs]
+    params = _gpu_params(3, scan="brent_kung")
+    levels = [lv for _, lv in specs]
+    say("series batch of sides 64, 128, 256")
+    outs, stats, lat = P.register_series_batch(frames, params=params, levels=levels)
+    say("  latencies ms", ["%.1f" % x for x in lat])
+    for f, lv, u, st in zip(frames, levels, outs, stats):
+        alone, st1, _ = P.prefix_register_series(f, params=_gpu_params(lv, scan="brent_kung"))
+        assert torch.equal(u, alone)
+        assert st.n_ops_a == st1.n_ops_a and st.n_ops_b == st1.n_ops_b
+        assert st.node_steps == st1.node_steps
+    assert all(x > 0 for x in lat)

@@ -218,3 +218,26 @@ def test_warm_series_runs_and_flags():
     rms = float(np.sqrt((d ** 2).mean()))
     say("warm (zero prediction) vs cold series: RMS %.3e px" % rms)
     assert rms < 0.05
+
+
+def test_warm_series_batch_matches_single_series():
+    """The warm start inside a segmented run: each warm-capable series (side >= 128) gets its
+    own network guesses and the same bits as when registered alone."""
+    torch = _torch()
+    import paper_1712_02533_amd as P
+    specs = [SeriesSpec(5, 128, 2.0, 0.5, 10.0, 61), SeriesSpec(4, 64, 2.0, 0.0, 20.0, 62),
+             SeriesSpec(4, 256, 2.0, 0.5, 10.0, 63)]
+    frames = [torch.tensor(make_series(sp).frames, device="cuda") for sp in specs]
+    levels = [3, 2, 3]
+    net = _constant_net(0.25, -0.25)
+    P.set_warm_start(net, max_cells=8.0, mode="refine")
+    try:
+        say("warm series batch 128, 64, 256")
+        outs, _, _ = P.register_series_batch(frames, params=P.Params(levels=3, scan="brent_kung"),
+                                             levels=levels)
+        alone = [P.prefix_register_series(f, params=P.Params(levels=lv, scan="brent_kung"))[0]
+                 for f, lv in zip(frames, levels)]
+    finally:
+        P.set_warm_start(None)
+    for u, a in zip(outs, alone):
+        assert torch.equal(u, a)
