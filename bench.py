@@ -28,6 +28,9 @@ WORKLOADS = {
                     "3 levels; Brent-Kung scan; cold start", spec=("c2",)),
     "c1": dict(name="8 frames of 64x64, drift<=2 px, 20 counts; 2 levels; sequential scan",
                spec=("c1",)),
+    "c5": dict(name="16 independent series in one run: sides {128,256,512,1024}, 32-512 "
+                    "frames, drift<=8 px, non-rigid<=1.5 px, 2-20 counts; coarsest level 6; "
+                    "Brent-Kung scans; segmented slot pool", spec=None),
 }
 
 
@@ -144,6 +147,69 @@ def warm_runs(P, frames, out, params, args, regs_per_step):
     return res
 
 
+def bench_uneven(args):
+    """The segmented workload: 16 series of mixed sides and lengths registered concurrently
+    (cold, then with the warm start); throughput over all series and per-series latency."""
+    import numpy as np
+    import torch
+    import paper_1712_02533_amd as P
+    from synth import make_series
+    from synth.blobs import uneven_batch
+    dev = torch.device("cuda", 0)
+    batch = uneven_batch()
+    t0 = time.perf_counter()
+    frames = [torch.tensor(make_series(b["spec"], workers=min(16, os.cpu_count() or 1)).frames,
+                           device=dev) for b in batch]
+    levels = [b["levels"] for b in batch]
+    log("generated %d series (%d frames) in %.1f s" % (len(frames), sum(f.shape[0] for f in frames),
+                                                       time.perf_counter() - t0))
+    params = P.Params(levels=max(levels), scan="brent_kung")
+    outs = [torch.empty((f.shape[0], 2, f.shape[1], f.shape[2]), device=dev) for f in frames]
+
+    def run(steps, tag):
+        lat, regs = [], 0
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for k in range(steps):
+            _, st, la = P.register_series_batch(frames, params=params, levels=levels, outs=outs)
+            lat += la
+            regs += sum(x.n_ops_a + x.n_ops_b for x in st)
+            log("%s step %d: latencies p50 %.0f ms, max %.0f ms" % (tag, k, np.percentile(la, 50),
+                                                                    max(la)))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        return regs / dt, 1e3 * dt / steps, lat
+
+    for w in range(args.warmup):
+        run(1, "warmup")
+    value, ms, lat = run(args.steps, "cold")
+    result = dict(
+        metric=METRIC, value=round(value, 3), unit="registrations/s", n_gpus=1,
+        steps=args.steps, warmup=args.warmup, ms_per_step=round(ms, 1), higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+        config=dict(workload=WORKLOADS["c5"]["name"], series=len(frames),
+                    sides=[int(f.shape[1]) for f in frames],
+                    frames=[int(f.shape[0]) for f in frames], levels=levels, start="cold"),
+        latency_ms=dict(p50=round(float(np.percentile(lat, 50)), 1),
+                        p99=round(float(np.percentile(lat, 99)), 1), samples=len(lat)))
+    if not args.no_warm and os.path.exists(args.weights):
+        net = P.WarmStartNet()
+        net.load(args.weights)
+        cold = [u.clone() for u in outs]
+        P.set_warm_start(net, mode="refine")
+        try:
+            run(1, "warm warmup")
+            wv, wms, wlat = run(args.steps, "warm")
+        finally:
+            P.set_warm_start(None)
+        d = [float((u - c)[:, :, 16:-16, 16:-16].pow(2).mean().sqrt()) for u, c in zip(outs, cold)]
+        result["warm"] = dict(value=round(wv, 3), ms_per_step=round(wms, 1),
+                              latency_ms=dict(p50=round(float(np.percentile(wlat, 50)), 1),
+                                              p99=round(float(np.percentile(wlat, 99)), 1)),
+                              rms_vs_cold_px_per_series=[round(x, 4) for x in d])
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,6 +230,8 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
+    if args.config == "c5":
+        return bench_uneven(args)
     import numpy as np
     import torch
     import paper_1712_02533_amd as P

@@ -257,6 +257,9 @@ pprs_status pprs_level7_targets(pprs_ctx* ctx, const float* u, int P, int H, int
    stats carry PPRS_FLAG_FALLBACK. ctx keeps the pointer: cnn must outlive its use. Returns
    PPRS_EINVAL for max_cells <= 0, an unknown mode or a network on another device. */
 pprs_status pprs_set_warm_start(pprs_ctx* ctx, pprs_cnn* cnn, double max_cells, int mode);
+/* Restricts the warm start to series whose side is 2^L (or 2^L + 1) for the bits L set in
+   level_mask (default: all), e.g. the sides the network was trained on. */
+pprs_status pprs_set_warm_sides(pprs_ctx* ctx, unsigned level_mask);
 
 #ifdef __cplusplus
 }

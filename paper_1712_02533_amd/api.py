@@ -424,6 +424,7 @@ def _cnn_sigs(lib):
         "pprs_pair_inputs": (i, [vp, vp, i, i, i, vp, vp, i, vp]),
         "pprs_level7_targets": (i, [vp, vp, i, i, i, vp]),
         "pprs_set_warm_start": (i, [vp, vp, ctypes.c_double, i]),
+        "pprs_set_warm_sides": (i, [vp, ctypes.c_uint]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -541,14 +542,22 @@ def level7_targets(u):
 WARM_MODES = {"refine": 0, "skip": 1}
 
 
-def set_warm_start(net, max_cells: float = 8.0, mode: str = "refine", device=None):
+def set_warm_start(net, max_cells: float = 8.0, mode: str = "refine", sides=None,
+                   device=None):
     """Use `net` (or None) to warm-start later series and pair-batch calls on the current
     stream's context. mode "refine": the prediction becomes the coarsest-level initial guess;
-    "skip": registrations start on level 7 from it and skip the coarser levels."""
+    "skip": registrations start on level 7 from it and skip the coarser levels. `sides`
+    (e.g. the sides the network was trained on) limits it to those frame sides."""
     import torch
     _cnn_sigs(_lib())
     dev = device or torch.device("cuda", torch.cuda.current_device())
     c = _ctx(dev)
     _check(_lib().pprs_set_warm_start(c.handle, net.handle if net else None, max_cells,
                                       WARM_MODES[mode]))
+    mask = 0xFFFFFFFF
+    if sides is not None:
+        mask = 0
+        for sd in sides:
+            mask |= 1 << (int(sd).bit_length() - 1)  # side 2^L or 2^L + 1
+    _check(_lib().pprs_set_warm_sides(c.handle, mask))
     c.warm_net = net  # the context refers to the network's device memory: keep it alive

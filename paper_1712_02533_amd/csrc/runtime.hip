@@ -99,6 +99,7 @@ struct pprs_ctx {
   pprs_cnn* cnn = nullptr;  // warm start network (not owned)
   double warm_max_cells = 8.0;
   int warm_mode = PPRS_WARM_REFINE;
+  unsigned warm_levels = ~0u;  // bit L set: series with side 2^L use the warm start
   DevBuf cnn_in, cnn_out, tmp, badflags, warm_stage;
   // slot pool: per-round index lists and staged slot states
   DevBuf pool_idx, pool_off, pool_states;
@@ -1100,7 +1101,8 @@ pprs_status pprs_register_pairs(pprs_ctx* c, const float* frames, int N, int H, 
   int nL = level_n(L);
   long long est = 2LL * nL * nL;
   size_t plane = (size_t)H * W;
-  bool warm = c->cnn != nullptr && m0 <= kWarmLevel && kWarmLevel <= L;
+  bool warm = c->cnn != nullptr && m0 <= kWarmLevel && kWarmLevel <= L &&
+              (c->warm_levels >> L & 1u);
   STCHK(prepare_frames(c, frames, N, H, L, m0, 0, &is_ref));
   int chunk = std::min(P, kPairChunk);
   STCHK(ensure(c->elems, sizeof(float) * est * chunk));
@@ -1212,7 +1214,8 @@ pprs_status run_series_set(pprs_ctx* c, std::vector<SeriesJob>& jobs, const pprs
   if (any_warm) {
     int nstage = 0;
     for (size_t j = 0; j < jobs.size(); ++j)
-      if (jobs[j].m0 <= kWarmLevel && kWarmLevel <= jobs[j].L && jobs[j].N > 1) {
+      if (jobs[j].m0 <= kWarmLevel && kWarmLevel <= jobs[j].L && jobs[j].N > 1 &&
+          (c->warm_levels >> jobs[j].L & 1u)) {
         stage_base[j] = nstage;
         nstage += jobs[j].N - 1;
       }
@@ -1237,7 +1240,16 @@ pprs_status run_series_set(pprs_ctx* c, std::vector<SeriesJob>& jobs, const pprs
                        P<float>(c->warm_stage) + (size_t)stage_base[j] * per7, per7, bad[j]));
   }
   HIPCHK(hipEventRecord(ev.e[2], c->stream));
-  for (size_t j = 0; j < jobs.size(); ++j) {
+  // op order is start priority: the cheapest series first (shortest job first keeps the
+  // latency of short series low; the pool's throughput does not depend on the order)
+  std::vector<int> order(jobs.size());
+  for (size_t j = 0; j < jobs.size(); ++j) order[j] = (int)j;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    double ca = (double)jobs[a].N * level_n(jobs[a].L) * level_n(jobs[a].L);
+    double cb = (double)jobs[b].N * level_n(jobs[b].L) * level_n(jobs[b].L);
+    return ca < cb;
+  });
+  for (int j : order) {
     SeriesJob& x = jobs[j];
     int M = x.N - 1;
     int nL = level_n(x.L);
@@ -1451,6 +1463,12 @@ pprs_status pprs_set_pool(pprs_ctx* c, int slots, int group_steps) {
     return fail(PPRS_EINVAL, "slots must be in [0, 65536] and group_steps in [0, 1024]");
   c->pool_slots = slots ? slots : 512;
   c->pool_group = group_steps ? group_steps : 8;
+  return PPRS_OK;
+}
+
+pprs_status pprs_set_warm_sides(pprs_ctx* c, unsigned level_mask) {
+  STCHK(enter(c));
+  c->warm_levels = level_mask;
   return PPRS_OK;
 }
 

@@ -34,32 +34,53 @@ def log(*a):
     print("[train]", *a, flush=True)
 
 
-def make_dataset(n_series, n_frames, seed0, params, device, workers):
+def series_specs(n_series, n_frames, seed0, mix):
+    """(SeriesSpec, levels) per training series. Default: the 512 x 512 workload's statistics,
+    one seed each from seed0. mix: sides drawn from {128, 256, 512, 1024} and mean counts from
+    U[2, 20] (the mixed-size batch workload), coarsest level 6."""
+    from dataclasses import replace
+    from synth import CONFIGS, SeriesSpec
+    if not mix:
+        base = CONFIGS["c3"]["spec"]
+        return [(replace(base, n_frames=n_frames, seed=seed0 + i), CONFIGS["c3"]["levels"])
+                for i in range(n_series)]
+    rng = np.random.Generator(np.random.PCG64(seed0))
+    out = []
+    for i in range(n_series):
+        side = int([128, 256, 512, 1024][i % 4])
+        mu = float(rng.uniform(2.0, 20.0))
+        out.append((SeriesSpec(n_frames, side, 8.0, 1.5, mu, seed0 + i),
+                    int(np.log2(side)) - 6 + 1))
+    return out
+
+
+def make_dataset(specs, device, workers):
     """Inputs X [P, 128, 128, 2] and targets T [P, 128, 128, 2] on the device."""
     import torch
     import paper_1712_02533_amd as P
-    from dataclasses import replace
-    from synth import CONFIGS, make_series
-    base = CONFIGS["c3"]["spec"]
-    specs = [replace(base, n_frames=n_frames, seed=seed0 + i) for i in range(n_series)]
+    from synth import make_series
+    n_series = len(specs)
     X, T = [], []
     last = None
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=1) as ex:
-        fut = ex.submit(make_series, specs[0], True, workers)
+        fut = ex.submit(make_series, specs[0][0], True, workers)
         for i in range(n_series):
             s = fut.result()
             if i + 1 < n_series:
-                fut = ex.submit(make_series, specs[i + 1], True, workers)
+                fut = ex.submit(make_series, specs[i + 1][0], True, workers)
             frames = torch.tensor(s.frames, device=device)
+            n_frames = frames.shape[0]
+            params = P.Params(levels=specs[i][1], scan="brent_kung")
             ref = np.arange(n_frames - 1, dtype=np.int32)
             u, st = P.register_pairs(frames, ref, ref + 1, params=params)
             X.append(P.pair_inputs(frames, ref, ref + 1))
             T.append(P.level7_targets(u))
             del u
             last = frames
-            log("series %d/%d (seed %d): %d pairs, %.0f s" %
-                (i + 1, n_series, specs[i].seed, n_frames - 1, time.perf_counter() - t0))
+            log("series %d/%d (side %d, seed %d): %d pairs, %.0f s" %
+                (i + 1, n_series, specs[i][0].side, specs[i][0].seed, n_frames - 1,
+                 time.perf_counter() - t0))
     return torch.cat(X), torch.cat(T), last
 
 
@@ -107,6 +128,8 @@ def main():
     ap.add_argument("--eval-only", action="store_true",
                     help="compare warm and cold on one series (seed --seed0) with --init")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--mix", action="store_true",
+                    help="series of mixed sides and counts (the mixed-size batch workload)")
     args = ap.parse_args()
     if args.eval_only:
         return evaluate_only(args)
@@ -117,8 +140,8 @@ def main():
     import paper_1712_02533_amd as P
     dev = torch.device("cuda", 0)
     params = P.Params(levels=4, scan="brent_kung")
-    X, T, val_frames = make_dataset(args.series, args.frames, args.seed0, params, dev,
-                                    args.workers)
+    specs = series_specs(args.series, args.frames, args.seed0, args.mix)
+    X, T, val_frames = make_dataset(specs, dev, args.workers)
     n_val = args.val_series * (args.frames - 1)
     Xv, Tv = X[-n_val:], T[-n_val:]
     Xt, Tt = X[:-n_val], T[:-n_val]
@@ -165,12 +188,14 @@ def main():
             break
     meta = dict(series=args.series, frames=args.frames, seeds=[args.seed0,
                 args.seed0 + args.series - 1], val_series=args.val_series, batch=args.batch,
+                sides=sorted({sp.side for sp, _ in specs}), mix=args.mix,
                 lr=args.lr, epochs=len(history), best_val_rms_cells=best[0],
                 train_seconds=time.perf_counter() - t0, history=history)
     _save(args.out, best[1], meta)
     log("saved %s (best val RMS %.4f cells)" % (args.out, best[0]))
     net.set_params(best[1])
-    meta["warm_vs_cold"] = warm_vs_cold(net, val_frames, params)[0]
+    meta["warm_vs_cold"] = warm_vs_cold(
+        net, val_frames, P.Params(levels=specs[-1][1], scan="brent_kung"))[0]
     _save(args.out, best[1], meta)
 
 
@@ -204,47 +229,46 @@ def warm_vs_cold(net, frames, params, border=16):
 
 
 def evaluate_only(args):
-    """Warm vs cold of saved weights on one fresh series (seed args.seed0)."""
+    """Warm vs cold of saved weights on fresh series (seed args.seed0): one series with the
+    512 x 512 workload's statistics, or with --mix one per side of the mixed workload. Accuracy
+    against the generator's analytic displacement on a sample of pairs."""
     import torch
     import paper_1712_02533_amd as P
-    from dataclasses import replace
-    from synth import CONFIGS, make_series
+    from synth import make_series, ground_truth_pair
     dev = torch.device("cuda", 0)
-    params = P.Params(levels=4, scan="brent_kung")
-    spec = replace(CONFIGS["c3"]["spec"], n_frames=args.frames, seed=args.seed0)
-    series = make_series(spec, workers=args.workers)
-    frames = torch.tensor(series.frames, device=dev)
     net = P.WarmStartNet(device=dev)
     net.load(args.init)
-    ref = np.arange(args.frames - 1, dtype=np.int32)
-    X = P.pair_inputs(frames, ref, ref + 1)
-    u, _ = P.register_pairs(frames, ref, ref + 1, params=params)
-    rms, good = evaluate(net, X, P.level7_targets(u), 64)
-    log("seed %d: prediction RMS %.4f cells, %.1f%% within 0.5 cell" % (args.seed0, rms,
-                                                                      100 * good))
-    res, out = warm_vs_cold(net, frames, params)
-    res.update(seed=args.seed0, prediction_rms_cells=rms, prediction_within_half_cell=good)
-    # against the generator's analytic displacement: the pairs where warm and cold differ most,
-    # and pairs spread over the series
-    from synth import ground_truth_pair
-    b = 24
-    diff = (out["refine"][0] - out["cold"][0])[:, :, b:-b, b:-b].pow(2).mean(dim=(1, 2, 3))
-    worst = torch.argsort(diff, descending=True)[:12].cpu().numpy().tolist()
-    spread = list(range(0, len(ref), max(1, len(ref) // 12)))[:12]
-    gt_rows = []
-    for m in worst + spread:
-        g = torch.tensor(ground_truth_pair(series, m, m + 1), device=dev, dtype=torch.float32)
-        row = dict(pair=m)
-        for mode in ("cold", "refine", "skip"):
-            e = (out[mode][0][m] - g)[:, b:-b, b:-b]
-            row[mode] = round(float(e.pow(2).mean().sqrt()), 4)
-        gt_rows.append(row)
-        log("pair %d: RMS error vs truth (px) cold %.4f refine %.4f skip %.4f" %
-            (m, row["cold"], row["refine"], row["skip"]))
-    res["ground_truth_rms_px"] = gt_rows
+    results = []
+    specs = series_specs(4 if args.mix else 1, args.frames, args.seed0, args.mix)
+    for spec, levels in specs:
+        params = P.Params(levels=levels, scan="brent_kung")
+        series = make_series(spec, workers=args.workers)
+        frames = torch.tensor(series.frames, device=dev)
+        n = spec.n_frames
+        ref = np.arange(n - 1, dtype=np.int32)
+        X = P.pair_inputs(frames, ref, ref + 1)
+        u, _ = P.register_pairs(frames, ref, ref + 1, params=params)
+        rms, good = evaluate(net, X, P.level7_targets(u), 64)
+        log("side %d seed %d: prediction RMS %.4f cells, %.1f%% within 0.5 cell" %
+            (spec.side, spec.seed, rms, 100 * good))
+        res, out = warm_vs_cold(net, frames, params)
+        res.update(side=spec.side, seed=spec.seed, prediction_rms_cells=rms,
+                   prediction_within_half_cell=good)
+        b = max(8, spec.side // 20)
+        sample = list(range(0, len(ref), max(1, len(ref) // 16)))[:16]
+        err = {k: [] for k in ("cold", "refine", "skip")}
+        for m in sample:
+            g = torch.tensor(ground_truth_pair(series, m, m + 1), device=dev, dtype=torch.float32)
+            for mode in err:
+                e = (out[mode][0][m] - g)[:, b:-b, b:-b]
+                err[mode].append(float(e.pow(2).mean().sqrt()))
+        res["truth_rms_px"] = {k: dict(mean=float(np.mean(v)), off_by_1px=int(np.sum(
+            np.array(v) > 1.0)), pairs=len(v)) for k, v in err.items()}
+        log("side %d: RMS error vs truth %s" % (spec.side, json.dumps(res["truth_rms_px"])))
+        results.append(res)
     if args.out:
         with open(args.out, "w") as f:
-            json.dump(res, f, indent=1)
+            json.dump(results, f, indent=1)
 
 
 def _save(path, params, meta):
