@@ -192,9 +192,10 @@ def bench_uneven(args):
                     frames=[int(f.shape[0]) for f in frames], levels=levels, start="cold"),
         latency_ms=dict(p50=round(float(np.percentile(lat, 50)), 1),
                         p99=round(float(np.percentile(lat, 99)), 1), samples=len(lat)))
-    if not args.no_warm and os.path.exists(args.weights):
+    weights = os.path.join(ROOT, "paper_1712_02533_amd", "weights", "warmstart_mixed.safetensors")
+    if not args.no_warm and os.path.exists(weights):
         net = P.WarmStartNet()
-        net.load(args.weights)
+        net.load(weights)
         cold = [u.clone() for u in outs]
         P.set_warm_start(net, mode="refine")
         try:
