@@ -171,6 +171,7 @@ typedef struct {
   int grid_prolong;  /* workgroups of the prolongation kernel (default 2048) */
   int tile_grad;     /* gradient tile shape: 0 = 32x16 (default), 1 = 64x8, 2 = 128x4,
                         3 = 64x16 nodes */
+  int smooth_lines;  /* columns per workgroup of the column solves: 8, 16 (default) or 32 */
 } pprs_tuning;
 
 /* Reads / replaces the launch shape of ctx (host struct). PPRS_EINVAL for out-of-range

@@ -50,7 +50,7 @@ class _CSeriesStats(ctypes.Structure):
 class _CTuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int) for n in ("pool_slots", "pool_group", "grid_energy",
                                             "grid_grad", "grid_smooth", "grid_prolong",
-                                            "tile_grad")]
+                                            "tile_grad", "smooth_lines")]
 
 
 TUNING_KEYS = [n for n, _ in _CTuning._fields_]

@@ -17,6 +17,7 @@ import time
 
 CANDIDATES = {
     "tile_grad": [1, 2, 3, 0],
+    "smooth_lines": [32, 8, 16],
     "pool_group": [4, 8, 16, 32],
     "grid_grad": [1024, 2048, 4096],
     "grid_energy": [1024, 2048, 4096],

@@ -31,7 +31,7 @@ enum { WK_PROLONG = 0, WK_EVAL = 1, WK_GRAD = 2, WK_SMY = 3, WK_SMX = 4, WK_LADD
 #define PT_X 64   // prolongation: fine nodes per tile along x
 #define PT_Y 8
 // smoother: lines per workgroup, chosen per level so one strip stays under 40 KB of LDS
-#define SM_LDS_MAX_FLOATS 9728
+#define SM_LDS_MAX_FLOATS 33825  // column-solve strip in LDS: n (lines + 1) floats, <= 135 KB
 #define SW_T 64          // windowed metric solve: output nodes per tile along each axis
 #define SW_THREADS 128
 #define SM_THREADS 256

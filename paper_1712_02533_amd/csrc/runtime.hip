@@ -109,6 +109,8 @@ struct pprs_ctx {
   int grid_energy = 2048, grid_grad = 2048, grid_smooth = 1024, grid_prolong = 2048;
   bool smooth_window = false;  // windowed one-pass metric solve (opt-in, where beta allows)
   int tile_grad = 0;          // gradient kernel tile shape (pprs_k::grad_tile variant)
+  int smooth_lines = 16;      // column-strip width of the line solves (8, 16 or 32)
+  size_t lds_smooth[2] = {0, 0};
   BatchDesc hd;
   int slots_cap = 0, slots_L = -1, slots_m0 = -1;
   double coef_beta = -1.0;
@@ -184,35 +186,46 @@ void fill_geom(LevelGeom& g, int l, int coef_off) {
   g.tiles_grad = 0;  // set per run from the gradient tile shape (set_grad_tiles)
   g.tiles_elem = ((n - 1 + ET_X - 1) / ET_X) * ((n - 1 + ET_Y - 1) / ET_Y);
   g.tiles_prol = ((n + PT_X - 1) / PT_X) * ((n + PT_Y - 1) / PT_Y);
-  int lines = 32;
-  while (lines > 1 && (long long)n * (lines + 1) > SM_LDS_MAX_FLOATS) lines /= 2;
-  g.sm_lines = lines;
-  g.sm_items = (n + lines - 1) / lines;
+  // column strips: set per run from the tuned width (set_run_geometry); 8 lines bound the
+  // item count the partial records are sized for
+  g.sm_lines = 8;
+  g.sm_items = (n + 7) / 8;
   g.coef_off = coef_off;
   g.sw_tiles = std::max(1, (n - 1) / SW_T);
 }
 
-size_t smooth_lds_bytes(const BatchDesc& hd) {
+// Dynamic LDS of the line solves: dir 0 stages a strip of columns (n (lines + 1) floats),
+// dir 1 the rows each wavefront solves.
+size_t smooth_lds_bytes(const BatchDesc& hd, int dir) {
   size_t mx = 0;
   for (int l = hd.coarsest; l <= hd.finest; ++l) {
     const LevelGeom& g = hd.geom[l];
     size_t C = (g.n + 63) / 64;
     size_t Rw = C <= 9 ? 4 : 2;  // lines per wavefront (SmoothR in kernels.hip)
     size_t a = (size_t)g.n * (g.sm_lines + 1), b = (BLOCK / 64) * Rw * (64 * C + 1);
-    mx = std::max(mx, std::max(a, b));
+    mx = std::max(mx, dir == 0 ? a : b);
   }
   return mx * sizeof(float);
 }
 
-// Gradient tiles per level for the context's tile shape (before each batch is uploaded).
-void set_grad_tiles(pprs_ctx* c) {
+// Per-run geometry from the launch shape (before each batch is uploaded): gradient tiles of
+// the chosen tile shape, column-strip width of the line solves (LDS permitting).
+pprs_status set_grad_tiles(pprs_ctx* c) {
   int tx, ty;
   pprs_k::grad_tile(c->tile_grad, &tx, &ty);
   BatchDesc& hd = c->hd;
   for (int l = hd.coarsest; l <= hd.finest; ++l) {
     int n = level_n(l);
-    hd.geom[l].tiles_grad = ((n + tx - 1) / tx) * ((n + ty - 1) / ty);
+    LevelGeom& g = hd.geom[l];
+    g.tiles_grad = ((n + tx - 1) / tx) * ((n + ty - 1) / ty);
+    int lines = c->smooth_lines;
+    while (lines > 8 && (long long)n * (lines + 1) > SM_LDS_MAX_FLOATS) lines /= 2;
+    g.sm_lines = lines;
+    g.sm_items = (n + lines - 1) / lines;
   }
+  size_t lds = std::max(smooth_lds_bytes(hd, 0), smooth_lds_bytes(hd, 1));
+  if (lds > 65536) HIPCHK(pprs_k::set_smooth_lds(lds));
+  return PPRS_OK;
 }
 
 // Halo of the windowed metric solve for beta: the LU recurrences of S1 = M1 + (beta h)^2 K1
@@ -455,7 +468,8 @@ pprs_status tk_collect(pprs_ctx* c) {
     STCHK(tk_end(c, stop_));              \
   } while (0)
 
-pprs_status launch_step(pprs_ctx* c, BatchDesc* d, int ladder_k, size_t lds) {
+pprs_status launch_step(pprs_ctx* c, BatchDesc* d, int ladder_k) {
+  size_t lds0 = c->lds_smooth[0], lds1 = c->lds_smooth[1];
   TIMED(TK_PLAN, pprs_k::plan(d, c->stream));
   TIMED(TK_PROLONG, pprs_k::prolong(d, c->grid_prolong, c->stream));
   TIMED(TK_EVAL, pprs_k::energy(d, 0, ladder_k, c->grid_energy, c->stream));
@@ -464,8 +478,8 @@ pprs_status launch_step(pprs_ctx* c, BatchDesc* d, int ladder_k, size_t lds) {
   if (c->hd.smooth_halo) {
     TIMED(TK_SMW, pprs_k::smooth_win(d, c->hd.smooth_halo, c->grid_smooth, c->stream));
   } else {
-    TIMED(TK_SMY, pprs_k::smooth(d, 0, c->grid_smooth, lds, c->stream));
-    TIMED(TK_SMX, pprs_k::smooth(d, 1, c->grid_smooth, lds, c->stream));
+    TIMED(TK_SMY, pprs_k::smooth(d, 0, c->grid_smooth, lds0, c->stream));
+    TIMED(TK_SMX, pprs_k::smooth(d, 1, c->grid_smooth, lds1, c->stream));
   }
   TIMED(TK_FIN, pprs_k::smooth_fin(d, kGridFin, c->stream));
   TIMED(TK_LADDER, pprs_k::energy(d, 1, ladder_k, c->grid_energy, c->stream));
@@ -496,7 +510,7 @@ pprs_status run_batch(pprs_ctx* c, int n, const int* ref, const int* tmpl, InitK
   hd.tau_min_rel = p->tau_min_rel;
   hd.eps = p->eps;
   hd.iter_max = p->iter_max;
-  set_grad_tiles(c);
+  STCHK(set_grad_tiles(c));
   BatchDesc* d = P<BatchDesc>(c->desc);
   HIPCHK(hipMemcpyAsync(d, &hd, sizeof(BatchDesc), hipMemcpyHostToDevice, c->stream));
   if (start < m0 || start > L) start = m0;
@@ -543,7 +557,8 @@ pprs_status run_batch(pprs_ctx* c, int n, const int* ref, const int* tmpl, InitK
     }
   }
   // steps
-  size_t lds = smooth_lds_bytes(hd);
+  c->lds_smooth[0] = smooth_lds_bytes(hd, 0);
+  c->lds_smooth[1] = smooth_lds_bytes(hd, 1);
   int K = p->ladder_k;
   long long passes_per_iter = 2 + (long long)ceil(log2(1.0 / p->tau_min_rel) / (2 * K + 1));
   long long max_steps =
@@ -551,7 +566,7 @@ pprs_status run_batch(pprs_ctx* c, int n, const int* ref, const int* tmpl, InitK
   long long done_steps = 0;
   int group = 4;
   while (true) {
-    for (int k = 0; k < group; ++k) STCHK(launch_step(c, d, K, lds));
+    for (int k = 0; k < group; ++k) STCHK(launch_step(c, d, K));
     done_steps += group;
     int active = 0;
     HIPCHK(hipMemcpyAsync(&active, &d->active, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -727,7 +742,7 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
   hd.tau_min_rel = p->tau_min_rel;
   hd.eps = p->eps;
   hd.iter_max = p->iter_max;
-  set_grad_tiles(c);
+  STCHK(set_grad_tiles(c));
   BatchDesc* d = P<BatchDesc>(c->desc);
   HIPCHK(hipMemcpyAsync(d, &hd, sizeof(BatchDesc), hipMemcpyHostToDevice, c->stream));
   for (const PoolOp& o : ops)
@@ -769,7 +784,8 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
   std::vector<int> slot_op(S, -1), free_slots;
   for (int s = S - 1; s >= 0; --s) free_slots.push_back(s);
   std::vector<long long> nodes((size_t)S * WK_COUNT);
-  size_t lds = smooth_lds_bytes(hd);
+  c->lds_smooth[0] = smooth_lds_bytes(hd, 0);
+  c->lds_smooth[1] = smooth_lds_bytes(hd, 1);
   int K = p->ladder_k;
   long long passes_per_iter = 2 + (long long)ceil(log2(1.0 / p->tau_min_rel) / (2 * K + 1));
   long long per_op_steps =
@@ -790,7 +806,7 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     pprs_status cs = PPRS_OK;
-    for (int k = 0; k < G && cs == PPRS_OK; ++k) cs = launch_step(c, d, K, lds);
+    for (int k = 0; k < G && cs == PPRS_OK; ++k) cs = launch_step(c, d, K);
     hipError_t ce = hipStreamEndCapture(c->stream, &g);
     if (cs != PPRS_OK) {
       if (g) (void)hipGraphDestroy(g);
@@ -889,7 +905,7 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
     if (graph.exec) {
       HIPCHK(hipGraphLaunch(graph.exec, c->stream));
     } else {
-      for (int k = 0; k < G; ++k) STCHK(launch_step(c, d, K, lds));
+      for (int k = 0; k < G; ++k) STCHK(launch_step(c, d, K));
     }
     done_steps += G;
     // 3. poll: retire finished slots, release their dependents
@@ -1437,15 +1453,16 @@ pprs_status pprs_get_tuning(pprs_ctx* c, pprs_tuning* t) {
   t->grid_smooth = c->grid_smooth;
   t->grid_prolong = c->grid_prolong;
   t->tile_grad = c->tile_grad;
+  t->smooth_lines = c->smooth_lines;
   return PPRS_OK;
 }
 
 pprs_status pprs_set_tuning(pprs_ctx* c, const pprs_tuning* t) {
   if (!c || !t) return fail(PPRS_EINVAL, "NULL argument");
-  const int v[7] = {t->pool_slots, t->pool_group, t->grid_energy, t->grid_grad, t->grid_smooth,
-                    t->grid_prolong, t->tile_grad};
-  const int hi[7] = {65536, 1024, 65536, 65536, 65536, 65536, 3};
-  for (int k = 0; k < 7; ++k)
+  const int v[8] = {t->pool_slots, t->pool_group, t->grid_energy, t->grid_grad, t->grid_smooth,
+                    t->grid_prolong, t->tile_grad, t->smooth_lines};
+  const int hi[8] = {65536, 1024, 65536, 65536, 65536, 65536, 3, 32};
+  for (int k = 0; k < 8; ++k)
     if (v[k] < 0 || v[k] > hi[k]) return fail(PPRS_EINVAL, "tuning value %d out of range", k);
   c->pool_slots = t->pool_slots ? t->pool_slots : 512;
   c->pool_group = t->pool_group ? t->pool_group : 8;
@@ -1454,6 +1471,10 @@ pprs_status pprs_set_tuning(pprs_ctx* c, const pprs_tuning* t) {
   c->grid_smooth = t->grid_smooth ? t->grid_smooth : 1024;
   c->grid_prolong = t->grid_prolong ? t->grid_prolong : 2048;
   c->tile_grad = t->tile_grad;
+  if (t->smooth_lines != 0 && t->smooth_lines != 8 && t->smooth_lines != 16 &&
+      t->smooth_lines != 32)
+    return fail(PPRS_EINVAL, "smooth_lines must be 8, 16 or 32");
+  c->smooth_lines = t->smooth_lines ? t->smooth_lines : 16;
   return PPRS_OK;
 }
 

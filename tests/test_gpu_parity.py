@@ -223,7 +223,7 @@ def test_launch_shape_does_not_change_results():
     u1, _, _ = P.prefix_register_series(frames, params=params)
     try:
         P.set_tuning(dict(grid_energy=333, grid_grad=97, grid_smooth=61, grid_prolong=5,
-                          pool_group=5, tile_grad=2))
+                          pool_group=5, tile_grad=2, smooth_lines=32))
         say("series 8 x 128 with odd grid sizes", P.get_tuning())
         u2, _, _ = P.prefix_register_series(frames, params=params)
     finally:
