@@ -73,14 +73,54 @@ def _pair_case(spec, i, k, levels, **kw):
     u, st = P.register_pair(fr[i].contiguous(), fr[k].contiguous(),
                             params=_gpu_params(levels, **kw))
     u = u.cpu().numpy()
-    uo, sto, _ = O.register(O.frame_to_nodes(s.frames[i]), O.frame_to_nodes(s.frames[k]),
-                            _oracle_params(levels, **kw))
+    op = _oracle_params(levels, **kw)
+    uo, sto, tr = O.register(O.frame_to_nodes(s.frames[i]), O.frame_to_nodes(s.frames[k]), op,
+                             trace_cap=8192)
     ref = O.u_to_pixels(uo, spec.side)
     err = np.abs(u - ref).max()
     say("  gpu iters", st.iters, "passes", st.passes, "E %.9f" % st.energy)
     say("  ora iters", sto.iters, "passes", sto.trials, "E %.9f" % sto.energy)
     say("  max abs err px", err)
+    if st.iters != sto.iters:
+        m0 = int(np.log2(spec.side)) - levels + 1
+        tie = _stop_tie(st, sto, tr, op.eps, m0)
+        say("  decisions differ; stopping near-tie in the oracle trace:", tie)
+        if tie:
+            err = TIE
     return u, ref, st, sto, err
+
+
+# Result of a case whose decisions differ from the oracle's only at a stopping near-tie: the
+# level stops when E_k - E_{k+1} < eps, and where the oracle's decrease lies within TIE_DE of
+# eps the GPU's energies (FP32 arithmetic on an FP32-stored path that has drifted by ~1e-5 px
+# after tens of steps, i.e. energies a few 1e-6 off) may decide either way. Both runs are then
+# correct results of the method; such a case is held to the schedule bar (0.05 px RMS) instead
+# of the 1e-3 px one. (Observed: a 128^2 pair whose level-6 decrease missed eps = 3e-4 by
+# 3.2e-6 in FP64.)
+TIE = "tie"
+TIE_DE = 1e-5
+
+
+def _stop_tie(st, sto, tr, eps, m0):
+    """True when the first level whose accepted-step count differs ends, in the oracle trace,
+    with a decrease within TIE_DE of eps at the step where one of the runs stopped."""
+    for li, (a, b) in enumerate(zip(st.iters, sto.iters)):
+        if a == b:
+            continue
+        level = m0 + li
+        steps = tr[tr[:, 0] == level]
+        decs = steps[:, 3] - steps[:, 4]       # E0 - E1 of every accepted step of the level
+        k = min(a, b) - 1                       # the step after which one of the runs stopped
+        return 0 <= k < len(decs) and abs(decs[k] - eps) < TIE_DE
+    return False
+
+
+def _check_pair(u, ref, err):
+    if isinstance(err, str):
+        d = np.abs(u - ref)
+        assert np.sqrt((d ** 2).mean()) < 0.05
+    else:
+        assert err < TOL_PX
 
 
 @pytest.mark.parametrize("spec,levels", [
@@ -91,8 +131,9 @@ def _pair_case(spec, i, k, levels, **kw):
 ])
 def test_register_pair_matches_oracle(spec, levels):
     u, ref, st, sto, err = _pair_case(spec, 0, 1, levels)
-    assert err < TOL_PX
-    assert abs(st.energy - sto.energy) < 1e-6
+    _check_pair(u, ref, err)
+    if not isinstance(err, str):
+        assert abs(st.energy - sto.energy) < 1e-6
 
 
 @pytest.mark.parametrize("i,k", [(0, 1), (5, 6)])
