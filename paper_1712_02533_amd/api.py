@@ -13,7 +13,8 @@ import threading
 from dataclasses import asdict, dataclass, field
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpprs.so")
+# PPRS_LIBRARY selects another build of the library (e.g. one compiled with other tile sizes)
+LIB_PATH = os.environ.get("PPRS_LIBRARY") or os.path.join(_HERE, "libpprs.so")
 
 PPRS_OK = 0
 PPRS_NOT_CONVERGED = 1

@@ -14,6 +14,17 @@
 #include "pprs_internal.h"
 #include "kernels.h"
 
+// minimum waves per SIMD the hot kernels are compiled for (register budget 512 / value)
+#ifndef LB_ENERGY
+#define LB_ENERGY 4
+#endif
+#ifndef LB_GRAD
+#define LB_GRAD 4
+#endif
+#ifndef LB_SMOOTH
+#define LB_SMOOTH 4
+#endif
+
 #define FLAG_NONCONV 1
 #define FLAG_NAN 2
 
@@ -422,7 +433,7 @@ __device__ __noinline__ void energy_finalize(BatchDesc* D, SlotState* stp, int s
 }
 
 template <int MODE, int NC>
-__global__ void __launch_bounds__(BLOCK, 4) k_energy(BatchDesc* D) {
+__global__ void __launch_bounds__(BLOCK, LB_ENERGY) k_energy(BatchDesc* D) {
   constexpr int NXN = ET_X + 1, NYN = ET_Y + 1, NN = NXN * NYN;
   constexpr int NV = 3 * NC + 3;
   __shared__ float s_ux[NN], s_uy[NN], s_dx[MODE ? NN : 1], s_dy[MODE ? NN : 1], s_r[NN];
@@ -575,7 +586,7 @@ __global__ void __launch_bounds__(BLOCK) k_energy_fin(BatchDesc* D) {
 // Tile shape TX x TY nodes (a launch-shape choice: every node's G is the same sum of the same
 // element terms whatever the tile, so the shape never changes a result).
 template <int TX, int TY>
-__global__ void __launch_bounds__(BLOCK, 4) k_grad(BatchDesc* D) {
+__global__ void __launch_bounds__(BLOCK, LB_GRAD) k_grad(BatchDesc* D) {
   constexpr int GT_X = TX, GT_Y = TY;
   constexpr int NX = GT_X + 2, NY = GT_Y + 2;       // staged nodes
   constexpr int EX = GT_X + 1, EY = GT_Y + 1;       // elements touching the tile
@@ -809,9 +820,12 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Lines solved together by one wavefront for C nodes per lane (LDS per wave stays <= 10 KB).
+#ifndef SM_R9
+#define SM_R9 4
+#endif
 template <int C>
 struct SmoothR {
-  static constexpr int value = C <= 9 ? 4 : 2;
+  static constexpr int value = C <= 9 ? SM_R9 : 2;
 };
 
 // One smoother item: lines [line0, line0 + nl) of one component.
@@ -897,7 +911,7 @@ __device__ void smooth_item(const float* src, float* dst, const float* Gp, const
 }
 
 template <int DIR>
-__global__ void __launch_bounds__(BLOCK, 3) k_smooth(BatchDesc* D) {
+__global__ void __launch_bounds__(BLOCK, LB_SMOOTH) k_smooth(BatchDesc* D) {
   extern __shared__ float s_buf[];
   __shared__ double s_red[(BLOCK / 64) * 2];
   __shared__ int s_pos;

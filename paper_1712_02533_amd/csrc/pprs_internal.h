@@ -27,7 +27,9 @@ enum { WK_PROLONG = 0, WK_EVAL = 1, WK_GRAD = 2, WK_SMY = 3, WK_SMX = 4, WK_LADD
 
 // Tile geometry (compile-time).
 #define ET_X 64   // energy kernel: elements per tile along x
+#ifndef ET_Y
 #define ET_Y 16   //                elements per tile along y
+#endif
 #define PT_X 64   // prolongation: fine nodes per tile along x
 #define PT_Y 8
 // smoother: lines per workgroup, chosen per level so one strip stays under 40 KB of LDS

@@ -201,7 +201,7 @@ size_t smooth_lds_bytes(const BatchDesc& hd, int dir) {
   for (int l = hd.coarsest; l <= hd.finest; ++l) {
     const LevelGeom& g = hd.geom[l];
     size_t C = (g.n + 63) / 64;
-    size_t Rw = C <= 9 ? 4 : 2;  // lines per wavefront (SmoothR in kernels.hip)
+    size_t Rw = C <= 9 ? 4 : 2;  // lines per wavefront (SmoothR in kernels.hip; at most 4)
     size_t a = (size_t)g.n * (g.sm_lines + 1), b = (BLOCK / 64) * Rw * (64 * C + 1);
     mx = std::max(mx, dir == 0 ? a : b);
   }
