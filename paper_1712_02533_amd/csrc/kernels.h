@@ -12,7 +12,7 @@ hipError_t smooth_fin(BatchDesc* d, int grid, hipStream_t st);
 // gradient tile variants: 0 = 32x16, 1 = 64x8, 2 = 128x4, 3 = 64x16 nodes
 void grad_tile(int variant, int* tx, int* ty);
 hipError_t grad(BatchDesc* d, int variant, int grid, hipStream_t st);
-hipError_t smooth(BatchDesc* d, int dir, int grid, size_t lds_bytes, hipStream_t st);
+hipError_t smooth(BatchDesc* d, int dir, bool big, int grid, size_t lds_bytes, hipStream_t st);
 hipError_t set_smooth_lds(size_t bytes);
 // windowed metric solve (both axes in one launch); halo 16 or 24
 hipError_t smooth_win(BatchDesc* d, int halo, int grid, hipStream_t st);

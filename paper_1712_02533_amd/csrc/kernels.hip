@@ -7,8 +7,9 @@
 //   k_energy   - energy at a set of step sizes (line-search pass) or at the current u
 //   k_grad     - applies the accepted step and computes the gradient G
 //   k_smooth   - metric solve d = (S1^-1 (x) S1^-1) G, one direction per launch
-// A per-slot "finaliser" runs in the last workgroup that finishes a slot's items of a kind
-// (atomic ticket), sums the tile partials in a fixed order and advances the slot's state.
+//   k_*_fin    - per-slot finalisers, launched after a pass: sum the pass's FP64 tile partials
+//                in tile order and advance the slot's state (the kernel boundary orders them
+//                after every tile; no fences or tickets inside a pass)
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include "pprs_internal.h"
@@ -464,27 +465,39 @@ __global__ void __launch_bounds__(BLOCK, LB_ENERGY) k_energy(BatchDesc* D) {
     float inv_h = (float)(n - 1);
     int ntx = (n - 1 + ET_X - 1) / ET_X;
     int e0x = (t % ntx) * ET_X, e0y = (t / ntx) * ET_Y;
-    // stage the nodes of the tile's elements
+    // stage the nodes of the tile's elements: every load of a lane is issued before the first
+    // LDS store (out-of-range nodes load node 0 and store zero), so a lane waits for memory
+    // once per item instead of once per strided round
     __syncthreads();
-    for (int k = threadIdx.x; k < NN; k += BLOCK) {
-      int a = e0y + k / NXN, b = e0x + k % NXN;
-      float ux = 0.f, uy = 0.f, dx = 0.f, dy = 0.f, r = 0.f;
-      if (a < n && b < n) {
-        size_t i = (size_t)a * n + b;
-        ux = gld(u, i);
-        uy = gld(u, nn + i);
-        r = gld(R, i);
+    {
+      constexpr int SIT = (NN + BLOCK - 1) / BLOCK;
+      float vux[SIT], vuy[SIT], vr[SIT], vdx[SIT], vdy[SIT];
+#pragma unroll
+      for (int it = 0; it < SIT; ++it) {
+        int k = threadIdx.x + it * BLOCK;
+        int a = e0y + k / NXN, b = e0x + k % NXN;
+        size_t i = (k < NN && a < n && b < n) ? (size_t)a * n + b : 0;
+        vux[it] = gld(u, i);
+        vuy[it] = gld(u, nn + i);
+        vr[it] = gld(R, i);
         if (MODE) {
-          dx = gld(d, i);
-          dy = gld(d, nn + i);
+          vdx[it] = gld(d, i);
+          vdy[it] = gld(d, nn + i);
         }
       }
-      s_ux[k] = ux;
-      s_uy[k] = uy;
-      s_r[k] = r;
-      if (MODE) {
-        s_dx[k] = dx;
-        s_dy[k] = dy;
+#pragma unroll
+      for (int it = 0; it < SIT; ++it) {
+        int k = threadIdx.x + it * BLOCK;
+        int a = e0y + k / NXN, b = e0x + k % NXN;
+        if (k >= NN) break;
+        bool ok = a < n && b < n;
+        s_ux[k] = ok ? vux[it] : 0.f;
+        s_uy[k] = ok ? vuy[it] : 0.f;
+        s_r[k] = ok ? vr[it] : 0.f;
+        if (MODE) {
+          s_dx[k] = ok ? vdx[it] : 0.f;
+          s_dy[k] = ok ? vdy[it] : 0.f;
+        }
       }
     }
     __syncthreads();
@@ -606,7 +619,9 @@ __global__ void __launch_bounds__(BLOCK, LB_GRAD) k_grad(BatchDesc* D) {
     const float* u = slot_u(D, s, l, stp->ub);
     float* un = slot_u(D, s, l, stp->ub ^ 1);
     const float* d = D->dbuf + (size_t)s * D->slot_f_stride;
-    float* G = D->gbuf + (size_t)s * D->slot_f_stride;
+    float* G = D->gbuf + (size_t)s * D->slot_p_stride;
+    const int gpi = row_pitch(n);
+    const size_t gpn = (size_t)n * gpi;
     const float* R = D->pyr + D->frame_off[(size_t)stp->ref * PPRS_MAXL + l];
     const float* T = D->pyr + D->frame_off[(size_t)stp->tmpl * PPRS_MAXL + l];
     float tau = (float)stp->tau_pend;
@@ -618,23 +633,42 @@ __global__ void __launch_bounds__(BLOCK, LB_GRAD) k_grad(BatchDesc* D) {
     float w = 0.25f / ((float)(n - 1) * (float)(n - 1));
     int ntx = (n + GT_X - 1) / GT_X;
     int x0 = (t % ntx) * GT_X, y0 = (t / ntx) * GT_Y;
+    // stage u - tau d and R with the halo: all loads of a lane first, then the LDS stores
     __syncthreads();
-    for (int k = threadIdx.x; k < NX * NY; k += BLOCK) {
-      int a = y0 - 1 + k / NX, b = x0 - 1 + k % NX;
-      float ux = 0.f, uy = 0.f, r = 0.f;
-      if (a >= 0 && a < n && b >= 0 && b < n) {
-        size_t i = (size_t)a * n + b;
-        ux = gld(u, i);
-        uy = gld(u, nn + i);
-        if (tau != 0.f) {
-          ux -= tau * gld(d, i);
-          uy -= tau * gld(d, nn + i);
-        }
-        r = gld(R, i);
+    {
+      constexpr int SIT = (NX * NY + BLOCK - 1) / BLOCK;
+      float vux[SIT], vuy[SIT], vr[SIT], vdx[SIT], vdy[SIT];
+      const bool mv = tau != 0.f;
+#pragma unroll
+      for (int it = 0; it < SIT; ++it) {
+        int k = threadIdx.x + it * BLOCK;
+        int a = y0 - 1 + k / NX, b = x0 - 1 + k % NX;
+        size_t i = (k < NX * NY && a >= 0 && a < n && b >= 0 && b < n) ? (size_t)a * n + b : 0;
+        vux[it] = gld(u, i);
+        vuy[it] = gld(u, nn + i);
+        vr[it] = gld(R, i);
+        vdx[it] = mv ? gld(d, i) : 0.f;
+        vdy[it] = mv ? gld(d, nn + i) : 0.f;
       }
-      s_ux[k] = ux;
-      s_uy[k] = uy;
-      s_r[k] = r;
+#pragma unroll
+      for (int it = 0; it < SIT; ++it) {
+        int k = threadIdx.x + it * BLOCK;
+        int a = y0 - 1 + k / NX, b = x0 - 1 + k % NX;
+        if (k >= NX * NY) break;
+        float ux = 0.f, uy = 0.f, r = 0.f;
+        if (a >= 0 && a < n && b >= 0 && b < n) {
+          ux = vux[it];
+          uy = vuy[it];
+          if (mv) {
+            ux -= tau * vdx[it];
+            uy -= tau * vdy[it];
+          }
+          r = vr[it];
+        }
+        s_ux[k] = ux;
+        s_uy[k] = uy;
+        s_r[k] = r;
+      }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < EX * EY; e += BLOCK) {
@@ -693,10 +727,10 @@ __global__ void __launch_bounds__(BLOCK, LB_GRAD) k_grad(BatchDesc* D) {
           e00 = (ty + 1) * EX + tx + 1;
       float gx = (s_c[6][e11] + s_c[4][e10]) + (s_c[2][e01] + s_c[0][e00]);
       float gy = (s_c[7][e11] + s_c[5][e10]) + (s_c[3][e01] + s_c[1][e00]);
-      size_t i = (size_t)a * n + b;
+      size_t i = (size_t)a * n + b, ig = (size_t)a * gpi + b;
       int kn = (ty + 1) * NX + tx + 1;
-      gst(G, i, gx);
-      gst(G, nn + i, gy);
+      gst(G, ig, gx);
+      gst(G, gpn + ig, gy);
       gst(un, i, s_ux[kn]);
       gst(un, nn + i, s_uy[kn]);
     }
@@ -831,7 +865,7 @@ struct SmoothR {
 // One smoother item: lines [line0, line0 + nl) of one component.
 template <int DIR, int C>
 __device__ void smooth_item(const float* src, float* dst, const float* Gp, const float* coef,
-                            int n, int line0, int nl, int SL, float* s_buf, double& gd,
+                            int n, int P, int line0, int nl, int SL, float* s_buf, double& gd,
                             double& dm) {
   constexpr int R = SmoothR<C>::value;
   constexpr int NW = BLOCK / 64;
@@ -840,9 +874,30 @@ __device__ void smooth_item(const float* src, float* dst, const float* Gp, const
   if (DIR == 0) {
     // strip [n][SL] with pitch SL + 1; wave wv solves columns g .. g+R-1, g = R wv + R NW j
     int pitch = SL + 1;
-    for (int k = threadIdx.x; k < n * SL; k += BLOCK) {
-      int i = k / SL, L = k - i * SL;
-      s_buf[i * pitch + L] = L < nl ? gld(src, (size_t)i * n + line0 + L) : 0.f;
+    {
+      // UB loads per lane in flight before the LDS stores (indices clamped into the strip)
+#ifndef SM_UB
+#define SM_UB 16
+#endif
+      constexpr int UB = SM_UB;
+      const int tot = n * SL;
+      for (int k0 = threadIdx.x; k0 < tot; k0 += UB * BLOCK) {
+        float v[UB];
+#pragma unroll
+        for (int j = 0; j < UB; ++j) {
+          int k = min(k0 + j * BLOCK, tot - 1);
+          int i = k / SL, L = min(k - i * SL, nl - 1);
+          v[j] = gld(src, (size_t)i * P + line0 + L);
+        }
+#pragma unroll
+        for (int j = 0; j < UB; ++j) {
+          int k = k0 + j * BLOCK;
+          if (k < tot) {
+            int i = k / SL, L = k - i * SL;
+            s_buf[i * pitch + L] = L < nl ? v[j] : 0.f;
+          }
+        }
+      }
     }
     __syncthreads();
     for (int g = wv * R; g < nl; g += R * NW) {
@@ -865,7 +920,7 @@ __device__ void smooth_item(const float* src, float* dst, const float* Gp, const
     __syncthreads();
     for (int k = threadIdx.x; k < n * SL; k += BLOCK) {
       int i = k / SL, L = k - i * SL;
-      if (L < nl) gst(dst, (size_t)i * n + line0 + L, s_buf[i * pitch + L]);
+      if (L < nl) gst(dst, (size_t)i * P + line0 + L, s_buf[i * pitch + L]);
     }
   } else {
     // each wave stages R rows in its own LDS area (row pitch 64 C + 1)
@@ -873,9 +928,29 @@ __device__ void smooth_item(const float* src, float* dst, const float* Gp, const
     float* rows = s_buf + wv * R * pitch;
     for (int g = wv * R; g < nl; g += R * NW) {
       int nr = min(R, nl - g);
-      for (int r = 0; r < nr; ++r) {
-        const float* sr = src + (size_t)(line0 + g + r) * n;
-        for (int i = lane; i < n; i += 64) rows[r * pitch + i] = gld(sr, i);
+      if constexpr (C <= 9) {
+        // all R x C loads of a lane in flight before the LDS stores (indices clamped)
+        float t[R][C];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int k = 0; k < C; ++k) {
+            int i = min(lane + 64 * k, n - 1);
+            const float* sr = src + (size_t)(line0 + g + min(r, nr - 1)) * P;
+            t[r][k] = gld(sr, i);
+          }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int k = 0; k < C; ++k) {
+            int i = lane + 64 * k;
+            if (r < nr && i < n) rows[r * pitch + i] = t[r][k];
+          }
+      } else {
+        for (int r = 0; r < nr; ++r) {
+          const float* sr = src + (size_t)(line0 + g + r) * P;
+          for (int i = lane; i < n; i += 64) rows[r * pitch + i] = gld(sr, i);
+        }
       }
       wave_sync();
 #pragma unroll
@@ -895,14 +970,22 @@ __device__ void smooth_item(const float* src, float* dst, const float* Gp, const
           if (i < n && r < nr) rows[r * pitch + i] = v[r][k];
         }
       wave_sync();
+      // the C loads of G of a row in flight together
       for (int r = 0; r < nr; ++r) {
         float* dr = dst + (size_t)(line0 + g + r) * n;
-        const float* gr = Gp + (size_t)(line0 + g + r) * n;
-        for (int i = lane; i < n; i += 64) {
-          float x = rows[r * pitch + i];
-          gst(dr, i, x);
-          gd += (double)(gld(gr, i) * x);
-          dm = fmax(dm, (double)fabsf(x));
+        const float* gr = Gp + (size_t)(line0 + g + r) * P;
+        float t[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) t[k] = gld(gr, min(lane + 64 * k, n - 1));
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+          int i = lane + 64 * k;
+          if (i < n) {
+            float x = rows[r * pitch + i];
+            gst(dr, i, x);
+            gd += (double)(t[k] * x);
+            dm = fmax(dm, (double)fabsf(x));
+          }
         }
       }
       wave_sync();
@@ -910,8 +993,14 @@ __device__ void smooth_item(const float* src, float* dst, const float* Gp, const
   }
 }
 
-template <int DIR>
-__global__ void __launch_bounds__(BLOCK, LB_SMOOTH) k_smooth(BatchDesc* D) {
+// BIG: the instance that also handles lines of more than 576 nodes (17 per lane); the smaller
+// instance leaves that path out, which keeps its register allocation free of spills. The host
+// launches BIG only when the batch's finest level needs it.
+#ifndef LB_SMX
+#define LB_SMX LB_SMOOTH
+#endif
+template <int DIR, bool BIG>
+__global__ void __launch_bounds__(BLOCK, DIR ? LB_SMX : LB_SMOOTH) k_smooth(BatchDesc* D) {
   extern __shared__ float s_buf[];
   __shared__ double s_red[(BLOCK / 64) * 2];
   __shared__ int s_pos;
@@ -931,19 +1020,22 @@ __global__ void __launch_bounds__(BLOCK, LB_SMOOTH) k_smooth(BatchDesc* D) {
     int comp = t / g.sm_items;
     int line0 = (t % g.sm_items) * SL;
     int nl = min(SL, n - line0);
-    const float* src = (DIR ? D->zbuf : D->gbuf) + (size_t)s * D->slot_f_stride + comp * nn;
-    float* dst = (DIR ? D->dbuf : D->zbuf) + (size_t)s * D->slot_f_stride + comp * nn;
-    const float* Gp = D->gbuf + (size_t)s * D->slot_f_stride + comp * nn;
+    const int P = row_pitch(n);
+    const size_t np = (size_t)n * P;
+    const float* src = (DIR ? D->zbuf : D->gbuf) + (size_t)s * D->slot_p_stride + comp * np;
+    float* dst = DIR ? D->dbuf + (size_t)s * D->slot_f_stride + comp * nn
+                     : D->zbuf + (size_t)s * D->slot_p_stride + comp * np;
+    const float* Gp = D->gbuf + (size_t)s * D->slot_p_stride + comp * np;
     const float* coef = D->coef + g.coef_off;
     double gd = 0.0, dm = 0.0;
     __syncthreads();
     int Cn = (n + 63) / 64;
-    if (Cn <= 1) smooth_item<DIR, 1>(src, dst, Gp, coef, n, line0, nl, SL, s_buf, gd, dm);
-    else if (Cn <= 2) smooth_item<DIR, 2>(src, dst, Gp, coef, n, line0, nl, SL, s_buf, gd, dm);
-    else if (Cn <= 3) smooth_item<DIR, 3>(src, dst, Gp, coef, n, line0, nl, SL, s_buf, gd, dm);
-    else if (Cn <= 5) smooth_item<DIR, 5>(src, dst, Gp, coef, n, line0, nl, SL, s_buf, gd, dm);
-    else if (Cn <= 9) smooth_item<DIR, 9>(src, dst, Gp, coef, n, line0, nl, SL, s_buf, gd, dm);
-    else smooth_item<DIR, 17>(src, dst, Gp, coef, n, line0, nl, SL, s_buf, gd, dm);
+    if (Cn <= 1) smooth_item<DIR, 1>(src, dst, Gp, coef, n, P, line0, nl, SL, s_buf, gd, dm);
+    else if (Cn <= 2) smooth_item<DIR, 2>(src, dst, Gp, coef, n, P, line0, nl, SL, s_buf, gd, dm);
+    else if (Cn <= 3) smooth_item<DIR, 3>(src, dst, Gp, coef, n, P, line0, nl, SL, s_buf, gd, dm);
+    else if (Cn <= 5) smooth_item<DIR, 5>(src, dst, Gp, coef, n, P, line0, nl, SL, s_buf, gd, dm);
+    else if (Cn <= 9) smooth_item<DIR, 9>(src, dst, Gp, coef, n, P, line0, nl, SL, s_buf, gd, dm);
+    else if constexpr (BIG) smooth_item<DIR, 17>(src, dst, Gp, coef, n, P, line0, nl, SL, s_buf, gd, dm);
     if (DIR == 1) {
       double acc[2] = {gd, dm};
       block_sum<2>(acc, s_red, true);
@@ -991,7 +1083,8 @@ __global__ void __launch_bounds__(SW_THREADS) k_smooth_win(BatchDesc* D) {
     int wy0 = max(0, oy0 - H), wy1 = min(n, oy1 + H);
     int wx0 = max(0, ox0 - H), wx1 = min(n, ox1 + H);
     int hy = wy1 - wy0, hx = wx1 - wx0;
-    const float* G = D->gbuf + (size_t)sl * D->slot_f_stride + comp * nn;
+    const int P = row_pitch(n);
+    const float* G = D->gbuf + (size_t)sl * D->slot_p_stride + comp * (size_t)n * P;
     float* dst = D->dbuf + (size_t)sl * D->slot_f_stride + comp * nn;
     const float* ca = D->coef + g.coef_off;  // a_i
     const float* ci = ca + n;                // 1 / den_i
@@ -999,7 +1092,7 @@ __global__ void __launch_bounds__(SW_THREADS) k_smooth_win(BatchDesc* D) {
     __syncthreads();
     for (int k = tid; k < hy * hx; k += SW_THREADS) {
       int r = k / hx, q = k - r * hx;
-      s[r * PITCH + q] = G[(size_t)(wy0 + r) * n + wx0 + q];
+      s[r * PITCH + q] = G[(size_t)(wy0 + r) * P + wx0 + q];
     }
     __syncthreads();
     if (tid < hx) {  // column tid of the window, rows wy0 .. wy1 - 1
@@ -1060,7 +1153,7 @@ __global__ void __launch_bounds__(SW_THREADS) k_smooth_win(BatchDesc* D) {
       float xv = s[(oy0 - wy0 + j) * PITCH + (ox0 - wx0) + q];
       size_t gi = (size_t)(oy0 + j) * n + ox0 + q;
       dst[gi] = xv;
-      gd += (double)(G[gi] * xv);
+      gd += (double)(G[(size_t)(oy0 + j) * P + ox0 + q] * xv);
       dm = fmax(dm, (double)fabsf(xv));
     }
     gd = wave_sum(gd);
@@ -1510,9 +1603,14 @@ hipError_t grad(BatchDesc* d, int variant, int grid, hipStream_t st) {
   }
   return hipGetLastError();
 }
-hipError_t smooth(BatchDesc* d, int dir, int grid, size_t lds_bytes, hipStream_t st) {
-  if (dir == 0) hipLaunchKernelGGL(k_smooth<0>, dim3(grid), dim3(SM_THREADS), lds_bytes, st, d);
-  else hipLaunchKernelGGL(k_smooth<1>, dim3(grid), dim3(SM_THREADS), lds_bytes, st, d);
+hipError_t smooth(BatchDesc* d, int dir, bool big, int grid, size_t lds_bytes, hipStream_t st) {
+  if (big) {
+    if (dir == 0) hipLaunchKernelGGL((k_smooth<0, true>), dim3(grid), dim3(SM_THREADS), lds_bytes, st, d);
+    else hipLaunchKernelGGL((k_smooth<1, true>), dim3(grid), dim3(SM_THREADS), lds_bytes, st, d);
+  } else {
+    if (dir == 0) hipLaunchKernelGGL((k_smooth<0, false>), dim3(grid), dim3(SM_THREADS), lds_bytes, st, d);
+    else hipLaunchKernelGGL((k_smooth<1, false>), dim3(grid), dim3(SM_THREADS), lds_bytes, st, d);
+  }
   return hipGetLastError();
 }
 hipError_t smooth_win(BatchDesc* d, int halo, int grid, hipStream_t st) {
@@ -1522,11 +1620,13 @@ hipError_t smooth_win(BatchDesc* d, int halo, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 hipError_t set_smooth_lds(size_t bytes) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_smooth<0>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_smooth<1>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  const void* fns[4] = {(const void*)k_smooth<0, false>, (const void*)k_smooth<1, false>,
+                        (const void*)k_smooth<0, true>, (const void*)k_smooth<1, true>};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 hipError_t restrict_planes(const float* src, long long s_outer, long long s_inner, float* dst,
                            long long d_outer, long long d_inner, int inner, int nf, int planes,

@@ -85,6 +85,13 @@ struct WorkList {
 };
 
 // Everything the per-step kernels need; lives in device memory, pointers fixed per context.
+// Row pitch (floats) of a level's gradient and metric-solve buffers: rows start on 128-byte
+// lines, so the column-strip solve reads and writes whole lines instead of straddling two.
+#ifndef WPAD
+#define WPAD 32
+#endif
+__host__ __device__ inline int row_pitch(int n) { return (n + WPAD - 1) / WPAD * WPAD; }
+
 struct BatchDesc {
   int n_slots;
   int finest;
@@ -108,13 +115,13 @@ struct BatchDesc {
   long long slot_u_stride;
   long long u_off[PPRS_MAXL];  // offset of level l: [2 buffers][2 comps][n_l^2]
   float* dbuf;             // [slot][2][nL^2] search direction
-  float* gbuf;             // [slot][2][nL^2] gradient
-  float* zbuf;             // [slot][2][nL^2] metric solve intermediate
+  float* gbuf;             // [slot][2][nL][row_pitch(nL)] gradient (rows padded, see row_pitch)
+  float* zbuf;             // [slot][2][nL][row_pitch(nL)] metric solve intermediate
   long long slot_f_stride; // 2 * nL^2
+  long long slot_p_stride; // 2 * nL * row_pitch(nL)
   double* partial;         // [slot][kind][max_items][PW]
   long long part_slot_stride;
   long long part_kind_stride;
-  int* counters;           // [slot][WK_COUNT]
   long long* node_count;   // [slot][WK_COUNT] grid nodes processed per kind (statistics)
   // smoother coefficients: inv_den[i], cprime[i] per level (float)
   float* coef;

@@ -90,7 +90,7 @@ struct pprs_ctx {
   DevBuf frames, frame_off, rsum, fr_ms, fr_part;
   std::vector<long long> frame_off_host;
   // slots
-  DevBuf state, ubuf, dbuf, gbuf, zbuf, partial, counters, nodecount, coef, list_slots, list_off,
+  DevBuf state, ubuf, dbuf, gbuf, zbuf, partial, nodecount, coef, list_slots, list_off,
       lists, desc, opidx;
   // scan elements [M][2][nL^2] and staging
   DevBuf elems;
@@ -267,21 +267,16 @@ pprs_status ensure_slots(pprs_ctx* c, int cap, int L, int m0, double beta) {
     int nL = level_n(L);
     hd.slot_u_stride = uoff;
     hd.slot_f_stride = 2LL * nL * nL;
+    hd.slot_p_stride = 2LL * nL * row_pitch(nL);
     hd.part_kind_stride = (long long)max_items * PW;
     hd.part_slot_stride = hd.part_kind_stride * WK_COUNT;
     hd.max_slots = cap;
     STCHK(ensure(c->state, sizeof(SlotState) * cap));
     STCHK(ensure(c->ubuf, sizeof(float) * hd.slot_u_stride * cap));
     STCHK(ensure(c->dbuf, sizeof(float) * hd.slot_f_stride * cap, true));
-    STCHK(ensure(c->gbuf, sizeof(float) * hd.slot_f_stride * cap));
-    STCHK(ensure(c->zbuf, sizeof(float) * hd.slot_f_stride * cap));
+    STCHK(ensure(c->gbuf, sizeof(float) * hd.slot_p_stride * cap));
+    STCHK(ensure(c->zbuf, sizeof(float) * hd.slot_p_stride * cap));
     STCHK(ensure(c->partial, sizeof(double) * hd.part_slot_stride * cap));
-    // counters must start at zero; the finalisers reset them after use
-    if (c->counters.bytes < sizeof(int) * WK_COUNT * cap) {
-      STCHK(ensure(c->counters, sizeof(int) * WK_COUNT * cap, true));
-    } else {
-      HIPCHK(hipMemset(c->counters.p, 0, c->counters.bytes));
-    }
     STCHK(ensure(c->nodecount, sizeof(long long) * WK_COUNT * cap));
     STCHK(ensure(c->coef, sizeof(float) * coef_off));
     STCHK(ensure(c->list_slots, sizeof(int) * WK_COUNT * cap));
@@ -295,7 +290,6 @@ pprs_status ensure_slots(pprs_ctx* c, int cap, int L, int m0, double beta) {
     hd.gbuf = P<float>(c->gbuf);
     hd.zbuf = P<float>(c->zbuf);
     hd.partial = P<double>(c->partial);
-    hd.counters = P<int>(c->counters);
     hd.node_count = P<long long>(c->nodecount);
     hd.coef = P<float>(c->coef);
     hd.list_slots = P<int>(c->list_slots);
@@ -478,8 +472,9 @@ pprs_status launch_step(pprs_ctx* c, BatchDesc* d, int ladder_k) {
   if (c->hd.smooth_halo) {
     TIMED(TK_SMW, pprs_k::smooth_win(d, c->hd.smooth_halo, c->grid_smooth, c->stream));
   } else {
-    TIMED(TK_SMY, pprs_k::smooth(d, 0, c->grid_smooth, lds0, c->stream));
-    TIMED(TK_SMX, pprs_k::smooth(d, 1, c->grid_smooth, lds1, c->stream));
+    bool big = level_n(c->hd.finest) > 9 * 64;  // lines longer than 9 nodes per lane
+    TIMED(TK_SMY, pprs_k::smooth(d, 0, big, c->grid_smooth, lds0, c->stream));
+    TIMED(TK_SMX, pprs_k::smooth(d, 1, big, c->grid_smooth, lds1, c->stream));
   }
   TIMED(TK_FIN, pprs_k::smooth_fin(d, kGridFin, c->stream));
   TIMED(TK_LADDER, pprs_k::energy(d, 1, ladder_k, c->grid_energy, c->stream));
@@ -1051,7 +1046,7 @@ void pprs_destroy(pprs_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   DevBuf* bufs[] = {&c->frames, &c->rsum, &c->fr_ms, &c->fr_part, &c->state, &c->ubuf,
-                    &c->dbuf, &c->gbuf, &c->zbuf, &c->partial, &c->counters, &c->nodecount,
+                    &c->dbuf, &c->gbuf, &c->zbuf, &c->partial, &c->nodecount,
                     &c->coef, &c->list_slots, &c->list_off, &c->lists, &c->desc, &c->opidx,
                     &c->elems, &c->cnn_in, &c->cnn_out, &c->tmp, &c->badflags};
   for (DevBuf* b : bufs)
