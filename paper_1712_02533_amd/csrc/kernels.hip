@@ -113,6 +113,18 @@ __device__ __forceinline__ float* slot_u(const BatchDesc* D, int s, int l, int b
   return D->ubuf + (size_t)s * D->slot_u_stride + D->u_off[l] + (size_t)buf * 2 * n * n;
 }
 
+// Copies of a slot's scalar fields (everything before the per-level arrays).
+__device__ __forceinline__ void load_head(SlotState& dst, const SlotState& src) {
+  dst.phase = src.phase; dst.level = src.level; dst.ub = src.ub; dst.iter = src.iter;
+  dst.flags = src.flags; dst.ref = src.ref; dst.tmpl = src.tmpl; dst.finest = src.finest;
+  dst.coarsest = src.coarsest; dst.E = src.E; dst.ncc = src.ncc; dst.mean = src.mean;
+  dst.sigma = src.sigma; dst.tau_prev = src.tau_prev; dst.top = src.top;
+  dst.tau_max = src.tau_max; dst.tau_pend = src.tau_pend; dst.gtd = src.gtd; dst.dmax = src.dmax;
+}
+__device__ __forceinline__ void store_head(SlotState& dst, const SlotState& src) {
+  load_head(dst, src);
+}
+
 __device__ __forceinline__ void level_done(SlotState& st) {
   st.phase = st.level < st.finest ? PH_PROLONG : PH_DONE;
 }
@@ -175,16 +187,21 @@ __device__ __forceinline__ double* slot_partial(const BatchDesc* D, int s, int k
 }
 
 // Fixed-order sum of NV columns over n_items partial records; result in thread 0's out[].
+// (Compile-time NV keeps out[] in registers; a record's NV loads are issued together.)
 template <int NV>
-__device__ void sum_partials(const BatchDesc* D, int s, int kind, int n_items, int nv,
-                             double (&out)[NV], double* scratch, bool max_last) {
+__device__ __forceinline__ void sum_partials(const BatchDesc* D, int s, int kind, int n_items,
+                                             double (&out)[NV], double* scratch, bool max_last) {
+#pragma unroll
   for (int k = 0; k < NV; ++k) out[k] = 0.0;
   for (int it = threadIdx.x; it < n_items; it += BLOCK) {
     const double* p = slot_partial(D, s, kind, it);
-    for (int k = 0; k < nv; ++k) {
-      double x = p[k];
-      if (max_last && k == NV - 1) out[k] = fmax(out[k], x);
-      else out[k] += x;
+    double x[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) x[k] = p[k];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      if (max_last && k == NV - 1) out[k] = fmax(out[k], x[k]);
+      else out[k] += x[k];
     }
   }
   block_sum<NV>(out, scratch, max_last);
@@ -353,10 +370,14 @@ __device__ __forceinline__ void ke_apply(const float u[4], float out[4]) {
 // Per element tile: quadrature sums S1 = sum w T, S2 = sum w T^2, S3 = sum w R~ T for each
 // step size, and the Dirichlet terms u^T K u, d^T K u, d^T K d via element matrices.
 
+// Works on a register copy of the slot's scalar fields (loaded together up front, stored back
+// at the end): every read of global state would otherwise wait behind the previous store.
 template <int MODE, int NC>
-__device__ __noinline__ void energy_finalize(BatchDesc* D, SlotState* stp, int s, int l, int n, int ph,
-                                double top, const double* tot) {
-  SlotState& st = *stp;
+__device__ __forceinline__ void energy_finalize(BatchDesc* D, SlotState* stp, int s, int l, int n,
+                                                int ph, double top,
+                                                const double (&tot)[3 * NC + 3]) {
+  SlotState st;
+  load_head(st, *stp);
   const int kind = MODE ? WK_LADDER : WK_EVAL;
   int K = D->ladder_k;
   double rs = D->rsum[(size_t)st.ref * PPRS_MAXL + l];
@@ -397,7 +418,7 @@ __device__ __noinline__ void energy_finalize(BatchDesc* D, SlotState* stp, int s
     }
   } else {
     int li = st.level - st.coarsest;
-    st.passes[li]++;
+    stp->passes[li]++;
     int acc_j = -1;
     for (int j = 0; j < NC; ++j) {
       double tj = ldexp(top, -j);
@@ -416,7 +437,7 @@ __device__ __noinline__ void energy_finalize(BatchDesc* D, SlotState* stp, int s
       st.tau_pend = tj;
       st.tau_prev = tj;
       st.iter++;
-      st.iters[li] = st.iter;
+      stp->iters[li] = st.iter;
       if (dec < D->eps) {
         level_done(st);
       } else if (st.iter >= D->iter_max) {
@@ -431,6 +452,7 @@ __device__ __noinline__ void energy_finalize(BatchDesc* D, SlotState* stp, int s
       else st.phase = PH_LADDER;
     }
   }
+  store_head(*stp, st);
 }
 
 template <int MODE, int NC>
@@ -584,7 +606,7 @@ __global__ void __launch_bounds__(BLOCK) k_energy_fin(BatchDesc* D) {
     int n = lvl_n(l);
     double top = MODE ? stp->top : 0.0;
     double tot[NV];
-    sum_partials<NV>(D, s, kind, D->geom[l].tiles_elem, NV, tot, s_red, false);
+    sum_partials<NV>(D, s, kind, D->geom[l].tiles_elem, tot, s_red, false);
     if (threadIdx.x == 0) energy_finalize<MODE, NC>(D, stp, s, l, n, ph, top, tot);
     __syncthreads();
   }
@@ -1182,13 +1204,15 @@ __global__ void __launch_bounds__(BLOCK) k_smooth_fin(BatchDesc* D) {
   const WorkList wl = D->lists[WK_SMX];
   for (int pos = blockIdx.x; pos < wl.n_slots; pos += gridDim.x) {
     int s = D->list_slots[(size_t)WK_SMX * D->max_slots + pos];
-    SlotState& st = D->state[s];
-    if (st.phase != PH_GRAD) continue;
-    int l = st.level;
+    SlotState* stp = D->state + s;
+    if (stp->phase != PH_GRAD) continue;
+    int l = stp->level;
     int n = lvl_n(l);
     double tot[2];
-    sum_partials<2>(D, s, WK_SMX, kind_items(D, WK_SMX, l), 2, tot, s_red, true);
+    sum_partials<2>(D, s, WK_SMX, kind_items(D, WK_SMX, l), tot, s_red, true);
     if (threadIdx.x == 0) {
+      SlotState st;
+      load_head(st, *stp);
       long long* nc_s = D->node_count + (size_t)s * WK_COUNT;
       nc_s[WK_GRAD] += (long long)n * n;
       if (!D->smooth_halo) nc_s[WK_SMY] += (long long)n * n;
@@ -1205,6 +1229,7 @@ __global__ void __launch_bounds__(BLOCK) k_smooth_fin(BatchDesc* D) {
         st.top = fmin(ldexp(st.tau_prev, D->ladder_k), st.tau_max);
         st.phase = PH_LADDER;
       }
+      store_head(*stp, st);
     }
     __syncthreads();
   }
