@@ -619,12 +619,15 @@ __global__ void __launch_bounds__(BLOCK) k_energy_fin(BatchDesc* D) {
 //       f_q = -w (R~(q) - NCC (T(q) - mean) / sigma) / sigma.
 
 // Tile shape TX x TY nodes (a launch-shape choice: every node's G is the same sum of the same
-// element terms whatever the tile, so the shape never changes a result).
+// element terms whatever the tile, so the shape never changes a result). A level has 2^l + 1
+// nodes per axis: the last tile of each row and column of tiles takes the extra node (TX + 1
+// wide), so no tile is a one-node sliver.
 template <int TX, int TY>
 __global__ void __launch_bounds__(BLOCK, LB_GRAD) k_grad(BatchDesc* D) {
   constexpr int GT_X = TX, GT_Y = TY;
-  constexpr int NX = GT_X + 2, NY = GT_Y + 2;       // staged nodes
-  constexpr int EX = GT_X + 1, EY = GT_Y + 1;       // elements touching the tile
+  static_assert((TX & (TX - 1)) == 0 && (TY & (TY - 1)) == 0, "tile sides are powers of two");
+  constexpr int NX = GT_X + 3, NY = GT_Y + 3;       // staged nodes of the widest tile
+  constexpr int EX = GT_X + 2, EY = GT_Y + 2;       // elements touching the widest tile
   __shared__ float s_ux[NX * NY], s_uy[NX * NY], s_r[NX * NY];
   __shared__ float s_c[8][EX * EY];                 // per element, per corner, (x, y)
   __shared__ int s_pos;
@@ -653,8 +656,11 @@ __global__ void __launch_bounds__(BLOCK, LB_GRAD) k_grad(BatchDesc* D) {
     float lam = (float)D->lambda;
     float inv_h = (float)(n - 1);
     float w = 0.25f / ((float)(n - 1) * (float)(n - 1));
-    int ntx = (n + GT_X - 1) / GT_X;
-    int x0 = (t % ntx) * GT_X, y0 = (t / ntx) * GT_Y;
+    const int ntx = max(1, (n - 1) / GT_X), nty = max(1, (n - 1) / GT_Y);
+    const int txi = t % ntx, tyi = t / ntx;
+    const int x0 = txi * GT_X, y0 = tyi * GT_Y;
+    const int tw = txi == ntx - 1 ? n - x0 : GT_X;  // nodes of this tile (<= GT_X + 1)
+    const int th = tyi == nty - 1 ? n - y0 : GT_Y;
     // stage u - tau d and R with the halo: all loads of a lane first, then the LDS stores
     __syncthreads();
     {
@@ -664,8 +670,10 @@ __global__ void __launch_bounds__(BLOCK, LB_GRAD) k_grad(BatchDesc* D) {
 #pragma unroll
       for (int it = 0; it < SIT; ++it) {
         int k = threadIdx.x + it * BLOCK;
-        int a = y0 - 1 + k / NX, b = x0 - 1 + k % NX;
-        size_t i = (k < NX * NY && a >= 0 && a < n && b >= 0 && b < n) ? (size_t)a * n + b : 0;
+        int ky = k / NX, kx = k % NX;
+        int a = y0 - 1 + ky, b = x0 - 1 + kx;
+        bool ok = k < NX * NY && ky < th + 2 && kx < tw + 2 && a >= 0 && a < n && b >= 0 && b < n;
+        size_t i = ok ? (size_t)a * n + b : 0;
         vux[it] = gld(u, i);
         vuy[it] = gld(u, nn + i);
         vr[it] = gld(R, i);
@@ -675,10 +683,11 @@ __global__ void __launch_bounds__(BLOCK, LB_GRAD) k_grad(BatchDesc* D) {
 #pragma unroll
       for (int it = 0; it < SIT; ++it) {
         int k = threadIdx.x + it * BLOCK;
-        int a = y0 - 1 + k / NX, b = x0 - 1 + k % NX;
+        int ky = k / NX, kx = k % NX;
+        int a = y0 - 1 + ky, b = x0 - 1 + kx;
         if (k >= NX * NY) break;
         float ux = 0.f, uy = 0.f, r = 0.f;
-        if (a >= 0 && a < n && b >= 0 && b < n) {
+        if (ky < th + 2 && kx < tw + 2 && a >= 0 && a < n && b >= 0 && b < n) {
           ux = vux[it];
           uy = vuy[it];
           if (mv) {
@@ -697,7 +706,7 @@ __global__ void __launch_bounds__(BLOCK, LB_GRAD) k_grad(BatchDesc* D) {
       int ey = e / EX, ex = e % EX;
       int a = y0 - 1 + ey, b = x0 - 1 + ex;
       float cx[4] = {0, 0, 0, 0}, cy[4] = {0, 0, 0, 0};
-      if (a >= 0 && a < n - 1 && b >= 0 && b < n - 1) {
+      if (ey < th + 1 && ex < tw + 1 && a >= 0 && a < n - 1 && b >= 0 && b < n - 1) {
         int k00 = ey * NX + ex;
         float ux[4] = {s_ux[k00], s_ux[k00 + 1], s_ux[k00 + NX], s_ux[k00 + NX + 1]};
         float uy[4] = {s_uy[k00], s_uy[k00 + 1], s_uy[k00 + NX], s_uy[k00 + NX + 1]};
@@ -740,10 +749,9 @@ __global__ void __launch_bounds__(BLOCK, LB_GRAD) k_grad(BatchDesc* D) {
       }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < GT_X * GT_Y; k += BLOCK) {
-      int ty = k / GT_X, tx = k % GT_X;
+    for (int k = threadIdx.x; k < tw * th; k += BLOCK) {
+      int ty = k / tw, tx = k - ty * tw;
       int a = y0 + ty, b = x0 + tx;
-      if (a >= n || b >= n) continue;
       // elements (local coords): (ty, tx) is element (a-1, b-1) -> corner 3, etc.
       int e11 = ty * EX + tx, e10 = ty * EX + tx + 1, e01 = (ty + 1) * EX + tx,
           e00 = (ty + 1) * EX + tx + 1;

@@ -217,7 +217,7 @@ pprs_status set_grad_tiles(pprs_ctx* c) {
   for (int l = hd.coarsest; l <= hd.finest; ++l) {
     int n = level_n(l);
     LevelGeom& g = hd.geom[l];
-    g.tiles_grad = ((n + tx - 1) / tx) * ((n + ty - 1) / ty);
+    g.tiles_grad = std::max(1, (n - 1) / tx) * std::max(1, (n - 1) / ty);  // last tiles absorb node n-1
     int lines = c->smooth_lines;
     while (lines > 8 && (long long)n * (lines + 1) > SM_LDS_MAX_FLOATS) lines /= 2;
     g.sm_lines = lines;
