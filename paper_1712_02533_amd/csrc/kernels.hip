@@ -905,9 +905,10 @@ __device__ void smooth_item(const float* src, float* dst, const float* Gp, const
     // strip [n][SL] with pitch SL + 1; wave wv solves columns g .. g+R-1, g = R wv + R NW j
     int pitch = SL + 1;
     {
-      // UB loads per lane in flight before the LDS stores (indices clamped into the strip)
+      // UB loads per lane in flight before the LDS stores (indices clamped into the strip);
+      // 17 covers a 513-node strip of 16 lines in two rounds
 #ifndef SM_UB
-#define SM_UB 16
+#define SM_UB 17
 #endif
       constexpr int UB = SM_UB;
       const int tot = n * SL;
