@@ -172,6 +172,10 @@ typedef struct {
   int tile_grad;     /* gradient tile shape: 0 = 32x16 (default), 1 = 64x8, 2 = 128x4,
                         3 = 64x16 nodes */
   int smooth_lines;  /* columns per workgroup of the column solves: 8, 16 (default) or 32 */
+  int ladder_rungs;  /* step sizes evaluated per line-search pass: 1, 2, 3, 5 or 7; 0 = one
+                        group of 2K+1. The ladder is walked step by step in the same order
+                        (groups of 2K+1, a group below tau_min_rel tau_max not begun) whatever
+                        the value, so the accepted steps are the same. */
 } pprs_tuning;
 
 /* Reads / replaces the launch shape of ctx (host struct). PPRS_EINVAL for out-of-range

@@ -51,7 +51,7 @@ class _CSeriesStats(ctypes.Structure):
 class _CTuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int) for n in ("pool_slots", "pool_group", "grid_energy",
                                             "grid_grad", "grid_smooth", "grid_prolong",
-                                            "tile_grad", "smooth_lines")]
+                                            "tile_grad", "smooth_lines", "ladder_rungs")]
 
 
 TUNING_KEYS = [n for n, _ in _CTuning._fields_]

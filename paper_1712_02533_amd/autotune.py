@@ -16,6 +16,7 @@ import os
 import time
 
 CANDIDATES = {
+    "ladder_rungs": [2, 1],
     "tile_grad": [1, 2, 3, 0],
     "smooth_lines": [32, 8, 16],
     "pool_group": [4, 8, 16, 32],

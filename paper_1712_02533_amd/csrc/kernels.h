@@ -6,8 +6,10 @@
 namespace pprs_k {
 hipError_t plan(BatchDesc* d, hipStream_t st);
 hipError_t prolong(BatchDesc* d, int grid, hipStream_t st);
-hipError_t energy(BatchDesc* d, int mode, int ladder_k, int grid, hipStream_t st);
-hipError_t energy_fin(BatchDesc* d, int mode, int ladder_k, int grid, hipStream_t st);
+// nc: step sizes per line-search pass (1, 2, 3, 5 or 7; ladder_rungs_ok)
+bool ladder_rungs_ok(int nc);
+hipError_t energy(BatchDesc* d, int mode, int nc, int grid, hipStream_t st);
+hipError_t energy_fin(BatchDesc* d, int mode, int nc, int grid, hipStream_t st);
 hipError_t smooth_fin(BatchDesc* d, int grid, hipStream_t st);
 // gradient tile variants: 0 = 32x16, 1 = 64x8, 2 = 128x4, 3 = 64x16 nodes
 void grad_tile(int variant, int* tx, int* ty);

@@ -117,7 +117,7 @@ __device__ __forceinline__ float* slot_u(const BatchDesc* D, int s, int l, int b
 __device__ __forceinline__ void load_head(SlotState& dst, const SlotState& src) {
   dst.phase = src.phase; dst.level = src.level; dst.ub = src.ub; dst.iter = src.iter;
   dst.flags = src.flags; dst.ref = src.ref; dst.tmpl = src.tmpl; dst.finest = src.finest;
-  dst.coarsest = src.coarsest; dst.E = src.E; dst.ncc = src.ncc; dst.mean = src.mean;
+  dst.coarsest = src.coarsest; dst.rung = src.rung; dst.E = src.E; dst.ncc = src.ncc; dst.mean = src.mean;
   dst.sigma = src.sigma; dst.tau_prev = src.tau_prev; dst.top = src.top;
   dst.tau_max = src.tau_max; dst.tau_pend = src.tau_pend; dst.gtd = src.gtd; dst.dmax = src.dmax;
 }
@@ -417,11 +417,26 @@ __device__ __forceinline__ void energy_finalize(BatchDesc* D, SlotState* stp, in
       st.phase = PH_GRAD;
     }
   } else {
+    // The pass evaluated NC consecutive steps of the ladder tau = top 2^-j; the ladder is taken
+    // in groups of G = 2K+1 steps, and a group whose first step is below tau_min_rel * tau_max
+    // is not started. Walking the steps in order with that rule gives the same accepted step
+    // and group count for any NC (NC is a launch-shape choice).
+    const int G = 2 * K + 1;
+    const double tmin = D->tau_min_rel * st.tau_max;
     int li = st.level - st.coarsest;
-    stp->passes[li]++;
+    int r = st.rung;
     int acc_j = -1;
-    for (int j = 0; j < NC; ++j) {
+    bool stop = false;
+    for (int j = 0; j < NC; ++j, ++r) {
       double tj = ldexp(top, -j);
+      if (r == G) {
+        r = 0;
+        if (tj < tmin) {
+          stop = true;
+          break;
+        }
+      }
+      if (r == 0) stp->passes[li]++;
       if (e_j[j] <= st.E - D->sigma * tj * st.gtd) {
         acc_j = j;
         break;
@@ -446,9 +461,17 @@ __device__ __forceinline__ void energy_finalize(BatchDesc* D, SlotState* stp, in
       } else {
         st.phase = PH_GRAD;
       }
+    } else if (stop) {
+      level_done(st);
     } else {
-      st.top = ldexp(top, -(2 * K + 1));
-      if (st.top < D->tau_min_rel * st.tau_max) level_done(st);
+      // next pass: the step after the last one evaluated
+      st.top = ldexp(top, -NC);
+      if (r == G) {
+        r = 0;
+        if (st.top < tmin) stop = true;
+      }
+      st.rung = r;
+      if (stop) level_done(st);
       else st.phase = PH_LADDER;
     }
   }
@@ -1236,7 +1259,10 @@ __global__ void __launch_bounds__(BLOCK) k_smooth_fin(BatchDesc* D) {
         double h = 1.0 / (n - 1);
         st.tau_max = D->step_cap * h / st.dmax;
         st.top = fmin(ldexp(st.tau_prev, D->ladder_k), st.tau_max);
-        st.phase = PH_LADDER;
+        st.rung = 0;
+        // a line search whose first step is already below tau_min_rel * tau_max is not begun
+        if (st.top < D->tau_min_rel * st.tau_max) level_done(st);
+        else st.phase = PH_LADDER;
       }
       store_head(*stp, st);
     }
@@ -1592,28 +1618,33 @@ hipError_t prolong(BatchDesc* d, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_prolong, dim3(grid), dim3(BLOCK), 0, st, d);
   return hipGetLastError();
 }
-hipError_t energy(BatchDesc* d, int mode, int ladder_k, int grid, hipStream_t st) {
+bool ladder_rungs_ok(int nc) { return nc == 1 || nc == 2 || nc == 3 || nc == 5 || nc == 7; }
+hipError_t energy(BatchDesc* d, int mode, int nc, int grid, hipStream_t st) {
   if (mode == 0) {
     hipLaunchKernelGGL((k_energy<0, 1>), dim3(grid), dim3(BLOCK), 0, st, d);
   } else {
-    switch (ladder_k) {
-      case 0: hipLaunchKernelGGL((k_energy<1, 1>), dim3(grid), dim3(BLOCK), 0, st, d); break;
-      case 1: hipLaunchKernelGGL((k_energy<1, 3>), dim3(grid), dim3(BLOCK), 0, st, d); break;
-      case 2: hipLaunchKernelGGL((k_energy<1, 5>), dim3(grid), dim3(BLOCK), 0, st, d); break;
-      default: hipLaunchKernelGGL((k_energy<1, 7>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    switch (nc) {
+      case 1: hipLaunchKernelGGL((k_energy<1, 1>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+      case 2: hipLaunchKernelGGL((k_energy<1, 2>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+      case 3: hipLaunchKernelGGL((k_energy<1, 3>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+      case 5: hipLaunchKernelGGL((k_energy<1, 5>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+      case 7: hipLaunchKernelGGL((k_energy<1, 7>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+      default: return hipErrorInvalidValue;
     }
   }
   return hipGetLastError();
 }
-hipError_t energy_fin(BatchDesc* d, int mode, int ladder_k, int grid, hipStream_t st) {
+hipError_t energy_fin(BatchDesc* d, int mode, int nc, int grid, hipStream_t st) {
   if (mode == 0) {
     hipLaunchKernelGGL((k_energy_fin<0, 1>), dim3(grid), dim3(BLOCK), 0, st, d);
   } else {
-    switch (ladder_k) {
-      case 0: hipLaunchKernelGGL((k_energy_fin<1, 1>), dim3(grid), dim3(BLOCK), 0, st, d); break;
-      case 1: hipLaunchKernelGGL((k_energy_fin<1, 3>), dim3(grid), dim3(BLOCK), 0, st, d); break;
-      case 2: hipLaunchKernelGGL((k_energy_fin<1, 5>), dim3(grid), dim3(BLOCK), 0, st, d); break;
-      default: hipLaunchKernelGGL((k_energy_fin<1, 7>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    switch (nc) {
+      case 1: hipLaunchKernelGGL((k_energy_fin<1, 1>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+      case 2: hipLaunchKernelGGL((k_energy_fin<1, 2>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+      case 3: hipLaunchKernelGGL((k_energy_fin<1, 3>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+      case 5: hipLaunchKernelGGL((k_energy_fin<1, 5>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+      case 7: hipLaunchKernelGGL((k_energy_fin<1, 7>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+      default: return hipErrorInvalidValue;
     }
   }
   return hipGetLastError();

@@ -51,7 +51,7 @@ struct SlotState {
   int tmpl;      // template frame index
   int finest;    // L
   int coarsest;  // m0
-  int pad0;
+  int rung;      // index, within its group of 2K+1 steps, of the pending pass's first step
   double E;      // energy at the accepted u (= u[ub] - tau_pend d)
   double ncc;
   double mean;   // quadrature mean of the warped template at the accepted u

@@ -109,6 +109,7 @@ struct pprs_ctx {
   int grid_energy = 2048, grid_grad = 2048, grid_smooth = 1024, grid_prolong = 2048;
   bool smooth_window = false;  // windowed one-pass metric solve (opt-in, where beta allows)
   int tile_grad = 0;          // gradient kernel tile shape (pprs_k::grad_tile variant)
+  int ladder_rungs = 0;       // step sizes per line-search pass (0: 2K+1)
   int smooth_lines = 16;      // column-strip width of the line solves (8, 16 or 32)
   size_t lds_smooth[2] = {0, 0};
   BatchDesc hd;
@@ -462,12 +463,23 @@ pprs_status tk_collect(pprs_ctx* c) {
     STCHK(tk_end(c, stop_));              \
   } while (0)
 
-pprs_status launch_step(pprs_ctx* c, BatchDesc* d, int ladder_k) {
+// Step sizes per line-search pass: the tuning value, else one group of 2K+1.
+int ladder_rungs(const pprs_ctx* c, int K) { return c->ladder_rungs ? c->ladder_rungs : 2 * K + 1; }
+
+// Upper bound on line-search passes per iteration (a guard against a run that never ends):
+// groups of 2K+1 halvings from tau_max down to tau_min_rel tau_max, walked nc steps a pass.
+long long ladder_pass_bound(const pprs_params* p, int nc) {
+  int G = 2 * p->ladder_k + 1;
+  long long groups = 2 + (long long)ceil(log2(1.0 / p->tau_min_rel) / G);
+  return groups * G / nc + groups + 2;
+}
+
+pprs_status launch_step(pprs_ctx* c, BatchDesc* d, int nc) {
   size_t lds0 = c->lds_smooth[0], lds1 = c->lds_smooth[1];
   TIMED(TK_PLAN, pprs_k::plan(d, c->stream));
   TIMED(TK_PROLONG, pprs_k::prolong(d, c->grid_prolong, c->stream));
-  TIMED(TK_EVAL, pprs_k::energy(d, 0, ladder_k, c->grid_energy, c->stream));
-  TIMED(TK_FIN, pprs_k::energy_fin(d, 0, ladder_k, kGridFin, c->stream));
+  TIMED(TK_EVAL, pprs_k::energy(d, 0, 1, c->grid_energy, c->stream));
+  TIMED(TK_FIN, pprs_k::energy_fin(d, 0, 1, kGridFin, c->stream));
   TIMED(TK_GRAD, pprs_k::grad(d, c->tile_grad, c->grid_grad, c->stream));
   if (c->hd.smooth_halo) {
     TIMED(TK_SMW, pprs_k::smooth_win(d, c->hd.smooth_halo, c->grid_smooth, c->stream));
@@ -477,8 +489,8 @@ pprs_status launch_step(pprs_ctx* c, BatchDesc* d, int ladder_k) {
     TIMED(TK_SMX, pprs_k::smooth(d, 1, big, c->grid_smooth, lds1, c->stream));
   }
   TIMED(TK_FIN, pprs_k::smooth_fin(d, kGridFin, c->stream));
-  TIMED(TK_LADDER, pprs_k::energy(d, 1, ladder_k, c->grid_energy, c->stream));
-  TIMED(TK_FIN, pprs_k::energy_fin(d, 1, ladder_k, kGridFin, c->stream));
+  TIMED(TK_LADDER, pprs_k::energy(d, 1, nc, c->grid_energy, c->stream));
+  TIMED(TK_FIN, pprs_k::energy_fin(d, 1, nc, kGridFin, c->stream));
   return PPRS_OK;
 }
 
@@ -554,14 +566,14 @@ pprs_status run_batch(pprs_ctx* c, int n, const int* ref, const int* tmpl, InitK
   // steps
   c->lds_smooth[0] = smooth_lds_bytes(hd, 0);
   c->lds_smooth[1] = smooth_lds_bytes(hd, 1);
-  int K = p->ladder_k;
-  long long passes_per_iter = 2 + (long long)ceil(log2(1.0 / p->tau_min_rel) / (2 * K + 1));
+  int K = p->ladder_k, nc = ladder_rungs(c, K);
+  long long passes_per_iter = ladder_pass_bound(p, nc);
   long long max_steps =
       (long long)p->levels * ((long long)p->iter_max + 2) * (passes_per_iter + 2) + 64;
   long long done_steps = 0;
   int group = 4;
   while (true) {
-    for (int k = 0; k < group; ++k) STCHK(launch_step(c, d, K));
+    for (int k = 0; k < group; ++k) STCHK(launch_step(c, d, nc));
     done_steps += group;
     int active = 0;
     HIPCHK(hipMemcpyAsync(&active, &d->active, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -781,8 +793,8 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
   std::vector<long long> nodes((size_t)S * WK_COUNT);
   c->lds_smooth[0] = smooth_lds_bytes(hd, 0);
   c->lds_smooth[1] = smooth_lds_bytes(hd, 1);
-  int K = p->ladder_k;
-  long long passes_per_iter = 2 + (long long)ceil(log2(1.0 / p->tau_min_rel) / (2 * K + 1));
+  int K = p->ladder_k, nc = ladder_rungs(c, K);
+  long long passes_per_iter = ladder_pass_bound(p, nc);
   long long per_op_steps =
       (long long)(Lmax - m0min + 1) * ((long long)p->iter_max + 2) * (passes_per_iter + 2) + 64;
   long long max_steps = per_op_steps * (long long)(n_ops / S + 2) + 64;
@@ -801,7 +813,7 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     pprs_status cs = PPRS_OK;
-    for (int k = 0; k < G && cs == PPRS_OK; ++k) cs = launch_step(c, d, K);
+    for (int k = 0; k < G && cs == PPRS_OK; ++k) cs = launch_step(c, d, nc);
     hipError_t ce = hipStreamEndCapture(c->stream, &g);
     if (cs != PPRS_OK) {
       if (g) (void)hipGraphDestroy(g);
@@ -900,7 +912,7 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
     if (graph.exec) {
       HIPCHK(hipGraphLaunch(graph.exec, c->stream));
     } else {
-      for (int k = 0; k < G; ++k) STCHK(launch_step(c, d, K));
+      for (int k = 0; k < G; ++k) STCHK(launch_step(c, d, nc));
     }
     done_steps += G;
     // 3. poll: retire finished slots, release their dependents
@@ -1449,6 +1461,7 @@ pprs_status pprs_get_tuning(pprs_ctx* c, pprs_tuning* t) {
   t->grid_prolong = c->grid_prolong;
   t->tile_grad = c->tile_grad;
   t->smooth_lines = c->smooth_lines;
+  t->ladder_rungs = c->ladder_rungs;
   return PPRS_OK;
 }
 
@@ -1470,6 +1483,9 @@ pprs_status pprs_set_tuning(pprs_ctx* c, const pprs_tuning* t) {
       t->smooth_lines != 32)
     return fail(PPRS_EINVAL, "smooth_lines must be 8, 16 or 32");
   c->smooth_lines = t->smooth_lines ? t->smooth_lines : 16;
+  if (t->ladder_rungs != 0 && !pprs_k::ladder_rungs_ok(t->ladder_rungs))
+    return fail(PPRS_EINVAL, "ladder_rungs must be 0, 1, 2, 3, 5 or 7");
+  c->ladder_rungs = t->ladder_rungs;
   return PPRS_OK;
 }
 

@@ -274,6 +274,33 @@ def test_launch_shape_does_not_change_results():
         P.set_tuning(dict(pool_group=-1))
 
 
+@pytest.mark.parametrize("K", [1, 2])
+def test_line_search_pass_width_does_not_change_results(K):
+    """Step sizes per line-search pass (1, 2, 3, 5, 7) only change how many ladder steps one
+    pass evaluates: the ladder is walked in the same order with the same group rule, so the
+    results, the accepted steps and the group counts are the same bits for every width."""
+    torch = _torch()
+    import paper_1712_02533_amd as P
+    from dataclasses import replace
+    s = make_series(SeriesSpec(8, 128, 4.0, 1.0, 10.0, 23))
+    frames = torch.tensor(s.frames, device="cuda")
+    params = replace(_gpu_params(3, scan="brent_kung"), ladder_k=K)
+    base = P.get_tuning()
+    u1, _, o1 = P.prefix_register_series(frames, params=params, want_op_stats=True)
+    try:
+        for nc in (1, 2, 3, 5, 7):
+            P.set_tuning(dict(ladder_rungs=nc))
+            u2, _, o2 = P.prefix_register_series(frames, params=params, want_op_stats=True)
+            say("K=%d, %d step sizes per pass: identical %s" % (K, nc, bool(torch.equal(u1, u2))))
+            assert torch.equal(u1, u2)
+            assert [a.iters for a in o1] == [b.iters for b in o2]
+            assert [a.passes for a in o1] == [b.passes for b in o2]
+        with pytest.raises(P.PprsError):
+            P.set_tuning(dict(ladder_rungs=4))
+    finally:
+        P.set_tuning(base)
+
+
 def test_windowed_metric_solve_matches_exact_line_solves():
     """The one-pass windowed metric solve (halo chosen from beta) against the exact two-pass
     line solves on the same series: FP32-rounding-level differences, the same decisions on
