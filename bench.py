@@ -82,6 +82,28 @@ def stream_bandwidth(torch, dev, gib=2, reps=3):
     return 2.0 * (gib << 30) / (best * 1e-3) / 1e9
 
 
+def kernel_roofline(kt, stream, traffic):
+    """Per-kind figures and the roofline object of the dominant kernel kind (most event time)
+    from P.kernel_timing() output {kind: (ms, launches, algorithmic bytes)}. traffic: read the
+    calibrated counter figure from profiles/ (taken on the 512-frame series only)."""
+    log("device copy (2 GiB each way): %.0f GB/s" % stream)
+    kernels = {}
+    for name, (ms, launches, byts) in kt.items():
+        if launches:
+            kernels[name] = dict(ms=round(ms, 3), launches=launches,
+                                 gbs=round(byts / (ms * 1e-3) / 1e9, 1) if ms > 0 else None)
+    cand = {k: v for k, v in kt.items() if v[2] > 0}
+    dom = max(cand, key=lambda k: cand[k][0])
+    ms, launches, byts = kt[dom]
+    achieved = byts / (ms * 1e-3) / 1e9
+    roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=traffic_from_profiles(dom) if traffic else None, launches=launches,
+                    avg_launch_us=round(1e3 * ms / launches, 2), bytes_per_launch=byts / launches,
+                    stream_gbs=round(stream, 1), frac_of_stream=round(achieved / stream, 4))
+    return roofline, kernels
+
+
 def cpu_baseline(series, cfg, n_ops, threads):
     """The FP64 oracle on `n_ops` neighbour registrations of the same series, run on `threads`
     host threads (one registration per thread at a time)."""
@@ -204,6 +226,15 @@ def bench_uneven(args):
     for w in range(args.warmup):
         run(1, "warmup")
     value, ms, lat = run(args.steps, "cold")
+    roofline, kernels = None, {}
+    if not args.no_timing:
+        P.set_kernel_timing(True, dev)
+        P.kernel_timing(reset=True, device=dev)
+        P.register_series_batch(frames, params=params, levels=levels, outs=outs)
+        torch.cuda.synchronize()
+        kt = P.kernel_timing(reset=True, device=dev)
+        P.set_kernel_timing(False, dev)
+        roofline, kernels = kernel_roofline(kt, stream_bandwidth(torch, dev), traffic=False)
     result = dict(
         metric=METRIC, value=round(value, 3), unit="registrations/s", n_gpus=1,
         steps=args.steps, warmup=args.warmup, ms_per_step=round(ms, 1), higher_is_better=True,
@@ -212,7 +243,8 @@ def bench_uneven(args):
                     sides=[int(f.shape[1]) for f in frames],
                     frames=[int(f.shape[0]) for f in frames], levels=levels, start="cold"),
         latency_ms=dict(p50=round(float(np.percentile(lat, 50)), 1),
-                        p99=round(float(np.percentile(lat, 99)), 1), samples=len(lat)))
+                        p99=round(float(np.percentile(lat, 99)), 1), samples=len(lat)),
+        roofline=roofline, kernels=kernels)
     weights = os.path.join(ROOT, "paper_1712_02533_amd", "weights", "warmstart_mixed.safetensors")
     if not args.no_warm and os.path.exists(weights):
         net = P.WarmStartNet()
@@ -316,24 +348,9 @@ def main():
     roofline = None
     kernels = {}
     if timing:
-        for name, (ms, launches, byts) in kt.items():
-            if launches:
-                kernels[name] = dict(ms=round(ms, 3), launches=launches,
-                                     gbs=round(byts / (ms * 1e-3) / 1e9, 1) if ms > 0 else None)
-        cand = {k: v for k, v in kt.items() if v[2] > 0}
-        dom = max(cand, key=lambda k: cand[k][0])
-        ms, launches, byts = kt[dom]
-        achieved = byts / (ms * 1e-3) / 1e9
-        tr = traffic_from_profiles(dom)
         # measured here only with timing on: the counter runs (no timing) keep the 256 MiB
         # calibration copy as their largest copy
-        stream = stream_bandwidth(torch, dev)
-        log("device copy (2 GiB each way): %.0f GB/s" % stream)
-        roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                        unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                        traffic=tr, launches=launches, avg_launch_us=round(1e3 * ms / launches, 2),
-                        bytes_per_launch=byts / launches, stream_gbs=round(stream, 1),
-                        frac_of_stream=round(achieved / stream, 4))
+        roofline, kernels = kernel_roofline(kt, stream_bandwidth(torch, dev), traffic=True)
     result = dict(
         metric=METRIC, value=round(value, 3), unit="registrations/s", n_gpus=1,
         steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_per_step, 1),
