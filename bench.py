@@ -20,6 +20,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "frame-pair registrations/s and series scan time (512², N=512), warm vs cold"
 HBM_PEAK_GBS = 8000.0
+SCAN_NAMES = {"sequential": "sequential", "brent_kung": "Brent-Kung", "kogge_stone": "Kogge-Stone",
+              "sklansky": "Sklansky"}
 WORKLOADS = {
     "c3": dict(name="512 frames of 512x512, drift<=8 px, non-rigid<=1.5 px, 5 counts; "
                     "4 levels; Brent-Kung scan; cold start",
@@ -271,6 +273,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--frames", type=int, default=0, help="override the series length")
+    ap.add_argument("--scan", default="", help="override the scan schedule (sequential, "
+                    "brent_kung, kogge_stone, sklansky)")
     ap.add_argument("--cpu-ops", type=int, default=0, help="oracle sample size (0 = auto)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
@@ -304,7 +308,8 @@ def main():
     dev = torch.device("cuda", 0)
     frames = torch.tensor(series.frames, device=dev)
     out = torch.empty((spec.n_frames, 2, spec.side, spec.side), device=dev)
-    params = P.Params(levels=cfg["levels"], scan=cfg["scan"])
+    scan = args.scan or cfg["scan"]
+    params = P.Params(levels=cfg["levels"], scan=scan)
     # a plain device copy of known size (256 MiB read + 256 MiB written), untimed: profiler
     # counters of this kernel calibrate the HBM byte counters of the registration kernels
     calib = torch.empty(64 << 20, device=dev)
@@ -356,8 +361,9 @@ def main():
         steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_per_step, 1),
         higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
         data="synthetic",
-        config=dict(workload=WORKLOADS[args.config]["name"], frames=spec.n_frames,
-                    side=spec.side, levels=cfg["levels"], scan=cfg["scan"], start="cold",
+        config=dict(workload=WORKLOADS[args.config]["name"].replace(
+                        "Brent-Kung scan", SCAN_NAMES[scan] + " scan"), frames=spec.n_frames,
+                    side=spec.side, levels=cfg["levels"], scan=scan, start="cold",
                     tuning=tuning,
                     registrations_per_step=stats[0].n_ops_a + stats[0].n_ops_b),
         series_scan_s=round(ms_per_step / 1e3, 3),

@@ -42,7 +42,12 @@ typedef enum {
   PPRS_ENAN = -6          /* a registration produced a non-finite energy */
 } pprs_status;
 
-enum { PPRS_SCAN_SEQUENTIAL = 0, PPRS_SCAN_BRENT_KUNG = 1 };
+enum {
+  PPRS_SCAN_SEQUENTIAL = 0,   /* algorithm "serial" of the Prefix sum chapter */
+  PPRS_SCAN_BRENT_KUNG = 1,   /* algorithm "brent_kung" (work-efficient, 2 log2 M - 1 levels) */
+  PPRS_SCAN_KOGGE_STONE = 2,  /* algorithm "kogge_stone" (log2 M levels, M log2 M - M + 1 ops) */
+  PPRS_SCAN_SKLANSKY = 3      /* algorithm "sklansky" (log2 M levels, M/2 log2 M ops) */
+};
 
 enum { PPRS_FLAG_NONCONV = 1, PPRS_FLAG_NAN = 2, PPRS_FLAG_FALLBACK = 4 };
 
@@ -134,8 +139,9 @@ pprs_status pprs_compose_deformations(pprs_ctx* ctx, const float* u_ij, const fl
    f_i o phi_{0,i} ~ f_0. The neighbour registrations and the scan's B applications run in one
    pool of concurrent registrations (pprs_set_pool), each B application as soon as its inputs
    exist. stats and op_stats are host pointers and
-   may be NULL; op_stats receives N-1 A entries followed by the B entries in schedule order
-   (pprs_scan_plan gives their count, at most 2(N-1)), so 3N entries always suffice. */
+   may be NULL; op_stats receives N-1 A entries followed by the B entries in schedule order,
+   so it needs N-1 + n_ops entries (n_ops from pprs_scan_plan for M = N-1: at most 2(N-1) for
+   the sequential and Brent-Kung schedules, about (N-1) log2(N-1) for the others). */
 pprs_status pprs_prefix_register_series(pprs_ctx* ctx, const float* frames, int N, int H,
                                         int W, float* u_out, const pprs_params* params,
                                         pprs_series_stats* stats, pprs_pair_stats* op_stats);
@@ -198,9 +204,13 @@ pprs_status pprs_register_series_batch(pprs_ctx* ctx, int S, const float* const*
                                        float* const* u_out, const pprs_params* params,
                                        pprs_series_stats* stats, double* latency_ms);
 
-/* Host-only: the scan schedule over M = N-1 elements (algorithms "serial" and "brent_kung").
+/* Host-only: the scan schedule over M = N-1 elements (PPRS_SCAN_*: the Prefix sum chapter's
+   algorithms "serial", "brent_kung", "kogge_stone" and "sklansky").
    ops (host, capacity `cap` triples) receives (left, right, level) per B application in
-   execution order: x[right] <- x[left] (.) x[right]; ops of one level are independent.
+   execution order: x[right] <- x[left] (.) x[right], each operand taken as it stands at that
+   point of the list. Within a level no op reads an element an earlier op of the level wrote,
+   so the ops of a level are independent (Kogge-Stone lists a level right to left for this: its
+   ops read the previous level's values, the double buffering of the paper's description).
    Writes the op count and level count. Returns PPRS_EINVAL for bad arguments or a too small
    capacity (then *n_ops holds the needed count). Makes no HIP call. */
 pprs_status pprs_scan_plan(int kind, int M, int* ops, int cap, int* n_ops, int* n_levels);

@@ -24,7 +24,7 @@ _lock = threading.Lock()
 _lib = None
 
 TRACE_W = 8
-SCAN_KINDS = {"sequential": 0, "brent_kung": 1}
+SCAN_KINDS = {"sequential": 0, "brent_kung": 1, "kogge_stone": 2, "sklansky": 3}
 
 
 def build(force: bool = True) -> str:
@@ -291,8 +291,11 @@ def series(frames_nodal, params: Params, scan: str = "brent_kung", threads: int 
     N, n = fr.shape[0], fr.shape[-1]
     u = np.zeros((N, 2, n, n))
     a_st = (_CStats * max(N - 1, 1))()
-    b_st = (_CStats * max(2 * N, 1))()
-    pairs = np.zeros(3 * max(2 * N, 1), dtype=np.int32)
+    # B ops: at most 2(M-1) for sequential and Brent-Kung, M log2 M for Kogge-Stone and Sklansky
+    M = max(N - 1, 1)
+    cap = 2 * M + M * max(1, int(np.ceil(np.log2(M))))
+    b_st = (_CStats * cap)()
+    pairs = np.zeros(3 * cap, dtype=np.int32)
     cp = params.c()
     rc = _load().or_series(_d(fr), N, n, ctypes.byref(cp), SCAN_KINDS[scan], _d(u), a_st, b_st,
                            pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), threads)

@@ -25,7 +25,9 @@
  *    tau_max = cap h / max|d|; the largest passing step is taken; if none passes the ladder
  *    moves 2K+1 halvings down; below tau_min_rel * tau_max the level stops;
  *  - stopping: E_k - E_{k+1} < eps, or iter_max accepted steps, or a failed line search, or
- *    G.d <= 0.
+ *    G.d <= 0;
+ *  - scans: the serial, Brent-Kung, Kogge-Stone and Sklansky listings in their standard
+ *    0-based forms for any element count (the Kogge-Stone inner loop starts at 2^i).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -711,7 +713,7 @@ void or_compose(const double* uij, const double* ujk, int n, double* out) {
 /* Elements x_m = (m, m+1, A(f_m, f_{m+1}, id)), m = 0..N-2; y_m = x_0 (.) ... (.) x_m.        */
 /* (i, j, u) (.) (j, k, v) = (i, k, A(f_i, f_k, v o u)).                                         */
 
-enum { OR_SCAN_SEQUENTIAL = 0, OR_SCAN_BRENT_KUNG = 1 };
+enum { OR_SCAN_SEQUENTIAL = 0, OR_SCAN_BRENT_KUNG = 1, OR_SCAN_KOGGE_STONE = 2, OR_SCAN_SKLANSKY = 3 };
 
 typedef struct {
   int i, k;
@@ -815,6 +817,36 @@ int or_series(const double* frames, int N, int nf, const or_params* p, int scan,
         apply_b(&S, &x[j - d], &x[j], ops + q);
       }
       ops += cnt;
+    }
+  } else if (scan == OR_SCAN_KOGGE_STONE) {
+    /* Step d = 1, 2, 4, ...: x_j <- x_{j-d} (.) x_j for every j >= d, each with the values of
+       the previous step (the double buffering the Kogge-Stone section describes); the listing's
+       lower bound of j is read as d. Taking j from the right end down reads every x_{j-d}
+       before this step rewrites it, which is that double buffering without a second array. */
+    for (int d = 1; d < M; d *= 2)
+      for (int j = M - 1; j >= d; --j) apply_b(&S, &x[j - d], &x[j], ops++);
+  } else if (scan == OR_SCAN_SKLANSKY) {
+    /* Step d = 1, 2, 4, ...: in every block of 2d elements, each of the upper d elements takes
+       the last element of the lower d as its left operand (Sklansky listing: sources j =
+       d-1, 3d-1, ..., destinations j+1 .. j+d). No op of a step rewrites a source. */
+    for (int d = 1; d < M; d *= 2) {
+      int cnt = 0;
+      for (int j = d - 1; j < M; j += 2 * d)
+        for (int k = 0; k < d && j + k + 1 < M; ++k) ++cnt;
+      int* src = malloc(sizeof(int) * (cnt > 0 ? cnt : 1));
+      int* dst = malloc(sizeof(int) * (cnt > 0 ? cnt : 1));
+      int q = 0;
+      for (int j = d - 1; j < M; j += 2 * d)
+        for (int k = 0; k < d && j + k + 1 < M; ++k) {
+          src[q] = j;
+          dst[q] = j + k + 1;
+          ++q;
+        }
+#pragma omp parallel for schedule(dynamic, 1)
+      for (int t = 0; t < cnt; ++t) apply_b(&S, &x[src[t]], &x[dst[t]], ops + t);
+      ops += cnt;
+      free(src);
+      free(dst);
     }
   } else {
     free(x);

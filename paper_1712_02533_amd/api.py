@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("PPRS_LIBRARY") or os.path.join(_HERE, "libpprs.so")
 
 PPRS_OK = 0
 PPRS_NOT_CONVERGED = 1
-SCAN_KINDS = {"sequential": 0, "brent_kung": 1}
+SCAN_KINDS = {"sequential": 0, "brent_kung": 1, "kogge_stone": 2, "sklansky": 3}
 MAX_LEVELS = 16
 
 
@@ -298,7 +298,8 @@ def prefix_register_series(frames, params: Params | None = None, out=None,
     ss = _CSeriesStats()
     ops = None
     if want_op_stats:
-        ops = (_CPairStats * max(3 * N, 1))()   # N-1 A entries + at most 2(N-1) B entries
+        n_b = len(scan_plan(params.scan, max(N - 1, 0))[0])
+        ops = (_CPairStats * max(N - 1 + n_b, 1))()   # N-1 A entries, then the B entries
     cp = params.c()
     c = _ctx(frames.device)
     _check(_lib().pprs_prefix_register_series(

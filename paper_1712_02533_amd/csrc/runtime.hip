@@ -168,7 +168,7 @@ pprs_status check_params(const pprs_params* p, int L) {
     return fail(PPRS_EINVAL, "tau_min_rel must be in (0, 1)");
   if (!(p->eps >= 0.0)) return fail(PPRS_EINVAL, "eps must be >= 0");
   if (p->iter_max < 0) return fail(PPRS_EINVAL, "iter_max must be >= 0");
-  if (p->scan != PPRS_SCAN_SEQUENTIAL && p->scan != PPRS_SCAN_BRENT_KUNG)
+  if (p->scan < PPRS_SCAN_SEQUENTIAL || p->scan > PPRS_SCAN_SKLANSKY)
     return fail(PPRS_EINVAL, "unknown scan kind %d", p->scan);
   return PPRS_OK;
 }
@@ -1194,7 +1194,7 @@ struct SeriesJob {
   int N, H, L, m0;
   float* u_out;         // device [N][2][H][H]
   pprs_series_stats* stats;
-  pprs_pair_stats* op_stats;  // 3N entries, may be NULL
+  pprs_pair_stats* op_stats;  // N-1 + B-op count entries, may be NULL
   double* latency_ms;   // time from the start of the run to the series' last result, or NULL
 };
 

@@ -46,7 +46,7 @@ def _interval(a, b):
     return (a[0], b[1])
 
 
-@pytest.mark.parametrize("kind", ["sequential", "brent_kung"])
+@pytest.mark.parametrize("kind", ["sequential", "brent_kung", "kogge_stone", "sklansky"])
 @pytest.mark.parametrize("M", [0, 1, 2, 3, 7, 8, 9, 63, 64, 100, 511])
 def test_plan_matches_sequential_scan_with_associative_ops(kind, M):
     plan, levels = P.scan_plan(kind, M)
@@ -61,22 +61,37 @@ def test_plan_matches_sequential_scan_with_associative_ops(kind, M):
     for m in range(M):
         acc = mats[m] if acc is None else acc @ mats[m]
         assert np.array_equal(got[m], acc)
-    # ops of one level are independent: no op reads an element written in the same level
+    # ops of one level are independent: in list order no op reads an element that an earlier
+    # op of its level wrote (Kogge-Stone relies on its right-to-left order for this), and no
+    # element is written twice in a level
     by_level = {}
     for left, right, lv in plan:
         by_level.setdefault(lv, []).append((left, right))
     for ops in by_level.values():
-        written = {r for _, r in ops}
-        assert not any(l in written for l, _ in ops)
-        assert len(written) == len(ops)
+        written = set()
+        for left, right in ops:
+            assert left not in written and right not in written
+            written.add(right)
     assert len(by_level) == levels
+    assert [lv for _, _, lv in plan] == sorted(lv for _, _, lv in plan)
 
 
 def test_plan_counts_match_paper_figures_and_table():
     fig = GOLD["scan_figures_N8"]
-    for kind in ("sequential", "brent_kung"):
+    for kind in ("sequential", "brent_kung", "kogge_stone", "sklansky"):
         plan, levels = P.scan_plan(kind, 8)
         assert len(plan) == fig[kind]["ops"] and levels == fig[kind]["steps"]
+    for k in range(1, 11):
+        N = 2 ** k
+        # work and span of the Kogge-Stone and Sklansky sections: N log2 N - N + 1 and
+        # N/2 log2 N operator applications, log2 N steps each
+        plan, levels = P.scan_plan("kogge_stone", N)
+        assert len(plan) == N * k - N + 1 and levels == k
+        plan, levels = P.scan_plan("sklansky", N)
+        assert len(plan) == N // 2 * k and levels == k
+        for kind in ("kogge_stone", "sklansky"):
+            plan, levels = P.scan_plan(kind, N)
+            assert len(plan) + levels >= 2 * N - 2    # Snir: size + depth >= 2N - 2
     for k in range(1, 11):
         N = 2 ** k
         plan, levels = P.scan_plan("brent_kung", N)
@@ -92,6 +107,8 @@ def test_plan_rejects_bad_arguments():
     lv = ctypes.c_int()
     lib = api._lib()
     assert lib.pprs_scan_plan(7, 8, None, 0, ctypes.byref(n), ctypes.byref(lv)) == -1
+    assert lib.pprs_scan_plan(4, 8, None, 0, ctypes.byref(n), ctypes.byref(lv)) == -1
+    assert lib.pprs_scan_plan(-1, 8, None, 0, ctypes.byref(n), ctypes.byref(lv)) == -1
     assert lib.pprs_scan_plan(1, -1, None, 0, ctypes.byref(n), ctypes.byref(lv)) == -1
     buf = (ctypes.c_int * 3)()
     assert lib.pprs_scan_plan(1, 8, buf, 1, ctypes.byref(n), ctypes.byref(lv)) == -1

@@ -191,8 +191,9 @@ def test_series_c1_sequential_matches_oracle():
     assert err < TOL_PX
 
 
-def test_series_brent_kung_matches_oracle():
-    u, ref, err = _series_case(SeriesSpec(12, 128, 4.0, 1.0, 10.0, 1), 3, "brent_kung")
+@pytest.mark.parametrize("scan", ["brent_kung", "kogge_stone", "sklansky"])
+def test_series_parallel_scans_match_oracle(scan):
+    u, ref, err = _series_case(SeriesSpec(12, 128, 4.0, 1.0, 10.0, 1), 3, scan)
     assert err < TOL_PX
 
 

@@ -432,7 +432,7 @@ def test_composition_identity_constants_affine():
 def test_series_identical_frames_all_zero():
     s = make_series(SeriesSpec(1, 32, 0.0, 0.0, 20.0, 13))
     fr = np.stack([O.frame_to_nodes(s.frames[0])] * 5)
-    for scan in ("sequential", "brent_kung"):
+    for scan in ("sequential", "brent_kung", "kogge_stone", "sklansky"):
         u, a, b, pairs = O.series(fr, O.Params(levels=2), scan=scan)
         assert np.all(u == 0.0)
 
@@ -451,22 +451,71 @@ def test_series_bk_schedule_counts_and_pairs(M, ops):
         assert i < j < k
 
 
+def _ks_expected(M):
+    """Kogge-Stone section: step d = 1, 2, 4, ... combines x_{j-d} with x_j for j = d .. M-1,
+    both as they were after the previous step. Tracked as frame intervals."""
+    x = [(m, m + 1) for m in range(M)]
+    out, d = [], 1
+    while d < M:
+        prev = list(x)
+        for j in range(d, M):
+            assert prev[j - d][1] == prev[j][0]
+            out.append((prev[j - d][0], prev[j - d][1], prev[j][1]))
+            x[j] = (prev[j - d][0], prev[j][1])
+        d *= 2
+    return out, x
+
+
+def _sk_expected(M):
+    """Sklansky section: step d = 1, 2, 4, ...: the upper half of every block of 2d elements
+    takes the last element of the lower half as left operand."""
+    x = [(m, m + 1) for m in range(M)]
+    out, d = [], 1
+    while d < M:
+        for base in range(0, M, 2 * d):
+            src = base + d - 1
+            for dst in range(base + d, min(base + 2 * d, M)):
+                out.append((x[src][0], x[src][1], x[dst][1]))
+                x[dst] = (x[src][0], x[dst][1])
+        d *= 2
+    return out, x
+
+
+@pytest.mark.parametrize("M", [1, 2, 5, 8, 11, 16])
+@pytest.mark.parametrize("scan", ["kogge_stone", "sklansky"])
+def test_series_ks_sklansky_schedule_pairs(scan, M):
+    """The oracle's Kogge-Stone and Sklansky scans apply B to exactly the (i, j, k) triples the
+    sections' step rules give (order within a step aside), 17 and 12 of them for 8 elements
+    (figures), and end with every element covering (0, m+1)."""
+    s = make_series(SeriesSpec(M + 1, 16, 0.5, 0.0, 0.0, 14))
+    fr = np.stack([O.frame_to_nodes(f) for f in s.frames])
+    u, a, b, pairs = O.series(fr, O.Params(levels=1, iter_max=0), scan=scan)
+    exp, final = (_ks_expected if scan == "kogge_stone" else _sk_expected)(M)
+    assert sorted(tuple(int(v) for v in p) for p in pairs) == sorted(exp)
+    assert final == [(0, m + 1) for m in range(M)]
+    if M == 8:
+        assert len(pairs) == GOLD["scan_figures_N8"][scan]["ops"]
+
+
 def test_series_translation_chain_and_bk_vs_sequential():
     spec = SeriesSpec(6, 64, 1.0, 0.0, 0.0, 15)
     s = make_series(spec)
     fr = np.stack([O.frame_to_nodes(f) for f in s.frames])
     p = O.Params(levels=3, lam=10.0, eps=3e-4)
     useq, _, _, _ = O.series(fr, p, scan="sequential")
-    ubk, _, _, _ = O.series(fr, p, scan="brent_kung")
     b = 8
     for k in range(1, 6):
         gt = ground_truth(s, k)
         e = O.u_to_pixels(useq[k], 64) - gt
         assert np.sqrt((e[:, b:-b, b:-b] ** 2).mean()) < 0.1
-        d = O.u_to_pixels(ubk[k] - useq[k], 64)
-        # approximate associativity (definition in the associativity section)
-        assert np.sqrt((d[:, b:-b, b:-b] ** 2).mean()) < 0.05
-    assert np.all(useq[0] == 0) and np.all(ubk[0] == 0)
+    for scan in ("brent_kung", "kogge_stone", "sklansky"):
+        upar, _, _, _ = O.series(fr, p, scan=scan)
+        for k in range(1, 6):
+            d = O.u_to_pixels(upar[k] - useq[k], 64)
+            # approximate associativity (definition in the associativity section)
+            assert np.sqrt((d[:, b:-b, b:-b] ** 2).mean()) < 0.05
+        assert np.all(upar[0] == 0)
+    assert np.all(useq[0] == 0)
 
 
 @pytest.mark.slow
