@@ -370,6 +370,21 @@ def main():
         roofline=roofline, kernels=kernels,
         node_steps=stats[0].node_steps, node_passes=stats[0].node_passes,
     )
+    # series averaging of the registered frames (the scan's consumer): u 8 B + frame 4 B per
+    # pixel and frame, plus the average written once
+    avg = torch.empty((spec.side, spec.side), device=dev)
+    P.series_average(frames, out, avg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        P.series_average(frames, out, avg)
+    torch.cuda.synchronize()
+    ams = 1e3 * (time.perf_counter() - t0) / reps
+    abytes = spec.n_frames * spec.side * spec.side * 12 + spec.side * spec.side * 4
+    result["average"] = dict(ms=round(ams, 3), bytes=abytes,
+                             gbs=round(abytes / (ams * 1e-3) / 1e9, 1))
+    log("series average: %.3f ms, %.0f GB/s" % (ams, abytes / (ams * 1e-3) / 1e9))
     if not args.no_warm and os.path.exists(args.weights) and spec.side >= 128:
         result["warm"] = warm_runs(P, frames, out, params, args, stats[0].n_ops_a + stats[0].n_ops_b)
     if not args.no_cpu:

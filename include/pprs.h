@@ -204,6 +204,15 @@ pprs_status pprs_register_series_batch(pprs_ctx* ctx, int S, const float* const*
                                        float* const* u_out, const pprs_params* params,
                                        pprs_series_stats* stats, double* latency_ms);
 
+/* Series averaging (Introduction; image series registration): the aligned frames f_i o phi_0i
+   averaged into one image, avg(x) = 1/N sum_i f_i(x + u_i(x)), the consumer of the scan output.
+   frames [N][H][W] and u [N][2][H][W] (pixels, as pprs_prefix_register_series writes them,
+   u[0] = 0) are device pointers; avg [H][W] (device) receives the mean. Frames are sampled
+   bilinearly on the pixel grid, positions clamped to [0, W-1] x [0, H-1]; the sum runs in FP64
+   in frame order. Any H, W >= 2. Synchronous on the context stream. */
+pprs_status pprs_series_average(pprs_ctx* ctx, const float* frames, const float* u, int N, int H,
+                                int W, float* avg);
+
 /* Host-only: the scan schedule over M = N-1 elements (PPRS_SCAN_*: the Prefix sum chapter's
    algorithms "serial", "brent_kung", "kogge_stone" and "sklansky").
    ops (host, capacity `cap` triples) receives (left, right, level) per B application in

@@ -306,6 +306,32 @@ def series(frames_nodal, params: Params, scan: str = "brent_kung", threads: int 
     return u, a, b, [tuple(pairs[3 * m: 3 * m + 3]) for m in range(rc)]
 
 
+def series_average(frames, u, pixels=None):
+    """Series averaging (Introduction; image series registration): the aligned frames
+    f_i o phi_{0,i} averaged, avg(x) = 1/N sum_i f_i(x + u_i(x)), on the pixel grid (x is the
+    column, y the row), each f_i interpolated bilinearly with the position clamped to
+    [0, W-1] x [0, H-1]. frames [N, H, W], u [N, 2, H, W] in pixels. pixels: optional
+    (rows, cols) integer arrays; then only those pixels are evaluated (1-D result). FP64."""
+    f = np.asarray(frames, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    N, H, W = f.shape
+    if pixels is None:
+        r, c = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    else:
+        r, c = (np.asarray(a) for a in pixels)
+    acc = np.zeros(r.shape)
+    for i in range(N):
+        x = np.clip(c + u[i, 0][r, c], 0.0, W - 1.0)
+        y = np.clip(r + u[i, 1][r, c], 0.0, H - 1.0)
+        x0 = np.minimum(np.floor(x).astype(np.int64), W - 2)
+        y0 = np.minimum(np.floor(y).astype(np.int64), H - 2)
+        fx, fy = x - x0, y - y0
+        top = (1.0 - fx) * f[i][y0, x0] + fx * f[i][y0, x0 + 1]
+        bot = (1.0 - fx) * f[i][y0 + 1, x0] + fx * f[i][y0 + 1, x0 + 1]
+        acc += (1.0 - fy) * top + fy * bot
+    return acc / N
+
+
 # ------------------------------------------------------------------------------------------ #
 # Pixel frames <-> nodal grids (the API works in pixels of 2^L x 2^L frames)
 

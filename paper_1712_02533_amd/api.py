@@ -125,6 +125,7 @@ def _lib():
                                             ctypes.POINTER(_CParams),
                                             ctypes.POINTER(_CPairStats)]),
                 "pprs_compose_deformations": (i, [vp, vp, vp, vp, i, i]),
+                "pprs_series_average": (i, [vp, vp, vp, i, i, i, vp]),
                 "pprs_prefix_register_series": (i, [vp, vp, i, i, i, vp,
                                                     ctypes.POINTER(_CParams),
                                                     ctypes.POINTER(_CSeriesStats),
@@ -283,6 +284,21 @@ def compose_deformations(u_ij, u_jk, out=None):
     c = _ctx(u_ij.device)
     _check(_lib().pprs_compose_deformations(c.handle, _dev_f32(u_ij, "u_ij"),
                                             _dev_f32(u_jk, "u_jk"), _dev_f32(out, "out"), H, W))
+    return out
+
+
+def series_average(frames, u, out=None):
+    """Average of the aligned frames f_i o phi_{0,i}: [H, W] from frames [N, H, W] and the
+    series result u [N, 2, H, W] (pixels)."""
+    import torch
+    N, H, W = frames.shape
+    if tuple(u.shape) != (N, 2, H, W):
+        raise PprsError(-1, "u must be [N, 2, H, W] for frames [N, H, W]")
+    if out is None:
+        out = torch.empty((H, W), device=frames.device, dtype=torch.float32)
+    c = _ctx(frames.device)
+    _check(_lib().pprs_series_average(c.handle, _dev_f32(frames, "frames"), _dev_f32(u, "u"),
+                                      N, H, W, _dev_f32(out, "out")))
     return out
 
 

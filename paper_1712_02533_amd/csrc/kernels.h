@@ -53,4 +53,7 @@ hipError_t pool_finish(BatchDesc* d, int L, const int* slots, const long long* o
                        float* vbuf, hipStream_t st);
 hipError_t from_nodes_idx(const float* vbuf, const long long* offs, int n, float* dst, int H,
                           long long d_plane, int elems, float scale, hipStream_t st);
+// avg[H][W] = mean over i of frames[i] sampled at x + u[i](x) (pixels, clamped, bilinear)
+hipError_t series_average(const float* frames, const float* u, int N, int H, int W, float* out,
+                          hipStream_t st);
 }  // namespace pprs_k

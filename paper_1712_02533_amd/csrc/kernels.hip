@@ -1599,6 +1599,53 @@ __global__ void __launch_bounds__(BLOCK) k_from_nodes_idx(const float* vbuf,
 }
 
 // ------------------------------------------------------------------------------------------
+// Series averaging: avg(x) = 1/N sum_i f_i(x + u_i(x)) over the aligned frames f_i o phi_{0,i}
+// (pixel grid, bilinear, clamped to [0, W-1] x [0, H-1]). One pixel per lane; the frames are
+// taken four at a time so a lane has 8 displacement loads and 16 frame loads in flight; the sum
+// runs in FP64 in frame order, so every pixel's result is fixed whatever the launch.
+
+__device__ __forceinline__ float sample_px(const float* f, int H, int W, float x, float y) {
+  x = fminf(fmaxf(x, 0.f), (float)(W - 1));
+  y = fminf(fmaxf(y, 0.f), (float)(H - 1));
+  int x0 = min((int)floorf(x), W - 2), y0 = min((int)floorf(y), H - 2);
+  float fx = x - (float)x0, fy = y - (float)y0;
+  const GAS float* p = (const GAS float*)f + (size_t)y0 * W + x0;
+  float v00 = p[0], v01 = p[1], v10 = p[W], v11 = p[W + 1];
+  float top = fmaf(fx, v01 - v00, v00);
+  float bot = fmaf(fx, v11 - v10, v10);
+  return fmaf(fy, bot - top, top);
+}
+
+__global__ void __launch_bounds__(BLOCK) k_series_average(const float* frames, const float* u,
+                                                          int N, int H, int W, float* out) {
+  const long long plane = (long long)H * W;
+  for (long long k = blockIdx.x * (long long)BLOCK + threadIdx.x; k < plane;
+       k += (long long)gridDim.x * BLOCK) {
+    int r = (int)(k / W), c = (int)(k - (long long)r * W);
+    double acc = 0.0;
+    int i = 0;
+    for (; i + 4 <= N; i += 4) {
+      float ux[4], uy[4], v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ux[q] = gld(u, (size_t)(i + q) * 2 * plane + k);
+        uy[q] = gld(u, (size_t)(i + q) * 2 * plane + plane + k);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        v[q] = sample_px(frames + (size_t)(i + q) * plane, H, W, (float)c + ux[q], (float)r + uy[q]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc += (double)v[q];
+    }
+    for (; i < N; ++i) {
+      float ux = gld(u, (size_t)i * 2 * plane + k), uy = gld(u, (size_t)i * 2 * plane + plane + k);
+      acc += (double)sample_px(frames + (size_t)i * plane, H, W, (float)c + ux, (float)r + uy);
+    }
+    gst(out, k, (float)(acc / N));
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // Host launch wrappers
 
 namespace pprs_k {
@@ -1796,6 +1843,13 @@ hipError_t from_nodes_idx(const float* vbuf, const long long* offs, int n, float
                           long long d_plane, int elems, float scale, hipStream_t st) {
   hipLaunchKernelGGL(k_from_nodes_idx, dim3(grid_for((long long)elems * 2 * H * H)), dim3(BLOCK),
                      0, st, vbuf, offs, n, dst, H, d_plane, elems, scale);
+  return hipGetLastError();
+}
+
+hipError_t series_average(const float* frames, const float* u, int N, int H, int W, float* out,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_series_average, dim3(grid_for((long long)H * W)), dim3(BLOCK), 0, st,
+                     frames, u, N, H, W, out);
   return hipGetLastError();
 }
 

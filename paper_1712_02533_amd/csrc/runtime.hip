@@ -1179,6 +1179,16 @@ pprs_status pprs_compose_deformations(pprs_ctx* c, const float* u_ij, const floa
   return PPRS_OK;
 }
 
+pprs_status pprs_series_average(pprs_ctx* c, const float* frames, const float* u, int N, int H,
+                                int W, float* avg) {
+  STCHK(enter(c));
+  if (N < 1 || H < 2 || W < 2) return fail(PPRS_EINVAL, "need N >= 1 frames of at least 2x2");
+  if (!frames || !u || !avg) return fail(PPRS_EINVAL, "NULL pointer");
+  HIPCHK(pprs_k::series_average(frames, u, N, H, W, avg, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return PPRS_OK;
+}
+
 // RAII for the series timing events.
 struct EventSet {
   hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};

@@ -539,3 +539,54 @@ def test_fp32_storage_sensitivity_at_full_size():
     assert np.sqrt((d ** 2).mean()) < 1e-4
     assert np.percentile(d, 99.9) < 1e-3
     assert 1e-3 < d.max() < 0.05
+
+
+# ------------------------------------------------------------------------------------------
+# Series averaging (Introduction: the aligned frames f_i o phi_{0,i} averaged)
+
+def test_average_zero_displacement_is_plain_mean():
+    rng = np.random.default_rng(31)
+    f = rng.uniform(0, 10, size=(5, 12, 17))
+    got = O.series_average(f, np.zeros((5, 2, 12, 17)))
+    assert np.allclose(got, f.mean(axis=0), rtol=0, atol=1e-12)
+
+
+def test_average_undoes_integer_shifts_inside():
+    """f_i is a reference image g shifted by t_i; with u_i = t_i every aligned frame is g again,
+    so the average is g wherever no sample was clamped."""
+    rng = np.random.default_rng(32)
+    g = rng.uniform(0, 1, size=(40, 40))
+    shifts = [(0, 0), (3, -2), (-4, 1), (2, 5)]
+    H = W = 40
+    f = np.zeros((len(shifts), H, W))
+    u = np.zeros((len(shifts), 2, H, W))
+    for i, (tx, ty) in enumerate(shifts):
+        for r in range(H):
+            for c in range(W):
+                rr, cc = min(max(r - ty, 0), H - 1), min(max(c - tx, 0), W - 1)
+                f[i, r, c] = g[rr, cc]
+        u[i, 0], u[i, 1] = tx, ty
+    got = O.series_average(f, u)
+    m = 6
+    assert np.abs(got[m:-m, m:-m] - g[m:-m, m:-m]).max() < 1e-12
+
+
+def test_average_half_pixel_and_clamp():
+    """One frame, u = (0.5, 0): the mean of each pixel and its right neighbour (the last
+    column is clamped onto itself); u = (0, 0.25): a quarter of the way to the row below;
+    u = (-10, 0): the first column."""
+    rng = np.random.default_rng(33)
+    f = rng.uniform(0, 1, size=(1, 9, 11))
+    u = np.zeros((1, 2, 9, 11))
+    u[0, 0] = 0.5
+    got = O.series_average(f, u)
+    assert np.allclose(got[:, :-1], 0.5 * (f[0, :, :-1] + f[0, :, 1:]), atol=1e-14)
+    assert np.allclose(got[:, -1], f[0, :, -1], atol=1e-14)
+    u[0, 0], u[0, 1] = 0.0, 0.25
+    got = O.series_average(f, u)
+    assert np.allclose(got[:-1], 0.75 * f[0, :-1] + 0.25 * f[0, 1:], atol=1e-14)
+    u[0, 0], u[0, 1] = -10.0, 0.0
+    got = O.series_average(f, u)
+    assert np.allclose(got[:, :11 - 1], f[0, :, :1], atol=1e-14)
+    sel = O.series_average(f, u, pixels=(np.array([0, 8]), np.array([10, 3])))
+    assert np.allclose(sel, got[[0, 8], [10, 3]], atol=1e-14)
