@@ -127,6 +127,19 @@ pprs_status pprs_register_pairs(pprs_ctx* ctx, const float* frames, int N, int H
                                 const int* ref, const int* tmpl, int P, float* u_out,
                                 const pprs_params* params, pprs_pair_stats* stats);
 
+/* Rigid variant of pprs_register_pairs (definition "Rigid transformation"): phi(x) =
+   R(alpha) x + t with R(alpha) the rotation by alpha about the pixel origin (row 0, column 0)
+   and t in pixels, found by the same multilevel gradient flow on the three parameters:
+   energy -NCC (no regulariser), steepest descent in (alpha, t) with the Armijo ladder and the
+   stopping rules of the displacement-field flow, the parameters carried from level to level.
+   f_ref[k] is approximated by f_tmpl[k] o phi_k. p_init (host, 3 per pair: alpha, t0, t1;
+   NULL = identity) and p_out (host, 3 per pair) use radians and pixels; frames, ref, tmpl and
+   stats as for pprs_register_pairs. */
+pprs_status pprs_register_pairs_rigid(pprs_ctx* ctx, const float* frames, int N, int H, int W,
+                                      const int* ref, const int* tmpl, int P,
+                                      const double* p_init, double* p_out,
+                                      const pprs_params* params, pprs_pair_stats* stats);
+
 /* Composition of deformations (section "Registration for series of images"):
    (phi_jk o phi_ij)(x) = phi_jk(phi_ij(x)), i.e. u_ik(x) = u_ij(x) + u_jk(x + u_ij(x)) with
    u_jk interpolated bilinearly and clamped to the domain. All [2][H][W]; u_ik may alias u_ij

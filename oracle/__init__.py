@@ -66,6 +66,7 @@ def _load():
             "or_register_from": (ctypes.c_int, [D, D, ctypes.c_int, ctypes.c_int, D, P, D, S, D,
                                                 ctypes.c_int, I]),
             "or_compose": (None, [D, D, ctypes.c_int, D]),
+            "or_register_rigid": (ctypes.c_int, [D, D, ctypes.c_int, D, P, D, S]),
             "or_series": (ctypes.c_int, [D, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, D, S,
                                          S, I, ctypes.c_int]),
             "or_set_u_storage_f32": (None, [ctypes.c_int]),
@@ -268,6 +269,24 @@ def register_from(R, T, start: int, u_start, params: Params, trace_cap: int = 0)
     if rc != 0:
         raise ValueError("invalid sizes, levels or start level")
     return u, _stats(st, params.levels), tr[: tl.value]
+
+
+def register_rigid(R, T, params: Params, p_init=None):
+    """Rigid variant of A on finest-level nodal frames: phi(x) = R(alpha) x + t about the domain
+    origin. Returns (p = [alpha, t0, t1] in radians and domain units, RegStats)."""
+    R, T = _f64(R), _f64(T)
+    n = R.shape[-1]
+    out = np.zeros(3)
+    st = _CStats()
+    cp = params.c()
+    pin = _f64(np.asarray(p_init, dtype=np.float64)) if p_init is not None else None
+    rc = _load().or_register_rigid(_d(R), _d(T), n, _d(pin) if pin is not None else None,
+                                   ctypes.byref(cp), _d(out), ctypes.byref(st))
+    if rc == -1:
+        raise ValueError("constant reference on some level")
+    if rc != 0:
+        raise ValueError("invalid sizes or levels")
+    return out, _stats(st, params.levels)
 
 
 def set_u_storage_f32(on: bool) -> None:

@@ -689,6 +689,142 @@ int or_register_from(const double* R, const double* T, int nf, int start,
 }
 
 /* ----------------------------------------------------------------------------------------- */
+/* Rigid variant (definition of a rigid transformation): phi(x) = R(alpha) x + t, parameters  */
+/* p = (alpha, t0, t1) in domain units, rotation about the domain origin as printed. Its     */
+/* nodal displacement u_p(x_i) = phi(x_i) - x_i is affine, which bilinear interpolation       */
+/* reproduces exactly, so the energy is the field energy of u_p with lambda = 0 (-NCC: a rigid */
+/* motion has no regulariser) and the parameter gradient is the chain rule through the nodes: */
+/* dE/dp_k = sum_i G_i . psi_k(x_i), G the nodal gradient at lambda = 0, psi_alpha =          */
+/* R'(alpha) x, psi_t0 = (1, 0), psi_t1 = (0, 1). Steepest descent in p (Euclidean metric)    */
+/* with the Armijo ladder, tau_max from the largest nodal |d| of the direction's field, and   */
+/* the stopping rules of the field flow; the multilevel loop carries p from level to level.   */
+
+static void rigid_field(int n, const double p[3], double* u) {
+  size_t nn = (size_t)n * n;
+  double h = 1.0 / (n - 1), c = cos(p[0]), s = sin(p[0]);
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      double x = b * h, y = a * h;
+      size_t i = (size_t)a * n + b;
+      u[i] = c * x - s * y + p[1] - x;
+      u[nn + i] = s * x + c * y + p[2] - y;
+    }
+}
+
+static int rigid_flow(const level_data* L, double p[3], const or_params* pr, int* passes_out,
+                      int* flags, double* e_out, double* ncc_out) {
+  int n = L->n;
+  size_t nn = (size_t)n * n;
+  double h = 1.0 / (n - 1);
+  double* u = malloc(sizeof(double) * 2 * nn);
+  double* G = malloc(sizeof(double) * 2 * nn);
+  int K = pr->ladder_k;
+  rigid_field(n, p, u);
+  double ncc;
+  double E = energy_level(L, u, 0.0, &ncc);
+  double tau_prev = INFINITY;
+  int steps = 0, passes_total = 0;
+  if (!isfinite(E)) *flags |= OR_FLAG_NAN;
+  while (isfinite(E) && steps < pr->iter_max) {
+    gradient_level(L, u, 0.0, G);
+    double c = cos(p[0]), s = sin(p[0]);
+    double g[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) {
+        double x = b * h, y = a * h;
+        size_t i = (size_t)a * n + b;
+        g[0] += G[i] * (-s * x - c * y) + G[nn + i] * (c * x - s * y);
+        g[1] += G[i];
+        g[2] += G[nn + i];
+      }
+    double d[3] = {g[0], g[1], g[2]};
+    double gtd = d[0] * g[0] + d[1] * g[1] + d[2] * g[2];
+    double dmax = 0.0;
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) {
+        double x = b * h, y = a * h;
+        dmax = fmax(dmax, fabs(d[0] * (-s * x - c * y) + d[1]));
+        dmax = fmax(dmax, fabs(d[0] * (c * x - s * y) + d[2]));
+      }
+    if (!(gtd > 0.0) || !(dmax > 0.0)) break;
+    double tau_max = pr->cap * h / dmax;
+    double top = fmin(ldexp(tau_prev, K), tau_max);
+    double tau_acc = 0.0, e_acc = E, ncc_acc = ncc;
+    double pt[3];
+    while (top >= pr->tau_min_rel * tau_max) {
+      passes_total++;
+      for (int j = 0; j <= 2 * K; ++j) {
+        double tau = ldexp(top, -j);
+        for (int k = 0; k < 3; ++k) pt[k] = p[k] - tau * d[k];
+        rigid_field(n, pt, u);
+        double nc;
+        double e = energy_level(L, u, 0.0, &nc);
+        if (e <= E - pr->sigma * tau * gtd) {
+          tau_acc = tau;
+          e_acc = e;
+          ncc_acc = nc;
+          break;
+        }
+      }
+      if (tau_acc > 0.0) break;
+      top = ldexp(top, -(2 * K + 1));
+    }
+    if (tau_acc == 0.0) break;
+    for (int k = 0; k < 3; ++k) p[k] -= tau_acc * d[k];
+    rigid_field(n, p, u);
+    double dec = E - e_acc;
+    E = e_acc;
+    ncc = ncc_acc;
+    tau_prev = tau_acc;
+    steps++;
+    if (dec < pr->eps) break;
+    if (steps >= pr->iter_max) *flags |= OR_FLAG_NONCONV;
+  }
+  if (passes_out) *passes_out = passes_total;
+  if (e_out) *e_out = E;
+  if (ncc_out) *ncc_out = ncc;
+  free(u);
+  free(G);
+  return steps;
+}
+
+/* Rigid registration of T to R (nodal frames of side nf) from p_init (NULL: identity) over the
+   multilevel pyramid; p_out receives the parameters (domain units). Returns 0, -1 for a constant
+   reference, -2 for bad sizes. */
+int or_register_rigid(const double* R, const double* T, int nf, const double* p_init,
+                      const or_params* pr, double* p_out, or_stats* st) {
+  int L = log2_exact(nf - 1);
+  if (L < 1 || pr->levels < 1 || pr->levels > L || pr->levels > OR_MAX_LEVELS) return -2;
+  int m0 = L - pr->levels + 1;
+  pyramid_t py;
+  int rc = pyramid_build(&py, R, T, L, m0);
+  if (rc == 0) {
+    double p[3] = {0.0, 0.0, 0.0};
+    if (p_init) memcpy(p, p_init, sizeof p);
+    if (st) memset(st, 0, sizeof(*st));
+    int flags = 0;
+    double e = 0.0, ncc = 0.0;
+    for (int l = m0; l <= L; ++l) {
+      level_data LD = {(1 << l) + 1, py.Rn[l], py.Tl[l]};
+      int passes = 0;
+      int steps = rigid_flow(&LD, p, pr, &passes, &flags, &e, &ncc);
+      if (st) {
+        st->iters[l - m0] = steps;
+        st->trials[l - m0] = passes;
+      }
+    }
+    memcpy(p_out, p, sizeof p);
+    if (st) {
+      st->energy = e;
+      st->ncc = ncc;
+      st->flags = flags;
+    }
+  }
+  pyramid_free(&py);
+  return rc;
+}
+
+/* ----------------------------------------------------------------------------------------- */
 /* Composition (Registration for series of images): (phi_jk o phi_ij)(x) = phi_jk(phi_ij(x)),  */
 /* i.e. w(x) = u_ij(x) + u_jk(x + u_ij(x)), bilinear and clamped. out may alias u_ij.          */
 

@@ -6,7 +6,7 @@ load the library; the first call does, and fails loudly if it has not been built
 """
 from .api import (Params, PairStats, SeriesStats, compose_deformations, default_params,
                   kernel_names, kernel_timing, prefix_register_series, register_pair,
-                  register_pairs, register_series_batch, PprsError,
+                  register_pairs, register_pairs_rigid, register_series_batch, PprsError,
                   scan_plan, series_average, set_kernel_timing, set_pool, get_tuning, set_tuning,
                   set_metric_solve,
                   Context, WarmStartNet, pair_inputs,
@@ -14,7 +14,7 @@ from .api import (Params, PairStats, SeriesStats, compose_deformations, default_
 
 __all__ = ["Params", "PairStats", "SeriesStats", "compose_deformations", "default_params",
            "kernel_names", "kernel_timing", "prefix_register_series", "register_pair",
-           "register_pairs", "register_series_batch", "PprsError",
+           "register_pairs", "register_pairs_rigid", "register_series_batch", "PprsError",
            "scan_plan", "series_average", "set_kernel_timing", "set_pool", "get_tuning", "set_tuning",
            "set_metric_solve", "Context", "WarmStartNet", "pair_inputs",
            "level7_targets", "set_warm_start"]

@@ -126,6 +126,7 @@ def _lib():
                                             ctypes.POINTER(_CPairStats)]),
                 "pprs_compose_deformations": (i, [vp, vp, vp, vp, i, i]),
                 "pprs_series_average": (i, [vp, vp, vp, i, i, i, vp]),
+                "pprs_register_pairs_rigid": (i, [vp, vp, i, i, i, vp, vp, i, vp, vp, vp, vp]),
                 "pprs_prefix_register_series": (i, [vp, vp, i, i, i, vp,
                                                     ctypes.POINTER(_CParams),
                                                     ctypes.POINTER(_CSeriesStats),
@@ -285,6 +286,30 @@ def compose_deformations(u_ij, u_jk, out=None):
     _check(_lib().pprs_compose_deformations(c.handle, _dev_f32(u_ij, "u_ij"),
                                             _dev_f32(u_jk, "u_jk"), _dev_f32(out, "out"), H, W))
     return out
+
+
+def register_pairs_rigid(frames, ref, tmpl, params: Params | None = None, p_init=None):
+    """Rigid variant: pairs (ref[k], tmpl[k]) of frames [N, H, W]; phi_k(x) = R(alpha) x + t
+    about pixel (0, 0). Returns (p [P, 3] float64: alpha (rad), t0, t1 (px), stats list)."""
+    import numpy as np
+    params = params or Params()
+    N, H, W = frames.shape
+    ref = np.ascontiguousarray(ref, dtype=np.int32)
+    tmpl = np.ascontiguousarray(tmpl, dtype=np.int32)
+    if ref.ndim != 1 or ref.shape != tmpl.shape:
+        raise ValueError("ref and tmpl must be 1-D index arrays of one length")
+    P = ref.shape[0]
+    out = np.zeros((max(P, 1), 3))
+    pin = None
+    if p_init is not None:
+        pin = np.ascontiguousarray(p_init, dtype=np.float64).reshape(P, 3)
+    st = (_CPairStats * max(P, 1))()
+    cp = params.c()
+    c = _ctx(frames.device)
+    _check(_lib().pprs_register_pairs_rigid(
+        c.handle, _dev_f32(frames, "frames"), N, H, W, ref.ctypes.data, tmpl.ctypes.data, P,
+        pin.ctypes.data if pin is not None else None, out.ctypes.data, ctypes.byref(cp), st))
+    return out[:P], [_pair_stats(st[k], params.levels) for k in range(P)]
 
 
 def series_average(frames, u, out=None):

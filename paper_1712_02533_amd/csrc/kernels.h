@@ -53,6 +53,11 @@ hipError_t pool_finish(BatchDesc* d, int L, const int* slots, const long long* o
                        float* vbuf, hipStream_t st);
 hipError_t from_nodes_idx(const float* vbuf, const long long* offs, int n, float* dst, int H,
                           long long d_plane, int elems, float scale, hipStream_t st);
+// rigid variant: energy passes (mode 0 start, 1 line search with nc steps), gradient, its
+// per-slot finaliser (the energy finalisers are energy_fin's)
+hipError_t rigid_energy(BatchDesc* d, int mode, int nc, int grid, hipStream_t st);
+hipError_t rigid_grad(BatchDesc* d, int grid, hipStream_t st);
+hipError_t rigid_grad_fin(BatchDesc* d, int grid, hipStream_t st);
 // avg[H][W] = mean over i of frames[i] sampled at x + u[i](x) (pixels, clamped, bilinear)
 hipError_t series_average(const float* frames, const float* u, int N, int H, int W, float* out,
                           hipStream_t st);

@@ -120,6 +120,10 @@ __device__ __forceinline__ void load_head(SlotState& dst, const SlotState& src) 
   dst.coarsest = src.coarsest; dst.rung = src.rung; dst.E = src.E; dst.ncc = src.ncc; dst.mean = src.mean;
   dst.sigma = src.sigma; dst.tau_prev = src.tau_prev; dst.top = src.top;
   dst.tau_max = src.tau_max; dst.tau_pend = src.tau_pend; dst.gtd = src.gtd; dst.dmax = src.dmax;
+  for (int k = 0; k < 3; ++k) {
+    dst.rp[k] = src.rp[k];
+    dst.rd[k] = src.rd[k];
+  }
 }
 __device__ __forceinline__ void store_head(SlotState& dst, const SlotState& src) {
   load_head(dst, src);
@@ -449,7 +453,11 @@ __device__ __forceinline__ void energy_finalize(BatchDesc* D, SlotState* stp, in
       st.ncc = ncc_j[acc_j];
       st.mean = m_j[acc_j];
       st.sigma = sg_j[acc_j];
-      st.tau_pend = tj;
+      if (D->rigid) {
+        for (int k = 0; k < 3; ++k) st.rp[k] -= tj * st.rd[k];  // parameters move at once
+      } else {
+        st.tau_pend = tj;  // applied to u by the next gradient pass
+      }
       st.tau_prev = tj;
       st.iter++;
       stp->iters[li] = st.iter;
@@ -1599,6 +1607,268 @@ __global__ void __launch_bounds__(BLOCK) k_from_nodes_idx(const float* vbuf,
 }
 
 // ------------------------------------------------------------------------------------------
+// Rigid variant (definition of a rigid transformation): phi(x) = R(alpha) x + t with the three
+// parameters in SlotState::rp, rotation about the domain origin as printed. A quadrature point
+// q (in cells) maps to R(alpha) q + t / h. No field is stored: the energy passes and the
+// gradient pass are reductions over the level's elements (same tiles as k_energy). The energy
+// is -NCC (no regulariser); the parameter gradient is
+//   dE/dp_k = sum_q f_q grad T(phi(q)) . dphi/dp_k(q),   dphi/dalpha = R'(alpha) q, dphi/dt = I,
+// f_q as in the gradient kernel; steepest descent in the parameters.
+
+// The map in cells as a displacement, phi(q) - q = (R - I) q + t / h: positions are formed
+// like the field kernels' (a node plus a small offset), so FP32 keeps them to ~1e-7 cells
+// however far the point is from the rotation centre. Per element the node's offset is taken
+// in FP64, per quadrature point the small (R - I)(xi, eta) is added in FP32.
+struct RigidMap {
+  double cm1, s, ox, oy;  // cos - 1 (as -2 sin^2(a/2)), sin, t / h (cells)
+};
+__device__ __forceinline__ RigidMap rigid_map(double a, double t0, double t1, int n) {
+  RigidMap m;
+  double sh = sin(0.5 * a);
+  m.cm1 = -2.0 * sh * sh;
+  m.s = sin(a);
+  m.ox = t0 * (n - 1);
+  m.oy = t1 * (n - 1);
+  return m;
+}
+// offset (cells) of node (a, b) under the map
+__device__ __forceinline__ void rigid_node_offset(const RigidMap& m, int a, int b, float& dx,
+                                                  float& dy) {
+  dx = (float)(m.cm1 * b - m.s * a + m.ox);
+  dy = (float)(m.s * b + m.cm1 * a + m.oy);
+}
+
+// Energy of the rigid parameters (MODE 0: at rp for slots starting a level; MODE 1: at
+// rp - tau_j rd for the NC steps of a line-search pass). Partials as k_energy's, the three
+// regulariser columns zero.
+template <int MODE, int NC>
+__global__ void __launch_bounds__(BLOCK) k_rigid_energy(BatchDesc* D) {
+  constexpr int NXN = ET_X + 1, NYN = ET_Y + 1, NN = NXN * NYN;
+  constexpr int NV = 3 * NC + 3;
+  __shared__ float s_r[NN];
+  __shared__ double s_red[(BLOCK / 64) * NV];
+  __shared__ int s_pos;
+  const int kind = MODE ? WK_LADDER : WK_EVAL;
+  ItemCursor c;
+  if (!cursor_begin(D, kind, c, &s_pos)) return;
+  for (; c.item < c.end; ++c.item) {
+    int s, t;
+    cursor_slot(D, kind, c, s, t);
+    const SlotState* stp = D->state + s;
+    int ph = stp->phase;
+    if (MODE == 0 && !(ph == PH_INIT || ph == PH_PROLONG)) continue;
+    if (MODE == 1 && ph != PH_LADDER) continue;
+    int l = (ph == PH_PROLONG) ? stp->level + 1 : stp->level;
+    int n = lvl_n(l);
+    const float* R = D->pyr + D->frame_off[(size_t)stp->ref * PPRS_MAXL + l];
+    const float* T = D->pyr + D->frame_off[(size_t)stp->tmpl * PPRS_MAXL + l];
+    double top = MODE ? stp->top : 0.0;
+    RigidMap mp[NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      double tj = MODE ? ldexp(top, -j) : 0.0;
+      mp[j] = rigid_map(stp->rp[0] - tj * stp->rd[0], stp->rp[1] - tj * stp->rd[1],
+                        stp->rp[2] - tj * stp->rd[2], n);
+    }
+    float inv_h = (float)(n - 1);
+    int ntx = (n - 1 + ET_X - 1) / ET_X;
+    int e0x = (t % ntx) * ET_X, e0y = (t / ntx) * ET_Y;
+    __syncthreads();
+    {
+      constexpr int SIT = (NN + BLOCK - 1) / BLOCK;
+      float vr[SIT];
+#pragma unroll
+      for (int it = 0; it < SIT; ++it) {
+        int k = threadIdx.x + it * BLOCK;
+        int a = e0y + k / NXN, b = e0x + k % NXN;
+        vr[it] = gld(R, (k < NN && a < n && b < n) ? (size_t)a * n + b : 0);
+      }
+#pragma unroll
+      for (int it = 0; it < SIT; ++it) {
+        int k = threadIdx.x + it * BLOCK;
+        int a = e0y + k / NXN, b = e0x + k % NXN;
+        if (k < NN) s_r[k] = (a < n && b < n) ? vr[it] : 0.f;
+      }
+    }
+    __syncthreads();
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    float w = 0.25f / ((float)(n - 1) * (float)(n - 1));
+    for (int e = threadIdx.x; e < ET_X * ET_Y; e += BLOCK) {
+      int ey = e / ET_X, ex = e % ET_X;
+      int a = e0y + ey, b = e0x + ex;
+      if (a >= n - 1 || b >= n - 1) continue;
+      int k00 = ey * NXN + ex;
+      float rr[4] = {s_r[k00], s_r[k00 + 1], s_r[k00 + NXN], s_r[k00 + NXN + 1]};
+      float ndx[NC], ndy[NC];
+#pragma unroll
+      for (int j = 0; j < NC; ++j) rigid_node_offset(mp[j], a, b, ndx[j], ndy[j]);
+      float es[3 * NC];
+#pragma unroll
+      for (int k = 0; k < 3 * NC; ++k) es[k] = 0.f;
+#pragma unroll 1
+      for (int p = 0; p < 2; ++p) {
+#pragma unroll 1
+        for (int q = 0; q < 2; ++q) {
+          float xi = c_gp[q], eta = c_gp[p];
+          float p0 = (1.f - xi) * (1.f - eta), p1 = xi * (1.f - eta), p2 = (1.f - xi) * eta, p3 = xi * eta;
+          float rq = p0 * rr[0] + p1 * rr[1] + p2 * rr[2] + p3 * rr[3];
+#pragma unroll
+          for (int j = 0; j < NC; ++j) {
+            float cm1 = (float)mp[j].cm1, sn = (float)mp[j].s;
+            float tx = xi + (ndx[j] + fmaf(cm1, xi, -sn * eta));
+            float ty = eta + (ndy[j] + fmaf(sn, xi, cm1 * eta));
+            float tv = sample_bil<false>(T, n, b, tx, a, ty, inv_h, nullptr, nullptr);
+            es[3 * j + 0] += tv;
+            es[3 * j + 1] += tv * tv;
+            es[3 * j + 2] += tv * rq;
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 3 * NC; ++k) acc[k] += (double)(w * es[k]);
+    }
+    block_sum<NV>(acc, s_red);
+    if (threadIdx.x == 0) {
+      double* pr = slot_partial(D, s, kind, t);
+      for (int k = 0; k < NV; ++k) pr[k] = acc[k];
+    }
+  }
+}
+
+// Parameter gradient of the slots in GRAD: three FP64 partials per element tile.
+__global__ void __launch_bounds__(BLOCK) k_rigid_grad(BatchDesc* D) {
+  constexpr int NXN = ET_X + 1, NYN = ET_Y + 1, NN = NXN * NYN;
+  __shared__ float s_r[NN];
+  __shared__ double s_red[(BLOCK / 64) * 3];
+  __shared__ int s_pos;
+  ItemCursor c;
+  if (!cursor_begin(D, WK_GRAD, c, &s_pos)) return;
+  for (; c.item < c.end; ++c.item) {
+    int s, t;
+    cursor_slot(D, WK_GRAD, c, s, t);
+    const SlotState* stp = D->state + s;
+    if (stp->phase != PH_GRAD) continue;
+    int l = stp->level;
+    int n = lvl_n(l);
+    const float* R = D->pyr + D->frame_off[(size_t)stp->ref * PPRS_MAXL + l];
+    const float* T = D->pyr + D->frame_off[(size_t)stp->tmpl * PPRS_MAXL + l];
+    RigidMap mp = rigid_map(stp->rp[0], stp->rp[1], stp->rp[2], n);
+    const float cm1 = (float)mp.cm1, sn = (float)mp.s, cs = (float)cos(stp->rp[0]);
+    double sg = stp->sigma;
+    float inv_sig = sg > 0.0 ? (float)(1.0 / sg) : 0.f;
+    float ncc = (float)stp->ncc, mean = (float)stp->mean;
+    float inv_h = (float)(n - 1), h = 1.f / inv_h;
+    float w = 0.25f / ((float)(n - 1) * (float)(n - 1));
+    int ntx = (n - 1 + ET_X - 1) / ET_X;
+    int e0x = (t % ntx) * ET_X, e0y = (t / ntx) * ET_Y;
+    __syncthreads();
+    {
+      constexpr int SIT = (NN + BLOCK - 1) / BLOCK;
+      float vr[SIT];
+#pragma unroll
+      for (int it = 0; it < SIT; ++it) {
+        int k = threadIdx.x + it * BLOCK;
+        int a = e0y + k / NXN, b = e0x + k % NXN;
+        vr[it] = gld(R, (k < NN && a < n && b < n) ? (size_t)a * n + b : 0);
+      }
+#pragma unroll
+      for (int it = 0; it < SIT; ++it) {
+        int k = threadIdx.x + it * BLOCK;
+        int a = e0y + k / NXN, b = e0x + k % NXN;
+        if (k < NN) s_r[k] = (a < n && b < n) ? vr[it] : 0.f;
+      }
+    }
+    __syncthreads();
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int e = threadIdx.x; e < ET_X * ET_Y; e += BLOCK) {
+      int ey = e / ET_X, ex = e % ET_X;
+      int a = e0y + ey, b = e0x + ex;
+      if (a >= n - 1 || b >= n - 1) continue;
+      int k00 = ey * NXN + ex;
+      float rr[4] = {s_r[k00], s_r[k00 + 1], s_r[k00 + NXN], s_r[k00 + NXN + 1]};
+      float ndx, ndy;
+      rigid_node_offset(mp, a, b, ndx, ndy);
+      float ga = 0.f, g0 = 0.f, g1 = 0.f;
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          float xi = c_gp[q], eta = c_gp[p];
+          float p0 = (1.f - xi) * (1.f - eta), p1 = xi * (1.f - eta), p2 = (1.f - xi) * eta, p3 = xi * eta;
+          float rq = p0 * rr[0] + p1 * rr[1] + p2 * rr[2] + p3 * rr[3];
+          float tx = xi + (ndx + fmaf(cm1, xi, -sn * eta));
+          float ty = eta + (ndy + fmaf(sn, xi, cm1 * eta));
+          float gx, gy;
+          float tv = sample_bil<true>(T, n, b, tx, a, ty, inv_h, &gx, &gy);
+          float f = -w * (rq - ncc * (tv - mean) * inv_sig) * inv_sig;
+          // dphi/dalpha = R'(alpha) q in domain units
+          float qxd = ((float)b + xi) * h, qyd = ((float)a + eta) * h;
+          float dax = -sn * qxd - cs * qyd, day = cs * qxd - sn * qyd;
+          ga += f * (gx * dax + gy * day);
+          g0 += f * gx;
+          g1 += f * gy;
+        }
+      }
+      acc[0] += (double)ga;
+      acc[1] += (double)g0;
+      acc[2] += (double)g1;
+    }
+    block_sum<3>(acc, s_red);
+    if (threadIdx.x == 0) {
+      double* pr = slot_partial(D, s, WK_GRAD, t);
+      for (int k = 0; k < 3; ++k) pr[k] = acc[k];
+    }
+  }
+}
+
+// Per slot after the gradient pass: steepest-descent direction rd = grad, G.d = |grad|^2,
+// max |d| over the level's nodes of the direction's displacement field (affine: its extreme
+// at a corner of the domain), then the line-search start as for the fields.
+__global__ void __launch_bounds__(BLOCK) k_rigid_grad_fin(BatchDesc* D) {
+  __shared__ double s_red[(BLOCK / 64) * 3];
+  const WorkList wl = D->lists[WK_GRAD];
+  for (int pos = blockIdx.x; pos < wl.n_slots; pos += gridDim.x) {
+    int s = D->list_slots[(size_t)WK_GRAD * D->max_slots + pos];
+    SlotState* stp = D->state + s;
+    if (stp->phase != PH_GRAD) continue;
+    int l = stp->level;
+    int n = lvl_n(l);
+    double tot[3];
+    sum_partials<3>(D, s, WK_GRAD, D->geom[l].tiles_elem, tot, s_red, false);
+    if (threadIdx.x == 0) {
+      SlotState st;
+      load_head(st, *stp);
+      D->node_count[(size_t)s * WK_COUNT + WK_GRAD] += (long long)n * n;
+      double ca = cos(st.rp[0]), sa = sin(st.rp[0]);
+      double dm = 0.0;
+      for (int k = 0; k < 3; ++k) st.rd[k] = tot[k];
+      for (int cy = 0; cy < 2; ++cy)
+        for (int cx = 0; cx < 2; ++cx) {
+          double dx = st.rd[0] * (-sa * cx - ca * cy) + st.rd[1];
+          double dy = st.rd[0] * (ca * cx - sa * cy) + st.rd[2];
+          dm = fmax(dm, fmax(fabs(dx), fabs(dy)));
+        }
+      st.gtd = tot[0] * tot[0] + tot[1] * tot[1] + tot[2] * tot[2];
+      st.dmax = dm;
+      if (!(st.gtd > 0.0) || !(st.dmax > 0.0)) {
+        level_done(st);
+      } else {
+        double hh = 1.0 / (n - 1);
+        st.tau_max = D->step_cap * hh / st.dmax;
+        st.top = fmin(ldexp(st.tau_prev, D->ladder_k), st.tau_max);
+        st.rung = 0;
+        if (st.top < D->tau_min_rel * st.tau_max) level_done(st);
+        else st.phase = PH_LADDER;
+      }
+      store_head(*stp, st);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // Series averaging: avg(x) = 1/N sum_i f_i(x + u_i(x)) over the aligned frames f_i o phi_{0,i}
 // (pixel grid, bilinear, clamped to [0, W-1] x [0, H-1]). One pixel per lane; the frames are
 // taken four at a time so a lane has 8 displacement loads and 16 frame loads in flight; the sum
@@ -1843,6 +2113,30 @@ hipError_t from_nodes_idx(const float* vbuf, const long long* offs, int n, float
                           long long d_plane, int elems, float scale, hipStream_t st) {
   hipLaunchKernelGGL(k_from_nodes_idx, dim3(grid_for((long long)elems * 2 * H * H)), dim3(BLOCK),
                      0, st, vbuf, offs, n, dst, H, d_plane, elems, scale);
+  return hipGetLastError();
+}
+
+hipError_t rigid_energy(BatchDesc* d, int mode, int nc, int grid, hipStream_t st) {
+  if (mode == 0) {
+    hipLaunchKernelGGL((k_rigid_energy<0, 1>), dim3(grid), dim3(BLOCK), 0, st, d);
+  } else {
+    switch (nc) {
+      case 1: hipLaunchKernelGGL((k_rigid_energy<1, 1>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+      case 2: hipLaunchKernelGGL((k_rigid_energy<1, 2>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+      case 3: hipLaunchKernelGGL((k_rigid_energy<1, 3>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+      case 5: hipLaunchKernelGGL((k_rigid_energy<1, 5>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+      case 7: hipLaunchKernelGGL((k_rigid_energy<1, 7>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
+}
+hipError_t rigid_grad(BatchDesc* d, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_rigid_grad, dim3(grid), dim3(BLOCK), 0, st, d);
+  return hipGetLastError();
+}
+hipError_t rigid_grad_fin(BatchDesc* d, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_rigid_grad_fin, dim3(grid), dim3(BLOCK), 0, st, d);
   return hipGetLastError();
 }
 

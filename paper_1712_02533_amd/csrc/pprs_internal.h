@@ -62,6 +62,8 @@ struct SlotState {
   double tau_pend;  // accepted step not yet applied to u[ub]
   double gtd;
   double dmax;
+  double rp[3];  // rigid variant: alpha, t0, t1 (domain units) of phi(x) = R(alpha) x + t
+  double rd[3];  // rigid variant: search direction in the parameters
   int iters[PPRS_MAXL];
   int passes[PPRS_MAXL];
 };
@@ -104,6 +106,7 @@ struct BatchDesc {
   double eps;
   int iter_max;
   int smooth_halo;         // windowed metric solve halo in nodes; 0: exact two-pass line solves
+  int rigid;               // 1: the slots run the rigid variant (parameters rp, no fields)
   LevelGeom geom[PPRS_MAXL];
   // frames: normalised pyramids; frame f at level l starts at pyr + frame_off[f][l]
   float* pyr;

@@ -496,6 +496,19 @@ pprs_status launch_step(pprs_ctx* c, BatchDesc* d, int nc) {
 
 enum InitKind { INIT_IDENTITY = 0, INIT_COMPOSE = 1, INIT_GIVEN = 2, INIT_PREPARED = 3 };
 
+// One step of the rigid variant: start energies of slots that begin a level, the parameter
+// gradient with its finaliser, one line-search pass (the energy finalisers are shared).
+pprs_status launch_step_rigid(pprs_ctx* c, BatchDesc* d, int nc) {
+  TIMED(TK_PLAN, pprs_k::plan(d, c->stream));
+  TIMED(TK_EVAL, pprs_k::rigid_energy(d, 0, 1, c->grid_energy, c->stream));
+  TIMED(TK_FIN, pprs_k::energy_fin(d, 0, 1, kGridFin, c->stream));
+  TIMED(TK_GRAD, pprs_k::rigid_grad(d, c->grid_grad, c->stream));
+  TIMED(TK_FIN, pprs_k::rigid_grad_fin(d, kGridFin, c->stream));
+  TIMED(TK_LADDER, pprs_k::rigid_energy(d, 1, nc, c->grid_energy, c->stream));
+  TIMED(TK_FIN, pprs_k::energy_fin(d, 1, nc, kGridFin, c->stream));
+  return PPRS_OK;
+}
+
 // Runs n slots (reference ref[s], template tmpl[s]) to completion and writes each result
 // (domain units, [2][nL][nL]) to elems[out_idx[s]]. INIT_COMPOSE composes elems[left[s]]
 // and elems[right[s]]; INIT_GIVEN takes the finest-level guess already in slot 0's buffer.
@@ -511,6 +524,7 @@ pprs_status run_batch(pprs_ctx* c, int n, const int* ref, const int* tmpl, InitK
   int nL = level_n(L);
   hd.n_slots = n;
   hd.ladder_k = p->ladder_k;
+  hd.rigid = 0;
   hd.lambda = p->lambda;
   hd.sigma = p->armijo_sigma;
   hd.step_cap = p->step_cap;
@@ -743,6 +757,7 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
   S = std::max(1, std::min(S, std::min(n_ops, hd.max_slots)));
   hd.n_slots = S;
   hd.ladder_k = p->ladder_k;
+  hd.rigid = 0;
   hd.lambda = p->lambda;
   hd.sigma = p->armijo_sigma;
   hd.step_cap = p->step_cap;
@@ -1150,6 +1165,127 @@ pprs_status pprs_register_pairs(pprs_ctx* c, const float* frames, int N, int H, 
                               (long long)plane, 2 * np, (float)(nL - 1), c->stream));
   }
   HIPCHK(hipStreamSynchronize(c->stream));
+  return status_from_flags(flags);
+}
+
+// Rigid variant of run_batch: n slots with parameters p0 (domain units, 3 per slot; NULL =
+// identity) to completion; their parameters into p_out (host, 3 per slot).
+pprs_status run_batch_rigid(pprs_ctx* c, int n, const int* ref, const int* tmpl,
+                            const double* p0, double* p_out, const pprs_params* p,
+                            pprs_pair_stats* stats, int* flags_or) {
+  if (n <= 0) return PPRS_OK;
+  BatchDesc& hd = c->hd;
+  int L = hd.finest, m0 = hd.coarsest;
+  hd.n_slots = n;
+  hd.ladder_k = p->ladder_k;
+  hd.rigid = 1;
+  hd.lambda = 0.0;
+  hd.sigma = p->armijo_sigma;
+  hd.step_cap = p->step_cap;
+  hd.tau_min_rel = p->tau_min_rel;
+  hd.eps = p->eps;
+  hd.iter_max = p->iter_max;
+  STCHK(set_grad_tiles(c));
+  // the rigid gradient pass works on the element tiles of the energy passes
+  for (int l = m0; l <= L; ++l) hd.geom[l].tiles_grad = hd.geom[l].tiles_elem;
+  BatchDesc* d = P<BatchDesc>(c->desc);
+  HIPCHK(hipMemcpyAsync(d, &hd, sizeof(BatchDesc), hipMemcpyHostToDevice, c->stream));
+  std::vector<SlotState> st(n);
+  for (int s = 0; s < n; ++s) {
+    memset(&st[s], 0, sizeof(SlotState));
+    st[s].phase = PH_INIT;
+    st[s].level = m0;
+    st[s].ref = ref[s];
+    st[s].tmpl = tmpl[s];
+    st[s].finest = L;
+    st[s].coarsest = m0;
+    st[s].tau_prev = INFINITY;
+    for (int k = 0; k < 3; ++k) st[s].rp[k] = p0 ? p0[3 * s + k] : 0.0;
+  }
+  HIPCHK(hipMemcpyAsync(hd.state, st.data(), sizeof(SlotState) * n, hipMemcpyHostToDevice,
+                        c->stream));
+  HIPCHK(hipMemsetAsync(hd.node_count, 0, sizeof(long long) * WK_COUNT * n, c->stream));
+  int K = p->ladder_k, nc = ladder_rungs(c, K);
+  long long max_steps = (long long)p->levels * ((long long)p->iter_max + 2) *
+                            (ladder_pass_bound(p, nc) + 2) + 64;
+  long long done_steps = 0;
+  int group = 4;
+  while (true) {
+    for (int k = 0; k < group; ++k) STCHK(launch_step_rigid(c, d, nc));
+    done_steps += group;
+    int active = 0;
+    HIPCHK(hipMemcpyAsync(&active, &d->active, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->timing) STCHK(tk_collect(c));
+    if (active == 0) break;
+    if (done_steps > max_steps) {
+      hd.rigid = 0;
+      return fail(PPRS_ESTATE, "rigid batch did not finish within %lld steps", max_steps);
+    }
+    group = std::min(group * 2, 32);
+  }
+  hd.rigid = 0;
+  HIPCHK(hipMemcpyAsync(st.data(), hd.state, sizeof(SlotState) * n, hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int s = 0; s < n; ++s) {
+    if (flags_or) *flags_or |= st[s].flags;
+    for (int k = 0; k < 3; ++k) p_out[3 * s + k] = st[s].rp[k];
+    if (stats) {
+      pprs_pair_stats& o = stats[s];
+      memset(&o, 0, sizeof o);
+      for (int l = m0; l <= L; ++l) {
+        o.iters[l - m0] = st[s].iters[l - m0];
+        o.passes[l - m0] = st[s].passes[l - m0];
+      }
+      o.energy = st[s].E;
+      o.ncc = st[s].ncc;
+      o.flags = st[s].flags;
+    }
+  }
+  return PPRS_OK;
+}
+
+pprs_status pprs_register_pairs_rigid(pprs_ctx* c, const float* frames, int N, int H, int W,
+                                      const int* ref, const int* tmpl, int P,
+                                      const double* p_init, double* p_out,
+                                      const pprs_params* params, pprs_pair_stats* stats) {
+  STCHK(enter(c));
+  int L = frame_level(H, W);
+  if (L < 0) return fail(PPRS_EINVAL, "frames must be square with side 2^L or 2^L+1, L in [2,10]");
+  if (!frames || !ref || !tmpl || !p_out || N < 1 || P < 0)
+    return fail(PPRS_EINVAL, "bad arguments");
+  STCHK(check_params(params, L));
+  if (P == 0) return PPRS_OK;
+  std::vector<char> is_ref(N, 0);
+  for (int p = 0; p < P; ++p) {
+    if (ref[p] < 0 || ref[p] >= N || tmpl[p] < 0 || tmpl[p] >= N)
+      return fail(PPRS_EINVAL, "pair %d has a frame index out of range", p);
+    is_ref[ref[p]] = 1;
+  }
+  int m0 = L - params->levels + 1;
+  // API units: alpha in radians, t in pixels of the finest level (2^L per domain unit)
+  const double px = (double)(level_n(L) - 1);
+  STCHK(prepare_frames(c, frames, N, H, L, m0, 0, &is_ref));
+  int chunk = std::min(P, kPairChunk);
+  STCHK(ensure_slots(c, chunk, L, m0, params->beta));
+  int flags = 0;
+  std::vector<double> pin(3 * (size_t)chunk), pout(3 * (size_t)chunk);
+  for (int p0 = 0; p0 < P; p0 += chunk) {
+    int np = std::min(chunk, P - p0);
+    for (int k = 0; k < np; ++k) {
+      pin[3 * k] = p_init ? p_init[3 * (p0 + k)] : 0.0;
+      pin[3 * k + 1] = p_init ? p_init[3 * (p0 + k) + 1] / px : 0.0;
+      pin[3 * k + 2] = p_init ? p_init[3 * (p0 + k) + 2] / px : 0.0;
+    }
+    STCHK(run_batch_rigid(c, np, ref + p0, tmpl + p0, pin.data(), pout.data(), params,
+                          stats ? stats + p0 : nullptr, &flags));
+    for (int k = 0; k < np; ++k) {
+      p_out[3 * (p0 + k)] = pout[3 * k];
+      p_out[3 * (p0 + k) + 1] = pout[3 * k + 1] * px;
+      p_out[3 * (p0 + k) + 2] = pout[3 * k + 2] * px;
+    }
+  }
   return status_from_flags(flags);
 }
 

@@ -1,0 +1,111 @@
+"""Rigid variant on the GPU (pprs_register_pairs_rigid) against the FP64 oracle
+(oracle.register_rigid): known rotations and shifts, a full-size pair of the 512 x 512
+workload, batch against single pairs, and a start at the answer.
+
+The comparison runs both to tight convergence (eps = 1e-9: each level ends when the line search
+finds no sufficient decrease above tau_min): with the default eps = 3e-4 a three-parameter
+energy is still sloping where a level stops, so where the two take one Armijo step differently
+near a tie (FP32 against FP64 energies) they stop at visibly different points. Converged, the
+two maps phi(x) = R(alpha) x + t may differ by at most 2e-3 px anywhere on the frame (their
+difference is affine, so its largest value is at a corner)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import CONFIGS, make_series
+from test_oracle_pins import _rotated_pair
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+def say(*a):
+    print("[rigid]", *a, flush=True)
+
+
+def _map_diff(pa, pb, side):
+    """Largest distance (px) between the maps of parameter rows (alpha, t0 px, t1 px)."""
+    worst = 0.0
+    for x in (0.0, side):
+        for y in (0.0, side):
+            xa = np.cos(pa[0]) * x - np.sin(pa[0]) * y + pa[1]
+            ya = np.sin(pa[0]) * x + np.cos(pa[0]) * y + pa[2]
+            xb = np.cos(pb[0]) * x - np.sin(pb[0]) * y + pb[1]
+            yb = np.sin(pb[0]) * x + np.cos(pb[0]) * y + pb[2]
+            worst = max(worst, float(np.hypot(xa - xb, ya - yb)))
+    return worst
+
+
+TIGHT = dict(eps=1e-9, iter_max=400)
+BAR_PX = 2e-3
+
+
+def _oracle_px(f0, f1, levels, side, **kw):
+    p, st = O.register_rigid(O.frame_to_nodes(f0), O.frame_to_nodes(f1),
+                             O.Params(levels=levels, **kw))
+    return np.array([p[0], p[1] * side, p[2] * side]), st
+
+
+@pytest.mark.parametrize("side,alpha,t", [(64, 0.0, (2.5, -1.75)), (64, 0.015, (1.0, 0.5)),
+                                          (128, -0.02, (-2.0, 1.5)), (128, 0.01, (3.0, 2.0))])
+def test_rigid_pair_matches_oracle(side, alpha, t):
+    torch = _torch()
+    import paper_1712_02533_amd as P
+    f0, f1 = _rotated_pair(side, alpha, t, 21)
+    frames = torch.tensor(np.stack([f0, f1]).astype(np.float32), device="cuda")
+    levels = 3
+    say("side %d, alpha %.3f, t %s" % (side, alpha, t))
+    p, st = P.register_pairs_rigid(frames, [0], [1], params=P.Params(levels=levels, **TIGHT))
+    po, sto = _oracle_px(f0.astype(np.float32), f1.astype(np.float32), levels, side, **TIGHT)
+    d = _map_diff(p[0], po, side)
+    say("  gpu", p[0], st[0].iters, " oracle", po, sto.iters, " map diff %.2e px" % d)
+    assert d < BAR_PX
+    # and both recover the map the frames were made with
+    assert _map_diff(p[0], np.array([alpha, t[0], t[1]]), side) < 0.05
+
+
+def test_rigid_full_size_pair_matches_oracle():
+    """Neighbour frames 0 and 1 of the 512-frame workload (drift <= 8 px plus a non-rigid part
+    the rigid map can only approximate), 4 levels."""
+    torch = _torch()
+    import paper_1712_02533_amd as P
+    from dataclasses import replace
+    spec = replace(CONFIGS["c3"]["spec"], n_frames=2)
+    s = make_series(spec)
+    frames = torch.tensor(s.frames, device="cuda")
+    say("512 x 512 pair, 4 levels")
+    p, st = P.register_pairs_rigid(frames, [0], [1], params=P.Params(levels=4, **TIGHT))
+    po, sto = _oracle_px(s.frames[0], s.frames[1], 4, 512, **TIGHT)
+    d = _map_diff(p[0], po, 512)
+    say("  gpu", p[0], st[0].iters, " oracle", po, sto.iters, " map diff %.2e px" % d)
+    assert d < BAR_PX
+
+
+def test_rigid_batch_equals_single_pairs_and_start_at_answer():
+    torch = _torch()
+    import paper_1712_02533_amd as P
+    side = 64
+    cases = [(0.01 * k, (0.5 * k, -0.25 * k)) for k in range(-2, 4)]
+    fr = []
+    for k, (a, t) in enumerate(cases):
+        f0, f1 = _rotated_pair(side, a, t, 30 + k)
+        fr += [f0, f1]
+    frames = torch.tensor(np.stack(fr).astype(np.float32), device="cuda")
+    ref = np.arange(0, 2 * len(cases), 2)
+    params = P.Params(levels=3, **TIGHT)
+    pb, sb = P.register_pairs_rigid(frames, ref, ref + 1, params=params)
+    for k in range(len(cases)):
+        p1, s1 = P.register_pairs_rigid(frames, ref[k:k + 1], ref[k:k + 1] + 1, params=params)
+        assert np.array_equal(p1[0], pb[k]) and s1[0].iters == sb[k].iters
+    # started at its own (converged) answer, a pair stays there
+    pa, sa = P.register_pairs_rigid(frames, ref, ref + 1, params=params, p_init=pb)
+    for k in range(len(cases)):
+        assert _map_diff(pa[k], pb[k], side) < BAR_PX
+        say("  case %d: %d iterations from the answer, %d from the identity"
+            % (k, sum(sa[k].iters), sum(sb[k].iters)))

@@ -590,3 +590,71 @@ def test_average_half_pixel_and_clamp():
     assert np.allclose(got[:, :11 - 1], f[0, :, :1], atol=1e-14)
     sel = O.series_average(f, u, pixels=(np.array([0, 8]), np.array([10, 3])))
     assert np.allclose(sel, got[[0, 8], [10, 3]], atol=1e-14)
+
+
+# ------------------------------------------------------------------------------------------
+# Rigid variant (definition of a rigid transformation): phi(x) = R(alpha) x + t
+
+def _rotated_pair(side, alpha, t_px, seed):
+    """Frame 0 is the blob lattice L; frame 1 is L seen through the rigid map, T(y) =
+    L(R(alpha)^-1 (y - t)), so that T(phi(x)) = L(x) with phi(x) = R(alpha) x + t (pixels,
+    rotation about pixel (0, 0)). Noise-free."""
+    from synth.blobs import _lattice
+    spec = SeriesSpec(2, side, 4.0, 0.0, 0.0, seed)
+    s = make_series(spec)
+    r, c = np.meshgrid(np.arange(side, dtype=np.float64), np.arange(side, dtype=np.float64),
+                       indexing="ij")
+    ca, sa = np.cos(alpha), np.sin(alpha)
+    x, y = c - t_px[0], r - t_px[1]
+    f0 = _lattice(spec, s.origin, s.amps, s.lattice_lo, c, r)
+    f1 = _lattice(spec, s.origin, s.amps, s.lattice_lo, ca * x + sa * y, -sa * x + ca * y)
+    return f0, f1
+
+
+@pytest.mark.parametrize("alpha,t", [(0.0, (2.5, -1.75)), (0.015, (1.0, 0.5)),
+                                     (-0.02, (-2.0, 1.5))])
+def test_rigid_recovers_known_rotation_and_shift(alpha, t):
+    side = 64
+    f0, f1 = _rotated_pair(side, alpha, t, 17)
+    p, st = O.register_rigid(O.frame_to_nodes(f0), O.frame_to_nodes(f1),
+                             O.Params(levels=3, eps=1e-9, iter_max=2000))
+    got_t = p[1:] * side                      # domain units -> pixels
+
+    def phi(a, tt, x, y):
+        return (np.cos(a) * x - np.sin(a) * y + tt[0], np.sin(a) * x + np.cos(a) * y + tt[1])
+
+    # the recovered map against the true one over the frame (its extremes are at the corners)
+    err = max(np.hypot(*(np.subtract(phi(p[0], got_t, x, y), phi(alpha, t, x, y))))
+              for x in (0, side) for y in (0, side))
+    assert err < 0.05
+    # below 1 only through the borders: clamped samples, and the replicated last node row and
+    # column of the 2^L-pixel frames
+    assert st.ncc > 0.97
+
+
+def test_rigid_identical_frames_stay_at_identity():
+    f0, _ = _rotated_pair(32, 0.0, (0.0, 0.0), 18)
+    fr = O.frame_to_nodes(f0)
+    p, st = O.register_rigid(fr, fr, O.Params(levels=2))
+    assert np.abs(p).max() < 1e-9
+    assert sum(st.iters) == 0 or np.abs(p).max() < 1e-9
+
+
+def test_rigid_energy_is_the_field_energy_of_the_affine_displacement():
+    """A rigid start guess evaluated through the rigid path equals the field oracle's energy of
+    the same (affine) displacement at lambda = 0, and the rigid flow from there never raises
+    the energy."""
+    side = 32
+    f0, f1 = _rotated_pair(side, 0.01, (1.0, -0.5), 19)
+    R, T = O.frame_to_nodes(f0), O.frame_to_nodes(f1)
+    n = side + 1
+    p0 = np.array([0.004, 0.5 / side, -0.25 / side])
+    yy, xx = np.meshgrid(np.arange(n) / side, np.arange(n) / side, indexing="ij")
+    ca, sa = np.cos(p0[0]), np.sin(p0[0])
+    u = np.stack([ca * xx - sa * yy + p0[1] - xx, sa * xx + ca * yy + p0[2] - yy])
+    e_field, _ = O.energy(R, T, u, 0.0)
+    p, st = O.register_rigid(R, T, O.Params(levels=1, iter_max=0), p_init=p0)
+    assert np.allclose(p, p0)
+    assert abs(st.energy - e_field) < 1e-12
+    p2, st2 = O.register_rigid(R, T, O.Params(levels=1), p_init=p0)
+    assert st2.energy <= e_field
