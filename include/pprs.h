@@ -140,6 +140,16 @@ pprs_status pprs_register_pairs_rigid(pprs_ctx* ctx, const float* frames, int N,
                                       const double* p_init, double* p_out,
                                       const pprs_params* params, pprs_pair_stats* stats);
 
+/* Rigid series (definition "Image series registration" with the rigid operator): p_out
+   (host, 3 per frame) receives phi_0i as (alpha, t0, t1) in radians and pixels, p_out[0] = 0.
+   The N-1 neighbour registrations run as one batch, then each level of the params->scan
+   schedule as one batch, every B application started from the composition of its operands'
+   maps (alpha = alpha_ij + alpha_jk, t = R(alpha_jk) t_ij + t_jk). stats (host, may be NULL):
+   op counts, flags and times (ms_prepare: pyramids; ms_scan: A and B applications). */
+pprs_status pprs_prefix_register_series_rigid(pprs_ctx* ctx, const float* frames, int N, int H,
+                                              int W, double* p_out, const pprs_params* params,
+                                              pprs_series_stats* stats);
+
 /* Composition of deformations (section "Registration for series of images"):
    (phi_jk o phi_ij)(x) = phi_jk(phi_ij(x)), i.e. u_ik(x) = u_ij(x) + u_jk(x + u_ij(x)) with
    u_jk interpolated bilinearly and clamped to the domain. All [2][H][W]; u_ik may alias u_ij

@@ -289,6 +289,59 @@ def register_rigid(R, T, params: Params, p_init=None):
     return out, _stats(st, params.levels)
 
 
+def _compose_rigid(u, v):
+    """phi_jk o phi_ij for parameter rows u = phi_ij, v = phi_jk (alpha, t0, t1): the rotation
+    angles add, t = R(alpha_jk) t_ij + t_jk."""
+    c, s = np.cos(v[0]), np.sin(v[0])
+    return np.array([u[0] + v[0], c * u[1] - s * u[2] + v[1], s * u[1] + c * u[2] + v[2]])
+
+
+def series_rigid(frames_nodal, params: Params, scan: str = "brent_kung"):
+    """Series registration with the rigid operator (definition of image series registration):
+    N-1 neighbour registrations, then the scan with B = rigid registration started from the
+    composition of the operands' maps. Schedules: "sequential" and "brent_kung" (Prefix sum
+    chapter; the standard 0-based Brent-Kung form for any element count). Returns p [N, 3]
+    (phi_0i; alpha in radians, t in domain units; p[0] = 0)."""
+    fr = _f64(frames_nodal)
+    N = fr.shape[0]
+    M = N - 1
+    out = np.zeros((N, 3))
+    if M < 1:
+        return out
+    el = [[m, m + 1, register_rigid(fr[m], fr[m + 1], params)[0]] for m in range(M)]
+
+    def apply(a, b):
+        ia, ka, pa = el[a]
+        ib, kb, pb = el[b]
+        assert ka == ib
+        el[b] = [ia, kb, register_rigid(fr[ia], fr[kb], params,
+                                        p_init=_compose_rigid(pa, pb))[0]]
+
+    if scan == "sequential":
+        for m in range(1, M):
+            apply(m - 1, m)
+    elif scan == "brent_kung":
+        d = 1
+        while d < M:
+            for j in range(2 * d - 1, M, 2 * d):
+                apply(j - d, j)
+            d *= 2
+        top = 1
+        while top * 2 < M:
+            top *= 2
+        d = top
+        while d >= 1:
+            for j in range(3 * d - 1, M, 2 * d):
+                apply(j - d, j)
+            d //= 2
+    else:
+        raise ValueError("rigid series: sequential or brent_kung")
+    for m in range(M):
+        assert el[m][0] == 0 and el[m][1] == m + 1
+        out[m + 1] = el[m][2]
+    return out
+
+
 def set_u_storage_f32(on: bool) -> None:
     """Test switch: round the displacement to FP32 after every accepted step (process-wide)."""
     _load().or_set_u_storage_f32(1 if on else 0)

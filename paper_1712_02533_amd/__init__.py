@@ -5,7 +5,8 @@ marshals arguments: torch tensors supply device memory and the stream. Importing
 load the library; the first call does, and fails loudly if it has not been built.
 """
 from .api import (Params, PairStats, SeriesStats, compose_deformations, default_params,
-                  kernel_names, kernel_timing, prefix_register_series, register_pair,
+                  kernel_names, kernel_timing, prefix_register_series,
+                  prefix_register_series_rigid, register_pair,
                   register_pairs, register_pairs_rigid, register_series_batch, PprsError,
                   scan_plan, series_average, set_kernel_timing, set_pool, get_tuning, set_tuning,
                   set_metric_solve,
@@ -13,7 +14,8 @@ from .api import (Params, PairStats, SeriesStats, compose_deformations, default_
                   level7_targets, set_warm_start)
 
 __all__ = ["Params", "PairStats", "SeriesStats", "compose_deformations", "default_params",
-           "kernel_names", "kernel_timing", "prefix_register_series", "register_pair",
+           "kernel_names", "kernel_timing", "prefix_register_series",
+           "prefix_register_series_rigid", "register_pair",
            "register_pairs", "register_pairs_rigid", "register_series_batch", "PprsError",
            "scan_plan", "series_average", "set_kernel_timing", "set_pool", "get_tuning", "set_tuning",
            "set_metric_solve", "Context", "WarmStartNet", "pair_inputs",

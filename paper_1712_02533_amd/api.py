@@ -127,6 +127,7 @@ def _lib():
                 "pprs_compose_deformations": (i, [vp, vp, vp, vp, i, i]),
                 "pprs_series_average": (i, [vp, vp, vp, i, i, i, vp]),
                 "pprs_register_pairs_rigid": (i, [vp, vp, i, i, i, vp, vp, i, vp, vp, vp, vp]),
+                "pprs_prefix_register_series_rigid": (i, [vp, vp, i, i, i, vp, vp, vp]),
                 "pprs_prefix_register_series": (i, [vp, vp, i, i, i, vp,
                                                     ctypes.POINTER(_CParams),
                                                     ctypes.POINTER(_CSeriesStats),
@@ -310,6 +311,25 @@ def register_pairs_rigid(frames, ref, tmpl, params: Params | None = None, p_init
         c.handle, _dev_f32(frames, "frames"), N, H, W, ref.ctypes.data, tmpl.ctypes.data, P,
         pin.ctypes.data if pin is not None else None, out.ctypes.data, ctypes.byref(cp), st))
     return out[:P], [_pair_stats(st[k], params.levels) for k in range(P)]
+
+
+def prefix_register_series_rigid(frames, params: Params | None = None):
+    """Rigid series: frames [N, H, W] -> (p [N, 3] float64: phi_0i as alpha (rad), t0, t1 (px),
+    p[0] = 0; SeriesStats)."""
+    import numpy as np
+    params = params or Params()
+    N, H, W = frames.shape
+    out = np.zeros((N, 3))
+    ss = _CSeriesStats()
+    cp = params.c()
+    c = _ctx(frames.device)
+    _check(_lib().pprs_prefix_register_series_rigid(
+        c.handle, _dev_f32(frames, "frames"), N, H, W, out.ctypes.data, ctypes.byref(cp),
+        ctypes.byref(ss)))
+    stats = SeriesStats(ss.n_ops_a, ss.n_ops_b, ss.n_scan_levels, ss.flags_or, ss.ms_total,
+                        ss.ms_prepare, ss.ms_preprocess, ss.ms_scan, ss.node_steps,
+                        ss.node_passes)
+    return out, stats
 
 
 def series_average(frames, u, out=None):

@@ -1315,6 +1315,103 @@ pprs_status pprs_compose_deformations(pprs_ctx* c, const float* u_ij, const floa
   return PPRS_OK;
 }
 
+// Rigid series (the series registration with the rigid operator): the N-1 neighbour
+// registrations in one batch, then every level of the scan schedule as one batch, each B
+// application started from the composition of its operands' maps,
+// phi_jk o phi_ij: alpha = alpha_ij + alpha_jk, t = R(alpha_jk) t_ij + t_jk.
+pprs_status pprs_prefix_register_series_rigid(pprs_ctx* c, const float* frames, int N, int H,
+                                              int W, double* p_out, const pprs_params* params,
+                                              pprs_series_stats* stats) {
+  STCHK(enter(c));
+  auto t0 = std::chrono::steady_clock::now();
+  int L = frame_level(H, W);
+  if (L < 0) return fail(PPRS_EINVAL, "frames must be square with side 2^L or 2^L+1, L in [2,10]");
+  if (!frames || !p_out || N < 1) return fail(PPRS_EINVAL, "bad arguments");
+  STCHK(check_params(params, L));
+  for (int k = 0; k < 3; ++k) p_out[k] = 0.0;
+  if (stats) memset(stats, 0, sizeof(*stats));
+  int M = N - 1;
+  if (M < 1) return PPRS_OK;
+  int m0 = L - params->levels + 1;
+  std::vector<char> is_ref(N, 1);
+  STCHK(prepare_frames(c, frames, N, H, L, m0, 0, &is_ref));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  auto t1 = std::chrono::steady_clock::now();
+  int n_ops = 0, n_levels = 0;
+  pprs_scan_plan(params->scan, M, nullptr, 0, &n_ops, &n_levels);
+  std::vector<int> plan(3 * (size_t)std::max(n_ops, 1));
+  if (pprs_scan_plan(params->scan, M, plan.data(), n_ops, &n_ops, &n_levels) != PPRS_OK)
+    return fail(PPRS_EINVAL, "scan planning failed");
+  int widest = M;
+  for (int i = 0; i < n_ops;) {
+    int j = i;
+    while (j < n_ops && plan[3 * j + 2] == plan[3 * i + 2]) ++j;
+    widest = std::max(widest, j - i);
+    i = j;
+  }
+  STCHK(ensure_slots(c, widest, L, m0, params->beta));
+  // elements x_m = (ei[m], ek[m], p[m]) in domain units
+  std::vector<int> ei(M), ek(M), ref(widest), tmpl(widest);
+  std::vector<double> pe(3 * (size_t)M), pin(3 * (size_t)widest), pres(3 * (size_t)widest);
+  int flags = 0;
+  for (int m = 0; m < M; ++m) {
+    ei[m] = m;
+    ek[m] = m + 1;
+    ref[m] = m;
+    tmpl[m] = m + 1;
+  }
+  STCHK(run_batch_rigid(c, M, ref.data(), tmpl.data(), nullptr, pe.data(), params, nullptr,
+                        &flags));
+  for (int i = 0; i < n_ops;) {
+    int j = i;
+    while (j < n_ops && plan[3 * j + 2] == plan[3 * i + 2]) ++j;
+    int cnt = j - i;
+    // operands as they stand before the level (within a level no op reads what another
+    // op of the level writes)
+    for (int q = 0; q < cnt; ++q) {
+      int a = plan[3 * (i + q)], b = plan[3 * (i + q) + 1];
+      if (ek[a] != ei[b])
+        return fail(PPRS_EINDEX, "scan operands (%d,%d) and (%d,%d) do not share a frame", ei[a],
+                    ek[a], ei[b], ek[b]);
+      const double* u = &pe[3 * (size_t)a];  // phi_ij
+      const double* v = &pe[3 * (size_t)b];  // phi_jk
+      double cb = cos(v[0]), sb = sin(v[0]);
+      pin[3 * q] = u[0] + v[0];
+      pin[3 * q + 1] = cb * u[1] - sb * u[2] + v[1];
+      pin[3 * q + 2] = sb * u[1] + cb * u[2] + v[2];
+      ref[q] = ei[a];
+      tmpl[q] = ek[b];
+    }
+    STCHK(run_batch_rigid(c, cnt, ref.data(), tmpl.data(), pin.data(), pres.data(), params,
+                          nullptr, &flags));
+    for (int q = 0; q < cnt; ++q) {
+      int a = plan[3 * (i + q)], b = plan[3 * (i + q) + 1];
+      ei[b] = ei[a];
+      for (int k = 0; k < 3; ++k) pe[3 * (size_t)b + k] = pres[3 * q + k];
+    }
+    i = j;
+  }
+  const double px = (double)(level_n(L) - 1);
+  for (int m = 0; m < M; ++m) {
+    if (ei[m] != 0 || ek[m] != m + 1)
+      return fail(PPRS_EINDEX, "element %d ends as (%d,%d)", m, ei[m], ek[m]);
+    p_out[3 * (m + 1)] = pe[3 * (size_t)m];
+    p_out[3 * (m + 1) + 1] = pe[3 * (size_t)m + 1] * px;
+    p_out[3 * (m + 1) + 2] = pe[3 * (size_t)m + 2] * px;
+  }
+  auto t2 = std::chrono::steady_clock::now();
+  if (stats) {
+    stats->n_ops_a = M;
+    stats->n_ops_b = n_ops;
+    stats->n_scan_levels = n_levels;
+    stats->flags_or = flags;
+    stats->ms_prepare = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    stats->ms_scan = std::chrono::duration<double, std::milli>(t2 - t1).count();
+    stats->ms_total = std::chrono::duration<double, std::milli>(t2 - t0).count();
+  }
+  return status_from_flags(flags);
+}
+
 pprs_status pprs_series_average(pprs_ctx* c, const float* frames, const float* u, int N, int H,
                                 int W, float* avg) {
   STCHK(enter(c));

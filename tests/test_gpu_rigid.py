@@ -13,7 +13,7 @@ import pytest
 
 import oracle as O
 from synth import CONFIGS, make_series
-from test_oracle_pins import _rotated_pair
+from test_oracle_pins import _rigid_series, _rotated_pair
 
 pytestmark = pytest.mark.gpu
 
@@ -109,3 +109,28 @@ def test_rigid_batch_equals_single_pairs_and_start_at_answer():
         assert _map_diff(pa[k], pb[k], side) < BAR_PX
         say("  case %d: %d iterations from the answer, %d from the identity"
             % (k, sum(sa[k].iters), sum(sb[k].iters)))
+
+
+@pytest.mark.parametrize("scan", ["sequential", "brent_kung"])
+def test_rigid_series_matches_oracle(scan):
+    """A 9-frame rigid series of 64 x 64 frames (cumulative rotations and shifts): every phi_0k
+    against the oracle's scan with the same schedule, and against the maps the frames were
+    made with."""
+    torch = _torch()
+    import paper_1712_02533_amd as P
+    side, N = 64, 9
+    frames, truth = _rigid_series(side, N, 36)
+    frames = frames.astype(np.float32)
+    say("rigid series %d x %d, %s" % (N, side, scan))
+    p, st = P.prefix_register_series_rigid(torch.tensor(frames, device="cuda"),
+                                           params=P.Params(levels=2, scan=scan, **TIGHT))
+    po = O.series_rigid(np.stack([O.frame_to_nodes(f) for f in frames]),
+                        O.Params(levels=2, **TIGHT), scan=scan)
+    po[:, 1:] *= side
+    assert np.all(p[0] == 0)
+    worst = max(_map_diff(p[k], po[k], side) for k in range(N))
+    to_truth = max(_map_diff(p[k], truth[k], side) for k in range(N))
+    say("  %d A + %d B ops, %.1f ms; largest map difference to the oracle %.2e px, to the "
+        "truth %.3f px" % (st.n_ops_a, st.n_ops_b, st.ms_total, worst, to_truth))
+    assert worst < BAR_PX
+    assert to_truth < 0.05

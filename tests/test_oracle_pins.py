@@ -658,3 +658,64 @@ def test_rigid_energy_is_the_field_energy_of_the_affine_displacement():
     assert abs(st.energy - e_field) < 1e-12
     p2, st2 = O.register_rigid(R, T, O.Params(levels=1), p_init=p0)
     assert st2.energy <= e_field
+
+
+def _rigid_series(side, N, seed, rot=0.008, shift=1.5):
+    """Frames f_k = L o Phi_k^-1 for cumulative random rigid maps Phi_k (Phi_0 = identity):
+    f_0 = f_k o phi_0k with phi_0k = Phi_k. Returns frames [N, side, side] and the true
+    parameter rows (alpha, t0 px, t1 px) of phi_0k."""
+    from synth.blobs import _lattice
+    spec = SeriesSpec(2, side, 8.0, 0.0, 0.0, seed)
+    s = make_series(spec)
+    rng = np.random.default_rng(seed)
+    r, c = np.meshgrid(np.arange(side, dtype=np.float64), np.arange(side, dtype=np.float64),
+                       indexing="ij")
+    frames, truth = [], []
+    a, t = 0.0, np.zeros(2)
+    for k in range(N):
+        if k:
+            a += rng.uniform(-rot, rot)
+            t = t + rng.uniform(-shift, shift, size=2)
+        ca, sa = np.cos(a), np.sin(a)
+        x, y = c - t[0], r - t[1]
+        frames.append(_lattice(spec, s.origin, s.amps, s.lattice_lo, ca * x + sa * y,
+                               -sa * x + ca * y))
+        truth.append([a, t[0], t[1]])
+    return np.stack(frames), np.array(truth)
+
+
+def test_rigid_composition_is_the_product_of_the_maps():
+    """phi_jk o phi_ij in parameters against the product of homogeneous 3x3 matrices."""
+    rng = np.random.default_rng(34)
+
+    def mat(p):
+        c, s = np.cos(p[0]), np.sin(p[0])
+        return np.array([[c, -s, p[1]], [s, c, p[2]], [0.0, 0.0, 1.0]])
+
+    for _ in range(20):
+        u, v = rng.uniform(-1, 1, 3), rng.uniform(-1, 1, 3)
+        w = O._compose_rigid(u, v)
+        assert np.allclose(mat(w), mat(v) @ mat(u), atol=1e-14)
+    assert np.allclose(O._compose_rigid(u, np.zeros(3)), u)
+
+
+def test_rigid_series_recovers_cumulative_maps():
+    side, N = 64, 6
+    frames, truth = _rigid_series(side, N, 35)
+    fr = np.stack([O.frame_to_nodes(f) for f in frames])
+    for scan in ("sequential", "brent_kung"):
+        p = O.series_rigid(fr, O.Params(levels=2, eps=1e-9, iter_max=400), scan=scan)
+        assert np.all(p[0] == 0)
+        for k in range(1, N):
+            got = np.array([p[k, 0], p[k, 1] * side, p[k, 2] * side])
+            # largest corner distance between the recovered and the true map (px)
+            d = 0.0
+            for x in (0, side):
+                for y in (0, side):
+                    ga = np.array([np.cos(got[0]) * x - np.sin(got[0]) * y + got[1],
+                                   np.sin(got[0]) * x + np.cos(got[0]) * y + got[2]])
+                    tr = truth[k]
+                    ta = np.array([np.cos(tr[0]) * x - np.sin(tr[0]) * y + tr[1],
+                                   np.sin(tr[0]) * x + np.cos(tr[0]) * y + tr[2]])
+                    d = max(d, float(np.hypot(*(ga - ta))))
+            assert d < 0.05, (scan, k, d)
