@@ -30,6 +30,8 @@ WORKLOADS = {
                     "3 levels; Brent-Kung scan; cold start", spec=("c2",)),
     "c1": dict(name="8 frames of 64x64, drift<=2 px, 20 counts; 2 levels; sequential scan",
                spec=("c1",)),
+    "paper": dict(name="4096 frames of 1024x1024, drift<=2 px, 10 counts; rigid operator; "
+                       "3 levels (the paper's levels 8-10); Brent-Kung scan", spec=None),
     "c5": dict(name="16 independent series in one run: sides {128,256,512,1024}, 32-512 "
                     "frames, drift<=8 px, non-rigid<=1.5 px, 2-20 counts; coarsest level 6; "
                     "Brent-Kung scans; segmented slot pool", spec=None),
@@ -192,6 +194,43 @@ def warm_runs(P, frames, out, params, args, regs_per_step):
     return res
 
 
+def bench_paper_rigid(args):
+    """The paper's serial experiment in shape (4096 frames of about 1024^2, levels 8-10, the
+    rigid operator it most likely timed), as one rigid series on one GPU. Synthetic frames."""
+    import torch
+    import paper_1712_02533_amd as P
+    from synth import SeriesSpec, make_series
+    spec = SeriesSpec(args.frames or 4096, 1024, 2.0, 0.0, 10.0, 4)
+    t0 = time.perf_counter()
+    series = make_series(spec, workers=min(16, os.cpu_count() or 1))
+    log("generated %d frames of 1024x1024 in %.1f s" % (spec.n_frames, time.perf_counter() - t0))
+    dev = torch.device("cuda", 0)
+    frames = torch.tensor(series.frames, device=dev)
+    del series
+    params = P.Params(levels=3, scan="brent_kung")
+    for w in range(args.warmup):
+        _, st = P.prefix_register_series_rigid(frames, params=params)
+        log("warmup %d: %.1f ms" % (w, st.ms_total))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    regs = 0
+    for k in range(args.steps):
+        _, st = P.prefix_register_series_rigid(frames, params=params)
+        regs += st.n_ops_a + st.n_ops_b
+        log("step %d: %.1f ms (prepare %.1f, scan %.1f), %d A + %d B" %
+            (k, st.ms_total, st.ms_prepare, st.ms_scan, st.n_ops_a, st.n_ops_b))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps(dict(
+        metric="frame-pair registrations/s and series time, rigid operator", value=round(regs / dt, 3),
+        unit="registrations/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=round(1e3 * dt / args.steps, 1), higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f32", data="synthetic",
+        config=dict(workload=WORKLOADS["paper"]["name"].replace("4096", str(spec.n_frames)),
+                    frames=spec.n_frames, side=1024,
+                    levels=3, scan="brent_kung", operator="rigid"))), flush=True)
+
+
 def bench_uneven(args):
     """The segmented workload: 16 series of mixed sides and lengths registered concurrently
     (cold, then with the warm start); throughput over all series and per-series latency."""
@@ -280,6 +319,7 @@ def main():
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start runs")
     ap.add_argument("--no-tune", action="store_true", help="default launch shape, no autotuning")
+    ap.add_argument("--no-rigid", action="store_true", help="skip the rigid-operator series")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1712_02533_amd", "weights",
                                                       "warmstart_512.safetensors"))
     args = ap.parse_args()
@@ -290,6 +330,8 @@ def main():
 
     if args.config == "c5":
         return bench_uneven(args)
+    if args.config == "paper":
+        return bench_paper_rigid(args)
     import numpy as np
     import torch
     import paper_1712_02533_amd as P
@@ -385,6 +427,20 @@ def main():
     result["average"] = dict(ms=round(ams, 3), bytes=abytes,
                              gbs=round(abytes / (ams * 1e-3) / 1e9, 1))
     log("series average: %.3f ms, %.0f GB/s" % (ams, abytes / (ams * 1e-3) / 1e9))
+    if not args.no_rigid:
+        # the same frames through the rigid operator (three parameters per registration)
+        rp = P.Params(levels=cfg["levels"], scan=scan)
+        P.prefix_register_series_rigid(frames, params=rp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = None
+        for _ in range(2):
+            _, rs = P.prefix_register_series_rigid(frames, params=rp)
+        rms = 1e3 * (time.perf_counter() - t0) / 2
+        rregs = rs.n_ops_a + rs.n_ops_b
+        result["rigid"] = dict(ms_per_step=round(rms, 1), value=round(rregs / (rms * 1e-3), 3),
+                               unit="registrations/s", registrations_per_step=rregs)
+        log("rigid series: %.1f ms, %d registrations" % (rms, rregs))
     if not args.no_warm and os.path.exists(args.weights) and spec.side >= 128:
         result["warm"] = warm_runs(P, frames, out, params, args, stats[0].n_ops_a + stats[0].n_ops_b)
     if not args.no_cpu:

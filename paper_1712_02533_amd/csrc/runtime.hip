@@ -114,6 +114,7 @@ struct pprs_ctx {
   size_t lds_smooth[2] = {0, 0};
   BatchDesc hd;
   int slots_cap = 0, slots_L = -1, slots_m0 = -1;
+  bool slots_fields = false;  // the per-slot field buffers (u, d, G, z) cover slots_cap slots
   double coef_beta = -1.0;
   int coef_L = -1, coef_m0 = -1;
   // kernel timing
@@ -247,9 +248,11 @@ int window_halo(double beta) {
 }
 
 // Workspace for up to `cap` slots on levels m0..L, and the metric coefficients for beta.
-pprs_status ensure_slots(pprs_ctx* c, int cap, int L, int m0, double beta) {
+// fields = false (the rigid variant): state, partials and lists only, no per-slot fields.
+pprs_status ensure_slots(pprs_ctx* c, int cap, int L, int m0, double beta, bool fields = true) {
   BatchDesc& hd = c->hd;
-  if (cap > c->slots_cap || L != c->slots_L || m0 != c->slots_m0) {
+  if (cap > c->slots_cap || L != c->slots_L || m0 != c->slots_m0 ||
+      (fields && !c->slots_fields)) {
     cap = std::max(cap, c->slots_cap);
     hd.finest = L;
     hd.coarsest = m0;
@@ -273,10 +276,12 @@ pprs_status ensure_slots(pprs_ctx* c, int cap, int L, int m0, double beta) {
     hd.part_slot_stride = hd.part_kind_stride * WK_COUNT;
     hd.max_slots = cap;
     STCHK(ensure(c->state, sizeof(SlotState) * cap));
-    STCHK(ensure(c->ubuf, sizeof(float) * hd.slot_u_stride * cap));
-    STCHK(ensure(c->dbuf, sizeof(float) * hd.slot_f_stride * cap, true));
-    STCHK(ensure(c->gbuf, sizeof(float) * hd.slot_p_stride * cap));
-    STCHK(ensure(c->zbuf, sizeof(float) * hd.slot_p_stride * cap));
+    if (fields) {
+      STCHK(ensure(c->ubuf, sizeof(float) * hd.slot_u_stride * cap));
+      STCHK(ensure(c->dbuf, sizeof(float) * hd.slot_f_stride * cap, true));
+      STCHK(ensure(c->gbuf, sizeof(float) * hd.slot_p_stride * cap));
+      STCHK(ensure(c->zbuf, sizeof(float) * hd.slot_p_stride * cap));
+    }
     STCHK(ensure(c->partial, sizeof(double) * hd.part_slot_stride * cap));
     STCHK(ensure(c->nodecount, sizeof(long long) * WK_COUNT * cap));
     STCHK(ensure(c->coef, sizeof(float) * coef_off));
@@ -297,6 +302,8 @@ pprs_status ensure_slots(pprs_ctx* c, int cap, int L, int m0, double beta) {
     hd.list_off = P<int>(c->list_off);
     hd.lists = P<WorkList>(c->lists);
     hd.active_host = nullptr;  // the host polls the device word instead
+    // the field buffers cover cap slots of this geometry only when allocated now
+    c->slots_fields = fields;
     c->slots_cap = cap;
     c->slots_L = L;
     c->slots_m0 = m0;
@@ -1268,7 +1275,7 @@ pprs_status pprs_register_pairs_rigid(pprs_ctx* c, const float* frames, int N, i
   const double px = (double)(level_n(L) - 1);
   STCHK(prepare_frames(c, frames, N, H, L, m0, 0, &is_ref));
   int chunk = std::min(P, kPairChunk);
-  STCHK(ensure_slots(c, chunk, L, m0, params->beta));
+  STCHK(ensure_slots(c, chunk, L, m0, params->beta, false));
   int flags = 0;
   std::vector<double> pin(3 * (size_t)chunk), pout(3 * (size_t)chunk);
   for (int p0 = 0; p0 < P; p0 += chunk) {
@@ -1349,7 +1356,7 @@ pprs_status pprs_prefix_register_series_rigid(pprs_ctx* c, const float* frames, 
     widest = std::max(widest, j - i);
     i = j;
   }
-  STCHK(ensure_slots(c, widest, L, m0, params->beta));
+  STCHK(ensure_slots(c, widest, L, m0, params->beta, false));
   // elements x_m = (ei[m], ek[m], p[m]) in domain units
   std::vector<int> ei(M), ek(M), ref(widest), tmpl(widest);
   std::vector<double> pe(3 * (size_t)M), pin(3 * (size_t)widest), pres(3 * (size_t)widest);
