@@ -10,6 +10,10 @@ hipError_t prolong(BatchDesc* d, int grid, hipStream_t st);
 bool ladder_rungs_ok(int nc);
 hipError_t energy(BatchDesc* d, int mode, int nc, int grid, hipStream_t st);
 hipError_t energy_fin(BatchDesc* d, int mode, int nc, int grid, hipStream_t st);
+// start energies (eval list) and line-search passes (ladder list) of a step in one launch,
+// and their finalisers
+hipError_t energy_step(BatchDesc* d, int nc, int grid, hipStream_t st);
+hipError_t energy_step_fin(BatchDesc* d, int nc, int grid, hipStream_t st);
 hipError_t smooth_fin(BatchDesc* d, int grid, hipStream_t st);
 // gradient tile variants: 0 = 32x16, 1 = 64x8, 2 = 128x4, 3 = 64x16 nodes
 void grad_tile(int variant, int* tx, int* ty);

@@ -177,6 +177,28 @@ __device__ bool cursor_begin(const BatchDesc* D, int kind, ItemCursor& c, int* s
   return true;
 }
 
+// The items [item0, item1) of one list (uniform over the block; false when empty).
+__device__ bool cursor_range(const BatchDesc* D, int kind, int item0, int item1, ItemCursor& c,
+                             int* s_pos) {
+  if (item0 >= item1) return false;
+  c.item = item0;
+  c.end = item1;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int* off = D->list_off + (size_t)kind * (D->max_slots + 1);
+    int lo = 0, hi = D->lists[kind].n_slots - 1;
+    while (lo < hi) {  // largest pos with off[pos] <= item
+      int mid = (lo + hi + 1) >> 1;
+      if (off[mid] <= c.item) lo = mid; else hi = mid - 1;
+    }
+    *s_pos = lo;
+  }
+  __syncthreads();
+  c.pos = *s_pos;
+  __syncthreads();
+  return true;
+}
+
 __device__ __forceinline__ void cursor_slot(const BatchDesc* D, int kind, ItemCursor& c,
                                             int& slot, int& local) {
   const int* off = D->list_off + (size_t)kind * (D->max_slots + 1);
@@ -242,11 +264,14 @@ __global__ void __launch_bounds__(PLAN_T) k_plan(BatchDesc* D) {
 #pragma unroll
     for (int k = 0; k < WK_COUNT; ++k) {
       bool m;
+      // A slot that begins a level this step (INIT, PROLONG) takes its start energy only, at
+      // the end of the step beside the line searches; its first iteration is the next step's.
+      // The iterating slots (GRAD, LADDER) take gradient, metric solve and line search.
       switch (k) {
         case WK_PROLONG: m = ph == PH_PROLONG; break;
         case WK_EVAL: m = ph == PH_PROLONG || ph == PH_INIT; break;
-        case WK_LADDER: m = ph != PH_DONE; break;
-        default: m = ph == PH_PROLONG || ph == PH_INIT || ph == PH_GRAD; break;
+        case WK_LADDER: m = ph == PH_GRAD || ph == PH_LADDER; break;
+        default: m = ph == PH_GRAD; break;
       }
       val[2 * k] = m ? 1 : 0;
       val[2 * k + 1] = m ? kind_items(D, k, eff) : 0;
@@ -486,23 +511,23 @@ __device__ __forceinline__ void energy_finalize(BatchDesc* D, SlotState* stp, in
   store_head(*stp, st);
 }
 
+// Staged nodes of an element tile (ET_X x ET_Y elements).
+#define ET_NN ((ET_X + 1) * (ET_Y + 1))
+
+// One energy item: element tile t of slot s (MODE and NC as k_energy's). The LDS arrays are
+// the caller's (s_dx, s_dy unused in MODE 0).
 template <int MODE, int NC>
-__global__ void __launch_bounds__(BLOCK, LB_ENERGY) k_energy(BatchDesc* D) {
-  constexpr int NXN = ET_X + 1, NYN = ET_Y + 1, NN = NXN * NYN;
+__device__ __forceinline__ void energy_item(BatchDesc* D, int s, int t, float* s_ux, float* s_uy,
+                                            float* s_dx, float* s_dy, float* s_r,
+                                            double* s_red) {
+  constexpr int NXN = ET_X + 1, NN = ET_NN;
   constexpr int NV = 3 * NC + 3;
-  __shared__ float s_ux[NN], s_uy[NN], s_dx[MODE ? NN : 1], s_dy[MODE ? NN : 1], s_r[NN];
-  __shared__ double s_red[(BLOCK / 64) * NV];
-  __shared__ int s_pos;
   const int kind = MODE ? WK_LADDER : WK_EVAL;
-  ItemCursor c;
-  if (!cursor_begin(D, kind, c, &s_pos)) return;
-  for (; c.item < c.end; ++c.item) {
-    int s, t;
-    cursor_slot(D, kind, c, s, t);
+  {
     SlotState* stp = D->state + s;
     int ph = stp->phase;
-    if (MODE == 0 && !(ph == PH_INIT || ph == PH_PROLONG)) continue;
-    if (MODE == 1 && ph != PH_LADDER) continue;
+    if (MODE == 0 && !(ph == PH_INIT || ph == PH_PROLONG)) return;
+    if (MODE == 1 && ph != PH_LADDER) return;
     int l = (ph == PH_PROLONG) ? stp->level + 1 : stp->level;
     int ub = (ph == PH_PROLONG) ? 0 : stp->ub;
     int n = lvl_n(l);
@@ -619,27 +644,97 @@ __global__ void __launch_bounds__(BLOCK, LB_ENERGY) k_energy(BatchDesc* D) {
   }
 }
 
+template <int MODE, int NC>
+__global__ void __launch_bounds__(BLOCK, LB_ENERGY) k_energy(BatchDesc* D) {
+  constexpr int NN = ET_NN;
+  constexpr int NV = 3 * NC + 3;
+  __shared__ float s_ux[NN], s_uy[NN], s_dx[MODE ? NN : 1], s_dy[MODE ? NN : 1], s_r[NN];
+  __shared__ double s_red[(BLOCK / 64) * NV];
+  __shared__ int s_pos;
+  const int kind = MODE ? WK_LADDER : WK_EVAL;
+  ItemCursor c;
+  if (!cursor_begin(D, kind, c, &s_pos)) return;
+  for (; c.item < c.end; ++c.item) {
+    int s, t;
+    cursor_slot(D, kind, c, s, t);
+    energy_item<MODE, NC>(D, s, t, s_ux, s_uy, s_dx, s_dy, s_r, s_red);
+  }
+}
+
+// The energy passes of a step in one launch: the start energies of the slots that begin a
+// level (the eval list) and the line-search passes (the ladder list), one item space made of
+// the two lists in that order. The two slot sets are disjoint (the plan gives a slot that
+// begins a level no gradient work in the same step).
+template <int NC>
+__global__ void __launch_bounds__(BLOCK, LB_ENERGY) k_energy_step(BatchDesc* D) {
+  constexpr int NN = ET_NN;
+  constexpr int NV = 3 * NC + 3;
+  __shared__ float s_ux[NN], s_uy[NN], s_dx[NN], s_dy[NN], s_r[NN];
+  __shared__ double s_red[(BLOCK / 64) * NV];
+  __shared__ int s_pos;
+  const int ne = D->lists[WK_EVAL].total, nl = D->lists[WK_LADDER].total;
+  const int total = ne + nl;
+  if (total <= 0) return;
+  int chunk = (total + gridDim.x - 1) / gridDim.x;
+  int b0 = blockIdx.x * chunk, b1 = min(b0 + chunk, total);
+  ItemCursor c;
+  if (b0 < ne && cursor_range(D, WK_EVAL, b0, min(b1, ne), c, &s_pos)) {
+    for (; c.item < c.end; ++c.item) {
+      int s, t;
+      cursor_slot(D, WK_EVAL, c, s, t);
+      energy_item<0, 1>(D, s, t, s_ux, s_uy, s_dx, s_dy, s_r, s_red);
+    }
+  }
+  if (b1 > ne && cursor_range(D, WK_LADDER, max(b0, ne) - ne, b1 - ne, c, &s_pos)) {
+    for (; c.item < c.end; ++c.item) {
+      int s, t;
+      cursor_slot(D, WK_LADDER, c, s, t);
+      energy_item<1, NC>(D, s, t, s_ux, s_uy, s_dx, s_dy, s_r, s_red);
+    }
+  }
+}
+
 // Per-slot finalisation of an energy pass: one workgroup per listed slot sums the tile
 // partials in tile order and advances the slot (the kernel boundary orders it after the pass).
+template <int MODE, int NC>
+__device__ __forceinline__ void energy_fin_slot(BatchDesc* D, int s, double* s_red) {
+  constexpr int NV = 3 * NC + 3;
+  const int kind = MODE ? WK_LADDER : WK_EVAL;
+  SlotState* stp = D->state + s;
+  int ph = stp->phase;
+  if (MODE == 0 && !(ph == PH_INIT || ph == PH_PROLONG)) return;
+  if (MODE == 1 && ph != PH_LADDER) return;
+  int l = (ph == PH_PROLONG) ? stp->level + 1 : stp->level;
+  int n = lvl_n(l);
+  double top = MODE ? stp->top : 0.0;
+  double tot[NV];
+  sum_partials<NV>(D, s, kind, D->geom[l].tiles_elem, tot, s_red, false);
+  if (threadIdx.x == 0) energy_finalize<MODE, NC>(D, stp, s, l, n, ph, top, tot);
+  __syncthreads();
+}
+
 template <int MODE, int NC>
 __global__ void __launch_bounds__(BLOCK) k_energy_fin(BatchDesc* D) {
   constexpr int NV = 3 * NC + 3;
   __shared__ double s_red[(BLOCK / 64) * NV];
   const int kind = MODE ? WK_LADDER : WK_EVAL;
   const WorkList wl = D->lists[kind];
-  for (int pos = blockIdx.x; pos < wl.n_slots; pos += gridDim.x) {
-    int s = D->list_slots[(size_t)kind * D->max_slots + pos];
-    SlotState* stp = D->state + s;
-    int ph = stp->phase;
-    if (MODE == 0 && !(ph == PH_INIT || ph == PH_PROLONG)) continue;
-    if (MODE == 1 && ph != PH_LADDER) continue;
-    int l = (ph == PH_PROLONG) ? stp->level + 1 : stp->level;
-    int n = lvl_n(l);
-    double top = MODE ? stp->top : 0.0;
-    double tot[NV];
-    sum_partials<NV>(D, s, kind, D->geom[l].tiles_elem, tot, s_red, false);
-    if (threadIdx.x == 0) energy_finalize<MODE, NC>(D, stp, s, l, n, ph, top, tot);
-    __syncthreads();
+  for (int pos = blockIdx.x; pos < wl.n_slots; pos += gridDim.x)
+    energy_fin_slot<MODE, NC>(D, D->list_slots[(size_t)kind * D->max_slots + pos], s_red);
+}
+
+// Finalisers of k_energy_step: the eval list's slots, then the ladder list's.
+template <int NC>
+__global__ void __launch_bounds__(BLOCK) k_energy_step_fin(BatchDesc* D) {
+  constexpr int NV = 3 * NC + 3;
+  __shared__ double s_red[(BLOCK / 64) * NV];
+  const int ne = D->lists[WK_EVAL].n_slots, nl = D->lists[WK_LADDER].n_slots;
+  for (int pos = blockIdx.x; pos < ne + nl; pos += gridDim.x) {
+    if (pos < ne)
+      energy_fin_slot<0, 1>(D, D->list_slots[(size_t)WK_EVAL * D->max_slots + pos], s_red);
+    else
+      energy_fin_slot<1, NC>(D, D->list_slots[(size_t)WK_LADDER * D->max_slots + pos - ne],
+                             s_red);
   }
 }
 
@@ -1948,6 +2043,28 @@ hipError_t energy(BatchDesc* d, int mode, int nc, int grid, hipStream_t st) {
       case 7: hipLaunchKernelGGL((k_energy<1, 7>), dim3(grid), dim3(BLOCK), 0, st, d); break;
       default: return hipErrorInvalidValue;
     }
+  }
+  return hipGetLastError();
+}
+hipError_t energy_step(BatchDesc* d, int nc, int grid, hipStream_t st) {
+  switch (nc) {
+    case 1: hipLaunchKernelGGL((k_energy_step<1>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    case 2: hipLaunchKernelGGL((k_energy_step<2>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    case 3: hipLaunchKernelGGL((k_energy_step<3>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    case 5: hipLaunchKernelGGL((k_energy_step<5>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    case 7: hipLaunchKernelGGL((k_energy_step<7>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+hipError_t energy_step_fin(BatchDesc* d, int nc, int grid, hipStream_t st) {
+  switch (nc) {
+    case 1: hipLaunchKernelGGL((k_energy_step_fin<1>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    case 2: hipLaunchKernelGGL((k_energy_step_fin<2>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    case 3: hipLaunchKernelGGL((k_energy_step_fin<3>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    case 5: hipLaunchKernelGGL((k_energy_step_fin<5>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    case 7: hipLaunchKernelGGL((k_energy_step_fin<7>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

@@ -485,8 +485,6 @@ pprs_status launch_step(pprs_ctx* c, BatchDesc* d, int nc) {
   size_t lds0 = c->lds_smooth[0], lds1 = c->lds_smooth[1];
   TIMED(TK_PLAN, pprs_k::plan(d, c->stream));
   TIMED(TK_PROLONG, pprs_k::prolong(d, c->grid_prolong, c->stream));
-  TIMED(TK_EVAL, pprs_k::energy(d, 0, 1, c->grid_energy, c->stream));
-  TIMED(TK_FIN, pprs_k::energy_fin(d, 0, 1, kGridFin, c->stream));
   TIMED(TK_GRAD, pprs_k::grad(d, c->tile_grad, c->grid_grad, c->stream));
   if (c->hd.smooth_halo) {
     TIMED(TK_SMW, pprs_k::smooth_win(d, c->hd.smooth_halo, c->grid_smooth, c->stream));
@@ -496,8 +494,9 @@ pprs_status launch_step(pprs_ctx* c, BatchDesc* d, int nc) {
     TIMED(TK_SMX, pprs_k::smooth(d, 1, big, c->grid_smooth, lds1, c->stream));
   }
   TIMED(TK_FIN, pprs_k::smooth_fin(d, kGridFin, c->stream));
-  TIMED(TK_LADDER, pprs_k::energy(d, 1, nc, c->grid_energy, c->stream));
-  TIMED(TK_FIN, pprs_k::energy_fin(d, 1, nc, kGridFin, c->stream));
+  // start energies of the slots that begin a level and the line-search passes, one launch
+  TIMED(TK_LADDER, pprs_k::energy_step(d, nc, c->grid_energy, c->stream));
+  TIMED(TK_FIN, pprs_k::energy_step_fin(d, nc, kGridFin, c->stream));
   return PPRS_OK;
 }
 
@@ -1843,6 +1842,10 @@ pprs_status pprs_get_kernel_timing(pprs_ctx* c, double* ms, long long* launches,
       bytes[k] = wk_of_tk[k] < 0 || c->t_launch[k] == 0
                      ? 0.0 : kBytesPerNode[k] * c->nodes_acc[wk_of_tk[k]];
   }
+  // the field path runs the start energies inside the line-search launches: their bytes
+  // belong to that kind
+  if (bytes && TK_LADDER < cap && c->t_launch[TK_EVAL] == 0 && c->t_launch[TK_LADDER] > 0)
+    bytes[TK_LADDER] += kBytesPerNode[TK_EVAL] * c->nodes_acc[WK_EVAL];
   if (reset) {
     for (int k = 0; k < TK_COUNT; ++k) {
       c->t_ms[k] = 0;
