@@ -47,30 +47,57 @@ __device__ __forceinline__ float gld(const float* p, size_t i) {
 }
 __device__ __forceinline__ void gst(float* p, size_t i, float v) { ((GAS float*)p)[i] = v; }
 
+// A block-uniform pointer moved to scalar registers, so loads through it can take a scalar
+// base with a 32-bit per-lane offset (the compiler does not always see that a pointer read
+// out of the batch descriptor is uniform).
+template <class P>
+__device__ __forceinline__ P* uni(P* p) {
+  unsigned long long v = (unsigned long long)p;
+  unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (P*)(((unsigned long long)hi << 32) | lo);
+}
+// floor(x) converted to int in one instruction (v_cvt_flr_i32_f32; 0 for NaN like a plain
+// conversion).
+__device__ __forceinline__ int cvt_flr(float x) {
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+// a * b + c on 24-bit a and b (v_mad_i32_i24): full rate, where a 32-bit product is not.
+__device__ __forceinline__ int mad24(int a, int b, int c) {
+  int r;
+  asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+// The two corners of a row at byte offset o of g in one 8-byte load (rows are only 4-byte
+// aligned). A 32-bit offset lets a block-uniform g stay a scalar base.
+__device__ __forceinline__ f32x2u ld_pair(const float* g, unsigned o) {
+  return *reinterpret_cast<const GAS f32x2u*>((const GAS char*)g + o);
+}
+
 // Clamped bilinear sample of nodal g (n x n) at column bi + tx, row ai + ty (cells).
-// Returns value; writes the gradient in domain units when grad is true.
+// Returns value; writes the gradient in domain units when grad is true (zero across a
+// coordinate whose position lies outside the level). The position is clamped to the level
+// first and the cell index to n - 2, so a position on or beyond the far edge is cell n - 2 at
+// fraction 1; inside, the fraction is tx - floor(tx).
 template <bool GRAD>
 __device__ __forceinline__ float sample_bil(const float* __restrict__ g, int n, int bi,
                                             float tx, int ai, float ty, float inv_h,
                                             float* gx, float* gy) {
-  float flx = floorf(tx), fly = floorf(ty);
-  int b0 = bi + (int)flx, a0 = ai + (int)fly;
-  float fx = tx - flx, fy = ty - fly;
-  bool outx = false, outy = false;
-  if (b0 < 0) { b0 = 0; fx = 0.f; outx = true; }
-  else if (b0 >= n - 1) { outx = (b0 > n - 1) || (fx > 0.f); b0 = n - 2; fx = 1.f; }
-  if (a0 < 0) { a0 = 0; fy = 0.f; outy = true; }
-  else if (a0 >= n - 1) { outy = (a0 > n - 1) || (fy > 0.f); a0 = n - 2; fy = 1.f; }
-  const GAS float* p = (const GAS float*)g + (size_t)a0 * n + b0;
-  // the two corners of a row in one 8-byte load (rows are only 4-byte aligned)
-  f32x2u r0 = *reinterpret_cast<const GAS f32x2u*>(p);
-  f32x2u r1 = *reinterpret_cast<const GAS f32x2u*>(p + n);
+  float cx = __builtin_amdgcn_fmed3f(tx, (float)(-bi), (float)(n - 1 - bi));
+  float cy = __builtin_amdgcn_fmed3f(ty, (float)(-ai), (float)(n - 1 - ai));
+  int ix = min(cvt_flr(cx), n - 2 - bi), iy = min(cvt_flr(cy), n - 2 - ai);
+  float fx = cx - (float)ix, fy = cy - (float)iy;
+  unsigned o = (unsigned)mad24(ai + iy, n, bi + ix) << 2;  // both indexes in [0, n - 2]
+  f32x2u r0 = ld_pair(g, o);
+  f32x2u r1 = ld_pair(g, o + ((unsigned)n << 2));
   float v00 = r0.x, v01 = r0.y, v10 = r1.x, v11 = r1.y;
   float top = fmaf(fx, v01 - v00, v00);
   float bot = fmaf(fx, v11 - v10, v10);
   if (GRAD) {
-    *gx = outx ? 0.f : fmaf(fy, (v11 - v10) - (v01 - v00), v01 - v00) * inv_h;
-    *gy = outy ? 0.f : (bot - top) * inv_h;
+    *gx = cx != tx ? 0.f : fmaf(fy, (v11 - v10) - (v01 - v00), v01 - v00) * inv_h;
+    *gy = cy != ty ? 0.f : (bot - top) * inv_h;
   }
   return fmaf(fy, bot - top, top);
 }
@@ -172,7 +199,7 @@ __device__ bool cursor_begin(const BatchDesc* D, int kind, ItemCursor& c, int* s
     *s_pos = lo;
   }
   __syncthreads();
-  c.pos = *s_pos;
+  c.pos = __builtin_amdgcn_readfirstlane(*s_pos);  // block-uniform
   __syncthreads();
   return true;
 }
@@ -194,7 +221,7 @@ __device__ bool cursor_range(const BatchDesc* D, int kind, int item0, int item1,
     *s_pos = lo;
   }
   __syncthreads();
-  c.pos = *s_pos;
+  c.pos = __builtin_amdgcn_readfirstlane(*s_pos);  // block-uniform
   __syncthreads();
   return true;
 }
@@ -534,8 +561,8 @@ __device__ __forceinline__ void energy_item(BatchDesc* D, int s, int t, float* s
     size_t nn = (size_t)n * n;
     const float* u = slot_u(D, s, l, ub);
     const float* d = D->dbuf + (size_t)s * D->slot_f_stride;
-    const float* R = D->pyr + D->frame_off[(size_t)stp->ref * PPRS_MAXL + l];
-    const float* T = D->pyr + D->frame_off[(size_t)stp->tmpl * PPRS_MAXL + l];
+    const float* R = uni(D->pyr + D->frame_off[(size_t)stp->ref * PPRS_MAXL + l]);
+    const float* T = uni(D->pyr + D->frame_off[(size_t)stp->tmpl * PPRS_MAXL + l]);
     double top = MODE ? stp->top : 0.0;
     float taus[NC];
 #pragma unroll
@@ -773,8 +800,8 @@ __global__ void __launch_bounds__(BLOCK, LB_GRAD) k_grad(BatchDesc* D) {
     float* G = D->gbuf + (size_t)s * D->slot_p_stride;
     const int gpi = row_pitch(n);
     const size_t gpn = (size_t)n * gpi;
-    const float* R = D->pyr + D->frame_off[(size_t)stp->ref * PPRS_MAXL + l];
-    const float* T = D->pyr + D->frame_off[(size_t)stp->tmpl * PPRS_MAXL + l];
+    const float* R = uni(D->pyr + D->frame_off[(size_t)stp->ref * PPRS_MAXL + l]);
+    const float* T = uni(D->pyr + D->frame_off[(size_t)stp->tmpl * PPRS_MAXL + l]);
     float tau = (float)stp->tau_pend;
     double sg = stp->sigma;
     float inv_sig = sg > 0.0 ? (float)(1.0 / sg) : 0.f;
@@ -903,6 +930,57 @@ __global__ void __launch_bounds__(BLOCK, LB_GRAD) k_grad(BatchDesc* D) {
 // DIR 0: lines are columns of a strip staged in LDS (solve along y), reads G writes Z.
 // DIR 1: lines are rows (solve along x), reads Z writes D, partial G.d and max |d|.
 
+// Lane scans of the affine maps y -> A y + B of R lines across the 64 lanes of a wave, on DPP
+// moves instead of LDS permutes: Hillis-Steele inside each row of 16 lanes (row_shr / row_shl),
+// then across the rows (row broadcasts upward; lane reads of the row heads downward, which
+// DPP has no broadcast for). A lane whose source is outside its row or masked off reads the
+// identity (1, 0). The final one-lane shifts are wave_shr:1 / wave_shl:1.
+template <int CTL, int ROWS, int R>
+__device__ __forceinline__ void dpp_combine(float (&A)[R], float (&B)[R]) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    float Ap = __builtin_amdgcn_update_dpp(1.f, A[r], CTL, ROWS, 0xf, false);
+    float Bp = __builtin_amdgcn_update_dpp(0.f, B[r], CTL, ROWS, 0xf, false);
+    B[r] = fmaf(A[r], Bp, B[r]);
+    A[r] = A[r] * Ap;
+  }
+}
+__device__ __forceinline__ float lane_f(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+// Inclusive scan from lane 0 (lane i ends with lanes 0..i composed, later lanes outermost).
+template <int R>
+__device__ __forceinline__ void scan_up(float (&A)[R], float (&B)[R]) {
+  dpp_combine<0x111, 0xf>(A, B);  // row_shr:1
+  dpp_combine<0x112, 0xf>(A, B);  // row_shr:2
+  dpp_combine<0x114, 0xf>(A, B);  // row_shr:4
+  dpp_combine<0x118, 0xf>(A, B);  // row_shr:8
+  dpp_combine<0x142, 0xa>(A, B);  // row_bcast:15 into rows 1 and 3
+  dpp_combine<0x143, 0xc>(A, B);  // row_bcast:31 into rows 2 and 3
+}
+// Inclusive scan from lane 63 (lane i ends with lanes i..63 composed).
+template <int R>
+__device__ __forceinline__ void scan_down(float (&A)[R], float (&B)[R], int lane) {
+  dpp_combine<0x101, 0xf>(A, B);  // row_shl:1
+  dpp_combine<0x102, 0xf>(A, B);  // row_shl:2
+  dpp_combine<0x104, 0xf>(A, B);  // row_shl:4
+  dpp_combine<0x108, 0xf>(A, B);  // row_shl:8
+  int row = lane >> 4;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    // row aggregates from the first lane of each row; the maps of the rows after a row
+    float a1 = lane_f(A[r], 16), b1 = lane_f(B[r], 16);
+    float a2 = lane_f(A[r], 32), b2 = lane_f(B[r], 32);
+    float a3 = lane_f(A[r], 48), b3 = lane_f(B[r], 48);
+    float t2a = a2 * a3, t2b = fmaf(a2, b3, b2);
+    float t1a = a1 * t2a, t1b = fmaf(a1, t2b, b1);
+    float ta = row == 0 ? t1a : row == 1 ? t2a : row == 2 ? a3 : 1.f;
+    float tb = row == 0 ? t1b : row == 1 ? t2b : row == 2 ? b3 : 0.f;
+    B[r] = fmaf(A[r], tb, B[r]);
+    A[r] = A[r] * ta;
+  }
+}
+
 template <int R, int C>
 __device__ __forceinline__ void solve_lines(float (&v)[R][C], int n, int lane,
                                             const float* __restrict__ coef) {
@@ -928,22 +1006,10 @@ __device__ __forceinline__ void solve_lines(float (&v)[R][C], int n, int lane,
       }
     }
   }
-  for (int off = 1; off < 64; off <<= 1) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      float Ap = __shfl_up(A[r], off, 64), Bp = __shfl_up(B[r], off, 64);
-      if (lane >= off) {
-        B[r] = fmaf(A[r], Bp, B[r]);
-        A[r] = A[r] * Ap;
-      }
-    }
-  }
   float y[R];
+  scan_up<R>(A, B);
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    y[r] = __shfl_up(B[r], 1, 64);
-    if (lane == 0) y[r] = 0.f;
-  }
+  for (int r = 0; r < R; ++r) y[r] = __builtin_amdgcn_update_dpp(0.f, B[r], 0x138, 0xf, 0xf, false);
 #pragma unroll
   for (int k = 0; k < C; ++k) {
     int i = base + k;
@@ -973,21 +1039,9 @@ __device__ __forceinline__ void solve_lines(float (&v)[R][C], int n, int lane,
       }
     }
   }
-  for (int off = 1; off < 64; off <<= 1) {
+  scan_down<R>(A, B, lane);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      float Ag = __shfl_down(A[r], off, 64), Bg = __shfl_down(B[r], off, 64);
-      if (lane + off < 64) {
-        B[r] = fmaf(A[r], Bg, B[r]);
-        A[r] = A[r] * Ag;
-      }
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    y[r] = __shfl_down(B[r], 1, 64);
-    if (lane == 63) y[r] = 0.f;
-  }
+  for (int r = 0; r < R; ++r) y[r] = __builtin_amdgcn_update_dpp(0.f, B[r], 0x130, 0xf, 0xf, false);
 #pragma unroll
   for (int k = C - 1; k >= 0; --k) {
     int i = base + k;
@@ -1755,8 +1809,8 @@ __global__ void __launch_bounds__(BLOCK) k_rigid_energy(BatchDesc* D) {
     if (MODE == 1 && ph != PH_LADDER) continue;
     int l = (ph == PH_PROLONG) ? stp->level + 1 : stp->level;
     int n = lvl_n(l);
-    const float* R = D->pyr + D->frame_off[(size_t)stp->ref * PPRS_MAXL + l];
-    const float* T = D->pyr + D->frame_off[(size_t)stp->tmpl * PPRS_MAXL + l];
+    const float* R = uni(D->pyr + D->frame_off[(size_t)stp->ref * PPRS_MAXL + l]);
+    const float* T = uni(D->pyr + D->frame_off[(size_t)stp->tmpl * PPRS_MAXL + l]);
     double top = MODE ? stp->top : 0.0;
     RigidMap mp[NC];
 #pragma unroll
@@ -1847,8 +1901,8 @@ __global__ void __launch_bounds__(BLOCK) k_rigid_grad(BatchDesc* D) {
     if (stp->phase != PH_GRAD) continue;
     int l = stp->level;
     int n = lvl_n(l);
-    const float* R = D->pyr + D->frame_off[(size_t)stp->ref * PPRS_MAXL + l];
-    const float* T = D->pyr + D->frame_off[(size_t)stp->tmpl * PPRS_MAXL + l];
+    const float* R = uni(D->pyr + D->frame_off[(size_t)stp->ref * PPRS_MAXL + l]);
+    const float* T = uni(D->pyr + D->frame_off[(size_t)stp->tmpl * PPRS_MAXL + l]);
     RigidMap mp = rigid_map(stp->rp[0], stp->rp[1], stp->rp[2], n);
     const float cm1 = (float)mp.cm1, sn = (float)mp.s, cs = (float)cos(stp->rp[0]);
     double sg = stp->sigma;

@@ -304,27 +304,38 @@ def test_line_search_pass_width_does_not_change_results(K):
 
 def test_windowed_metric_solve_matches_exact_line_solves():
     """The one-pass windowed metric solve (halo chosen from beta) against the exact two-pass
-    line solves on the same series: FP32-rounding-level differences, the same decisions on
-    (nearly) every application, and both within the oracle bar of each other."""
+    line solves. The two differ at FP32 rounding. An Armijo comparison that lands within
+    rounding of a tie can go either way, and a flipped decision moves the rest of that
+    application's path (on the 10-frame series below, scanned, the FP64 oracle itself decides
+    3 of 21 applications differently from both FP32 solves). So, on independent applications:
+    the same decisions on all but one, and agreement to 1e-4 px RMS (0.05 px max) wherever
+    the decisions are the same."""
     torch = _torch()
     import paper_1712_02533_amd as P
     s = make_series(SeriesSpec(10, 256, 4.0, 1.0, 10.0, 24))
     frames = torch.tensor(s.frames, device="cuda")
-    params = _gpu_params(3, scan="brent_kung")
-    say("series 10 x 256, exact line solves")
-    ue, _, oe = P.prefix_register_series(frames, params=params, want_op_stats=True)
+    params = _gpu_params(3)
+    ref = np.array(list(range(9)) + [0] * 8, dtype=np.int32)
+    tmpl = np.array(list(range(1, 10)) + list(range(2, 10)), dtype=np.int32)
+    say("17 pairs of 256, exact line solves")
+    ue, oe = P.register_pairs(frames, ref, tmpl, params=params)
     P.set_metric_solve("window")
     try:
-        say("series 10 x 256, windowed metric solve")
-        uw, _, ow = P.prefix_register_series(frames, params=params, want_op_stats=True)
+        say("17 pairs of 256, windowed metric solve")
+        uw, ow = P.register_pairs(frames, ref, tmpl, params=params)
     finally:
         P.set_metric_solve("exact")
-    same = sum(1 for a, b in zip(oe, ow) if a.iters == b.iters)
-    d = (uw - ue).abs()
-    say("  identical decisions on %d of %d applications, max %.2e px" % (same, len(oe),
-                                                                        float(d.max())))
-    assert same >= len(oe) - 1
-    assert float(d.pow(2).mean().sqrt()) < 1e-4 and float(d.max()) < 0.05
+    # the same decisions: the same iterations and line-search passes on every level
+    same = [k for k in range(len(oe))
+            if oe[k].iters == ow[k].iters and oe[k].passes == ow[k].passes]
+    diff = (uw - ue).abs()
+    d = diff.amax(dim=(1, 2, 3)).cpu().numpy()
+    rms = float(diff[same].pow(2).mean().sqrt())
+    say("  identical decisions on %d of %d applications; where identical: max %.2e px, "
+        "RMS %.2e px; elsewhere max %s" % (len(same), len(oe), d[same].max(), rms,
+                                           np.round(np.delete(d, same), 3)))
+    assert len(same) >= len(oe) - 1
+    assert rms < 1e-4 and d[same].max() < 0.05
 
 
 def test_series_batch_equals_each_series_alone():
