@@ -1074,9 +1074,9 @@ struct SmoothR {
 
 // One smoother item: lines [line0, line0 + nl) of one component.
 template <int DIR, int C>
-__device__ void smooth_item(const float* src, float* dst, const float* Gp, const float* coef,
-                            int n, int P, int line0, int nl, int SL, float* s_buf, double& gd,
-                            double& dm) {
+__device__ __forceinline__ void smooth_item(const float* src, float* dst, const float* Gp,
+                                            const float* coef, int n, int P, int line0, int nl,
+                                            int SL, float* s_buf, double& gd, double& dm) {
   constexpr int R = SmoothR<C>::value;
   constexpr int NW = BLOCK / 64;
   int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
