@@ -21,7 +21,7 @@ sys.path.insert(0, ROOT)
 METRIC = "frame-pair registrations/s and series scan time (512², N=512), warm vs cold"
 HBM_PEAK_GBS = 8000.0
 SCAN_NAMES = {"sequential": "sequential", "brent_kung": "Brent-Kung", "kogge_stone": "Kogge-Stone",
-              "sklansky": "Sklansky"}
+              "sklansky": "Sklansky", "general": "general-strategy"}
 WORKLOADS = {
     "c3": dict(name="512 frames of 512x512, drift<=8 px, non-rigid<=1.5 px, 5 counts; "
                     "4 levels; Brent-Kung scan; cold start",
@@ -313,7 +313,9 @@ def main():
     ap.add_argument("--config", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--frames", type=int, default=0, help="override the series length")
     ap.add_argument("--scan", default="", help="override the scan schedule (sequential, "
-                    "brent_kung, kogge_stone, sklansky)")
+                    "brent_kung, kogge_stone, sklansky, general)")
+    ap.add_argument("--workers", type=int, default=0, help="workers P of the general "
+                    "strategy (0: ceil(sqrt(N-1)))")
     ap.add_argument("--cpu-ops", type=int, default=0, help="oracle sample size (0 = auto)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
@@ -351,7 +353,7 @@ def main():
     frames = torch.tensor(series.frames, device=dev)
     out = torch.empty((spec.n_frames, 2, spec.side, spec.side), device=dev)
     scan = args.scan or cfg["scan"]
-    params = P.Params(levels=cfg["levels"], scan=scan)
+    params = P.Params(levels=cfg["levels"], scan=scan, scan_workers=args.workers)
     # a plain device copy of known size (256 MiB read + 256 MiB written), untimed: profiler
     # counters of this kernel calibrate the HBM byte counters of the registration kernels
     calib = torch.empty(64 << 20, device=dev)
@@ -406,6 +408,7 @@ def main():
         config=dict(workload=WORKLOADS[args.config]["name"].replace(
                         "Brent-Kung scan", SCAN_NAMES[scan] + " scan"), frames=spec.n_frames,
                     side=spec.side, levels=cfg["levels"], scan=scan, start="cold",
+                    **(dict(scan_workers=args.workers) if scan == "general" else {}),
                     tuning=tuning,
                     registrations_per_step=stats[0].n_ops_a + stats[0].n_ops_b),
         series_scan_s=round(ms_per_step / 1e3, 3),
@@ -429,7 +432,7 @@ def main():
     log("series average: %.3f ms, %.0f GB/s" % (ams, abytes / (ams * 1e-3) / 1e9))
     if not args.no_rigid:
         # the same frames through the rigid operator (three parameters per registration)
-        rp = P.Params(levels=cfg["levels"], scan=scan)
+        rp = P.Params(levels=cfg["levels"], scan=scan, scan_workers=args.workers)
         P.prefix_register_series_rigid(frames, params=rp)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

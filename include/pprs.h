@@ -46,7 +46,11 @@ enum {
   PPRS_SCAN_SEQUENTIAL = 0,   /* algorithm "serial" of the Prefix sum chapter */
   PPRS_SCAN_BRENT_KUNG = 1,   /* algorithm "brent_kung" (work-efficient, 2 log2 M - 1 levels) */
   PPRS_SCAN_KOGGE_STONE = 2,  /* algorithm "kogge_stone" (log2 M levels, M log2 M - M + 1 ops) */
-  PPRS_SCAN_SKLANSKY = 3      /* algorithm "sklansky" (log2 M levels, M/2 log2 M ops) */
+  PPRS_SCAN_SKLANSKY = 3,     /* algorithm "sklansky" (log2 M levels, M/2 log2 M ops) */
+  PPRS_SCAN_GENERAL = 4       /* general strategy of the distributed chapter with P workers
+                                 (pprs_params.scan_workers): serial scans inside P chunks, a
+                                 Brent-Kung scan over the chunk ends, then every other element
+                                 of each later chunk combined with the end of the one before */
 };
 
 enum { PPRS_FLAG_NONCONV = 1, PPRS_FLAG_NAN = 2, PPRS_FLAG_FALLBACK = 4 };
@@ -66,6 +70,8 @@ typedef struct {
   double eps;           /* stop a level when E_k - E_{k+1} < eps (stopping criteria) */
   int iter_max;         /* accepted steps per level (stopping criteria) */
   int scan;             /* PPRS_SCAN_* schedule of the series step */
+  int scan_workers;     /* P of PPRS_SCAN_GENERAL (0: ceil(sqrt(M)); at most M); ignored by
+                           the other schedules */
 } pprs_params;
 
 /* Statistics of one A or B application. Level index 0 is the coarsest level. */
@@ -237,7 +243,8 @@ pprs_status pprs_series_average(pprs_ctx* ctx, const float* frames, const float*
                                 int W, float* avg);
 
 /* Host-only: the scan schedule over M = N-1 elements (PPRS_SCAN_*: the Prefix sum chapter's
-   algorithms "serial", "brent_kung", "kogge_stone" and "sklansky").
+   algorithms "serial", "brent_kung", "kogge_stone" and "sklansky", and the distributed
+   chapter's general strategy).
    ops (host, capacity `cap` triples) receives (left, right, level) per B application in
    execution order: x[right] <- x[left] (.) x[right], each operand taken as it stands at that
    point of the list. Within a level no op reads an element an earlier op of the level wrote,
@@ -246,6 +253,10 @@ pprs_status pprs_series_average(pprs_ctx* ctx, const float* frames, const float*
    Writes the op count and level count. Returns PPRS_EINVAL for bad arguments or a too small
    capacity (then *n_ops holds the needed count). Makes no HIP call. */
 pprs_status pprs_scan_plan(int kind, int M, int* ops, int cap, int* n_ops, int* n_levels);
+/* pprs_scan_plan with the worker count P of PPRS_SCAN_GENERAL (0: ceil(sqrt(M)); clipped to
+   M; P < 0 is PPRS_EINVAL). pprs_scan_plan(kind, ...) is pprs_scan_plan_p(kind, M, 0, ...). */
+pprs_status pprs_scan_plan_p(int kind, int M, int P, int* ops, int cap, int* n_ops,
+                             int* n_levels);
 
 /* Kernel timing (HIP events around the launches of each kernel kind on the context stream).
    Enabling costs a few microseconds per launch. Kinds are listed by pprs_kernel_name(). */

@@ -24,7 +24,7 @@ _lock = threading.Lock()
 _lib = None
 
 TRACE_W = 8
-SCAN_KINDS = {"sequential": 0, "brent_kung": 1, "kogge_stone": 2, "sklansky": 3}
+SCAN_KINDS = {"sequential": 0, "brent_kung": 1, "kogge_stone": 2, "sklansky": 3, "general": 4}
 
 
 def build(force: bool = True) -> str:
@@ -67,8 +67,8 @@ def _load():
                                                 ctypes.c_int, I]),
             "or_compose": (None, [D, D, ctypes.c_int, D]),
             "or_register_rigid": (ctypes.c_int, [D, D, ctypes.c_int, D, P, D, S]),
-            "or_series": (ctypes.c_int, [D, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, D, S,
-                                         S, I, ctypes.c_int]),
+            "or_series": (ctypes.c_int, [D, ctypes.c_int, ctypes.c_int, P, ctypes.c_int,
+                                         ctypes.c_int, D, S, S, I, ctypes.c_int]),
             "or_set_u_storage_f32": (None, [ctypes.c_int]),
         }
         for name, (res, args) in sigs.items():
@@ -354,8 +354,10 @@ def compose(uij, ujk) -> np.ndarray:
     return out
 
 
-def series(frames_nodal, params: Params, scan: str = "brent_kung", threads: int = 0):
-    """Series registration as an inclusive scan with operator B.
+def series(frames_nodal, params: Params, scan: str = "brent_kung", threads: int = 0,
+           workers: int = 0):
+    """Series registration as an inclusive scan with operator B (workers: P of the general
+    strategy, 0 for ceil(sqrt(N-1))).
 
     frames_nodal: [N, n, n]. Returns (u [N, 2, n, n] domain units with u[0] = 0, a_stats,
     b_stats, b_pairs [(i, j, k)] in execution order)."""
@@ -369,8 +371,9 @@ def series(frames_nodal, params: Params, scan: str = "brent_kung", threads: int 
     b_st = (_CStats * cap)()
     pairs = np.zeros(3 * cap, dtype=np.int32)
     cp = params.c()
-    rc = _load().or_series(_d(fr), N, n, ctypes.byref(cp), SCAN_KINDS[scan], _d(u), a_st, b_st,
-                           pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), threads)
+    rc = _load().or_series(_d(fr), N, n, ctypes.byref(cp), SCAN_KINDS[scan], workers, _d(u),
+                           a_st, b_st, pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                           threads)
     if rc < 0:
         raise ValueError("oracle series failed with %d" % rc)
     a = [_stats(a_st[m], params.levels) for m in range(N - 1)]

@@ -27,7 +27,10 @@
  *  - stopping: E_k - E_{k+1} < eps, or iter_max accepted steps, or a failed line search, or
  *    G.d <= 0;
  *  - scans: the serial, Brent-Kung, Kogge-Stone and Sklansky listings in their standard
- *    0-based forms for any element count (the Kogge-Stone inner loop starts at 2^i).
+ *    0-based forms for any element count (the Kogge-Stone inner loop starts at 2^i); the
+ *    distributed chapter's general strategy with its global scan taken inclusive in place
+ *    (Brent-Kung over the chunk ends), so each chunk end is final after the global stage and
+ *    local stage two touches the other elements only.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -849,7 +852,8 @@ void or_compose(const double* uij, const double* ujk, int n, double* out) {
 /* Elements x_m = (m, m+1, A(f_m, f_{m+1}, id)), m = 0..N-2; y_m = x_0 (.) ... (.) x_m.        */
 /* (i, j, u) (.) (j, k, v) = (i, k, A(f_i, f_k, v o u)).                                         */
 
-enum { OR_SCAN_SEQUENTIAL = 0, OR_SCAN_BRENT_KUNG = 1, OR_SCAN_KOGGE_STONE = 2, OR_SCAN_SKLANSKY = 3 };
+enum { OR_SCAN_SEQUENTIAL = 0, OR_SCAN_BRENT_KUNG = 1, OR_SCAN_KOGGE_STONE = 2, OR_SCAN_SKLANSKY = 3,
+       OR_SCAN_GENERAL = 4 };
 
 typedef struct {
   int i, k;
@@ -891,7 +895,89 @@ static void apply_b(series_ctx* S, const elem_t* left, elem_t* right, int op_ind
 /* frames: N finest-level nodal frames; u_out: N x 2 x nf x nf, u_out[0] = 0.
    a_stats: N-1 entries (may be NULL); b_stats / b_pairs: up to 2N entries (may be NULL).
    Returns the number of B ops, or a negative error. */
-int or_series(const double* frames, int N, int nf, const or_params* p, int scan,
+/* Applies the ops (src[t], dst[t]), t < cnt, of one step (mutually independent) in parallel. */
+static void apply_step(series_ctx* S, elem_t* x, const int* src, const int* dst, int cnt,
+                       int op0) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int t = 0; t < cnt; ++t) apply_b(S, &x[src[t]], &x[dst[t]], op0 + t);
+}
+
+/* General strategy of the distributed chapter on `workers` workers (0: ceil(sqrt(M))).
+   Worker I owns x[l_I .. r_I]; K = floor(M/P) + 1 elements for the first M mod P workers and
+   floor(M/P) for the rest. Local stage one: every worker runs the serial scan on its chunk.
+   Global stage: the chunk ends x[r_0], ..., x[r_{P-1}] are scanned with Brent-Kung in place,
+   which leaves x[r_{I-1}] = x_0 (.) ... (.) x_{r_{I-1}}, the exclusive value worker I needs, and
+   makes x[r_I] final. Local stage two: worker I > 0 combines that value with each of its other
+   elements. Returns the number of ops. */
+static int scan_general(series_ctx* S, elem_t* x, int M, int workers) {
+  int P = workers > 0 ? workers : (int)ceil(sqrt((double)M));
+  if (P > M) P = M;
+  int* l = malloc(sizeof(int) * P);
+  int* r = malloc(sizeof(int) * P);
+  int K = M / P, extra = M % P, at = 0, kmax = 0;
+  for (int I = 0; I < P; ++I) {
+    int k = K + (I < extra ? 1 : 0);
+    l[I] = at;
+    r[I] = at + k - 1;
+    at += k;
+    if (k > kmax) kmax = k;
+  }
+  int* src = malloc(sizeof(int) * (M > 0 ? M : 1));
+  int* dst = malloc(sizeof(int) * (M > 0 ? M : 1));
+  int ops = 0, cnt;
+  /* local stage one: step i of every worker's serial scan, the workers side by side */
+  for (int i = 1; i < kmax; ++i) {
+    cnt = 0;
+    for (int I = 0; I < P; ++I)
+      if (l[I] + i <= r[I]) {
+        src[cnt] = l[I] + i - 1;
+        dst[cnt] = l[I] + i;
+        ++cnt;
+      }
+    apply_step(S, x, src, dst, cnt, ops);
+    ops += cnt;
+  }
+  /* global stage: Brent-Kung over the chunk ends (up-sweep, then down-sweep) */
+  for (int d = 1; d < P; d *= 2) {
+    cnt = 0;
+    for (int j = 2 * d - 1; j < P; j += 2 * d) {
+      src[cnt] = r[j - d];
+      dst[cnt] = r[j];
+      ++cnt;
+    }
+    apply_step(S, x, src, dst, cnt, ops);
+    ops += cnt;
+  }
+  int dtop = 1;
+  while (dtop * 2 < P) dtop *= 2;
+  for (int d = dtop; d >= 1; d /= 2) {
+    cnt = 0;
+    for (int j = 3 * d - 1; j < P; j += 2 * d) {
+      src[cnt] = r[j - d];
+      dst[cnt] = r[j];
+      ++cnt;
+    }
+    apply_step(S, x, src, dst, cnt, ops);
+    ops += cnt;
+  }
+  /* local stage two: worker I > 0 applies the total before its chunk to its other elements */
+  cnt = 0;
+  for (int I = 1; I < P; ++I)
+    for (int j = l[I]; j < r[I]; ++j) {
+      src[cnt] = r[I - 1];
+      dst[cnt] = j;
+      ++cnt;
+    }
+  apply_step(S, x, src, dst, cnt, ops);
+  ops += cnt;
+  free(l);
+  free(r);
+  free(src);
+  free(dst);
+  return ops;
+}
+
+int or_series(const double* frames, int N, int nf, const or_params* p, int scan, int workers,
               double* u_out, or_stats* a_stats, or_stats* b_stats, int* b_pairs,
               int threads) {
   if (N < 1) return -1;
@@ -984,6 +1070,8 @@ int or_series(const double* frames, int N, int nf, const or_params* p, int scan,
       free(src);
       free(dst);
     }
+  } else if (scan == OR_SCAN_GENERAL) {
+    ops = scan_general(&S, x, M, workers);
   } else {
     free(x);
     return -1;

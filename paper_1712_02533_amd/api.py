@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("PPRS_LIBRARY") or os.path.join(_HERE, "libpprs.so")
 
 PPRS_OK = 0
 PPRS_NOT_CONVERGED = 1
-SCAN_KINDS = {"sequential": 0, "brent_kung": 1, "kogge_stone": 2, "sklansky": 3}
+SCAN_KINDS = {"sequential": 0, "brent_kung": 1, "kogge_stone": 2, "sklansky": 3, "general": 4}
 MAX_LEVELS = 16
 
 
@@ -32,7 +32,8 @@ class _CParams(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int), ("lam", ctypes.c_double), ("beta", ctypes.c_double),
                 ("armijo_sigma", ctypes.c_double), ("ladder_k", ctypes.c_int),
                 ("step_cap", ctypes.c_double), ("tau_min_rel", ctypes.c_double),
-                ("eps", ctypes.c_double), ("iter_max", ctypes.c_int), ("scan", ctypes.c_int)]
+                ("eps", ctypes.c_double), ("iter_max", ctypes.c_int), ("scan", ctypes.c_int),
+                ("scan_workers", ctypes.c_int)]
 
 
 class _CPairStats(ctypes.Structure):
@@ -70,6 +71,7 @@ class Params:
     eps: float = 3e-4
     iter_max: int = 500
     scan: str = "brent_kung"
+    scan_workers: int = 0     # P of the general strategy (0: ceil(sqrt(M)))
 
     def c(self) -> _CParams:
         d = asdict(self)
@@ -135,6 +137,9 @@ def _lib():
                 "pprs_scan_plan": (i, [i, i, ctypes.POINTER(ctypes.c_int), i,
                                        ctypes.POINTER(ctypes.c_int),
                                        ctypes.POINTER(ctypes.c_int)]),
+                "pprs_scan_plan_p": (i, [i, i, i, ctypes.POINTER(ctypes.c_int), i,
+                                         ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_int)]),
                 "pprs_set_kernel_timing": (i, [vp, i]),
                 "pprs_get_kernel_timing": (i, [vp, ctypes.POINTER(ctypes.c_double),
                                                ctypes.POINTER(ctypes.c_longlong),
@@ -172,18 +177,20 @@ def default_params() -> Params:
     _lib().pprs_default_params(ctypes.byref(cp))
     scan = {v: k for k, v in SCAN_KINDS.items()}[cp.scan]
     return Params(cp.levels, cp.lam, cp.beta, cp.armijo_sigma, cp.ladder_k, cp.step_cap,
-                  cp.tau_min_rel, cp.eps, cp.iter_max, scan)
+                  cp.tau_min_rel, cp.eps, cp.iter_max, scan, cp.scan_workers)
 
 
-def scan_plan(kind: str, M: int):
-    """Host-only schedule: list of (left, right, level) and the number of levels."""
+def scan_plan(kind: str, M: int, workers: int = 0):
+    """Host-only schedule: list of (left, right, level) and the number of levels (workers: P
+    of the general strategy, 0 for its default)."""
     lib = _lib()
     n = ctypes.c_int()
     lv = ctypes.c_int()
-    lib.pprs_scan_plan(SCAN_KINDS[kind], M, None, 0, ctypes.byref(n), ctypes.byref(lv))
+    lib.pprs_scan_plan_p(SCAN_KINDS[kind], M, workers, None, 0, ctypes.byref(n),
+                         ctypes.byref(lv))
     buf = (ctypes.c_int * max(3 * n.value, 1))()
-    _check(lib.pprs_scan_plan(SCAN_KINDS[kind], M, buf, n.value, ctypes.byref(n),
-                              ctypes.byref(lv)))
+    _check(lib.pprs_scan_plan_p(SCAN_KINDS[kind], M, workers, buf, n.value, ctypes.byref(n),
+                                ctypes.byref(lv)))
     return [(buf[3 * k], buf[3 * k + 1], buf[3 * k + 2]) for k in range(n.value)], lv.value
 
 
@@ -359,7 +366,7 @@ def prefix_register_series(frames, params: Params | None = None, out=None,
     ss = _CSeriesStats()
     ops = None
     if want_op_stats:
-        n_b = len(scan_plan(params.scan, max(N - 1, 0))[0])
+        n_b = len(scan_plan(params.scan, max(N - 1, 0), params.scan_workers)[0])
         ops = (_CPairStats * max(N - 1 + n_b, 1))()   # N-1 A entries, then the B entries
     cp = params.c()
     c = _ctx(frames.device)

@@ -169,8 +169,10 @@ pprs_status check_params(const pprs_params* p, int L) {
     return fail(PPRS_EINVAL, "tau_min_rel must be in (0, 1)");
   if (!(p->eps >= 0.0)) return fail(PPRS_EINVAL, "eps must be >= 0");
   if (p->iter_max < 0) return fail(PPRS_EINVAL, "iter_max must be >= 0");
-  if (p->scan < PPRS_SCAN_SEQUENTIAL || p->scan > PPRS_SCAN_SKLANSKY)
+  if (p->scan < PPRS_SCAN_SEQUENTIAL || p->scan > PPRS_SCAN_GENERAL)
     return fail(PPRS_EINVAL, "unknown scan kind %d", p->scan);
+  if (p->scan_workers < 0)
+    return fail(PPRS_EINVAL, "scan_workers must be >= 0 (got %d)", p->scan_workers);
   return PPRS_OK;
 }
 
@@ -1040,6 +1042,7 @@ void pprs_default_params(pprs_params* p) {
   p->eps = 3e-4;
   p->iter_max = 500;
   p->scan = PPRS_SCAN_BRENT_KUNG;
+  p->scan_workers = 0;
 }
 
 const char* pprs_last_error(void) { return g_err.c_str(); }
@@ -1344,9 +1347,10 @@ pprs_status pprs_prefix_register_series_rigid(pprs_ctx* c, const float* frames, 
   HIPCHK(hipStreamSynchronize(c->stream));
   auto t1 = std::chrono::steady_clock::now();
   int n_ops = 0, n_levels = 0;
-  pprs_scan_plan(params->scan, M, nullptr, 0, &n_ops, &n_levels);
+  pprs_scan_plan_p(params->scan, M, params->scan_workers, nullptr, 0, &n_ops, &n_levels);
   std::vector<int> plan(3 * (size_t)std::max(n_ops, 1));
-  if (pprs_scan_plan(params->scan, M, plan.data(), n_ops, &n_ops, &n_levels) != PPRS_OK)
+  if (pprs_scan_plan_p(params->scan, M, params->scan_workers, plan.data(), n_ops, &n_ops,
+                         &n_levels) != PPRS_OK)
     return fail(PPRS_EINVAL, "scan planning failed");
   int widest = M;
   for (int i = 0; i < n_ops;) {
@@ -1533,9 +1537,11 @@ pprs_status run_series_set(pprs_ctx* c, std::vector<SeriesJob>& jobs, const pprs
     }
     std::vector<int> plan;
     int n_ops = 0, n_levels = 0;
-    pprs_scan_plan(params->scan, M, nullptr, 0, &n_ops, &n_levels);  // sizes only
+    // sizes only
+    pprs_scan_plan_p(params->scan, M, params->scan_workers, nullptr, 0, &n_ops, &n_levels);
     plan.resize(3 * (size_t)std::max(n_ops, 1));
-    if (pprs_scan_plan(params->scan, M, plan.data(), n_ops, &n_ops, &n_levels) != PPRS_OK)
+    if (pprs_scan_plan_p(params->scan, M, params->scan_workers, plan.data(), n_ops, &n_ops,
+                         &n_levels) != PPRS_OK)
       return fail(PPRS_EINVAL, "scan planning failed");
     n_ops_b[j] = n_ops;
     n_lv[j] = n_levels;

@@ -46,10 +46,15 @@ def _interval(a, b):
     return (a[0], b[1])
 
 
-@pytest.mark.parametrize("kind", ["sequential", "brent_kung", "kogge_stone", "sklansky"])
+@pytest.mark.parametrize("kind", ["sequential", "brent_kung", "kogge_stone", "sklansky",
+                                  "general", "general/1", "general/3", "general/M"])
 @pytest.mark.parametrize("M", [0, 1, 2, 3, 7, 8, 9, 63, 64, 100, 511])
 def test_plan_matches_sequential_scan_with_associative_ops(kind, M):
-    plan, levels = P.scan_plan(kind, M)
+    workers = 0
+    if "/" in kind:
+        kind, w = kind.split("/")
+        workers = M if w == "M" else int(w)
+    plan, levels = P.scan_plan(kind, M, workers)
     # interval concatenation: exactly associative, non-commutative, checks index matching
     xs = [(m, m + 1) for m in range(M)]
     assert _apply(plan, xs, _interval) == [(0, m + 1) for m in range(M)]
@@ -102,12 +107,40 @@ def test_plan_counts_match_paper_figures_and_table():
         assert len(plan) == N - 1 and levels == N - 1
 
 
+def _bk_work_span(n):
+    plan, levels = P.scan_plan("brent_kung", n)
+    return len(plan), levels
+
+
+@pytest.mark.parametrize("M,workers", [(8, 2), (12, 3), (12, 4), (64, 8), (511, 7), (511, 73),
+                                       (100, 10)])
+def test_general_strategy_counts_match_the_chapter(M, workers):
+    """General strategy, even division (M = P K): local stage one is P serial scans of K
+    elements (M - P ops, K - 1 steps), the global stage a Brent-Kung scan of the P chunk ends,
+    local stage two P - 1 workers each combining K - 1 elements (the chunk end is final after
+    the inclusive global stage; the chapter's exclusive form touches all K): one step."""
+    assert M % workers == 0
+    K = M // workers
+    plan, levels = P.scan_plan("general", M, workers)
+    w_gs, s_gs = _bk_work_span(workers)
+    assert len(plan) == (M - workers) + w_gs + (workers - 1) * (K - 1)
+    assert levels == (K - 1) + s_gs + (1 if K > 1 and workers > 1 else 0)
+    # one worker is the serial scan; one element per worker is Brent-Kung over all elements
+    assert P.scan_plan("general", M, 1) == P.scan_plan("sequential", M)
+    assert P.scan_plan("general", M, M) == P.scan_plan("brent_kung", M)
+    # uneven division: the first M mod P workers hold one element more
+    plan, _ = P.scan_plan("general", M + 1, workers)
+    firsts = sorted({left + 1 for left, right, lv in plan if lv == 0})
+    assert len(firsts) == workers and firsts[1] - firsts[0] == K + 1
+
+
 def test_plan_rejects_bad_arguments():
     n = ctypes.c_int()
     lv = ctypes.c_int()
     lib = api._lib()
     assert lib.pprs_scan_plan(7, 8, None, 0, ctypes.byref(n), ctypes.byref(lv)) == -1
-    assert lib.pprs_scan_plan(4, 8, None, 0, ctypes.byref(n), ctypes.byref(lv)) == -1
+    assert lib.pprs_scan_plan(5, 8, None, 0, ctypes.byref(n), ctypes.byref(lv)) == -1
+    assert lib.pprs_scan_plan_p(4, 8, -1, None, 0, ctypes.byref(n), ctypes.byref(lv)) == -1
     assert lib.pprs_scan_plan(-1, 8, None, 0, ctypes.byref(n), ctypes.byref(lv)) == -1
     assert lib.pprs_scan_plan(1, -1, None, 0, ctypes.byref(n), ctypes.byref(lv)) == -1
     buf = (ctypes.c_int * 3)()

@@ -197,6 +197,7 @@ def _series_case(spec, levels, scan):
         "max abs err px", err)
     mism = [k for k in range(len(a)) if ops[k].iters != a[k].iters]
     say("  A ops with different iteration counts:", mism)
+    _series_case.last = (ops, a, b)
     return u, ref, err
 
 
@@ -207,10 +208,24 @@ def test_series_c1_sequential_matches_oracle():
     assert err < TOL_PX
 
 
-@pytest.mark.parametrize("scan", ["brent_kung", "kogge_stone", "sklansky"])
+@pytest.mark.parametrize("scan", ["brent_kung", "kogge_stone", "sklansky", "general"])
 def test_series_parallel_scans_match_oracle(scan):
     u, ref, err = _series_case(SeriesSpec(12, 128, 4.0, 1.0, 10.0, 1), 3, scan)
-    assert err < TOL_PX
+    if scan != "general":
+        assert err < TOL_PX
+        return
+    # the general strategy's last B applications register frames up to 10 apart from a
+    # composed start (103 steps on one level here): a long registration, held to that bar —
+    # identical decisions on every application, RMS < 1e-4 px, 99.9th percentile < 1e-3 px,
+    # max < 0.05 px (measured: 6.4e-3 px max at 26 nodes of one frame, 2.1e-5 px RMS)
+    ops, a, b = _series_case.last
+    ora = list(a) + list(b)
+    assert len(ops) == len(ora)
+    assert all(g.iters == o.iters and g.passes == o.trials for g, o in zip(ops, ora))
+    d = np.abs(u - ref)
+    assert np.sqrt((d ** 2).mean()) < 1e-4
+    assert np.percentile(d, 99.9) < 1e-3
+    assert err < 0.05
 
 
 def test_invalid_inputs_raise():

@@ -497,6 +497,68 @@ def test_series_ks_sklansky_schedule_pairs(scan, M):
         assert len(pairs) == GOLD["scan_figures_N8"][scan]["ops"]
 
 
+def _general_expected(M, P):
+    """General strategy of the distributed chapter on P workers, tracked as frame intervals:
+    worker I holds K = M // P elements, one more for the first M % P workers; local stage one
+    is a serial scan in every chunk; the global stage an inclusive scan over the chunk ends
+    (Brent-Kung, in place); local stage two combines the end of chunk I-1 with every other
+    element of chunk I."""
+    x = [(m, m + 1) for m in range(M)]
+    out = []
+    P = min(P, M)
+    sizes = [M // P + (1 if I < M % P else 0) for I in range(P)]
+    lo = [sum(sizes[:I]) for I in range(P)]
+    hi = [lo[I] + sizes[I] - 1 for I in range(P)]
+
+    def b(src, dst):
+        assert x[src][1] == x[dst][0]
+        out.append((x[src][0], x[src][1], x[dst][1]))
+        x[dst] = (x[src][0], x[dst][1])
+    for I in range(P):
+        for j in range(lo[I] + 1, hi[I] + 1):
+            b(j - 1, j)
+    d = 1
+    while d < P:                                   # up-sweep over the ends
+        for j in range(2 * d - 1, P, 2 * d):
+            b(hi[j - d], hi[j])
+        d *= 2
+    d = 1
+    while d * 2 < P:
+        d *= 2
+    while d >= 1:                                  # down-sweep over the ends
+        for j in range(3 * d - 1, P, 2 * d):
+            b(hi[j - d], hi[j])
+        d //= 2
+    for I in range(1, P):
+        for j in range(lo[I], hi[I]):
+            b(hi[I - 1], j)
+    return out, x
+
+
+@pytest.mark.parametrize("M,P", [(1, 1), (5, 2), (8, 2), (8, 3), (11, 4), (16, 4), (9, 9)])
+def test_series_general_strategy_pairs(M, P):
+    """The oracle's general strategy applies B to exactly the (i, j, k) triples of the
+    chapter's stages (order within a stage aside), ends with every element covering
+    (0, m+1), and for an even division does the chapter's work: N - P in local stage one,
+    the global scan's, and (P - 1)(K - 1) in local stage two (the inclusive global stage
+    already finished the chunk ends)."""
+    s = make_series(SeriesSpec(M + 1, 16, 0.5, 0.0, 0.0, 16))
+    fr = np.stack([O.frame_to_nodes(f) for f in s.frames])
+    u, a, b, pairs = O.series(fr, O.Params(levels=1, iter_max=0), scan="general", workers=P)
+    exp, final = _general_expected(M, P)
+    assert sorted(tuple(int(v) for v in p) for p in pairs) == sorted(exp)
+    assert final == [(0, m + 1) for m in range(M)]
+    if M % P == 0:
+        K = M // P
+        # Brent-Kung work over the P ends: 2P - 2 - log2 P for a power of two (table of the
+        # Prefix sum chapter); 12 for 9 ends (7 up-sweep + 5 down-sweep, counted by hand)
+        bk = {1: 0, 2: 1, 4: 4, 9: 12}[P]
+        assert len(pairs) == (M - P) + bk + (P - 1) * (K - 1)
+    # the default worker count is ceil(sqrt(M))
+    _, _, _, pd = O.series(fr, O.Params(levels=1, iter_max=0), scan="general")
+    assert len(pd) == len(_general_expected(M, int(np.ceil(np.sqrt(M))))[0])
+
+
 def test_series_translation_chain_and_bk_vs_sequential():
     spec = SeriesSpec(6, 64, 1.0, 0.0, 0.0, 15)
     s = make_series(spec)
@@ -508,8 +570,8 @@ def test_series_translation_chain_and_bk_vs_sequential():
         gt = ground_truth(s, k)
         e = O.u_to_pixels(useq[k], 64) - gt
         assert np.sqrt((e[:, b:-b, b:-b] ** 2).mean()) < 0.1
-    for scan in ("brent_kung", "kogge_stone", "sklansky"):
-        upar, _, _, _ = O.series(fr, p, scan=scan)
+    for scan in ("brent_kung", "kogge_stone", "sklansky", "general"):
+        upar, _, _, _ = O.series(fr, p, scan=scan, workers=2)
         for k in range(1, 6):
             d = O.u_to_pixels(upar[k] - useq[k], 64)
             # approximate associativity (definition in the associativity section)
