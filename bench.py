@@ -23,16 +23,16 @@ HBM_PEAK_GBS = 8000.0
 SCAN_NAMES = {"sequential": "sequential", "brent_kung": "Brent-Kung", "kogge_stone": "Kogge-Stone",
               "sklansky": "Sklansky", "general": "general-strategy"}
 WORKLOADS = {
-    "c3": dict(name="512 frames of 512x512, drift<=8 px, non-rigid<=1.5 px, 5 counts; "
+    "series512": dict(name="512 frames of 512x512, drift<=8 px, non-rigid<=1.5 px, 5 counts; "
                     "4 levels; Brent-Kung scan; cold start",
-               spec=("c3",)),
-    "c2": dict(name="64 frames of 256x256, drift<=4 px, non-rigid<=1 px, 10 counts; "
-                    "3 levels; Brent-Kung scan; cold start", spec=("c2",)),
-    "c1": dict(name="8 frames of 64x64, drift<=2 px, 20 counts; 2 levels; sequential scan",
-               spec=("c1",)),
+               spec=("series512",)),
+    "series256": dict(name="64 frames of 256x256, drift<=4 px, non-rigid<=1 px, 10 counts; "
+                    "3 levels; Brent-Kung scan; cold start", spec=("series256",)),
+    "tiny64": dict(name="8 frames of 64x64, drift<=2 px, 20 counts; 2 levels; sequential scan",
+               spec=("tiny64",)),
     "paper": dict(name="4096 frames of 1024x1024, drift<=2 px, 10 counts; rigid operator; "
                        "3 levels (the paper's levels 8-10); Brent-Kung scan", spec=None),
-    "c5": dict(name="16 independent series in one run: sides {128,256,512,1024}, 32-512 "
+    "mixed": dict(name="16 independent series in one run: sides {128,256,512,1024}, 32-512 "
                     "frames, drift<=8 px, non-rigid<=1.5 px, 2-20 counts; coarsest level 6; "
                     "Brent-Kung scans; segmented slot pool", spec=None),
 }
@@ -280,7 +280,7 @@ def bench_uneven(args):
         metric=METRIC, value=round(value, 3), unit="registrations/s", n_gpus=1,
         steps=args.steps, warmup=args.warmup, ms_per_step=round(ms, 1), higher_is_better=True,
         scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
-        config=dict(workload=WORKLOADS["c5"]["name"], series=len(frames),
+        config=dict(workload=WORKLOADS["mixed"]["name"], series=len(frames),
                     sides=[int(f.shape[1]) for f in frames],
                     frames=[int(f.shape[0]) for f in frames], levels=levels, start="cold"),
         latency_ms=dict(p50=round(float(np.percentile(lat, 50)), 1),
@@ -310,7 +310,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--config", default="series512", choices=sorted(WORKLOADS))
     ap.add_argument("--frames", type=int, default=0, help="override the series length")
     ap.add_argument("--scan", default="", help="override the scan schedule (sequential, "
                     "brent_kung, kogge_stone, sklansky, general)")
@@ -330,7 +330,7 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    if args.config == "c5":
+    if args.config == "mixed":
         return bench_uneven(args)
     if args.config == "paper":
         return bench_paper_rigid(args)

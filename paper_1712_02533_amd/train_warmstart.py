@@ -41,8 +41,8 @@ def series_specs(n_series, n_frames, seed0, mix):
     from dataclasses import replace
     from synth import CONFIGS, SeriesSpec
     if not mix:
-        base = CONFIGS["c3"]["spec"]
-        return [(replace(base, n_frames=n_frames, seed=seed0 + i), CONFIGS["c3"]["levels"])
+        base = CONFIGS["series512"]["spec"]
+        return [(replace(base, n_frames=n_frames, seed=seed0 + i), CONFIGS["series512"]["levels"])
                 for i in range(n_series)]
     rng = np.random.Generator(np.random.PCG64(seed0))
     out = []

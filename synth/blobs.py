@@ -188,9 +188,9 @@ def ground_truth_pair(series: Series, i: int, k: int, iters: int = 60) -> np.nda
 
 # Workload recipes. Levels are listed finest first; "scan" is the schedule of the series step.
 CONFIGS = {
-    "c1": dict(spec=SeriesSpec(8, 64, 2.0, 0.0, 20.0, 0), levels=2, scan="sequential"),
-    "c2": dict(spec=SeriesSpec(64, 256, 4.0, 1.0, 10.0, 1), levels=3, scan="brent_kung"),
-    "c3": dict(spec=SeriesSpec(512, 512, 8.0, 1.5, 5.0, 2), levels=4, scan="brent_kung"),
+    "tiny64": dict(spec=SeriesSpec(8, 64, 2.0, 0.0, 20.0, 0), levels=2, scan="sequential"),
+    "series256": dict(spec=SeriesSpec(64, 256, 4.0, 1.0, 10.0, 1), levels=3, scan="brent_kung"),
+    "series512": dict(spec=SeriesSpec(512, 512, 8.0, 1.5, 5.0, 2), levels=4, scan="brent_kung"),
 }
 
 

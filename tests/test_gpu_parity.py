@@ -124,7 +124,7 @@ def _check_pair(u, ref, err):
 
 
 @pytest.mark.parametrize("spec,levels", [
-    (CONFIGS["c1"]["spec"], 2),
+    (CONFIGS["tiny64"]["spec"], 2),
     (SeriesSpec(2, 64, 1.5, 0.0, 0.0, 100), 3),
     (SeriesSpec(2, 128, 4.0, 1.0, 10.0, 1), 3),
     (SeriesSpec(2, 256, 4.0, 1.0, 10.0, 1), 3),
@@ -202,7 +202,7 @@ def _series_case(spec, levels, scan):
 
 
 def test_series_c1_sequential_matches_oracle():
-    cfg = CONFIGS["c1"]
+    cfg = CONFIGS["tiny64"]
     u, ref, err = _series_case(cfg["spec"], cfg["levels"], cfg["scan"])
     assert np.all(u[0] == 0)
     assert err < TOL_PX

@@ -76,7 +76,7 @@ def test_rigid_full_size_pair_matches_oracle():
     torch = _torch()
     import paper_1712_02533_amd as P
     from dataclasses import replace
-    spec = replace(CONFIGS["c3"]["spec"], n_frames=2)
+    spec = replace(CONFIGS["series512"]["spec"], n_frames=2)
     s = make_series(spec)
     frames = torch.tensor(s.frames, device="cuda")
     say("512 x 512 pair, 4 levels")

@@ -40,7 +40,7 @@ def case():
     torch = _torch()
     import paper_1712_02533_amd as P
     from dataclasses import replace
-    spec = replace(CONFIGS["c3"]["spec"], n_frames=48, seed=150)  # not a training seed
+    spec = replace(CONFIGS["series512"]["spec"], n_frames=48, seed=150)  # not a training seed
     s = make_series(spec, workers=8)
     frames = torch.tensor(s.frames, device="cuda")
     net = P.WarmStartNet()
