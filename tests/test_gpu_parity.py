@@ -369,7 +369,8 @@ def test_windowed_metric_solve_matches_exact_line_solves():
     assert rms < 1e-4 and d[same].max() < 0.05
 
 
-def test_series_batch_equals_each_series_alone():
+@pytest.mark.parametrize("scan,workers", [("brent_kung", 0), ("general", 3)])
+def test_series_batch_equals_each_series_alone(scan, workers):
     """Segmented run: three series of different sides and level counts in one slot pool give
     each series' single-series result bit for bit (no op depends on what ran beside it)."""
     torch = _torch()
@@ -377,13 +378,14 @@ def test_series_batch_equals_each_series_alone():
     specs = [(SeriesSpec(9, 64, 2.0, 0.0, 20.0, 31), 2), (SeriesSpec(7, 128, 4.0, 1.0, 10.0, 32), 3),
              (SeriesSpec(6, 256, 4.0, 1.0, 10.0, 33), 3)]
     frames = [torch.tensor(make_series(sp).frames, device="cuda") for sp, _ in specs]
-    params = _gpu_params(3, scan="brent_kung")
+    params = _gpu_params(3, scan=scan, scan_workers=workers)
     levels = [lv for _, lv in specs]
-    say("series batch of sides 64, 128, 256")
+    say("series batch of sides 64, 128, 256,", scan, workers)
     outs, stats, lat = P.register_series_batch(frames, params=params, levels=levels)
     say("  latencies ms", ["%.1f" % x for x in lat])
     for f, lv, u, st in zip(frames, levels, outs, stats):
-        alone, st1, _ = P.prefix_register_series(f, params=_gpu_params(lv, scan="brent_kung"))
+        alone, st1, _ = P.prefix_register_series(f, params=_gpu_params(lv, scan=scan,
+                                                                       scan_workers=workers))
         assert torch.equal(u, alone)
         assert st.n_ops_a == st1.n_ops_a and st.n_ops_b == st1.n_ops_b
         assert st.node_steps == st1.node_steps
