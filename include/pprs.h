@@ -179,7 +179,7 @@ pprs_status pprs_prefix_register_series(pprs_ctx* ctx, const float* frames, int 
    registrations and every B application) run in one pool of `slots` concurrent registrations
    (0 = 512). An application starts as soon as the applications producing its two inputs have
    finished and a slot is free (in schedule order); the host retires finished registrations and
-   starts new ones every `group_steps` steps (0 = 8). Results do not depend on either value.
+   starts new ones every `group_steps` steps (0 = 16). Results do not depend on either value.
    Returns PPRS_EINVAL for values out of range (slots > 65536, group_steps > 1024). */
 pprs_status pprs_set_pool(pprs_ctx* ctx, int slots, int group_steps);
 
@@ -199,10 +199,10 @@ pprs_status pprs_set_metric_solve(pprs_ctx* ctx, int mode);
    candidates and keeps the fastest. */
 typedef struct {
   int pool_slots;    /* concurrent registrations of a series (default 512, at most 65536) */
-  int pool_group;    /* steps between polls of the slot pool (default 8, at most 1024) */
+  int pool_group;    /* steps between polls of the slot pool (default 16, at most 1024) */
   int grid_energy;   /* workgroups of the energy kernels (default 2048) */
   int grid_grad;     /* workgroups of the gradient kernel (default 2048) */
-  int grid_smooth;   /* workgroups of the metric-solve kernels (default 1024) */
+  int grid_smooth;   /* workgroups of the metric-solve kernels (default 2048) */
   int grid_prolong;  /* workgroups of the prolongation kernel (default 2048) */
   int tile_grad;     /* gradient tile shape: 0 = 32x16 (default), 1 = 64x8, 2 = 128x4,
                         3 = 64x16 nodes */

@@ -103,10 +103,10 @@ struct pprs_ctx {
   DevBuf cnn_in, cnn_out, tmp, badflags, warm_stage;
   // slot pool: per-round index lists and staged slot states
   DevBuf pool_idx, pool_off, pool_states;
-  int pool_group = 8;    // steps between polls of the slot pool
+  int pool_group = 16;   // steps between polls of the slot pool
   int pool_slots = 512;  // concurrent registrations of a series
   // workgroups of the per-step item kernels (results do not depend on them)
-  int grid_energy = 2048, grid_grad = 2048, grid_smooth = 1024, grid_prolong = 2048;
+  int grid_energy = 2048, grid_grad = 2048, grid_smooth = 2048, grid_prolong = 2048;
   bool smooth_window = false;  // windowed one-pass metric solve (opt-in, where beta allows)
   int tile_grad = 0;          // gradient kernel tile shape (pprs_k::grad_tile variant)
   int ladder_rungs = 0;       // step sizes per line-search pass (0: 2K+1)
@@ -1728,10 +1728,10 @@ pprs_status pprs_set_tuning(pprs_ctx* c, const pprs_tuning* t) {
   for (int k = 0; k < 8; ++k)
     if (v[k] < 0 || v[k] > hi[k]) return fail(PPRS_EINVAL, "tuning value %d out of range", k);
   c->pool_slots = t->pool_slots ? t->pool_slots : 512;
-  c->pool_group = t->pool_group ? t->pool_group : 8;
+  c->pool_group = t->pool_group ? t->pool_group : 16;
   c->grid_energy = t->grid_energy ? t->grid_energy : 2048;
   c->grid_grad = t->grid_grad ? t->grid_grad : 2048;
-  c->grid_smooth = t->grid_smooth ? t->grid_smooth : 1024;
+  c->grid_smooth = t->grid_smooth ? t->grid_smooth : 2048;
   c->grid_prolong = t->grid_prolong ? t->grid_prolong : 2048;
   c->tile_grad = t->tile_grad;
   if (t->smooth_lines != 0 && t->smooth_lines != 8 && t->smooth_lines != 16 &&
@@ -1749,7 +1749,7 @@ pprs_status pprs_set_pool(pprs_ctx* c, int slots, int group_steps) {
   if (slots < 0 || group_steps < 0 || slots > 65536 || group_steps > 1024)
     return fail(PPRS_EINVAL, "slots must be in [0, 65536] and group_steps in [0, 1024]");
   c->pool_slots = slots ? slots : 512;
-  c->pool_group = group_steps ? group_steps : 8;
+  c->pool_group = group_steps ? group_steps : 16;
   return PPRS_OK;
 }
 
