@@ -200,9 +200,9 @@ pprs_status pprs_set_metric_solve(pprs_ctx* ctx, int mode);
 typedef struct {
   int pool_slots;    /* concurrent registrations of a series (default 512, at most 65536) */
   int pool_group;    /* steps between polls of the slot pool (default 16, at most 1024) */
-  int grid_energy;   /* workgroups of the energy kernels (default 2048) */
-  int grid_grad;     /* workgroups of the gradient kernel (default 2048) */
-  int grid_smooth;   /* workgroups of the metric-solve kernels (default 2048) */
+  int grid_energy;   /* workgroups of the energy kernels (default 8192) */
+  int grid_grad;     /* workgroups of the gradient kernel (default 8192) */
+  int grid_smooth;   /* workgroups of the metric-solve kernels (default 8192) */
   int grid_prolong;  /* workgroups of the prolongation kernel (default 2048) */
   int tile_grad;     /* gradient tile shape: 0 = 32x16 (default), 1 = 64x8, 2 = 128x4,
                         3 = 64x16 nodes */

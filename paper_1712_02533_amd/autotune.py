@@ -19,10 +19,10 @@ CANDIDATES = {
     "ladder_rungs": [2, 1],
     "tile_grad": [1, 2, 3, 0],
     "smooth_lines": [32, 8, 16],
-    "pool_group": [4, 8, 16, 32],
-    "grid_grad": [1024, 2048, 4096],
-    "grid_energy": [1024, 2048, 4096],
-    "grid_smooth": [512, 1024, 2048],
+    "pool_group": [16, 32, 8],
+    "grid_grad": [8192, 4096, 2048],
+    "grid_energy": [8192, 16384, 4096],
+    "grid_smooth": [8192, 16384, 4096],
     "pool_slots": [256, 512, 1024],
     "grid_prolong": [1024, 2048],
 }

@@ -106,7 +106,7 @@ struct pprs_ctx {
   int pool_group = 16;   // steps between polls of the slot pool
   int pool_slots = 512;  // concurrent registrations of a series
   // workgroups of the per-step item kernels (results do not depend on them)
-  int grid_energy = 2048, grid_grad = 2048, grid_smooth = 2048, grid_prolong = 2048;
+  int grid_energy = 8192, grid_grad = 8192, grid_smooth = 8192, grid_prolong = 2048;
   bool smooth_window = false;  // windowed one-pass metric solve (opt-in, where beta allows)
   int tile_grad = 0;          // gradient kernel tile shape (pprs_k::grad_tile variant)
   int ladder_rungs = 0;       // step sizes per line-search pass (0: 2K+1)
@@ -1729,9 +1729,9 @@ pprs_status pprs_set_tuning(pprs_ctx* c, const pprs_tuning* t) {
     if (v[k] < 0 || v[k] > hi[k]) return fail(PPRS_EINVAL, "tuning value %d out of range", k);
   c->pool_slots = t->pool_slots ? t->pool_slots : 512;
   c->pool_group = t->pool_group ? t->pool_group : 16;
-  c->grid_energy = t->grid_energy ? t->grid_energy : 2048;
-  c->grid_grad = t->grid_grad ? t->grid_grad : 2048;
-  c->grid_smooth = t->grid_smooth ? t->grid_smooth : 2048;
+  c->grid_energy = t->grid_energy ? t->grid_energy : 8192;
+  c->grid_grad = t->grid_grad ? t->grid_grad : 8192;
+  c->grid_smooth = t->grid_smooth ? t->grid_smooth : 8192;
   c->grid_prolong = t->grid_prolong ? t->grid_prolong : 2048;
   c->tile_grad = t->tile_grad;
   if (t->smooth_lines != 0 && t->smooth_lines != 8 && t->smooth_lines != 16 &&
