@@ -108,7 +108,7 @@ struct pprs_ctx {
   // workgroups of the per-step item kernels (results do not depend on them)
   int grid_energy = 8192, grid_grad = 8192, grid_smooth = 8192, grid_prolong = 2048;
   bool smooth_window = false;  // windowed one-pass metric solve (opt-in, where beta allows)
-  int tile_grad = 0;          // gradient kernel tile shape (pprs_k::grad_tile variant)
+  int tile_grad = 0;          // gradient tile setting (grad_variant maps it to the kernel's)
   int ladder_rungs = 0;       // step sizes per line-search pass (0: 2K+1)
   int smooth_lines = 16;      // column-strip width of the line solves (8, 16 or 32)
   size_t lds_smooth[2] = {0, 0};
@@ -212,11 +212,15 @@ size_t smooth_lds_bytes(const BatchDesc& hd, int dir) {
   return mx * sizeof(float);
 }
 
+// Gradient kernel variant of a tile_grad setting: 0 (default) = 64x16, 4 = 32x16; 1, 2 and 3
+// are the kernel's own variants (64x8, 128x4, 64x16).
+int grad_variant(int tile_grad) { return tile_grad == 0 ? 3 : tile_grad == 4 ? 0 : tile_grad; }
+
 // Per-run geometry from the launch shape (before each batch is uploaded): gradient tiles of
 // the chosen tile shape, column-strip width of the line solves (LDS permitting).
 pprs_status set_grad_tiles(pprs_ctx* c) {
   int tx, ty;
-  pprs_k::grad_tile(c->tile_grad, &tx, &ty);
+  pprs_k::grad_tile(grad_variant(c->tile_grad), &tx, &ty);
   BatchDesc& hd = c->hd;
   for (int l = hd.coarsest; l <= hd.finest; ++l) {
     int n = level_n(l);
@@ -487,7 +491,7 @@ pprs_status launch_step(pprs_ctx* c, BatchDesc* d, int nc) {
   size_t lds0 = c->lds_smooth[0], lds1 = c->lds_smooth[1];
   TIMED(TK_PLAN, pprs_k::plan(d, c->stream));
   TIMED(TK_PROLONG, pprs_k::prolong(d, c->grid_prolong, c->stream));
-  TIMED(TK_GRAD, pprs_k::grad(d, c->tile_grad, c->grid_grad, c->stream));
+  TIMED(TK_GRAD, pprs_k::grad(d, grad_variant(c->tile_grad), c->grid_grad, c->stream));
   if (c->hd.smooth_halo) {
     TIMED(TK_SMW, pprs_k::smooth_win(d, c->hd.smooth_halo, c->grid_smooth, c->stream));
   } else {
@@ -1724,7 +1728,7 @@ pprs_status pprs_set_tuning(pprs_ctx* c, const pprs_tuning* t) {
   if (!c || !t) return fail(PPRS_EINVAL, "NULL argument");
   const int v[8] = {t->pool_slots, t->pool_group, t->grid_energy, t->grid_grad, t->grid_smooth,
                     t->grid_prolong, t->tile_grad, t->smooth_lines};
-  const int hi[8] = {65536, 1024, 65536, 65536, 65536, 65536, 3, 32};
+  const int hi[8] = {65536, 1024, 65536, 65536, 65536, 65536, 4, 32};
   for (int k = 0; k < 8; ++k)
     if (v[k] < 0 || v[k] > hi[k]) return fail(PPRS_EINVAL, "tuning value %d out of range", k);
   c->pool_slots = t->pool_slots ? t->pool_slots : 512;
