@@ -63,12 +63,17 @@ def _load():
             "or_gradient_flow": (ctypes.c_int, [D, D, ctypes.c_int, D, P, I, I, D, D,
                                                 ctypes.c_int, I]),
             "or_register": (ctypes.c_int, [D, D, ctypes.c_int, D, P, D, S, D, ctypes.c_int, I]),
+            "or_register_f": (ctypes.c_int, [D, D, ctypes.c_int, D, P, I, D, S, D,
+                                             ctypes.c_int, I]),
             "or_register_from": (ctypes.c_int, [D, D, ctypes.c_int, ctypes.c_int, D, P, D, S, D,
                                                 ctypes.c_int, I]),
             "or_compose": (None, [D, D, ctypes.c_int, D]),
             "or_register_rigid": (ctypes.c_int, [D, D, ctypes.c_int, D, P, D, S]),
+            "or_register_rigid_f": (ctypes.c_int, [D, D, ctypes.c_int, D, P, I, D, S]),
             "or_series": (ctypes.c_int, [D, ctypes.c_int, ctypes.c_int, P, ctypes.c_int,
                                          ctypes.c_int, D, S, S, I, ctypes.c_int]),
+            "or_series_f": (ctypes.c_int, [D, ctypes.c_int, ctypes.c_int, P, ctypes.c_int,
+                                           ctypes.c_int, I, I, D, S, S, I, ctypes.c_int]),
             "or_set_u_storage_f32": (None, [ctypes.c_int]),
         }
         for name, (res, args) in sigs.items():
@@ -88,7 +93,8 @@ class _CParams(ctypes.Structure):
 
 class _CStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int * 16), ("trials", ctypes.c_int * 16),
-                ("energy", ctypes.c_double), ("ncc", ctypes.c_double), ("flags", ctypes.c_int)]
+                ("energy", ctypes.c_double), ("ncc", ctypes.c_double), ("flags", ctypes.c_int),
+                ("tie_gap", ctypes.c_double)]
 
 
 @dataclass
@@ -219,16 +225,45 @@ class RegStats:
     energy: float
     ncc: float
     flags: int
+    tie_gap: float = 0.0   # replayed decisions only: largest distance of the energy test
+                           # from deciding a replayed step the other way
+
+
+def _force(force, rows: int = 1):
+    """Replayed stopping decisions: `rows` lists of accepted-step counts per level (coarsest
+    first; None or -1 where the energy-decrease test decides) -> int32 [rows][16], or None."""
+    if force is None:
+        return None
+    if rows == 1:
+        force = [force]
+    if len(force) != rows:
+        raise ValueError("need %d lists of replayed step counts" % rows)
+    out = np.full((rows, 16), -1, dtype=np.int32)
+    for r, lst in enumerate(force):
+        if lst is None:
+            continue
+        if len(lst) > 16:
+            raise ValueError("at most 16 levels")
+        out[r, :len(lst)] = [-1 if v is None else int(v) for v in lst]
+    return out
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int)) if a is not None else None
 
 
 def _stats(st: _CStats, levels: int) -> RegStats:
     return RegStats(list(st.iters[:levels]), list(st.trials[:levels]), st.energy, st.ncc,
-                    st.flags)
+                    st.flags, st.tie_gap)
 
 
-def register(R, T, params: Params, u0=None, trace_cap: int = 0):
+def register(R, T, params: Params, u0=None, trace_cap: int = 0, force=None):
     """Operator A on finest-level nodal frames. Returns (u [2,n,n] domain units, RegStats,
-    trace)."""
+    trace).
+
+    force (test switch): accepted-step counts per level, coarsest first; a level with a count
+    takes exactly that many steps (unless its line search fails first) instead of stopping by
+    the energy-decrease test. It replays stopping decisions another implementation took."""
     R, T = _f64(R), _f64(T)
     n = R.shape[-1]
     u = np.empty((2, n, n))
@@ -240,8 +275,9 @@ def register(R, T, params: Params, u0=None, trace_cap: int = 0):
     keep = _f64(u0) if u0 is not None else None
     if keep is not None:
         u0p = _d(keep)
-    rc = _load().or_register(_d(R), _d(T), n, u0p, ctypes.byref(cp), _d(u), ctypes.byref(st),
-                             _d(tr), trace_cap, ctypes.byref(tl))
+    fo = _force(force)
+    rc = _load().or_register_f(_d(R), _d(T), n, u0p, ctypes.byref(cp), _ip(fo), _d(u),
+                               ctypes.byref(st), _d(tr), trace_cap, ctypes.byref(tl))
     if rc == -1:
         raise ValueError("constant reference on some level")
     if rc != 0:
@@ -271,17 +307,19 @@ def register_from(R, T, start: int, u_start, params: Params, trace_cap: int = 0)
     return u, _stats(st, params.levels), tr[: tl.value]
 
 
-def register_rigid(R, T, params: Params, p_init=None):
+def register_rigid(R, T, params: Params, p_init=None, force=None):
     """Rigid variant of A on finest-level nodal frames: phi(x) = R(alpha) x + t about the domain
-    origin. Returns (p = [alpha, t0, t1] in radians and domain units, RegStats)."""
+    origin. Returns (p = [alpha, t0, t1] in radians and domain units, RegStats). force: as for
+    register()."""
     R, T = _f64(R), _f64(T)
     n = R.shape[-1]
     out = np.zeros(3)
     st = _CStats()
     cp = params.c()
     pin = _f64(np.asarray(p_init, dtype=np.float64)) if p_init is not None else None
-    rc = _load().or_register_rigid(_d(R), _d(T), n, _d(pin) if pin is not None else None,
-                                   ctypes.byref(cp), _d(out), ctypes.byref(st))
+    fo = _force(force)
+    rc = _load().or_register_rigid_f(_d(R), _d(T), n, _d(pin) if pin is not None else None,
+                                     ctypes.byref(cp), _ip(fo), _d(out), ctypes.byref(st))
     if rc == -1:
         raise ValueError("constant reference on some level")
     if rc != 0:
@@ -296,26 +334,34 @@ def _compose_rigid(u, v):
     return np.array([u[0] + v[0], c * u[1] - s * u[2] + v[1], s * u[1] + c * u[2] + v[2]])
 
 
-def series_rigid(frames_nodal, params: Params, scan: str = "brent_kung"):
+def series_rigid(frames_nodal, params: Params, scan: str = "brent_kung", force_a=None,
+                 force_b=None):
     """Series registration with the rigid operator (definition of image series registration):
     N-1 neighbour registrations, then the scan with B = rigid registration started from the
     composition of the operands' maps. Schedules: "sequential" and "brent_kung" (Prefix sum
     chapter; the standard 0-based Brent-Kung form for any element count). Returns p [N, 3]
-    (phi_0i; alpha in radians, t in domain units; p[0] = 0)."""
+    (phi_0i; alpha in radians, t in domain units; p[0] = 0). force_a / force_b: replayed
+    step counts (see register()) per neighbour registration / per B application in schedule
+    order."""
     fr = _f64(frames_nodal)
     N = fr.shape[0]
     M = N - 1
     out = np.zeros((N, 3))
     if M < 1:
         return out
-    el = [[m, m + 1, register_rigid(fr[m], fr[m + 1], params)[0]] for m in range(M)]
+    el = [[m, m + 1, register_rigid(fr[m], fr[m + 1], params,
+                                    force=force_a[m] if force_a is not None else None)[0]]
+          for m in range(M)]
+    nb = [0]
 
     def apply(a, b):
         ia, ka, pa = el[a]
         ib, kb, pb = el[b]
         assert ka == ib
+        fb = force_b[nb[0]] if force_b is not None else None
+        nb[0] += 1
         el[b] = [ia, kb, register_rigid(fr[ia], fr[kb], params,
-                                        p_init=_compose_rigid(pa, pb))[0]]
+                                        p_init=_compose_rigid(pa, pb), force=fb)[0]]
 
     if scan == "sequential":
         for m in range(1, M):
@@ -355,9 +401,10 @@ def compose(uij, ujk) -> np.ndarray:
 
 
 def series(frames_nodal, params: Params, scan: str = "brent_kung", threads: int = 0,
-           workers: int = 0):
+           workers: int = 0, force_a=None, force_b=None):
     """Series registration as an inclusive scan with operator B (workers: P of the general
-    strategy, 0 for ceil(sqrt(N-1))).
+    strategy, 0 for ceil(sqrt(N-1))). force_a (N-1 lists) and force_b (one list per B
+    application in schedule order): replayed step counts, see register().
 
     frames_nodal: [N, n, n]. Returns (u [N, 2, n, n] domain units with u[0] = 0, a_stats,
     b_stats, b_pairs [(i, j, k)] in execution order)."""
@@ -371,9 +418,16 @@ def series(frames_nodal, params: Params, scan: str = "brent_kung", threads: int 
     b_st = (_CStats * cap)()
     pairs = np.zeros(3 * cap, dtype=np.int32)
     cp = params.c()
-    rc = _load().or_series(_d(fr), N, n, ctypes.byref(cp), SCAN_KINDS[scan], workers, _d(u),
-                           a_st, b_st, pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
-                           threads)
+    fa = _force(force_a, N - 1) if force_a is not None else None
+    fb = None
+    if force_b is not None:
+        fb = np.full((cap, 16), -1, dtype=np.int32)
+        if len(force_b) > cap:
+            raise ValueError("too many B lists")
+        fb[:len(force_b)] = _force(force_b, len(force_b))
+    rc = _load().or_series_f(_d(fr), N, n, ctypes.byref(cp), SCAN_KINDS[scan], workers,
+                             _ip(fa), _ip(fb), _d(u), a_st, b_st,
+                             pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), threads)
     if rc < 0:
         raise ValueError("oracle series failed with %d" % rc)
     a = [_stats(a_st[m], params.levels) for m in range(N - 1)]

@@ -58,6 +58,9 @@ typedef struct {
   double energy;              /* final energy at the finest level */
   double ncc;                 /* final NCC at the finest level */
   int flags;                  /* OR_FLAG_* */
+  double tie_gap;             /* with replayed stopping decisions: the largest distance by which
+                                 the energy test would have decided a replayed step the other way
+                                 (0 when every replayed decision agrees with the test) */
 } or_stats;
 
 enum { OR_FLAG_NONCONV = 1, OR_FLAG_NAN = 2 };
@@ -460,9 +463,13 @@ static void trace_put(trace_t* tr, int level, int step, double tau, double e0, d
   tr->len++;
 }
 
+/* force >= 0 is a test switch: the level takes exactly `force` accepted steps (unless the
+   line search fails or the flow is stationary first) and the energy-decrease test is not
+   applied. It lets a test replay the stopping decisions another implementation took where a
+   decrease lies so close to eps that rounding decides it; -1 is the method itself. */
 static int gradient_flow(const level_data* L, double* u, const or_params* p, int level,
-                         int* trials, int* flags, double* e_out, double* ncc_out,
-                         trace_t* tr) {
+                         int force, int* trials, int* flags, double* e_out, double* ncc_out,
+                         double* gap, trace_t* tr) {
   int n = L->n;
   size_t nn = (size_t)n * n;
   double h = 1.0 / (n - 1);
@@ -515,7 +522,11 @@ static int gradient_flow(const level_data* L, double* u, const or_params* p, int
     ncc = ncc_acc;
     tau_prev = tau_acc;
     steps++;
-    if (dec < p->eps) break;                              /* converged */
+    if (force >= 0 && gap) { /* how far the energy test is from the replayed decision */
+      if (steps < force) *gap = fmax(*gap, p->eps - dec);
+      else if (steps < p->iter_max) *gap = fmax(*gap, dec - p->eps);
+    }
+    if (force >= 0 ? steps >= force : dec < p->eps) break; /* converged (or replayed stop) */
     if (steps >= p->iter_max) *flags |= OR_FLAG_NONCONV;
   }
   if (trials) *trials = passes_total;
@@ -540,7 +551,7 @@ int or_gradient_flow(const double* R, const double* T, int n, double* u, const o
   level_data L = {n, Rn, T};
   trace_t tr = {trace, trace_cap, 0};
   int flags = 0;
-  int s = gradient_flow(&L, u, p, 0, passes, &flags, energy, NULL, &tr);
+  int s = gradient_flow(&L, u, p, 0, -1, passes, &flags, energy, NULL, NULL, &tr);
   if (steps) *steps = s;
   if (trace_len) *trace_len = tr.len;
   free(Rn);
@@ -601,18 +612,19 @@ static void pyramid_free(pyramid_t* py) {
 /* Gradient flow on levels start..L from the guess u (level `start`, owned: freed here), each
    result prolongated as the next level's start. Statistics are indexed from level m0. */
 static void run_levels(const pyramid_t* py, int start, double* u, const or_params* p,
-                       double* u_out, or_stats* st, double* trace, int trace_cap,
-                       int* trace_len) {
+                       const int* force, double* u_out, or_stats* st, double* trace,
+                       int trace_cap, int* trace_len) {
   int L = py->L, m0 = py->m0, nf = (1 << L) + 1;
   trace_t tr = {trace, trace_cap, 0};
   if (st) memset(st, 0, sizeof(*st));
   int flags = 0;
-  double e = 0.0, ncc = 0.0;
+  double e = 0.0, ncc = 0.0, gap = 0.0;
   for (int l = start; l <= L; ++l) {
     int n = (1 << l) + 1;
     level_data LD = {n, py->Rn[l], py->Tl[l]};
     int passes = 0;
-    int steps = gradient_flow(&LD, u, p, l, &passes, &flags, &e, &ncc, &tr);
+    int steps = gradient_flow(&LD, u, p, l, force ? force[l - m0] : -1, &passes, &flags, &e,
+                              &ncc, &gap, &tr);
     if (st) {
       st->iters[l - m0] = steps;
       st->trials[l - m0] = passes;
@@ -632,12 +644,16 @@ static void run_levels(const pyramid_t* py, int start, double* u, const or_param
     st->energy = e;
     st->ncc = ncc;
     st->flags = flags;
+    st->tie_gap = gap;
   }
   if (trace_len) *trace_len = tr.len;
 }
 
-int or_register(const double* R, const double* T, int nf, const double* u0, const or_params* p,
-                double* u_out, or_stats* st, double* trace, int trace_cap, int* trace_len) {
+/* force (may be NULL): per level from m0, the number of accepted steps to take instead of
+   applying the energy-decrease stopping test (-1: the test applies); see gradient_flow. */
+int or_register_f(const double* R, const double* T, int nf, const double* u0,
+                  const or_params* p, const int* force, double* u_out, or_stats* st,
+                  double* trace, int trace_cap, int* trace_len) {
   int L = log2_exact(nf - 1);
   if (L < 1 || p->levels < 1 || p->levels > L || p->levels > OR_MAX_LEVELS) return -2;
   int m0 = L - p->levels + 1;
@@ -663,10 +679,15 @@ int or_register(const double* R, const double* T, int nf, const double* u0, cons
       memcpy(u, cur, sizeof(double) * 2 * n0 * n0);
       free(cur);
     }
-    run_levels(&py, m0, u, p, u_out, st, trace, trace_cap, trace_len);
+    run_levels(&py, m0, u, p, force, u_out, st, trace, trace_cap, trace_len);
   }
   pyramid_free(&py);
   return rc;
+}
+
+int or_register(const double* R, const double* T, int nf, const double* u0, const or_params* p,
+                double* u_out, or_stats* st, double* trace, int trace_cap, int* trace_len) {
+  return or_register_f(R, T, nf, u0, p, NULL, u_out, st, trace, trace_cap, trace_len);
 }
 
 /* Function A started on level `start` (m0 <= start <= L) from the guess u_start given on that
@@ -685,7 +706,7 @@ int or_register_from(const double* R, const double* T, int nf, int start,
     int ns = (1 << start) + 1;
     double* u = malloc(sizeof(double) * 2 * ns * ns);
     memcpy(u, u_start, sizeof(double) * 2 * ns * ns);
-    run_levels(&py, start, u, p, u_out, st, trace, trace_cap, trace_len);
+    run_levels(&py, start, u, p, NULL, u_out, st, trace, trace_cap, trace_len);
   }
   pyramid_free(&py);
   return rc;
@@ -714,8 +735,9 @@ static void rigid_field(int n, const double p[3], double* u) {
     }
 }
 
-static int rigid_flow(const level_data* L, double p[3], const or_params* pr, int* passes_out,
-                      int* flags, double* e_out, double* ncc_out) {
+static int rigid_flow(const level_data* L, double p[3], const or_params* pr, int force,
+                      int* passes_out, int* flags, double* e_out, double* ncc_out,
+                      double* gap) {
   int n = L->n;
   size_t nn = (size_t)n * n;
   double h = 1.0 / (n - 1);
@@ -780,7 +802,11 @@ static int rigid_flow(const level_data* L, double p[3], const or_params* pr, int
     ncc = ncc_acc;
     tau_prev = tau_acc;
     steps++;
-    if (dec < pr->eps) break;
+    if (force >= 0) { /* how far the energy test is from the replayed decision */
+      if (steps < force) *gap = fmax(*gap, pr->eps - dec);
+      else if (steps < pr->iter_max) *gap = fmax(*gap, dec - pr->eps);
+    }
+    if (force >= 0 ? steps >= force : dec < pr->eps) break;
     if (steps >= pr->iter_max) *flags |= OR_FLAG_NONCONV;
   }
   if (passes_out) *passes_out = passes_total;
@@ -794,8 +820,9 @@ static int rigid_flow(const level_data* L, double p[3], const or_params* pr, int
 /* Rigid registration of T to R (nodal frames of side nf) from p_init (NULL: identity) over the
    multilevel pyramid; p_out receives the parameters (domain units). Returns 0, -1 for a constant
    reference, -2 for bad sizes. */
-int or_register_rigid(const double* R, const double* T, int nf, const double* p_init,
-                      const or_params* pr, double* p_out, or_stats* st) {
+/* force: as for or_register_f (may be NULL). */
+int or_register_rigid_f(const double* R, const double* T, int nf, const double* p_init,
+                        const or_params* pr, const int* force, double* p_out, or_stats* st) {
   int L = log2_exact(nf - 1);
   if (L < 1 || pr->levels < 1 || pr->levels > L || pr->levels > OR_MAX_LEVELS) return -2;
   int m0 = L - pr->levels + 1;
@@ -806,11 +833,12 @@ int or_register_rigid(const double* R, const double* T, int nf, const double* p_
     if (p_init) memcpy(p, p_init, sizeof p);
     if (st) memset(st, 0, sizeof(*st));
     int flags = 0;
-    double e = 0.0, ncc = 0.0;
+    double e = 0.0, ncc = 0.0, gap = 0.0;
     for (int l = m0; l <= L; ++l) {
       level_data LD = {(1 << l) + 1, py.Rn[l], py.Tl[l]};
       int passes = 0;
-      int steps = rigid_flow(&LD, p, pr, &passes, &flags, &e, &ncc);
+      int steps = rigid_flow(&LD, p, pr, force ? force[l - m0] : -1, &passes, &flags, &e, &ncc,
+                             &gap);
       if (st) {
         st->iters[l - m0] = steps;
         st->trials[l - m0] = passes;
@@ -821,6 +849,7 @@ int or_register_rigid(const double* R, const double* T, int nf, const double* p_
       st->energy = e;
       st->ncc = ncc;
       st->flags = flags;
+      st->tie_gap = gap;
     }
   }
   pyramid_free(&py);
@@ -866,6 +895,7 @@ typedef struct {
   const or_params* p;
   or_stats* op_stats;  /* per op, in execution order; may be NULL */
   int* op_pairs;       /* (i, j, k) per op in execution order; may be NULL */
+  const int* force_b;  /* per op, OR_MAX_LEVELS replayed step counts (see or_register_f); or NULL */
   int n_ops;
   int err;
 } series_ctx;
@@ -879,8 +909,10 @@ static void apply_b(series_ctx* S, const elem_t* left, elem_t* right, int op_ind
   double* w = malloc(sizeof(double) * 2 * nn);
   or_compose(left->u, right->u, S->nf, w);
   or_stats st;
-  int rc = or_register(S->frames + (size_t)left->i * nn, S->frames + (size_t)right->k * nn,
-                       S->nf, w, S->p, right->u, &st, NULL, 0, NULL);
+  int rc = or_register_f(S->frames + (size_t)left->i * nn, S->frames + (size_t)right->k * nn,
+                         S->nf, w, S->p,
+                         S->force_b ? S->force_b + (size_t)op_index * OR_MAX_LEVELS : NULL,
+                         right->u, &st, NULL, 0, NULL);
   if (rc != 0) S->err = rc;
   if (S->op_stats) S->op_stats[op_index] = st;
   if (S->op_pairs) {
@@ -977,9 +1009,11 @@ static int scan_general(series_ctx* S, elem_t* x, int M, int workers) {
   return ops;
 }
 
-int or_series(const double* frames, int N, int nf, const or_params* p, int scan, int workers,
-              double* u_out, or_stats* a_stats, or_stats* b_stats, int* b_pairs,
-              int threads) {
+/* force_a ([N-1][OR_MAX_LEVELS]) and force_b ([ops][OR_MAX_LEVELS]), each may be NULL: the
+   replayed step counts of or_register_f for every neighbour registration and B application. */
+int or_series_f(const double* frames, int N, int nf, const or_params* p, int scan, int workers,
+                const int* force_a, const int* force_b, double* u_out, or_stats* a_stats,
+                or_stats* b_stats, int* b_pairs, int threads) {
   if (N < 1) return -1;
   size_t nn = (size_t)nf * nf;
   memset(u_out, 0, sizeof(double) * 2 * nn);
@@ -1001,8 +1035,9 @@ int or_series(const double* frames, int N, int nf, const or_params* p, int scan,
 #pragma omp parallel for schedule(dynamic, 1)
   for (int m = 0; m < M; ++m) {
     or_stats st;
-    int rc = or_register(frames + (size_t)m * nn, frames + (size_t)(m + 1) * nn, nf, NULL, p,
-                         x[m].u, &st, NULL, 0, NULL);
+    int rc = or_register_f(frames + (size_t)m * nn, frames + (size_t)(m + 1) * nn, nf, NULL, p,
+                           force_a ? force_a + (size_t)m * OR_MAX_LEVELS : NULL, x[m].u, &st,
+                           NULL, 0, NULL);
     if (rc != 0) err = rc;
     if (a_stats) a_stats[m] = st;
   }
@@ -1010,7 +1045,7 @@ int or_series(const double* frames, int N, int nf, const or_params* p, int scan,
     free(x);
     return err;
   }
-  series_ctx S = {frames, nf, p, b_stats, b_pairs, 0, 0};
+  series_ctx S = {frames, nf, p, b_stats, b_pairs, force_b, 0, 0};
   int ops = 0;
   if (scan == OR_SCAN_SEQUENTIAL) {
     /* y_0 = x_0, y_m = y_{m-1} (.) x_m */
@@ -1080,4 +1115,16 @@ int or_series(const double* frames, int N, int nf, const or_params* p, int scan,
     if (x[m].i != 0 || x[m].k != m + 1) S.err = -4;
   free(x);
   return S.err ? S.err : ops;
+}
+
+int or_series(const double* frames, int N, int nf, const or_params* p, int scan, int workers,
+              double* u_out, or_stats* a_stats, or_stats* b_stats, int* b_pairs,
+              int threads) {
+  return or_series_f(frames, N, nf, p, scan, workers, NULL, NULL, u_out, a_stats, b_stats,
+                     b_pairs, threads);
+}
+
+int or_register_rigid(const double* R, const double* T, int nf, const double* p_init,
+                      const or_params* pr, double* p_out, or_stats* st) {
+  return or_register_rigid_f(R, T, nf, p_init, pr, NULL, p_out, st);
 }
