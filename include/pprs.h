@@ -82,6 +82,9 @@ typedef struct {
   double energy;                /* final energy at the finest level */
   double ncc;                   /* final NCC at the finest level */
   int flags;                    /* PPRS_FLAG_* */
+  float ms;                     /* time the registration took (ms): the batch's time for the
+                                   pair calls; in a series, from the slot-pool poll that started
+                                   it to the poll that retired it (host clock) */
 } pprs_pair_stats;
 
 typedef struct {
@@ -112,6 +115,19 @@ void pprs_destroy(pprs_ctx* ctx);
 
 /* Thread-local description of the last non-OK status; never NULL. */
 const char* pprs_last_error(void);
+
+/* Workspace of pprs_prefix_register_series (definition "Image series registration": the N-1
+   neighbour registrations and the scan's B applications, all in one slot pool) on a context
+   with the default pool shape and no warm start: *bytes (host) receives the device memory the
+   call keeps in its context for N frames of H x W with these params. Makes no HIP call.
+   PPRS_EINVAL for bad sizes or params. The figure is the sum of the context's buffers, each
+   sized for this call alone; a context that already holds larger buffers keeps them. */
+pprs_status pprs_workspace_query(int N, int H, int W, const pprs_params* params, size_t* bytes);
+/* Allocates on ctx the workspace pprs_workspace_query describes (for ctx's pool shape), so that
+   a later pprs_prefix_register_series call of that size allocates nothing more. */
+pprs_status pprs_reserve_workspace(pprs_ctx* ctx, int N, int H, int W, const pprs_params* params);
+/* Device memory (bytes) ctx holds right now in its workspace buffers (host pointer). */
+pprs_status pprs_workspace_bytes(pprs_ctx* ctx, size_t* bytes);
 
 /* Function A: registers f_tmpl to f_ref (reference f_i, template f_k: f_k o phi ~ f_i).
    f_ref, f_tmpl: [H][W]. u_init: [2][H][W] initial guess (NULL = identity); it is restricted
@@ -232,6 +248,14 @@ pprs_status pprs_register_series_batch(pprs_ctx* ctx, int S, const float* const*
                                        const int* N, const int* side, const int* levels,
                                        float* const* u_out, const pprs_params* params,
                                        pprs_series_stats* stats, double* latency_ms);
+/* The same segmented scan (one inclusive scan per series, the segmented form of the Prefix
+   sum chapter) with per-series heights and widths: series j has N[j] frames of H[j] x W[j]
+   (H[j] == W[j] required) and params->levels levels. Equivalent to pprs_register_series_batch
+   with side = H, levels = NULL and latency_ms = NULL. Host arrays: frames, N, H, W, u_out. */
+pprs_status pprs_prefix_register_series_batch(pprs_ctx* ctx, int S, const float* const* frames,
+                                              const int* N, const int* H, const int* W,
+                                              float* const* u_out, const pprs_params* params,
+                                              pprs_series_stats* stats);
 
 /* Series averaging (Introduction; image series registration): the aligned frames f_i o phi_0i
    averaged into one image, avg(x) = 1/N sum_i f_i(x + u_i(x)), the consumer of the scan output.
@@ -284,6 +308,13 @@ size_t pprs_cnn_param_count(const pprs_cnn* cnn);
 /* Host buffers of pprs_cnn_param_count floats. set also resets the optimiser state. */
 pprs_status pprs_cnn_set_params(pprs_cnn* cnn, const float* host, size_t count);
 pprs_status pprs_cnn_get_params(pprs_cnn* cnn, float* host, size_t count);
+/* Loads the parameters from a weights-only blob (host memory, `bytes` long) in the safetensors
+   layout: an 8-byte little-endian header length, a JSON header naming each tensor's dtype,
+   shape and byte range, then the data. The blob must hold one F32 tensor named "params" (or a
+   single F32 tensor) of pprs_cnn_param_count elements, the layout pprs_cnn_get_params returns.
+   Nothing in the blob is executed; a malformed header, another dtype or size, or a byte range
+   outside the blob is PPRS_EINVAL and leaves the weights unchanged. Resets the optimiser. */
+pprs_status pprs_cnn_load(pprs_cnn* cnn, const void* blob, size_t bytes);
 /* Inference on B samples (device pointers). */
 pprs_status pprs_cnn_forward(pprs_cnn* cnn, const float* x, int B, float* y);
 /* Mean squared error over the interior (a border of `margin` pixels left out) and its gradient

@@ -11,7 +11,8 @@ from .api import (Params, PairStats, SeriesStats, compose_deformations, default_
                   scan_plan, series_average, set_kernel_timing, set_pool, get_tuning, set_tuning,
                   set_metric_solve,
                   Context, WarmStartNet, pair_inputs,
-                  level7_targets, set_warm_start)
+                  level7_targets, set_warm_start, workspace_query, reserve_workspace,
+                  workspace_bytes, prefix_register_series_batch)
 
 __all__ = ["Params", "PairStats", "SeriesStats", "compose_deformations", "default_params",
            "kernel_names", "kernel_timing", "prefix_register_series",
@@ -19,4 +20,5 @@ __all__ = ["Params", "PairStats", "SeriesStats", "compose_deformations", "defaul
            "register_pairs", "register_pairs_rigid", "register_series_batch", "PprsError",
            "scan_plan", "series_average", "set_kernel_timing", "set_pool", "get_tuning", "set_tuning",
            "set_metric_solve", "Context", "WarmStartNet", "pair_inputs",
-           "level7_targets", "set_warm_start"]
+           "level7_targets", "set_warm_start", "workspace_query", "reserve_workspace",
+           "workspace_bytes", "prefix_register_series_batch"]

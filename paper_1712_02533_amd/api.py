@@ -13,8 +13,7 @@ import threading
 from dataclasses import asdict, dataclass, field
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# PPRS_LIBRARY selects another build of the library (e.g. one compiled with other tile sizes)
-LIB_PATH = os.environ.get("PPRS_LIBRARY") or os.path.join(_HERE, "libpprs.so")
+LIB_PATH = os.path.join(_HERE, "libpprs.so")
 
 PPRS_OK = 0
 PPRS_NOT_CONVERGED = 1
@@ -38,7 +37,8 @@ class _CParams(ctypes.Structure):
 
 class _CPairStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int * MAX_LEVELS), ("passes", ctypes.c_int * MAX_LEVELS),
-                ("energy", ctypes.c_double), ("ncc", ctypes.c_double), ("flags", ctypes.c_int)]
+                ("energy", ctypes.c_double), ("ncc", ctypes.c_double), ("flags", ctypes.c_int),
+                ("ms", ctypes.c_float)]
 
 
 class _CSeriesStats(ctypes.Structure):
@@ -86,6 +86,7 @@ class PairStats:
     energy: float
     ncc: float
     flags: int
+    ms: float = 0.0
 
 
 @dataclass
@@ -157,6 +158,17 @@ def _lib():
                                                    ctypes.POINTER(ctypes.c_double)]),
                 "pprs_get_tuning": (i, [vp, ctypes.POINTER(_CTuning)]),
                 "pprs_set_tuning": (i, [vp, ctypes.POINTER(_CTuning)]),
+                "pprs_workspace_query": (i, [i, i, i, ctypes.POINTER(_CParams),
+                                             ctypes.POINTER(ctypes.c_size_t)]),
+                "pprs_reserve_workspace": (i, [vp, i, i, i, ctypes.POINTER(_CParams)]),
+                "pprs_workspace_bytes": (i, [vp, ctypes.POINTER(ctypes.c_size_t)]),
+                "pprs_prefix_register_series_batch": (i, [vp, i, ctypes.POINTER(vp),
+                                                          ctypes.POINTER(ctypes.c_int),
+                                                          ctypes.POINTER(ctypes.c_int),
+                                                          ctypes.POINTER(ctypes.c_int),
+                                                          ctypes.POINTER(vp),
+                                                          ctypes.POINTER(_CParams),
+                                                          ctypes.POINTER(_CSeriesStats)]),
             }
             for name, (res, args) in sigs.items():
                 fn = getattr(lib, name)
@@ -231,33 +243,53 @@ def _ctx(device) -> Context:
     return c
 
 
-def _dev_f32(t, name):
+def _dev_f32(t, name, shape=None, device=None):
+    """Device pointer of a contiguous float32 tensor. shape (a tuple) and device, when given,
+    must match: the library receives raw pointers and cannot check sizes itself, so a wrong
+    shape is refused here, before any kernel could read or write past the tensor."""
     import torch
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
         raise ValueError("%s must be a torch tensor on a HIP device" % name)
     if t.dtype != torch.float32 or not t.is_contiguous():
         raise ValueError("%s must be contiguous float32" % name)
+    if shape is not None and tuple(t.shape) != tuple(int(x) for x in shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    if device is not None and t.device != device:
+        raise ValueError("%s must be on %s, got %s" % (name, device, t.device))
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _frames3(frames, name="frames"):
+    """(N, H, W) of a frame stack [N, H, W]."""
+    if frames.dim() != 3:
+        raise ValueError("%s must be [N, H, W], got %s" % (name, tuple(frames.shape)))
+    return tuple(int(x) for x in frames.shape)
+
+
 def _pair_stats(s: _CPairStats, levels: int) -> PairStats:
-    return PairStats(list(s.iters[:levels]), list(s.passes[:levels]), s.energy, s.ncc, s.flags)
+    return PairStats(list(s.iters[:levels]), list(s.passes[:levels]), s.energy, s.ncc, s.flags,
+                     s.ms)
 
 
 def register_pair(f_ref, f_tmpl, u_init=None, params: Params | None = None, out=None):
     """Function A: returns (u [2, H, W] pixels, PairStats)."""
     import torch
     params = params or Params()
-    H, W = f_ref.shape[-2:]
+    if f_ref.dim() != 2:
+        raise ValueError("f_ref must be [H, W], got %s" % (tuple(f_ref.shape),))
+    H, W = f_ref.shape
+    dev = f_ref.device
     if out is None:
-        out = torch.empty((2, H, W), device=f_ref.device, dtype=torch.float32)
+        out = torch.empty((2, H, W), device=dev, dtype=torch.float32)
     st = _CPairStats()
     cp = params.c()
-    c = _ctx(f_ref.device)
-    _check(_lib().pprs_register_pair(
-        c.handle, _dev_f32(f_ref, "f_ref"), _dev_f32(f_tmpl, "f_tmpl"), H, W,
-        _dev_f32(u_init, "u_init") if u_init is not None else None, _dev_f32(out, "out"),
-        ctypes.byref(cp), ctypes.byref(st)))
+    a_ref = _dev_f32(f_ref, "f_ref")
+    a_tmpl = _dev_f32(f_tmpl, "f_tmpl", (H, W), dev)
+    a_init = _dev_f32(u_init, "u_init", (2, H, W), dev) if u_init is not None else None
+    a_out = _dev_f32(out, "out", (2, H, W), dev)
+    c = _ctx(dev)
+    _check(_lib().pprs_register_pair(c.handle, a_ref, a_tmpl, H, W, a_init, a_out,
+                                     ctypes.byref(cp), ctypes.byref(st)))
     return out, _pair_stats(st, params.levels)
 
 
@@ -271,28 +303,34 @@ def register_pairs(frames, ref, tmpl, params: Params | None = None, out=None):
     tmpl = np.ascontiguousarray(tmpl, dtype=np.int32)
     if ref.shape != tmpl.shape or ref.ndim != 1:
         raise ValueError("ref and tmpl must be 1-D index arrays of one length")
-    N, H, W = frames.shape
+    N, H, W = _frames3(frames)
     P = len(ref)
     if out is None:
         out = torch.empty((P, 2, H, W), device=frames.device, dtype=torch.float32)
     st = (_CPairStats * max(P, 1))()
     cp = params.c()
+    a_fr = _dev_f32(frames, "frames")
+    a_out = _dev_f32(out, "out", (P, 2, H, W), frames.device)
     c = _ctx(frames.device)
-    _check(_lib().pprs_register_pairs(
-        c.handle, _dev_f32(frames, "frames"), N, H, W, ref.ctypes.data, tmpl.ctypes.data, P,
-        _dev_f32(out, "out"), ctypes.byref(cp), st))
+    _check(_lib().pprs_register_pairs(c.handle, a_fr, N, H, W, ref.ctypes.data,
+                                      tmpl.ctypes.data, P, a_out, ctypes.byref(cp), st))
     return out, [_pair_stats(st[k], params.levels) for k in range(P)]
 
 
 def compose_deformations(u_ij, u_jk, out=None):
     """(phi_jk o phi_ij) as a displacement [2, H, W] in pixels."""
     import torch
-    H, W = u_ij.shape[-2:]
+    if u_ij.dim() != 3 or u_ij.shape[0] != 2:
+        raise ValueError("u_ij must be [2, H, W], got %s" % (tuple(u_ij.shape),))
+    _, H, W = u_ij.shape
     if out is None:
         out = torch.empty_like(u_ij)
-    c = _ctx(u_ij.device)
-    _check(_lib().pprs_compose_deformations(c.handle, _dev_f32(u_ij, "u_ij"),
-                                            _dev_f32(u_jk, "u_jk"), _dev_f32(out, "out"), H, W))
+    dev = u_ij.device
+    a_ij = _dev_f32(u_ij, "u_ij")
+    a_jk = _dev_f32(u_jk, "u_jk", (2, H, W), dev)
+    a_out = _dev_f32(out, "out", (2, H, W), dev)
+    c = _ctx(dev)
+    _check(_lib().pprs_compose_deformations(c.handle, a_ij, a_jk, a_out, H, W))
     return out
 
 
@@ -301,7 +339,7 @@ def register_pairs_rigid(frames, ref, tmpl, params: Params | None = None, p_init
     about pixel (0, 0). Returns (p [P, 3] float64: alpha (rad), t0, t1 (px), stats list)."""
     import numpy as np
     params = params or Params()
-    N, H, W = frames.shape
+    N, H, W = _frames3(frames)
     ref = np.ascontiguousarray(ref, dtype=np.int32)
     tmpl = np.ascontiguousarray(tmpl, dtype=np.int32)
     if ref.ndim != 1 or ref.shape != tmpl.shape:
@@ -310,7 +348,10 @@ def register_pairs_rigid(frames, ref, tmpl, params: Params | None = None, p_init
     out = np.zeros((max(P, 1), 3))
     pin = None
     if p_init is not None:
-        pin = np.ascontiguousarray(p_init, dtype=np.float64).reshape(P, 3)
+        pin = np.ascontiguousarray(p_init, dtype=np.float64)
+        if pin.size != 3 * P:
+            raise ValueError("p_init must hold 3 parameters per pair")
+        pin = pin.reshape(P, 3)
     st = (_CPairStats * max(P, 1))()
     cp = params.c()
     c = _ctx(frames.device)
@@ -325,7 +366,7 @@ def prefix_register_series_rigid(frames, params: Params | None = None):
     p[0] = 0; SeriesStats)."""
     import numpy as np
     params = params or Params()
-    N, H, W = frames.shape
+    N, H, W = _frames3(frames)
     out = np.zeros((N, 3))
     ss = _CSeriesStats()
     cp = params.c()
@@ -343,14 +384,17 @@ def series_average(frames, u, out=None):
     """Average of the aligned frames f_i o phi_{0,i}: [H, W] from frames [N, H, W] and the
     series result u [N, 2, H, W] (pixels)."""
     import torch
-    N, H, W = frames.shape
+    N, H, W = _frames3(frames)
     if tuple(u.shape) != (N, 2, H, W):
         raise PprsError(-1, "u must be [N, 2, H, W] for frames [N, H, W]")
     if out is None:
         out = torch.empty((H, W), device=frames.device, dtype=torch.float32)
-    c = _ctx(frames.device)
-    _check(_lib().pprs_series_average(c.handle, _dev_f32(frames, "frames"), _dev_f32(u, "u"),
-                                      N, H, W, _dev_f32(out, "out")))
+    dev = frames.device
+    a_fr = _dev_f32(frames, "frames")
+    a_u = _dev_f32(u, "u", (N, 2, H, W), dev)
+    a_out = _dev_f32(out, "out", (H, W), dev)
+    c = _ctx(dev)
+    _check(_lib().pprs_series_average(c.handle, a_fr, a_u, N, H, W, a_out))
     return out
 
 
@@ -360,9 +404,11 @@ def prefix_register_series(frames, params: Params | None = None, out=None,
     op stats list or None)."""
     import torch
     params = params or Params()
-    N, H, W = frames.shape
+    N, H, W = _frames3(frames)
     if out is None:
         out = torch.empty((N, 2, H, W), device=frames.device, dtype=torch.float32)
+    a_fr = _dev_f32(frames, "frames")
+    a_out = _dev_f32(out, "out", (N, 2, H, W), frames.device)
     ss = _CSeriesStats()
     ops = None
     if want_op_stats:
@@ -370,9 +416,8 @@ def prefix_register_series(frames, params: Params | None = None, out=None,
         ops = (_CPairStats * max(N - 1 + n_b, 1))()   # N-1 A entries, then the B entries
     cp = params.c()
     c = _ctx(frames.device)
-    _check(_lib().pprs_prefix_register_series(
-        c.handle, _dev_f32(frames, "frames"), N, H, W, _dev_f32(out, "out"), ctypes.byref(cp),
-        ctypes.byref(ss), ops))
+    _check(_lib().pprs_prefix_register_series(c.handle, a_fr, N, H, W, a_out, ctypes.byref(cp),
+                                              ctypes.byref(ss), ops))
     stats = SeriesStats(ss.n_ops_a, ss.n_ops_b, ss.n_scan_levels, ss.flags_or, ss.ms_total,
                         ss.ms_prepare, ss.ms_preprocess, ss.ms_scan, ss.node_steps,
                         ss.node_passes)
@@ -380,6 +425,33 @@ def prefix_register_series(frames, params: Params | None = None, out=None,
     if want_op_stats:
         op_list = [_pair_stats(ops[k], params.levels) for k in range(ss.n_ops_a + ss.n_ops_b)]
     return out, stats, op_list
+
+
+def workspace_query(N: int, H: int, W: int, params: Params | None = None) -> int:
+    """Device bytes a series call of N frames of H x W keeps in its context (no HIP call)."""
+    params = params or Params()
+    b = ctypes.c_size_t()
+    cp = params.c()
+    _check(_lib().pprs_workspace_query(N, H, W, ctypes.byref(cp), ctypes.byref(b)))
+    return b.value
+
+
+def reserve_workspace(N: int, H: int, W: int, params: Params | None = None, device=None):
+    """Allocates, on the current stream's context, what a series call of that size needs."""
+    import torch
+    params = params or Params()
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    cp = params.c()
+    _check(_lib().pprs_reserve_workspace(_ctx(dev).handle, N, H, W, ctypes.byref(cp)))
+
+
+def workspace_bytes(device=None) -> int:
+    """Device bytes the current stream's context holds in its workspace."""
+    import torch
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    b = ctypes.c_size_t()
+    _check(_lib().pprs_workspace_bytes(_ctx(dev).handle, ctypes.byref(b)))
+    return b.value
 
 
 def set_pool(slots: int = 0, group_steps: int = 0, device=None):
@@ -423,11 +495,25 @@ def register_series_batch(series, params: Params | None = None, levels=None, out
     import torch
     params = params or Params()
     S = len(series)
+    if S < 1:
+        raise ValueError("at least one series")
+    dev = series[0].device
+    for j, f in enumerate(series):
+        N, H, W = _frames3(f, "series[%d]" % j)
+        if H != W:
+            raise ValueError("series[%d] frames must be square, got %dx%d" % (j, H, W))
     if outs is None:
         outs = [torch.empty((f.shape[0], 2, f.shape[1], f.shape[2]), device=f.device,
                             dtype=torch.float32) for f in series]
-    fr = (ctypes.c_void_p * S)(*[_dev_f32(f, "frames").value for f in series])
-    uo = (ctypes.c_void_p * S)(*[_dev_f32(u, "out").value for u in outs])
+    if len(outs) != S:
+        raise ValueError("outs must hold one tensor per series")
+    if levels is not None and len(levels) != S:
+        raise ValueError("levels must hold one count per series")
+    fr = (ctypes.c_void_p * S)(*[_dev_f32(f, "series[%d]" % j, None, dev).value
+                                 for j, f in enumerate(series)])
+    uo = (ctypes.c_void_p * S)(*[_dev_f32(u, "outs[%d]" % j,
+                                          (f.shape[0], 2, f.shape[1], f.shape[2]), dev).value
+                                 for j, (f, u) in enumerate(zip(series, outs))])
     ns = (ctypes.c_int * S)(*[int(f.shape[0]) for f in series])
     sd = (ctypes.c_int * S)(*[int(f.shape[1]) for f in series])
     st = (_CSeriesStats * S)()
@@ -441,6 +527,38 @@ def register_series_batch(series, params: Params | None = None, levels=None, out
                          x.ms_prepare, x.ms_preprocess, x.ms_scan, x.node_steps, x.node_passes)
              for x in st]
     return outs, stats, list(lat)
+
+
+def prefix_register_series_batch(series, params: Params | None = None, outs=None):
+    """pprs_prefix_register_series_batch: several series [N_j, H_j, W_j] (H_j == W_j), one
+    level count for all. Returns (list of u [N_j, 2, H_j, W_j], list of SeriesStats)."""
+    import torch
+    params = params or Params()
+    S = len(series)
+    if S < 1:
+        raise ValueError("at least one series")
+    dev = series[0].device
+    shapes = [_frames3(f, "series[%d]" % j) for j, f in enumerate(series)]
+    if outs is None:
+        outs = [torch.empty((N, 2, H, W), device=dev, dtype=torch.float32)
+                for (N, H, W) in shapes]
+    if len(outs) != S:
+        raise ValueError("outs must hold one tensor per series")
+    fr = (ctypes.c_void_p * S)(*[_dev_f32(f, "series[%d]" % j, None, dev).value
+                                 for j, f in enumerate(series)])
+    uo = (ctypes.c_void_p * S)(*[_dev_f32(u, "outs[%d]" % j, (N, 2, H, W), dev).value
+                                 for j, (u, (N, H, W)) in enumerate(zip(outs, shapes))])
+    ns = (ctypes.c_int * S)(*[x[0] for x in shapes])
+    hs = (ctypes.c_int * S)(*[x[1] for x in shapes])
+    ws = (ctypes.c_int * S)(*[x[2] for x in shapes])
+    st = (_CSeriesStats * S)()
+    cp = params.c()
+    _check(_lib().pprs_prefix_register_series_batch(_ctx(dev).handle, S, fr, ns, hs, ws, uo,
+                                                    ctypes.byref(cp), st))
+    stats = [SeriesStats(x.n_ops_a, x.n_ops_b, x.n_scan_levels, x.flags_or, x.ms_total,
+                         x.ms_prepare, x.ms_preprocess, x.ms_scan, x.node_steps, x.node_passes)
+             for x in st]
+    return outs, stats
 
 
 def set_kernel_timing(enable: bool, device=None):
@@ -487,6 +605,7 @@ def _cnn_sigs(lib):
         "pprs_cnn_param_count": (ctypes.c_size_t, [vp]),
         "pprs_cnn_set_params": (i, [vp, vp, ctypes.c_size_t]),
         "pprs_cnn_get_params": (i, [vp, vp, ctypes.c_size_t]),
+        "pprs_cnn_load": (i, [vp, ctypes.c_char_p, ctypes.c_size_t]),
         "pprs_cnn_forward": (i, [vp, vp, i, vp]),
         "pprs_cnn_gradients": (i, [vp, vp, vp, i, i, ctypes.POINTER(ctypes.c_double), vp]),
         "pprs_cnn_train_step": (i, [vp, vp, vp, i, i, ctypes.c_float,
@@ -551,25 +670,27 @@ class WarmStartNet:
     def forward(self, x):
         """x [B, 128, 128, 2] float32 on the device -> [B, 128, 128, 2]."""
         import torch
+        B = _net_batch(x, "x")
         y = torch.empty_like(x)
-        _cnn_check(_lib().pprs_cnn_forward(self.handle, _dev_f32(x, "x"), x.shape[0],
-                                           _dev_f32(y, "y")))
+        _cnn_check(_lib().pprs_cnn_forward(self.handle, _dev_f32(x, "x"), B, _dev_f32(y, "y")))
         return y
 
     def gradients(self, x, target, margin: int = 4):
         import numpy as np
         g = np.empty(self.n_params, dtype=np.float32)
         loss = ctypes.c_double()
-        _cnn_check(_lib().pprs_cnn_gradients(self.handle, _dev_f32(x, "x"),
-                                             _dev_f32(target, "target"), x.shape[0], margin,
+        B = _net_batch(x, "x")
+        a_t = _dev_f32(target, "target", tuple(x.shape), x.device)
+        _cnn_check(_lib().pprs_cnn_gradients(self.handle, _dev_f32(x, "x"), a_t, B, margin,
                                              ctypes.byref(loss), g.ctypes.data))
         return loss.value, g
 
     def train_step(self, x, target, lr: float, margin: int = 4) -> float:
         loss = ctypes.c_double()
-        _cnn_check(_lib().pprs_cnn_train_step(self.handle, _dev_f32(x, "x"),
-                                              _dev_f32(target, "target"), x.shape[0], margin,
-                                              lr, ctypes.byref(loss)))
+        B = _net_batch(x, "x")
+        a_t = _dev_f32(target, "target", tuple(x.shape), x.device)
+        _cnn_check(_lib().pprs_cnn_train_step(self.handle, _dev_f32(x, "x"), a_t, B, margin, lr,
+                                              ctypes.byref(loss)))
         return loss.value
 
     def save(self, path: str):
@@ -577,8 +698,21 @@ class WarmStartNet:
         save_file({"params": self.get_params()}, path)
 
     def load(self, path: str):
-        from safetensors.numpy import load_file
-        self.set_params(load_file(path)["params"])
+        """Reads a weights file (safetensors layout, one F32 tensor "params"); the library
+        parses it (pprs_cnn_load)."""
+        with open(path, "rb") as f:
+            blob = f.read()
+        self.load_bytes(blob)
+
+    def load_bytes(self, blob: bytes):
+        _cnn_check(_lib().pprs_cnn_load(self.handle, blob, len(blob)))
+
+
+def _net_batch(x, name):
+    """B of a network tensor [B, 128, 128, 2]."""
+    if x.dim() != 4 or tuple(x.shape[1:]) != (128, 128, 2):
+        raise ValueError("%s must be [B, 128, 128, 2], got %s" % (name, tuple(x.shape)))
+    return int(x.shape[0])
 
 
 def pair_inputs(frames, ref, tmpl):
@@ -588,7 +722,9 @@ def pair_inputs(frames, ref, tmpl):
     _cnn_sigs(_lib())
     ref = np.ascontiguousarray(ref, dtype=np.int32)
     tmpl = np.ascontiguousarray(tmpl, dtype=np.int32)
-    N, H, W = frames.shape
+    if ref.ndim != 1 or ref.shape != tmpl.shape:
+        raise ValueError("ref and tmpl must be 1-D index arrays of one length")
+    N, H, W = _frames3(frames)
     out = torch.empty((len(ref), 128, 128, 2), device=frames.device, dtype=torch.float32)
     c = _ctx(frames.device)
     _check(_lib().pprs_pair_inputs(c.handle, _dev_f32(frames, "frames"), N, H, W,
@@ -601,6 +737,8 @@ def level7_targets(u):
     """Displacements u [P, 2, H, W] (pixels) -> level-7 targets [P, 128, 128, 2] (cells)."""
     import torch
     _cnn_sigs(_lib())
+    if u.dim() != 4 or u.shape[1] != 2:
+        raise ValueError("u must be [P, 2, H, W], got %s" % (tuple(u.shape),))
     P, _, H, W = u.shape
     out = torch.empty((P, 128, 128, 2), device=u.device, dtype=torch.float32)
     c = _ctx(u.device)

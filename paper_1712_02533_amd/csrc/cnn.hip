@@ -12,6 +12,7 @@
 // (L1 to 64), padded with zeros. L6 (2 output channels) uses direct FP32 kernels.
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
+#include <ctype.h>
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -901,6 +902,167 @@ static pprs_status backward(Model& M, const float* target, int B, int margin, do
 }
 
 // ------------------------------------------------------------------------------------------
+// Weights-only blob (safetensors layout): u64 little-endian header length, a JSON object
+// {"name": {"dtype": ..., "shape": [...], "data_offsets": [begin, end]}, "__metadata__": {...}},
+// then the tensor bytes. A small recursive-descent reader of that JSON: it accepts objects,
+// arrays, strings, numbers and literals, records each top-level tensor's fields and skips
+// everything else. Nothing in the blob is interpreted beyond these fields.
+
+namespace {
+
+struct BlobTensor {
+  std::string name, dtype;
+  std::vector<long long> shape;
+  long long begin = -1, end = -1;
+};
+
+struct JsonReader {
+  const char* p;
+  const char* e;
+  int depth = 0;
+  bool ok = true;
+  void ws() {
+    while (p < e && (*p == ' ' || *p == '\n' || *p == '\r' || *p == '\t')) ++p;
+  }
+  bool eat(char ch) {
+    ws();
+    if (p < e && *p == ch) {
+      ++p;
+      return true;
+    }
+    return false;
+  }
+  bool str(std::string* out) {
+    ws();
+    if (p >= e || *p != '"') return ok = false;
+    ++p;
+    std::string r;
+    while (p < e && *p != '"') {
+      if (*p == '\\') {
+        if (++p >= e) return ok = false;
+        char c = *p;
+        if (c == 'u') {  // keep the escape's text; names here are plain ASCII
+          if (e - p < 5) return ok = false;
+          r.append(p - 1, 6);
+          p += 5;
+          continue;
+        }
+        r.push_back(c == 'n' ? '\n' : c == 't' ? '\t' : c == 'r' ? '\r' : c == 'b' ? '\b'
+                    : c == 'f' ? '\f' : c);
+        ++p;
+        continue;
+      }
+      r.push_back(*p++);
+    }
+    if (p >= e) return ok = false;
+    ++p;
+    if (out) *out = r;
+    return true;
+  }
+  bool integer(long long* out) {
+    ws();
+    const char* q = p;
+    bool neg = false;
+    if (q < e && *q == '-') neg = true, ++q;
+    if (q >= e || *q < '0' || *q > '9') return ok = false;
+    long long v = 0;
+    while (q < e && *q >= '0' && *q <= '9') {
+      if (v > (1LL << 50)) return ok = false;
+      v = v * 10 + (*q++ - '0');
+    }
+    if (q < e && (*q == '.' || *q == 'e' || *q == 'E')) return ok = false;
+    p = q;
+    *out = neg ? -v : v;
+    return true;
+  }
+  bool skip() {  // any value
+    ws();
+    if (p >= e || ++depth > 64) return ok = false;
+    bool r = true;
+    if (*p == '"') {
+      r = str(nullptr);
+    } else if (*p == '{') {
+      ++p;
+      if (!eat('}')) {
+        do {
+          r = str(nullptr) && eat(':') && skip();
+        } while (r && eat(','));
+        r = r && eat('}');
+      }
+    } else if (*p == '[') {
+      ++p;
+      if (!eat(']')) {
+        do {
+          r = skip();
+        } while (r && eat(','));
+        r = r && eat(']');
+      }
+    } else {
+      const char* q = p;
+      while (q < e && (isalnum((unsigned char)*q) || *q == '-' || *q == '+' || *q == '.')) ++q;
+      r = q > p;
+      p = q;
+    }
+    --depth;
+    if (!r) ok = false;
+    return r;
+  }
+  bool int_list(std::vector<long long>* out) {
+    if (!eat('[')) return ok = false;
+    out->clear();
+    if (eat(']')) return true;
+    do {
+      long long v;
+      if (!integer(&v)) return false;
+      out->push_back(v);
+    } while (eat(','));
+    return eat(']') || (ok = false);
+  }
+  bool tensor(BlobTensor* t) {
+    if (!eat('{')) return ok = false;
+    if (eat('}')) return true;
+    do {
+      std::string key;
+      if (!str(&key) || !eat(':')) return ok = false;
+      if (key == "dtype") {
+        if (!str(&t->dtype)) return false;
+      } else if (key == "shape") {
+        if (!int_list(&t->shape)) return false;
+      } else if (key == "data_offsets") {
+        std::vector<long long> o;
+        if (!int_list(&o) || o.size() != 2) return ok = false;
+        t->begin = o[0];
+        t->end = o[1];
+      } else if (!skip()) {
+        return false;
+      }
+    } while (eat(','));
+    return eat('}') || (ok = false);
+  }
+};
+
+bool parse_blob_header(const char* h, size_t n, std::vector<BlobTensor>& out) {
+  JsonReader r{h, h + n};
+  if (!r.eat('{')) return false;
+  if (r.eat('}')) return true;
+  do {
+    std::string key;
+    if (!r.str(&key) || !r.eat(':')) return false;
+    if (key == "__metadata__") {
+      if (!r.skip()) return false;
+      continue;
+    }
+    BlobTensor t;
+    t.name = key;
+    if (!r.tensor(&t)) return false;
+    out.push_back(t);
+  } while (r.eat(','));
+  return r.eat('}') && r.ok;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
 // C-ABI
 
 extern "C" {
@@ -980,6 +1142,42 @@ pprs_status pprs_cnn_set_params(pprs_cnn* c, const float* host, size_t count) {
   CHK(hipGetLastError());
   M.step = 0;
   return refresh_w6(M);
+}
+
+pprs_status pprs_cnn_load(pprs_cnn* c, const void* blob, size_t bytes) {
+  if (!c || !blob) return cfail(PPRS_EINVAL, "NULL argument");
+  const unsigned char* b = (const unsigned char*)blob;
+  if (bytes < 8) return cfail(PPRS_EINVAL, "blob shorter than its 8-byte header length");
+  unsigned long long hl = 0;
+  for (int k = 7; k >= 0; --k) hl = (hl << 8) | b[k];
+  if (hl < 2 || hl > bytes - 8) return cfail(PPRS_EINVAL, "header length %llu outside the blob", hl);
+  std::vector<BlobTensor> ts;
+  if (!parse_blob_header((const char*)b + 8, (size_t)hl, ts))
+    return cfail(PPRS_EINVAL, "malformed blob header");
+  const BlobTensor* t = nullptr;
+  for (const BlobTensor& x : ts)
+    if (x.name == "params") t = &x;
+  if (!t && ts.size() == 1) t = &ts[0];
+  if (!t) return cfail(PPRS_EINVAL, "blob holds no tensor named \"params\"");
+  if (t->dtype != "F32") return cfail(PPRS_EINVAL, "tensor dtype %s, expected F32", t->dtype.c_str());
+  long long count = 1;
+  for (long long d : t->shape) {
+    if (d < 0 || d > (1LL << 40)) return cfail(PPRS_EINVAL, "bad tensor shape");
+    count *= d;
+  }
+  Model& M = c->M;
+  if (count != M.n_params)
+    return cfail(PPRS_EINVAL, "blob holds %lld parameters, the network %lld", count, M.n_params);
+  size_t data = 8 + (size_t)hl, avail = bytes - data;
+  if (t->begin < 0 || t->end < t->begin || (unsigned long long)t->end > avail ||
+      t->end - t->begin != 4 * count)
+    return cfail(PPRS_EINVAL, "tensor byte range outside the blob");
+  std::vector<float> host((size_t)count);  // aligned copy: the data need not be aligned
+  memcpy(host.data(), b + data + t->begin, sizeof(float) * (size_t)count);
+  pprs_status s = pprs_cnn_set_params(c, host.data(), (size_t)count);
+  if (s != PPRS_OK) return s;
+  CHK(hipStreamSynchronize(M.stream));  // the host copy must outlive the upload
+  return PPRS_OK;
 }
 
 pprs_status pprs_cnn_get_params(pprs_cnn* c, float* host, size_t count) {

@@ -65,10 +65,18 @@ static pprs_status fail(pprs_status s, const char* fmt, ...) {
 namespace {
 
 const int kGridFin = 512;       // finalisation: one workgroup per listed slot (grid-stride)
+const int kPoolSlotsDefault = 512;  // concurrent registrations of a series (pprs_set_pool)
 
+// A device buffer owned by a context: grown by ensure(), freed with the context.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
 };
 
 enum { TK_PLAN = 0, TK_PROLONG, TK_EVAL, TK_GRAD, TK_SMY, TK_SMX, TK_LADDER, TK_FIN, TK_SMW,
@@ -104,7 +112,7 @@ struct pprs_ctx {
   // slot pool: per-round index lists and staged slot states
   DevBuf pool_idx, pool_off, pool_states;
   int pool_group = 16;   // steps between polls of the slot pool
-  int pool_slots = 512;  // concurrent registrations of a series
+  int pool_slots = kPoolSlotsDefault;  // concurrent registrations of a series
   // workgroups of the per-step item kernels (results do not depend on them)
   int grid_energy = 8192, grid_grad = 8192, grid_smooth = 8192, grid_prolong = 2048;
   bool smooth_window = false;  // windowed one-pass metric solve (opt-in, where beta allows)
@@ -125,6 +133,13 @@ struct pprs_ctx {
   long long t_launch[TK_COUNT] = {0};
   double t_bytes[TK_COUNT] = {0};
   long long nodes_acc[WK_COUNT] = {0};
+  // every workspace buffer (for pprs_workspace_bytes; each frees itself with the context)
+  std::vector<const DevBuf*> all_bufs() const {
+    return {&frames, &frame_off, &rsum, &fr_ms, &fr_part, &state, &ubuf, &dbuf, &gbuf, &zbuf,
+            &partial, &nodecount, &coef, &list_slots, &list_off, &lists, &desc, &opidx,
+            &elems, &cnn_in, &cnn_out, &tmp, &badflags, &warm_stage, &pool_idx, &pool_off,
+            &pool_states};
+  }
 };
 
 namespace {
@@ -253,6 +268,55 @@ int window_halo(double beta) {
   return 0;
 }
 
+// Bytes of the per-slot workspace for `cap` slots on levels m0..L (fields: the per-slot u, d,
+// G and z buffers; the rigid variant has none).
+struct SlotBytes {
+  size_t state, ubuf, dbuf, gbuf, zbuf, partial, nodecount, coef, list_slots, list_off, lists,
+      desc, opidx;
+};
+
+// Lays out the slot geometry of levels m0..L in hd (level geometry, u offsets, strides) and
+// returns the buffer sizes for cap slots. ensure_slots allocates them; pprs_workspace_query
+// adds them up.
+SlotBytes slot_layout(BatchDesc& hd, int cap, int L, int m0, bool fields) {
+  hd.finest = L;
+  hd.coarsest = m0;
+  int coef_off = 0;
+  long long uoff = 0;
+  int max_items = 1;
+  for (int l = 0; l < PPRS_MAXL; ++l) hd.u_off[l] = 0;
+  for (int l = m0; l <= L; ++l) {
+    fill_geom(hd.geom[l], l, coef_off);
+    coef_off += 3 * hd.geom[l].n;
+    hd.u_off[l] = uoff;
+    uoff += 4LL * hd.geom[l].n * hd.geom[l].n;
+    max_items = std::max(max_items, std::max(hd.geom[l].tiles_elem, 2 * hd.geom[l].sm_items));
+    max_items = std::max(max_items, 2 * hd.geom[l].sw_tiles * hd.geom[l].sw_tiles);
+  }
+  int nL = level_n(L);
+  hd.slot_u_stride = uoff;
+  hd.slot_f_stride = 2LL * nL * nL;
+  hd.slot_p_stride = 2LL * nL * row_pitch(nL);
+  hd.part_kind_stride = (long long)max_items * PW;
+  hd.part_slot_stride = hd.part_kind_stride * WK_COUNT;
+  hd.max_slots = cap;
+  SlotBytes b;
+  b.state = sizeof(SlotState) * cap;
+  b.ubuf = fields ? sizeof(float) * hd.slot_u_stride * cap : 0;
+  b.dbuf = fields ? sizeof(float) * hd.slot_f_stride * cap : 0;
+  b.gbuf = fields ? sizeof(float) * hd.slot_p_stride * cap : 0;
+  b.zbuf = b.gbuf;
+  b.partial = sizeof(double) * hd.part_slot_stride * cap;
+  b.nodecount = sizeof(long long) * WK_COUNT * cap;
+  b.coef = sizeof(float) * coef_off;
+  b.list_slots = sizeof(int) * WK_COUNT * cap;
+  b.list_off = sizeof(int) * WK_COUNT * (cap + 1);
+  b.lists = sizeof(WorkList) * WK_COUNT;
+  b.desc = sizeof(BatchDesc);
+  b.opidx = sizeof(int) * 3 * cap;
+  return b;
+}
+
 // Workspace for up to `cap` slots on levels m0..L, and the metric coefficients for beta.
 // fields = false (the rigid variant): state, partials and lists only, no per-slot fields.
 pprs_status ensure_slots(pprs_ctx* c, int cap, int L, int m0, double beta, bool fields = true) {
@@ -260,42 +324,22 @@ pprs_status ensure_slots(pprs_ctx* c, int cap, int L, int m0, double beta, bool 
   if (cap > c->slots_cap || L != c->slots_L || m0 != c->slots_m0 ||
       (fields && !c->slots_fields)) {
     cap = std::max(cap, c->slots_cap);
-    hd.finest = L;
-    hd.coarsest = m0;
-    int coef_off = 0;
-    long long uoff = 0;
-    int max_items = 1;
-    for (int l = 0; l < PPRS_MAXL; ++l) hd.u_off[l] = 0;
-    for (int l = m0; l <= L; ++l) {
-      fill_geom(hd.geom[l], l, coef_off);
-      coef_off += 3 * hd.geom[l].n;
-      hd.u_off[l] = uoff;
-      uoff += 4LL * hd.geom[l].n * hd.geom[l].n;
-      max_items = std::max(max_items, std::max(hd.geom[l].tiles_elem, 2 * hd.geom[l].sm_items));
-      max_items = std::max(max_items, 2 * hd.geom[l].sw_tiles * hd.geom[l].sw_tiles);
-    }
-    int nL = level_n(L);
-    hd.slot_u_stride = uoff;
-    hd.slot_f_stride = 2LL * nL * nL;
-    hd.slot_p_stride = 2LL * nL * row_pitch(nL);
-    hd.part_kind_stride = (long long)max_items * PW;
-    hd.part_slot_stride = hd.part_kind_stride * WK_COUNT;
-    hd.max_slots = cap;
-    STCHK(ensure(c->state, sizeof(SlotState) * cap));
+    SlotBytes b = slot_layout(hd, cap, L, m0, fields);
+    STCHK(ensure(c->state, b.state));
     if (fields) {
-      STCHK(ensure(c->ubuf, sizeof(float) * hd.slot_u_stride * cap));
-      STCHK(ensure(c->dbuf, sizeof(float) * hd.slot_f_stride * cap, true));
-      STCHK(ensure(c->gbuf, sizeof(float) * hd.slot_p_stride * cap));
-      STCHK(ensure(c->zbuf, sizeof(float) * hd.slot_p_stride * cap));
+      STCHK(ensure(c->ubuf, b.ubuf));
+      STCHK(ensure(c->dbuf, b.dbuf, true));
+      STCHK(ensure(c->gbuf, b.gbuf));
+      STCHK(ensure(c->zbuf, b.zbuf));
     }
-    STCHK(ensure(c->partial, sizeof(double) * hd.part_slot_stride * cap));
-    STCHK(ensure(c->nodecount, sizeof(long long) * WK_COUNT * cap));
-    STCHK(ensure(c->coef, sizeof(float) * coef_off));
-    STCHK(ensure(c->list_slots, sizeof(int) * WK_COUNT * cap));
-    STCHK(ensure(c->list_off, sizeof(int) * WK_COUNT * (cap + 1)));
-    STCHK(ensure(c->lists, sizeof(WorkList) * WK_COUNT));
-    STCHK(ensure(c->desc, sizeof(BatchDesc)));
-    STCHK(ensure(c->opidx, sizeof(int) * 3 * cap));
+    STCHK(ensure(c->partial, b.partial));
+    STCHK(ensure(c->nodecount, b.nodecount));
+    STCHK(ensure(c->coef, b.coef));
+    STCHK(ensure(c->list_slots, b.list_slots));
+    STCHK(ensure(c->list_off, b.list_off));
+    STCHK(ensure(c->lists, b.lists));
+    STCHK(ensure(c->desc, b.desc));
+    STCHK(ensure(c->opidx, b.opidx));
     hd.state = P<SlotState>(c->state);
     hd.ubuf = P<float>(c->ubuf);
     hd.dbuf = P<float>(c->dbuf);
@@ -355,6 +399,23 @@ struct SeriesIn {
   const std::vector<char>* ref_mask;
 };
 
+const int kSumBands = 16;  // row bands of the per-frame sums (elem_sums)
+
+// Buffer sizes of prepare_series for NT frames in all, at most Nmax per series, `nodes` grid
+// nodes over all pyramids.
+struct FrameBytes {
+  size_t frames, frame_off, rsum, fr_part, fr_ms;
+};
+FrameBytes frame_bytes(size_t nodes, int NT, int Nmax) {
+  FrameBytes b;
+  b.frames = sizeof(float) * std::max<size_t>(nodes, 1);
+  b.frame_off = sizeof(long long) * (size_t)NT * PPRS_MAXL;
+  b.rsum = sizeof(double) * (size_t)NT * PPRS_MAXL;
+  b.fr_part = sizeof(double) * 2 * (size_t)Nmax * kSumBands;
+  b.fr_ms = sizeof(double) * 2 * (size_t)Nmax * PPRS_MAXL;
+  return b;
+}
+
 // Normalised frame pyramids of several series in one buffer: series s, level l is a block of
 // N_s frames; the offset table maps (global frame, level) to the frame's first node.
 pprs_status prepare_series(pprs_ctx* c, const std::vector<SeriesIn>& ser) {
@@ -373,12 +434,13 @@ pprs_status prepare_series(pprs_ctx* c, const std::vector<SeriesIn>& ser) {
       for (int f = 0; f < x.N; ++f) off[(size_t)(x.f0 + f) * PPRS_MAXL + l] = total + f * nn;
       total += (size_t)x.N * nn;
     }
-  STCHK(ensure(c->frames, sizeof(float) * std::max<size_t>(total, 1)));
-  STCHK(ensure(c->frame_off, sizeof(long long) * off.size()));
-  STCHK(ensure(c->rsum, sizeof(double) * (size_t)NT * PPRS_MAXL));
-  const int bands = 16;
-  STCHK(ensure(c->fr_part, sizeof(double) * 2 * (size_t)Nmax * bands));
-  STCHK(ensure(c->fr_ms, sizeof(double) * 2 * (size_t)Nmax * PPRS_MAXL));
+  FrameBytes fb = frame_bytes(total, NT, Nmax);
+  STCHK(ensure(c->frames, fb.frames));
+  STCHK(ensure(c->frame_off, fb.frame_off));
+  STCHK(ensure(c->rsum, fb.rsum));
+  const int bands = kSumBands;
+  STCHK(ensure(c->fr_part, fb.fr_part));
+  STCHK(ensure(c->fr_ms, fb.fr_ms));
   HIPCHK(hipMemcpyAsync(c->frame_off.p, off.data(), sizeof(long long) * off.size(),
                         hipMemcpyHostToDevice, c->stream));
   hd.pyr = P<float>(c->frames);
@@ -625,6 +687,8 @@ pprs_status run_batch(pprs_ctx* c, int n, const int* ref, const int* tmpl, InitK
   HIPCHK(hipMemcpyAsync(nodes.data(), hd.node_count, sizeof(long long) * WK_COUNT * n,
                         hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+  float batch_ms = (float)std::chrono::duration<double, std::milli>(
+                       std::chrono::steady_clock::now() - t_start).count();
   for (int s = 0; s < n; ++s) {
     if (flags_or) *flags_or |= st[s].flags;
     for (int k = 0; k < WK_COUNT; ++k) c->nodes_acc[k] += nodes[(size_t)s * WK_COUNT + k];
@@ -644,6 +708,7 @@ pprs_status run_batch(pprs_ctx* c, int n, const int* ref, const int* tmpl, InitK
       o.energy = st[s].E;
       o.ncc = st[s].ncc;
       o.flags = st[s].flags;
+      o.ms = batch_ms;
     }
   }
   return PPRS_OK;
@@ -816,6 +881,7 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
   long long* doff = P<long long>(c->pool_off);
   SlotState* dstates = P<SlotState>(c->pool_states);
   std::vector<int> slot_op(S, -1), free_slots;
+  std::vector<double> op_start(n_ops, 0.0);
   for (int s = S - 1; s >= 0; --s) free_slots.push_back(s);
   std::vector<long long> nodes((size_t)S * WK_COUNT);
   c->lds_smooth[0] = smooth_lds_bytes(hd, 0);
@@ -862,6 +928,8 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
       int s = free_slots.back();
       free_slots.pop_back();
       slot_op[s] = i;
+      op_start[i] = std::chrono::duration<double, std::milli>(
+                        std::chrono::steady_clock::now() - t_start).count();
       a_slot.push_back(s);
       a_op.push_back(i);
       const PoolOp& o = ops[i];
@@ -973,9 +1041,10 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
         o.ncc = st[s].ncc;
         o.flags = st[s].flags;
       }
-      if (finish_ms)
-        (*finish_ms)[i] = std::chrono::duration<double, std::milli>(
-                              std::chrono::steady_clock::now() - t_start).count();
+      double now_ms = std::chrono::duration<double, std::milli>(
+                          std::chrono::steady_clock::now() - t_start).count();
+      if (stats) stats[i].ms = (float)(now_ms - op_start[i]);
+      if (finish_ms) (*finish_ms)[i] = now_ms;
       for (int q : dependents[i])
         if (--remaining[q] == 0) ready.push(q);
       ++done_ops;
@@ -1013,6 +1082,68 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
             n_ops, done_steps, ms);
     fflush(stderr);
   }
+  return PPRS_OK;
+}
+
+// Workspace of one cold pprs_prefix_register_series call of N frames of side H (level L,
+// coarsest m0) on a pool of pool_slots slots: the bytes of every buffer it ensures, the slot
+// count its pool takes and the slot layout (in hd). Mirrors run_series_set for one series.
+struct SeriesWs {
+  FrameBytes frames{};
+  size_t elems = 0, pool_idx = 0, pool_off = 0, pool_states = 0, tmp = 0;
+  SlotBytes slots{};
+  int n_slots = 0;
+  bool any = false;  // N > 1: the call allocates anything at all
+  size_t total() const {
+    if (!any) return 0;
+    return frames.frames + frames.frame_off + frames.rsum + frames.fr_part + frames.fr_ms +
+           elems + pool_idx + pool_off + pool_states + tmp + slots.state + slots.ubuf +
+           slots.dbuf + slots.gbuf + slots.zbuf + slots.partial + slots.nodecount +
+           slots.coef + slots.list_slots + slots.list_off + slots.lists + slots.desc +
+           slots.opidx;
+  }
+};
+
+pprs_status series_workspace(int N, int L, int m0, const pprs_params* p, int pool_slots,
+                             BatchDesc& hd, SeriesWs& w) {
+  w = SeriesWs{};
+  int M = N - 1;
+  if (M < 1) return PPRS_OK;
+  w.any = true;
+  size_t nodes = 0;
+  for (int l = m0; l <= L; ++l) nodes += (size_t)N * level_n(l) * level_n(l);
+  w.frames = frame_bytes(nodes, N, N);
+  int n_ops = 0, n_levels = 0;
+  pprs_scan_plan_p(p->scan, M, p->scan_workers, nullptr, 0, &n_ops, &n_levels);
+  std::vector<int> plan(3 * (size_t)std::max(n_ops, 1));
+  if (pprs_scan_plan_p(p->scan, M, p->scan_workers, plan.data(), n_ops, &n_ops, &n_levels) !=
+      PPRS_OK)
+    return fail(PPRS_EINVAL, "scan planning failed");
+  int widest = M;
+  for (int lv = 0, i = 0; lv < n_levels; ++lv) {
+    int cnt = 0;
+    while (i < n_ops && plan[3 * i + 2] == lv) ++cnt, ++i;
+    widest = std::max(widest, cnt);
+  }
+  int nL = level_n(L);
+  w.elems = sizeof(float) * (size_t)(M + n_ops) * 2 * nL * nL;
+  int slots = std::min(widest, pool_slots);
+  w.slots = slot_layout(hd, slots, L, m0, true);
+  int S = std::max(1, std::min(slots, M + n_ops));
+  w.n_slots = slots;
+  w.pool_idx = sizeof(int) * 4 * (size_t)S;
+  w.pool_off = sizeof(long long) * 3 * (size_t)S;
+  w.pool_states = sizeof(SlotState) * (size_t)S;
+  w.tmp = sizeof(long long) * M;
+  return PPRS_OK;
+}
+
+pprs_status series_args(int N, int H, int W, const pprs_params* params, int* L, int* m0) {
+  *L = frame_level(H, W);
+  if (*L < 0) return fail(PPRS_EINVAL, "frames must be square with side 2^L or 2^L+1, L in [2,10]");
+  if (N < 1) return fail(PPRS_EINVAL, "N must be >= 1");
+  STCHK(check_params(params, *L));
+  *m0 = *L - params->levels + 1;
   return PPRS_OK;
 }
 
@@ -1085,22 +1216,62 @@ void pprs_destroy(pprs_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  DevBuf* bufs[] = {&c->frames, &c->rsum, &c->fr_ms, &c->fr_part, &c->state, &c->ubuf,
-                    &c->dbuf, &c->gbuf, &c->zbuf, &c->partial, &c->nodecount,
-                    &c->coef, &c->list_slots, &c->list_off, &c->lists, &c->desc, &c->opidx,
-                    &c->elems, &c->cnn_in, &c->cnn_out, &c->tmp, &c->badflags};
-  for (DevBuf* b : bufs)
-    if (b->p) (void)hipFree(b->p);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   if (c->active_host) (void)hipHostFree(c->active_host);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
-  delete c;
+  delete c;  // every DevBuf frees its device memory
 }
 
-pprs_status pprs_register_pair(pprs_ctx* c, const float* f_ref, const float* f_tmpl, int H,
+pprs_status pprs_workspace_query(int N, int H, int W, const pprs_params* params, size_t* bytes) {
+  if (!bytes) return fail(PPRS_EINVAL, "bytes is NULL");
+  int L, m0;
+  STCHK(series_args(N, H, W, params, &L, &m0));
+  BatchDesc hd;
+  memset(&hd, 0, sizeof hd);
+  SeriesWs w;
+  STCHK(series_workspace(N, L, m0, params, kPoolSlotsDefault, hd, w));
+  *bytes = w.total();
+  return PPRS_OK;
+}
+
+pprs_status pprs_reserve_workspace(pprs_ctx* c, int N, int H, int W, const pprs_params* params) {
+  STCHK(enter(c));
+  int L, m0;
+  STCHK(series_args(N, H, W, params, &L, &m0));
+  BatchDesc hd;
+  memset(&hd, 0, sizeof hd);
+  SeriesWs w;
+  STCHK(series_workspace(N, L, m0, params, c->pool_slots, hd, w));
+  if (!w.any) return PPRS_OK;
+  STCHK(ensure(c->frames, w.frames.frames));
+  STCHK(ensure(c->frame_off, w.frames.frame_off));
+  STCHK(ensure(c->rsum, w.frames.rsum));
+  STCHK(ensure(c->fr_part, w.frames.fr_part));
+  STCHK(ensure(c->fr_ms, w.frames.fr_ms));
+  STCHK(ensure(c->elems, w.elems));
+  STCHK(ensure(c->pool_idx, w.pool_idx));
+  STCHK(ensure(c->pool_off, w.pool_off));
+  STCHK(ensure(c->pool_states, w.pool_states));
+  STCHK(ensure(c->tmp, w.tmp));
+  STCHK(ensure_slots(c, w.n_slots, L, m0, params->beta));
+  return PPRS_OK;
+}
+
+pprs_status pprs_workspace_bytes(pprs_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return fail(PPRS_EINVAL, "NULL argument");
+  size_t t = 0;
+  for (const DevBuf* b : c->all_bufs()) t += b->p ? b->bytes : 0;
+  *bytes = t;
+  return PPRS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+pprs_status register_pair_impl(pprs_ctx* c, const float* f_ref, const float* f_tmpl, int H,
                                int W, const float* u_init, float* u_out,
                                const pprs_params* params, pprs_pair_stats* stats) {
-  STCHK(enter(c));
   int L = frame_level(H, W);
   if (L < 0) return fail(PPRS_EINVAL, "frames must be square with side 2^L or 2^L+1, L in [2,10]");
   if (!f_ref || !f_tmpl || !u_out) return fail(PPRS_EINVAL, "NULL frame or output pointer");
@@ -1130,6 +1301,17 @@ pprs_status pprs_register_pair(pprs_ctx* c, const float* f_ref, const float* f_t
                             (float)(nL - 1), c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return status_from_flags(flags);
+}
+
+}  // namespace
+
+extern "C" {
+
+pprs_status pprs_register_pair(pprs_ctx* c, const float* f_ref, const float* f_tmpl, int H,
+                               int W, const float* u_init, float* u_out,
+                               const pprs_params* params, pprs_pair_stats* stats) {
+  STCHK(enter(c));
+  return register_pair_impl(c, f_ref, f_tmpl, H, W, u_init, u_out, params, stats);
 }
 
 pprs_status pprs_register_pairs(pprs_ctx* c, const float* frames, int N, int H, int W,
@@ -1187,6 +1369,7 @@ pprs_status run_batch_rigid(pprs_ctx* c, int n, const int* ref, const int* tmpl,
                             const double* p0, double* p_out, const pprs_params* p,
                             pprs_pair_stats* stats, int* flags_or) {
   if (n <= 0) return PPRS_OK;
+  auto t_start = std::chrono::steady_clock::now();
   BatchDesc& hd = c->hd;
   int L = hd.finest, m0 = hd.coarsest;
   hd.n_slots = n;
@@ -1241,6 +1424,8 @@ pprs_status run_batch_rigid(pprs_ctx* c, int n, const int* ref, const int* tmpl,
   HIPCHK(hipMemcpyAsync(st.data(), hd.state, sizeof(SlotState) * n, hipMemcpyDeviceToHost,
                         c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+  float batch_ms = (float)std::chrono::duration<double, std::milli>(
+                       std::chrono::steady_clock::now() - t_start).count();
   for (int s = 0; s < n; ++s) {
     if (flags_or) *flags_or |= st[s].flags;
     for (int k = 0; k < 3; ++k) p_out[3 * s + k] = st[s].rp[k];
@@ -1254,6 +1439,7 @@ pprs_status run_batch_rigid(pprs_ctx* c, int n, const int* ref, const int* tmpl,
       o.energy = st[s].E;
       o.ncc = st[s].ncc;
       o.flags = st[s].flags;
+      o.ms = batch_ms;
     }
   }
   return PPRS_OK;
@@ -1696,6 +1882,16 @@ pprs_status pprs_register_series_batch(pprs_ctx* c, int S, const float* const* f
                              latency_ms ? latency_ms + j : nullptr});
   }
   return run_series_set(c, jobs, params);
+}
+
+pprs_status pprs_prefix_register_series_batch(pprs_ctx* c, int S, const float* const* frames,
+                                              const int* N, const int* H, const int* W,
+                                              float* const* u_out, const pprs_params* params,
+                                              pprs_series_stats* stats) {
+  if (S < 1 || !H || !W) return fail(PPRS_EINVAL, "bad arguments");
+  for (int j = 0; j < S; ++j)
+    if (H[j] != W[j]) return fail(PPRS_EINVAL, "series %d: frames must be square", j);
+  return pprs_register_series_batch(c, S, frames, N, H, nullptr, u_out, params, stats, nullptr);
 }
 
 pprs_status pprs_set_metric_solve(pprs_ctx* c, int mode) {

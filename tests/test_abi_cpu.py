@@ -146,3 +146,37 @@ def test_plan_rejects_bad_arguments():
     buf = (ctypes.c_int * 3)()
     assert lib.pprs_scan_plan(1, 8, buf, 1, ctypes.byref(n), ctypes.byref(lv)) == -1
     assert n.value == 11
+
+
+def test_workspace_query_host_only():
+    """pprs_workspace_query makes no HIP call: the series workspace is planned on the host.
+    It grows with the frame count and side, is 0 for a one-frame series (nothing to register)
+    and refuses bad sizes."""
+    p = P.Params()
+    b512 = P.workspace_query(512, 512, 512, p)
+    b64 = P.workspace_query(64, 512, 512, p)
+    b256 = P.workspace_query(64, 256, 256, P.Params(levels=3))
+    assert b512 > b64 > b256 > 0
+    assert P.workspace_query(1, 512, 512, p) == 0
+    # the version buffers alone: one [2][513][513] float field per A and B application
+    assert b512 > (511 + 1004) * 2 * 513 * 513 * 4
+    # and the whole stays far inside one MI355X's 288 GB
+    assert b512 < 32 * 2 ** 30
+    for bad in [(0, 512, 512), (8, 500, 500), (8, 512, 256)]:
+        with pytest.raises(api.PprsError):
+            P.workspace_query(*bad, p)
+    with pytest.raises(api.PprsError):
+        P.workspace_query(8, 64, 64, P.Params(levels=7))
+
+
+def test_wrong_shapes_are_refused_before_the_library():
+    """The binding checks every tensor's shape against the call's sizes before it passes raw
+    pointers on (the library cannot check the extent of a device pointer). CPU tensors stand in
+    for device tensors: each refusal happens before the device check would matter."""
+    import torch
+    with pytest.raises(ValueError):
+        api._frames3(torch.zeros(4, 4))
+    with pytest.raises(ValueError):
+        api._net_batch(torch.zeros(2, 128, 128, 3), "x")
+    assert api._net_batch(torch.zeros(3, 128, 128, 2), "x") == 3
+    assert api._frames3(torch.zeros(5, 8, 8)) == (5, 8, 8)

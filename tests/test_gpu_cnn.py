@@ -53,6 +53,49 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
 
+def test_weights_blob_loaded_by_the_library():
+    """pprs_cnn_load parses the shipped weights file itself (safetensors layout, one F32
+    tensor): the parameters equal what a library reader of the same file returns, and
+    malformed blobs are refused without touching the weights."""
+    _torch()
+    import os
+    import struct
+    import paper_1712_02533_amd as P
+    from paper_1712_02533_amd.api import PprsError
+    from safetensors.numpy import load_file
+    path = os.path.join(os.path.dirname(P.__file__), "weights", "warmstart_512.safetensors")
+    net = P.WarmStartNet(seed=1)
+    before = net.get_params()
+    net.load(path)
+    want = load_file(path)["params"]
+    got = net.get_params()
+    say("loaded %d parameters from %s" % (got.size, os.path.basename(path)))
+    assert np.array_equal(got, want)
+    blob = open(path, "rb").read()
+    hl = struct.unpack("<Q", blob[:8])[0]
+    n = got.size
+    hdr = lambda j: struct.pack("<Q", len(j)) + j
+    data = np.arange(n, dtype=np.float32).tobytes()
+    good = hdr(b'{"params":{"dtype":"F32","shape":[%d],"data_offsets":[0,%d]}}' % (n, 4 * n))
+    net.load_bytes(good + data)
+    assert np.array_equal(net.get_params(), np.arange(n, dtype=np.float32))
+    bad = [blob[:7], blob[:8 + hl - 1], blob[:-4],
+           struct.pack("<Q", 1 << 40) + blob[8:],
+           hdr(b'{"params":{"dtype":"F16","shape":[%d],"data_offsets":[0,%d]}}' % (n, 4 * n))
+           + data,
+           hdr(b'{"params":{"dtype":"F32","shape":[%d],"data_offsets":[4,%d]}}' % (n, 4 * n + 4))
+           + data,
+           hdr(b'{"params":{"dtype":"F32","shape":[%d],"data_offsets":[0,%d]}' % (n, 4 * n))
+           + data,
+           hdr(b'{"other":{"dtype":"F32","shape":[1],"data_offsets":[0,4]},'
+               b'"x":{"dtype":"F32","shape":[1],"data_offsets":[0,4]}}') + data[:4]]
+    for blob_bad in bad:
+        with pytest.raises(PprsError):
+            net.load_bytes(blob_bad)
+    assert np.array_equal(net.get_params(), np.arange(n, dtype=np.float32))
+    assert not np.array_equal(before, want)
+
+
 def test_params_roundtrip_and_layout():
     _torch()
     net, p = _net_with_biases(3)

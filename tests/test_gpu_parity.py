@@ -74,53 +74,42 @@ def _pair_case(spec, i, k, levels, **kw):
                             params=_gpu_params(levels, **kw))
     u = u.cpu().numpy()
     op = _oracle_params(levels, **kw)
-    uo, sto, tr = O.register(O.frame_to_nodes(s.frames[i]), O.frame_to_nodes(s.frames[k]), op,
-                             trace_cap=8192)
-    ref = O.u_to_pixels(uo, spec.side)
-    err = np.abs(u - ref).max()
+    R, T = O.frame_to_nodes(s.frames[i]), O.frame_to_nodes(s.frames[k])
+    uo, sto, tr = O.register(R, T, op, trace_cap=8192)
     say("  gpu iters", st.iters, "passes", st.passes, "E %.9f" % st.energy)
     say("  ora iters", sto.iters, "passes", sto.trials, "E %.9f" % sto.energy)
-    say("  max abs err px", err)
     if st.iters != sto.iters:
-        m0 = int(np.log2(spec.side)) - levels + 1
-        tie = _stop_tie(st, sto, tr, op.eps, m0)
-        say("  decisions differ; stopping near-tie in the oracle trace:", tie)
-        if tie:
-            err = TIE
+        uo, sto = replay_gpu_decisions(R, T, op, st.iters, sto.iters)
+    ref = O.u_to_pixels(uo, spec.side)
+    err = np.abs(u - ref).max()
+    say("  max abs err px", err)
+    assert st.iters == sto.iters and st.passes == sto.trials
     return u, ref, st, sto, err
 
 
-# Result of a case whose decisions differ from the oracle's only at a stopping near-tie: the
-# level stops when E_k - E_{k+1} < eps, and where the oracle's decrease lies within TIE_DE of
-# eps the GPU's energies (FP32 arithmetic on an FP32-stored path that has drifted by ~1e-5 px
-# after tens of steps, i.e. energies a few 1e-6 off) may decide either way. Both runs are then
-# correct results of the method; such a case is held to the schedule bar (0.05 px RMS) instead
-# of the 1e-3 px one. (Observed: a 128^2 pair whose level-6 decrease missed eps = 3e-4 by
-# 3.2e-6 in FP64.)
-TIE = "tie"
+# Stopping near-ties. A level stops after the first step whose energy decrease falls below
+# eps; where that decrease lies within rounding of eps, the FP32 path (energies a few 1e-7 to
+# 1e-6 off after tens of steps on an FP32-stored displacement) may stop one step earlier or
+# later than the FP64 oracle, and both are correct runs of the method. Such a case is re-run
+# in the oracle with the GPU's step counts replayed (the oracle's test switch), which reports
+# how far its own energy test was from each replayed decision (tie_gap): at most TIE_DE is a
+# near-tie, and the replayed run is then held to the full bar (1e-3 px, energy, pass counts).
+# A larger gap means the GPU decided differently away from a tie, and fails. Observed once: a
+# 128^2 pair whose level-6 decrease missed eps = 3e-4 by 3.2e-6 in FP64.
 TIE_DE = 1e-5
 
 
-def _stop_tie(st, sto, tr, eps, m0):
-    """True when the first level whose accepted-step count differs ends, in the oracle trace,
-    with a decrease within TIE_DE of eps at the step where one of the runs stopped."""
-    for li, (a, b) in enumerate(zip(st.iters, sto.iters)):
-        if a == b:
-            continue
-        level = m0 + li
-        steps = tr[tr[:, 0] == level]
-        decs = steps[:, 3] - steps[:, 4]       # E0 - E1 of every accepted step of the level
-        k = min(a, b) - 1                       # the step after which one of the runs stopped
-        return 0 <= k < len(decs) and abs(decs[k] - eps) < TIE_DE
-    return False
+def replay_gpu_decisions(R, T, op, gpu_iters, ora_iters, **kw):
+    """Re-runs the oracle pair with the GPU's step counts; returns (u, stats) of that run."""
+    uo, sto, _ = O.register(R, T, op, force=list(gpu_iters), **kw)
+    say("  STOPPING NEAR-TIE: oracle iters %s, gpu %s; replayed, tie gap %.3e (bar %.0e)"
+        % (ora_iters, gpu_iters, sto.tie_gap, TIE_DE))
+    assert sto.tie_gap <= TIE_DE, "decisions differ away from a stopping near-tie"
+    return uo, sto
 
 
 def _check_pair(u, ref, err):
-    if isinstance(err, str):
-        d = np.abs(u - ref)
-        assert np.sqrt((d ** 2).mean()) < 0.05
-    else:
-        assert err < TOL_PX
+    assert err < TOL_PX
 
 
 @pytest.mark.parametrize("spec,levels", [
@@ -132,8 +121,7 @@ def _check_pair(u, ref, err):
 def test_register_pair_matches_oracle(spec, levels):
     u, ref, st, sto, err = _pair_case(spec, 0, 1, levels)
     _check_pair(u, ref, err)
-    if not isinstance(err, str):
-        assert abs(st.energy - sto.energy) < 1e-6
+    assert abs(st.energy - sto.energy) < 1e-6
 
 
 @pytest.mark.parametrize("i,k", [(0, 1), (5, 6)])
@@ -180,7 +168,11 @@ def test_identical_frames_give_identity():
     assert torch.count_nonzero(u).item() == 0
 
 
-def _series_case(spec, levels, scan):
+def _series_case(spec, levels, scan, threads=0):
+    """GPU series against the oracle series on the same frames. Every application (the N-1
+    neighbour registrations, then the B applications in schedule order) must take the oracle's
+    step and pass counts on every level; where some differ, the oracle series is re-run with the
+    GPU's counts replayed and each replayed decision must be a stopping near-tie (TIE_DE)."""
     torch = _torch()
     import paper_1712_02533_amd as P
     s = make_series(spec)
@@ -190,15 +182,40 @@ def _series_case(spec, levels, scan):
                                           want_op_stats=True)
     u = u.cpu().numpy()
     fr = np.stack([O.frame_to_nodes(f) for f in s.frames])
-    uo, a, b, pairs = O.series(fr, _oracle_params(levels), scan=scan)
+    op = _oracle_params(levels)
+    uo, a, b, pairs = O.series(fr, op, scan=scan, threads=threads)
+    ora = list(a) + list(b)
+    assert len(ops) == len(ora)
+    differ = [k for k in range(len(ora)) if ops[k].iters != ora[k].iters]
+    if differ:
+        M = spec.n_frames - 1
+        say("  STOPPING NEAR-TIE candidates (op: oracle / gpu iters):",
+            [(k, ora[k].iters, ops[k].iters) for k in differ])
+        uo, a, b, pairs = O.series(fr, op, scan=scan, threads=threads,
+                                   force_a=[ops[k].iters for k in range(M)],
+                                   force_b=[ops[k].iters for k in range(M, len(ops))])
+        ora = list(a) + list(b)
+        gaps = [o.tie_gap for o in ora]
+        say("  replayed; largest tie gap %.3e (bar %.0e)" % (max(gaps), TIE_DE))
+        assert max(gaps) <= TIE_DE, "decisions differ away from a stopping near-tie"
+    assert all(g.iters == o.iters and g.passes == o.trials for g, o in zip(ops, ora))
     ref = np.stack([O.u_to_pixels(x, spec.side) for x in uo])
     err = np.abs(u - ref).max()
+    d = np.abs(u - ref)
     say("  ops", st.n_ops_a, st.n_ops_b, "levels", st.n_scan_levels, "ms %.1f" % st.ms_total,
-        "max abs err px", err)
-    mism = [k for k in range(len(a)) if ops[k].iters != a[k].iters]
-    say("  A ops with different iteration counts:", mism)
-    _series_case.last = (ops, a, b)
+        "max abs err px %.2e rms %.2e p99.9 %.2e" % (err, np.sqrt((d ** 2).mean()),
+                                                    np.percentile(d, 99.9)))
     return u, ref, err
+
+
+def _full_size_bar(u, ref):
+    """The bar where FP32 storage of u alone moves the FP64 oracle by ~1e-2 px at isolated
+    nodes (test_fp32_storage_sensitivity_at_full_size): RMS < 1e-4 px, 99.9th percentile
+    < 1e-3 px, max < 0.05 px, with identical decisions (checked by the caller)."""
+    d = np.abs(u - ref)
+    assert np.sqrt((d ** 2).mean()) < 1e-4
+    assert np.percentile(d, 99.9) < 1e-3
+    assert d.max() < 0.05
 
 
 def test_series_c1_sequential_matches_oracle():
@@ -215,17 +232,9 @@ def test_series_parallel_scans_match_oracle(scan):
         assert err < TOL_PX
         return
     # the general strategy's last B applications register frames up to 10 apart from a
-    # composed start (103 steps on one level here): a long registration, held to that bar —
-    # identical decisions on every application, RMS < 1e-4 px, 99.9th percentile < 1e-3 px,
-    # max < 0.05 px (measured: 6.4e-3 px max at 26 nodes of one frame, 2.1e-5 px RMS)
-    ops, a, b = _series_case.last
-    ora = list(a) + list(b)
-    assert len(ops) == len(ora)
-    assert all(g.iters == o.iters and g.passes == o.trials for g, o in zip(ops, ora))
-    d = np.abs(u - ref)
-    assert np.sqrt((d ** 2).mean()) < 1e-4
-    assert np.percentile(d, 99.9) < 1e-3
-    assert err < 0.05
+    # composed start (103 steps on one level here): a long registration, held to the full-size
+    # bar (measured: 6.4e-3 px max at 26 nodes of one frame, 2.1e-5 px RMS)
+    _full_size_bar(u, ref)
 
 
 def test_invalid_inputs_raise():
@@ -241,6 +250,71 @@ def test_invalid_inputs_raise():
         P.register_pair(t[:60, :60].contiguous(), t[:60, :60].contiguous(), params=_gpu_params(2))
     with pytest.raises(PprsError):
         P.register_pair(t, t, params=_gpu_params(9))
+    # wrong shapes are refused by the binding before any pointer reaches the library
+    with pytest.raises(ValueError):
+        P.register_pair(t, t, params=_gpu_params(2), out=torch.empty((2, 32, 32), device="cuda"))
+    with pytest.raises(ValueError):
+        P.register_pair(t, t, u_init=torch.zeros((2, 64, 32), device="cuda"),
+                        params=_gpu_params(2))
+    with pytest.raises(ValueError):
+        P.register_pair(t, t[:32].contiguous(), params=_gpu_params(2))
+    u = torch.zeros((2, 64, 64), device="cuda")
+    with pytest.raises(ValueError):
+        P.compose_deformations(u, torch.zeros((2, 64, 63), device="cuda"))
+    with pytest.raises(ValueError):
+        P.compose_deformations(u, u, out=torch.empty((2, 32, 64), device="cuda"))
+    fr = torch.rand((3, 64, 64), device="cuda")
+    with pytest.raises(ValueError):
+        P.register_pairs(fr, [0, 1], [1, 2], params=_gpu_params(2),
+                         out=torch.empty((1, 2, 64, 64), device="cuda"))
+    with pytest.raises(ValueError):
+        P.prefix_register_series(fr, params=_gpu_params(2),
+                                 out=torch.empty((2, 2, 64, 64), device="cuda"))
+    with pytest.raises(ValueError):
+        P.register_series_batch([fr, fr], params=_gpu_params(2), levels=[2])
+    with pytest.raises(ValueError):
+        P.register_series_batch([fr], params=_gpu_params(2),
+                                outs=[torch.empty((3, 2, 64, 32), device="cuda")])
+    with pytest.raises(ValueError):
+        P.series_average(fr, torch.zeros((3, 2, 64, 64), device="cuda"),
+                         out=torch.empty((64, 63), device="cuda"))
+
+
+def test_workspace_reserve_then_series_allocates_nothing_more():
+    """pprs_reserve_workspace sizes a context for a series call; the call then grows no buffer,
+    and what the context holds is what pprs_workspace_query reported."""
+    torch = _torch()
+    import paper_1712_02533_amd as P
+    s = make_series(SeriesSpec(16, 256, 4.0, 1.0, 10.0, 41))
+    frames = torch.tensor(s.frames, device="cuda")
+    params = _gpu_params(3, scan="brent_kung")
+    stream = torch.cuda.Stream()        # a fresh context (contexts are per stream)
+    with torch.cuda.stream(stream):
+        q = P.workspace_query(16, 256, 256, params)
+        P.reserve_workspace(16, 256, 256, params)
+        held = P.workspace_bytes()
+        u, st, ops = P.prefix_register_series(frames, params=params, want_op_stats=True)
+        after = P.workspace_bytes()
+    stream.synchronize()
+    say("workspace: query %d, reserved %d, after the series %d bytes" % (q, held, after))
+    assert held == q and after == held
+    ref, _, _ = P.prefix_register_series(frames, params=params)
+    assert torch.equal(u, ref)
+    assert all(o.ms > 0 for o in ops)
+
+
+def test_prefix_register_series_batch_alias():
+    """pprs_prefix_register_series_batch (per-series H and W) gives the results of
+    pprs_register_series_batch for the same series."""
+    torch = _torch()
+    import paper_1712_02533_amd as P
+    frames = [torch.tensor(make_series(SeriesSpec(n, sd, 2.0, 0.0, 20.0, 50 + n)).frames,
+                           device="cuda") for n, sd in [(5, 64), (4, 128)]]
+    params = _gpu_params(2, scan="brent_kung")
+    a, sa = P.prefix_register_series_batch(frames, params=params)
+    b, sb, _ = P.register_series_batch(frames, params=params)
+    for x, y, p, q in zip(a, b, sa, sb):
+        assert torch.equal(x, y) and p.node_steps == q.node_steps
 
 
 def test_series_pool_shape_does_not_change_results():
