@@ -138,6 +138,20 @@ pprs_status pprs_register_pair(pprs_ctx* ctx, const float* f_ref, const float* f
                                int W, const float* u_init, float* u_out,
                                const pprs_params* params, pprs_pair_stats* stats);
 
+/* pprs_register_pair for callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same registration and
+   the same result bits, with every working buffer carved from a fixed scratch array in the
+   library (PPRS_SCRATCH_BYTES = 24 MiB per device, held until the process ends) instead of the
+   context's workspace. It calls no hipMalloc, hipFree or other allocating routine. Frames up to
+   512 x 512 (513 x 513 nodes) fit at any level count; larger frames are PPRS_EINVAL. The
+   caller still passes ctx (its stream and launch shape), the inputs and the output. All calls
+   on one device share that device's scratch and it keeps the last call's contents (whatever
+   must start at zero is cleared by the call): calls that overlap on one device, from any
+   context or thread, race and must not be made. Synchronous on ctx's stream. */
+pprs_status pprs_register_pair_noalloc(pprs_ctx* ctx, const float* f_ref, const float* f_tmpl,
+                                       int H, int W, const float* u_init, float* u_out,
+                                       const pprs_params* params, pprs_pair_stats* stats);
+
 /* Function A over a batch: for p < P registers frames[tmpl[p]] to frames[ref[p]] (as
    pprs_register_pair with the identity start, or the learned warm start when it is enabled on
    ctx). frames: device [N][H][W]; ref, tmpl: host arrays of P indices in [0, N);

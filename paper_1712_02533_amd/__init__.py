@@ -12,7 +12,7 @@ from .api import (Params, PairStats, SeriesStats, compose_deformations, default_
                   set_metric_solve,
                   Context, WarmStartNet, pair_inputs,
                   level7_targets, set_warm_start, workspace_query, reserve_workspace,
-                  workspace_bytes, prefix_register_series_batch)
+                  workspace_bytes, prefix_register_series_batch, register_pair_noalloc)
 
 __all__ = ["Params", "PairStats", "SeriesStats", "compose_deformations", "default_params",
            "kernel_names", "kernel_timing", "prefix_register_series",
@@ -21,4 +21,4 @@ __all__ = ["Params", "PairStats", "SeriesStats", "compose_deformations", "defaul
            "scan_plan", "series_average", "set_kernel_timing", "set_pool", "get_tuning", "set_tuning",
            "set_metric_solve", "Context", "WarmStartNet", "pair_inputs",
            "level7_targets", "set_warm_start", "workspace_query", "reserve_workspace",
-           "workspace_bytes", "prefix_register_series_batch"]
+           "workspace_bytes", "prefix_register_series_batch", "register_pair_noalloc"]

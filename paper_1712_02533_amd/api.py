@@ -124,6 +124,9 @@ def _lib():
                 "pprs_last_error": (ctypes.c_char_p, []),
                 "pprs_register_pair": (i, [vp, vp, vp, i, i, vp, vp, ctypes.POINTER(_CParams),
                                            ctypes.POINTER(_CPairStats)]),
+                "pprs_register_pair_noalloc": (i, [vp, vp, vp, i, i, vp, vp,
+                                                   ctypes.POINTER(_CParams),
+                                                   ctypes.POINTER(_CPairStats)]),
                 "pprs_register_pairs": (i, [vp, vp, i, i, i, vp, vp, i, vp,
                                             ctypes.POINTER(_CParams),
                                             ctypes.POINTER(_CPairStats)]),
@@ -290,6 +293,27 @@ def register_pair(f_ref, f_tmpl, u_init=None, params: Params | None = None, out=
     c = _ctx(dev)
     _check(_lib().pprs_register_pair(c.handle, a_ref, a_tmpl, H, W, a_init, a_out,
                                      ctypes.byref(cp), ctypes.byref(st)))
+    return out, _pair_stats(st, params.levels)
+
+
+def register_pair_noalloc(f_ref, f_tmpl, out, u_init=None, params: Params | None = None):
+    """Function A through pprs_register_pair_noalloc: the library allocates nothing (its
+    buffers lie in a fixed per-device scratch array; frames up to 512 x 512). out [2, H, W] is
+    the caller's. Returns (out, PairStats)."""
+    params = params or Params()
+    if f_ref.dim() != 2:
+        raise ValueError("f_ref must be [H, W], got %s" % (tuple(f_ref.shape),))
+    H, W = f_ref.shape
+    dev = f_ref.device
+    st = _CPairStats()
+    cp = params.c()
+    a_ref = _dev_f32(f_ref, "f_ref")
+    a_tmpl = _dev_f32(f_tmpl, "f_tmpl", (H, W), dev)
+    a_init = _dev_f32(u_init, "u_init", (2, H, W), dev) if u_init is not None else None
+    a_out = _dev_f32(out, "out", (2, H, W), dev)
+    c = _ctx(dev)
+    _check(_lib().pprs_register_pair_noalloc(c.handle, a_ref, a_tmpl, H, W, a_init, a_out,
+                                             ctypes.byref(cp), ctypes.byref(st)))
     return out, _pair_stats(st, params.levels)
 
 

@@ -18,6 +18,7 @@
 #include <vector>
 #include <queue>
 #include <functional>
+#include <mutex>
 
 #include "../../include/pprs.h"
 #include "kernels.h"
@@ -67,17 +68,30 @@ namespace {
 const int kGridFin = 512;       // finalisation: one workgroup per listed slot (grid-stride)
 const int kPoolSlotsDefault = 512;  // concurrent registrations of a series (pprs_set_pool)
 
-// A device buffer owned by a context: grown by ensure(), freed with the context.
+// A device buffer of a context: grown by ensure(), freed with the context unless it is a
+// piece of the allocation-free entry point's scratch array (owned = false).
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool owned = true;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() {
-    if (p) (void)hipFree(p);
+    if (p && owned) (void)hipFree(p);
   }
 };
+
+// The allocation-free entry point hands ensure() a bump arena over the device's scratch array
+// for the duration of its call (set on the calling thread only): buffers are then carved from
+// it instead of allocated.
+struct Arena {
+  char* base;
+  size_t size, used;
+  hipStream_t stream;
+};
+thread_local Arena* g_arena = nullptr;
+const size_t kArenaAlign = 256;
 
 enum { TK_PLAN = 0, TK_PROLONG, TK_EVAL, TK_GRAD, TK_SMY, TK_SMX, TK_LADDER, TK_FIN, TK_SMW,
        TK_COUNT };
@@ -146,6 +160,20 @@ namespace {
 
 pprs_status ensure(DevBuf& b, size_t bytes, bool zero = false) {
   if (b.bytes >= bytes && b.p) return PPRS_OK;
+  if (g_arena) {
+    size_t off = (g_arena->used + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
+    if (off + bytes > g_arena->size)
+      return fail(PPRS_ENOMEM, "scratch array exhausted (%zu of %zu bytes needed)", off + bytes,
+                  g_arena->size);
+    b.p = g_arena->base + off;
+    b.bytes = bytes;
+    b.owned = false;
+    g_arena->used = off + bytes;
+    // the scratch keeps the previous call's contents: clear what must start at zero
+    if (zero) HIPCHK(pprs_k::fill((float*)b.p, (long long)(bytes / sizeof(float)), 0.f,
+                                  g_arena->stream));
+    return PPRS_OK;
+  }
   if (b.p) {
     (void)hipFree(b.p);
     b.p = nullptr;
@@ -1161,6 +1189,60 @@ pprs_status enter(pprs_ctx* c) {
 
 }  // namespace
 
+// ---- allocation-free pair registration ----------------------------------------------------
+// pprs_register_pair_noalloc carves every buffer of one pair registration out of this array
+// instead of allocating: frame staging and pyramids, the slot's fields, partial records and
+// lists. Each device the library runs on holds its own copy until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress returns for that device (the
+// array's name is a host-side stand-in, not a device address).
+#define PPRS_SCRATCH_BYTES (24u << 20)
+static __device__ __align__(256) unsigned char scratch[PPRS_SCRATCH_BYTES];
+
+namespace {
+
+const int kMaxScratchDevices = 64;
+void* g_scratch_dev[kMaxScratchDevices] = {nullptr};
+std::mutex g_scratch_mu;
+
+// Device address of `device`'s scratch array, looked up once per device with it current.
+pprs_status scratch_for_device(int device, char** out) {
+  if (device < 0 || device >= kMaxScratchDevices)
+    return fail(PPRS_EINVAL, "device %d beyond the scratch table", device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    HIPCHK(hipSetDevice(device));
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(PPRS_EHIP, "no device address for the scratch array");
+    g_scratch_dev[device] = p;
+  }
+  *out = (char*)g_scratch_dev[device];
+  return PPRS_OK;
+}
+
+size_t align_up(size_t b) { return (b + kArenaAlign - 1) / kArenaAlign * kArenaAlign; }
+
+// Scratch a pair registration of H x W frames on levels m0..L carves (an upper bound: every
+// buffer padded to the arena alignment), in the order pprs_register_pair ensures them.
+size_t pair_scratch_bytes(int H, int W, int L, int m0) {
+  int nL = level_n(L);
+  size_t t = align_up(sizeof(float) * std::max((size_t)2 * H * W, (size_t)2 * nL * nL));
+  size_t nodes = 0;
+  for (int l = m0; l <= L; ++l) nodes += 2 * (size_t)level_n(l) * level_n(l);
+  FrameBytes f = frame_bytes(nodes, 2, 2);
+  t += align_up(f.frames) + align_up(f.frame_off) + align_up(f.rsum) + align_up(f.fr_part) +
+       align_up(f.fr_ms);
+  BatchDesc hd;
+  memset(&hd, 0, sizeof hd);
+  SlotBytes b = slot_layout(hd, 1, L, m0, true);
+  for (size_t x : {b.state, b.ubuf, b.dbuf, b.gbuf, b.zbuf, b.partial, b.nodecount, b.coef,
+                   b.list_slots, b.list_off, b.lists, b.desc, b.opidx})
+    t += align_up(x);
+  return t;
+}
+
+}  // namespace
+
 // ---- C-ABI ---------------------------------------------------------------------------------
 
 extern "C" {
@@ -1208,6 +1290,12 @@ pprs_status pprs_create(pprs_ctx** out, int device, void* stream) {
   }
   hipError_t e = hipHostMalloc((void**)&c->active_host, sizeof(int), hipHostMallocDefault);
   if (e != hipSuccess) c->active_host = nullptr;
+  char* sp = nullptr;
+  pprs_status ss = scratch_for_device(device, &sp);  // once per device, this device current
+  if (ss != PPRS_OK) {
+    pprs_destroy(c);
+    return ss;
+  }
   *out = c;
   return PPRS_OK;
 }
@@ -1312,6 +1400,41 @@ pprs_status pprs_register_pair(pprs_ctx* c, const float* f_ref, const float* f_t
                                const pprs_params* params, pprs_pair_stats* stats) {
   STCHK(enter(c));
   return register_pair_impl(c, f_ref, f_tmpl, H, W, u_init, u_out, params, stats);
+}
+
+pprs_status pprs_register_pair_noalloc(pprs_ctx* c, const float* f_ref, const float* f_tmpl,
+                                       int H, int W, const float* u_init, float* u_out,
+                                       const pprs_params* params, pprs_pair_stats* stats) {
+  STCHK(enter(c));
+  int L = frame_level(H, W);
+  if (L < 0) return fail(PPRS_EINVAL, "frames must be square with side 2^L or 2^L+1, L in [2,10]");
+  STCHK(check_params(params, L));
+  size_t need = pair_scratch_bytes(H, W, L, L - params->levels + 1);
+  if (need > PPRS_SCRATCH_BYTES)
+    return fail(PPRS_EINVAL,
+                "frames of %d x %d need %zu bytes of scratch; the allocation-free entry point "
+                "has %u (frames up to 512 x 512)", H, W, need, PPRS_SCRATCH_BYTES);
+  char* base = nullptr;
+  STCHK(scratch_for_device(c->device, &base));
+  // a context of the caller's stream and launch shape whose buffers all lie in the scratch
+  pprs_ctx w;
+  memset(&w.hd, 0, sizeof(BatchDesc));
+  w.device = c->device;
+  w.stream = c->stream;
+  w.log = c->log;
+  w.grid_energy = c->grid_energy;
+  w.grid_grad = c->grid_grad;
+  w.grid_smooth = c->grid_smooth;
+  w.grid_prolong = c->grid_prolong;
+  w.smooth_window = c->smooth_window;
+  w.tile_grad = c->tile_grad;
+  w.ladder_rungs = c->ladder_rungs;
+  w.smooth_lines = c->smooth_lines;
+  Arena arena{base, PPRS_SCRATCH_BYTES, 0, c->stream};
+  g_arena = &arena;
+  pprs_status s = register_pair_impl(&w, f_ref, f_tmpl, H, W, u_init, u_out, params, stats);
+  g_arena = nullptr;
+  return s;
 }
 
 pprs_status pprs_register_pairs(pprs_ctx* c, const float* frames, int N, int H, int W,
