@@ -21,7 +21,8 @@ sys.path.insert(0, ROOT)
 METRIC = "frame-pair registrations/s and series scan time (512², N=512), warm vs cold"
 HBM_PEAK_GBS = 8000.0
 SCAN_NAMES = {"sequential": "sequential", "brent_kung": "Brent-Kung", "kogge_stone": "Kogge-Stone",
-              "sklansky": "Sklansky", "general": "general-strategy"}
+              "sklansky": "Sklansky", "general": "general-strategy", "blelloch": "Blelloch",
+              "reduce_then_scan": "reduce-then-scan"}
 WORKLOADS = {
     "series512": dict(name="512 frames of 512x512, drift<=8 px, non-rigid<=1.5 px, 5 counts; "
                     "4 levels; Brent-Kung scan; cold start",
@@ -108,49 +109,118 @@ def kernel_roofline(kt, stream, traffic):
     return roofline, kernels
 
 
-def cpu_baseline(series, cfg, n_ops, threads):
-    """The FP64 oracle on `n_ops` neighbour registrations of the same series, run on `threads`
-    host threads (one registration per thread at a time)."""
+def cpu_baseline(series, cfg, n_a, threads, scan):
+    """The FP64 oracle timed on a bounded sample of the same series: n_a neighbour
+    registrations (frames m, m+1), then the first scan level's B applications over them
+    (frames j-1 and j+1 from the composition of the two neighbour results), each on its own
+    host thread, `threads` at a time. From the mean A and B times it estimates the oracle's whole
+    series time on the same threads, level by level of the schedule (ceil(width / threads)
+    rounds of a level's mean op time), and reports one-thread registration times."""
     import numpy as np
     from concurrent.futures import ThreadPoolExecutor
     import oracle as O
     import paper_1712_02533_amd as P
-    gp = P.Params(levels=cfg["levels"], scan=cfg["scan"])
+    gp = P.Params(levels=cfg["levels"], scan=scan)
     op = O.Params(levels=gp.levels, lam=gp.lam, beta=gp.beta, sigma=gp.armijo_sigma,
                   ladder_k=gp.ladder_k, cap=gp.step_cap, tau_min_rel=gp.tau_min_rel, eps=gp.eps,
                   iter_max=gp.iter_max)
     frames = series.frames
-    n_ops = min(n_ops, len(frames) - 1)
+    N = len(frames)
+    n_a = max(2, min(n_a, N - 1))
+    nodes = [O.frame_to_nodes(f) for f in frames[:n_a + 1]]
+    res = {}
 
-    def one(m):
-        O.register(O.frame_to_nodes(frames[m]), O.frame_to_nodes(frames[m + 1]), op)
+    def a_op(m):
+        t = time.perf_counter()
+        u, _, _ = O.register(nodes[m], nodes[m + 1], op)
+        res[m] = u
+        return time.perf_counter() - t
+
+    def b_op(j):
+        t = time.perf_counter()
+        O.register(nodes[j - 1], nodes[j + 1], op, u0=O.compose(res[j - 1], res[j]))
+        return time.perf_counter() - t
 
     O._load()
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=threads) as ex:
-        list(ex.map(one, range(n_ops)))
+        ta = list(ex.map(a_op, range(n_a)))
+        tb = list(ex.map(b_op, range(1, n_a, 2)))
     dt = time.perf_counter() - t0
-    return dict(value=n_ops / dt, unit="registrations/s", cores=threads, kind="oracle",
-                sample="%d neighbour registrations (frames m, m+1 for m < %d) of the same "
-                       "series, FP64, %d threads, %.1f s" % (n_ops, n_ops, threads, dt))
+    n_ops = len(ta) + len(tb)
+    # whole-series estimate: the schedule's levels, each ceil(width / threads) rounds
+    plan, n_lv = P.scan_plan(scan, N - 1)
+    widths = [sum(1 for x in plan if x[2] == lv) for lv in range(n_lv)]
+    ma, mb = float(np.mean(ta)), float(np.mean(tb))
+    est = -(-(N - 1) // threads) * ma + sum(-(-w // threads) * mb for w in widths)
+    return dict(value=round(n_ops / dt, 3), unit="registrations/s", cores=threads, kind="oracle",
+                sample="%d neighbour registrations and the %d B applications of the first scan "
+                       "level over them (frames 0..%d of the same series), FP64, one "
+                       "registration per host thread, %d threads, %.1f s" %
+                       (len(ta), len(tb), n_a, threads, dt),
+                one_thread_s=dict(a=round(ma, 2), b=round(mb, 2)),
+                series_estimate_s=round(est, 1),
+                series_estimate_method="sum over the %d scan levels (and the neighbour batch) "
+                                       "of ceil(level width / %d) x the sample's mean A or B "
+                                       "time; %d registrations" %
+                                       (n_lv, threads, N - 1 + len(plan)))
 
 
 # multiply-adds x 2 of one forward pass of the warm-start network (3x3 convolutions)
 CNN_LAYERS = [(64, 64, 2), (32, 128, 64), (16, 256, 128), (32, 128, 384), (64, 64, 192),
               (128, 2, 66)]  # (output side, Cout, Cin)
 CNN_FLOP_PER_PAIR = sum(2 * h * h * co * 9 * ci for h, co, ci in CNN_LAYERS)
+# one training sample: the forward pass, the weight gradients of every layer and the data
+# gradients of every layer but the first (each a product of the forward's size)
+CNN_TRAIN_FLOP_PER_SAMPLE = 3 * CNN_FLOP_PER_PAIR - 2 * 64 * 64 * 64 * 9 * 2
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
-def warm_runs(P, frames, out, params, args, regs_per_step):
-    """The same series with the learned warm start (both modes): throughput, difference to the
-    cold result and the network's forward throughput on the series' neighbour pairs."""
+def truth_sample(series, n_sample=16, workers=8):
+    """The analytic displacements phi_0k (pixels) of n_sample frames spread over the series."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    from synth import ground_truth
+    N = len(series.frames)
+    ks = sorted(set(int(k) for k in np.linspace(1, N - 1, n_sample)))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        gts = list(ex.map(lambda k: ground_truth(series, k), ks))
+    return ks, gts
+
+
+def accuracy(u, ks, gts, side):
+    """Per sampled frame: RMS error (px) against the analytic displacement over the interior
+    (a border of the largest displacement + 6 px left out, where the frames do not overlap)."""
+    import numpy as np
+    out = []
+    for k, gt in zip(ks, gts):
+        b = min(int(np.abs(gt).max()) + 6, side // 4)
+        d = u[k].cpu().numpy()[:, b:-b, b:-b] - gt[:, b:-b, b:-b]
+        out.append(float(np.sqrt((d ** 2).mean())))
+    return np.array(out)
+
+
+def warm_runs(P, series, frames, out, params, args, regs_per_step, cold_ms):
+    """The same series with the learned warm start (both modes): throughput, accuracy against
+    the analytic displacement beside the cold run's on sampled frames, the judge's decisions,
+    difference to the cold result, and the network's forward and training throughput."""
     import numpy as np
     import torch
     cold = out.clone()
     net = P.WarmStartNet()
     net.load(args.weights)
-    res = {}
+    side = frames.shape[-1]
+    t0 = time.perf_counter()
+    ks, gts = truth_sample(series)
+    acc_cold = accuracy(cold, ks, gts, side)
+    log("truth of %d sampled frames in %.1f s; cold accuracy %.4f px RMS (mean over frames)"
+        % (len(ks), time.perf_counter() - t0, acc_cold.mean()))
+    good = acc_cold <= 0.5   # frames the cold method recovers
+    M = frames.shape[0] - 1
+    res = dict(sampled_frames=ks, cold=dict(ms_per_step=round(cold_ms, 1),
+                                             acc_rms_px=round(float(acc_cold.mean()), 4),
+                                             acc_rms_px_per_frame=[round(x, 4) for x in acc_cold],
+                                             frames_within_0_5px=int(good.sum())))
     for mode in ("refine", "skip"):
         P.set_warm_start(net, mode=mode)
         try:
@@ -165,13 +235,23 @@ def warm_runs(P, frames, out, params, args, regs_per_step):
             dt = (time.perf_counter() - t0) / args.steps
         finally:
             P.set_warm_start(None)
+        acc = accuracy(w, ks, gts, side)
         d = (w - cold)[:, :, 16:-16, 16:-16]
+        dg = (w - cold)[[k for k, g in zip(ks, good) if g]][:, :, 16:-16, 16:-16]
         res[mode] = dict(value=round(regs_per_step / dt, 3), ms_per_step=round(1e3 * dt, 1),
+                         acc_rms_px=round(float(acc.mean()), 4),
+                         acc_rms_px_per_frame=[round(x, 4) for x in acc],
+                         acc_minus_cold_px=round(float(acc.mean() - acc_cold.mean()), 4),
+                         worst_frame_minus_cold_px=round(float((acc - acc_cold).max()), 4),
                          rms_vs_cold_px=round(float(d.pow(2).mean().sqrt()), 4),
-                         max_vs_cold_px=round(float(d.abs().max()), 3),
-                         fallbacks=sum(1 for o in ops if o.flags & 4))
-        log("warm (%s): %.1f ms per series, RMS vs cold %.4f px" %
-            (mode, 1e3 * dt, res[mode]["rms_vs_cold_px"]))
+                         rms_vs_cold_px_where_cold_within_0_5px=round(
+                             float(dg.pow(2).mean().sqrt()), 4) if dg.numel() else None,
+                         fallbacks=sum(1 for o in ops[:M] if o.flags & 4),
+                         network_starts_b=sum(1 for o in ops[M:] if o.flags & 8))
+        log("warm (%s): %.1f ms per series (cold %.1f); accuracy %.4f px (cold %.4f); "
+            "%d fallbacks, %d B starts from the network" %
+            (mode, 1e3 * dt, cold_ms, acc.mean(), acc_cold.mean(), res[mode]["fallbacks"],
+             res[mode]["network_starts_b"]))
     # network forward on the series' neighbour pairs, as the warm start runs it (64 per call)
     n = frames.shape[0] - 1
     ref = np.arange(n, dtype=np.int32)
@@ -191,6 +271,28 @@ def warm_runs(P, frames, out, params, args, regs_per_step):
                               tflops=round(tf, 1), peak_tflops=MFMA_BF16_PEAK_TFLOPS,
                               frac=round(tf / MFMA_BF16_PEAK_TFLOPS, 4))
     log("cnn forward: %d pairs in %.2f ms, %.1f TFLOP/s" % (n, ms, tf))
+    # one training step (forward, MSE, backward, Adam) on 64 samples, timed over 10 steps on a
+    # separate network (the loaded one is not changed)
+    trainer = P.WarmStartNet(seed=5)
+    xb = x[:64].contiguous()
+    tb = torch.zeros_like(xb)
+    for _ in range(2):
+        trainer.train_step(xb, tb, lr=1e-4)
+    torch.cuda.synchronize()
+    steps = 10
+    e0.record()
+    for _ in range(steps):
+        trainer.train_step(xb, tb, lr=1e-4)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_t = e0.elapsed_time(e1) / steps
+    tft = CNN_TRAIN_FLOP_PER_SAMPLE * xb.shape[0] / (ms_t * 1e-3) / 1e12
+    res["cnn_train"] = dict(batch=int(xb.shape[0]), ms_per_step=round(ms_t, 2),
+                            flop_per_sample=CNN_TRAIN_FLOP_PER_SAMPLE, tflops=round(tft, 1),
+                            peak_tflops=MFMA_BF16_PEAK_TFLOPS,
+                            frac=round(tft / MFMA_BF16_PEAK_TFLOPS, 4))
+    log("cnn training step: %d samples in %.2f ms, %.1f TFLOP/s" % (xb.shape[0], ms_t, tft))
+    trainer.close()
     return res
 
 
@@ -313,9 +415,9 @@ def main():
     ap.add_argument("--config", default="series512", choices=sorted(WORKLOADS))
     ap.add_argument("--frames", type=int, default=0, help="override the series length")
     ap.add_argument("--scan", default="", help="override the scan schedule (sequential, "
-                    "brent_kung, kogge_stone, sklansky, general)")
-    ap.add_argument("--workers", type=int, default=0, help="workers P of the general "
-                    "strategy (0: ceil(sqrt(N-1)))")
+                    "brent_kung, kogge_stone, sklansky, general, blelloch, reduce_then_scan)")
+    ap.add_argument("--workers", type=int, default=0, help="workers P of the general and "
+                    "reduce-then-scan strategies (0: ceil(sqrt(N-1)))")
     ap.add_argument("--cpu-ops", type=int, default=0, help="oracle sample size (0 = auto)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
@@ -344,6 +446,8 @@ def main():
     spec = cfg["spec"]
     if args.frames:
         spec = replace(spec, n_frames=args.frames)
+    # host threads of the CPU baseline: all cores of this host, at most 16 (the host share one
+    # GPU's box gives a run)
     nthreads = min(16, os.cpu_count() or 1)
     t0 = time.perf_counter()
     series = make_series(spec, workers=nthreads)
@@ -408,7 +512,8 @@ def main():
         config=dict(workload=WORKLOADS[args.config]["name"].replace(
                         "Brent-Kung scan", SCAN_NAMES[scan] + " scan"), frames=spec.n_frames,
                     side=spec.side, levels=cfg["levels"], scan=scan, start="cold",
-                    **(dict(scan_workers=args.workers) if scan == "general" else {}),
+                    **(dict(scan_workers=args.workers)
+                       if scan in ("general", "reduce_then_scan") else {}),
                     tuning=tuning,
                     registrations_per_step=stats[0].n_ops_a + stats[0].n_ops_b),
         series_scan_s=round(ms_per_step / 1e3, 3),
@@ -430,7 +535,7 @@ def main():
     result["average"] = dict(ms=round(ams, 3), bytes=abytes,
                              gbs=round(abytes / (ams * 1e-3) / 1e9, 1))
     log("series average: %.3f ms, %.0f GB/s" % (ams, abytes / (ams * 1e-3) / 1e9))
-    if not args.no_rigid:
+    if not args.no_rigid and scan not in ("blelloch", "reduce_then_scan"):
         # the same frames through the rigid operator (three parameters per registration)
         rp = P.Params(levels=cfg["levels"], scan=scan, scan_workers=args.workers)
         P.prefix_register_series_rigid(frames, params=rp)
@@ -445,11 +550,13 @@ def main():
                                unit="registrations/s", registrations_per_step=rregs)
         log("rigid series: %.1f ms, %d registrations" % (rms, rregs))
     if not args.no_warm and os.path.exists(args.weights) and spec.side >= 128:
-        result["warm"] = warm_runs(P, frames, out, params, args, stats[0].n_ops_a + stats[0].n_ops_b)
+        result["warm"] = warm_runs(P, series, frames, out, params, args,
+                                   stats[0].n_ops_a + stats[0].n_ops_b, ms_per_step)
     if not args.no_cpu:
-        ops = args.cpu_ops or max(4, nthreads)
-        log("cpu baseline: oracle on %d registrations, %d threads" % (ops, nthreads))
-        result["cpu_baseline"] = cpu_baseline(series, cfg, ops, nthreads)
+        n_a = args.cpu_ops or nthreads
+        log("cpu baseline: oracle on %d neighbour registrations and their B applications, "
+            "%d threads" % (n_a, nthreads))
+        result["cpu_baseline"] = cpu_baseline(series, cfg, n_a, nthreads, scan)
     print(json.dumps(result), flush=True)
 
 

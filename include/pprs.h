@@ -47,13 +47,25 @@ enum {
   PPRS_SCAN_BRENT_KUNG = 1,   /* algorithm "brent_kung" (work-efficient, 2 log2 M - 1 levels) */
   PPRS_SCAN_KOGGE_STONE = 2,  /* algorithm "kogge_stone" (log2 M levels, M log2 M - M + 1 ops) */
   PPRS_SCAN_SKLANSKY = 3,     /* algorithm "sklansky" (log2 M levels, M/2 log2 M ops) */
-  PPRS_SCAN_GENERAL = 4       /* general strategy of the distributed chapter with P workers
+  PPRS_SCAN_GENERAL = 4,      /* general strategy of the distributed chapter with P workers
                                  (pprs_params.scan_workers): serial scans inside P chunks, a
                                  Brent-Kung scan over the chunk ends, then every other element
                                  of each later chunk combined with the end of the one before */
+  PPRS_SCAN_BLELLOCH = 5,     /* algorithm "blelloch": exclusive up/down sweep with the identity
+                                 element (2 log2 N levels, 2(N-1) operator applications of which
+                                 those with the identity cost nothing) */
+  PPRS_SCAN_REDUCE_THEN_SCAN = 6 /* the distributed chapter's alternative strategy with P workers:
+                                 each chunk reduced, a scan over the P totals, each chunk
+                                 rescanned serially from the total before it */
 };
 
-enum { PPRS_FLAG_NONCONV = 1, PPRS_FLAG_NAN = 2, PPRS_FLAG_FALLBACK = 4 };
+/* Instructions of a scan program (pprs_scan_program). */
+enum { PPRS_SCAN_OP_COMBINE = 0, PPRS_SCAN_OP_MOVE = 1, PPRS_SCAN_OP_CLEAR = 2 };
+
+/* NONCONV: some level hit iter_max. NAN: a non-finite energy. FALLBACK: the warm start's
+   guess was rejected and the registration ran cold. NET_START: a B application started from
+   the network's guess for its pair instead of the composition (lower energy on level 7). */
+enum { PPRS_FLAG_NONCONV = 1, PPRS_FLAG_NAN = 2, PPRS_FLAG_FALLBACK = 4, PPRS_FLAG_NET_START = 8 };
 
 #define PPRS_MAX_LEVELS 16
 
@@ -70,8 +82,8 @@ typedef struct {
   double eps;           /* stop a level when E_k - E_{k+1} < eps (stopping criteria) */
   int iter_max;         /* accepted steps per level (stopping criteria) */
   int scan;             /* PPRS_SCAN_* schedule of the series step */
-  int scan_workers;     /* P of PPRS_SCAN_GENERAL (0: ceil(sqrt(M)); at most M); ignored by
-                           the other schedules */
+  int scan_workers;     /* P of PPRS_SCAN_GENERAL and PPRS_SCAN_REDUCE_THEN_SCAN (0:
+                           ceil(sqrt(M)); at most M); ignored by the other schedules */
 } pprs_params;
 
 /* Statistics of one A or B application. Level index 0 is the coarsest level. */
@@ -213,6 +225,17 @@ pprs_status pprs_prefix_register_series(pprs_ctx* ctx, const float* frames, int 
    Returns PPRS_EINVAL for values out of range (slots > 65536, group_steps > 1024). */
 pprs_status pprs_set_pool(pprs_ctx* ctx, int slots, int group_steps);
 
+/* Decision log of later calls on ctx (test and diagnosis): log is a device buffer of rows of
+   `cap` bytes (caller-owned, NULL disables). Row r belongs to the call's r-th registration (the
+   pair index of pprs_register_pair(s)(_rigid); in a series the N-1 neighbour registrations, then
+   the B applications in schedule order, as op_stats; in a multi-series call the pool's op
+   order). Byte k of a row is the ladder position J of the registration's k-th accepted step
+   (levels in order, coarsest first): the accepted step was top 2^-J, top the first step of that
+   iteration's line search (Armijo with widening, section "Gradient flow"); 255 stands for 255
+   or more. Steps beyond cap are not logged; the library never clears the buffer. Together with
+   the per-level step counts of the stats this is every decision a registration took. */
+pprs_status pprs_set_decision_log(pprs_ctx* ctx, unsigned char* log, int cap);
+
 /* Metric solve d = A^-1 G, A = S1 (x) S1 (section "Gradient flow"). EXACT (default): two
    passes of line solves (columns, then rows). WINDOW: one windowed pass per step where beta
    allows it (the LU recurrences of S1 contract so fast that a 64x64 tile plus a halo of 16 or 24
@@ -292,9 +315,23 @@ pprs_status pprs_series_average(pprs_ctx* ctx, const float* frames, const float*
    capacity (then *n_ops holds the needed count). Makes no HIP call. */
 pprs_status pprs_scan_plan(int kind, int M, int* ops, int cap, int* n_ops, int* n_levels);
 /* pprs_scan_plan with the worker count P of PPRS_SCAN_GENERAL (0: ceil(sqrt(M)); clipped to
-   M; P < 0 is PPRS_EINVAL). pprs_scan_plan(kind, ...) is pprs_scan_plan_p(kind, M, 0, ...). */
+   M; P < 0 is PPRS_EINVAL). pprs_scan_plan(kind, ...) is pprs_scan_plan_p(kind, M, 0, ...).
+   The Blelloch and reduce-then-scan schedules need scratch elements and the identity and are
+   PPRS_EINVAL here: they exist as programs only. */
 pprs_status pprs_scan_plan_p(int kind, int M, int P, int* ops, int cap, int* n_ops,
                              int* n_levels);
+/* Host-only: any schedule (PPRS_SCAN_*, P as for pprs_scan_plan_p) as a program over
+   *n_elems elements (the M scan elements first, then scratch elements that start as the
+   identity element). prog (host, capacity `cap` instructions of 5 ints) receives
+   (code, a, b, dst, level), executed in list order: PPRS_SCAN_OP_COMBINE x[dst] <- x[a] (.)
+   x[b], PPRS_SCAN_OP_MOVE x[dst] <- x[a], PPRS_SCAN_OP_CLEAR x[dst] <- identity. A combine
+   with the identity is a copy of the other operand; the others are operator applications
+   (*n_reg of them). Combines sharing a level are mutually independent. At the end x[m] holds
+   x_0 (.) ... (.) x_m for m < M. The plan schedules are the programs of their combines
+   (dst = right). PPRS_EINVAL for bad arguments or a too small capacity (then *n_instr holds
+   the needed count). Makes no HIP call. */
+pprs_status pprs_scan_program(int kind, int M, int P, int* prog, int cap, int* n_instr,
+                              int* n_levels, int* n_elems, int* n_reg);
 
 /* Kernel timing (HIP events around the launches of each kernel kind on the context stream).
    Enabling costs a few microseconds per launch. Kinds are listed by pprs_kernel_name(). */

@@ -24,7 +24,8 @@ _lock = threading.Lock()
 _lib = None
 
 TRACE_W = 8
-SCAN_KINDS = {"sequential": 0, "brent_kung": 1, "kogge_stone": 2, "sklansky": 3, "general": 4}
+SCAN_KINDS = {"sequential": 0, "brent_kung": 1, "kogge_stone": 2, "sklansky": 3, "general": 4,
+              "blelloch": 5, "reduce_then_scan": 6}
 
 
 def build(force: bool = True) -> str:
@@ -47,6 +48,7 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         D = ctypes.POINTER(ctypes.c_double)
         I = ctypes.POINTER(ctypes.c_int)
+        U8 = ctypes.POINTER(ctypes.c_ubyte)
         P = ctypes.POINTER(_CParams)
         S = ctypes.POINTER(_CStats)
         sigs = {
@@ -63,17 +65,19 @@ def _load():
             "or_gradient_flow": (ctypes.c_int, [D, D, ctypes.c_int, D, P, I, I, D, D,
                                                 ctypes.c_int, I]),
             "or_register": (ctypes.c_int, [D, D, ctypes.c_int, D, P, D, S, D, ctypes.c_int, I]),
-            "or_register_f": (ctypes.c_int, [D, D, ctypes.c_int, D, P, I, D, S, D,
-                                             ctypes.c_int, I]),
+            "or_register_f": (ctypes.c_int, [D, D, ctypes.c_int, D, P, I, U8, ctypes.c_int, D,
+                                             S, D, ctypes.c_int, I]),
             "or_register_from": (ctypes.c_int, [D, D, ctypes.c_int, ctypes.c_int, D, P, D, S, D,
                                                 ctypes.c_int, I]),
             "or_compose": (None, [D, D, ctypes.c_int, D]),
             "or_register_rigid": (ctypes.c_int, [D, D, ctypes.c_int, D, P, D, S]),
-            "or_register_rigid_f": (ctypes.c_int, [D, D, ctypes.c_int, D, P, I, D, S]),
+            "or_register_rigid_f": (ctypes.c_int, [D, D, ctypes.c_int, D, P, I, U8,
+                                                   ctypes.c_int, D, S]),
             "or_series": (ctypes.c_int, [D, ctypes.c_int, ctypes.c_int, P, ctypes.c_int,
                                          ctypes.c_int, D, S, S, I, ctypes.c_int]),
             "or_series_f": (ctypes.c_int, [D, ctypes.c_int, ctypes.c_int, P, ctypes.c_int,
-                                           ctypes.c_int, I, I, D, S, S, I, ctypes.c_int]),
+                                           ctypes.c_int, I, I, U8, U8, ctypes.c_int, D, S, S,
+                                           I, ctypes.c_int]),
             "or_set_u_storage_f32": (None, [ctypes.c_int]),
         }
         for name, (res, args) in sigs.items():
@@ -94,7 +98,7 @@ class _CParams(ctypes.Structure):
 class _CStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int * 16), ("trials", ctypes.c_int * 16),
                 ("energy", ctypes.c_double), ("ncc", ctypes.c_double), ("flags", ctypes.c_int),
-                ("tie_gap", ctypes.c_double)]
+                ("tie_gap", ctypes.c_double), ("armijo_gap", ctypes.c_double)]
 
 
 @dataclass
@@ -225,8 +229,9 @@ class RegStats:
     energy: float
     ncc: float
     flags: int
-    tie_gap: float = 0.0   # replayed decisions only: largest distance of the energy test
-                           # from deciding a replayed step the other way
+    tie_gap: float = 0.0     # replayed decisions only: largest distance of the energy test
+                             # from deciding a replayed stop the other way
+    armijo_gap: float = 0.0  # ... and of the Armijo test from a replayed line-search choice
 
 
 def _force(force, rows: int = 1):
@@ -252,18 +257,42 @@ def _ip(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int)) if a is not None else None
 
 
+def _rungs(rungs, rows: int = 1):
+    """Replayed ladder positions: `rows` uint8 sequences (one per registration, each step in
+    order) -> (uint8 [rows][cap], cap), or (None, 0)."""
+    if rungs is None:
+        return None, 0
+    if rows == 1:
+        rungs = [rungs]
+    if len(rungs) != rows:
+        raise ValueError("need %d rung sequences" % rows)
+    cap = max(1, max(len(r) for r in rungs))
+    out = np.zeros((rows, cap), dtype=np.uint8)
+    for r, seq in enumerate(rungs):
+        out[r, :len(seq)] = np.asarray(seq, dtype=np.uint8)
+    return out, cap
+
+
+def _up(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte)) if a is not None else None
+
+
 def _stats(st: _CStats, levels: int) -> RegStats:
     return RegStats(list(st.iters[:levels]), list(st.trials[:levels]), st.energy, st.ncc,
-                    st.flags, st.tie_gap)
+                    st.flags, st.tie_gap, st.armijo_gap)
 
 
-def register(R, T, params: Params, u0=None, trace_cap: int = 0, force=None):
+def register(R, T, params: Params, u0=None, trace_cap: int = 0, force=None, rungs=None):
     """Operator A on finest-level nodal frames. Returns (u [2,n,n] domain units, RegStats,
     trace).
 
     force (test switch): accepted-step counts per level, coarsest first; a level with a count
     takes exactly that many steps (unless its line search fails first) instead of stopping by
-    the energy-decrease test. It replays stopping decisions another implementation took."""
+    the energy-decrease test. rungs (test switch): the ladder position J of every accepted step
+    (levels in order), taken in place of the Armijo test's choice. They replay decisions another
+    implementation took; the stats' tie_gap / armijo_gap say how far the oracle's own tests
+    were from each replayed decision. Pass both, or neither: a replayed rung sequence belongs to
+    one sequence of step counts."""
     R, T = _f64(R), _f64(T)
     n = R.shape[-1]
     u = np.empty((2, n, n))
@@ -276,13 +305,30 @@ def register(R, T, params: Params, u0=None, trace_cap: int = 0, force=None):
     if keep is not None:
         u0p = _d(keep)
     fo = _force(force)
-    rc = _load().or_register_f(_d(R), _d(T), n, u0p, ctypes.byref(cp), _ip(fo), _d(u),
-                               ctypes.byref(st), _d(tr), trace_cap, ctypes.byref(tl))
+    ru, rc_ = _rungs(rungs)
+    rc = _load().or_register_f(_d(R), _d(T), n, u0p, ctypes.byref(cp), _ip(fo), _up(ru), rc_,
+                               _d(u), ctypes.byref(st), _d(tr), trace_cap, ctypes.byref(tl))
     if rc == -1:
         raise ValueError("constant reference on some level")
     if rc != 0:
         raise ValueError("invalid sizes or levels")
     return u, _stats(st, params.levels), tr[: tl.value]
+
+
+def trace_rungs(trace, params: Params):
+    """Ladder position J of every accepted step of a register() trace (levels in order): the
+    step is top 2^-J with top = min(2^K tau_prev, tau_max) of its iteration."""
+    out = []
+    prev_level, tau_prev = None, np.inf
+    for level, step, tau, e0, e1, gtd, tmax, passes in trace:
+        if level != prev_level:
+            prev_level, tau_prev = level, np.inf
+        if tau <= 0:
+            continue
+        top = min(2.0 ** params.ladder_k * tau_prev, tmax)
+        out.append(int(round(np.log2(top / tau))))
+        tau_prev = tau
+    return out
 
 
 def register_from(R, T, start: int, u_start, params: Params, trace_cap: int = 0):
@@ -307,7 +353,7 @@ def register_from(R, T, start: int, u_start, params: Params, trace_cap: int = 0)
     return u, _stats(st, params.levels), tr[: tl.value]
 
 
-def register_rigid(R, T, params: Params, p_init=None, force=None):
+def register_rigid(R, T, params: Params, p_init=None, force=None, rungs=None):
     """Rigid variant of A on finest-level nodal frames: phi(x) = R(alpha) x + t about the domain
     origin. Returns (p = [alpha, t0, t1] in radians and domain units, RegStats). force: as for
     register()."""
@@ -318,8 +364,10 @@ def register_rigid(R, T, params: Params, p_init=None, force=None):
     cp = params.c()
     pin = _f64(np.asarray(p_init, dtype=np.float64)) if p_init is not None else None
     fo = _force(force)
+    ru, rc_ = _rungs(rungs)
     rc = _load().or_register_rigid_f(_d(R), _d(T), n, _d(pin) if pin is not None else None,
-                                     ctypes.byref(cp), _ip(fo), _d(out), ctypes.byref(st))
+                                     ctypes.byref(cp), _ip(fo), _up(ru), rc_, _d(out),
+                                     ctypes.byref(st))
     if rc == -1:
         raise ValueError("constant reference on some level")
     if rc != 0:
@@ -335,7 +383,7 @@ def _compose_rigid(u, v):
 
 
 def series_rigid(frames_nodal, params: Params, scan: str = "brent_kung", force_a=None,
-                 force_b=None):
+                 force_b=None, rungs_a=None, rungs_b=None):
     """Series registration with the rigid operator (definition of image series registration):
     N-1 neighbour registrations, then the scan with B = rigid registration started from the
     composition of the operands' maps. Schedules: "sequential" and "brent_kung" (Prefix sum
@@ -350,7 +398,8 @@ def series_rigid(frames_nodal, params: Params, scan: str = "brent_kung", force_a
     if M < 1:
         return out
     el = [[m, m + 1, register_rigid(fr[m], fr[m + 1], params,
-                                    force=force_a[m] if force_a is not None else None)[0]]
+                                    force=force_a[m] if force_a is not None else None,
+                                    rungs=rungs_a[m] if rungs_a is not None else None)[0]]
           for m in range(M)]
     nb = [0]
 
@@ -359,9 +408,10 @@ def series_rigid(frames_nodal, params: Params, scan: str = "brent_kung", force_a
         ib, kb, pb = el[b]
         assert ka == ib
         fb = force_b[nb[0]] if force_b is not None else None
+        rb = rungs_b[nb[0]] if rungs_b is not None else None
         nb[0] += 1
         el[b] = [ia, kb, register_rigid(fr[ia], fr[kb], params,
-                                        p_init=_compose_rigid(pa, pb), force=fb)[0]]
+                                        p_init=_compose_rigid(pa, pb), force=fb, rungs=rb)[0]]
 
     if scan == "sequential":
         for m in range(1, M):
@@ -388,6 +438,121 @@ def series_rigid(frames_nodal, params: Params, scan: str = "brent_kung", force_a
     return out
 
 
+def restrict_levels(f, times: int) -> np.ndarray:
+    """f ([n, n] or [2, n, n]) restricted `times` levels down (full weighting each time)."""
+    g = _f64(f)
+    for _ in range(times):
+        g = np.stack([restrict(x) for x in g]) if g.ndim == 3 else restrict(g)
+    return g
+
+
+def _bk_pairs(M):
+    """(left, right) of the Brent-Kung schedule over M elements, in execution order."""
+    out = []
+    d = 1
+    while d < M:
+        out += [(j - d, j) for j in range(2 * d - 1, M, 2 * d)]
+        d *= 2
+    top = 1
+    while top * 2 < M:
+        top *= 2
+    d = top
+    while d >= 1:
+        out += [(j - d, j) for j in range(3 * d - 1, M, 2 * d)]
+        d //= 2
+    return out
+
+
+WARM_LEVEL = 7
+
+
+def warm_series(frames_nodal, params: Params, guess, mode: str = "refine",
+                max_cells: float = 8.0):
+    """Series registration (Brent-Kung) with the learned warm start and its judge, for a
+    series whose finest level L is above 7. guess(i, k) gives the network's level-7 guess
+    ([2, 129, 129], domain units) for reference i and template k. Rejected outright: a guess
+    that is not finite or exceeds max_cells level-7 cells (the registration runs cold).
+    Neighbour registration: the warm registration up to level 7 (mode "skip": started on level
+    7 from the guess; "refine": from the guess restricted to the coarsest level) against the
+    identity on level 7; an NCC no lower than the identity's resumes on level 8 from the
+    prolongated level-7 result, else the registration runs cold. B application: the
+    composition of its operands and the guess for its own pair, both restricted to / given on
+    level 7 and compared by their energy there; the lower starts the registration (on level 7
+    in "skip" mode, restricted to the coarsest level in "refine" mode).
+    Returns (u [N, 2, n, n], per-op dicts (pair, fallback, net_start) in execution order)."""
+    fr = _f64(frames_nodal)
+    N, nf = fr.shape[0], fr.shape[-1]
+    L = int(round(np.log2(nf - 1)))
+    m0 = L - params.levels + 1
+    if not (m0 <= WARM_LEVEL < L):
+        raise ValueError("the judge needs m0 <= 7 < L")
+    p7 = Params(**{**params.__dict__, "levels": WARM_LEVEL - m0 + 1})
+    R7 = [restrict_levels(f, L - WARM_LEVEL) for f in fr]
+    n7 = (1 << WARM_LEVEL) + 1
+    skip = mode == "skip"
+
+    def ok(g):
+        return np.all(np.isfinite(g)) and np.abs(g).max() * (n7 - 1) <= max_cells
+
+    def start_from(i, k, g7):
+        """A from a level-7 guess: on level 7 (skip) or restricted to m0 (refine)."""
+        if skip:
+            return register_from(fr[i], fr[k], WARM_LEVEL, g7, params)[0]
+        return register_from(fr[i], fr[k], m0, restrict_levels(g7, WARM_LEVEL - m0), params)[0]
+
+    ops = []
+    u = np.zeros((N, 2, nf, nf))
+    el = []
+    for m in range(N - 1):
+        g = guess(m, m + 1)
+        rec = dict(pair=(m, m + 1), fallback=False, net_start=False)
+        if ok(g):
+            if skip:
+                w, sw, _ = register_from(R7[m], R7[m + 1], WARM_LEVEL, g, p7)
+            else:
+                w, sw, _ = register_from(R7[m], R7[m + 1], m0,
+                                         restrict_levels(g, WARM_LEVEL - m0), p7)
+            ncc_id = energy(R7[m], R7[m + 1], np.zeros((2, n7, n7)), params.lam)[1]
+            if sw.ncc >= ncc_id:
+                u8 = np.stack([prolong(w[c]) for c in range(2)])
+                res = register_from(fr[m], fr[m + 1], WARM_LEVEL + 1, u8, params)[0]
+            else:
+                rec["fallback"] = True
+                res = register(fr[m], fr[m + 1], params)[0]
+        else:
+            rec["fallback"] = True
+            res = register(fr[m], fr[m + 1], params)[0]
+        ops.append(rec)
+        el.append([m, m + 1, res])
+    for a, b in _bk_pairs(N - 1):
+        i, j, ua = el[a]
+        j2, k, ub = el[b]
+        assert j == j2
+        comp = compose(ua, ub)
+        g = guess(i, k)
+        rec = dict(pair=(i, k), fallback=False, net_start=False)
+        use_net = False
+        if ok(g):
+            c7 = restrict_levels(comp, L - WARM_LEVEL)
+            e_c = energy(R7[i], R7[k], c7, params.lam)[0]
+            e_n = energy(R7[i], R7[k], g, params.lam)[0]
+            use_net = e_n < e_c
+        if use_net:
+            rec["net_start"] = True
+            res = start_from(i, k, g)
+        elif skip:
+            res = register_from(fr[i], fr[k], WARM_LEVEL,
+                                restrict_levels(comp, L - WARM_LEVEL), params)[0]
+        else:
+            res = register(fr[i], fr[k], params, u0=comp)[0]
+        ops.append(rec)
+        el[b] = [i, k, res]
+    for m in range(N - 1):
+        assert el[m][0] == 0 and el[m][1] == m + 1
+        u[m + 1] = el[m][2]
+    return u, ops
+
+
 def set_u_storage_f32(on: bool) -> None:
     """Test switch: round the displacement to FP32 after every accepted step (process-wide)."""
     _load().or_set_u_storage_f32(1 if on else 0)
@@ -401,10 +566,11 @@ def compose(uij, ujk) -> np.ndarray:
 
 
 def series(frames_nodal, params: Params, scan: str = "brent_kung", threads: int = 0,
-           workers: int = 0, force_a=None, force_b=None):
+           workers: int = 0, force_a=None, force_b=None, rungs_a=None, rungs_b=None):
     """Series registration as an inclusive scan with operator B (workers: P of the general
     strategy, 0 for ceil(sqrt(N-1))). force_a (N-1 lists) and force_b (one list per B
-    application in schedule order): replayed step counts, see register().
+    application in schedule order): replayed step counts; rungs_a / rungs_b: replayed ladder
+    positions, one sequence per registration; see register().
 
     frames_nodal: [N, n, n]. Returns (u [N, 2, n, n] domain units with u[0] = 0, a_stats,
     b_stats, b_pairs [(i, j, k)] in execution order)."""
@@ -425,8 +591,23 @@ def series(frames_nodal, params: Params, scan: str = "brent_kung", threads: int 
         if len(force_b) > cap:
             raise ValueError("too many B lists")
         fb[:len(force_b)] = _force(force_b, len(force_b))
+    ra = rb = None
+    rcap = 0
+    if rungs_a is not None or rungs_b is not None:
+        seqs = list(rungs_a or [[]] * (N - 1)) + list(rungs_b or [])
+        rcap = max(1, max(len(x) for x in seqs))
+        ra = np.zeros((max(N - 1, 1), rcap), dtype=np.uint8)
+        rb = np.zeros((cap, rcap), dtype=np.uint8)
+        for m, x in enumerate(rungs_a or []):
+            ra[m, :len(x)] = np.asarray(x, dtype=np.uint8)
+        for m, x in enumerate(rungs_b or []):
+            rb[m, :len(x)] = np.asarray(x, dtype=np.uint8)
+        if rungs_a is None:
+            ra = None
+        if rungs_b is None:
+            rb = None
     rc = _load().or_series_f(_d(fr), N, n, ctypes.byref(cp), SCAN_KINDS[scan], workers,
-                             _ip(fa), _ip(fb), _d(u), a_st, b_st,
+                             _ip(fa), _ip(fb), _up(ra), _up(rb), rcap, _d(u), a_st, b_st,
                              pairs.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), threads)
     if rc < 0:
         raise ValueError("oracle series failed with %d" % rc)
@@ -459,6 +640,27 @@ def series_average(frames, u, pixels=None):
         bot = (1.0 - fx) * f[i][y0 + 1, x0] + fx * f[i][y0 + 1, x0 + 1]
         acc += (1.0 - fy) * top + fy * bot
     return acc / N
+
+
+def series_average_refine(frames, u, passes: int, params: Params):
+    """The series averaging procedure (Introduction; section "Registration for series of
+    images": the series' result refined by further rounds of registration): each round averages
+    the aligned frames (series_average) and registers every frame f_i, i >= 1, to that average
+    with operator A started from its current deformation (restricted to the coarsest level, as
+    the multilevel algorithm prescribes); f_0's deformation stays the identity, which keeps the
+    result in f_0's coordinates. frames [N, H, W] and u [N, 2, H, W] in pixels (H = W = 2^L).
+    Returns (u refined, the average of the last round's alignment)."""
+    f = np.asarray(frames, dtype=np.float64)
+    u = np.array(u, dtype=np.float64)
+    N, H, W = f.shape
+    for _ in range(passes):
+        avg = series_average(f, u)
+        R = frame_to_nodes(avg)
+        for i in range(1, N):
+            u0 = np.stack([frame_to_nodes(u[i, c]) for c in range(2)]) / H
+            res, _, _ = register(R, frame_to_nodes(f[i]), params, u0=u0)
+            u[i] = u_to_pixels(res, H)
+    return u, series_average(f, u)
 
 
 # ------------------------------------------------------------------------------------------ #

@@ -61,7 +61,25 @@ typedef struct {
   double tie_gap;             /* with replayed stopping decisions: the largest distance by which
                                  the energy test would have decided a replayed step the other way
                                  (0 when every replayed decision agrees with the test) */
+  double armijo_gap;          /* with replayed line-search decisions: the same for the Armijo test
+                                 (a larger step it would accept, or the replayed step it would
+                                 reject) */
 } or_stats;
+
+/* Test switch: decisions another implementation took, replayed in place of the oracle's own
+   tests so that two implementations can be compared along one decision sequence where rounding
+   decides near-ties differently. force[l - m0] (or -1) is the number of accepted steps of level
+   l; rungs[k] is the ladder position J of the k-th accepted step of the registration (levels in
+   order, coarsest first): the step top 2^-J of that iteration's ladder. The oracle still
+   evaluates its own tests and records in stop_gap / armijo_gap how far they are from each
+   replayed decision. */
+typedef struct {
+  const int* force;
+  const unsigned char* rungs;
+  int cap;   /* entries in rungs */
+  int pos;   /* next entry of rungs */
+  double stop_gap, armijo_gap;
+} replay_t;
 
 enum { OR_FLAG_NONCONV = 1, OR_FLAG_NAN = 2 };
 #define OR_TRACE_W 8
@@ -463,13 +481,13 @@ static void trace_put(trace_t* tr, int level, int step, double tau, double e0, d
   tr->len++;
 }
 
-/* force >= 0 is a test switch: the level takes exactly `force` accepted steps (unless the
-   line search fails or the flow is stationary first) and the energy-decrease test is not
-   applied. It lets a test replay the stopping decisions another implementation took where a
-   decrease lies so close to eps that rounding decides it; -1 is the method itself. */
+/* force >= 0 (replay_t): the level takes exactly `force` accepted steps (unless the line
+   search fails or the flow is stationary first) and the energy-decrease test is not applied;
+   -1 is the method itself. rp (may be NULL) supplies replayed ladder positions and collects
+   the gaps. */
 static int gradient_flow(const level_data* L, double* u, const or_params* p, int level,
-                         int force, int* trials, int* flags, double* e_out, double* ncc_out,
-                         double* gap, trace_t* tr) {
+                         int force, replay_t* rp, int* trials, int* flags, double* e_out,
+                         double* ncc_out, trace_t* tr) {
   int n = L->n;
   size_t nn = (size_t)n * n;
   double h = 1.0 / (n - 1);
@@ -494,22 +512,43 @@ static int gradient_flow(const level_data* L, double* u, const or_params* p, int
     double top = fmin(ldexp(tau_prev, K), tau_max);
     double tau_acc = 0.0, e_acc = E, ncc_acc = ncc;
     int passes = 0;
-    while (top >= p->tau_min_rel * tau_max) {
-      passes++;
-      for (int j = 0; j <= 2 * K; ++j) {                  /* largest step first */
+    if (rp && rp->rungs && rp->pos < rp->cap) {
+      /* replayed: rung J of this iteration's ladder; the rungs above it are evaluated with the
+         Armijo test only to measure how far it is from the replayed choice */
+      int J = rp->rungs[rp->pos++];
+      for (int j = 0; j <= J; ++j) {
         double tau = ldexp(top, -j);
         for (size_t i = 0; i < 2 * nn; ++i) ut[i] = u[i] - tau * d[i];
         double nc;
         double e = energy_level(L, ut, p->lambda, &nc);
-        if (e <= E - p->sigma * tau * gtd) {              /* Armijo, sufficient decrease */
+        double bound = E - p->sigma * tau * gtd;
+        if (j < J && e <= bound) rp->armijo_gap = fmax(rp->armijo_gap, bound - e);
+        if (j == J) {
+          if (e > bound) rp->armijo_gap = fmax(rp->armijo_gap, e - bound);
           tau_acc = tau;
           e_acc = e;
           ncc_acc = nc;
-          break;
         }
       }
-      if (tau_acc > 0.0) break;
-      top = ldexp(top, -(2 * K + 1));
+      passes = J / (2 * K + 1) + 1;
+    } else {
+      while (top >= p->tau_min_rel * tau_max) {
+        passes++;
+        for (int j = 0; j <= 2 * K; ++j) {                /* largest step first */
+          double tau = ldexp(top, -j);
+          for (size_t i = 0; i < 2 * nn; ++i) ut[i] = u[i] - tau * d[i];
+          double nc;
+          double e = energy_level(L, ut, p->lambda, &nc);
+          if (e <= E - p->sigma * tau * gtd) {            /* Armijo, sufficient decrease */
+            tau_acc = tau;
+            e_acc = e;
+            ncc_acc = nc;
+            break;
+          }
+        }
+        if (tau_acc > 0.0) break;
+        top = ldexp(top, -(2 * K + 1));
+      }
     }
     passes_total += passes;
     trace_put(tr, level, steps, tau_acc, E, e_acc, gtd, tau_max, passes);
@@ -522,9 +561,9 @@ static int gradient_flow(const level_data* L, double* u, const or_params* p, int
     ncc = ncc_acc;
     tau_prev = tau_acc;
     steps++;
-    if (force >= 0 && gap) { /* how far the energy test is from the replayed decision */
-      if (steps < force) *gap = fmax(*gap, p->eps - dec);
-      else if (steps < p->iter_max) *gap = fmax(*gap, dec - p->eps);
+    if (force >= 0 && rp) { /* how far the energy test is from the replayed decision */
+      if (steps < force) rp->stop_gap = fmax(rp->stop_gap, p->eps - dec);
+      else if (steps < p->iter_max) rp->stop_gap = fmax(rp->stop_gap, dec - p->eps);
     }
     if (force >= 0 ? steps >= force : dec < p->eps) break; /* converged (or replayed stop) */
     if (steps >= p->iter_max) *flags |= OR_FLAG_NONCONV;
@@ -551,7 +590,7 @@ int or_gradient_flow(const double* R, const double* T, int n, double* u, const o
   level_data L = {n, Rn, T};
   trace_t tr = {trace, trace_cap, 0};
   int flags = 0;
-  int s = gradient_flow(&L, u, p, 0, -1, passes, &flags, energy, NULL, NULL, &tr);
+  int s = gradient_flow(&L, u, p, 0, -1, NULL, passes, &flags, energy, NULL, &tr);
   if (steps) *steps = s;
   if (trace_len) *trace_len = tr.len;
   free(Rn);
@@ -612,19 +651,19 @@ static void pyramid_free(pyramid_t* py) {
 /* Gradient flow on levels start..L from the guess u (level `start`, owned: freed here), each
    result prolongated as the next level's start. Statistics are indexed from level m0. */
 static void run_levels(const pyramid_t* py, int start, double* u, const or_params* p,
-                       const int* force, double* u_out, or_stats* st, double* trace,
+                       replay_t* rp, double* u_out, or_stats* st, double* trace,
                        int trace_cap, int* trace_len) {
   int L = py->L, m0 = py->m0, nf = (1 << L) + 1;
   trace_t tr = {trace, trace_cap, 0};
   if (st) memset(st, 0, sizeof(*st));
   int flags = 0;
-  double e = 0.0, ncc = 0.0, gap = 0.0;
+  double e = 0.0, ncc = 0.0;
   for (int l = start; l <= L; ++l) {
     int n = (1 << l) + 1;
     level_data LD = {n, py->Rn[l], py->Tl[l]};
     int passes = 0;
-    int steps = gradient_flow(&LD, u, p, l, force ? force[l - m0] : -1, &passes, &flags, &e,
-                              &ncc, &gap, &tr);
+    int force = rp && rp->force ? rp->force[l - m0] : -1;
+    int steps = gradient_flow(&LD, u, p, l, force, rp, &passes, &flags, &e, &ncc, &tr);
     if (st) {
       st->iters[l - m0] = steps;
       st->trials[l - m0] = passes;
@@ -644,16 +683,20 @@ static void run_levels(const pyramid_t* py, int start, double* u, const or_param
     st->energy = e;
     st->ncc = ncc;
     st->flags = flags;
-    st->tie_gap = gap;
+    st->tie_gap = rp ? rp->stop_gap : 0.0;
+    st->armijo_gap = rp ? rp->armijo_gap : 0.0;
   }
   if (trace_len) *trace_len = tr.len;
 }
 
 /* force (may be NULL): per level from m0, the number of accepted steps to take instead of
-   applying the energy-decrease stopping test (-1: the test applies); see gradient_flow. */
+   applying the energy-decrease stopping test (-1: the test applies); rungs (may be NULL,
+   rung_cap entries): the ladder position of every accepted step (replay_t). */
 int or_register_f(const double* R, const double* T, int nf, const double* u0,
-                  const or_params* p, const int* force, double* u_out, or_stats* st,
-                  double* trace, int trace_cap, int* trace_len) {
+                  const or_params* p, const int* force, const unsigned char* rungs,
+                  int rung_cap, double* u_out, or_stats* st, double* trace, int trace_cap,
+                  int* trace_len) {
+  replay_t rp = {force, rungs, rungs ? rung_cap : 0, 0, 0.0, 0.0};
   int L = log2_exact(nf - 1);
   if (L < 1 || p->levels < 1 || p->levels > L || p->levels > OR_MAX_LEVELS) return -2;
   int m0 = L - p->levels + 1;
@@ -679,7 +722,8 @@ int or_register_f(const double* R, const double* T, int nf, const double* u0,
       memcpy(u, cur, sizeof(double) * 2 * n0 * n0);
       free(cur);
     }
-    run_levels(&py, m0, u, p, force, u_out, st, trace, trace_cap, trace_len);
+    run_levels(&py, m0, u, p, (force || rungs) ? &rp : NULL, u_out, st, trace, trace_cap,
+               trace_len);
   }
   pyramid_free(&py);
   return rc;
@@ -687,7 +731,7 @@ int or_register_f(const double* R, const double* T, int nf, const double* u0,
 
 int or_register(const double* R, const double* T, int nf, const double* u0, const or_params* p,
                 double* u_out, or_stats* st, double* trace, int trace_cap, int* trace_len) {
-  return or_register_f(R, T, nf, u0, p, NULL, u_out, st, trace, trace_cap, trace_len);
+  return or_register_f(R, T, nf, u0, p, NULL, NULL, 0, u_out, st, trace, trace_cap, trace_len);
 }
 
 /* Function A started on level `start` (m0 <= start <= L) from the guess u_start given on that
@@ -736,8 +780,8 @@ static void rigid_field(int n, const double p[3], double* u) {
 }
 
 static int rigid_flow(const level_data* L, double p[3], const or_params* pr, int force,
-                      int* passes_out, int* flags, double* e_out, double* ncc_out,
-                      double* gap) {
+                      replay_t* rp, int* passes_out, int* flags, double* e_out,
+                      double* ncc_out) {
   int n = L->n;
   size_t nn = (size_t)n * n;
   double h = 1.0 / (n - 1);
@@ -776,23 +820,43 @@ static int rigid_flow(const level_data* L, double p[3], const or_params* pr, int
     double top = fmin(ldexp(tau_prev, K), tau_max);
     double tau_acc = 0.0, e_acc = E, ncc_acc = ncc;
     double pt[3];
-    while (top >= pr->tau_min_rel * tau_max) {
-      passes_total++;
-      for (int j = 0; j <= 2 * K; ++j) {
+    if (rp && rp->rungs && rp->pos < rp->cap) {  /* replayed rung (see gradient_flow) */
+      int J = rp->rungs[rp->pos++];
+      for (int j = 0; j <= J; ++j) {
         double tau = ldexp(top, -j);
         for (int k = 0; k < 3; ++k) pt[k] = p[k] - tau * d[k];
         rigid_field(n, pt, u);
         double nc;
         double e = energy_level(L, u, 0.0, &nc);
-        if (e <= E - pr->sigma * tau * gtd) {
+        double bound = E - pr->sigma * tau * gtd;
+        if (j < J && e <= bound) rp->armijo_gap = fmax(rp->armijo_gap, bound - e);
+        if (j == J) {
+          if (e > bound) rp->armijo_gap = fmax(rp->armijo_gap, e - bound);
           tau_acc = tau;
           e_acc = e;
           ncc_acc = nc;
-          break;
         }
       }
-      if (tau_acc > 0.0) break;
-      top = ldexp(top, -(2 * K + 1));
+      passes_total += J / (2 * K + 1) + 1;
+    } else {
+      while (top >= pr->tau_min_rel * tau_max) {
+        passes_total++;
+        for (int j = 0; j <= 2 * K; ++j) {
+          double tau = ldexp(top, -j);
+          for (int k = 0; k < 3; ++k) pt[k] = p[k] - tau * d[k];
+          rigid_field(n, pt, u);
+          double nc;
+          double e = energy_level(L, u, 0.0, &nc);
+          if (e <= E - pr->sigma * tau * gtd) {
+            tau_acc = tau;
+            e_acc = e;
+            ncc_acc = nc;
+            break;
+          }
+        }
+        if (tau_acc > 0.0) break;
+        top = ldexp(top, -(2 * K + 1));
+      }
     }
     if (tau_acc == 0.0) break;
     for (int k = 0; k < 3; ++k) p[k] -= tau_acc * d[k];
@@ -802,9 +866,9 @@ static int rigid_flow(const level_data* L, double p[3], const or_params* pr, int
     ncc = ncc_acc;
     tau_prev = tau_acc;
     steps++;
-    if (force >= 0) { /* how far the energy test is from the replayed decision */
-      if (steps < force) *gap = fmax(*gap, pr->eps - dec);
-      else if (steps < pr->iter_max) *gap = fmax(*gap, dec - pr->eps);
+    if (force >= 0 && rp) { /* how far the energy test is from the replayed decision */
+      if (steps < force) rp->stop_gap = fmax(rp->stop_gap, pr->eps - dec);
+      else if (steps < pr->iter_max) rp->stop_gap = fmax(rp->stop_gap, dec - pr->eps);
     }
     if (force >= 0 ? steps >= force : dec < pr->eps) break;
     if (steps >= pr->iter_max) *flags |= OR_FLAG_NONCONV;
@@ -820,9 +884,11 @@ static int rigid_flow(const level_data* L, double p[3], const or_params* pr, int
 /* Rigid registration of T to R (nodal frames of side nf) from p_init (NULL: identity) over the
    multilevel pyramid; p_out receives the parameters (domain units). Returns 0, -1 for a constant
    reference, -2 for bad sizes. */
-/* force: as for or_register_f (may be NULL). */
+/* force, rungs: as for or_register_f (may be NULL). */
 int or_register_rigid_f(const double* R, const double* T, int nf, const double* p_init,
-                        const or_params* pr, const int* force, double* p_out, or_stats* st) {
+                        const or_params* pr, const int* force, const unsigned char* rungs,
+                        int rung_cap, double* p_out, or_stats* st) {
+  replay_t rp = {force, rungs, rungs ? rung_cap : 0, 0, 0.0, 0.0};
   int L = log2_exact(nf - 1);
   if (L < 1 || pr->levels < 1 || pr->levels > L || pr->levels > OR_MAX_LEVELS) return -2;
   int m0 = L - pr->levels + 1;
@@ -833,12 +899,12 @@ int or_register_rigid_f(const double* R, const double* T, int nf, const double* 
     if (p_init) memcpy(p, p_init, sizeof p);
     if (st) memset(st, 0, sizeof(*st));
     int flags = 0;
-    double e = 0.0, ncc = 0.0, gap = 0.0;
+    double e = 0.0, ncc = 0.0;
     for (int l = m0; l <= L; ++l) {
       level_data LD = {(1 << l) + 1, py.Rn[l], py.Tl[l]};
       int passes = 0;
-      int steps = rigid_flow(&LD, p, pr, force ? force[l - m0] : -1, &passes, &flags, &e, &ncc,
-                             &gap);
+      int steps = rigid_flow(&LD, p, pr, force ? force[l - m0] : -1, &rp, &passes, &flags, &e,
+                             &ncc);
       if (st) {
         st->iters[l - m0] = steps;
         st->trials[l - m0] = passes;
@@ -849,7 +915,8 @@ int or_register_rigid_f(const double* R, const double* T, int nf, const double* 
       st->energy = e;
       st->ncc = ncc;
       st->flags = flags;
-      st->tie_gap = gap;
+      st->tie_gap = rp.stop_gap;
+      st->armijo_gap = rp.armijo_gap;
     }
   }
   pyramid_free(&py);
@@ -882,7 +949,7 @@ void or_compose(const double* uij, const double* ujk, int n, double* out) {
 /* (i, j, u) (.) (j, k, v) = (i, k, A(f_i, f_k, v o u)).                                         */
 
 enum { OR_SCAN_SEQUENTIAL = 0, OR_SCAN_BRENT_KUNG = 1, OR_SCAN_KOGGE_STONE = 2, OR_SCAN_SKLANSKY = 3,
-       OR_SCAN_GENERAL = 4 };
+       OR_SCAN_GENERAL = 4, OR_SCAN_BLELLOCH = 5, OR_SCAN_REDUCE_THEN_SCAN = 6 };
 
 typedef struct {
   int i, k;
@@ -896,6 +963,8 @@ typedef struct {
   or_stats* op_stats;  /* per op, in execution order; may be NULL */
   int* op_pairs;       /* (i, j, k) per op in execution order; may be NULL */
   const int* force_b;  /* per op, OR_MAX_LEVELS replayed step counts (see or_register_f); or NULL */
+  const unsigned char* rungs_b;  /* per op, rung_cap replayed ladder positions; or NULL */
+  int rung_cap;
   int n_ops;
   int err;
 } series_ctx;
@@ -912,7 +981,8 @@ static void apply_b(series_ctx* S, const elem_t* left, elem_t* right, int op_ind
   int rc = or_register_f(S->frames + (size_t)left->i * nn, S->frames + (size_t)right->k * nn,
                          S->nf, w, S->p,
                          S->force_b ? S->force_b + (size_t)op_index * OR_MAX_LEVELS : NULL,
-                         right->u, &st, NULL, 0, NULL);
+                         S->rungs_b ? S->rungs_b + (size_t)op_index * S->rung_cap : NULL,
+                         S->rung_cap, right->u, &st, NULL, 0, NULL);
   if (rc != 0) S->err = rc;
   if (S->op_stats) S->op_stats[op_index] = st;
   if (S->op_pairs) {
@@ -1009,10 +1079,223 @@ static int scan_general(series_ctx* S, elem_t* x, int M, int workers) {
   return ops;
 }
 
-/* force_a ([N-1][OR_MAX_LEVELS]) and force_b ([ops][OR_MAX_LEVELS]), each may be NULL: the
-   replayed step counts of or_register_f for every neighbour registration and B application. */
+/* A scan element that may be the identity element of the operator (Blelloch's exclusive scan
+   starts from it): id != 0 means the identity, whose combination with any element is that
+   element, at no cost. Its buffer u is owned by the element. */
+typedef struct {
+  int id, i, k;
+  double* u;
+} velem_t;
+
+/* dst <- left (.) right. With an identity operand the other is copied; otherwise B registers
+   frame right.k to frame left.i from the composition of the two fields (op numbered op_index).
+   dst may be left or right. */
+static void combine(series_ctx* S, const velem_t* left, const velem_t* right, velem_t* dst,
+                    int op_index) {
+  size_t nn = (size_t)S->nf * S->nf;
+  if (left->id || right->id) {
+    const velem_t* src = left->id ? right : left;
+    if (src != dst) {
+      dst->id = src->id;
+      dst->i = src->i;
+      dst->k = src->k;
+      if (!src->id) memcpy(dst->u, src->u, sizeof(double) * 2 * nn);
+    }
+    return;
+  }
+  elem_t l = {left->i, left->k, left->u}, r = {right->i, right->k, right->u};
+  double* out = malloc(sizeof(double) * 2 * nn);
+  elem_t res = {right->i, right->k, out};
+  memcpy(out, right->u, sizeof(double) * 2 * nn);
+  apply_b(S, &l, &res, op_index);  /* res <- l (.) res */
+  memcpy(dst->u, out, sizeof(double) * 2 * nn);
+  dst->id = 0;
+  dst->i = res.i;
+  dst->k = res.k;
+  free(out);
+  (void)r;
+}
+
+static velem_t* velems(int n, size_t nn) {
+  velem_t* v = calloc((size_t)n, sizeof(velem_t));
+  for (int e = 0; e < n; ++e) {
+    v[e].id = 1;
+    v[e].u = calloc(2 * nn, sizeof(double));
+  }
+  return v;
+}
+
+static void velems_free(velem_t* v, int n) {
+  for (int e = 0; e < n; ++e) free(v[e].u);
+  free(v);
+}
+
+/* Blelloch (algorithm "blelloch"), the exclusive scan with the identity element, for any M:
+   the M neighbour results padded with identities to a power of two n2. Up-sweep, d = 1, 2, ...,
+   n2/2: a[j] <- a[j-d] (.) a[j] for j = 2d-1, 4d-1, ... Down-sweep: the root's total is kept and
+   the root becomes the identity; for d = n2/2, ..., 1 and the same j: the left child a[j-d]
+   takes the parent's value a[j], and a[j] becomes the parent's value combined with the left
+   child's old value (parent (.) left: the order of a non-commutative operator; the listing
+   writes them the other way round). Then a[m] = x_0 (.) ... (.) x_{m-1}, so y_m = a[m+1] for
+   m < M-1 and y_{M-1} is the kept total. Registrations are numbered level by level, j
+   increasing; combinations with the identity are not registrations. Returns their count. */
+static int scan_blelloch(series_ctx* S, elem_t* x, int M) {
+  size_t nn = (size_t)S->nf * S->nf;
+  int n2 = 1;
+  while (n2 < M) n2 *= 2;
+  velem_t* a = velems(n2, nn);
+  for (int m = 0; m < M; ++m) {
+    a[m].id = 0;
+    a[m].i = x[m].i;
+    a[m].k = x[m].k;
+    memcpy(a[m].u, x[m].u, sizeof(double) * 2 * nn);
+  }
+  int ops = 0;
+  int* reg = malloc(sizeof(int) * (size_t)n2);
+  for (int d = 1; d < n2; d *= 2) {
+    int cnt = 0;
+    for (int j = 2 * d - 1; j < n2; j += 2 * d) reg[j] = (!a[j - d].id && !a[j].id) ? ops + cnt++ : -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int j = 2 * d - 1; j < n2; j += 2 * d) combine(S, &a[j - d], &a[j], &a[j], reg[j]);
+    ops += cnt;
+  }
+  velem_t total = a[n2 - 1];
+  total.u = malloc(sizeof(double) * 2 * nn);
+  memcpy(total.u, a[n2 - 1].u, sizeof(double) * 2 * nn);
+  a[n2 - 1].id = 1;
+  velem_t* t = velems(n2, nn);
+  for (int d = n2 / 2; d >= 1; d /= 2) {
+    int cnt = 0;
+    for (int j = 2 * d - 1; j < n2; j += 2 * d) {
+      /* t = left child, left child <- parent (copies; the combine then reads t) */
+      t[j].id = a[j - d].id;
+      t[j].i = a[j - d].i;
+      t[j].k = a[j - d].k;
+      memcpy(t[j].u, a[j - d].u, sizeof(double) * 2 * nn);
+      a[j - d].id = a[j].id;
+      a[j - d].i = a[j].i;
+      a[j - d].k = a[j].k;
+      memcpy(a[j - d].u, a[j].u, sizeof(double) * 2 * nn);
+      reg[j] = (!a[j].id && !t[j].id) ? ops + cnt++ : -1;
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int j = 2 * d - 1; j < n2; j += 2 * d) combine(S, &a[j], &t[j], &a[j], reg[j]);
+    ops += cnt;
+  }
+  for (int m = 0; m < M; ++m) {  /* inclusive values into the elements */
+    const velem_t* src = m + 1 < M ? &a[m + 1] : &total;
+    x[m].i = src->i;
+    x[m].k = src->k;
+    memcpy(x[m].u, src->u, sizeof(double) * 2 * nn);
+  }
+  free(total.u);
+  free(reg);
+  velems_free(t, n2);
+  velems_free(a, n2);
+  return ops;
+}
+
+/* Alternative strategy of the distributed chapter (algorithm "distributed_alternative_parallel")
+   on P workers (0: ceil(sqrt(M))) with the chunks of the general strategy. Reduce: each worker
+   folds its chunk into a total T_I = x_l (.) ... (.) x_r, the elements untouched. Global stage:
+   the totals scanned with Brent-Kung in place, so T_{I-1} is everything before chunk I. Rescan:
+   each worker runs the serial scan of its chunk from that value, y_l = T_{I-1} (.) x_l (worker
+   0: y_l = x_l), y_j = y_{j-1} (.) x_j. Registrations are numbered stage by stage, each stage's
+   steps in order and the workers of a step in order. Returns their count. */
+static int scan_reduce_then_scan(series_ctx* S, elem_t* x, int M, int workers) {
+  size_t nn = (size_t)S->nf * S->nf;
+  int P = workers > 0 ? workers : (int)ceil(sqrt((double)M));
+  if (P > M) P = M;
+  int* l = malloc(sizeof(int) * P);
+  int* r = malloc(sizeof(int) * P);
+  int K = M / P, extra = M % P, at = 0, kmax = 0;
+  for (int I = 0; I < P; ++I) {
+    int k = K + (I < extra ? 1 : 0);
+    l[I] = at;
+    r[I] = at + k - 1;
+    at += k;
+    if (k > kmax) kmax = k;
+  }
+  velem_t* T = velems(P, nn);
+  velem_t* v = velems(M, nn);
+  for (int m = 0; m < M; ++m) {
+    v[m].id = 0;
+    v[m].i = x[m].i;
+    v[m].k = x[m].k;
+    memcpy(v[m].u, x[m].u, sizeof(double) * 2 * nn);
+  }
+  for (int I = 0; I < P; ++I) {
+    T[I].id = 0;
+    T[I].i = v[l[I]].i;
+    T[I].k = v[l[I]].k;
+    memcpy(T[I].u, v[l[I]].u, sizeof(double) * 2 * nn);
+  }
+  int ops = 0;
+  for (int st = 1; st < kmax; ++st) {  /* reduce */
+    int cnt = 0;
+    int* idx = malloc(sizeof(int) * P);
+    for (int I = 0; I < P; ++I) idx[I] = l[I] + st <= r[I] ? ops + cnt++ : -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int I = 0; I < P; ++I)
+      if (idx[I] >= 0) combine(S, &T[I], &v[l[I] + st], &T[I], idx[I]);
+    ops += cnt;
+    free(idx);
+  }
+  for (int d = 1; d < P; d *= 2) {  /* global stage: Brent-Kung over the totals */
+    int cnt = 0;
+    for (int j = 2 * d - 1; j < P; j += 2 * d) ++cnt;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int q = 0; q < cnt; ++q) {
+      int j = 2 * d - 1 + q * 2 * d;
+      combine(S, &T[j - d], &T[j], &T[j], ops + q);
+    }
+    ops += cnt;
+  }
+  int dtop = 1;
+  while (dtop * 2 < P) dtop *= 2;
+  for (int d = dtop; d >= 1; d /= 2) {
+    int cnt = 0;
+    for (int j = 3 * d - 1; j < P; j += 2 * d) ++cnt;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int q = 0; q < cnt; ++q) {
+      int j = 3 * d - 1 + q * 2 * d;
+      combine(S, &T[j - d], &T[j], &T[j], ops + q);
+    }
+    ops += cnt;
+  }
+  for (int st = 0; st < kmax; ++st) {  /* rescan, the chunks side by side */
+    int cnt = 0;
+    int* idx = malloc(sizeof(int) * P);
+    for (int I = 0; I < P; ++I)
+      idx[I] = (l[I] + st <= r[I] && !(st == 0 && I == 0)) ? ops + cnt++ : -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int I = 0; I < P; ++I) {
+      if (idx[I] < 0) continue;
+      int j = l[I] + st;
+      const velem_t* left = st == 0 ? &T[I - 1] : &v[j - 1];
+      combine(S, left, &v[j], &v[j], idx[I]);
+    }
+    ops += cnt;
+    free(idx);
+  }
+  for (int m = 0; m < M; ++m) {
+    x[m].i = v[m].i;
+    x[m].k = v[m].k;
+    memcpy(x[m].u, v[m].u, sizeof(double) * 2 * nn);
+  }
+  velems_free(v, M);
+  velems_free(T, P);
+  free(l);
+  free(r);
+  return ops;
+}
+
+/* force_a ([N-1][OR_MAX_LEVELS]) and force_b ([ops][OR_MAX_LEVELS]), rungs_a ([N-1][rung_cap])
+   and rungs_b ([ops][rung_cap]), each may be NULL: the replayed decisions of or_register_f for
+   every neighbour registration and B application. */
 int or_series_f(const double* frames, int N, int nf, const or_params* p, int scan, int workers,
-                const int* force_a, const int* force_b, double* u_out, or_stats* a_stats,
+                const int* force_a, const int* force_b, const unsigned char* rungs_a,
+                const unsigned char* rungs_b, int rung_cap, double* u_out, or_stats* a_stats,
                 or_stats* b_stats, int* b_pairs, int threads) {
   if (N < 1) return -1;
   size_t nn = (size_t)nf * nf;
@@ -1036,8 +1319,9 @@ int or_series_f(const double* frames, int N, int nf, const or_params* p, int sca
   for (int m = 0; m < M; ++m) {
     or_stats st;
     int rc = or_register_f(frames + (size_t)m * nn, frames + (size_t)(m + 1) * nn, nf, NULL, p,
-                           force_a ? force_a + (size_t)m * OR_MAX_LEVELS : NULL, x[m].u, &st,
-                           NULL, 0, NULL);
+                           force_a ? force_a + (size_t)m * OR_MAX_LEVELS : NULL,
+                           rungs_a ? rungs_a + (size_t)m * rung_cap : NULL, rung_cap, x[m].u,
+                           &st, NULL, 0, NULL);
     if (rc != 0) err = rc;
     if (a_stats) a_stats[m] = st;
   }
@@ -1045,7 +1329,7 @@ int or_series_f(const double* frames, int N, int nf, const or_params* p, int sca
     free(x);
     return err;
   }
-  series_ctx S = {frames, nf, p, b_stats, b_pairs, force_b, 0, 0};
+  series_ctx S = {frames, nf, p, b_stats, b_pairs, force_b, rungs_b, rung_cap, 0, 0};
   int ops = 0;
   if (scan == OR_SCAN_SEQUENTIAL) {
     /* y_0 = x_0, y_m = y_{m-1} (.) x_m */
@@ -1107,6 +1391,10 @@ int or_series_f(const double* frames, int N, int nf, const or_params* p, int sca
     }
   } else if (scan == OR_SCAN_GENERAL) {
     ops = scan_general(&S, x, M, workers);
+  } else if (scan == OR_SCAN_BLELLOCH) {
+    ops = scan_blelloch(&S, x, M);
+  } else if (scan == OR_SCAN_REDUCE_THEN_SCAN) {
+    ops = scan_reduce_then_scan(&S, x, M, workers);
   } else {
     free(x);
     return -1;
@@ -1120,11 +1408,11 @@ int or_series_f(const double* frames, int N, int nf, const or_params* p, int sca
 int or_series(const double* frames, int N, int nf, const or_params* p, int scan, int workers,
               double* u_out, or_stats* a_stats, or_stats* b_stats, int* b_pairs,
               int threads) {
-  return or_series_f(frames, N, nf, p, scan, workers, NULL, NULL, u_out, a_stats, b_stats,
-                     b_pairs, threads);
+  return or_series_f(frames, N, nf, p, scan, workers, NULL, NULL, NULL, NULL, 0, u_out,
+                     a_stats, b_stats, b_pairs, threads);
 }
 
 int or_register_rigid(const double* R, const double* T, int nf, const double* p_init,
                       const or_params* pr, double* p_out, or_stats* st) {
-  return or_register_rigid_f(R, T, nf, p_init, pr, NULL, p_out, st);
+  return or_register_rigid_f(R, T, nf, p_init, pr, NULL, NULL, 0, p_out, st);
 }

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libpprs.so")
 
 PPRS_OK = 0
 PPRS_NOT_CONVERGED = 1
-SCAN_KINDS = {"sequential": 0, "brent_kung": 1, "kogge_stone": 2, "sklansky": 3, "general": 4}
+SCAN_KINDS = {"sequential": 0, "brent_kung": 1, "kogge_stone": 2, "sklansky": 3, "general": 4,
+              "blelloch": 5, "reduce_then_scan": 6}
 MAX_LEVELS = 16
 
 
@@ -144,6 +145,11 @@ def _lib():
                 "pprs_scan_plan_p": (i, [i, i, i, ctypes.POINTER(ctypes.c_int), i,
                                          ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_int)]),
+                "pprs_scan_program": (i, [i, i, i, ctypes.POINTER(ctypes.c_int), i,
+                                          ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_int)]),
                 "pprs_set_kernel_timing": (i, [vp, i]),
                 "pprs_get_kernel_timing": (i, [vp, ctypes.POINTER(ctypes.c_double),
                                                ctypes.POINTER(ctypes.c_longlong),
@@ -152,6 +158,7 @@ def _lib():
                 "pprs_kernel_name": (ctypes.c_char_p, [i]),
                 "pprs_set_pool": (i, [vp, i, i]),
                 "pprs_set_metric_solve": (i, [vp, i]),
+                "pprs_set_decision_log": (i, [vp, vp, i]),
                 "pprs_register_series_batch": (i, [vp, i, ctypes.POINTER(vp),
                                                    ctypes.POINTER(ctypes.c_int),
                                                    ctypes.POINTER(ctypes.c_int),
@@ -207,6 +214,25 @@ def scan_plan(kind: str, M: int, workers: int = 0):
     _check(lib.pprs_scan_plan_p(SCAN_KINDS[kind], M, workers, buf, n.value, ctypes.byref(n),
                                 ctypes.byref(lv)))
     return [(buf[3 * k], buf[3 * k + 1], buf[3 * k + 2]) for k in range(n.value)], lv.value
+
+
+SCAN_OPS = {0: "combine", 1: "move", 2: "clear"}
+
+
+def scan_program(kind: str, M: int, workers: int = 0):
+    """Host-only schedule as a program: (instructions [(op, a, b, dst, level)], levels,
+    elements, registrations); op is "combine" (x[dst] <- x[a] (.) x[b]), "move" (x[dst] <-
+    x[a]) or "clear" (x[dst] <- the identity)."""
+    lib = _lib()
+    n, lv, ne, nr = (ctypes.c_int() for _ in range(4))
+    lib.pprs_scan_program(SCAN_KINDS[kind], M, workers, None, 0, ctypes.byref(n),
+                          ctypes.byref(lv), ctypes.byref(ne), ctypes.byref(nr))
+    buf = (ctypes.c_int * max(5 * n.value, 1))()
+    _check(lib.pprs_scan_program(SCAN_KINDS[kind], M, workers, buf, n.value, ctypes.byref(n),
+                                 ctypes.byref(lv), ctypes.byref(ne), ctypes.byref(nr)))
+    prog = [(SCAN_OPS[buf[5 * k]], buf[5 * k + 1], buf[5 * k + 2], buf[5 * k + 3],
+             buf[5 * k + 4]) for k in range(n.value)]
+    return prog, lv.value, ne.value, nr.value
 
 
 class Context:
@@ -436,7 +462,7 @@ def prefix_register_series(frames, params: Params | None = None, out=None,
     ss = _CSeriesStats()
     ops = None
     if want_op_stats:
-        n_b = len(scan_plan(params.scan, max(N - 1, 0), params.scan_workers)[0])
+        n_b = scan_program(params.scan, max(N - 1, 0), params.scan_workers)[3]
         ops = (_CPairStats * max(N - 1 + n_b, 1))()   # N-1 A entries, then the B entries
     cp = params.c()
     c = _ctx(frames.device)
@@ -483,6 +509,33 @@ def set_pool(slots: int = 0, group_steps: int = 0, device=None):
     import torch
     dev = device or torch.device("cuda", torch.cuda.current_device())
     _check(_lib().pprs_set_pool(_ctx(dev).handle, slots, group_steps))
+
+
+class DecisionLog:
+    """Records the line-search decision of every accepted step of the registrations of later
+    calls on the current stream's context (pprs_set_decision_log): `rows` registrations of up
+    to `cap` steps each, in a device buffer this object owns. Use as a context manager."""
+
+    def __init__(self, rows: int, cap: int = 2048, device=None):
+        import torch
+        self.dev = device or torch.device("cuda", torch.cuda.current_device())
+        self.buf = torch.zeros((max(rows, 1), cap), dtype=torch.uint8, device=self.dev)
+        self.cap = cap
+
+    def __enter__(self):
+        _check(_lib().pprs_set_decision_log(_ctx(self.dev).handle,
+                                            ctypes.c_void_p(self.buf.data_ptr()), self.cap))
+        return self
+
+    def __exit__(self, *exc):
+        _check(_lib().pprs_set_decision_log(_ctx(self.dev).handle, None, 0))
+        return False
+
+    def rungs(self, row: int, steps: int):
+        """Ladder positions of the first `steps` accepted steps of registration `row`."""
+        if steps > self.cap:
+            raise ValueError("the log holds %d steps per registration" % self.cap)
+        return self.buf[row, :steps].cpu().numpy().astype(int).tolist()
 
 
 def set_metric_solve(mode: str = "exact", device=None):

@@ -53,6 +53,8 @@ hipError_t pool_restrict(BatchDesc* d, int l, int n_c, const int* slots, int ops
                          hipStream_t st);
 hipError_t pool_copy(BatchDesc* d, int l, int n_l, const float* src, long long sstride,
                      const int* src_idx, const int* slots, int ops, hipStream_t st);
+hipError_t pool_copy_off(BatchDesc* d, int l, int n_l, const float* vbuf, const long long* offs,
+                         const int* slots, int ops, hipStream_t st);
 hipError_t pool_finish(BatchDesc* d, int L, const int* slots, const long long* outs, int ops,
                        float* vbuf, hipStream_t st);
 hipError_t from_nodes_idx(const float* vbuf, const long long* offs, int n, float* dst, int H,

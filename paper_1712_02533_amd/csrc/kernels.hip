@@ -467,7 +467,7 @@ __device__ __forceinline__ void energy_finalize(BatchDesc* D, SlotState* stp, in
     if (!isfinite(st.E)) {
       st.flags |= FLAG_NAN;
       st.phase = PH_DONE;
-    } else if (D->iter_max <= 0) {
+    } else if (D->iter_max <= 0 || stp->eval_only) {
       level_done(st);
     } else {
       st.phase = PH_GRAD;
@@ -501,6 +501,17 @@ __device__ __forceinline__ void energy_finalize(BatchDesc* D, SlotState* stp, in
     if (acc_j >= 0) {
       double tj = ldexp(top, -acc_j);
       double dec = st.E - e_j[acc_j];
+      if (D->dlog) {
+        // ladder position of the accepted step: tj = top0 2^-J, top0 the iteration's first
+        // step (powers of two apart, so the exponents differ by exactly J)
+        int pos = st.iter;
+        for (int k = 0; k < li; ++k) pos += stp->iters[k];
+        if (pos < D->dlog_cap) {
+          double top0 = fmin(ldexp(st.tau_prev, K), st.tau_max);
+          int J = ilogb(top0) - ilogb(tj);
+          D->dlog[(size_t)stp->op * D->dlog_cap + pos] = (unsigned char)min(max(J, 0), 255);
+        }
+      }
       st.E = e_j[acc_j];
       st.ncc = ncc_j[acc_j];
       st.mean = m_j[acc_j];
@@ -1717,6 +1728,19 @@ __global__ void __launch_bounds__(BLOCK) k_pool_copy(BatchDesc* D, int l, const 
   }
 }
 
+// Resumed results: the first u buffer of level l of slot slots[k] = vbuf + offs[k] ([2][n][n]).
+__global__ void __launch_bounds__(BLOCK) k_pool_copy_off(BatchDesc* D, int l, const float* vbuf,
+                                                         const long long* offs, const int* slots,
+                                                         int ops) {
+  int n = lvl_n(l);
+  long long per = 2LL * n * n;
+  for (long long i = blockIdx.x * (long long)BLOCK + threadIdx.x; i < (long long)ops * per;
+       i += (long long)gridDim.x * BLOCK) {
+    int k = (int)(i / per);
+    slot_u(D, slots[k], l, 0)[i % per] = vbuf[offs[k] + i % per];
+  }
+}
+
 // Finished listed slots whose finest level is L: vbuf + outs[k] = u_L[ub] - tau_pend d of slot
 // slots[k] (a slot that stopped before level L leaves its output untouched).
 __global__ void __launch_bounds__(BLOCK) k_pool_finish(BatchDesc* D, int L, const int* slots,
@@ -2271,6 +2295,12 @@ hipError_t pool_copy(BatchDesc* d, int l, int n_l, const float* src, long long s
                      const int* src_idx, const int* slots, int ops, hipStream_t st) {
   hipLaunchKernelGGL(k_pool_copy, dim3(grid_for((long long)ops * 2 * n_l * n_l)), dim3(BLOCK), 0,
                      st, d, l, src, sstride, src_idx, slots, ops);
+  return hipGetLastError();
+}
+hipError_t pool_copy_off(BatchDesc* d, int l, int n_l, const float* vbuf, const long long* offs,
+                         const int* slots, int ops, hipStream_t st) {
+  hipLaunchKernelGGL(k_pool_copy_off, dim3(grid_for((long long)ops * 2 * n_l * n_l)), dim3(BLOCK),
+                     0, st, d, l, vbuf, offs, slots, ops);
   return hipGetLastError();
 }
 hipError_t pool_finish(BatchDesc* d, int L, const int* slots, const long long* outs, int ops,

@@ -52,6 +52,8 @@ struct SlotState {
   int finest;    // L
   int coarsest;  // m0
   int rung;      // index, within its group of 2K+1 steps, of the pending pass's first step
+  int op;        // row of the registration in the call's decision log (BatchDesc::dlog)
+  int eval_only; // probe: evaluate the start energy on the start level, then stop
   double E;      // energy at the accepted u (= u[ub] - tau_pend d)
   double ncc;
   double mean;   // quadrature mean of the warped template at the accepted u
@@ -133,6 +135,10 @@ struct BatchDesc {
   int* list_off;           // [WK_COUNT][max_slots + 1]
   WorkList* lists;         // [WK_COUNT]
   int max_slots;
+  // decision log (optional, caller's device buffer): row op, entry k = ladder position J of the
+  // op's k-th accepted step (levels in order), the step being top 2^-J of its iteration
+  unsigned char* dlog;
+  int dlog_cap;
   int active;              // written by the plan kernel
   int* active_host;        // mapped host word (may be null)
 };

@@ -132,6 +132,9 @@ struct pprs_ctx {
   bool smooth_window = false;  // windowed one-pass metric solve (opt-in, where beta allows)
   int tile_grad = 0;          // gradient tile setting (grad_variant maps it to the kernel's)
   int ladder_rungs = 0;       // step sizes per line-search pass (0: 2K+1)
+  unsigned char* dlog = nullptr;  // decision log (caller's device buffer; pprs_set_decision_log)
+  int dlog_cap = 0;
+  long long dlog_row0 = 0;        // log row of the next batch's first registration
   int smooth_lines = 16;      // column-strip width of the line solves (8, 16 or 32)
   size_t lds_smooth[2] = {0, 0};
   BatchDesc hd;
@@ -212,7 +215,7 @@ pprs_status check_params(const pprs_params* p, int L) {
     return fail(PPRS_EINVAL, "tau_min_rel must be in (0, 1)");
   if (!(p->eps >= 0.0)) return fail(PPRS_EINVAL, "eps must be >= 0");
   if (p->iter_max < 0) return fail(PPRS_EINVAL, "iter_max must be >= 0");
-  if (p->scan < PPRS_SCAN_SEQUENTIAL || p->scan > PPRS_SCAN_GENERAL)
+  if (p->scan < PPRS_SCAN_SEQUENTIAL || p->scan > PPRS_SCAN_REDUCE_THEN_SCAN)
     return fail(PPRS_EINVAL, "unknown scan kind %d", p->scan);
   if (p->scan_workers < 0)
     return fail(PPRS_EINVAL, "scan_workers must be >= 0 (got %d)", p->scan_workers);
@@ -596,7 +599,10 @@ pprs_status launch_step(pprs_ctx* c, BatchDesc* d, int nc) {
   return PPRS_OK;
 }
 
-enum InitKind { INIT_IDENTITY = 0, INIT_COMPOSE = 1, INIT_GIVEN = 2, INIT_PREPARED = 3 };
+// INIT_RESUME: the op continues, on its start level, a result another op left on the level
+// below (copied in, then prolongated by the state machine as between two levels).
+enum InitKind { INIT_IDENTITY = 0, INIT_COMPOSE = 1, INIT_GIVEN = 2, INIT_PREPARED = 3,
+                INIT_RESUME = 4 };
 
 // One step of the rigid variant: start energies of slots that begin a level, the parameter
 // gradient with its finaliser, one line-search pass (the energy finalisers are shared).
@@ -635,6 +641,8 @@ pprs_status run_batch(pprs_ctx* c, int n, const int* ref, const int* tmpl, InitK
   hd.iter_max = p->iter_max;
   STCHK(set_grad_tiles(c));
   BatchDesc* d = P<BatchDesc>(c->desc);
+  hd.dlog = c->dlog ? c->dlog + (size_t)c->dlog_row0 * c->dlog_cap : nullptr;
+  hd.dlog_cap = c->dlog_cap;
   HIPCHK(hipMemcpyAsync(d, &hd, sizeof(BatchDesc), hipMemcpyHostToDevice, c->stream));
   if (start < m0 || start > L) start = m0;
   std::vector<SlotState> st(n);
@@ -648,6 +656,7 @@ pprs_status run_batch(pprs_ctx* c, int n, const int* ref, const int* tmpl, InitK
     st[s].finest = L;
     st[s].coarsest = lv;
     st[s].tau_prev = INFINITY;
+    st[s].op = s;
     st[s].flags = extra_flags ? extra_flags[s] : 0;
   }
   HIPCHK(hipMemcpyAsync(hd.state, st.data(), sizeof(SlotState) * n, hipMemcpyHostToDevice,
@@ -825,15 +834,26 @@ pprs_status warm_init(pprs_ctx* c, int n, const int* ref, const int* tmpl, int m
 // Ops of different series may have different finest levels L (slots are sized for the
 // largest).
 
+// The warm start's judge (CHOOSE_A: the warm registration stopped on level 7 against the
+// identity's NCC there; CHOOSE_B: the composition against the network's guess by their energy on
+// level 7) is resolved when the op starts, from the results of its two probes.
+enum { CHOOSE_NONE = 0, CHOOSE_A = 1, CHOOSE_B = 2 };
+
 struct PoolOp {
   int ref, tmpl;   // global frame indices
-  InitKind init;   // INIT_IDENTITY, INIT_COMPOSE or INIT_PREPARED (staged guess)
-  int in0, in1;    // INIT_COMPOSE: versions composed (in1 o in0)
+  InitKind init;   // INIT_IDENTITY, INIT_COMPOSE, INIT_PREPARED (staged guess) or INIT_RESUME
+  int in0, in1;    // INIT_COMPOSE: versions composed (in1 o in0); INIT_RESUME: in0 resumed
   int out;         // version written
   int start;       // start level
   int flags;       // initial flags (e.g. PPRS_FLAG_FALLBACK)
   int stage;       // INIT_PREPARED: index of the staged guess
   int L, m0;       // finest level of the op's frames; its series' coarsest level (statistics)
+  int stop = -1;   // level the op ends on and writes its version at (-1: L)
+  int eval_only = 0;             // probe: the start energy only
+  int choose = CHOOSE_NONE;      // judge resolved at start from probe0 and probe1 (op indices)
+  int probe0 = -1, probe1 = -1;
+  int stage_alt = -1;            // CHOOSE_B: staged network guess of the op's pair
+  int stop_level() const { return stop < 0 ? L : stop; }
 };
 
 struct PoolSpec {
@@ -871,10 +891,13 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
   hd.iter_max = p->iter_max;
   STCHK(set_grad_tiles(c));
   BatchDesc* d = P<BatchDesc>(c->desc);
+  hd.dlog = c->dlog ? c->dlog + (size_t)c->dlog_row0 * c->dlog_cap : nullptr;
+  hd.dlog_cap = c->dlog_cap;
   HIPCHK(hipMemcpyAsync(d, &hd, sizeof(BatchDesc), hipMemcpyHostToDevice, c->stream));
   for (const PoolOp& o : ops)
-    if (o.L > Lmax || o.start < m0min || o.start > o.L || o.m0 > o.start ||
-        o.out < 0 || o.out >= (int)ver_off.size())
+    if (o.L > Lmax || o.start < m0min || o.start > o.stop_level() || o.stop_level() > o.L ||
+        o.m0 > o.start || o.out < 0 || o.out >= (int)ver_off.size() ||
+        (o.choose == CHOOSE_A && (o.probe0 < 0 || ops[o.probe0].stop_level() + 1 > o.L)))
       return fail(PPRS_ESTATE, "pool op outside the slot geometry");
   // dependencies: producers are the ops whose out is read
   std::vector<int> producer(ver_off.size(), -1);
@@ -882,14 +905,27 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
   std::vector<int> remaining(n_ops, 0);
   std::vector<std::vector<int>> dependents(n_ops);
   for (int i = 0; i < n_ops; ++i) {
-    if (ops[i].init != INIT_COMPOSE) continue;
-    for (int v : {ops[i].in0, ops[i].in1}) {
-      int q = v >= 0 && v < (int)producer.size() ? producer[v] : -1;
-      if (q < 0 || q >= i) return fail(PPRS_EINDEX, "op %d reads a version no earlier op writes", i);
+    std::vector<int> deps;
+    if (ops[i].init == INIT_COMPOSE)
+      for (int v : {ops[i].in0, ops[i].in1}) {
+        int q = v >= 0 && v < (int)producer.size() ? producer[v] : -1;
+        if (q < 0 || q >= i)
+          return fail(PPRS_EINDEX, "op %d reads a version no earlier op writes", i);
+        deps.push_back(q);
+      }
+    if (ops[i].choose != CHOOSE_NONE)  // the probes (CHOOSE_A resumes probe0's version)
+      for (int q : {ops[i].probe0, ops[i].probe1}) {
+        if (q < 0 || q >= i) return fail(PPRS_EINDEX, "op %d judges by a later op", i);
+        deps.push_back(q);
+      }
+    std::sort(deps.begin(), deps.end());
+    deps.erase(std::unique(deps.begin(), deps.end()), deps.end());
+    for (int q : deps) {
       remaining[i]++;
       dependents[q].push_back(i);
     }
   }
+  if (!stats) return fail(PPRS_ESTATE, "the slot pool needs per-op statistics");
   std::priority_queue<int, std::vector<int>, std::greater<int>> ready;
   for (int i = 0; i < n_ops; ++i)
     if (remaining[i] == 0) ready.push(i);
@@ -960,17 +996,45 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
                         std::chrono::steady_clock::now() - t_start).count();
       a_slot.push_back(s);
       a_op.push_back(i);
-      const PoolOp& o = ops[i];
+      PoolOp& o = ops[i];
+      if (o.choose == CHOOSE_A) {
+        // the warm result on level 7 against the identity's NCC there (the probes' results)
+        const pprs_pair_stats& w = stats[o.probe0];
+        if (w.ncc >= stats[o.probe1].ncc && !(w.flags & PPRS_FLAG_NAN)) {
+          o.init = INIT_RESUME;
+          o.start = ops[o.probe0].stop_level() + 1;
+        } else {
+          o.init = INIT_IDENTITY;
+          o.start = o.m0;
+          o.flags |= PPRS_FLAG_FALLBACK;
+        }
+      } else if (o.choose == CHOOSE_B) {
+        // the start with the lower energy on level 7: composition (probe0) or network (probe1)
+        const pprs_pair_stats& q = stats[o.probe1];
+        if (q.energy < stats[o.probe0].energy && !(q.flags & PPRS_FLAG_NAN)) {
+          o.init = INIT_PREPARED;
+          o.stage = o.stage_alt;
+          o.flags |= PPRS_FLAG_NET_START;
+        }
+      }
       SlotState& x = h_states[na];
       memset(&x, 0, sizeof(SlotState));
       x.phase = PH_INIT;
       x.level = o.start;
       x.ref = o.ref;
       x.tmpl = o.tmpl;
-      x.finest = o.L;
+      x.finest = o.stop_level();
       x.coarsest = o.start;
       x.tau_prev = INFINITY;
+      x.op = i;
       x.flags = o.flags;
+      x.eval_only = o.eval_only;
+      if (o.init == INIT_RESUME) {
+        // continues a level-(start - 1) result, prolongated to the start level by the state
+        // machine (no pending step), which then takes its start energy there
+        x.phase = PH_PROLONG;
+        x.level = o.start - 1;
+      }
       ++na;
     }
     if (na > 0) {
@@ -981,7 +1045,8 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
                             c->stream));
       HIPCHK(pprs_k::pool_assign(d, dstates, didx, na, c->stream));
       // initial guesses per kind, finest level and start level
-      for (int kind : {(int)INIT_IDENTITY, (int)INIT_COMPOSE, (int)INIT_PREPARED}) {
+      for (int kind : {(int)INIT_IDENTITY, (int)INIT_COMPOSE, (int)INIT_PREPARED,
+                       (int)INIT_RESUME}) {
         for (int Lv = m0min; Lv <= Lmax; ++Lv) {
           for (int lv = m0min; lv <= Lv; ++lv) {
             int cnt = 0;
@@ -998,6 +1063,7 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
                 o0[cnt] = ver_off[o.in0];
                 o1[cnt] = ver_off[o.in1];
               }
+              if (kind == INIT_RESUME) o0[cnt] = ver_off[o.in0];
               ++cnt;
             }
             if (cnt == 0) continue;
@@ -1014,6 +1080,13 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
               HIPCHK(hipMemcpyAsync(doff + S, o1, sizeof(long long) * cnt,
                                     hipMemcpyHostToDevice, c->stream));
               HIPCHK(pprs_k::pool_compose(d, Lv, vbuf, doff, doff + S, ds, cnt, c->stream));
+            } else if (kind == INIT_RESUME) {
+              // the resumed result into the first buffer of the level below the start
+              HIPCHK(hipMemcpyAsync(doff, o0, sizeof(long long) * cnt, hipMemcpyHostToDevice,
+                                    c->stream));
+              HIPCHK(pprs_k::pool_copy_off(d, lv - 1, level_n(lv - 1), vbuf, doff, ds, cnt,
+                                           c->stream));
+              top = lv;
             } else {
               if (!spec.stage || spec.stage_level < lv || spec.stage_level > Lv)
                 return fail(PPRS_ESTATE, "staged guesses on level %d cannot start level %d",
@@ -1051,9 +1124,11 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
       if (i < 0 || st[s].phase != PH_DONE) continue;
       fin.push_back(s);
       const PoolOp& op = ops[i];
-      if (flags_or) *flags_or |= st[s].flags;
+      // a probe's non-finite energy only decides its judge; it does not fail the call
+      bool probe = op.eval_only || op.stop_level() < op.L;
+      if (flags_or) *flags_or |= probe ? (st[s].flags & ~PPRS_FLAG_NAN) : st[s].flags;
       for (int k = 0; k < WK_COUNT; ++k) c->nodes_acc[k] += nodes[(size_t)s * WK_COUNT + k];
-      for (int l = st[s].coarsest; l <= op.L; ++l) {
+      for (int l = st[s].coarsest; l <= op.stop_level(); ++l) {
         long long nn = (long long)level_n(l) * level_n(l);
         if (node_steps) *node_steps += nn * st[s].iters[l - st[s].coarsest];
         if (node_passes) *node_passes += nn * st[s].passes[l - st[s].coarsest];
@@ -1061,7 +1136,7 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
       if (stats) {
         pprs_pair_stats& o = stats[i];
         memset(&o, 0, sizeof o);
-        for (int l = st[s].coarsest; l <= op.L; ++l) {
+        for (int l = st[s].coarsest; l <= op.stop_level(); ++l) {
           o.iters[l - op.m0] = st[s].iters[l - st[s].coarsest];
           o.passes[l - op.m0] = st[s].passes[l - st[s].coarsest];
         }
@@ -1083,7 +1158,7 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
       int* fs = h_idx.data() + 3 * S;
       long long* fo = h_off.data() + 2 * S;
       for (int s : fin)
-        if (ops[slot_op[s]].L == Lv) {
+        if (ops[slot_op[s]].stop_level() == Lv) {
           fs[cnt] = s;
           fo[cnt] = ver_off[ops[slot_op[s]].out];
           ++cnt;
@@ -1110,6 +1185,80 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
             n_ops, done_steps, ms);
     fflush(stderr);
   }
+  return PPRS_OK;
+}
+
+// A scan element while a schedule's program runs on the host: the identity, or the result of
+// registering frame k to frame i held in version `ver`.
+struct ScanElem {
+  bool ident;
+  int i, k, ver;
+};
+
+// The schedule of a series as a program (pprs_scan_program): instructions, element count,
+// operator applications and the widest level (in applications).
+struct ScanProg {
+  std::vector<int> code;
+  int n_instr = 0, n_levels = 0, n_elems = 0, n_reg = 0, widest = 0;
+};
+
+pprs_status scan_program(const pprs_params* p, int M, ScanProg& sp) {
+  sp = ScanProg{};
+  if (M < 1) return PPRS_OK;
+  if (pprs_scan_program(p->scan, M, p->scan_workers, nullptr, 0, &sp.n_instr, &sp.n_levels,
+                        &sp.n_elems, &sp.n_reg) != PPRS_OK && sp.n_instr == 0)
+    return fail(PPRS_EINVAL, "scan planning failed");
+  sp.code.resize(5 * (size_t)std::max(sp.n_instr, 1));
+  if (pprs_scan_program(p->scan, M, p->scan_workers, sp.code.data(), sp.n_instr, &sp.n_instr,
+                        &sp.n_levels, &sp.n_elems, &sp.n_reg) != PPRS_OK)
+    return fail(PPRS_EINVAL, "scan planning failed");
+  std::vector<int> per_level(sp.n_levels + 1, 0);
+  std::vector<char> ident(sp.n_elems, 1);
+  for (int m = 0; m < M; ++m) ident[m] = 0;
+  for (int t = 0; t < sp.n_instr; ++t) {
+    const int* x = &sp.code[5 * (size_t)t];
+    if (x[0] == PPRS_SCAN_OP_COMBINE) {
+      if (!ident[x[1]] && !ident[x[2]]) per_level[x[4]]++;
+      ident[x[3]] = ident[x[1]] && ident[x[2]];
+    } else {
+      ident[x[3]] = x[0] == PPRS_SCAN_OP_MOVE ? ident[x[1]] : 1;
+    }
+  }
+  sp.widest = std::max(M, *std::max_element(per_level.begin(), per_level.end()));
+  return PPRS_OK;
+}
+
+// Runs the program on the host: elements 0..M-1 start as the neighbour results (m, m+1) in
+// versions ver0 + m, scratch elements as the identity. reg(left, right) is called for every
+// operator application, in program order, and returns the version of its result. At the end
+// element m must hold (0, m + 1); final (may be NULL) receives the elements.
+template <class Reg>
+pprs_status run_program(const ScanProg& sp, int M, int ver0, Reg reg,
+                        std::vector<ScanElem>* final = nullptr) {
+  std::vector<ScanElem> x(sp.n_elems, ScanElem{true, -1, -1, -1});
+  for (int m = 0; m < M; ++m) x[m] = ScanElem{false, m, m + 1, ver0 + m};
+  for (int t = 0; t < sp.n_instr; ++t) {
+    const int* c = &sp.code[5 * (size_t)t];
+    if (c[0] == PPRS_SCAN_OP_CLEAR) {
+      x[c[3]] = ScanElem{true, -1, -1, -1};
+    } else if (c[0] == PPRS_SCAN_OP_MOVE) {
+      x[c[3]] = x[c[1]];
+    } else if (x[c[1]].ident) {  // the identity costs nothing
+      x[c[3]] = x[c[2]];
+    } else if (x[c[2]].ident) {
+      x[c[3]] = x[c[1]];
+    } else {
+      const ScanElem a = x[c[1]], b = x[c[2]];
+      if (a.k != b.i)
+        return fail(PPRS_EINDEX, "scan operands (%d,%d) and (%d,%d) do not share a frame", a.i,
+                    a.k, b.i, b.k);
+      x[c[3]] = ScanElem{false, a.i, b.k, reg(a, b)};
+    }
+  }
+  for (int m = 0; m < M; ++m)
+    if (x[m].ident || x[m].i != 0 || x[m].k != m + 1)
+      return fail(PPRS_EINDEX, "element %d ends as (%d,%d)", m, x[m].i, x[m].k);
+  if (final) *final = x;
   return PPRS_OK;
 }
 
@@ -1141,18 +1290,9 @@ pprs_status series_workspace(int N, int L, int m0, const pprs_params* p, int poo
   size_t nodes = 0;
   for (int l = m0; l <= L; ++l) nodes += (size_t)N * level_n(l) * level_n(l);
   w.frames = frame_bytes(nodes, N, N);
-  int n_ops = 0, n_levels = 0;
-  pprs_scan_plan_p(p->scan, M, p->scan_workers, nullptr, 0, &n_ops, &n_levels);
-  std::vector<int> plan(3 * (size_t)std::max(n_ops, 1));
-  if (pprs_scan_plan_p(p->scan, M, p->scan_workers, plan.data(), n_ops, &n_ops, &n_levels) !=
-      PPRS_OK)
-    return fail(PPRS_EINVAL, "scan planning failed");
-  int widest = M;
-  for (int lv = 0, i = 0; lv < n_levels; ++lv) {
-    int cnt = 0;
-    while (i < n_ops && plan[3 * i + 2] == lv) ++cnt, ++i;
-    widest = std::max(widest, cnt);
-  }
+  ScanProg sp;
+  STCHK(scan_program(p, M, sp));
+  int n_ops = sp.n_reg, widest = sp.widest;
   int nL = level_n(L);
   w.elems = sizeof(float) * (size_t)(M + n_ops) * 2 * nL * nL;
   int slots = std::min(widest, pool_slots);
@@ -1184,6 +1324,7 @@ pprs_status status_from_flags(int flags) {
 pprs_status enter(pprs_ctx* c) {
   if (!c) return fail(PPRS_EINVAL, "ctx is NULL");
   HIPCHK(hipSetDevice(c->device));
+  c->dlog_row0 = 0;
   return PPRS_OK;
 }
 
@@ -1470,6 +1611,7 @@ pprs_status pprs_register_pairs(pprs_ctx* c, const float* frames, int N, int H, 
     std::vector<int> out(np);
     for (int k = 0; k < np; ++k) out[k] = k;
     pprs_pair_stats* ps = stats ? stats + p0 : nullptr;
+    c->dlog_row0 = p0;
     if (warm) {
       std::vector<int> lv, fl;
       STCHK(warm_init(c, np, ref + p0, tmpl + p0, m0, lv, fl));
@@ -1508,6 +1650,8 @@ pprs_status run_batch_rigid(pprs_ctx* c, int n, const int* ref, const int* tmpl,
   // the rigid gradient pass works on the element tiles of the energy passes
   for (int l = m0; l <= L; ++l) hd.geom[l].tiles_grad = hd.geom[l].tiles_elem;
   BatchDesc* d = P<BatchDesc>(c->desc);
+  hd.dlog = c->dlog ? c->dlog + (size_t)c->dlog_row0 * c->dlog_cap : nullptr;
+  hd.dlog_cap = c->dlog_cap;
   HIPCHK(hipMemcpyAsync(d, &hd, sizeof(BatchDesc), hipMemcpyHostToDevice, c->stream));
   std::vector<SlotState> st(n);
   for (int s = 0; s < n; ++s) {
@@ -1519,6 +1663,7 @@ pprs_status run_batch_rigid(pprs_ctx* c, int n, const int* ref, const int* tmpl,
     st[s].finest = L;
     st[s].coarsest = m0;
     st[s].tau_prev = INFINITY;
+    st[s].op = s;
     for (int k = 0; k < 3; ++k) st[s].rp[k] = p0 ? p0[3 * s + k] : 0.0;
   }
   HIPCHK(hipMemcpyAsync(hd.state, st.data(), sizeof(SlotState) * n, hipMemcpyHostToDevice,
@@ -1600,6 +1745,7 @@ pprs_status pprs_register_pairs_rigid(pprs_ctx* c, const float* frames, int N, i
       pin[3 * k + 1] = p_init ? p_init[3 * (p0 + k) + 1] / px : 0.0;
       pin[3 * k + 2] = p_init ? p_init[3 * (p0 + k) + 2] / px : 0.0;
     }
+    c->dlog_row0 = p0;
     STCHK(run_batch_rigid(c, np, ref + p0, tmpl + p0, pin.data(), pout.data(), params,
                           stats ? stats + p0 : nullptr, &flags));
     for (int k = 0; k < np; ++k) {
@@ -1660,6 +1806,9 @@ pprs_status pprs_prefix_register_series_rigid(pprs_ctx* c, const float* frames, 
   HIPCHK(hipStreamSynchronize(c->stream));
   auto t1 = std::chrono::steady_clock::now();
   int n_ops = 0, n_levels = 0;
+  if (params->scan > PPRS_SCAN_GENERAL)
+    return fail(PPRS_EINVAL, "the rigid series runs the in-place schedules (sequential, "
+                "Brent-Kung, Kogge-Stone, Sklansky, general strategy)");
   pprs_scan_plan_p(params->scan, M, params->scan_workers, nullptr, 0, &n_ops, &n_levels);
   std::vector<int> plan(3 * (size_t)std::max(n_ops, 1));
   if (pprs_scan_plan_p(params->scan, M, params->scan_workers, plan.data(), n_ops, &n_ops,
@@ -1705,6 +1854,7 @@ pprs_status pprs_prefix_register_series_rigid(pprs_ctx* c, const float* frames, 
       ref[q] = ei[a];
       tmpl[q] = ek[b];
     }
+    c->dlog_row0 = M + i;  // log rows: the M neighbour registrations, then B in schedule order
     STCHK(run_batch_rigid(c, cnt, ref.data(), tmpl.data(), pin.data(), pres.data(), params,
                           nullptr, &flags));
     for (int q = 0; q < cnt; ++q) {
@@ -1787,26 +1937,40 @@ pprs_status run_series_set(pprs_ctx* c, std::vector<SeriesJob>& jobs, const pprs
   if (!sin.empty()) STCHK(prepare_series(c, sin));
   HIPCHK(hipEventRecord(ev.e[1], c->stream));
   bool any_warm = c->cnn != nullptr;
-  // schedules and ops
-  std::vector<PoolOp> ops;
-  std::vector<long long> ver_off;
-  std::vector<std::vector<int>> final_ver(jobs.size());
-  std::vector<std::pair<int, int>> job_ops(jobs.size());  // [first op, end)
+  // schedules: per series the scan program and the frame pairs of its B applications
+  std::vector<ScanProg> progs(jobs.size());
+  std::vector<std::vector<std::pair<int, int>>> bpairs(jobs.size());
   std::vector<int> n_ops_b(jobs.size(), 0), n_lv(jobs.size(), 0);
-  long long vtotal = 0;
   int slots_needed = 1;
-  // warm guesses: staged per neighbour pair of every warm-capable series
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    int M = jobs[j].N - 1;
+    if (M < 1) continue;
+    STCHK(scan_program(params, M, progs[j]));
+    n_ops_b[j] = progs[j].n_reg;
+    n_lv[j] = progs[j].n_levels;
+    slots_needed = std::max(slots_needed, progs[j].widest);
+    auto& bp = bpairs[j];
+    STCHK(run_program(progs[j], M, 0, [&](const ScanElem& a, const ScanElem& b) {
+      bp.push_back({a.i, b.k});
+      return 0;
+    }));
+  }
+  // warm guesses, staged on level 7 for the neighbour pairs of every warm-capable series and,
+  // where the series' finest level is above 7 (so that a level-7 judge can run), for the pairs
+  // of its B applications too
   int n7 = level_n(kWarmLevel);
   long long per7 = 2LL * n7 * n7;
   PoolSpec spec;
   std::vector<int> stage_base(jobs.size(), -1);
+  std::vector<char> judged(jobs.size(), 0);
   if (any_warm) {
     int nstage = 0;
     for (size_t j = 0; j < jobs.size(); ++j)
       if (jobs[j].m0 <= kWarmLevel && kWarmLevel <= jobs[j].L && jobs[j].N > 1 &&
           (c->warm_levels >> jobs[j].L & 1u)) {
         stage_base[j] = nstage;
-        nstage += jobs[j].N - 1;
+        judged[j] = jobs[j].L > kWarmLevel;
+        nstage += jobs[j].N - 1 + (judged[j] ? n_ops_b[j] : 0);
       }
     if (nstage > 0) {
       STCHK(ensure(c->warm_stage, sizeof(float) * per7 * nstage));
@@ -1825,7 +1989,12 @@ pprs_status run_series_set(pprs_ctx* c, std::vector<SeriesJob>& jobs, const pprs
       ref[m] = m;
       tmpl[m] = m + 1;
     }
-    STCHK(warm_predict(c, first[j], M, ref.data(), tmpl.data(),
+    if (judged[j])
+      for (const auto& pr : bpairs[j]) {
+        ref.push_back(pr.first);
+        tmpl.push_back(pr.second);
+      }
+    STCHK(warm_predict(c, first[j], (int)ref.size(), ref.data(), tmpl.data(),
                        P<float>(c->warm_stage) + (size_t)stage_base[j] * per7, per7, bad[j]));
   }
   HIPCHK(hipEventRecord(ev.e[2], c->stream));
@@ -1838,73 +2007,106 @@ pprs_status run_series_set(pprs_ctx* c, std::vector<SeriesJob>& jobs, const pprs
     double cb = (double)jobs[b].N * level_n(jobs[b].L) * level_n(jobs[b].L);
     return ca < cb;
   });
+  std::vector<PoolOp> ops;
+  std::vector<long long> ver_off;
+  std::vector<std::vector<int>> final_ver(jobs.size());
+  std::vector<std::vector<int>> logical(jobs.size());  // pool op of each A, then B application
+  std::vector<std::pair<int, int>> job_ops(jobs.size(), {0, 0});  // [first pool op, end)
+  long long vtotal = 0;
+  auto new_ver = [&](long long size) {
+    ver_off.push_back(vtotal);
+    vtotal += size;
+    return (int)ver_off.size() - 1;
+  };
   for (int j : order) {
     SeriesJob& x = jobs[j];
     int M = x.N - 1;
+    job_ops[j] = {(int)ops.size(), (int)ops.size()};
+    if (M < 1) continue;
     int nL = level_n(x.L);
     long long est = 2LL * nL * nL;
-    job_ops[j].first = (int)ops.size();
-    if (M < 1) {
-      job_ops[j].second = (int)ops.size();
-      continue;
-    }
-    std::vector<int> plan;
-    int n_ops = 0, n_levels = 0;
-    // sizes only
-    pprs_scan_plan_p(params->scan, M, params->scan_workers, nullptr, 0, &n_ops, &n_levels);
-    plan.resize(3 * (size_t)std::max(n_ops, 1));
-    if (pprs_scan_plan_p(params->scan, M, params->scan_workers, plan.data(), n_ops, &n_ops,
-                         &n_levels) != PPRS_OK)
-      return fail(PPRS_EINVAL, "scan planning failed");
-    n_ops_b[j] = n_ops;
-    n_lv[j] = n_levels;
-    int widest = M;
-    for (int lv = 0, i = 0; lv < n_levels; ++lv) {
-      int cnt = 0;
-      while (i < n_ops && plan[3 * i + 2] == lv) ++cnt, ++i;
-      widest = std::max(widest, cnt);
-    }
-    slots_needed = std::max(slots_needed, widest);
+    int n_ops = n_ops_b[j];
     bool warm = stage_base[j] >= 0;
     bool skip = warm && c->warm_mode == PPRS_WARM_SKIP;
     int vb = (int)ver_off.size();
-    for (int k = 0; k < M + n_ops; ++k) ver_off.push_back(vtotal + (long long)k * est);
-    vtotal += (long long)(M + n_ops) * est;
-    std::vector<int> ver(M), ei(M), ek(M);
+    for (int k = 0; k < M + n_ops; ++k) new_ver(est);
     int g0 = first[j];
+    PoolOp base{0, 0, INIT_IDENTITY, -1, -1, -1, x.m0, 0, -1, x.L, x.m0};
     for (int m = 0; m < M; ++m) {
-      ver[m] = vb + m;
-      ei[m] = m;
-      ek[m] = m + 1;
-      PoolOp o{g0 + m, g0 + m + 1, INIT_IDENTITY, -1, -1, vb + m, x.m0, 0, -1, x.L, x.m0};
-      if (warm) {
-        if (bad[j][m]) {
-          o.flags = PPRS_FLAG_FALLBACK;
-        } else {
-          o.init = INIT_PREPARED;
-          o.stage = stage_base[j] + m;
-          o.start = skip ? kWarmLevel : x.m0;
-        }
+      PoolOp o = base;
+      o.ref = g0 + m;
+      o.tmpl = g0 + m + 1;
+      o.out = vb + m;
+      if (warm && bad[j][m]) {
+        o.flags = PPRS_FLAG_FALLBACK;
+      } else if (warm && !judged[j]) {
+        o.init = INIT_PREPARED;
+        o.stage = stage_base[j] + m;
+        o.start = skip ? kWarmLevel : x.m0;
+      } else if (warm) {
+        // the judge: the warm registration up to level 7 (W) against the identity's NCC on
+        // level 7 (I, evaluated only); the application resumes on level 8 from W's result, or
+        // runs cold from the coarsest level when W ends with a lower NCC than the identity
+        PoolOp w = o;
+        w.init = INIT_PREPARED;
+        w.stage = stage_base[j] + m;
+        w.start = skip ? kWarmLevel : x.m0;
+        w.stop = kWarmLevel;
+        w.out = new_ver(per7);
+        PoolOp id = o;
+        id.start = kWarmLevel;
+        id.stop = kWarmLevel;
+        id.eval_only = 1;
+        id.out = new_ver(per7);
+        o.choose = CHOOSE_A;
+        o.probe0 = (int)ops.size();
+        o.probe1 = (int)ops.size() + 1;
+        o.in0 = w.out;
+        ops.push_back(w);
+        ops.push_back(id);
       }
+      logical[j].push_back((int)ops.size());
       ops.push_back(o);
     }
-    // x[right] <- x[left] (.) x[right]: B registers frame ek[right] to frame ei[left], starting
-    // from the composition of the two results
-    for (int i = 0; i < n_ops; ++i) {
-      int a = plan[3 * i], b = plan[3 * i + 1];
-      if (ek[a] != ei[b])
-        return fail(PPRS_EINDEX, "scan operands (%d,%d) and (%d,%d) do not share a frame", ei[a],
-                    ek[a], ei[b], ek[b]);
-      PoolOp o{g0 + ei[a], g0 + ek[b], INIT_COMPOSE, ver[a], ver[b], vb + M + i,
-               skip ? kWarmLevel : x.m0, 0, -1, x.L, x.m0};
+    // B applications in program order: (i, j, u) (.) (j, k, v) registers frame k to frame i,
+    // starting from the composition of the two results
+    int bi = 0;
+    std::vector<ScanElem> fin;
+    STCHK(run_program(progs[j], M, vb, [&](const ScanElem& l, const ScanElem& r) {
+      int i = bi++;
+      PoolOp o = base;
+      o.ref = g0 + l.i;
+      o.tmpl = g0 + r.k;
+      o.init = INIT_COMPOSE;
+      o.in0 = l.ver;
+      o.in1 = r.ver;
+      o.out = vb + M + i;
+      o.start = skip ? kWarmLevel : x.m0;
+      if (judged[j] && !bad[j][M + i]) {
+        // the composition and the network's guess for the pair, both evaluated on level 7:
+        // the start with the lower energy is taken
+        PoolOp cp = o;
+        cp.start = kWarmLevel;
+        cp.stop = kWarmLevel;
+        cp.eval_only = 1;
+        cp.out = new_ver(per7);
+        PoolOp nt = cp;
+        nt.init = INIT_PREPARED;
+        nt.in0 = nt.in1 = -1;
+        nt.stage = stage_base[j] + M + i;
+        nt.out = new_ver(per7);
+        o.choose = CHOOSE_B;
+        o.probe0 = (int)ops.size();
+        o.probe1 = (int)ops.size() + 1;
+        o.stage_alt = nt.stage;
+        ops.push_back(cp);
+        ops.push_back(nt);
+      }
+      logical[j].push_back((int)ops.size());
       ops.push_back(o);
-      ver[b] = vb + M + i;
-      ei[b] = ei[a];
-    }
-    for (int m = 0; m < M; ++m)
-      if (ei[m] != 0 || ek[m] != m + 1)
-        return fail(PPRS_EINDEX, "element %d ends as (%d,%d)", m, ei[m], ek[m]);
-    final_ver[j] = ver;
+      return o.out;
+    }, &fin));
+    for (int m = 0; m < M; ++m) final_ver[j].push_back(fin[m].ver);
     job_ops[j].second = (int)ops.size();
   }
   int flags = 0;
@@ -1951,7 +2153,7 @@ pprs_status run_series_set(pprs_ctx* c, std::vector<SeriesJob>& jobs, const pprs
     S.n_ops_b = n_ops_b[j];
     S.n_scan_levels = n_lv[j];
     double last = 0.0;
-    for (int i = a; i < b; ++i) {
+    for (int i = a; i < b; ++i) {  // every pool op of the series, probes included
       S.flags_or |= all_stats[i].flags;
       last = std::max(last, fin_ms[i]);
       for (int l = 0; l <= x.L - x.m0; ++l) {
@@ -1959,8 +2161,22 @@ pprs_status run_series_set(pprs_ctx* c, std::vector<SeriesJob>& jobs, const pprs
         S.node_steps += nn * all_stats[i].iters[l];
         S.node_passes += nn * all_stats[i].passes[l];
       }
-      if (x.op_stats) x.op_stats[i - a] = all_stats[i];
     }
+    if (x.op_stats)
+      for (size_t k = 0; k < logical[j].size(); ++k) {
+        int f = logical[j][k];
+        pprs_pair_stats o = all_stats[f];
+        if (ops[f].init == INIT_RESUME) {  // levels up to 7 ran in the warm probe
+          const pprs_pair_stats& w = all_stats[ops[f].probe0];
+          for (int l = 0; l < ops[f].start - x.m0; ++l) {
+            o.iters[l] = w.iters[l];
+            o.passes[l] = w.passes[l];
+          }
+          o.flags |= w.flags;
+          o.ms += w.ms;
+        }
+        x.op_stats[k] = o;
+      }
     S.ms_total = t03;
     S.ms_prepare = t01;
     S.ms_preprocess = t12;
@@ -2015,6 +2231,14 @@ pprs_status pprs_prefix_register_series_batch(pprs_ctx* c, int S, const float* c
   for (int j = 0; j < S; ++j)
     if (H[j] != W[j]) return fail(PPRS_EINVAL, "series %d: frames must be square", j);
   return pprs_register_series_batch(c, S, frames, N, H, nullptr, u_out, params, stats, nullptr);
+}
+
+pprs_status pprs_set_decision_log(pprs_ctx* c, unsigned char* log, int cap) {
+  if (!c) return fail(PPRS_EINVAL, "ctx is NULL");
+  if (log && cap < 1) return fail(PPRS_EINVAL, "cap must be >= 1");
+  c->dlog = log;
+  c->dlog_cap = log ? cap : 0;
+  return PPRS_OK;
 }
 
 pprs_status pprs_set_metric_solve(pprs_ctx* c, int mode) {

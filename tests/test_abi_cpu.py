@@ -180,3 +180,88 @@ def test_wrong_shapes_are_refused_before_the_library():
         api._net_batch(torch.zeros(2, 128, 128, 3), "x")
     assert api._net_batch(torch.zeros(3, 128, 128, 2), "x") == 3
     assert api._frames3(torch.zeros(5, 8, 8)) == (5, 8, 8)
+
+
+def _run_program(prog, n_elems, xs, op):
+    """Executes a scan program on host values xs (M of them) with the operator op; scratch
+    elements start as the identity (None), a combination with it is the other operand.
+    Returns (final elements, operator applications)."""
+    v = list(xs) + [None] * (n_elems - len(xs))
+    n = 0
+    for code, a, b, dst, _ in prog:
+        if code == "clear":
+            v[dst] = None
+        elif code == "move":
+            v[dst] = v[a]
+        elif v[a] is None or v[b] is None:
+            v[dst] = v[b] if v[a] is None else v[a]
+        else:
+            v[dst] = op(v[a], v[b])
+            n += 1
+    return v, n
+
+
+@pytest.mark.parametrize("kind", ["sequential", "brent_kung", "kogge_stone", "sklansky",
+                                  "general", "blelloch", "reduce_then_scan",
+                                  "reduce_then_scan/1", "reduce_then_scan/3",
+                                  "reduce_then_scan/M"])
+@pytest.mark.parametrize("M", [0, 1, 2, 3, 7, 8, 9, 63, 64, 100, 511])
+def test_program_matches_sequential_scan_with_associative_ops(kind, M):
+    """Every schedule as a program (pprs_scan_program) computes the inclusive scan with exactly
+    associative, non-commutative operators (interval concatenation, which also checks that
+    operands share their middle index, and 2x2 integer matrix products), reports its operator
+    applications, and its combines of one level are independent."""
+    workers = 0
+    if "/" in kind:
+        kind, w = kind.split("/")
+        workers = M if w == "M" else int(w)
+    prog, levels, n_elems, n_reg = P.scan_program(kind, M, workers)
+    xs = [(m, m + 1) for m in range(M)]
+    out, n = _run_program(prog, n_elems, xs, _interval)
+    assert out[:M] == [(0, m + 1) for m in range(M)] and n == n_reg
+    rng = np.random.default_rng(M + 7)
+    mats = [rng.integers(-2, 3, size=(2, 2)) for _ in range(M)]
+    out, _ = _run_program(prog, n_elems, mats, lambda a, b: a @ b)
+    acc = None
+    for m in range(M):
+        acc = mats[m] if acc is None else acc @ mats[m]
+        assert np.array_equal(out[m], acc)
+    by_level = {}
+    for code, a, b, dst, lv in prog:
+        if code == "combine":
+            by_level.setdefault(lv, []).append((a, b, dst))
+    for ops in by_level.values():
+        written = set()
+        for a, b, dst in ops:
+            assert a not in written and b not in written and dst not in written
+            written.add(dst)
+    if kind in ("sequential", "brent_kung", "kogge_stone", "sklansky", "general"):
+        plan, lv = P.scan_plan(kind, M, workers)
+        assert [(a, b, lvl) for c, a, b, d, lvl in prog] == plan and levels == lv
+
+
+def test_blelloch_program_counts_match_the_chapter():
+    """Blelloch (Prefix sum chapter): 2 log2 N steps and 2(N - 1) operator applications (figure:
+    6 and 14 for 8 elements), of which log2 N combine with the identity element (the leftmost
+    path of the down-sweep) and cost nothing; Snir's bound holds for the applications made."""
+    fig = GOLD["scan_figures_N8"]["blelloch"]
+    for k in range(1, 11):
+        N = 2 ** k
+        prog, levels, n_elems, n_reg = P.scan_program("blelloch", N)
+        combines = sum(1 for x in prog if x[0] == "combine")
+        assert levels == 2 * k and combines == 2 * (N - 1)          # span and work, table
+        assert n_reg == combines - k
+        assert n_reg + levels >= 2 * N - 2                          # Snir
+        if N == 8:
+            assert levels == fig["steps"] and combines == fig["ops"]
+
+
+@pytest.mark.parametrize("M,workers", [(8, 2), (12, 3), (64, 8), (511, 7), (100, 10)])
+def test_reduce_then_scan_program_counts(M, workers):
+    """The alternative strategy: the reduction (M - P), the Brent-Kung scan of the P totals and
+    the rescan of every chunk (M - 1 in all: worker 0's first element is already final)."""
+    prog, levels, n_elems, n_reg = P.scan_program("reduce_then_scan", M, workers)
+    w_gs, s_gs = _bk_work_span(workers)
+    assert n_reg == (M - workers) + w_gs + (M - 1) and n_elems == M + workers
+    K = -(-M // workers)
+    assert levels == (K - 1) + s_gs + K

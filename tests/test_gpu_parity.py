@@ -70,16 +70,18 @@ def _pair_case(spec, i, k, levels, **kw):
     s = make_series(spec)
     fr = torch.tensor(s.frames, device="cuda")
     say("register_pair", spec, (i, k), "levels", levels)
-    u, st = P.register_pair(fr[i].contiguous(), fr[k].contiguous(),
-                            params=_gpu_params(levels, **kw))
+    with P.DecisionLog(1) as log:
+        u, st = P.register_pair(fr[i].contiguous(), fr[k].contiguous(),
+                                params=_gpu_params(levels, **kw))
     u = u.cpu().numpy()
+    rungs = log.rungs(0, sum(st.iters))
     op = _oracle_params(levels, **kw)
     R, T = O.frame_to_nodes(s.frames[i]), O.frame_to_nodes(s.frames[k])
     uo, sto, tr = O.register(R, T, op, trace_cap=8192)
     say("  gpu iters", st.iters, "passes", st.passes, "E %.9f" % st.energy)
     say("  ora iters", sto.iters, "passes", sto.trials, "E %.9f" % sto.energy)
-    if st.iters != sto.iters:
-        uo, sto = replay_gpu_decisions(R, T, op, st.iters, sto.iters)
+    if st.iters != sto.iters or rungs != O.trace_rungs(tr, op):
+        uo, sto = replay_gpu_decisions(R, T, op, st, rungs)
     ref = O.u_to_pixels(uo, spec.side)
     err = np.abs(u - ref).max()
     say("  max abs err px", err)
@@ -87,24 +89,27 @@ def _pair_case(spec, i, k, levels, **kw):
     return u, ref, st, sto, err
 
 
-# Stopping near-ties. A level stops after the first step whose energy decrease falls below
-# eps; where that decrease lies within rounding of eps, the FP32 path (energies a few 1e-7 to
-# 1e-6 off after tens of steps on an FP32-stored displacement) may stop one step earlier or
-# later than the FP64 oracle, and both are correct runs of the method. Such a case is re-run
-# in the oracle with the GPU's step counts replayed (the oracle's test switch), which reports
-# how far its own energy test was from each replayed decision (tie_gap): at most TIE_DE is a
-# near-tie, and the replayed run is then held to the full bar (1e-3 px, energy, pass counts).
-# A larger gap means the GPU decided differently away from a tie, and fails. Observed once: a
-# 128^2 pair whose level-6 decrease missed eps = 3e-4 by 3.2e-6 in FP64.
+# Near-ties. A level stops after the first step whose energy decrease falls below eps, and each
+# line search takes the largest ladder step with sufficient decrease. Where such a test lies
+# within rounding of its threshold, the FP32 path may decide one way and the FP64 oracle the
+# other; both are correct runs of the method, but their results then differ by far more than
+# rounding (long registrations on a flat energy are sensitive: the oracle itself moves by
+# ~0.3 px at isolated nodes when only its u is stored in FP32). The GPU logs every decision it
+# took (step counts per level and the ladder position of every accepted step); where they differ
+# from the oracle's, the oracle is re-run along the GPU's decisions (its test switch) and reports
+# how far its own tests were from each one: at most TIE_DE (energy units) for both kinds of
+# decision is a near-tie, and the replayed run is then held to the full bar. A larger gap means
+# the GPU decided differently away from a tie, and fails.
 TIE_DE = 1e-5
 
 
-def replay_gpu_decisions(R, T, op, gpu_iters, ora_iters, **kw):
-    """Re-runs the oracle pair with the GPU's step counts; returns (u, stats) of that run."""
-    uo, sto, _ = O.register(R, T, op, force=list(gpu_iters), **kw)
-    say("  STOPPING NEAR-TIE: oracle iters %s, gpu %s; replayed, tie gap %.3e (bar %.0e)"
-        % (ora_iters, gpu_iters, sto.tie_gap, TIE_DE))
-    assert sto.tie_gap <= TIE_DE, "decisions differ away from a stopping near-tie"
+def replay_gpu_decisions(R, T, op, gpu_stats, rungs):
+    """Re-runs the oracle pair along the GPU's decisions; returns (u, stats) of that run."""
+    uo, sto, _ = O.register(R, T, op, force=list(gpu_stats.iters), rungs=rungs)
+    say("  NEAR-TIE: replayed the GPU's decisions (iters %s); stop gap %.3e, Armijo gap %.3e "
+        "(bar %.0e)" % (gpu_stats.iters, sto.tie_gap, sto.armijo_gap, TIE_DE))
+    assert sto.tie_gap <= TIE_DE and sto.armijo_gap <= TIE_DE, \
+        "decisions differ away from a near-tie"
     return uo, sto
 
 
@@ -169,35 +174,36 @@ def test_identical_frames_give_identity():
 
 
 def _series_case(spec, levels, scan, threads=0):
-    """GPU series against the oracle series on the same frames. Every application (the N-1
-    neighbour registrations, then the B applications in schedule order) must take the oracle's
-    step and pass counts on every level; where some differ, the oracle series is re-run with the
-    GPU's counts replayed and each replayed decision must be a stopping near-tie (TIE_DE)."""
+    """GPU series against the oracle series on the same frames, compared along the GPU's
+    decisions: every application (the N-1 neighbour registrations, then the B applications in
+    schedule order) logs its step counts and line-search choices, the oracle series replays them
+    and each replayed decision must be its own test's or a near-tie (TIE_DE)."""
     torch = _torch()
     import paper_1712_02533_amd as P
     s = make_series(spec)
+    M = spec.n_frames - 1
+    n_b = P.scan_program(scan, M)[3] if M > 0 else 0
     say("series", spec, "levels", levels, scan)
-    u, st, ops = P.prefix_register_series(torch.tensor(s.frames, device="cuda"),
-                                          params=_gpu_params(levels, scan=scan),
-                                          want_op_stats=True)
+    with P.DecisionLog(M + n_b) as log:
+        u, st, ops = P.prefix_register_series(torch.tensor(s.frames, device="cuda"),
+                                              params=_gpu_params(levels, scan=scan),
+                                              want_op_stats=True)
     u = u.cpu().numpy()
+    assert len(ops) == M + n_b
+    force = [o.iters for o in ops]
+    rungs = [log.rungs(k, sum(o.iters)) for k, o in enumerate(ops)]
     fr = np.stack([O.frame_to_nodes(f) for f in s.frames])
     op = _oracle_params(levels)
-    uo, a, b, pairs = O.series(fr, op, scan=scan, threads=threads)
+    uo, a, b, pairs = O.series(fr, op, scan=scan, threads=threads, force_a=force[:M],
+                               force_b=force[M:], rungs_a=rungs[:M], rungs_b=rungs[M:])
     ora = list(a) + list(b)
-    assert len(ops) == len(ora)
-    differ = [k for k in range(len(ora)) if ops[k].iters != ora[k].iters]
-    if differ:
-        M = spec.n_frames - 1
-        say("  STOPPING NEAR-TIE candidates (op: oracle / gpu iters):",
-            [(k, ora[k].iters, ops[k].iters) for k in differ])
-        uo, a, b, pairs = O.series(fr, op, scan=scan, threads=threads,
-                                   force_a=[ops[k].iters for k in range(M)],
-                                   force_b=[ops[k].iters for k in range(M, len(ops))])
-        ora = list(a) + list(b)
-        gaps = [o.tie_gap for o in ora]
-        say("  replayed; largest tie gap %.3e (bar %.0e)" % (max(gaps), TIE_DE))
-        assert max(gaps) <= TIE_DE, "decisions differ away from a stopping near-tie"
+    assert len(ora) == len(ops)
+    ties = [(k, o.tie_gap, o.armijo_gap) for k, o in enumerate(ora)
+            if o.tie_gap > 0 or o.armijo_gap > 0]
+    say("  %d of %d applications took a decision the oracle's own test would have taken the "
+        "other way:" % (len(ties), len(ora)), ["op %d: stop %.1e, Armijo %.1e" % t for t in ties])
+    assert all(t[1] <= TIE_DE and t[2] <= TIE_DE for t in ties), \
+        "decisions differ away from a near-tie"
     assert all(g.iters == o.iters and g.passes == o.trials for g, o in zip(ops, ora))
     ref = np.stack([O.u_to_pixels(x, spec.side) for x in uo])
     err = np.abs(u - ref).max()
@@ -225,16 +231,107 @@ def test_series_c1_sequential_matches_oracle():
     assert err < TOL_PX
 
 
-@pytest.mark.parametrize("scan", ["brent_kung", "kogge_stone", "sklansky", "general"])
+@pytest.mark.parametrize("scan", ["brent_kung", "kogge_stone", "sklansky", "general",
+                                  "blelloch", "reduce_then_scan"])
 def test_series_parallel_scans_match_oracle(scan):
     u, ref, err = _series_case(SeriesSpec(12, 128, 4.0, 1.0, 10.0, 1), 3, scan)
-    if scan != "general":
+    if scan not in ("general", "reduce_then_scan"):
         assert err < TOL_PX
         return
     # the general strategy's last B applications register frames up to 10 apart from a
-    # composed start (103 steps on one level here): a long registration, held to the full-size
-    # bar (measured: 6.4e-3 px max at 26 nodes of one frame, 2.1e-5 px RMS)
+    # composed start (103 steps on one level here), and the alternative strategy's chunk totals
+    # and rescans register frames several apart too: long registrations, held to the full-size
+    # bar (measured for the general strategy: 6.4e-3 px max at 26 nodes of one frame, 2.1e-5 px
+    # RMS)
     _full_size_bar(u, ref)
+
+
+def test_series_512_short_chain_matches_oracle():
+    """The timed workload's statistics (512^2 frames, drift 8 px, non-rigid 1.5 px, 5 counts,
+    4 levels, Brent-Kung) on 4 frames: 3 neighbour registrations and 2 B applications whose
+    starts the pool composes at 513^2 and restricts to the coarsest level, compared node by node
+    along the GPU's decisions at the full-size bar."""
+    u, ref, err = _series_case(SeriesSpec(4, 512, 8.0, 1.5, 5.0, 2), 4, "brent_kung")
+    assert np.all(u[0] == 0)
+    _full_size_bar(u, ref)
+
+
+def _long_series_case(spec, levels, scan):
+    """Long series at the benchmark's statistics. Their long registrations are chaotic in finite
+    precision: along one and the same decision sequence the FP64 oracle with only u stored in
+    FP32 ends up to ~0.7 px (RMS ~0.03 px) away from itself at isolated nodes of some frames
+    (a near-tie of a stop or an Armijo test, or a cell edge crossed on the other side, is
+    amplified along a flat energy), so no FP32 implementation can follow the FP64 oracle node by
+    node there, and now and then a chained B application settles in another local minimum (the
+    approximate associativity of the section on it: both are results of the method). Such a
+    series is held to what holds whatever the rounding: the mean accuracy against the analytic
+    displacement over the frames equals the oracle's within 0.02 px, at least 80% of the frames
+    do so each, and the median over frames of the field difference stays within 0.05 px RMS
+    (the tolerance of approximate associativity). The FP32-storage oracle's own spread is
+    printed beside the GPU's."""
+    torch = _torch()
+    import paper_1712_02533_amd as P
+    s = make_series(spec)
+    say("long series", spec, "levels", levels, scan)
+    u, st, ops = P.prefix_register_series(torch.tensor(s.frames, device="cuda"),
+                                          params=_gpu_params(levels, scan=scan),
+                                          want_op_stats=True)
+    u = u.cpu().numpy()
+    fr = np.stack([O.frame_to_nodes(f) for f in s.frames])
+    op = _oracle_params(levels)
+    u64, a, b, _ = O.series(fr, op, scan=scan)
+    O.set_u_storage_f32(True)
+    try:
+        u32, a32, b32, _ = O.series(fr, op, scan=scan)
+    finally:
+        O.set_u_storage_f32(False)
+    px = lambda x: np.stack([O.u_to_pixels(v, spec.side) for v in x])
+    ref, r32 = px(u64), px(u32)
+    ora, ora32 = list(a) + list(b), list(a32) + list(b32)
+    same = sum(g.iters == o.iters for g, o in zip(ops, ora))
+    same32 = sum(o.iters == q.iters for o, q in zip(ora, ora32))
+    say("  step counts as the FP64 oracle's: GPU %d of %d applications, FP32-storage oracle %d"
+        % (same, len(ora), same32))
+    rms = lambda d: float(np.sqrt((d ** 2).mean()))
+    acc_gpu, acc_ora, field = [], [], []
+    for k in range(1, spec.n_frames):
+        gt = ground_truth(s, k)
+        b = int(np.abs(gt).max() + 6)
+        if 2 * b >= spec.side - 16:
+            continue
+        t_gpu = rms((u[k] - gt)[:, b:-b, b:-b])
+        t_ora = rms((ref[k] - gt)[:, b:-b, b:-b])
+        t_32 = rms((r32[k] - gt)[:, b:-b, b:-b])
+        say("  frame %2d: vs truth GPU %.4f oracle %.4f (FP32-storage oracle %.4f) px; GPU - "
+            "oracle rms %.1e max %.1e (FP32-storage oracle %.1e / %.1e)"
+            % (k, t_gpu, t_ora, t_32, rms(u[k] - ref[k]), np.abs(u[k] - ref[k]).max(),
+               rms(r32[k] - ref[k]), np.abs(r32[k] - ref[k]).max()))
+        acc_gpu.append(t_gpu)
+        acc_ora.append(t_ora)
+        field.append(rms(u[k] - ref[k]))
+    acc_gpu, acc_ora = np.array(acc_gpu), np.array(acc_ora)
+    close = float(np.mean(np.abs(acc_gpu - acc_ora) <= 0.02))
+    say("  mean accuracy against the truth: GPU %.4f, oracle %.4f px; %.0f%% of frames within "
+        "0.02 px; median field RMS %.2e px (FP32-storage oracle, whole series %.2e)"
+        % (acc_gpu.mean(), acc_ora.mean(), 100 * close, np.median(field),
+           rms(r32[1:] - ref[1:])))
+    assert np.all(u[0] == 0)
+    assert len(acc_gpu) >= 4
+    assert abs(acc_gpu.mean() - acc_ora.mean()) <= 0.02
+    assert close >= 0.8
+    assert np.median(field) <= 0.05
+
+
+def test_series_256_brent_kung_long_matches_oracle_statistics():
+    """The 256^2 configuration's statistics (drift 4 px, non-rigid 1 px, 10 counts, 3 levels,
+    Brent-Kung) on 16 frames: 15 neighbour registrations and 22 B applications on 257^2 grids."""
+    _long_series_case(SeriesSpec(16, 256, 4.0, 1.0, 10.0, 1), 3, "brent_kung")
+
+
+def test_series_512_brent_kung_long_matches_oracle_statistics():
+    """The timed workload's statistics on 12 frames: 11 neighbour registrations and 15 B
+    applications on 513^2 grids."""
+    _long_series_case(SeriesSpec(12, 512, 8.0, 1.5, 5.0, 2), 4, "brent_kung")
 
 
 def test_invalid_inputs_raise():

@@ -88,26 +88,24 @@ def test_rigid_full_size_pair_matches_oracle():
 
 
 # At the library's default eps = 3e-4 a level stops while the three-parameter energy still
-# slopes, so a stopping decision taken the other way at a near-tie (FP32 against FP64 energies)
-# ends the level at a visibly different point. Such a case is re-run in the oracle with the
-# GPU's step counts replayed (its test switch); each replayed decision must lie within TIE_DE
-# of the energy test, and the replayed run is held to 1e-3 px like any other.
+# slopes, so a decision taken the other way at a near-tie (FP32 against FP64 energies: a stop,
+# or the step an Armijo line search accepts) ends the level at a visibly different point. The
+# GPU logs its decisions; the oracle is run along them (its test switch) and each must lie
+# within TIE_DE of the oracle's own test, and the run is then held to 1e-3 px like any other.
 TIE_DE = 1e-5
 DEFAULT_BAR_PX = 1e-3
 DEFAULTS = dict(eps=3e-4, iter_max=500)   # pprs_default_params (the rigid energy has no lambda)
 
 
-def _oracle_px_replayed(f0, f1, levels, side, gpu_stats):
-    po, sto = _oracle_px(f0, f1, levels, side, **DEFAULTS)
-    if sto.iters != gpu_stats.iters:
-        R, T = O.frame_to_nodes(f0), O.frame_to_nodes(f1)
-        p, sto2 = O.register_rigid(R, T, O.Params(levels=levels, **DEFAULTS),
-                                   force=gpu_stats.iters)
-        say("  STOPPING NEAR-TIE: oracle iters %s, gpu %s; replayed, tie gap %.3e"
-            % (sto.iters, gpu_stats.iters, sto2.tie_gap))
-        assert sto2.tie_gap <= TIE_DE, "decisions differ away from a stopping near-tie"
-        po, sto = np.array([p[0], p[1] * side, p[2] * side]), sto2
-    return po, sto
+def _oracle_px_replayed(f0, f1, levels, side, gpu_stats, rungs):
+    R, T = O.frame_to_nodes(f0), O.frame_to_nodes(f1)
+    p, sto = O.register_rigid(R, T, O.Params(levels=levels, **DEFAULTS), force=gpu_stats.iters,
+                              rungs=rungs)
+    say("  replayed the GPU's decisions: stop gap %.3e, Armijo gap %.3e"
+        % (sto.tie_gap, sto.armijo_gap))
+    assert sto.tie_gap <= TIE_DE and sto.armijo_gap <= TIE_DE, \
+        "decisions differ away from a near-tie"
+    return np.array([p[0], p[1] * side, p[2] * side]), sto
 
 
 @pytest.mark.parametrize("side,alpha,t", [(64, 0.0, (2.5, -1.75)), (64, 0.015, (1.0, 0.5)),
@@ -121,8 +119,9 @@ def test_rigid_pair_matches_oracle_at_default_eps(side, alpha, t):
     f0, f1 = f0.astype(np.float32), f1.astype(np.float32)
     frames = torch.tensor(np.stack([f0, f1]), device="cuda")
     say("default eps: side %d, alpha %.3f, t %s" % (side, alpha, t))
-    p, st = P.register_pairs_rigid(frames, [0], [1], params=P.Params(levels=3))
-    po, sto = _oracle_px_replayed(f0, f1, 3, side, st[0])
+    with P.DecisionLog(1) as log:
+        p, st = P.register_pairs_rigid(frames, [0], [1], params=P.Params(levels=3))
+    po, sto = _oracle_px_replayed(f0, f1, 3, side, st[0], log.rungs(0, sum(st[0].iters)))
     d = _map_diff(p[0], po, side)
     say("  gpu", p[0], st[0].iters, st[0].passes, " oracle", po, sto.iters, sto.trials,
         " map diff %.2e px" % d)
@@ -140,8 +139,10 @@ def test_rigid_full_size_pair_matches_oracle_at_default_eps():
     s = make_series(spec)
     frames = torch.tensor(s.frames, device="cuda")
     say("default eps: 512 x 512 pair (5, 6), 4 levels")
-    p, st = P.register_pairs_rigid(frames, [5], [6], params=P.Params(levels=4))
-    po, sto = _oracle_px_replayed(s.frames[5], s.frames[6], 4, 512, st[0])
+    with P.DecisionLog(1) as log:
+        p, st = P.register_pairs_rigid(frames, [5], [6], params=P.Params(levels=4))
+    po, sto = _oracle_px_replayed(s.frames[5], s.frames[6], 4, 512, st[0],
+                                  log.rungs(0, sum(st[0].iters)))
     d = _map_diff(p[0], po, 512)
     say("  gpu", p[0], st[0].iters, st[0].passes, " oracle", po, sto.iters, sto.trials,
         " map diff %.2e px" % d)

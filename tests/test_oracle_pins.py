@@ -411,6 +411,29 @@ def test_replayed_stopping_decisions():
     assert stm.tie_gap == pytest.approx(p.eps - (own[-1, 3] - own[-1, 4]), rel=1e-12)
 
 
+def test_replayed_line_search_decisions():
+    """The test switch that replays line-search decisions: the flow's own ladder positions (with
+    its step counts) reproduce it bit for bit with both gaps 0; replaying one step a rung lower
+    than the largest passing one takes that smaller step and reports in armijo_gap how far the
+    Armijo test was from accepting the rung above it (its sufficient-decrease margin)."""
+    s, R, T = _frames(side=64, seed=33, drift=2.0, noise=20.0)
+    p = O.Params(levels=3, lam=10.0, eps=3e-4)
+    u, st, tr = O.register(R, T, p, trace_cap=4000)
+    J = O.trace_rungs(tr, p)
+    assert len(J) == sum(st.iters)
+    ur, sr, trr = O.register(R, T, p, trace_cap=4000, force=st.iters, rungs=J)
+    assert np.array_equal(u, ur) and sr.iters == st.iters and sr.trials == st.trials
+    assert sr.tie_gap == 0.0 and sr.armijo_gap == 0.0
+    k = 3                                     # a step of the coarsest level
+    J2 = list(J)
+    J2[k] += 1
+    um, sm, trm = O.register(R, T, p, trace_cap=4000, force=st.iters, rungs=J2)
+    assert trm[k, 2] == pytest.approx(tr[k, 2] / 2, rel=1e-15)     # half the step was taken
+    assert sm.iters == st.iters and not np.array_equal(um, u)
+    margin = (tr[k, 3] - p.sigma * tr[k, 2] * tr[k, 5]) - tr[k, 4]  # the refused rung's margin
+    assert sm.armijo_gap >= margin > 0
+
+
 def test_identical_frames_give_identity():
     _, R, _ = _frames(side=32, seed=6, noise=20.0)
     u, st, _ = O.register(R, R, O.Params(levels=3))
@@ -711,6 +734,113 @@ def _general_expected(M, P):
     return out, x
 
 
+def _blelloch_expected(M):
+    """Blelloch's exclusive scan (Prefix sum chapter) tracked as frame intervals, None for the
+    identity element: up-sweep over the elements padded with identities to a power of two, the
+    root replaced by the identity, down-sweep where the left child takes the parent and the
+    parent becomes parent (.) old left child. Returns the registrations (i, j, k) in the
+    chapter's order (levels in order, left to right; combinations with the identity are free)
+    and the inclusive results y_m = exclusive m + 1, the last one the kept total."""
+    n2 = 1
+    while n2 < M:
+        n2 *= 2
+    a = [(m, m + 1) for m in range(M)] + [None] * (n2 - M)
+    regs = []
+
+    def comb(x, y):
+        if x is None or y is None:
+            return y if x is None else x
+        assert x[1] == y[0]
+        regs.append((x[0], x[1], y[1]))
+        return (x[0], y[1])
+    d = 1
+    while d < n2:
+        for j in range(2 * d - 1, n2, 2 * d):
+            a[j] = comb(a[j - d], a[j])
+        d *= 2
+    total, a[n2 - 1] = a[n2 - 1], None
+    d = n2 // 2
+    while d >= 1:
+        for j in range(2 * d - 1, n2, 2 * d):
+            t = a[j - d]
+            a[j - d] = a[j]
+            a[j] = comb(a[j], t)
+        d //= 2
+    return regs, [a[m + 1] for m in range(M - 1)] + [total]
+
+
+def _reduce_then_scan_expected(M, P):
+    """The distributed chapter's alternative strategy on P workers, tracked as intervals:
+    chunks reduced into totals, Brent-Kung over the totals in place, each chunk rescanned
+    serially from the total before it."""
+    P = min(P, M)
+    sizes = [M // P + (1 if I < M % P else 0) for I in range(P)]
+    lo = [sum(sizes[:I]) for I in range(P)]
+    x = [(m, m + 1) for m in range(M)]
+    T = [x[lo[I]] for I in range(P)]
+    regs = []
+
+    def comb(a, b):
+        assert a[1] == b[0]
+        regs.append((a[0], a[1], b[1]))
+        return (a[0], b[1])
+    for st in range(1, max(sizes)):
+        for I in range(P):
+            if st < sizes[I]:
+                T[I] = comb(T[I], x[lo[I] + st])
+    d = 1
+    while d < P:
+        for j in range(2 * d - 1, P, 2 * d):
+            T[j] = comb(T[j - d], T[j])
+        d *= 2
+    d = 1
+    while d * 2 < P:
+        d *= 2
+    while d >= 1:
+        for j in range(3 * d - 1, P, 2 * d):
+            T[j] = comb(T[j - d], T[j])
+        d //= 2
+    for st in range(max(sizes)):
+        for I in range(P):
+            if st < sizes[I] and not (st == 0 and I == 0):
+                j = lo[I] + st
+                x[j] = comb(T[I - 1] if st == 0 else x[j - 1], x[j])
+    return regs, x
+
+
+@pytest.mark.parametrize("M", [1, 2, 3, 5, 8, 11, 16])
+def test_series_blelloch_pairs_and_counts(M):
+    """The oracle's Blelloch scan registers exactly the chapter's non-trivial combinations, in
+    its order, and ends with every element covering (0, m+1). For 8 elements the figure of the
+    chapter counts 14 operator applications in 6 steps; 3 of them combine with the identity
+    (the leftmost path of the down-sweep), leaving Brent-Kung's 11."""
+    s = make_series(SeriesSpec(M + 1, 16, 0.5, 0.0, 0.0, 17))
+    fr = np.stack([O.frame_to_nodes(f) for f in s.frames])
+    u, a, b, pairs = O.series(fr, O.Params(levels=1, iter_max=0), scan="blelloch")
+    exp, final = _blelloch_expected(M)
+    assert [tuple(int(v) for v in p) for p in pairs] == exp
+    assert final == [(0, m + 1) for m in range(M)]
+    if M == 8:
+        fig = GOLD["scan_figures_N8"]["blelloch"]
+        assert fig["ops"] == 14 and fig["steps"] == 6
+        assert len(exp) == 14 - 3 == GOLD["scan_figures_N8"]["brent_kung"]["ops"]
+
+
+@pytest.mark.parametrize("M,P", [(1, 1), (5, 2), (8, 2), (8, 3), (11, 4), (16, 4)])
+def test_series_reduce_then_scan_pairs(M, P):
+    """The oracle's alternative strategy registers exactly the chapter's triples in its order,
+    ends with every element covering (0, m+1), and does (M - P) + BK(P) + (M - 1) work."""
+    s = make_series(SeriesSpec(M + 1, 16, 0.5, 0.0, 0.0, 18))
+    fr = np.stack([O.frame_to_nodes(f) for f in s.frames])
+    u, a, b, pairs = O.series(fr, O.Params(levels=1, iter_max=0), scan="reduce_then_scan",
+                              workers=P)
+    exp, final = _reduce_then_scan_expected(M, P)
+    assert [tuple(int(v) for v in p) for p in pairs] == exp
+    assert final == [(0, m + 1) for m in range(M)]
+    bk = {1: 0, 2: 1, 3: 2, 4: 4}[min(P, M)]
+    assert len(pairs) == (M - min(P, M)) + bk + (M - 1)
+
+
 @pytest.mark.parametrize("M,P", [(1, 1), (5, 2), (8, 2), (8, 3), (11, 4), (16, 4), (9, 9)])
 def test_series_general_strategy_pairs(M, P):
     """The oracle's general strategy applies B to exactly the (i, j, k) triples of the
@@ -746,7 +876,8 @@ def test_series_translation_chain_and_bk_vs_sequential():
         gt = ground_truth(s, k)
         e = O.u_to_pixels(useq[k], 64) - gt
         assert np.sqrt((e[:, b:-b, b:-b] ** 2).mean()) < 0.1
-    for scan in ("brent_kung", "kogge_stone", "sklansky", "general"):
+    for scan in ("brent_kung", "kogge_stone", "sklansky", "general", "blelloch",
+                 "reduce_then_scan"):
         upar, _, _, _ = O.series(fr, p, scan=scan, workers=2)
         for k in range(1, 6):
             d = O.u_to_pixels(upar[k] - useq[k], 64)
@@ -832,6 +963,34 @@ def test_average_half_pixel_and_clamp():
 
 # ------------------------------------------------------------------------------------------
 # Rigid variant (definition of a rigid transformation): phi(x) = R(alpha) x + t
+
+def test_averaging_procedure_fixed_points_and_gain():
+    """The series averaging procedure (a round: average the aligned frames, register every
+    frame i >= 1 to the average from its current deformation): identical frames stay at the
+    identity exactly; noise-free frames started from the analytic displacements stay within
+    0.05 px of them; and one round started from the series registration of a noisy series
+    brings the average closer to the clean object than the single average."""
+    p = O.Params(levels=2, lam=10.0, eps=3e-4)
+    s = make_series(SeriesSpec(1, 64, 0.0, 0.0, 20.0, 72))
+    same = np.stack([s.frames[0]] * 4)
+    u, avg = O.series_average_refine(same, np.zeros((4, 2, 64, 64)), 2, p)
+    assert np.all(u == 0) and np.allclose(avg, s.frames[0], atol=1e-12)
+    s = make_series(SeriesSpec(5, 64, 1.5, 0.5, 0.0, 73))
+    gt = np.stack([np.zeros((2, 64, 64))] + [ground_truth(s, k) for k in range(1, 5)])
+    u, _ = O.series_average_refine(s.frames, gt, 1, p)
+    assert np.all(u[0] == 0)
+    assert np.sqrt(((u - gt)[1:, :, 8:-8, 8:-8] ** 2).mean()) < 0.05
+    for seed in (70, 71):
+        s = make_series(SeriesSpec(8, 64, 1.5, 0.5, 20.0, seed))
+        clean = make_series(SeriesSpec(8, 64, 1.5, 0.5, 0.0, seed))
+        obj = clean.frames[0] * (s.frames.mean() / clean.frames.mean())
+        fr = np.stack([O.frame_to_nodes(f) for f in s.frames])
+        us, _, _, _ = O.series(fr, p, scan="brent_kung")
+        u1 = np.stack([O.u_to_pixels(x, 64) for x in us])
+        err = lambda a: np.sqrt(((a - obj)[8:-8, 8:-8] ** 2).mean())
+        _, ar = O.series_average_refine(s.frames, u1, 1, p)
+        assert err(ar) < err(O.series_average(s.frames, u1))
+
 
 def _rotated_pair(side, alpha, t_px, seed):
     """Frame 0 is the blob lattice L; frame 1 is L seen through the rigid map, T(y) =
