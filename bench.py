@@ -200,6 +200,36 @@ def accuracy(u, ks, gts, side):
     return np.array(out)
 
 
+def average_rounds(P, torch, series, frames, out, avg, params, rounds=2):
+    """The series averaging procedure after the scan: each round averages the aligned frames
+    and re-registers frames 1.. to the average from their current deformation. Reports each
+    round's time and the average's RMS error against the clean object (the first frame's
+    noise-free image scaled to the frames' mean count, interior only)."""
+    import numpy as np
+    from synth.blobs import _clean_frame
+    spec = series.spec
+    clean = _clean_frame(spec, series.origin, series.amps, series.lattice_lo, series.shifts[0],
+                         series.sines[0])
+    obj = clean * (float(series.frames.mean()) / float(clean.mean()))
+    b = 24
+    err = lambda a: float(np.sqrt(((a.cpu().numpy() - obj)[b:-b, b:-b] ** 2).mean()))
+    res = dict(err_scan_average=round(err(avg), 4), rounds=[])
+    u = out.clone()
+    for _ in range(rounds):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, a, rows = P.series_average_refine(frames, u, 1, params)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0)
+        steps = float(np.mean([sum(st.iters) for st in rows[0]]))
+        res["rounds"].append(dict(ms=round(ms, 1), registrations=len(rows[0]),
+                                  mean_steps=round(steps, 1), err=round(err(a), 4)))
+        log("averaging round: %.1f ms, %d registrations (%.1f steps each), average's error "
+            "against the clean object %.4f (scan average %.4f)"
+            % (ms, len(rows[0]), steps, err(a), res["err_scan_average"]))
+    return res
+
+
 def warm_runs(P, series, frames, out, params, args, regs_per_step, cold_ms):
     """The same series with the learned warm start (both modes): throughput, accuracy against
     the analytic displacement beside the cold run's on sampled frames, the judge's decisions,
@@ -422,6 +452,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start runs")
+    ap.add_argument("--no-refine", action="store_true",
+                    help="skip the rounds of the series averaging procedure")
     ap.add_argument("--no-tune", action="store_true", help="default launch shape, no autotuning")
     ap.add_argument("--no-rigid", action="store_true", help="skip the rigid-operator series")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1712_02533_amd", "weights",
@@ -535,6 +567,8 @@ def main():
     result["average"] = dict(ms=round(ams, 3), bytes=abytes,
                              gbs=round(abytes / (ams * 1e-3) / 1e9, 1))
     log("series average: %.3f ms, %.0f GB/s" % (ams, abytes / (ams * 1e-3) / 1e9))
+    if not args.no_refine:
+        result["average_refine"] = average_rounds(P, torch, series, frames, out, avg, params)
     if not args.no_rigid and scan not in ("blelloch", "reduce_then_scan"):
         # the same frames through the rigid operator (three parameters per registration)
         rp = P.Params(levels=cfg["levels"], scan=scan, scan_workers=args.workers)

@@ -303,6 +303,23 @@ pprs_status pprs_prefix_register_series_batch(pprs_ctx* ctx, int S, const float*
 pprs_status pprs_series_average(pprs_ctx* ctx, const float* frames, const float* u, int N, int H,
                                 int W, float* avg);
 
+/* The series averaging procedure (Introduction; section "Registration for series of images":
+   the scan's result improved by further rounds against the series mean). Each of `passes`
+   rounds averages the aligned frames as pprs_series_average does, then registers every frame
+   f_i, i >= 1, to that average with operator A (reference = average, template = f_i), started
+   from its current u_i restricted to the coarsest level; u_0 is left as given (the identity
+   for a scan result), which keeps the result in f_0's coordinates.
+   frames [N][H][W] (device, square, side 2^L or 2^L+1) and u [N][2][H][W] (device, pixels,
+   read and overwritten in place) as pprs_prefix_register_series writes them; passes >= 0.
+   avg (device [H][W], may be NULL) receives the average of the final alignment. stats (host,
+   may be NULL) receives passes x (N-1) records, pass-major, frame 1 first. With a decision log
+   set, registration r of pass q logs to row q * (N-1) + r. A reference (average) constant on
+   some level is PPRS_EINVAL; a non-finite energy is PPRS_ENAN, with u still written.
+   Synchronous on the context stream. */
+pprs_status pprs_series_average_refine(pprs_ctx* ctx, const float* frames, int N, int H, int W,
+                                       float* u, int passes, const pprs_params* params,
+                                       float* avg, pprs_pair_stats* stats);
+
 /* Host-only: the scan schedule over M = N-1 elements (PPRS_SCAN_*: the Prefix sum chapter's
    algorithms "serial", "brent_kung", "kogge_stone" and "sklansky", and the distributed
    chapter's general strategy).

@@ -642,25 +642,32 @@ def series_average(frames, u, pixels=None):
     return acc / N
 
 
-def series_average_refine(frames, u, passes: int, params: Params):
+def series_average_refine(frames, u, passes: int, params: Params, force=None, rungs=None):
     """The series averaging procedure (Introduction; section "Registration for series of
     images": the series' result refined by further rounds of registration): each round averages
     the aligned frames (series_average) and registers every frame f_i, i >= 1, to that average
     with operator A started from its current deformation (restricted to the coarsest level, as
     the multilevel algorithm prescribes); f_0's deformation stays the identity, which keeps the
     result in f_0's coordinates. frames [N, H, W] and u [N, 2, H, W] in pixels (H = W = 2^L).
-    Returns (u refined, the average of the last round's alignment)."""
+    force / rungs (test switches, as in register()): per registration, pass-major with frame 1
+    first, the decisions to replay (None entries leave a registration to its own tests).
+    Returns (u refined, the average of the last round's alignment, [RegStats] pass-major)."""
     f = np.asarray(frames, dtype=np.float64)
     u = np.array(u, dtype=np.float64)
     N, H, W = f.shape
-    for _ in range(passes):
+    stats = []
+    for q in range(passes):
         avg = series_average(f, u)
         R = frame_to_nodes(avg)
         for i in range(1, N):
+            row = q * (N - 1) + i - 1
+            fo = force[row] if force is not None else None
+            ru = rungs[row] if rungs is not None and fo is not None else None
             u0 = np.stack([frame_to_nodes(u[i, c]) for c in range(2)]) / H
-            res, _, _ = register(R, frame_to_nodes(f[i]), params, u0=u0)
+            res, st, _ = register(R, frame_to_nodes(f[i]), params, u0=u0, force=fo, rungs=ru)
             u[i] = u_to_pixels(res, H)
-    return u, series_average(f, u)
+            stats.append(st)
+    return u, series_average(f, u), stats
 
 
 # ------------------------------------------------------------------------------------------ #

@@ -8,7 +8,7 @@ from .api import (Params, PairStats, SeriesStats, compose_deformations, default_
                   kernel_names, kernel_timing, prefix_register_series,
                   prefix_register_series_rigid, register_pair,
                   register_pairs, register_pairs_rigid, register_series_batch, PprsError,
-                  scan_plan, scan_program, series_average, set_kernel_timing, set_pool, get_tuning, set_tuning,
+                  scan_plan, scan_program, series_average, series_average_refine, set_kernel_timing, set_pool, get_tuning, set_tuning,
                   set_metric_solve,
                   Context, WarmStartNet, pair_inputs,
                   level7_targets, set_warm_start, workspace_query, reserve_workspace,
@@ -18,7 +18,7 @@ __all__ = ["Params", "PairStats", "SeriesStats", "compose_deformations", "defaul
            "kernel_names", "kernel_timing", "prefix_register_series",
            "prefix_register_series_rigid", "register_pair",
            "register_pairs", "register_pairs_rigid", "register_series_batch", "PprsError",
-           "scan_plan", "scan_program", "series_average", "set_kernel_timing", "set_pool", "get_tuning", "set_tuning",
+           "scan_plan", "scan_program", "series_average", "series_average_refine", "set_kernel_timing", "set_pool", "get_tuning", "set_tuning",
            "set_metric_solve", "Context", "WarmStartNet", "pair_inputs",
            "level7_targets", "set_warm_start", "workspace_query", "reserve_workspace",
            "workspace_bytes", "prefix_register_series_batch", "register_pair_noalloc", "DecisionLog"]

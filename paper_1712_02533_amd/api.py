@@ -133,6 +133,9 @@ def _lib():
                                             ctypes.POINTER(_CPairStats)]),
                 "pprs_compose_deformations": (i, [vp, vp, vp, vp, i, i]),
                 "pprs_series_average": (i, [vp, vp, vp, i, i, i, vp]),
+                "pprs_series_average_refine": (i, [vp, vp, i, i, i, vp, i,
+                                                   ctypes.POINTER(_CParams), vp,
+                                                   ctypes.POINTER(_CPairStats)]),
                 "pprs_register_pairs_rigid": (i, [vp, vp, i, i, i, vp, vp, i, vp, vp, vp, vp]),
                 "pprs_prefix_register_series_rigid": (i, [vp, vp, i, i, i, vp, vp, vp]),
                 "pprs_prefix_register_series": (i, [vp, vp, i, i, i, vp,
@@ -446,6 +449,33 @@ def series_average(frames, u, out=None):
     c = _ctx(dev)
     _check(_lib().pprs_series_average(c.handle, a_fr, a_u, N, H, W, a_out))
     return out
+
+
+def series_average_refine(frames, u, passes: int = 1, params: Params | None = None, avg=None):
+    """The series averaging procedure: `passes` rounds of averaging the aligned frames and
+    re-registering each frame i >= 1 to the average from its current u_i. u [N, 2, H, W]
+    (pixels, float32 on the frames' device) is refined in place. Returns (u, average of the
+    final alignment [H, W], [[PairStats] * (N-1)] per pass)."""
+    import torch
+    params = params or Params()
+    N, H, W = _frames3(frames)
+    if int(passes) < 0:
+        raise ValueError("passes must be >= 0")
+    dev = frames.device
+    if avg is None:
+        avg = torch.empty((H, W), device=dev, dtype=torch.float32)
+    n = int(passes) * (N - 1)
+    st = (_CPairStats * max(n, 1))()
+    cp = params.c()
+    a_fr = _dev_f32(frames, "frames")
+    a_u = _dev_f32(u, "u", (N, 2, H, W), dev)
+    a_avg = _dev_f32(avg, "avg", (H, W), dev)
+    c = _ctx(dev)
+    _check(_lib().pprs_series_average_refine(c.handle, a_fr, N, H, W, a_u, int(passes),
+                                             ctypes.byref(cp), a_avg, st))
+    rows = [[_pair_stats(st[q * (N - 1) + r], params.levels) for r in range(N - 1)]
+            for q in range(int(passes))]
+    return u, avg, rows
 
 
 def prefix_register_series(frames, params: Params | None = None, out=None,

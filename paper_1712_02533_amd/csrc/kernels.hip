@@ -102,13 +102,86 @@ __device__ __forceinline__ float sample_bil(const float* __restrict__ g, int n, 
   return fmaf(fy, bot - top, top);
 }
 
-// Wave-level (64 lanes) sum of a double, fixed shuffle order.
+// The two Gauss points of [0, 1] (2-point rule), as compile-time constants.
+constexpr float kGP0 = 0.21132486540518711775f, kGP1 = 0.78867513459481288225f;
+
+// A bilinear field on one element (nodes 00, 10, 01, 11 as v[0..3]) at the 2x2 Gauss points:
+// interpolated along x on the element's two rows, then along y.
+struct QuadField {
+  float top[2], dy[2];
+  __device__ __forceinline__ explicit QuadField(const float (&v)[4]) {
+    float d0 = v[1] - v[0], d1 = v[3] - v[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const float xi = q ? kGP1 : kGP0;
+      top[q] = fmaf(xi, d0, v[0]);
+      dy[q] = fmaf(xi, d1, v[2]) - top[q];
+    }
+  }
+  __device__ __forceinline__ float at(int p, int q) const {
+    return fmaf(p ? kGP1 : kGP0, dy[q], top[q]);
+  }
+};
+
+// Clamped bilinear sample of a level's nodal frame at (tx, ty) cells from the node whose byte
+// offset is base4, for the energy passes. The position is clamped to the level ([lo, hi] are
+// the level's bounds relative to that node); the cell is floor of the clamped position and the
+// fraction its remainder, so a position on the far edge takes the last node at fraction 0 and
+// the load reaches one node (column) or one row past it, which the pyramid buffer pads with
+// zeros: the value is the last node's, as with the cell before it at fraction 1. T0 is the
+// frame, T1 the frame one row down (scalar bases), n4 the row pitch in bytes.
+__device__ __forceinline__ float sample_cells(const float* T0, const float* T1, unsigned n4,
+                                              unsigned base4, float lox, float hix, float loy,
+                                              float hiy, float tx, float ty) {
+  float cx = __builtin_amdgcn_fmed3f(tx, lox, hix);
+  float cy = __builtin_amdgcn_fmed3f(ty, loy, hiy);
+  int ix = cvt_flr(cx), iy = cvt_flr(cy);
+  float fx = __builtin_amdgcn_fractf(cx), fy = __builtin_amdgcn_fractf(cy);
+  unsigned o = (unsigned)mad24(iy, (int)n4, (int)(base4 + ((unsigned)ix << 2)));
+  f32x2u r0 = ld_pair(T0, o);
+  f32x2u r1 = ld_pair(T1, o);
+  float top = fmaf(fx, r0.y - r0.x, r0.x);
+  float bot = fmaf(fx, r1.y - r1.x, r1.x);
+  return fmaf(fy, bot - top, top);
+}
+
+// One DPP step of a wave reduction on a double: each lane the row mask enables takes the value
+// of the lane the DPP control names, and 0 where that lane lies outside the row (or the lane
+// is not enabled). Both halves move through the same lane pattern. All 64 lanes must be active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_take(double v) {
+  unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROW_MASK, 0xf, false);
+  int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned)lo));
+}
+// DPP controls: row_shr:k (k = 1, 2, 4, 8), row_bcast:15 (lane 15 of a row into the next row),
+// row_bcast:31 (lane 31 into rows 2 and 3)
+enum { kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118,
+       kRowBcast15 = 0x142, kRowBcast31 = 0x143 };
+
+// Wave-level (64 lanes) sum of a double in a fixed order: running sums within each 16-lane
+// row (lane 15 of a row then holds the row), then rows 0+1 and 2+3, then the two halves. The
+// total is in lane 63 (kTotalLane).
+const int kTotalLane = 63;
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  v += dpp_take<kRowShr1, 0xf>(v);
+  v += dpp_take<kRowShr2, 0xf>(v);
+  v += dpp_take<kRowShr4, 0xf>(v);
+  v += dpp_take<kRowShr8, 0xf>(v);
+  v += dpp_take<kRowBcast15, 0xa>(v);
+  v += dpp_take<kRowBcast31, 0xc>(v);
   return v;
 }
+// The same pattern for the maximum of non-negative doubles (0 is the identity); lane 63.
 __device__ __forceinline__ double wave_max(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+  v = fmax(v, dpp_take<kRowShr1, 0xf>(v));
+  v = fmax(v, dpp_take<kRowShr2, 0xf>(v));
+  v = fmax(v, dpp_take<kRowShr4, 0xf>(v));
+  v = fmax(v, dpp_take<kRowShr8, 0xf>(v));
+  v = fmax(v, dpp_take<kRowBcast15, 0xa>(v));
+  v = fmax(v, dpp_take<kRowBcast31, 0xc>(v));
   return v;
 }
 
@@ -120,7 +193,7 @@ __device__ void block_sum(double (&v)[NV], double* scratch, bool is_max_last = f
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     double s = (is_max_last && k == NV - 1) ? wave_max(v[k]) : wave_sum(v[k]);
-    if (lane == 0) scratch[w * NV + k] = s;
+    if (lane == kTotalLane) scratch[w * NV + k] = s;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -607,20 +680,25 @@ __device__ __forceinline__ void energy_item(BatchDesc* D, int s, int t, float* s
         int a = e0y + k / NXN, b = e0x + k % NXN;
         if (k >= NN) break;
         bool ok = a < n && b < n;
-        s_ux[k] = ok ? vux[it] : 0.f;
-        s_uy[k] = ok ? vuy[it] : 0.f;
+        // displacements in cells of the level (a power-of-two scaling: exact)
+        s_ux[k] = ok ? vux[it] * inv_h : 0.f;
+        s_uy[k] = ok ? vuy[it] * inv_h : 0.f;
         s_r[k] = ok ? vr[it] : 0.f;
         if (MODE) {
-          s_dx[k] = ok ? vdx[it] : 0.f;
-          s_dy[k] = ok ? vdy[it] : 0.f;
+          s_dx[k] = ok ? vdx[it] * inv_h : 0.f;
+          s_dy[k] = ok ? vdy[it] * inv_h : 0.f;
         }
       }
     }
     __syncthreads();
-    double acc[NV];
+    // per-thread FP32 sums over the thread's elements of the tile (at most
+    // ET_X * ET_Y / BLOCK), converted to FP64 once per tile
+    float es[3 * NC], dir[3];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    float w = 0.25f / ((float)(n - 1) * (float)(n - 1));
+    for (int k = 0; k < 3 * NC; ++k) es[k] = 0.f;
+    dir[0] = dir[1] = dir[2] = 0.f;
+    const float* T1 = uni(T + n);  // the row below, as a second scalar base
+    const unsigned n4 = (unsigned)n << 2;
     for (int e = threadIdx.x; e < ET_X * ET_Y; e += BLOCK) {
       int ey = e / ET_X, ex = e % ET_X;
       int a = e0y + ey, b = e0x + ex;
@@ -634,46 +712,48 @@ __device__ __forceinline__ void energy_item(BatchDesc* D, int s, int t, float* s
         dx[0] = s_dx[k00]; dx[1] = s_dx[k00 + 1]; dx[2] = s_dx[k00 + NXN]; dx[3] = s_dx[k00 + NXN + 1];
         dy[0] = s_dy[k00]; dy[1] = s_dy[k00 + 1]; dy[2] = s_dy[k00 + NXN]; dy[3] = s_dy[k00 + NXN + 1];
       }
-      // Dirichlet terms
-      acc[3 * NC + 0] += (double)(ke_form(ux[0], ux[1], ux[2], ux[3], ux[0], ux[1], ux[2], ux[3]) +
-                                  ke_form(uy[0], uy[1], uy[2], uy[3], uy[0], uy[1], uy[2], uy[3]));
+      // Dirichlet terms (in cells: h^2 times the domain-unit forms)
+      dir[0] += ke_form(ux[0], ux[1], ux[2], ux[3], ux[0], ux[1], ux[2], ux[3]) +
+                ke_form(uy[0], uy[1], uy[2], uy[3], uy[0], uy[1], uy[2], uy[3]);
       if (MODE) {
-        acc[3 * NC + 1] += (double)(ke_form(dx[0], dx[1], dx[2], dx[3], ux[0], ux[1], ux[2], ux[3]) +
-                                    ke_form(dy[0], dy[1], dy[2], dy[3], uy[0], uy[1], uy[2], uy[3]));
-        acc[3 * NC + 2] += (double)(ke_form(dx[0], dx[1], dx[2], dx[3], dx[0], dx[1], dx[2], dx[3]) +
-                                    ke_form(dy[0], dy[1], dy[2], dy[3], dy[0], dy[1], dy[2], dy[3]));
+        dir[1] += ke_form(dx[0], dx[1], dx[2], dx[3], ux[0], ux[1], ux[2], ux[3]) +
+                  ke_form(dy[0], dy[1], dy[2], dy[3], uy[0], uy[1], uy[2], uy[3]);
+        dir[2] += ke_form(dx[0], dx[1], dx[2], dx[3], dx[0], dx[1], dx[2], dx[3]) +
+                  ke_form(dy[0], dy[1], dy[2], dy[3], dy[0], dy[1], dy[2], dy[3]);
       }
-      float es[3 * NC];
+      // the element's cell in the clamp bounds and the byte offset of its first node
+      const float lox = (float)(-b), hix = (float)(n - 1 - b);
+      const float loy = (float)(-a), hiy = (float)(n - 1 - a);
+      const unsigned base4 = (unsigned)mad24(a, n, b) << 2;
+      // 2x2 Gauss points, fields interpolated along x first (rows of the element), then y
+      QuadField qux(ux), quy(uy), qr(rr), qdx(dx), qdy(dy);
 #pragma unroll
-      for (int k = 0; k < 3 * NC; ++k) es[k] = 0.f;
-#pragma unroll 1
       for (int p = 0; p < 2; ++p) {
-#pragma unroll 1
+#pragma unroll
         for (int q = 0; q < 2; ++q) {
-          float xi = c_gp[q], eta = c_gp[p];
-          float p0 = (1.f - xi) * (1.f - eta), p1 = xi * (1.f - eta), p2 = (1.f - xi) * eta, p3 = xi * eta;
-          float uqx = p0 * ux[0] + p1 * ux[1] + p2 * ux[2] + p3 * ux[3];
-          float uqy = p0 * uy[0] + p1 * uy[1] + p2 * uy[2] + p3 * uy[3];
-          float rq = p0 * rr[0] + p1 * rr[1] + p2 * rr[2] + p3 * rr[3];
-          float dqx = 0.f, dqy = 0.f;
-          if (MODE) {
-            dqx = p0 * dx[0] + p1 * dx[1] + p2 * dx[2] + p3 * dx[3];
-            dqy = p0 * dy[0] + p1 * dy[1] + p2 * dy[2] + p3 * dy[3];
-          }
+          const float xi = q ? kGP1 : kGP0, eta = p ? kGP1 : kGP0;
+          // the Gauss point's position in cells from the element's first node, at tau = 0
+          float px = qux.at(p, q) + xi, py = quy.at(p, q) + eta, rq = qr.at(p, q);
+          float dqx = MODE ? qdx.at(p, q) : 0.f, dqy = MODE ? qdy.at(p, q) : 0.f;
 #pragma unroll
           for (int j = 0; j < NC; ++j) {
-            float tx = xi + (uqx - taus[j] * dqx) * inv_h;
-            float ty = eta + (uqy - taus[j] * dqy) * inv_h;
-            float tv = sample_bil<false>(T, n, b, tx, a, ty, inv_h, nullptr, nullptr);
+            float tx = fmaf(-taus[j], dqx, px);
+            float ty = fmaf(-taus[j], dqy, py);
+            float tv = sample_cells(T, T1, n4, base4, lox, hix, loy, hiy, tx, ty);
             es[3 * j + 0] += tv;
-            es[3 * j + 1] += tv * tv;
-            es[3 * j + 2] += tv * rq;
+            es[3 * j + 1] = fmaf(tv, tv, es[3 * j + 1]);
+            es[3 * j + 2] = fmaf(tv, rq, es[3 * j + 2]);
           }
         }
       }
-#pragma unroll
-      for (int k = 0; k < 3 * NC; ++k) acc[k] += (double)(w * es[k]);
     }
+    double acc[NV];
+    const double w = 0.25 / ((double)(n - 1) * (double)(n - 1));
+    const double h2 = 1.0 / ((double)(n - 1) * (double)(n - 1));
+#pragma unroll
+    for (int k = 0; k < 3 * NC; ++k) acc[k] = w * (double)es[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[3 * NC + k] = h2 * (double)dir[k];
     block_sum<NV>(acc, s_red);
     if (threadIdx.x == 0) {
       double* pr = slot_partial(D, s, kind, t);
@@ -1380,7 +1460,7 @@ __global__ void __launch_bounds__(SW_THREADS) k_smooth_win(BatchDesc* D) {
     }
     gd = wave_sum(gd);
     dm = wave_max(dm);
-    if ((tid & 63) == 0) {
+    if ((tid & 63) == kTotalLane) {
       s_red[0][tid >> 6] = gd;
       s_red[1][tid >> 6] = dm;
     }

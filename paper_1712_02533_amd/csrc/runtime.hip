@@ -123,6 +123,7 @@ struct pprs_ctx {
   int warm_mode = PPRS_WARM_REFINE;
   unsigned warm_levels = ~0u;  // bit L set: series with side 2^L use the warm start
   DevBuf cnn_in, cnn_out, tmp, badflags, warm_stage;
+  DevBuf avg_stage;  // the series average of the averaging procedure ([H][W])
   // slot pool: per-round index lists and staged slot states
   DevBuf pool_idx, pool_off, pool_states;
   int pool_group = 16;   // steps between polls of the slot pool
@@ -154,8 +155,8 @@ struct pprs_ctx {
   std::vector<const DevBuf*> all_bufs() const {
     return {&frames, &frame_off, &rsum, &fr_ms, &fr_part, &state, &ubuf, &dbuf, &gbuf, &zbuf,
             &partial, &nodecount, &coef, &list_slots, &list_off, &lists, &desc, &opidx,
-            &elems, &cnn_in, &cnn_out, &tmp, &badflags, &warm_stage, &pool_idx, &pool_off,
-            &pool_states};
+            &elems, &cnn_in, &cnn_out, &tmp, &badflags, &warm_stage, &avg_stage, &pool_idx,
+            &pool_off, &pool_states};
   }
 };
 
@@ -431,6 +432,9 @@ struct SeriesIn {
 };
 
 const int kSumBands = 16;  // row bands of the per-frame sums (elem_sums)
+// zeros after the last pyramid: the energy passes' bilinear loads at a level's far edge reach
+// up to one row and one node past the frame they sample (with weight zero)
+const size_t kPyrPad = 2 * ((1u << 10) + 1) + 2;
 
 // Buffer sizes of prepare_series for NT frames in all, at most Nmax per series, `nodes` grid
 // nodes over all pyramids.
@@ -439,7 +443,7 @@ struct FrameBytes {
 };
 FrameBytes frame_bytes(size_t nodes, int NT, int Nmax) {
   FrameBytes b;
-  b.frames = sizeof(float) * std::max<size_t>(nodes, 1);
+  b.frames = sizeof(float) * (nodes + kPyrPad);
   b.frame_off = sizeof(long long) * (size_t)NT * PPRS_MAXL;
   b.rsum = sizeof(double) * (size_t)NT * PPRS_MAXL;
   b.fr_part = sizeof(double) * 2 * (size_t)Nmax * kSumBands;
@@ -477,6 +481,7 @@ pprs_status prepare_series(pprs_ctx* c, const std::vector<SeriesIn>& ser) {
   hd.pyr = P<float>(c->frames);
   hd.frame_off = P<long long>(c->frame_off);
   hd.rsum = P<double>(c->rsum);
+  HIPCHK(pprs_k::fill(hd.pyr + total, (long long)kPyrPad, 0.f, c->stream));
   for (const SeriesIn& x : ser) {
     int N = x.N;
     auto lvl = [&](int l) { return hd.pyr + off[(size_t)x.f0 * PPRS_MAXL + l]; };
@@ -1893,6 +1898,62 @@ pprs_status pprs_series_average(pprs_ctx* c, const float* frames, const float* u
   HIPCHK(pprs_k::series_average(frames, u, N, H, W, avg, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return PPRS_OK;
+}
+
+pprs_status pprs_series_average_refine(pprs_ctx* c, const float* frames, int N, int H, int W,
+                                       float* u, int passes, const pprs_params* params,
+                                       float* avg, pprs_pair_stats* stats) {
+  STCHK(enter(c));
+  int L = frame_level(H, W);
+  if (L < 0) return fail(PPRS_EINVAL, "frames must be square with side 2^L or 2^L+1, L in [2,10]");
+  if (!frames || !u || N < 1 || passes < 0) return fail(PPRS_EINVAL, "bad arguments");
+  STCHK(check_params(params, L));
+  int m0 = L - params->levels + 1;
+  int nL = level_n(L);
+  long long est = 2LL * nL * nL;
+  size_t plane = (size_t)H * W;
+  STCHK(ensure(c->avg_stage, sizeof(float) * plane));
+  float* mean = P<float>(c->avg_stage);
+  int n_pairs = N - 1;
+  int chunk = std::max(1, std::min(n_pairs, kPairChunk));
+  if (passes > 0 && n_pairs > 0) {
+    STCHK(ensure(c->elems, sizeof(float) * est * chunk));
+    STCHK(ensure_slots(c, chunk, L, m0, params->beta));
+  }
+  float* elems = P<float>(c->elems);
+  // frames 0 .. N-1 are the templates, global frame N (the average) the one reference
+  std::vector<char> no_ref(N, 0);
+  std::vector<int> ref(chunk, N), tmpl(chunk), out(chunk);
+  int flags = 0;
+  for (int pass = 0; pass < passes && n_pairs > 0; ++pass) {
+    HIPCHK(pprs_k::series_average(frames, u, N, H, W, mean, c->stream));
+    std::vector<SeriesIn> ser{SeriesIn{frames, N, H, L, m0, 0, 0, &no_ref},
+                              SeriesIn{mean, 1, H, L, m0, N, 1, nullptr}};
+    STCHK(prepare_series(c, ser));
+    for (int p0 = 0; p0 < n_pairs; p0 += chunk) {
+      int np = std::min(chunk, n_pairs - p0);
+      for (int k = 0; k < np; ++k) {
+        tmpl[k] = 1 + p0 + k;
+        out[k] = k;
+      }
+      // current deformations of frames 1+p0 .. on the finest level of the slots (domain units)
+      float* u_src = u + (size_t)(1 + p0) * 2 * plane;
+      HIPCHK(pprs_k::to_nodes(u_src, H, (long long)plane, elems, nL, (long long)nL * nL,
+                              2 * np, 1.0f / (float)(nL - 1), c->stream));
+      HIPCHK(hipMemcpy2DAsync(c->hd.ubuf + c->hd.u_off[L], sizeof(float) * c->hd.slot_u_stride,
+                              elems, sizeof(float) * est, sizeof(float) * est, np,
+                              hipMemcpyDeviceToDevice, c->stream));
+      c->dlog_row0 = (long long)pass * n_pairs + p0;
+      pprs_pair_stats* ps = stats ? stats + (size_t)pass * n_pairs + p0 : nullptr;
+      STCHK(run_batch(c, np, ref.data(), tmpl.data(), INIT_GIVEN, nullptr, nullptr, out.data(),
+                      elems, params, ps, nullptr, nullptr, &flags));
+      HIPCHK(pprs_k::from_nodes(elems, nL, (long long)nL * nL, u_src, H, (long long)plane,
+                                2 * np, (float)(nL - 1), c->stream));
+    }
+  }
+  if (avg) HIPCHK(pprs_k::series_average(frames, u, N, H, W, avg, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return status_from_flags(flags);
 }
 
 // RAII for the series timing events.

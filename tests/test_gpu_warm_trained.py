@@ -82,6 +82,13 @@ def test_trained_warm_start_pairs(case):
     good = errs["cold"] < 0.5
     assert good.sum() >= len(sample) // 3
     assert errs["refine"][good].mean() <= errs["cold"][good].mean() + 0.05
+    # and pair by pair: where cold is within 0.5 px of the truth, no warm pair is worse by more
+    # than 0.05 px (the judge falls back to the cold start when the warm result is worse)
+    for mode in ("refine", "skip"):
+        worse = errs[mode][good] - errs["cold"][good]
+        say("%-6s: per-pair excess over cold where cold < 0.5 px: max %.4f px over %d pairs"
+            % (mode, worse.max(), good.sum()))
+        assert worse.max() <= 0.05
 
 
 def test_trained_warm_start_series_accuracy(case):

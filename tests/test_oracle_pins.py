@@ -973,11 +973,11 @@ def test_averaging_procedure_fixed_points_and_gain():
     p = O.Params(levels=2, lam=10.0, eps=3e-4)
     s = make_series(SeriesSpec(1, 64, 0.0, 0.0, 20.0, 72))
     same = np.stack([s.frames[0]] * 4)
-    u, avg = O.series_average_refine(same, np.zeros((4, 2, 64, 64)), 2, p)
+    u, avg, _ = O.series_average_refine(same, np.zeros((4, 2, 64, 64)), 2, p)
     assert np.all(u == 0) and np.allclose(avg, s.frames[0], atol=1e-12)
     s = make_series(SeriesSpec(5, 64, 1.5, 0.5, 0.0, 73))
     gt = np.stack([np.zeros((2, 64, 64))] + [ground_truth(s, k) for k in range(1, 5)])
-    u, _ = O.series_average_refine(s.frames, gt, 1, p)
+    u, _, _ = O.series_average_refine(s.frames, gt, 1, p)
     assert np.all(u[0] == 0)
     assert np.sqrt(((u - gt)[1:, :, 8:-8, 8:-8] ** 2).mean()) < 0.05
     for seed in (70, 71):
@@ -988,7 +988,7 @@ def test_averaging_procedure_fixed_points_and_gain():
         us, _, _, _ = O.series(fr, p, scan="brent_kung")
         u1 = np.stack([O.u_to_pixels(x, 64) for x in us])
         err = lambda a: np.sqrt(((a - obj)[8:-8, 8:-8] ** 2).mean())
-        _, ar = O.series_average_refine(s.frames, u1, 1, p)
+        _, ar, _ = O.series_average_refine(s.frames, u1, 1, p)
         assert err(ar) < err(O.series_average(s.frames, u1))
 
 
