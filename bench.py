@@ -43,9 +43,10 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def traffic_from_profiles(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
-    (profiles/counters_<kernel>.md), if it was taken for the current kernel source."""
+def profile_figure(kernel, key):
+    """A per-launch figure of `kernel` (hbm_bytes_per_launch: calibrated FETCH_SIZE +
+    WRITE_SIZE; valu_insts_per_launch: SQ_INSTS_VALU) from the committed rocprofv3 counter
+    summary profiles/counters_<kernel>.md, if it was taken for the current kernel source."""
     path = os.path.join(ROOT, "profiles", "counters_%s.md" % kernel)
     if not os.path.exists(path):
         return None
@@ -54,16 +55,21 @@ def traffic_from_profiles(kernel):
         rec = {}
         for line in open(path):
             line = line.strip()
-            if ":" in line and line.split(":")[0] in ("kernel", "kernels_hip_sha256",
-                                                      "hbm_bytes_per_launch"):
+            if ":" in line and line.split(":")[0] in ("kernel", "kernels_hip_sha256", key):
                 k, v = line.split(":", 1)
                 rec[k.strip()] = v.strip()
         src = open(os.path.join(ROOT, "paper_1712_02533_amd", "csrc", "kernels.hip"), "rb").read()
         if rec.get("kernels_hip_sha256") != hashlib.sha256(src).hexdigest():
             return None
-        return float(rec["hbm_bytes_per_launch"])
+        return float(rec[key])
     except Exception:
         return None
+
+
+# VALU issue peak of MI355X without packed FP32: 256 CUs x 4 SIMDs, a wave64 instruction
+# occupying a 16-lane SIMD for 4 cycles, at 2.4 GHz (the same rate gives the 78.6 TFLOP/s of
+# non-packed FMA)
+VALU_PEAK_GINST = 256 * 4 * 2.4e9 / 4 / 1e9
 
 
 def stream_bandwidth(torch, dev, gib=2, reps=3):
@@ -103,9 +109,19 @@ def kernel_roofline(kt, stream, traffic):
     achieved = byts / (ms * 1e-3) / 1e9
     roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
                     unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=traffic_from_profiles(dom) if traffic else None, launches=launches,
-                    avg_launch_us=round(1e3 * ms / launches, 2), bytes_per_launch=byts / launches,
-                    stream_gbs=round(stream, 1), frac_of_stream=round(achieved / stream, 4))
+                    traffic=profile_figure(dom, "hbm_bytes_per_launch") if traffic else None,
+                    launches=launches, avg_launch_us=round(1e3 * ms / launches, 2),
+                    bytes_per_launch=byts / launches, stream_gbs=round(stream, 1),
+                    frac_of_stream=round(achieved / stream, 4))
+    # the issue-rate view of the same launches: the kernel's wave64 VALU instructions per
+    # launch (counted by rocprofv3 on this workload) over the live average launch time
+    insts = profile_figure(dom, "valu_insts_per_launch") if traffic else None
+    if insts:
+        ginst = insts / (ms * 1e-3 / launches) / 1e9
+        roofline["valu_issue"] = dict(achieved=round(ginst, 1), peak=VALU_PEAK_GINST,
+                                      unit="G wave64 VALU instructions/s",
+                                      frac=round(ginst / VALU_PEAK_GINST, 4),
+                                      insts_per_launch=insts)
     return roofline, kernels
 
 

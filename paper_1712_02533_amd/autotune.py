@@ -24,7 +24,6 @@ CANDIDATES = {
     "grid_energy": [8192, 16384, 4096],
     "grid_smooth": [8192, 16384, 4096],
     "pool_slots": [256, 512, 1024],
-    "grid_prolong": [1024, 2048],
 }
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pprs", "tuning.json")
 

@@ -462,37 +462,61 @@ __global__ void k_l6_bwd_data(const float* __restrict__ dY, const float* __restr
   }
 }
 
-// dW6[o][tap][c] and db6[o]: per (weight, chunk) partial sums over pixels.
-__global__ void k_l6_bwd_w_part(const float* __restrict__ dY, const bf16* __restrict__ U,
-                                int Bn, int H, int Wd, int C, int chunks,
-                                float* __restrict__ part) {
-  __shared__ float red[kBlock];
-  int widx = blockIdx.x;  // 0 .. 2*9*C + 2 - 1
-  int ch = blockIdx.y;
-  int nw = 2 * 9 * C;
-  long long total = (long long)Bn * H * Wd;
-  long long rows = (total + chunks - 1) / chunks;
-  long long p0 = ch * rows, p1 = p0 + rows < total ? p0 + rows : total;
-  float s = 0.f;
-  if (widx < nw) {
-    int o = widx / (9 * C), tap = (widx / C) % 9, c = widx % C;
-    for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-      int x = (int)(p % Wd), y = (int)((p / Wd) % H), b = (int)(p / ((long long)Wd * H));
-      int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
-      if (yy < 0 || yy >= H || xx < 0 || xx >= Wd) continue;
-      s = fmaf(dY[p * 2 + o], (float)U[(((size_t)b * H + yy) * Wd + xx) * C + c], s);
-    }
-  } else {
-    int o = widx - nw;
-    for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) s += dY[p * 2 + o];
+
+// L6 weight and bias gradients by tiles: one block per 16x16 tile of output positions of one
+// image. The tile's 18x18 halo of U (zero outside the image, C channels) and its dY are staged
+// in LDS; each thread sums, over the tile's 256 positions in order, dY(p, o) U(p + tap, c) for
+// both outputs o of its (tap, c) pairs, or dY(p, o) for the bias. Per-block partials
+// [block][2 * 9 * C + 2] (weights o-major as in the layer, then the two biases), summed over
+// blocks in block order by k_colsum_final. H and Wd are multiples of 16; C == L6C.
+constexpr int L6T = 16, L6H = L6T + 2, L6C = 66;
+__global__ void __launch_bounds__(256) k_l6_bwd_w_tile(const float* __restrict__ dY,
+                                                       const bf16* __restrict__ U, int H, int Wd,
+                                                       float* __restrict__ part) {
+  __shared__ bf16 sU[L6H * L6H * L6C];
+  __shared__ float2 sY[L6T * L6T];
+  const int tx_n = Wd / L6T, per_img = tx_n * (H / L6T);
+  const int b = blockIdx.x / per_img, tt = blockIdx.x % per_img;
+  const int y0 = (tt / tx_n) * L6T, x0 = (tt % tx_n) * L6T;
+  for (int i = threadIdx.x; i < L6H * L6H * L6C; i += blockDim.x) {
+    int c = i % L6C, pix = i / L6C;
+    int y = y0 + pix / L6H - 1, x = x0 + pix % L6H - 1;
+    bool in = y >= 0 && y < H && x >= 0 && x < Wd;
+    sU[i] = in ? U[(((size_t)b * H + y) * Wd + x) * L6C + c] : (bf16)0.f;
   }
-  red[threadIdx.x] = s;
+  for (int p = threadIdx.x; p < L6T * L6T; p += blockDim.x) {
+    size_t q = ((size_t)b * H + y0 + p / L6T) * Wd + x0 + p % L6T;
+    sY[p] = make_float2(dY[2 * q], dY[2 * q + 1]);
+  }
   __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
+  constexpr int NP = 9 * L6C;  // (tap, c) pairs
+  float* out = part + (size_t)blockIdx.x * (2 * NP + 2);
+  for (int q = threadIdx.x; q <= NP; q += blockDim.x) {
+    float a0 = 0.f, a1 = 0.f;
+    if (q < NP) {
+      const int tap = q / L6C, c = q % L6C;
+      const bf16* u0 = sU + ((tap / 3) * L6H + tap % 3) * L6C + c;
+      for (int py = 0; py < L6T; ++py) {
+        const bf16* ur = u0 + py * L6H * L6C;
+#pragma unroll
+        for (int px = 0; px < L6T; ++px) {
+          float u = (float)ur[px * L6C];
+          float2 g = sY[py * L6T + px];
+          a0 = fmaf(g.x, u, a0);
+          a1 = fmaf(g.y, u, a1);
+        }
+      }
+      out[q] = a0;
+      out[NP + q] = a1;
+    } else {
+      for (int p = 0; p < L6T * L6T; ++p) {
+        a0 += sY[p].x;
+        a1 += sY[p].y;
+      }
+      out[2 * NP] = a0;
+      out[2 * NP + 1] = a1;
+    }
   }
-  if (threadIdx.x == 0) part[(size_t)ch * gridDim.x + widx] = red[0];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -750,7 +774,8 @@ static pprs_status alloc_batch(Model& M, int B) {
   // split-K partials: weight gradients (<= 64 splits of the largest weight) or layer outputs
   long long wmax = 0;
   for (int l = 0; l < 5; ++l) wmax = std::max(wmax, (long long)M.L[l].cout * M.L[l].kp);
-  M.part_floats = (size_t)std::max(64 * wmax, 4 * (long long)(2 * 9 * 66 + 2) * 64);
+  M.part_floats = (size_t)std::max(64 * wmax, (long long)B * (128 / L6T) * (128 / L6T) *
+                                                  (2 * 9 * L6C + 2));
   CHK(hipMalloc(&M.part, sizeof(float) * M.part_floats));
   CHK(hipMalloc(&M.lpart, sizeof(double) * 1024));
   M.cap_b = B;
@@ -847,8 +872,8 @@ static pprs_status backward(Model& M, const float* target, int B, int margin, do
   // L6: dW6, db6, dU6
   const Layer& y6 = M.L[5];
   {
-    int nw = 2 * 9 * 66 + 2, chunks = 64;
-    hipLaunchKernelGGL(k_l6_bwd_w_part, dim3(nw, chunks), dim3(kBlock), 0, st, M.dy, M.u6, B, 128, 128, 66, chunks, M.part);
+    int nw = 2 * 9 * 66 + 2, chunks = B * (128 / L6T) * (128 / L6T);
+    hipLaunchKernelGGL(k_l6_bwd_w_tile, dim3(chunks), dim3(256), 0, st, M.dy, M.u6, 128, 128, M.part);
     // weights [2][9*66] then bias [2] are contiguous at woff: columns 0..nw-1 map to them
     hipLaunchKernelGGL(k_colsum_final, dim3((nw + 255) / 256), dim3(256), 0, st, M.part, nw, chunks, M.g + y6.woff);
     hipLaunchKernelGGL(k_l6_bwd_data, dim3(grid1d(P128 * 66)), dim3(kBlock), 0, st, M.dy, M.w6, B, 128, 128, 66, M.du);

@@ -5,7 +5,6 @@
 
 namespace pprs_k {
 hipError_t plan(BatchDesc* d, hipStream_t st);
-hipError_t prolong(BatchDesc* d, int grid, hipStream_t st);
 // nc: step sizes per line-search pass (1, 2, 3, 5 or 7; ladder_rungs_ok)
 bool ladder_rungs_ok(int nc);
 hipError_t energy(BatchDesc* d, int mode, int nc, int grid, hipStream_t st);

@@ -3,9 +3,9 @@
 //
 // Per-step kernels (one "step" advances every active registration by one phase):
 //   k_plan     - builds per-kind item lists from the slot phases (one workgroup)
-//   k_prolong  - bilinear prolongation of a finished level's u to the next level
+//   k_grad     - applies the accepted step and computes the gradient G; in the same launch,
+//                the bilinear prolongation of a finished level's u to the next level
 //   k_energy   - energy at a set of step sizes (line-search pass) or at the current u
-//   k_grad     - applies the accepted step and computes the gradient G
 //   k_smooth   - metric solve d = (S1^-1 (x) S1^-1) G, one direction per launch
 //   k_*_fin    - per-slot finalisers, launched after a pass: sum the pass's FP64 tile partials
 //                in tile order and advance the slot's state (the kernel boundary orders them
@@ -99,6 +99,30 @@ __device__ __forceinline__ float sample_bil(const float* __restrict__ g, int n, 
     *gx = cx != tx ? 0.f : fmaf(fy, (v11 - v10) - (v01 - v00), v01 - v00) * inv_h;
     *gy = cy != ty ? 0.f : (bot - top) * inv_h;
   }
+  return fmaf(fy, bot - top, top);
+}
+
+// Clamped bilinear sample with its gradient (domain units) for the gradient pass, at (tx, ty)
+// cells from the node whose byte offset is base4 (bounds relative to that node as in
+// sample_cells). The cell index is clamped to the last cell (ixmax, iymax relative to the
+// node), so a position on the far edge is the last cell at fraction 1 and its gradient that
+// cell's slope; across a coordinate clamped to the level the gradient is zero.
+__device__ __forceinline__ float sample_grad(const float* T0, const float* T1, unsigned n4,
+                                             unsigned base4, float lox, float hix, float loy,
+                                             float hiy, int ixmax, int iymax, float tx,
+                                             float ty, float inv_h, float* gx, float* gy) {
+  float cx = __builtin_amdgcn_fmed3f(tx, lox, hix);
+  float cy = __builtin_amdgcn_fmed3f(ty, loy, hiy);
+  int ix = min(cvt_flr(cx), ixmax), iy = min(cvt_flr(cy), iymax);
+  float fx = cx - (float)ix, fy = cy - (float)iy;
+  unsigned o = (unsigned)mad24(iy, (int)n4, (int)(base4 + ((unsigned)ix << 2)));
+  f32x2u r0 = ld_pair(T0, o);
+  f32x2u r1 = ld_pair(T1, o);
+  float d0 = r0.y - r0.x, d1 = r1.y - r1.x;
+  float top = fmaf(fx, d0, r0.x);
+  float bot = fmaf(fx, d1, r1.x);
+  *gx = cx != tx ? 0.f : fmaf(fy, d1 - d0, d0) * inv_h;
+  *gy = cy != ty ? 0.f : (bot - top) * inv_h;
   return fmaf(fy, bot - top, top);
 }
 
@@ -339,19 +363,25 @@ __device__ __forceinline__ void sum_partials(const BatchDesc* D, int s, int kind
 #define PLAN_T 1024
 #define PLAN_V (2 * WK_COUNT)
 
-// One workgroup: per kind, the compacted list of member slots and the prefix sum of their
-// item counts. Wave-level shuffle scans, then a scan over the 16 wave totals.
-__global__ void __launch_bounds__(PLAN_T) k_plan(BatchDesc* D) {
-  __shared__ int s_wtot[PLAN_T / 64][PLAN_V];
-  __shared__ int s_woff[PLAN_T / 64][PLAN_V];
-  __shared__ int s_carry[PLAN_V];
-  __shared__ int s_active[PLAN_T / 64];
+// LDS of the planning pass for a workgroup of NT threads.
+template <int NT>
+struct PlanLds {
+  int wtot[NT / 64][PLAN_V];
+  int woff[NT / 64][PLAN_V];
+  int carry[PLAN_V];
+  int active[NT / 64];
+};
+
+// One workgroup of NT threads: per kind, the compacted list of member slots and the prefix sum
+// of their item counts. Wave-level shuffle scans, then a scan over the wave totals.
+template <int NT>
+__device__ void plan_body(BatchDesc* D, PlanLds<NT>& P) {
   int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (threadIdx.x < PLAN_V) s_carry[threadIdx.x] = 0;
+  if (threadIdx.x < PLAN_V) P.carry[threadIdx.x] = 0;
   int n_slots = D->n_slots;
   int active = 0;
   __syncthreads();
-  for (int base = 0; base < n_slots; base += PLAN_T) {
+  for (int base = 0; base < n_slots; base += NT) {
     int s = base + threadIdx.x;
     int ph = PH_DONE, eff = 0;
     if (s < n_slots) {
@@ -388,22 +418,22 @@ __global__ void __launch_bounds__(PLAN_T) k_plan(BatchDesc* D) {
     }
     if (lane == 63)
 #pragma unroll
-      for (int v = 0; v < PLAN_V; ++v) s_wtot[wv][v] = inc[v];
+      for (int v = 0; v < PLAN_V; ++v) P.wtot[wv][v] = inc[v];
     __syncthreads();
     if (threadIdx.x < PLAN_V) {
-      int v = threadIdx.x, acc = s_carry[v];
-      for (int w = 0; w < PLAN_T / 64; ++w) {
-        s_woff[w][v] = acc;
-        acc += s_wtot[w][v];
+      int v = threadIdx.x, acc = P.carry[v];
+      for (int w = 0; w < NT / 64; ++w) {
+        P.woff[w][v] = acc;
+        acc += P.wtot[w][v];
       }
-      s_carry[v] = acc;
+      P.carry[v] = acc;
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < WK_COUNT; ++k) {
       if (val[2 * k]) {
-        int pos = s_woff[wv][2 * k] + inc[2 * k] - 1;
-        int off = s_woff[wv][2 * k + 1] + inc[2 * k + 1] - val[2 * k + 1];
+        int pos = P.woff[wv][2 * k] + inc[2 * k] - 1;
+        int off = P.woff[wv][2 * k + 1] + inc[2 * k + 1] - val[2 * k + 1];
         D->list_slots[(size_t)k * D->max_slots + pos] = s;
         D->list_off[(size_t)k * (D->max_slots + 1) + pos] = off;
       }
@@ -411,34 +441,35 @@ __global__ void __launch_bounds__(PLAN_T) k_plan(BatchDesc* D) {
     __syncthreads();
   }
   for (int o = 32; o > 0; o >>= 1) active += __shfl_down(active, o, 64);
-  if (lane == 0) s_active[wv] = active;
+  if (lane == 0) P.active[wv] = active;
   __syncthreads();
   if (threadIdx.x == 0) {
     int tot = 0;
-    for (int w = 0; w < PLAN_T / 64; ++w) tot += s_active[w];
+    for (int w = 0; w < NT / 64; ++w) tot += P.active[w];
     D->active = tot;
   }
   if (threadIdx.x < WK_COUNT) {
     int k = threadIdx.x;
-    int cnt = s_carry[2 * k], items = s_carry[2 * k + 1];
+    int cnt = P.carry[2 * k], items = P.carry[2 * k + 1];
     D->list_off[(size_t)k * (D->max_slots + 1) + cnt] = items;
     D->lists[k].n_slots = cnt;
     D->lists[k].total = items;
   }
 }
 
+__global__ void __launch_bounds__(PLAN_T) k_plan(BatchDesc* D) {
+  __shared__ PlanLds<PLAN_T> P;
+  plan_body<PLAN_T>(D, P);
+}
+
 // ------------------------------------------------------------------------------------------
 // Prolongation of u (level l -> l+1) with the pending step applied: u_l - tau_pend d.
 
-__global__ void __launch_bounds__(BLOCK) k_prolong(BatchDesc* D) {
-  __shared__ int s_pos;
-  ItemCursor c;
-  if (!cursor_begin(D, WK_PROLONG, c, &s_pos)) return;
-  for (; c.item < c.end; ++c.item) {
-    int s, t;
-    cursor_slot(D, WK_PROLONG, c, s, t);
+// One prolongation item: fine-level tile t of slot s.
+__device__ __forceinline__ void prolong_item(BatchDesc* D, int s, int t) {
+  {
     const SlotState& st = D->state[s];
-    if (st.phase != PH_PROLONG) continue;
+    if (st.phase != PH_PROLONG) return;
     int lc = st.level, lf = lc + 1;
     int nc = lvl_n(lc), nf = lvl_n(lf);
     const float* uc = slot_u(D, s, lc, st.ub);
@@ -470,6 +501,7 @@ __global__ void __launch_bounds__(BLOCK) k_prolong(BatchDesc* D) {
     }
   }
 }
+
 
 // Element stiffness (Q1, h-independent in 2-D), corners ordered 00, 01, 10, 11: diagonal 2/3,
 // edge pairs -1/6, opposite pairs -1/3. Its rows sum to zero, so the bilinear form is written
@@ -867,21 +899,27 @@ __global__ void __launch_bounds__(BLOCK) k_energy_step_fin(BatchDesc* D) {
 // nodes per axis: the last tile of each row and column of tiles takes the extra node (TX + 1
 // wide), so no tile is a one-node sliver.
 template <int TX, int TY>
-__global__ void __launch_bounds__(BLOCK, LB_GRAD) k_grad(BatchDesc* D) {
+struct GradLds {
+  static constexpr int NX = TX + 3, NY = TY + 3;  // staged nodes of the widest tile
+  static constexpr int EX = TX + 2, EY = TY + 2;  // elements touching the widest tile
+  float ux[NX * NY], uy[NX * NY], r[NX * NY];
+  float c[8][EX * EY];                             // per element, per corner, (x, y)
+};
+
+// One gradient item: node tile t of slot s (the LDS block is the caller's).
+template <int TX, int TY>
+__device__ __forceinline__ void grad_item(BatchDesc* D, int s, int t, GradLds<TX, TY>& L) {
   constexpr int GT_X = TX, GT_Y = TY;
   static_assert((TX & (TX - 1)) == 0 && (TY & (TY - 1)) == 0, "tile sides are powers of two");
-  constexpr int NX = GT_X + 3, NY = GT_Y + 3;       // staged nodes of the widest tile
-  constexpr int EX = GT_X + 2, EY = GT_Y + 2;       // elements touching the widest tile
-  __shared__ float s_ux[NX * NY], s_uy[NX * NY], s_r[NX * NY];
-  __shared__ float s_c[8][EX * EY];                 // per element, per corner, (x, y)
-  __shared__ int s_pos;
-  ItemCursor c;
-  if (!cursor_begin(D, WK_GRAD, c, &s_pos)) return;
-  for (; c.item < c.end; ++c.item) {
-    int s, t;
-    cursor_slot(D, WK_GRAD, c, s, t);
+  constexpr int NX = GradLds<TX, TY>::NX, NY = GradLds<TX, TY>::NY;
+  constexpr int EX = GradLds<TX, TY>::EX, EY = GradLds<TX, TY>::EY;
+  float* s_ux = L.ux;
+  float* s_uy = L.uy;
+  float* s_r = L.r;
+  auto& s_c = L.c;
+  {
     const SlotState* stp = D->state + s;
-    if (stp->phase != PH_GRAD) continue;
+    if (stp->phase != PH_GRAD) return;
     int l = stp->level;
     int n = lvl_n(l);
     size_t nn = (size_t)n * n;
@@ -893,6 +931,8 @@ __global__ void __launch_bounds__(BLOCK, LB_GRAD) k_grad(BatchDesc* D) {
     const size_t gpn = (size_t)n * gpi;
     const float* R = uni(D->pyr + D->frame_off[(size_t)stp->ref * PPRS_MAXL + l]);
     const float* T = uni(D->pyr + D->frame_off[(size_t)stp->tmpl * PPRS_MAXL + l]);
+    const float* T1 = uni(T + n);  // the row below, as a second scalar base
+    const unsigned n4 = (unsigned)n << 2;
     float tau = (float)stp->tau_pend;
     double sg = stp->sigma;
     float inv_sig = sg > 0.0 ? (float)(1.0 / sg) : 0.f;
@@ -955,18 +995,21 @@ __global__ void __launch_bounds__(BLOCK, LB_GRAD) k_grad(BatchDesc* D) {
         float ux[4] = {s_ux[k00], s_ux[k00 + 1], s_ux[k00 + NX], s_ux[k00 + NX + 1]};
         float uy[4] = {s_uy[k00], s_uy[k00 + 1], s_uy[k00 + NX], s_uy[k00 + NX + 1]};
         float rr[4] = {s_r[k00], s_r[k00 + 1], s_r[k00 + NX], s_r[k00 + NX + 1]};
+        QuadField qux(ux), quy(uy), qr(rr);
+        const unsigned base4 = (unsigned)mad24(a, n, b) << 2;
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
-            float xi = c_gp[q], eta = c_gp[p];
-            float ps[4] = {(1.f - xi) * (1.f - eta), xi * (1.f - eta), (1.f - xi) * eta, xi * eta};
-            float uqx = ps[0] * ux[0] + ps[1] * ux[1] + ps[2] * ux[2] + ps[3] * ux[3];
-            float uqy = ps[0] * uy[0] + ps[1] * uy[1] + ps[2] * uy[2] + ps[3] * uy[3];
-            float rq = ps[0] * rr[0] + ps[1] * rr[1] + ps[2] * rr[2] + ps[3] * rr[3];
+            const float xi = q ? kGP1 : kGP0, eta = p ? kGP1 : kGP0;
+            const float ps[4] = {(1.f - xi) * (1.f - eta), xi * (1.f - eta), (1.f - xi) * eta,
+                                 xi * eta};
+            float rq = qr.at(p, q);
             float gx, gy;
-            float tv = sample_bil<true>(T, n, b, xi + uqx * inv_h, a, eta + uqy * inv_h, inv_h,
-                                        &gx, &gy);
+            float tv = sample_grad(T, T1, n4, base4, (float)(-b), (float)(n - 1 - b),
+                                   (float)(-a), (float)(n - 1 - a), n - 2 - b, n - 2 - a,
+                                   fmaf(qux.at(p, q), inv_h, xi), fmaf(quy.at(p, q), inv_h, eta),
+                                   inv_h, &gx, &gy);
             float f = -w * (rq - ncc * (tv - mean) * inv_sig) * inv_sig;
             float fx = f * gx, fy = f * gy;
 #pragma unroll
@@ -1009,6 +1052,35 @@ __global__ void __launch_bounds__(BLOCK, LB_GRAD) k_grad(BatchDesc* D) {
       gst(un, nn + i, s_uy[kn]);
     }
     __syncthreads();
+  }
+}
+
+// The gradient items of a step and its prolongations (slots that finished a level: disjoint
+// from the gradient slots, and nothing here reads what they write), one item space made of
+// the two lists in that order.
+template <int TX, int TY>
+__global__ void __launch_bounds__(BLOCK, LB_GRAD) k_grad(BatchDesc* D) {
+  __shared__ GradLds<TX, TY> L;
+  __shared__ int s_pos;
+  const int ng = D->lists[WK_GRAD].total, np = D->lists[WK_PROLONG].total;
+  const int total = ng + np;
+  if (total <= 0) return;
+  int chunk = (total + gridDim.x - 1) / gridDim.x;
+  int b0 = blockIdx.x * chunk, b1 = min(b0 + chunk, total);
+  ItemCursor c;
+  if (b0 < ng && cursor_range(D, WK_GRAD, b0, min(b1, ng), c, &s_pos)) {
+    for (; c.item < c.end; ++c.item) {
+      int s, t;
+      cursor_slot(D, WK_GRAD, c, s, t);
+      grad_item<TX, TY>(D, s, t, L);
+    }
+  }
+  if (b1 > ng && cursor_range(D, WK_PROLONG, max(b0, ng) - ng, b1 - ng, c, &s_pos)) {
+    for (; c.item < c.end; ++c.item) {
+      int s, t;
+      cursor_slot(D, WK_PROLONG, c, s, t);
+      prolong_item(D, s, t);
+    }
   }
 }
 
@@ -2182,10 +2254,6 @@ static int grid_for(long long work, int cap = 8192) {
 
 hipError_t plan(BatchDesc* d, hipStream_t st) {
   hipLaunchKernelGGL(k_plan, dim3(1), dim3(PLAN_T), 0, st, d);
-  return hipGetLastError();
-}
-hipError_t prolong(BatchDesc* d, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_prolong, dim3(grid), dim3(BLOCK), 0, st, d);
   return hipGetLastError();
 }
 bool ladder_rungs_ok(int nc) { return nc == 1 || nc == 2 || nc == 3 || nc == 5 || nc == 7; }

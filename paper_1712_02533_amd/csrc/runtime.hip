@@ -585,10 +585,11 @@ long long ladder_pass_bound(const pprs_params* p, int nc) {
   return groups * G / nc + groups + 2;
 }
 
+// One step of every active slot: plan, gradient (with the prolongations of slots that
+// finished a level), metric solve, line search.
 pprs_status launch_step(pprs_ctx* c, BatchDesc* d, int nc) {
   size_t lds0 = c->lds_smooth[0], lds1 = c->lds_smooth[1];
   TIMED(TK_PLAN, pprs_k::plan(d, c->stream));
-  TIMED(TK_PROLONG, pprs_k::prolong(d, c->grid_prolong, c->stream));
   TIMED(TK_GRAD, pprs_k::grad(d, grad_variant(c->tile_grad), c->grid_grad, c->stream));
   if (c->hd.smooth_halo) {
     TIMED(TK_SMW, pprs_k::smooth_win(d, c->hd.smooth_halo, c->grid_smooth, c->stream));
@@ -2456,10 +2457,12 @@ pprs_status pprs_get_kernel_timing(pprs_ctx* c, double* ms, long long* launches,
       bytes[k] = wk_of_tk[k] < 0 || c->t_launch[k] == 0
                      ? 0.0 : kBytesPerNode[k] * c->nodes_acc[wk_of_tk[k]];
   }
-  // the field path runs the start energies inside the line-search launches: their bytes
-  // belong to that kind
+  // the field path runs the start energies inside the line-search launches and the
+  // prolongations inside the gradient launches: their bytes belong to those kinds
   if (bytes && TK_LADDER < cap && c->t_launch[TK_EVAL] == 0 && c->t_launch[TK_LADDER] > 0)
     bytes[TK_LADDER] += kBytesPerNode[TK_EVAL] * c->nodes_acc[WK_EVAL];
+  if (bytes && TK_GRAD < cap && c->t_launch[TK_PROLONG] == 0 && c->t_launch[TK_GRAD] > 0)
+    bytes[TK_GRAD] += kBytesPerNode[TK_PROLONG] * c->nodes_acc[WK_PROLONG];
   if (reset) {
     for (int k = 0; k < TK_COUNT; ++k) {
       c->t_ms[k] = 0;
