@@ -119,11 +119,13 @@ __global__ void __launch_bounds__(256) k_gemm(const bf16* __restrict__ A, int ld
 
 constexpr int CV_BM = 128, CV_BK = 64, CV_LD = CV_BK + 8;
 
-template <int BN, bool UP>
+// DGRAD: the same product for a data gradient (input dZ, weights flipped and transposed):
+// no bias or ReLU, FP32 output (`out` is then a float*).
+template <int BN, bool UP, bool DGRAD = false>
 __global__ void __launch_bounds__(256, 2) k_conv_fwd(
     const bf16* __restrict__ src0, int C0, const bf16* __restrict__ src1, int C1, int Hin,
     int stride, const bf16* __restrict__ Wt, int Kp, const float* __restrict__ bias, int Cout,
-    bf16* __restrict__ out) {
+    void* __restrict__ out_) {
   constexpr int WN = BN / 2;          // columns per wave
   constexpr int TN = WN / 16;         // 16-wide MFMA tiles per wave along n
   constexpr int B_PIECES = BN * 8 / 256;
@@ -214,19 +216,36 @@ __global__ void __launch_bounds__(256, 2) k_conv_fwd(
     if (chunk + 1 < nchunks) stash(buf ^ 1);
     __syncthreads();
   }
-  // epilogue: bias, ReLU, bf16 NHWC
+  // epilogue: bias, ReLU, bf16 NHWC (forward) or the plain FP32 sums (data gradient)
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
     int col = n0 + wn + 16 * j + (lane & 15);
-    float bv = bias[col];
+    float bv = DGRAD ? 0.f : bias[col];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         long long row = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
         float v = acc[i][j][r] + bv;
-        out[row * Cout + col] = (bf16)(v > 0.f ? v : 0.f);
+        if (DGRAD)
+          ((float*)out_)[row * Cout + col] = v;
+        else
+          ((bf16*)out_)[row * Cout + col] = (bf16)(v > 0.f ? v : 0.f);
       }
+  }
+}
+
+// Weights of a stride-1 3x3 layer for its data gradient: W'[ci][tap][co] = W[co][8 - tap][ci]
+// (the transposed convolution is the convolution with the taps flipped), BF16.
+__global__ void k_flip_weights(const bf16* __restrict__ W, int Cout, int Cin, int Kp,
+                               bf16* __restrict__ Wf) {
+  long long total = (long long)Cin * 9 * Cout;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    int co = (int)(i % Cout);
+    int tap = (int)((i / Cout) % 9);
+    int ci = (int)(i / (9LL * Cout));
+    Wf[i] = W[(size_t)co * Kp + (size_t)(8 - tap) * Cin + ci];
   }
 }
 
@@ -648,6 +667,7 @@ struct Model {
   long long n_params = 0;
   float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;  // fp32 master, Adam, grad
   bf16* wb = nullptr;                                            // bf16 copy of w
+  bf16* wflip = nullptr;  // flipped, transposed weights of a decoder layer (its data gradient)
   long long step = 0;
   int cap_b = 0;
   // activations and workspaces (sized for cap_b)
@@ -740,15 +760,16 @@ static pprs_status alloc_batch(Model& M, int B) {
   if (B <= M.cap_b) return PPRS_OK;
   void* ptrs[] = {M.x0, M.a[0], M.a[1], M.a[2], M.a[3], M.a[4], M.u4, M.u5, M.u6, M.col, M.dzb,
                   M.z, M.y, M.dy, M.dcol, M.du, M.da[0], M.da[1], M.da[2], M.da[3], M.da[4],
-                  M.part, M.lpart};
+                  M.part, M.lpart, M.wflip};
   for (void* p : ptrs)
     if (p) CHK(hipFree(p));
   long long P128 = (long long)B * 128 * 128, P64 = P128 / 4, P32 = P128 / 16, P16 = P128 / 64;
-  long long col_max = 0, z_max = 0;
+  long long col_max = 0, z_max = 0, dcol_max = 0;
   for (int l = 0; l < 5; ++l) {
     long long pix = (long long)B * M.L[l].hout * M.L[l].hout;
     col_max = std::max(col_max, pix * M.L[l].kp);
     z_max = std::max(z_max, pix * (long long)M.L[l].cout);
+    if (l == 1 || l == 2) dcol_max = std::max(dcol_max, pix * M.L[l].kp);  // via col2im
   }
   CHK(hipMalloc(&M.x0, sizeof(bf16) * P128 * 2));
   CHK(hipMalloc(&M.a[0], sizeof(bf16) * P64 * 64));
@@ -759,12 +780,15 @@ static pprs_status alloc_batch(Model& M, int B) {
   CHK(hipMalloc(&M.u4, sizeof(bf16) * P32 * 384));
   CHK(hipMalloc(&M.u5, sizeof(bf16) * P64 * 192));
   CHK(hipMalloc(&M.u6, sizeof(bf16) * P128 * 66));
+  long long wf = 0;
+  for (int l = 3; l < 5; ++l) wf = std::max(wf, (long long)M.L[l].cin * 9 * M.L[l].cout);
+  CHK(hipMalloc(&M.wflip, sizeof(bf16) * wf));
   CHK(hipMalloc(&M.col, sizeof(bf16) * col_max));
   CHK(hipMalloc(&M.dzb, sizeof(bf16) * z_max));
   CHK(hipMalloc(&M.z, sizeof(float) * z_max));
   CHK(hipMalloc(&M.y, sizeof(float) * P128 * 2));
   CHK(hipMalloc(&M.dy, sizeof(float) * P128 * 2));
-  CHK(hipMalloc(&M.dcol, sizeof(float) * col_max));
+  CHK(hipMalloc(&M.dcol, sizeof(float) * dcol_max));
   CHK(hipMalloc(&M.du, sizeof(float) * P128 * 66));
   CHK(hipMalloc(&M.da[0], sizeof(float) * P64 * 64));
   CHK(hipMalloc(&M.da[1], sizeof(float) * P32 * 128));
@@ -899,18 +923,29 @@ static pprs_status backward(Model& M, const float* target, int B, int margin, do
     pprs_status s = gemm(M, true, true, M.dzb, y.cout, M.col, y.kp, M.g + y.woff, y.kp, y.cout, y.kp, (int)pix, splits);
     if (s != PPRS_OK) return s;
     if (l == 0) break;
+    if (l == 4 || l == 3) {
+      // data gradient of the stride-1 decoder layers as a convolution of dZ with the flipped,
+      // transposed weights (implicit GEMM, no materialised columns): dU [pix][cin] FP32
+      hipLaunchKernelGGL(k_flip_weights, dim3(grid1d((long long)y.cin * 9 * y.cout)), dim3(kBlock), 0, st, M.wb + y.woff, y.cout, y.cin, y.kp, M.wflip);
+      int bn = y.cin % 128 == 0 ? 128 : 64;
+      dim3 grid((unsigned)(pix / CV_BM), y.cin / bn);
+      if (bn == 128)
+        hipLaunchKernelGGL((k_conv_fwd<128, false, true>), grid, dim3(256), 0, st, M.dzb, y.cout, (const bf16*)nullptr, 0, y.hout, 1, M.wflip, 9 * y.cout, (const float*)nullptr, y.cin, (void*)M.du);
+      else
+        hipLaunchKernelGGL((k_conv_fwd<64, false, true>), grid, dim3(256), 0, st, M.dzb, y.cout, (const bf16*)nullptr, 0, y.hout, 1, M.wflip, 9 * y.cout, (const float*)nullptr, y.cin, (void*)M.du);
+      if (l == 4)
+        // input u5 = [up2(a4) 128, a1 64] at 64^2
+        hipLaunchKernelGGL(k_upcat_bwd, dim3(grid1d((long long)B * 64 * 64 * 64 + (long long)B * 32 * 32 * 128)), dim3(kBlock), 0, st, M.du, 128, 64, B, 64, 64, M.da[3], M.da[0], 0);
+      else
+        // input u4 = [up2(a3) 256, a2 128] at 32^2
+        hipLaunchKernelGGL(k_upcat_bwd, dim3(grid1d((long long)B * 16 * 16 * 256 + (long long)B * 32 * 32 * 128)), dim3(kBlock), 0, st, M.du, 256, 128, B, 32, 32, M.da[2], M.da[1], 0);
+      CHK(hipGetLastError());
+      continue;
+    }
     // data gradient: dcol[pix][k] = sum_co dZ[pix][co] W[co][k]; then col2im into the input
     s = gemm(M, false, true, M.dzb, y.cout, M.wb + y.woff, y.kp, M.dcol, y.kp, (int)pix, y.kp, y.cout, 1);
     if (s != PPRS_OK) return s;
-    if (l == 4) {
-      // input u5 = [up2(a4) 128, a1 64] at 64^2
-      hipLaunchKernelGGL(k_col2im, dim3(grid1d((long long)B * 64 * 64 * 192)), dim3(kBlock), 0, st, M.dcol, B, 64, 64, 192, 1, y.kp, M.du, 0);
-      hipLaunchKernelGGL(k_upcat_bwd, dim3(grid1d((long long)B * 64 * 64 * 64 + (long long)B * 32 * 32 * 128)), dim3(kBlock), 0, st, M.du, 128, 64, B, 64, 64, M.da[3], M.da[0], 0);
-    } else if (l == 3) {
-      // input u4 = [up2(a3) 256, a2 128] at 32^2
-      hipLaunchKernelGGL(k_col2im, dim3(grid1d((long long)B * 32 * 32 * 384)), dim3(kBlock), 0, st, M.dcol, B, 32, 32, 384, 1, y.kp, M.du, 0);
-      hipLaunchKernelGGL(k_upcat_bwd, dim3(grid1d((long long)B * 16 * 16 * 256 + (long long)B * 32 * 32 * 128)), dim3(kBlock), 0, st, M.du, 256, 128, B, 32, 32, M.da[2], M.da[1], 0);
-    } else if (l == 2) {
+    if (l == 2) {
       // input a2 (32^2 x 128), stride 2; a2 already holds the skip gradient from L4
       hipLaunchKernelGGL(k_col2im, dim3(grid1d((long long)B * 32 * 32 * 128)), dim3(kBlock), 0, st, M.dcol, B, 32, 32, 128, 2, y.kp, M.da[1], 1);
     } else if (l == 1) {
@@ -1147,7 +1182,7 @@ void pprs_cnn_destroy(pprs_cnn* c) {
   (void)hipStreamSynchronize(M.stream);
   void* ptrs[] = {M.w, M.m, M.v, M.g, M.wb, M.w6, M.x0, M.a[0], M.a[1], M.a[2], M.a[3], M.a[4],
                   M.u4, M.u5, M.u6, M.col, M.dzb, M.z, M.y, M.dy, M.dcol, M.du, M.da[0],
-                  M.da[1], M.da[2], M.da[3], M.da[4], M.part, M.lpart};
+                  M.da[1], M.da[2], M.da[3], M.da[4], M.part, M.lpart, M.wflip};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
