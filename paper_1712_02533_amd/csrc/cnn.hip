@@ -392,13 +392,21 @@ __global__ void k_colsum_part(const bf16* __restrict__ G, long long M, int N, in
   if (threadIdx.x == 0) part[(size_t)ch * N + n] = red[0];
 }
 
-__global__ void k_colsum_final(const float* __restrict__ part, int N, int chunks,
-                               float* __restrict__ out) {
-  int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+// Column sums of per-chunk partials [chunks][N]: one workgroup (kBlock threads) per column;
+// thread j sums chunks j, j + kBlock, ... in order, then a fixed tree over the threads.
+__global__ void __launch_bounds__(kBlock) k_colsum_final(const float* __restrict__ part, int N,
+                                                         int chunks, float* __restrict__ out) {
+  __shared__ float red[kBlock];
+  int n = blockIdx.x;
   float s = 0.f;
-  for (int c = 0; c < chunks; ++c) s += part[(size_t)c * N + n];
-  out[n] = s;
+  for (int c = threadIdx.x; c < chunks; c += kBlock) s += part[(size_t)c * N + n];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[n] = red[0];
 }
 
 __global__ void k_f32_to_bf16(const float* __restrict__ x, long long count,
@@ -487,7 +495,7 @@ __global__ void k_l6_bwd_data(const float* __restrict__ dY, const float* __restr
 // in LDS; each thread sums, over the tile's 256 positions in order, dY(p, o) U(p + tap, c) for
 // both outputs o of its (tap, c) pairs, or dY(p, o) for the bias. Per-block partials
 // [block][2 * 9 * C + 2] (weights o-major as in the layer, then the two biases), summed over
-// blocks in block order by k_colsum_final. H and Wd are multiples of 16; C == L6C.
+// blocks in a fixed order by k_colsum_final. H and Wd are multiples of 16; C == L6C.
 constexpr int L6T = 16, L6H = L6T + 2, L6C = 66;
 __global__ void __launch_bounds__(256) k_l6_bwd_w_tile(const float* __restrict__ dY,
                                                        const bf16* __restrict__ U, int H, int Wd,
@@ -899,7 +907,7 @@ static pprs_status backward(Model& M, const float* target, int B, int margin, do
     int nw = 2 * 9 * 66 + 2, chunks = B * (128 / L6T) * (128 / L6T);
     hipLaunchKernelGGL(k_l6_bwd_w_tile, dim3(chunks), dim3(256), 0, st, M.dy, M.u6, 128, 128, M.part);
     // weights [2][9*66] then bias [2] are contiguous at woff: columns 0..nw-1 map to them
-    hipLaunchKernelGGL(k_colsum_final, dim3((nw + 255) / 256), dim3(256), 0, st, M.part, nw, chunks, M.g + y6.woff);
+    hipLaunchKernelGGL(k_colsum_final, dim3(nw), dim3(kBlock), 0, st, M.part, nw, chunks, M.g + y6.woff);
     hipLaunchKernelGGL(k_l6_bwd_data, dim3(grid1d(P128 * 66)), dim3(kBlock), 0, st, M.dy, M.w6, B, 128, 128, 66, M.du);
     // split dU6 into d a[4] (upsampled part); the input part needs no gradient
     hipLaunchKernelGGL(k_upcat_bwd, dim3(grid1d(P128 / 4 * 64)), dim3(kBlock), 0, st, M.du, 64, 2, B, 128, 128, M.da[4], (float*)nullptr, 0);
@@ -915,7 +923,7 @@ static pprs_status backward(Model& M, const float* target, int B, int margin, do
     // bias gradient
     int chunks = 64;
     hipLaunchKernelGGL(k_colsum_part, dim3(y.cout, chunks), dim3(kBlock), 0, st, M.dzb, pix, y.cout, chunks, M.part);
-    hipLaunchKernelGGL(k_colsum_final, dim3((y.cout + 255) / 256), dim3(256), 0, st, M.part, y.cout, chunks, M.g + y.boff);
+    hipLaunchKernelGGL(k_colsum_final, dim3(y.cout), dim3(kBlock), 0, st, M.part, y.cout, chunks, M.g + y.boff);
     // weight gradient: dW[co][k] = sum_pix dZ[pix][co] col[pix][k]
     hipLaunchKernelGGL(k_im2col, dim3(grid1d(pix * y.kp)), dim3(kBlock), 0, st, in[l], B, y.hin, y.hin, y.cin, y.stride, y.kp, M.col);
     int splits = (int)std::min<long long>(64, pix / 256);

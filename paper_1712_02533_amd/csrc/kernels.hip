@@ -180,6 +180,16 @@ __device__ __forceinline__ double dpp_take(double v) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
                                           (unsigned)lo));
 }
+// A row shift of a double by DPP with bound control: a lane whose source lies outside its row
+// reads 0 (every lane is written, so no zeroed destination is needed).
+template <int CTRL>
+__device__ __forceinline__ double dpp_shr(double v) {
+  unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, true);
+  int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned)lo));
+}
 // DPP controls: row_shr:k (k = 1, 2, 4, 8), row_bcast:15 (lane 15 of a row into the next row),
 // row_bcast:31 (lane 31 into rows 2 and 3)
 enum { kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118,
@@ -190,20 +200,20 @@ enum { kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118,
 // total is in lane 63 (kTotalLane).
 const int kTotalLane = 63;
 __device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_take<kRowShr1, 0xf>(v);
-  v += dpp_take<kRowShr2, 0xf>(v);
-  v += dpp_take<kRowShr4, 0xf>(v);
-  v += dpp_take<kRowShr8, 0xf>(v);
+  v += dpp_shr<kRowShr1>(v);
+  v += dpp_shr<kRowShr2>(v);
+  v += dpp_shr<kRowShr4>(v);
+  v += dpp_shr<kRowShr8>(v);
   v += dpp_take<kRowBcast15, 0xa>(v);
   v += dpp_take<kRowBcast31, 0xc>(v);
   return v;
 }
 // The same pattern for the maximum of non-negative doubles (0 is the identity); lane 63.
 __device__ __forceinline__ double wave_max(double v) {
-  v = fmax(v, dpp_take<kRowShr1, 0xf>(v));
-  v = fmax(v, dpp_take<kRowShr2, 0xf>(v));
-  v = fmax(v, dpp_take<kRowShr4, 0xf>(v));
-  v = fmax(v, dpp_take<kRowShr8, 0xf>(v));
+  v = fmax(v, dpp_shr<kRowShr1>(v));
+  v = fmax(v, dpp_shr<kRowShr2>(v));
+  v = fmax(v, dpp_shr<kRowShr4>(v));
+  v = fmax(v, dpp_shr<kRowShr8>(v));
   v = fmax(v, dpp_take<kRowBcast15, 0xa>(v));
   v = fmax(v, dpp_take<kRowBcast31, 0xc>(v));
   return v;
