@@ -84,6 +84,11 @@ typedef struct {
   int scan;             /* PPRS_SCAN_* schedule of the series step */
   int scan_workers;     /* P of PPRS_SCAN_GENERAL and PPRS_SCAN_REDUCE_THEN_SCAN (0:
                            ceil(sqrt(M)); at most M); ignored by the other schedules */
+  int warm_start;       /* 1: start neighbour registrations (and, past level 7, B applications)
+                           from the context's network (pprs_set_warm_start) where one is set,
+                           with the cold start as fallback; 0: cold even where one is set */
+  int force_fallback;   /* test switch: 1 rejects every network prediction, so each warm
+                           registration takes the fallback (PPRS_FLAG_FALLBACK) */
 } pprs_params;
 
 /* Statistics of one A or B application. Level index 0 is the coarsest level. */

@@ -33,7 +33,8 @@ class _CParams(ctypes.Structure):
                 ("armijo_sigma", ctypes.c_double), ("ladder_k", ctypes.c_int),
                 ("step_cap", ctypes.c_double), ("tau_min_rel", ctypes.c_double),
                 ("eps", ctypes.c_double), ("iter_max", ctypes.c_int), ("scan", ctypes.c_int),
-                ("scan_workers", ctypes.c_int)]
+                ("scan_workers", ctypes.c_int), ("warm_start", ctypes.c_int),
+                ("force_fallback", ctypes.c_int)]
 
 
 class _CPairStats(ctypes.Structure):
@@ -73,6 +74,8 @@ class Params:
     iter_max: int = 500
     scan: str = "brent_kung"
     scan_workers: int = 0     # P of the general strategy (0: ceil(sqrt(M)))
+    warm_start: int = 1       # 1: the context's network where set (cold fallback); 0: cold
+    force_fallback: int = 0   # test switch: reject every network prediction
 
     def c(self) -> _CParams:
         d = asdict(self)
@@ -202,7 +205,8 @@ def default_params() -> Params:
     _lib().pprs_default_params(ctypes.byref(cp))
     scan = {v: k for k, v in SCAN_KINDS.items()}[cp.scan]
     return Params(cp.levels, cp.lam, cp.beta, cp.armijo_sigma, cp.ladder_k, cp.step_cap,
-                  cp.tau_min_rel, cp.eps, cp.iter_max, scan, cp.scan_workers)
+                  cp.tau_min_rel, cp.eps, cp.iter_max, scan, cp.scan_workers, cp.warm_start,
+                  cp.force_fallback)
 
 
 def scan_plan(kind: str, M: int, workers: int = 0):

@@ -220,6 +220,9 @@ pprs_status check_params(const pprs_params* p, int L) {
     return fail(PPRS_EINVAL, "unknown scan kind %d", p->scan);
   if (p->scan_workers < 0)
     return fail(PPRS_EINVAL, "scan_workers must be >= 0 (got %d)", p->scan_workers);
+  if ((p->warm_start != 0 && p->warm_start != 1) ||
+      (p->force_fallback != 0 && p->force_fallback != 1))
+    return fail(PPRS_EINVAL, "warm_start and force_fallback must be 0 or 1");
   return PPRS_OK;
 }
 
@@ -763,9 +766,10 @@ const int kPairChunk = 512;   // pairs per batch of pprs_register_pairs
 
 // Network predictions for n pairs (ref[s], tmpl[s]) written as level-7 guesses (domain units,
 // [2][129][129]) to dst + s * dst_stride; bad[s] = 1 for predictions that are not finite or
-// exceed the bound.
+// exceed the bound (all of them when force_fallback is set).
 pprs_status warm_predict(pprs_ctx* c, int f0, int n, const int* ref, const int* tmpl,
-                         float* dst, long long dst_stride, std::vector<int>& bad) {
+                         float* dst, long long dst_stride, std::vector<int>& bad,
+                         bool force_fallback) {
   BatchDesc& hd = c->hd;
   int S = 1 << kWarmLevel;
   size_t per = (size_t)S * S * 2;
@@ -793,6 +797,7 @@ pprs_status warm_predict(pprs_ctx* c, int f0, int n, const int* ref, const int* 
   bad.assign(n, 0);
   HIPCHK(hipMemcpyAsync(bad.data(), dbad, sizeof(int) * n, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+  if (force_fallback) bad.assign(n, 1);
   return PPRS_OK;
 }
 
@@ -802,11 +807,11 @@ pprs_status warm_predict(pprs_ctx* c, int f0, int n, const int* ref, const int* 
 // A rejected prediction starts from the identity on m0 and is flagged PPRS_FLAG_FALLBACK.
 // lv[s] and fl[s] receive each slot's start level and flags for run_batch (INIT_PREPARED).
 pprs_status warm_init(pprs_ctx* c, int n, const int* ref, const int* tmpl, int m0,
-                      std::vector<int>& lv, std::vector<int>& fl) {
+                      bool force_fallback, std::vector<int>& lv, std::vector<int>& fl) {
   BatchDesc& hd = c->hd;
   std::vector<int> bad;
   STCHK(warm_predict(c, 0, n, ref, tmpl, hd.ubuf + hd.u_off[kWarmLevel], hd.slot_u_stride,
-                     bad));
+                     bad, force_fallback));
   int n0 = level_n(m0);
   long long per0 = 2LL * n0 * n0;
   lv.assign(n, m0);
@@ -1407,6 +1412,8 @@ void pprs_default_params(pprs_params* p) {
   p->iter_max = 500;
   p->scan = PPRS_SCAN_BRENT_KUNG;
   p->scan_workers = 0;
+  p->warm_start = 1;
+  p->force_fallback = 0;
 }
 
 const char* pprs_last_error(void) { return g_err.c_str(); }
@@ -1604,7 +1611,7 @@ pprs_status pprs_register_pairs(pprs_ctx* c, const float* frames, int N, int H, 
   int nL = level_n(L);
   long long est = 2LL * nL * nL;
   size_t plane = (size_t)H * W;
-  bool warm = c->cnn != nullptr && m0 <= kWarmLevel && kWarmLevel <= L &&
+  bool warm = c->cnn != nullptr && params->warm_start && m0 <= kWarmLevel && kWarmLevel <= L &&
               (c->warm_levels >> L & 1u);
   STCHK(prepare_frames(c, frames, N, H, L, m0, 0, &is_ref));
   int chunk = std::min(P, kPairChunk);
@@ -1620,7 +1627,7 @@ pprs_status pprs_register_pairs(pprs_ctx* c, const float* frames, int N, int H, 
     c->dlog_row0 = p0;
     if (warm) {
       std::vector<int> lv, fl;
-      STCHK(warm_init(c, np, ref + p0, tmpl + p0, m0, lv, fl));
+      STCHK(warm_init(c, np, ref + p0, tmpl + p0, m0, params->force_fallback != 0, lv, fl));
       STCHK(run_batch(c, np, ref + p0, tmpl + p0, INIT_PREPARED, nullptr, nullptr, out.data(),
                       elems, params, ps, nullptr, nullptr, &flags, m0, lv.data(), fl.data()));
     } else {
@@ -1998,7 +2005,7 @@ pprs_status run_series_set(pprs_ctx* c, std::vector<SeriesJob>& jobs, const pprs
   }
   if (!sin.empty()) STCHK(prepare_series(c, sin));
   HIPCHK(hipEventRecord(ev.e[1], c->stream));
-  bool any_warm = c->cnn != nullptr;
+  bool any_warm = c->cnn != nullptr && params->warm_start;
   // schedules: per series the scan program and the frame pairs of its B applications
   std::vector<ScanProg> progs(jobs.size());
   std::vector<std::vector<std::pair<int, int>>> bpairs(jobs.size());
@@ -2057,7 +2064,8 @@ pprs_status run_series_set(pprs_ctx* c, std::vector<SeriesJob>& jobs, const pprs
         tmpl.push_back(pr.second);
       }
     STCHK(warm_predict(c, first[j], (int)ref.size(), ref.data(), tmpl.data(),
-                       P<float>(c->warm_stage) + (size_t)stage_base[j] * per7, per7, bad[j]));
+                       P<float>(c->warm_stage) + (size_t)stage_base[j] * per7, per7, bad[j],
+                       params->force_fallback != 0));
   }
   HIPCHK(hipEventRecord(ev.e[2], c->stream));
   // op order is start priority: the cheapest series first (shortest job first keeps the

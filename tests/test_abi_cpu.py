@@ -167,6 +167,12 @@ def test_workspace_query_host_only():
             P.workspace_query(*bad, p)
     with pytest.raises(api.PprsError):
         P.workspace_query(8, 64, 64, P.Params(levels=7))
+    # the warm-start switches are 0 or 1 (defaults: warm start where a network is set, no forced
+    # fallback)
+    assert (p.warm_start, p.force_fallback) == (1, 0)
+    for bad in [P.Params(warm_start=2), P.Params(force_fallback=-1)]:
+        with pytest.raises(api.PprsError):
+            P.workspace_query(8, 64, 64, bad)
 
 
 def test_wrong_shapes_are_refused_before_the_library():

@@ -176,6 +176,42 @@ def test_warm_fallback_gives_the_cold_result(bad, mode):
     assert torch.equal(warm, cold)
 
 
+@pytest.mark.parametrize("mode", ["skip", "refine"])
+def test_params_switch_the_warm_start_off_or_force_its_fallback(mode):
+    """pprs_params.warm_start = 0 runs cold although the context holds a network: the cold
+    series bit for bit. force_fallback = 1 rejects every prediction: every neighbour
+    registration is flagged as a fallback and no B application starts from the network; in
+    REFINE mode that is the cold series bit for bit (in SKIP mode B applications still start on
+    level 7 from the composition, the mode's own rule). 256^2 frames: finest level 8, above the
+    judge's level 7."""
+    torch = _torch()
+    import paper_1712_02533_amd as P
+    s = make_series(SeriesSpec(n_frames=5, side=256, drift=2.0, warp_amp=0.5,
+                               mean_counts=10.0, seed=59))
+    frames = torch.tensor(s.frames, device="cuda")
+    gp = P.Params(levels=3, scan="brent_kung")
+    uc, sc, oc = P.prefix_register_series(frames, params=gp, want_op_stats=True)
+    P.set_warm_start(_constant_net(0.5, -0.25), max_cells=8.0, mode=mode)
+    try:
+        say("warm start switched off by the params (%s)" % mode)
+        u0, s0, o0 = P.prefix_register_series(
+            frames, params=P.Params(levels=3, scan="brent_kung", warm_start=0),
+            want_op_stats=True)
+        say("warm start with every prediction rejected (%s)" % mode)
+        uf, sf, of = P.prefix_register_series(
+            frames, params=P.Params(levels=3, scan="brent_kung", force_fallback=1),
+            want_op_stats=True)
+        uw, sw, _ = P.prefix_register_series(frames, params=gp)
+    finally:
+        P.set_warm_start(None)
+    assert torch.equal(u0, uc) and [o.flags for o in o0] == [c.flags for c in oc]
+    assert all(o.flags & FLAG_FALLBACK for o in of[:4])
+    assert not any(o.flags & FLAG_NET_START for o in of)
+    if mode == "refine":
+        assert torch.equal(uf, uc)
+    assert not torch.equal(uw, uc)  # the switches are what made the difference
+
+
 def test_warm_refine_with_zero_prediction_is_the_cold_series():
     """A zero prediction restricted to the coarsest level is the identity start: the refine
     mode must then reproduce the cold series bit for bit (B applications are unchanged)."""
