@@ -284,6 +284,30 @@ __global__ void k_im2col(const bf16* __restrict__ X, int Bn, int H, int W, int C
   }
 }
 
+// The same columns 8 at a time (C and Kp multiples of 8, so 8 consecutive columns share one
+// tap): one 16-byte load and store per thread, 32-bit index arithmetic (Bn Ho Wo Kp / 8 < 2^31).
+__global__ void k_im2col8(const bf16* __restrict__ X, int Bn, int H, int W, int C, int s,
+                          int Kp, bf16* __restrict__ col) {
+  const int Ho = H / s, Wo = W / s, KV = Kp / 8;
+  const unsigned total = (unsigned)((long long)Bn * Ho * Wo * KV);
+  for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += gridDim.x * blockDim.x) {
+    unsigned p = i / KV;
+    int k = (int)(i - p * KV) * 8;
+    int ox = (int)(p % Wo);
+    unsigned q = p / Wo;
+    int oy = (int)(q % Ho), b = (int)(q / Ho);
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (k < 9 * C) {
+      int tap = k / C, c = k - tap * C;
+      int y = oy * s + tap / 3 - 1, x = ox * s + tap % 3 - 1;
+      if (y >= 0 && y < H && x >= 0 && x < W)
+        v = *(const uint4*)(X + (((size_t)b * H + y) * W + x) * C + c);
+    }
+    *(uint4*)(col + (size_t)p * Kp + k) = v;
+  }
+}
+
 // dX[b][y][x][c] = sum of dcol over the output positions whose patch covers (y, x).
 __global__ void k_col2im(const float* __restrict__ dcol, int Bn, int H, int W, int C, int s,
                          int ldk, float* __restrict__ dX, int accumulate) {
@@ -925,7 +949,10 @@ static pprs_status backward(Model& M, const float* target, int B, int margin, do
     hipLaunchKernelGGL(k_colsum_part, dim3(y.cout, chunks), dim3(kBlock), 0, st, M.dzb, pix, y.cout, chunks, M.part);
     hipLaunchKernelGGL(k_colsum_final, dim3(y.cout), dim3(kBlock), 0, st, M.part, y.cout, chunks, M.g + y.boff);
     // weight gradient: dW[co][k] = sum_pix dZ[pix][co] col[pix][k]
-    hipLaunchKernelGGL(k_im2col, dim3(grid1d(pix * y.kp)), dim3(kBlock), 0, st, in[l], B, y.hin, y.hin, y.cin, y.stride, y.kp, M.col);
+    if (y.cin % 8 == 0 && y.kp % 8 == 0 && pix * (y.kp / 8) < (1LL << 31))
+      hipLaunchKernelGGL(k_im2col8, dim3(grid1d(pix * y.kp / 8)), dim3(kBlock), 0, st, in[l], B, y.hin, y.hin, y.cin, y.stride, y.kp, M.col);
+    else
+      hipLaunchKernelGGL(k_im2col, dim3(grid1d(pix * y.kp)), dim3(kBlock), 0, st, in[l], B, y.hin, y.hin, y.cin, y.stride, y.kp, M.col);
     int splits = (int)std::min<long long>(64, pix / 256);
     if (splits < 1) splits = 1;
     pprs_status s = gemm(M, true, true, M.dzb, y.cout, M.col, y.kp, M.g + y.woff, y.kp, y.cout, y.kp, (int)pix, splits);
