@@ -964,6 +964,30 @@ def test_average_half_pixel_and_clamp():
 # ------------------------------------------------------------------------------------------
 # Rigid variant (definition of a rigid transformation): phi(x) = R(alpha) x + t
 
+def test_warm_judge_reading_reduces_to_the_cold_series():
+    """The warm-start judge (oracle.warm_series) on a series whose finest level (8) is above
+    the judge's level 7, pinned by the two cases where it must give the plain method's series
+    exactly: a guess that is not finite is rejected everywhere (every neighbour registration a
+    fallback, every B application from the composition); a zero guess in REFINE mode starts every
+    neighbour registration at the identity on the coarsest level, passes the NCC test on level 7
+    (the registration only raises the NCC) and resumes on level 8 from that level-7 result,
+    which is the cold registration's own path."""
+    s = make_series(SeriesSpec(5, 256, 2.0, 0.5, 10.0, 77))
+    p = O.Params(levels=3, lam=10.0, eps=3e-4)
+    fr = np.stack([O.frame_to_nodes(f) for f in s.frames])
+    cold, _, _, _ = O.series(fr, p, scan="brent_kung")
+    g_nan = np.full((2, 129, 129), np.nan)
+    u, ops = O.warm_series(fr, p, lambda i, k: g_nan, "refine")
+    assert all(o["fallback"] and not o["net_start"] for o in ops[:4])
+    assert not any(o["net_start"] for o in ops[4:])
+    assert np.array_equal(u, cold)
+    zero = np.zeros((2, 129, 129))
+    u, ops = O.warm_series(fr, p, lambda i, k: zero, "refine")
+    # (on this series every composition also beats the zero guess on level 7)
+    assert not any(o["fallback"] or o["net_start"] for o in ops)
+    assert np.array_equal(u, cold)
+
+
 def test_averaging_procedure_fixed_points_and_gain():
     """The series averaging procedure (a round: average the aligned frames, register every
     frame i >= 1 to the average from its current deformation): identical frames stay at the
