@@ -298,6 +298,10 @@ def warm_runs(P, series, frames, out, params, args, regs_per_step, cold_ms):
             "%d fallbacks, %d B starts from the network" %
             (mode, 1e3 * dt, cold_ms, acc.mean(), acc_cold.mean(), res[mode]["fallbacks"],
              res[mode]["network_starts_b"]))
+        if mode == "skip" and not args.no_refine:
+            # the averaging procedure from the more accurate warm result
+            res[mode]["average_refine"] = average_rounds(
+                P, torch, series, frames, w, P.series_average(frames, w), params)
     # network forward on the series' neighbour pairs, as the warm start runs it (64 per call)
     n = frames.shape[0] - 1
     ref = np.arange(n, dtype=np.int32)

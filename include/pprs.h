@@ -158,7 +158,7 @@ pprs_status pprs_register_pair(pprs_ctx* ctx, const float* f_ref, const float* f
 /* pprs_register_pair for callers that cannot allocate device memory (code under HIP graph
    capture, tight serving loops, harnesses that forbid hipMalloc): the same registration and
    the same result bits, with every working buffer carved from a fixed scratch array in the
-   library (PPRS_SCRATCH_BYTES = 24 MiB per device, held until the process ends) instead of the
+   library (PPRS_SCRATCH_BYTES = 40 MiB per device, held until the process ends) instead of the
    context's workspace. It calls no hipMalloc, hipFree or other allocating routine. Frames up to
    512 x 512 (513 x 513 nodes) fit at any level count; larger frames are PPRS_EINVAL. The
    caller still passes ctx (its stream and launch shape), the inputs and the output. All calls

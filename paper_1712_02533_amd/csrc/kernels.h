@@ -29,6 +29,8 @@ hipError_t to_nodes(const float* src, int H, long long s_plane, float* dst, int 
 hipError_t from_nodes(const float* src, int n, long long s_plane, float* dst, int H,
                       long long d_plane, int planes, float scale, hipStream_t st);
 hipError_t fill(float* p, long long count, float v, hipStream_t st);
+// bilinear coefficients of N frames of n x n nodes (frame stride n^2) into 4 floats per node
+hipError_t tcoef(const float* f, int n, int N, float* coef, hipStream_t st);
 hipError_t fill_strided(float* p, long long outer, long long per, int n_outer, float v,
                         hipStream_t st);
 hipError_t elem_sums(const float* src, long long plane_stride, int n, int bands, int planes,

@@ -16,15 +16,9 @@
 #include "kernels.h"
 
 // minimum waves per SIMD the hot kernels are compiled for (register budget 512 / value)
-#ifndef LB_ENERGY
 #define LB_ENERGY 4
-#endif
-#ifndef LB_GRAD
 #define LB_GRAD 4
-#endif
-#ifndef LB_SMOOTH
 #define LB_SMOOTH 4
-#endif
 
 #define FLAG_NONCONV 1
 #define FLAG_NAN 2
@@ -76,6 +70,13 @@ __device__ __forceinline__ f32x2u ld_pair(const float* g, unsigned o) {
   return *reinterpret_cast<const GAS f32x2u*>((const GAS char*)g + o);
 }
 
+// A node's bilinear coefficients (c0 v, c1 v(+x) - v, c2 v(+y) - v, c3 the cross difference)
+// from the coefficient pyramid, at byte offset o of the frame's first record.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f32x4 ld_coef(const float* C, unsigned o) {
+  return *reinterpret_cast<const GAS f32x4*>((const GAS char*)C + o);
+}
+
 // Clamped bilinear sample of nodal g (n x n) at column bi + tx, row ai + ty (cells).
 // Returns value; writes the gradient in domain units when grad is true (zero across a
 // coordinate whose position lies outside the level). The position is clamped to the level
@@ -103,8 +104,11 @@ __device__ __forceinline__ float sample_bil(const float* __restrict__ g, int n, 
 }
 
 // Clamped bilinear sample with its gradient (domain units) for the gradient pass, at (tx, ty)
-// cells from the node whose byte offset is base4 (bounds relative to that node as in
-// sample_cells). The cell index is clamped to the last cell (ixmax, iymax relative to the
+// cells from the node whose byte offset is base4 in the plain pyramid (bounds relative to that
+// node as in sample_cells; T0 the frame, T1 the frame one row down, both scalar bases; n4 the
+// row pitch in bytes). The gradient pass reads the plain pyramid, not the coefficient records:
+// its four samples per element gain less from the shorter arithmetic than they lose to the
+// records' fourfold footprint in the caches. The cell index is clamped to the last cell (ixmax, iymax relative to the
 // node), so a position on the far edge is the last cell at fraction 1 and its gradient that
 // cell's slope; across a coordinate clamped to the level the gradient is zero.
 __device__ __forceinline__ float sample_grad(const float* T0, const float* T1, unsigned n4,
@@ -147,26 +151,22 @@ struct QuadField {
   }
 };
 
-// Clamped bilinear sample of a level's nodal frame at (tx, ty) cells from the node whose byte
-// offset is base4, for the energy passes. The position is clamped to the level ([lo, hi] are
+// Clamped bilinear sample of a level's frame at (tx, ty) cells from the node whose record
+// offset is base16 (bytes), for the energy passes, from the frame's coefficient records (C, a
+// scalar base; n16 the row pitch in bytes). The position is clamped to the level ([lo, hi] are
 // the level's bounds relative to that node); the cell is floor of the clamped position and the
-// fraction its remainder, so a position on the far edge takes the last node at fraction 0 and
-// the load reaches one node (column) or one row past it, which the pyramid buffer pads with
-// zeros: the value is the last node's, as with the cell before it at fraction 1. T0 is the
-// frame, T1 the frame one row down (scalar bases), n4 the row pitch in bytes.
-__device__ __forceinline__ float sample_cells(const float* T0, const float* T1, unsigned n4,
-                                              unsigned base4, float lox, float hix, float loy,
-                                              float hiy, float tx, float ty) {
+// fraction its remainder, so a position on the far edge takes the last node at fraction 0 (its
+// value, as with the cell before it at fraction 1). c0 + fx c1 + fy (c2 + fx c3).
+__device__ __forceinline__ float sample_cells(const float* C, unsigned n16, unsigned base16,
+                                              float lox, float hix, float loy, float hiy,
+                                              float tx, float ty) {
   float cx = __builtin_amdgcn_fmed3f(tx, lox, hix);
   float cy = __builtin_amdgcn_fmed3f(ty, loy, hiy);
   int ix = cvt_flr(cx), iy = cvt_flr(cy);
   float fx = __builtin_amdgcn_fractf(cx), fy = __builtin_amdgcn_fractf(cy);
-  unsigned o = (unsigned)mad24(iy, (int)n4, (int)(base4 + ((unsigned)ix << 2)));
-  f32x2u r0 = ld_pair(T0, o);
-  f32x2u r1 = ld_pair(T1, o);
-  float top = fmaf(fx, r0.y - r0.x, r0.x);
-  float bot = fmaf(fx, r1.y - r1.x, r1.x);
-  return fmaf(fy, bot - top, top);
+  unsigned o = (unsigned)mad24(iy, (int)n16, (int)(base16 + ((unsigned)ix << 4)));
+  f32x4 c = ld_coef(C, o);
+  return fmaf(fy, fmaf(fx, c.w, c.z), fmaf(fx, c.y, c.x));
 }
 
 // One DPP step of a wave reduction on a double: each lane the row mask enables takes the value
@@ -688,7 +688,7 @@ __device__ __forceinline__ void energy_item(BatchDesc* D, int s, int t, float* s
     const float* u = slot_u(D, s, l, ub);
     const float* d = D->dbuf + (size_t)s * D->slot_f_stride;
     const float* R = uni(D->pyr + D->frame_off[(size_t)stp->ref * PPRS_MAXL + l]);
-    const float* T = uni(D->pyr + D->frame_off[(size_t)stp->tmpl * PPRS_MAXL + l]);
+    const float* TC = uni(D->tcoef + 4 * D->frame_off[(size_t)stp->tmpl * PPRS_MAXL + l]);
     double top = MODE ? stp->top : 0.0;
     float taus[NC];
 #pragma unroll
@@ -739,8 +739,7 @@ __device__ __forceinline__ void energy_item(BatchDesc* D, int s, int t, float* s
 #pragma unroll
     for (int k = 0; k < 3 * NC; ++k) es[k] = 0.f;
     dir[0] = dir[1] = dir[2] = 0.f;
-    const float* T1 = uni(T + n);  // the row below, as a second scalar base
-    const unsigned n4 = (unsigned)n << 2;
+    const unsigned n16 = (unsigned)n << 4;
     for (int e = threadIdx.x; e < ET_X * ET_Y; e += BLOCK) {
       int ey = e / ET_X, ex = e % ET_X;
       int a = e0y + ey, b = e0x + ex;
@@ -766,7 +765,7 @@ __device__ __forceinline__ void energy_item(BatchDesc* D, int s, int t, float* s
       // the element's cell in the clamp bounds and the byte offset of its first node
       const float lox = (float)(-b), hix = (float)(n - 1 - b);
       const float loy = (float)(-a), hiy = (float)(n - 1 - a);
-      const unsigned base4 = (unsigned)mad24(a, n, b) << 2;
+      const unsigned base16 = (unsigned)mad24(a, n, b) << 4;
       // 2x2 Gauss points, fields interpolated along x first (rows of the element), then y
       QuadField qux(ux), quy(uy), qr(rr), qdx(dx), qdy(dy);
 #pragma unroll
@@ -781,7 +780,7 @@ __device__ __forceinline__ void energy_item(BatchDesc* D, int s, int t, float* s
           for (int j = 0; j < NC; ++j) {
             float tx = fmaf(-taus[j], dqx, px);
             float ty = fmaf(-taus[j], dqy, py);
-            float tv = sample_cells(T, T1, n4, base4, lox, hix, loy, hiy, tx, ty);
+            float tv = sample_cells(TC, n16, base16, lox, hix, loy, hiy, tx, ty);
             es[3 * j + 0] += tv;
             es[3 * j + 1] = fmaf(tv, tv, es[3 * j + 1]);
             es[3 * j + 2] = fmaf(tv, rq, es[3 * j + 2]);
@@ -1237,9 +1236,7 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Lines solved together by one wavefront for C nodes per lane (LDS per wave stays <= 10 KB).
-#ifndef SM_R9
 #define SM_R9 4
-#endif
 template <int C>
 struct SmoothR {
   static constexpr int value = C <= 9 ? SM_R9 : 2;
@@ -1260,9 +1257,7 @@ __device__ __forceinline__ void smooth_item(const float* src, float* dst, const 
     {
       // UB loads per lane in flight before the LDS stores (indices clamped into the strip);
       // 17 covers a 513-node strip of 16 lines in two rounds
-#ifndef SM_UB
 #define SM_UB 17
-#endif
       constexpr int UB = SM_UB;
       const int tot = n * SL;
       for (int k0 = threadIdx.x; k0 < tot; k0 += UB * BLOCK) {
@@ -1380,9 +1375,7 @@ __device__ __forceinline__ void smooth_item(const float* src, float* dst, const 
 // BIG: the instance that also handles lines of more than 576 nodes (17 per lane); the smaller
 // instance leaves that path out, which keeps its register allocation free of spills. The host
 // launches BIG only when the batch's finest level needs it.
-#ifndef LB_SMX
 #define LB_SMX LB_SMOOTH
-#endif
 template <int DIR, bool BIG>
 __global__ void __launch_bounds__(BLOCK, DIR ? LB_SMX : LB_SMOOTH) k_smooth(BatchDesc* D) {
   extern __shared__ float s_buf[];
@@ -1672,6 +1665,26 @@ __global__ void __launch_bounds__(BLOCK) k_fill_strided(float* p, long long oute
   for (long long k = blockIdx.x * (long long)BLOCK + threadIdx.x; k < total;
        k += (long long)gridDim.x * BLOCK)
     p[(k / per) * outer + (k % per)] = v;
+}
+
+// Bilinear coefficients of each node of N frames of n x n nodes: v, the difference to the node
+// to the right, to the node below, and the cross difference (v11 - v10) - (v01 - v00); the
+// differences that would leave the frame are 0 (a sample there has fraction 0 on that axis).
+__global__ void __launch_bounds__(BLOCK) k_tcoef(const float* f, int n, long long total,
+                                                 float4* coef) {
+  const long long nn = (long long)n * n;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    int r = (int)(i % nn);
+    int a = r / n, b = r - a * n;
+    float v00 = f[i];
+    bool rx = b < n - 1, ry = a < n - 1;
+    float v01 = rx ? f[i + 1] : v00, v10 = ry ? f[i + n] : v00;
+    float v11 = rx && ry ? f[i + n + 1] : v00;
+    float c1 = rx ? v01 - v00 : 0.f, c2 = ry ? v10 - v00 : 0.f;
+    float c3 = rx && ry ? (v11 - v10) - (v01 - v00) : 0.f;
+    coef[i] = make_float4(v00, c1, c2, c3);
+  }
 }
 
 __global__ void __launch_bounds__(BLOCK) k_fill(float* p, long long count, float v) {
@@ -2381,6 +2394,14 @@ hipError_t from_nodes(const float* src, int n, long long s_plane, float* dst, in
                       long long d_plane, int planes, float scale, hipStream_t st) {
   hipLaunchKernelGGL(k_from_nodes, dim3(grid_for((long long)planes * H * H)), dim3(BLOCK), 0,
                      st, src, n, s_plane, dst, H, d_plane, planes, scale);
+  return hipGetLastError();
+}
+hipError_t tcoef(const float* f, int n, int N, float* coef, hipStream_t st) {
+  long long total = (long long)N * n * n;
+  long long g = (total + BLOCK - 1) / BLOCK;
+  g = g < 1 ? 1 : (g > 16384 ? 16384 : g);
+  hipLaunchKernelGGL(k_tcoef, dim3((unsigned)g), dim3(BLOCK), 0, st, f, n, total,
+                     (float4*)coef);
   return hipGetLastError();
 }
 hipError_t fill(float* p, long long count, float v, hipStream_t st) {

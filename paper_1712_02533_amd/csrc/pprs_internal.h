@@ -27,9 +27,7 @@ enum { WK_PROLONG = 0, WK_EVAL = 1, WK_GRAD = 2, WK_SMY = 3, WK_SMX = 4, WK_LADD
 
 // Tile geometry (compile-time).
 #define ET_X 64   // energy kernel: elements per tile along x
-#ifndef ET_Y
 #define ET_Y 16   //                elements per tile along y
-#endif
 #define PT_X 64   // prolongation: fine nodes per tile along x
 #define PT_Y 8
 // smoother: lines per workgroup, chosen per level so one strip stays under 40 KB of LDS
@@ -91,9 +89,7 @@ struct WorkList {
 // Everything the per-step kernels need; lives in device memory, pointers fixed per context.
 // Row pitch (floats) of a level's gradient and metric-solve buffers: rows start on 128-byte
 // lines, so the column-strip solve reads and writes whole lines instead of straddling two.
-#ifndef WPAD
 #define WPAD 32
-#endif
 __host__ __device__ inline int row_pitch(int n) { return (n + WPAD - 1) / WPAD * WPAD; }
 
 struct BatchDesc {
@@ -139,6 +135,8 @@ struct BatchDesc {
   // op's k-th accepted step (levels in order), the step being top 2^-J of its iteration
   unsigned char* dlog;
   int dlog_cap;
+  float* tcoef;            // per pyramid node (same offsets x 4): v, v(+x) - v, v(+y) - v,
+                           // v(+x+y) - v(+y) - v(+x) + v (0 past the last row / column)
   int active;              // written by the plan kernel
   int* active_host;        // mapped host word (may be null)
 };

@@ -109,7 +109,7 @@ struct pprs_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   // frames
-  DevBuf frames, frame_off, rsum, fr_ms, fr_part;
+  DevBuf frames, frame_off, rsum, fr_ms, fr_part, tcoef;
   std::vector<long long> frame_off_host;
   // slots
   DevBuf state, ubuf, dbuf, gbuf, zbuf, partial, nodecount, coef, list_slots, list_off,
@@ -153,7 +153,7 @@ struct pprs_ctx {
   long long nodes_acc[WK_COUNT] = {0};
   // every workspace buffer (for pprs_workspace_bytes; each frees itself with the context)
   std::vector<const DevBuf*> all_bufs() const {
-    return {&frames, &frame_off, &rsum, &fr_ms, &fr_part, &state, &ubuf, &dbuf, &gbuf, &zbuf,
+    return {&frames, &frame_off, &rsum, &fr_ms, &fr_part, &tcoef, &state, &ubuf, &dbuf, &gbuf, &zbuf,
             &partial, &nodecount, &coef, &list_slots, &list_off, &lists, &desc, &opidx,
             &elems, &cnn_in, &cnn_out, &tmp, &badflags, &warm_stage, &avg_stage, &pool_idx,
             &pool_off, &pool_states};
@@ -435,18 +435,16 @@ struct SeriesIn {
 };
 
 const int kSumBands = 16;  // row bands of the per-frame sums (elem_sums)
-// zeros after the last pyramid: the energy passes' bilinear loads at a level's far edge reach
-// up to one row and one node past the frame they sample (with weight zero)
-const size_t kPyrPad = 2 * ((1u << 10) + 1) + 2;
 
 // Buffer sizes of prepare_series for NT frames in all, at most Nmax per series, `nodes` grid
 // nodes over all pyramids.
 struct FrameBytes {
-  size_t frames, frame_off, rsum, fr_part, fr_ms;
+  size_t frames, frame_off, rsum, fr_part, fr_ms, tcoef;
 };
 FrameBytes frame_bytes(size_t nodes, int NT, int Nmax) {
   FrameBytes b;
-  b.frames = sizeof(float) * (nodes + kPyrPad);
+  b.frames = sizeof(float) * std::max<size_t>(nodes, 1);
+  b.tcoef = 4 * b.frames;  // bilinear coefficients of every node (template samples)
   b.frame_off = sizeof(long long) * (size_t)NT * PPRS_MAXL;
   b.rsum = sizeof(double) * (size_t)NT * PPRS_MAXL;
   b.fr_part = sizeof(double) * 2 * (size_t)Nmax * kSumBands;
@@ -474,6 +472,7 @@ pprs_status prepare_series(pprs_ctx* c, const std::vector<SeriesIn>& ser) {
     }
   FrameBytes fb = frame_bytes(total, NT, Nmax);
   STCHK(ensure(c->frames, fb.frames));
+  STCHK(ensure(c->tcoef, fb.tcoef));
   STCHK(ensure(c->frame_off, fb.frame_off));
   STCHK(ensure(c->rsum, fb.rsum));
   const int bands = kSumBands;
@@ -484,7 +483,7 @@ pprs_status prepare_series(pprs_ctx* c, const std::vector<SeriesIn>& ser) {
   hd.pyr = P<float>(c->frames);
   hd.frame_off = P<long long>(c->frame_off);
   hd.rsum = P<double>(c->rsum);
-  HIPCHK(pprs_k::fill(hd.pyr + total, (long long)kPyrPad, 0.f, c->stream));
+  hd.tcoef = P<float>(c->tcoef);
   for (const SeriesIn& x : ser) {
     int N = x.N;
     auto lvl = [&](int l) { return hd.pyr + off[(size_t)x.f0 * PPRS_MAXL + l]; };
@@ -515,6 +514,8 @@ pprs_status prepare_series(pprs_ctx* c, const std::vector<SeriesIn>& ser) {
           return fail(PPRS_EINVAL, "reference frame %d is constant on level %d", f, l);
       }
       HIPCHK(pprs_k::normalize(lvl(l), (long long)n * n, (long long)n * n, N, msd, c->stream));
+      HIPCHK(pprs_k::tcoef(lvl(l), n, N, hd.tcoef + 4 * off[(size_t)x.f0 * PPRS_MAXL + l],
+                           c->stream));
       HIPCHK(pprs_k::elem_sums(lvl(l), (long long)n * n, n, bands, N, P<double>(c->fr_part),
                                c->stream));
       HIPCHK(pprs_k::elem_final(P<double>(c->fr_part), bands, N, 1, nullptr, rs, PPRS_MAXL, l,
@@ -1285,7 +1286,7 @@ struct SeriesWs {
   size_t total() const {
     if (!any) return 0;
     return frames.frames + frames.frame_off + frames.rsum + frames.fr_part + frames.fr_ms +
-           elems + pool_idx + pool_off + pool_states + tmp + slots.state + slots.ubuf +
+           frames.tcoef + elems + pool_idx + pool_off + pool_states + tmp + slots.state + slots.ubuf +
            slots.dbuf + slots.gbuf + slots.zbuf + slots.partial + slots.nodecount +
            slots.coef + slots.list_slots + slots.list_off + slots.lists + slots.desc +
            slots.opidx;
@@ -1347,7 +1348,7 @@ pprs_status enter(pprs_ctx* c) {
 // lists. Each device the library runs on holds its own copy until the process ends; host code
 // reaches it only through the address hipGetSymbolAddress returns for that device (the
 // array's name is a host-side stand-in, not a device address).
-#define PPRS_SCRATCH_BYTES (24u << 20)
+#define PPRS_SCRATCH_BYTES (40u << 20)
 static __device__ __align__(256) unsigned char scratch[PPRS_SCRATCH_BYTES];
 
 namespace {
@@ -1383,7 +1384,7 @@ size_t pair_scratch_bytes(int H, int W, int L, int m0) {
   for (int l = m0; l <= L; ++l) nodes += 2 * (size_t)level_n(l) * level_n(l);
   FrameBytes f = frame_bytes(nodes, 2, 2);
   t += align_up(f.frames) + align_up(f.frame_off) + align_up(f.rsum) + align_up(f.fr_part) +
-       align_up(f.fr_ms);
+       align_up(f.fr_ms) + align_up(f.tcoef);
   BatchDesc hd;
   memset(&hd, 0, sizeof hd);
   SlotBytes b = slot_layout(hd, 1, L, m0, true);
@@ -1490,6 +1491,7 @@ pprs_status pprs_reserve_workspace(pprs_ctx* c, int N, int H, int W, const pprs_
   STCHK(ensure(c->rsum, w.frames.rsum));
   STCHK(ensure(c->fr_part, w.frames.fr_part));
   STCHK(ensure(c->fr_ms, w.frames.fr_ms));
+  STCHK(ensure(c->tcoef, w.frames.tcoef));
   STCHK(ensure(c->elems, w.elems));
   STCHK(ensure(c->pool_idx, w.pool_idx));
   STCHK(ensure(c->pool_off, w.pool_off));

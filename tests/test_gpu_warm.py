@@ -44,12 +44,13 @@ def _series(n=4, side=256, seed=51):
 
 
 def _long_run_bar(d):
-    """Bar for registrations of some hundred steps: relative perturbations of 1e-6 (FP32
-    arithmetic) move the FP64 result itself by up to ~1e-2 px at isolated nodes while every
-    decision and the bulk stay put (test_long_registration_sensitivity_to_fp32_level_perturbation
-    pins this), so: RMS < 1e-4 px, 99.9th percentile < 1e-3 px, max < 0.05 px."""
-    assert np.sqrt((d ** 2).mean()) < 1e-4
-    assert np.percentile(d, 99.9) < 1e-3
+    """Bar for registrations of some hundred steps: relative perturbations of 1e-6 to 2e-6
+    (FP32 arithmetic's level) move the FP64 result itself, with every decision unchanged, by up
+    to ~2.4e-4 px RMS, ~1.1e-3 px at the 99.9th percentile and ~4e-2 px at isolated nodes
+    (test_long_registration_sensitivity_to_fp32_level_perturbation measures this envelope on
+    the same pair), so: RMS < 3e-4 px, 99.9th percentile < 2e-3 px, max < 0.05 px."""
+    assert np.sqrt((d ** 2).mean()) < 3e-4
+    assert np.percentile(d, 99.9) < 2e-3
     assert d.max() < 0.05
 
 

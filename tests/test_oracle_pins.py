@@ -568,26 +568,35 @@ def test_start_level_variant_reduces_to_multilevel_and_skips_levels():
 
 def test_long_registration_sensitivity_to_fp32_level_perturbation():
     """Derived tolerance for long registrations: a pair four frames' drift apart (about 230
-    accepted steps over 3 levels) is sensitive to perturbations at the level of FP32 rounding.
-    Relative noise of 1e-6 on the template leaves every line-search decision unchanged and the
-    RMS change below 1e-4 px, but moves isolated nodes by more than 1e-3 px (a sample point
-    crossing a cell edge switches the one-sided bilinear gradient there)."""
+    accepted steps over 3 levels) is sensitive to perturbations at the level of FP32
+    arithmetic. Relative noise of 1e-6 and 2e-6 on the template (four draws each) leaves the
+    line-search decisions unchanged on most draws; with unchanged decisions the result moves by
+    up to ~2.4e-4 px RMS, ~1.1e-3 px at the 99.9th percentile and by more than 1e-3 px at
+    isolated nodes (a sample point crossing a cell edge switches the one-sided bilinear gradient
+    there), never by 0.05 px. The long-run bar of the GPU tests (RMS < 3e-4, 99.9th percentile
+    < 2e-3, max < 0.05 px) is this envelope."""
     s = make_series(SeriesSpec(n_frames=4, side=256, drift=4.0, warp_amp=1.0,
                                mean_counts=10.0, seed=51))
     p = O.Params(levels=3, lam=10.0, beta=1.0, sigma=0.5, ladder_k=1, cap=1.0,
                  tau_min_rel=1e-4, eps=3e-4, iter_max=500)
     R, T = O.frame_to_nodes(s.frames[3]), O.frame_to_nodes(s.frames[0])
     u0, s0, _ = O.register(R, T, p)
-    rng = np.random.default_rng(0)
-    worst = 0.0
-    for _ in range(2):
-        up, sp, _ = O.register(R, T * (1 + 1e-6 * rng.standard_normal(T.shape)), p)
-        d = np.abs(O.u_to_pixels(u0, 256) - O.u_to_pixels(up, 256))
-        assert sp.iters == s0.iters and sp.trials == s0.trials
-        assert np.sqrt((d ** 2).mean()) < 1e-4
-        assert np.percentile(d, 99.9) < 1e-3
-        worst = max(worst, d.max())
-    assert 1e-3 < worst < 0.05
+    same, rms, p999, worst = 0, [], [], 0.0
+    for amp in (1e-6, 2e-6):
+        rng = np.random.default_rng(0)
+        for _ in range(4):
+            up, sp, _ = O.register(R, T * (1 + amp * rng.standard_normal(T.shape)), p)
+            if sp.iters != s0.iters or sp.trials != s0.trials:
+                continue
+            same += 1
+            d = np.abs(O.u_to_pixels(u0, 256) - O.u_to_pixels(up, 256))
+            rms.append(float(np.sqrt((d ** 2).mean())))
+            p999.append(float(np.percentile(d, 99.9)))
+            worst = max(worst, float(d.max()))
+    assert same >= 6
+    assert max(rms) < 3e-4 and max(p999) < 2e-3 and 1e-3 < worst < 0.05
+    # the envelope reaches past the former 1e-4 / 1e-3 bar
+    assert max(rms) > 1e-4 and max(p999) > 1e-3
 
 
 def test_constant_reference_rejected():
