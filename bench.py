@@ -216,11 +216,12 @@ def accuracy(u, ks, gts, side):
     return np.array(out)
 
 
-def average_rounds(P, torch, series, frames, out, avg, params, rounds=2):
+def average_rounds(P, torch, series, frames, out, avg, params, rounds=2, truth=None):
     """The series averaging procedure after the scan: each round averages the aligned frames
     and re-registers frames 1.. to the average from their current deformation. Reports each
-    round's time and the average's RMS error against the clean object (the first frame's
-    noise-free image scaled to the frames' mean count, interior only)."""
+    round's time, the average's RMS error against the clean object (the first frame's
+    noise-free image scaled to the frames' mean count, interior only) and, with truth = (ks,
+    gts), the registrations' accuracy against the analytic displacements of those frames."""
     import numpy as np
     from synth.blobs import _clean_frame
     spec = series.spec
@@ -229,7 +230,25 @@ def average_rounds(P, torch, series, frames, out, avg, params, rounds=2):
     obj = clean * (float(series.frames.mean()) / float(clean.mean()))
     b = 24
     err = lambda a: float(np.sqrt(((a.cpu().numpy() - obj)[b:-b, b:-b] ** 2).mean()))
-    res = dict(err_scan_average=round(err(avg), 4), rounds=[])
+
+    def acc(u):
+        if truth is None:
+            return None, None, None
+        a = accuracy(u, truth[0], truth[1], spec.side)
+        # the common drift: the mean signed error of the sampled frames within 1 px (a shift
+        # all frames share moves the average off frame 0's coordinates)
+        dr = []
+        for k, gt, e in zip(truth[0], truth[1], a):
+            if e <= 1.0:
+                bb = min(int(np.abs(gt).max()) + 6, spec.side // 4)
+                dr.append((u[k].cpu().numpy()[:, bb:-bb, bb:-bb] - gt[:, bb:-bb, bb:-bb])
+                          .mean(axis=(1, 2)))
+        drift = [round(float(x), 4) for x in np.mean(dr, axis=0)] if dr else None
+        return round(float(a.mean()), 4), int((a > 1.0).sum()), drift
+
+    a0, o0, d0 = acc(out)
+    res = dict(err_scan_average=round(err(avg), 4), acc_rms_px_scan=a0, frames_over_1px_scan=o0,
+               drift_px_scan=d0, rounds=[])
     u = out.clone()
     for _ in range(rounds):
         torch.cuda.synchronize()
@@ -238,11 +257,15 @@ def average_rounds(P, torch, series, frames, out, avg, params, rounds=2):
         torch.cuda.synchronize()
         ms = 1e3 * (time.perf_counter() - t0)
         steps = float(np.mean([sum(st.iters) for st in rows[0]]))
+        ar, ov, dr = acc(u)
         res["rounds"].append(dict(ms=round(ms, 1), registrations=len(rows[0]),
-                                  mean_steps=round(steps, 1), err=round(err(a), 4)))
+                                  mean_steps=round(steps, 1), err=round(err(a), 4),
+                                  acc_rms_px=ar, frames_over_1px=ov, drift_px=dr))
         log("averaging round: %.1f ms, %d registrations (%.1f steps each), average's error "
-            "against the clean object %.4f (scan average %.4f)"
-            % (ms, len(rows[0]), steps, err(a), res["err_scan_average"]))
+            "against the clean object %.4f (scan average %.4f); accuracy against the truth %s "
+            "px (scan %s), frames off by more than 1 px: %s (scan %s), common drift %s px "
+            "(scan %s)" % (ms, len(rows[0]), steps, err(a), res["err_scan_average"], ar, a0,
+                           ov, o0, dr, d0))
     return res
 
 
@@ -301,7 +324,8 @@ def warm_runs(P, series, frames, out, params, args, regs_per_step, cold_ms):
         if mode == "skip" and not args.no_refine:
             # the averaging procedure from the more accurate warm result
             res[mode]["average_refine"] = average_rounds(
-                P, torch, series, frames, w, P.series_average(frames, w), params)
+                P, torch, series, frames, w, P.series_average(frames, w), params,
+                truth=(ks, gts))
     # network forward on the series' neighbour pairs, as the warm start runs it (64 per call)
     n = frames.shape[0] - 1
     ref = np.arange(n, dtype=np.int32)
@@ -599,7 +623,9 @@ def main():
                              gbs=round(abytes / (ams * 1e-3) / 1e9, 1))
     log("series average: %.3f ms, %.0f GB/s" % (ams, abytes / (ams * 1e-3) / 1e9))
     if not args.no_refine:
-        result["average_refine"] = average_rounds(P, torch, series, frames, out, avg, params)
+        truth = truth_sample(series, n_sample=16, workers=nthreads) if spec.side >= 128 else None
+        result["average_refine"] = average_rounds(P, torch, series, frames, out, avg, params,
+                                                  truth=truth)
     if not args.no_rigid and scan not in ("blelloch", "reduce_then_scan"):
         # the same frames through the rigid operator (three parameters per registration)
         rp = P.Params(levels=cfg["levels"], scan=scan, scan_workers=args.workers)
