@@ -1153,12 +1153,18 @@ __device__ __forceinline__ void scan_down(float (&A)[R], float (&B)[R], int lane
   }
 }
 
+// Levels have n = 2^l + 1 nodes, so the C chosen for a level (the smallest of 1, 2, 3, 5, 9, 17
+// with 64 C >= n) gives exactly coef_pitch(n) = 64 C node slots per line. The coefficient
+// arrays are zero past node n - 1, so every lane runs its whole chunk without a branch: a
+// padded node's forward map is the constant 0 (its y is 0) and, in the backward direction,
+// c'_{n-1} = 0 already cuts node n - 1 off from anything above it.
 template <int R, int C>
 __device__ __forceinline__ void solve_lines(float (&v)[R][C], int n, int lane,
                                             const float* __restrict__ coef) {
+  const int cs = coef_pitch(n);
   const GAS float* ca = (const GAS float*)coef;  // a_i
-  const GAS float* ci = ca + n;                   // 1 / den_i
-  const GAS float* cp = ca + 2 * n;               // c'_i
+  const GAS float* ci = ca + cs;                  // 1 / den_i
+  const GAS float* cp = ca + 2 * cs;              // c'_i
   int base = lane * C;
   float A[R], B[R];
 #pragma unroll
@@ -1169,13 +1175,11 @@ __device__ __forceinline__ void solve_lines(float (&v)[R][C], int n, int lane,
 #pragma unroll
   for (int k = 0; k < C; ++k) {
     int i = base + k;
-    if (i < n) {
-      float a = ca[i], c = ci[i];
+    float a = ca[i], c = ci[i];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        A[r] = a * A[r];
-        B[r] = fmaf(a, B[r], c * v[r][k]);
-      }
+    for (int r = 0; r < R; ++r) {
+      A[r] = a * A[r];
+      B[r] = fmaf(a, B[r], c * v[r][k]);
     }
   }
   float y[R];
@@ -1185,13 +1189,11 @@ __device__ __forceinline__ void solve_lines(float (&v)[R][C], int n, int lane,
 #pragma unroll
   for (int k = 0; k < C; ++k) {
     int i = base + k;
-    if (i < n) {
-      float a = ca[i], c = ci[i];
+    float a = ca[i], c = ci[i];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        y[r] = fmaf(a, y[r], c * v[r][k]);
-        v[r][k] = y[r];
-      }
+    for (int r = 0; r < R; ++r) {
+      y[r] = fmaf(a, y[r], c * v[r][k]);
+      v[r][k] = y[r];
     }
   }
 #pragma unroll
@@ -1202,13 +1204,11 @@ __device__ __forceinline__ void solve_lines(float (&v)[R][C], int n, int lane,
 #pragma unroll
   for (int k = C - 1; k >= 0; --k) {
     int i = base + k;
-    if (i < n) {
-      float mm = -cp[i];
+    float mm = -cp[i];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        A[r] = mm * A[r];
-        B[r] = fmaf(mm, B[r], v[r][k]);
-      }
+    for (int r = 0; r < R; ++r) {
+      A[r] = mm * A[r];
+      B[r] = fmaf(mm, B[r], v[r][k]);
     }
   }
   scan_down<R>(A, B, lane);
@@ -1217,13 +1217,11 @@ __device__ __forceinline__ void solve_lines(float (&v)[R][C], int n, int lane,
 #pragma unroll
   for (int k = C - 1; k >= 0; --k) {
     int i = base + k;
-    if (i < n) {
-      float mm = -cp[i];
+    float mm = -cp[i];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        y[r] = fmaf(mm, y[r], v[r][k]);
-        v[r][k] = y[r];
-      }
+    for (int r = 0; r < R; ++r) {
+      y[r] = fmaf(mm, y[r], v[r][k]);
+      v[r][k] = y[r];
     }
   }
 }
@@ -1252,27 +1250,30 @@ __device__ __forceinline__ void smooth_item(const float* src, float* dst, const 
   int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   float v[R][C];
   if (DIR == 0) {
-    // strip [n][SL] with pitch SL + 1; wave wv solves columns g .. g+R-1, g = R wv + R NW j
+    // strip [n][SL] with pitch SL + 1; wave wv solves columns g .. g+R-1, g = R wv + R NW j.
+    // SL is a power of two (8, 16 or 32): strip element k is row k >> sh, line k & (SL - 1).
     int pitch = SL + 1;
+    const int sh = __builtin_ctz(SL);
     {
       // UB loads per lane in flight before the LDS stores (indices clamped into the strip);
       // 17 covers a 513-node strip of 16 lines in two rounds
 #define SM_UB 17
       constexpr int UB = SM_UB;
-      const int tot = n * SL;
+      const int tot = n << sh;
+      const GAS float* sb = (const GAS float*)src + line0;
       for (int k0 = threadIdx.x; k0 < tot; k0 += UB * BLOCK) {
         float v[UB];
 #pragma unroll
         for (int j = 0; j < UB; ++j) {
           int k = min(k0 + j * BLOCK, tot - 1);
-          int i = k / SL, L = min(k - i * SL, nl - 1);
-          v[j] = gld(src, (size_t)i * P + line0 + L);
+          int i = k >> sh, L = min(k & (SL - 1), nl - 1);
+          v[j] = sb[(unsigned)(i * P + L)];
         }
 #pragma unroll
         for (int j = 0; j < UB; ++j) {
           int k = k0 + j * BLOCK;
           if (k < tot) {
-            int i = k / SL, L = k - i * SL;
+            int i = k >> sh, L = k & (SL - 1);
             s_buf[i * pitch + L] = L < nl ? v[j] : 0.f;
           }
         }
@@ -1285,7 +1286,8 @@ __device__ __forceinline__ void smooth_item(const float* src, float* dst, const 
 #pragma unroll
         for (int k = 0; k < C; ++k) {
           int i = lane * C + k, L = min(g + r, SL - 1);
-          v[r][k] = i < n ? s_buf[i * pitch + L] : 0.f;
+          float x = s_buf[min(i, n - 1) * pitch + L];
+          v[r][k] = i < n ? x : 0.f;
         }
       solve_lines<R, C>(v, n, lane, coef);
 #pragma unroll
@@ -1297,14 +1299,16 @@ __device__ __forceinline__ void smooth_item(const float* src, float* dst, const 
         }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < n * SL; k += BLOCK) {
-      int i = k / SL, L = k - i * SL;
-      if (L < nl) gst(dst, (size_t)i * P + line0 + L, s_buf[i * pitch + L]);
+    GAS float* db = (GAS float*)dst + line0;
+    for (int k = threadIdx.x; k < (n << sh); k += BLOCK) {
+      int i = k >> sh, L = k & (SL - 1);
+      if (L < nl) db[(unsigned)(i * P + L)] = s_buf[i * pitch + L];
     }
   } else {
     // each wave stages R rows in its own LDS area (row pitch 64 C + 1)
     int pitch = 64 * C + 1;
     float* rows = s_buf + wv * R * pitch;
+    float dmf = 0.f;  // max |d| (exact in FP32)
     for (int g = wv * R; g < nl; g += R * NW) {
       int nr = min(R, nl - g);
       if constexpr (C <= 9) {
@@ -1363,12 +1367,13 @@ __device__ __forceinline__ void smooth_item(const float* src, float* dst, const 
             float x = rows[r * pitch + i];
             gst(dr, i, x);
             gd += (double)(t[k] * x);
-            dm = fmax(dm, (double)fabsf(x));
+            dmf = fmaxf(dmf, fabsf(x));
           }
         }
       }
       wave_sync();
     }
+    dm = fmax(dm, (double)dmf);
   }
 }
 
@@ -1464,8 +1469,8 @@ __global__ void __launch_bounds__(SW_THREADS) k_smooth_win(BatchDesc* D) {
     const float* G = D->gbuf + (size_t)sl * D->slot_p_stride + comp * (size_t)n * P;
     float* dst = D->dbuf + (size_t)sl * D->slot_f_stride + comp * nn;
     const float* ca = D->coef + g.coef_off;  // a_i
-    const float* ci = ca + n;                // 1 / den_i
-    const float* cp = ca + 2 * n;            // c'_i
+    const float* ci = ca + coef_pitch(n);    // 1 / den_i
+    const float* cp = ca + 2 * coef_pitch(n);  // c'_i
     __syncthreads();
     for (int k = tid; k < hy * hx; k += SW_THREADS) {
       int r = k / hx, q = k - r * hx;

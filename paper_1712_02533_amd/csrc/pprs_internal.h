@@ -91,6 +91,8 @@ struct WorkList {
 // lines, so the column-strip solve reads and writes whole lines instead of straddling two.
 #define WPAD 32
 __host__ __device__ inline int row_pitch(int n) { return (n + WPAD - 1) / WPAD * WPAD; }
+// Entries per coefficient array of a level's line solves: n rounded up to whole 64-lane chunks.
+__host__ __device__ inline int coef_pitch(int n) { return (n + 63) / 64 * 64; }
 
 struct BatchDesc {
   int n_slots;

@@ -322,7 +322,7 @@ SlotBytes slot_layout(BatchDesc& hd, int cap, int L, int m0, bool fields) {
   for (int l = 0; l < PPRS_MAXL; ++l) hd.u_off[l] = 0;
   for (int l = m0; l <= L; ++l) {
     fill_geom(hd.geom[l], l, coef_off);
-    coef_off += 3 * hd.geom[l].n;
+    coef_off += 3 * coef_pitch(hd.geom[l].n);
     hd.u_off[l] = uoff;
     uoff += 4LL * hd.geom[l].n * hd.geom[l].n;
     max_items = std::max(max_items, std::max(hd.geom[l].tiles_elem, 2 * hd.geom[l].sm_items));
@@ -395,7 +395,9 @@ pprs_status ensure_slots(pprs_ctx* c, int cap, int L, int m0, double beta, bool 
     c->coef_beta = -1.0;
   }
   if (beta != c->coef_beta || c->coef_L != L || c->coef_m0 != m0) {
-    // LU of S1 = M1 + (beta h)^2 K1 per level, in FP64, stored as FP32 a_i, 1/den_i, c'_i.
+    // LU of S1 = M1 + (beta h)^2 K1 per level, in FP64, stored as FP32 a_i, 1/den_i, c'_i,
+    // each array padded with zeros to coef_pitch(n) entries (the line solves read whole
+    // lanes' chunks; zero coefficients make the padded nodes' maps constant zero).
     std::vector<float> host;
     for (int l = m0; l <= L; ++l) {
       int n = level_n(l);
@@ -408,11 +410,12 @@ pprs_status ensure_slots(pprs_ctx* c, int cap, int L, int m0, double beta, bool 
         cp[i] = o / den[i];
       }
       size_t base = host.size();
-      host.resize(base + 3 * n);
+      const int cs = coef_pitch(n);
+      host.resize(base + 3 * cs, 0.f);
       for (int i = 0; i < n; ++i) {
         host[base + i] = i == 0 ? 0.f : (float)(-o / den[i]);
-        host[base + n + i] = (float)(1.0 / den[i]);
-        host[base + 2 * n + i] = i == n - 1 ? 0.f : (float)cp[i];
+        host[base + cs + i] = (float)(1.0 / den[i]);
+        host[base + 2 * cs + i] = i == n - 1 ? 0.f : (float)cp[i];
       }
     }
     HIPCHK(hipMemcpy(c->coef.p, host.data(), host.size() * sizeof(float),
