@@ -242,6 +242,41 @@ __device__ void block_sum(double (&v)[NV], double* scratch, bool is_max_last = f
   __syncthreads();
 }
 
+// Deterministic block reduction of NV doubles per thread (blockDim.x == BLOCK) with the totals
+// stored to out[0..NV) in global memory. Per group of up to BLOCK / 16 values: one DPP step
+// adds each odd lane's left neighbour, the BLOCK / 2 pair sums of each value go to LDS, and one
+// 16-lane row per value adds its entries (lane j: entries j, j + 16, ..., in order), then the
+// row's running sums leave the total in the row's last lane, which stores it. stage: at least
+// min(NV, BLOCK / 16) * BLOCK / 2 doubles of LDS, free for this call's duration (it may alias
+// the caller's tile buffers: the first barrier waits for every lane to be done with them).
+// Far fewer instructions than a wave reduction per value.
+template <int NV>
+__device__ void block_sum_store(const double (&v)[NV], double* stage, double* out) {
+  constexpr int KG = NV < BLOCK / 16 ? NV : BLOCK / 16, HALF = BLOCK / 2;
+  const int tid = threadIdx.x, row = tid >> 4, sub = tid & 15;
+#pragma unroll
+  for (int k0 = 0; k0 < NV; k0 += KG) {
+    __syncthreads();
+#pragma unroll
+    for (int k = k0; k < k0 + KG && k < NV; ++k) {
+      double p = v[k] + dpp_shr<kRowShr1>(v[k]);
+      if (tid & 1) stage[(k - k0) * HALF + (tid >> 1)] = p;
+    }
+    __syncthreads();
+    if (row < KG && k0 + row < NV) {
+      const double* src = stage + row * HALF + sub;
+      double t = src[0];
+#pragma unroll
+      for (int j = 1; j < HALF / 16; ++j) t += src[16 * j];
+      t += dpp_shr<kRowShr1>(t);
+      t += dpp_shr<kRowShr2>(t);
+      t += dpp_shr<kRowShr4>(t);
+      t += dpp_shr<kRowShr8>(t);
+      if (sub == 15) out[k0 + row] = t;
+    }
+  }
+}
+
 __device__ __forceinline__ float* slot_u(const BatchDesc* D, int s, int l, int buf) {
   int n = lvl_n(l);
   return D->ubuf + (size_t)s * D->slot_u_stride + D->u_off[l] + (size_t)buf * 2 * n * n;
@@ -672,7 +707,7 @@ __device__ __forceinline__ void energy_finalize(BatchDesc* D, SlotState* stp, in
 template <int MODE, int NC>
 __device__ __forceinline__ void energy_item(BatchDesc* D, int s, int t, float* s_ux, float* s_uy,
                                             float* s_dx, float* s_dy, float* s_r,
-                                            double* s_red) {
+                                            double* s_stage) {
   constexpr int NXN = ET_X + 1, NN = ET_NN;
   constexpr int NV = 3 * NC + 3;
   const int kind = MODE ? WK_LADDER : WK_EVAL;
@@ -795,20 +830,26 @@ __device__ __forceinline__ void energy_item(BatchDesc* D, int s, int t, float* s
     for (int k = 0; k < 3 * NC; ++k) acc[k] = w * (double)es[k];
 #pragma unroll
     for (int k = 0; k < 3; ++k) acc[3 * NC + k] = h2 * (double)dir[k];
-    block_sum<NV>(acc, s_red);
-    if (threadIdx.x == 0) {
-      double* pr = slot_partial(D, s, kind, t);
-      for (int k = 0; k < NV; ++k) pr[k] = acc[k];
-    }
+    // s_stage aliases the tile buffers
+    block_sum_store<NV>(acc, s_stage, slot_partial(D, s, kind, t));
   }
 }
 
+// LDS of an energy workgroup: the tile's staged fields (NF arrays of ET_NN floats), also the
+// stage of the partial-sum reduction once the tile is done.
+template <int NF, int NV>
+struct EnergyLds {
+  static constexpr int FLOATS = NF * ET_NN, KG = NV < BLOCK / 16 ? NV : BLOCK / 16;
+  static_assert(FLOATS / 2 >= KG * (BLOCK / 2), "reduction stage fits the tile buffers");
+  double buf[(FLOATS + 1) / 2];
+  __device__ float* field(int i) { return reinterpret_cast<float*>(buf) + i * ET_NN; }
+};
+
 template <int MODE, int NC>
 __global__ void __launch_bounds__(BLOCK, LB_ENERGY) k_energy(BatchDesc* D) {
-  constexpr int NN = ET_NN;
-  constexpr int NV = 3 * NC + 3;
-  __shared__ float s_ux[NN], s_uy[NN], s_dx[MODE ? NN : 1], s_dy[MODE ? NN : 1], s_r[NN];
-  __shared__ double s_red[(BLOCK / 64) * NV];
+  __shared__ EnergyLds<MODE ? 5 : 3, 3 * NC + 3> L;
+  float *s_ux = L.field(0), *s_uy = L.field(1), *s_r = L.field(2);
+  float *s_dx = MODE ? L.field(3) : nullptr, *s_dy = MODE ? L.field(4) : nullptr;
   __shared__ int s_pos;
   const int kind = MODE ? WK_LADDER : WK_EVAL;
   ItemCursor c;
@@ -816,7 +857,7 @@ __global__ void __launch_bounds__(BLOCK, LB_ENERGY) k_energy(BatchDesc* D) {
   for (; c.item < c.end; ++c.item) {
     int s, t;
     cursor_slot(D, kind, c, s, t);
-    energy_item<MODE, NC>(D, s, t, s_ux, s_uy, s_dx, s_dy, s_r, s_red);
+    energy_item<MODE, NC>(D, s, t, s_ux, s_uy, s_dx, s_dy, s_r, L.buf);
   }
 }
 
@@ -826,10 +867,9 @@ __global__ void __launch_bounds__(BLOCK, LB_ENERGY) k_energy(BatchDesc* D) {
 // begins a level no gradient work in the same step).
 template <int NC>
 __global__ void __launch_bounds__(BLOCK, LB_ENERGY) k_energy_step(BatchDesc* D) {
-  constexpr int NN = ET_NN;
-  constexpr int NV = 3 * NC + 3;
-  __shared__ float s_ux[NN], s_uy[NN], s_dx[NN], s_dy[NN], s_r[NN];
-  __shared__ double s_red[(BLOCK / 64) * NV];
+  __shared__ EnergyLds<5, 3 * NC + 3> L;
+  float *s_ux = L.field(0), *s_uy = L.field(1), *s_r = L.field(2), *s_dx = L.field(3),
+        *s_dy = L.field(4);
   __shared__ int s_pos;
   const int ne = D->lists[WK_EVAL].total, nl = D->lists[WK_LADDER].total;
   const int total = ne + nl;
@@ -841,14 +881,14 @@ __global__ void __launch_bounds__(BLOCK, LB_ENERGY) k_energy_step(BatchDesc* D) 
     for (; c.item < c.end; ++c.item) {
       int s, t;
       cursor_slot(D, WK_EVAL, c, s, t);
-      energy_item<0, 1>(D, s, t, s_ux, s_uy, s_dx, s_dy, s_r, s_red);
+      energy_item<0, 1>(D, s, t, s_ux, s_uy, s_dx, s_dy, s_r, L.buf);
     }
   }
   if (b1 > ne && cursor_range(D, WK_LADDER, max(b0, ne) - ne, b1 - ne, c, &s_pos)) {
     for (; c.item < c.end; ++c.item) {
       int s, t;
       cursor_slot(D, WK_LADDER, c, s, t);
-      energy_item<1, NC>(D, s, t, s_ux, s_uy, s_dx, s_dy, s_r, s_red);
+      energy_item<1, NC>(D, s, t, s_ux, s_uy, s_dx, s_dy, s_r, L.buf);
     }
   }
 }
