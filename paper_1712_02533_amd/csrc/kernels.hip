@@ -70,6 +70,16 @@ __device__ __forceinline__ f32x2u ld_pair(const float* g, unsigned o) {
   return *reinterpret_cast<const GAS f32x2u*>((const GAS char*)g + o);
 }
 
+// One float at byte offset o of a block-uniform base (scalar base + 32-bit lane offset: no
+// 64-bit address arithmetic per access). Every buffer a kernel addresses this way is under
+// 4 GiB from its base.
+__device__ __forceinline__ float ldo(const float* g, unsigned o) {
+  return *reinterpret_cast<const GAS float*>((const GAS char*)g + o);
+}
+__device__ __forceinline__ void sto(float* g, unsigned o, float v) {
+  *reinterpret_cast<GAS float*>((GAS char*)g + o) = v;
+}
+
 // A node's bilinear coefficients (c0 v, c1 v(+x) - v, c2 v(+y) - v, c3 the cross difference)
 // from the coefficient pyramid, at byte offset o of the frame's first record.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -720,10 +730,11 @@ __device__ __forceinline__ void energy_item(BatchDesc* D, int s, int t, float* s
     int ub = (ph == PH_PROLONG) ? 0 : stp->ub;
     int n = lvl_n(l);
     size_t nn = (size_t)n * n;
-    const float* u = slot_u(D, s, l, ub);
-    const float* d = D->dbuf + (size_t)s * D->slot_f_stride;
+    const float* u = uni(slot_u(D, s, l, ub));
+    const float* d = uni(D->dbuf + (size_t)s * D->slot_f_stride);
     const float* R = uni(D->pyr + D->frame_off[(size_t)stp->ref * PPRS_MAXL + l]);
     const float* TC = uni(D->tcoef + 4 * D->frame_off[(size_t)stp->tmpl * PPRS_MAXL + l]);
+    const unsigned nn4 = (unsigned)nn << 2;
     double top = MODE ? stp->top : 0.0;
     float taus[NC];
 #pragma unroll
@@ -742,13 +753,13 @@ __device__ __forceinline__ void energy_item(BatchDesc* D, int s, int t, float* s
       for (int it = 0; it < SIT; ++it) {
         int k = threadIdx.x + it * BLOCK;
         int a = e0y + k / NXN, b = e0x + k % NXN;
-        size_t i = (k < NN && a < n && b < n) ? (size_t)a * n + b : 0;
-        vux[it] = gld(u, i);
-        vuy[it] = gld(u, nn + i);
-        vr[it] = gld(R, i);
+        unsigned o = ((k < NN) & (a < n) & (b < n)) ? (unsigned)mad24(a, n, b) << 2 : 0u;
+        vux[it] = ldo(u, o);
+        vuy[it] = ldo(u, nn4 + o);
+        vr[it] = ldo(R, o);
         if (MODE) {
-          vdx[it] = gld(d, i);
-          vdy[it] = gld(d, nn + i);
+          vdx[it] = ldo(d, o);
+          vdy[it] = ldo(d, nn4 + o);
         }
       }
 #pragma unroll
@@ -972,12 +983,12 @@ __device__ __forceinline__ void grad_item(BatchDesc* D, int s, int t, GradLds<TX
     int l = stp->level;
     int n = lvl_n(l);
     size_t nn = (size_t)n * n;
-    const float* u = slot_u(D, s, l, stp->ub);
-    float* un = slot_u(D, s, l, stp->ub ^ 1);
-    const float* d = D->dbuf + (size_t)s * D->slot_f_stride;
-    float* G = D->gbuf + (size_t)s * D->slot_p_stride;
+    const float* u = uni(slot_u(D, s, l, stp->ub));
+    float* un = uni(slot_u(D, s, l, stp->ub ^ 1));
+    const float* d = uni(D->dbuf + (size_t)s * D->slot_f_stride);
+    float* G = uni(D->gbuf + (size_t)s * D->slot_p_stride);
     const int gpi = row_pitch(n);
-    const size_t gpn = (size_t)n * gpi;
+    const unsigned nn4 = (unsigned)nn << 2, gpn4 = (unsigned)(n * gpi) << 2;
     const float* R = uni(D->pyr + D->frame_off[(size_t)stp->ref * PPRS_MAXL + l]);
     const float* T = uni(D->pyr + D->frame_off[(size_t)stp->tmpl * PPRS_MAXL + l]);
     const float* T1 = uni(T + n);  // the row below, as a second scalar base
@@ -1000,27 +1011,27 @@ __device__ __forceinline__ void grad_item(BatchDesc* D, int s, int t, GradLds<TX
       constexpr int SIT = (NX * NY + BLOCK - 1) / BLOCK;
       float vux[SIT], vuy[SIT], vr[SIT], vdx[SIT], vdy[SIT];
       const bool mv = tau != 0.f;
+      bool okv[SIT];
 #pragma unroll
       for (int it = 0; it < SIT; ++it) {
         int k = threadIdx.x + it * BLOCK;
         int ky = k / NX, kx = k % NX;
         int a = y0 - 1 + ky, b = x0 - 1 + kx;
-        bool ok = k < NX * NY && ky < th + 2 && kx < tw + 2 && a >= 0 && a < n && b >= 0 && b < n;
-        size_t i = ok ? (size_t)a * n + b : 0;
-        vux[it] = gld(u, i);
-        vuy[it] = gld(u, nn + i);
-        vr[it] = gld(R, i);
-        vdx[it] = mv ? gld(d, i) : 0.f;
-        vdy[it] = mv ? gld(d, nn + i) : 0.f;
+        okv[it] = (k < NX * NY) & (ky < th + 2) & (kx < tw + 2) & ((unsigned)a < (unsigned)n) &
+                  ((unsigned)b < (unsigned)n);
+        unsigned o = okv[it] ? (unsigned)mad24(a, n, b) << 2 : 0u;
+        vux[it] = ldo(u, o);
+        vuy[it] = ldo(u, nn4 + o);
+        vr[it] = ldo(R, o);
+        vdx[it] = mv ? ldo(d, o) : 0.f;
+        vdy[it] = mv ? ldo(d, nn4 + o) : 0.f;
       }
 #pragma unroll
       for (int it = 0; it < SIT; ++it) {
         int k = threadIdx.x + it * BLOCK;
-        int ky = k / NX, kx = k % NX;
-        int a = y0 - 1 + ky, b = x0 - 1 + kx;
         if (k >= NX * NY) break;
         float ux = 0.f, uy = 0.f, r = 0.f;
-        if (ky < th + 2 && kx < tw + 2 && a >= 0 && a < n && b >= 0 && b < n) {
+        if (okv[it]) {
           ux = vux[it];
           uy = vuy[it];
           if (mv) {
@@ -1039,7 +1050,10 @@ __device__ __forceinline__ void grad_item(BatchDesc* D, int s, int t, GradLds<TX
       int ey = e / EX, ex = e % EX;
       int a = y0 - 1 + ey, b = x0 - 1 + ex;
       float cx[4] = {0, 0, 0, 0}, cy[4] = {0, 0, 0, 0};
-      if (ey < th + 1 && ex < tw + 1 && a >= 0 && a < n - 1 && b >= 0 && b < n - 1) {
+      // one branch (not a chain of short-circuit branches, each re-zeroing the sums)
+      const bool live = (ey < th + 1) & (ex < tw + 1) & (a >= 0) & (a < n - 1) & (b >= 0) &
+                        (b < n - 1);
+      if (live) {
         int k00 = ey * NX + ex;
         float ux[4] = {s_ux[k00], s_ux[k00 + 1], s_ux[k00 + NX], s_ux[k00 + NX + 1]};
         float uy[4] = {s_uy[k00], s_uy[k00 + 1], s_uy[k00 + NX], s_uy[k00 + NX + 1]};
@@ -1085,20 +1099,23 @@ __device__ __forceinline__ void grad_item(BatchDesc* D, int s, int t, GradLds<TX
       }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < tw * th; k += BLOCK) {
-      int ty = k / tw, tx = k - ty * tw;
+    // rows of TX + 1 slots (a compile-time divisor); the slot past the tile's width is skipped
+    constexpr int TW1 = TX + 1;
+    for (int k = threadIdx.x; k < th * TW1; k += BLOCK) {
+      int ty = k / TW1, tx = k - ty * TW1;
+      if (tx >= tw) continue;
       int a = y0 + ty, b = x0 + tx;
       // elements (local coords): (ty, tx) is element (a-1, b-1) -> corner 3, etc.
       int e11 = ty * EX + tx, e10 = ty * EX + tx + 1, e01 = (ty + 1) * EX + tx,
           e00 = (ty + 1) * EX + tx + 1;
       float gx = (s_c[6][e11] + s_c[4][e10]) + (s_c[2][e01] + s_c[0][e00]);
       float gy = (s_c[7][e11] + s_c[5][e10]) + (s_c[3][e01] + s_c[1][e00]);
-      size_t i = (size_t)a * n + b, ig = (size_t)a * gpi + b;
+      unsigned o = (unsigned)mad24(a, n, b) << 2, og = (unsigned)mad24(a, gpi, b) << 2;
       int kn = (ty + 1) * NX + tx + 1;
-      gst(G, ig, gx);
-      gst(G, gpn + ig, gy);
-      gst(un, i, s_ux[kn]);
-      gst(un, nn + i, s_uy[kn]);
+      sto(G, og, gx);
+      sto(G, gpn4 + og, gy);
+      sto(un, o, s_ux[kn]);
+      sto(un, nn4 + o, s_uy[kn]);
     }
     __syncthreads();
   }
