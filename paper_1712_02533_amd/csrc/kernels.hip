@@ -415,27 +415,43 @@ __device__ __forceinline__ void sum_partials(const BatchDesc* D, int s, int kind
 // ------------------------------------------------------------------------------------------
 // Planning kernel: one workgroup of 1024 threads.
 
-#define PLAN_T 1024
+#define PLAN_T 256
 #define PLAN_V (2 * WK_COUNT)
-
-// LDS of the planning pass for a workgroup of NT threads.
 template <int NT>
 struct PlanLds {
   int wtot[NT / 64][PLAN_V];
   int woff[NT / 64][PLAN_V];
   int carry[PLAN_V];
   int active[NT / 64];
+  int items[PPRS_MAXL][WK_COUNT];  // kind_items per effective level
 };
 
+// Inclusive scan of an int over the 64 lanes of a wave on DPP moves: running sums inside each
+// 16-lane row, then row 0 into row 1 and row 2 into row 3 (row_bcast:15), then rows 0-1 into
+// rows 2-3 (row_bcast:31). A lane reading outside its row, or not enabled, adds 0.
+__device__ __forceinline__ int wave_scan_incl(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, kRowShr1, 0xf, 0xf, true);
+  v += __builtin_amdgcn_update_dpp(0, v, kRowShr2, 0xf, 0xf, true);
+  v += __builtin_amdgcn_update_dpp(0, v, kRowShr4, 0xf, 0xf, true);
+  v += __builtin_amdgcn_update_dpp(0, v, kRowShr8, 0xf, 0xf, true);
+  v += __builtin_amdgcn_update_dpp(0, v, kRowBcast15, 0xa, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, kRowBcast31, 0xc, 0xf, false);
+  return v;
+}
+
 // One workgroup of NT threads: per kind, the compacted list of member slots and the prefix sum
-// of their item counts. Wave-level shuffle scans, then a scan over the wave totals.
+// of their item counts. The item counts per level come from a table in LDS (filled while the
+// slot states load); wave-level DPP scans, then a scan over the wave totals.
 template <int NT>
 __device__ void plan_body(BatchDesc* D, PlanLds<NT>& P) {
   int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (threadIdx.x < PLAN_V) P.carry[threadIdx.x] = 0;
   int n_slots = D->n_slots;
   int active = 0;
-  __syncthreads();
+  if (threadIdx.x < PLAN_V) P.carry[threadIdx.x] = 0;
+  if (threadIdx.x < PPRS_MAXL * WK_COUNT) {
+    int l = threadIdx.x / WK_COUNT, k = threadIdx.x - l * WK_COUNT;
+    P.items[l][k] = (l >= D->coarsest && l <= D->finest) ? kind_items(D, k, l) : 0;
+  }
   for (int base = 0; base < n_slots; base += NT) {
     int s = base + threadIdx.x;
     int ph = PH_DONE, eff = 0;
@@ -444,6 +460,7 @@ __device__ void plan_body(BatchDesc* D, PlanLds<NT>& P) {
       ph = st->phase;
       eff = ph == PH_PROLONG ? st->level + 1 : st->level;
     }
+    __syncthreads();  // the table and the carries (and the previous round's offsets)
     active += ph != PH_DONE;
     int val[PLAN_V];
 #pragma unroll
@@ -459,18 +476,11 @@ __device__ void plan_body(BatchDesc* D, PlanLds<NT>& P) {
         default: m = ph == PH_GRAD; break;
       }
       val[2 * k] = m ? 1 : 0;
-      val[2 * k + 1] = m ? kind_items(D, k, eff) : 0;
+      val[2 * k + 1] = m ? P.items[eff][k] : 0;
     }
     int inc[PLAN_V];
 #pragma unroll
-    for (int v = 0; v < PLAN_V; ++v) inc[v] = val[v];
-    for (int off = 1; off < 64; off <<= 1) {
-#pragma unroll
-      for (int v = 0; v < PLAN_V; ++v) {
-        int x = __shfl_up(inc[v], off, 64);
-        if (lane >= off) inc[v] += x;
-      }
-    }
+    for (int v = 0; v < PLAN_V; ++v) inc[v] = wave_scan_incl(val[v]);
     if (lane == 63)
 #pragma unroll
       for (int v = 0; v < PLAN_V; ++v) P.wtot[wv][v] = inc[v];
@@ -493,7 +503,6 @@ __device__ void plan_body(BatchDesc* D, PlanLds<NT>& P) {
         D->list_off[(size_t)k * (D->max_slots + 1) + pos] = off;
       }
     }
-    __syncthreads();
   }
   for (int o = 32; o > 0; o >>= 1) active += __shfl_down(active, o, 64);
   if (lane == 0) P.active[wv] = active;
@@ -589,11 +598,9 @@ __device__ __forceinline__ void ke_apply(const float u[4], float out[4]) {
 // Works on a register copy of the slot's scalar fields (loaded together up front, stored back
 // at the end): every read of global state would otherwise wait behind the previous store.
 template <int MODE, int NC>
-__device__ __forceinline__ void energy_finalize(BatchDesc* D, SlotState* stp, int s, int l, int n,
-                                                int ph, double top,
+__device__ __forceinline__ void energy_finalize(BatchDesc* D, SlotState* stp, SlotState& st,
+                                                int s, int l, int n, int ph, double top,
                                                 const double (&tot)[3 * NC + 3]) {
-  SlotState st;
-  load_head(st, *stp);
   const int kind = MODE ? WK_LADDER : WK_EVAL;
   int K = D->ladder_k;
   double rs = D->rsum[(size_t)st.ref * PPRS_MAXL + l];
@@ -906,20 +913,27 @@ __global__ void __launch_bounds__(BLOCK, LB_ENERGY) k_energy_step(BatchDesc* D) 
 
 // Per-slot finalisation of an energy pass: one workgroup per listed slot sums the tile
 // partials in tile order and advances the slot (the kernel boundary orders it after the pass).
+// The slot's item count comes from the list offsets the plan wrote (the slot's tiles on the
+// level it was listed for), so the partial loads do not wait for the slot state; a slot the
+// metric-solve finaliser already moved off its line search is skipped after the sums.
 template <int MODE, int NC>
-__device__ __forceinline__ void energy_fin_slot(BatchDesc* D, int s, double* s_red) {
+__device__ __forceinline__ void energy_fin_slot(BatchDesc* D, int pos, double* s_red) {
   constexpr int NV = 3 * NC + 3;
   const int kind = MODE ? WK_LADDER : WK_EVAL;
+  const int* off = D->list_off + (size_t)kind * (D->max_slots + 1);
+  const int s = D->list_slots[(size_t)kind * D->max_slots + pos];
+  const int n_items = off[pos + 1] - off[pos];
   SlotState* stp = D->state + s;
-  int ph = stp->phase;
-  if (MODE == 0 && !(ph == PH_INIT || ph == PH_PROLONG)) return;
-  if (MODE == 1 && ph != PH_LADDER) return;
-  int l = (ph == PH_PROLONG) ? stp->level + 1 : stp->level;
-  int n = lvl_n(l);
-  double top = MODE ? stp->top : 0.0;
+  SlotState st;
+  load_head(st, *stp);  // in flight with the partial loads
   double tot[NV];
-  sum_partials<NV>(D, s, kind, D->geom[l].tiles_elem, tot, s_red, false);
-  if (threadIdx.x == 0) energy_finalize<MODE, NC>(D, stp, s, l, n, ph, top, tot);
+  sum_partials<NV>(D, s, kind, n_items, tot, s_red, false);
+  const int ph = st.phase;
+  bool live = MODE == 0 ? (ph == PH_INIT || ph == PH_PROLONG) : ph == PH_LADDER;
+  if (live && threadIdx.x == 0) {
+    int l = (ph == PH_PROLONG) ? st.level + 1 : st.level;
+    energy_finalize<MODE, NC>(D, stp, st, s, l, lvl_n(l), ph, MODE ? st.top : 0.0, tot);
+  }
   __syncthreads();
 }
 
@@ -930,7 +944,7 @@ __global__ void __launch_bounds__(BLOCK) k_energy_fin(BatchDesc* D) {
   const int kind = MODE ? WK_LADDER : WK_EVAL;
   const WorkList wl = D->lists[kind];
   for (int pos = blockIdx.x; pos < wl.n_slots; pos += gridDim.x)
-    energy_fin_slot<MODE, NC>(D, D->list_slots[(size_t)kind * D->max_slots + pos], s_red);
+    energy_fin_slot<MODE, NC>(D, pos, s_red);
 }
 
 // Finalisers of k_energy_step: the eval list's slots, then the ladder list's.
@@ -941,10 +955,9 @@ __global__ void __launch_bounds__(BLOCK) k_energy_step_fin(BatchDesc* D) {
   const int ne = D->lists[WK_EVAL].n_slots, nl = D->lists[WK_LADDER].n_slots;
   for (int pos = blockIdx.x; pos < ne + nl; pos += gridDim.x) {
     if (pos < ne)
-      energy_fin_slot<0, 1>(D, D->list_slots[(size_t)WK_EVAL * D->max_slots + pos], s_red);
+      energy_fin_slot<0, 1>(D, pos, s_red);
     else
-      energy_fin_slot<1, NC>(D, D->list_slots[(size_t)WK_LADDER * D->max_slots + pos - ne],
-                             s_red);
+      energy_fin_slot<1, NC>(D, pos - ne, s_red);
   }
 }
 
@@ -1619,17 +1632,19 @@ __global__ void __launch_bounds__(SW_THREADS) k_smooth_win(BatchDesc* D) {
 __global__ void __launch_bounds__(BLOCK) k_smooth_fin(BatchDesc* D) {
   __shared__ double s_red[(BLOCK / 64) * 2];
   const WorkList wl = D->lists[WK_SMX];
+  const int* off = D->list_off + (size_t)WK_SMX * (D->max_slots + 1);
   for (int pos = blockIdx.x; pos < wl.n_slots; pos += gridDim.x) {
+    // listed slots are in GRAD (nothing between the plan and here changes a phase); the item
+    // count comes from the list offsets, so the partial loads do not wait for the slot state
     int s = D->list_slots[(size_t)WK_SMX * D->max_slots + pos];
     SlotState* stp = D->state + s;
-    if (stp->phase != PH_GRAD) continue;
-    int l = stp->level;
-    int n = lvl_n(l);
+    SlotState st;
+    load_head(st, *stp);  // in flight with the partial loads
     double tot[2];
-    sum_partials<2>(D, s, WK_SMX, kind_items(D, WK_SMX, l), tot, s_red, true);
+    sum_partials<2>(D, s, WK_SMX, off[pos + 1] - off[pos], tot, s_red, true);
     if (threadIdx.x == 0) {
-      SlotState st;
-      load_head(st, *stp);
+      int l = st.level;
+      int n = lvl_n(l);
       long long* nc_s = D->node_count + (size_t)s * WK_COUNT;
       nc_s[WK_GRAD] += (long long)n * n;
       if (!D->smooth_halo) nc_s[WK_SMY] += (long long)n * n;
