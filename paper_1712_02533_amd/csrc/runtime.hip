@@ -124,8 +124,8 @@ struct pprs_ctx {
   unsigned warm_levels = ~0u;  // bit L set: series with side 2^L use the warm start
   DevBuf cnn_in, cnn_out, tmp, badflags, warm_stage;
   DevBuf avg_stage;  // the series average of the averaging procedure ([H][W])
-  // slot pool: per-round index lists and staged slot states
-  DevBuf pool_idx, pool_off, pool_states;
+  // slot pool: one poll's packed uploads (finish lists, staged slot states, init lists)
+  DevBuf pool_pack;
   int pool_group = 16;   // steps between polls of the slot pool
   int pool_slots = kPoolSlotsDefault;  // concurrent registrations of a series
   // workgroups of the per-step item kernels (results do not depend on them)
@@ -155,8 +155,7 @@ struct pprs_ctx {
   std::vector<const DevBuf*> all_bufs() const {
     return {&frames, &frame_off, &rsum, &fr_ms, &fr_part, &tcoef, &state, &ubuf, &dbuf, &gbuf, &zbuf,
             &partial, &nodecount, &coef, &list_slots, &list_off, &lists, &desc, &opidx,
-            &elems, &cnn_in, &cnn_out, &tmp, &badflags, &warm_stage, &avg_stage, &pool_idx,
-            &pool_off, &pool_states};
+            &elems, &cnn_in, &cnn_out, &tmp, &badflags, &warm_stage, &avg_stage, &pool_pack};
   }
 };
 
@@ -884,6 +883,17 @@ struct GraphExec {
   }
 };
 
+// Bytes of one poll's packed upload for a pool of S slots: at most S finished slots (slot and
+// version offset each), S starting registrations (staged state and slot) and their initial-
+// guess lists (slot, stage index, two version offsets), every list 8-byte aligned, with one
+// list per finest level and one per kind, finest and start level at most.
+size_t pool_pack_bytes(int S) {
+  const size_t lists = PPRS_MAXL + 2 + 4 * PPRS_MAXL * PPRS_MAXL;
+  return (size_t)S * (sizeof(int) + sizeof(long long)) +
+         (size_t)S * (sizeof(SlotState) + sizeof(int)) +
+         (size_t)S * (2 * sizeof(int) + 2 * sizeof(long long)) + lists * 4 * 8;
+}
+
 pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
                      const std::vector<long long>& ver_off, const pprs_params* p,
                      const PoolSpec& spec, pprs_pair_stats* stats, long long* node_steps,
@@ -953,12 +963,31 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
   }
   HIPCHK(hipMemcpyAsync(hd.state, st.data(), sizeof(SlotState) * S, hipMemcpyHostToDevice,
                         c->stream));
-  STCHK(ensure(c->pool_idx, sizeof(int) * 4 * (size_t)S));
-  STCHK(ensure(c->pool_off, sizeof(long long) * 3 * (size_t)S));
-  STCHK(ensure(c->pool_states, sizeof(SlotState) * (size_t)S));
-  int* didx = P<int>(c->pool_idx);
-  long long* doff = P<long long>(c->pool_off);
-  SlotState* dstates = P<SlotState>(c->pool_states);
+  // Every poll uploads what it hands the device (the finished slots' result lists, the staged
+  // states of the starting registrations and the index lists of their initial guesses) as one
+  // packed buffer in one copy; the kernels read their lists from it in stream order, so a poll
+  // waits for the device once (the state read-back).
+  const size_t pack_cap = pool_pack_bytes(S);
+  STCHK(ensure(c->pool_pack, pack_cap));
+  char* dpack = P<char>(c->pool_pack);
+  std::vector<char> hpack(pack_cap);
+  size_t pack_used = 0;
+  bool pack_over = false;
+  auto put = [&](const void* src, size_t bytes) -> size_t {
+    size_t o = (pack_used + 7) & ~(size_t)7;
+    if (o + bytes > pack_cap) {
+      pack_over = true;
+      return 0;
+    }
+    memcpy(hpack.data() + o, src, bytes);
+    pack_used = o + bytes;
+    return o;
+  };
+  struct FinishList {
+    int L, cnt;
+    size_t slots, outs;
+  };
+  std::vector<FinishList> finish_lists;
   std::vector<int> slot_op(S, -1), free_slots;
   std::vector<double> op_start(n_ops, 0.0);
   for (int s = S - 1; s >= 0; --s) free_slots.push_back(s);
@@ -972,9 +1001,8 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
   long long max_steps = per_op_steps * (long long)(n_ops / S + 2) + 64;
   long long done_steps = 0;
   int done_ops = 0;
-  // host copies of the per-round lists (they must outlive the asynchronous uploads)
-  std::vector<int> h_idx(4 * (size_t)S);
-  std::vector<long long> h_off(3 * (size_t)S);
+  std::vector<int> lst(S), lst_stage(S);
+  std::vector<long long> lst_o0(S), lst_o1(S);
   std::vector<SlotState> h_states(S);
   int G = std::max(1, c->pool_group);
   // the G steps between polls always launch the same kernels with the same arguments (all
@@ -997,8 +1025,17 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
     if (ie != hipSuccess)
       return fail(PPRS_EHIP, "graph instantiation failed: %s", hipGetErrorString(ie));
   }
+  // The finished slots' results go to their versions (grouped by finest level) before the
+  // slots are handed to new registrations: those lists open the next upload.
+  auto launch_finish = [&]() -> pprs_status {
+    for (const FinishList& f : finish_lists)
+      HIPCHK(pprs_k::pool_finish(d, f.L, (const int*)(dpack + f.slots),
+                                 (const long long*)(dpack + f.outs), f.cnt, vbuf, c->stream));
+    finish_lists.clear();
+    return PPRS_OK;
+  };
   while (done_ops < n_ops) {
-    // 1. start ready ops in free slots
+    // 1. start ready ops in free slots (the upload already holds the last poll's finish lists)
     int na = 0;
     std::vector<int> a_slot, a_op;
     while (!free_slots.empty() && !ready.empty()) {
@@ -1052,71 +1089,77 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
       }
       ++na;
     }
+    // initial-guess lists per kind, finest level and start level
+    struct InitList {
+      int kind, Lv, lv, cnt;
+      size_t slots, stage, o0, o1;
+    };
+    std::vector<InitList> init_lists;
+    size_t a_states = 0, a_slots = 0;
     if (na > 0) {
-      for (int k = 0; k < na; ++k) h_idx[k] = a_slot[k];
-      HIPCHK(hipMemcpyAsync(dstates, h_states.data(), sizeof(SlotState) * na,
-                            hipMemcpyHostToDevice, c->stream));
-      HIPCHK(hipMemcpyAsync(didx, h_idx.data(), sizeof(int) * na, hipMemcpyHostToDevice,
-                            c->stream));
-      HIPCHK(pprs_k::pool_assign(d, dstates, didx, na, c->stream));
-      // initial guesses per kind, finest level and start level
+      a_states = put(h_states.data(), sizeof(SlotState) * na);
+      a_slots = put(a_slot.data(), sizeof(int) * na);
       for (int kind : {(int)INIT_IDENTITY, (int)INIT_COMPOSE, (int)INIT_PREPARED,
                        (int)INIT_RESUME}) {
         for (int Lv = m0min; Lv <= Lmax; ++Lv) {
           for (int lv = m0min; lv <= Lv; ++lv) {
             int cnt = 0;
-            int* hs = h_idx.data() + S;        // slots
-            int* h0 = h_idx.data() + 2 * S;    // stage index
-            long long* o0 = h_off.data();      // composed versions
-            long long* o1 = h_off.data() + S;
             for (int k = 0; k < na; ++k) {
               const PoolOp& o = ops[a_op[k]];
               if ((int)o.init != kind || o.start != lv || o.L != Lv) continue;
-              hs[cnt] = a_slot[k];
-              h0[cnt] = o.stage;
-              if (kind == INIT_COMPOSE) {
-                o0[cnt] = ver_off[o.in0];
-                o1[cnt] = ver_off[o.in1];
-              }
-              if (kind == INIT_RESUME) o0[cnt] = ver_off[o.in0];
+              lst[cnt] = a_slot[k];
+              lst_stage[cnt] = o.stage;
+              lst_o0[cnt] = kind == INIT_COMPOSE || kind == INIT_RESUME ? ver_off[o.in0] : 0;
+              lst_o1[cnt] = kind == INIT_COMPOSE ? ver_off[o.in1] : 0;
               ++cnt;
             }
             if (cnt == 0) continue;
-            int* ds = didx + S;
-            int* d0 = didx + 2 * S;
-            HIPCHK(hipMemcpyAsync(ds, hs, sizeof(int) * cnt, hipMemcpyHostToDevice, c->stream));
-            int top = Lv;
-            if (kind == INIT_IDENTITY) {
-              HIPCHK(pprs_k::pool_zero(d, lv, level_n(lv), ds, cnt, c->stream));
-              top = lv;
-            } else if (kind == INIT_COMPOSE) {
-              HIPCHK(hipMemcpyAsync(doff, o0, sizeof(long long) * cnt, hipMemcpyHostToDevice,
-                                    c->stream));
-              HIPCHK(hipMemcpyAsync(doff + S, o1, sizeof(long long) * cnt,
-                                    hipMemcpyHostToDevice, c->stream));
-              HIPCHK(pprs_k::pool_compose(d, Lv, vbuf, doff, doff + S, ds, cnt, c->stream));
-            } else if (kind == INIT_RESUME) {
-              // the resumed result into the first buffer of the level below the start
-              HIPCHK(hipMemcpyAsync(doff, o0, sizeof(long long) * cnt, hipMemcpyHostToDevice,
-                                    c->stream));
-              HIPCHK(pprs_k::pool_copy_off(d, lv - 1, level_n(lv - 1), vbuf, doff, ds, cnt,
-                                           c->stream));
-              top = lv;
-            } else {
-              if (!spec.stage || spec.stage_level < lv || spec.stage_level > Lv)
-                return fail(PPRS_ESTATE, "staged guesses on level %d cannot start level %d",
-                            spec.stage_level, lv);
-              HIPCHK(hipMemcpyAsync(d0, h0, sizeof(int) * cnt, hipMemcpyHostToDevice, c->stream));
-              HIPCHK(pprs_k::pool_copy(d, spec.stage_level, level_n(spec.stage_level),
-                                       spec.stage, spec.stage_stride, d0, ds, cnt, c->stream));
-              top = spec.stage_level;
-            }
-            for (int l = top; l > lv; --l)
-              HIPCHK(pprs_k::pool_restrict(d, l, level_n(l - 1), ds, cnt, c->stream));
-            // the lists are reused by the next group: wait for the uploads to be consumed
-            HIPCHK(hipStreamSynchronize(c->stream));
+            if (kind == INIT_PREPARED &&
+                (!spec.stage || spec.stage_level < lv || spec.stage_level > Lv))
+              return fail(PPRS_ESTATE, "staged guesses on level %d cannot start level %d",
+                          spec.stage_level, lv);
+            InitList il{kind, Lv, lv, cnt, 0, 0, 0, 0};
+            il.slots = put(lst.data(), sizeof(int) * cnt);
+            if (kind == INIT_PREPARED) il.stage = put(lst_stage.data(), sizeof(int) * cnt);
+            if (kind == INIT_COMPOSE || kind == INIT_RESUME)
+              il.o0 = put(lst_o0.data(), sizeof(long long) * cnt);
+            if (kind == INIT_COMPOSE) il.o1 = put(lst_o1.data(), sizeof(long long) * cnt);
+            init_lists.push_back(il);
           }
         }
+      }
+    }
+    if (pack_over) return fail(PPRS_ESTATE, "pool upload exceeds its %zu bytes", pack_cap);
+    if (pack_used > 0)
+      HIPCHK(hipMemcpyAsync(dpack, hpack.data(), pack_used, hipMemcpyHostToDevice, c->stream));
+    pack_used = 0;
+    STCHK(launch_finish());
+    if (na > 0) {
+      HIPCHK(pprs_k::pool_assign(d, (const SlotState*)(dpack + a_states),
+                                 (const int*)(dpack + a_slots), na, c->stream));
+      for (const InitList& il : init_lists) {
+        const int* ds = (const int*)(dpack + il.slots);
+        const int lv = il.lv, Lv = il.Lv, cnt = il.cnt;
+        int top = Lv;
+        if (il.kind == INIT_IDENTITY) {
+          HIPCHK(pprs_k::pool_zero(d, lv, level_n(lv), ds, cnt, c->stream));
+          top = lv;
+        } else if (il.kind == INIT_COMPOSE) {
+          HIPCHK(pprs_k::pool_compose(d, Lv, vbuf, (const long long*)(dpack + il.o0),
+                                      (const long long*)(dpack + il.o1), ds, cnt, c->stream));
+        } else if (il.kind == INIT_RESUME) {
+          // the resumed result into the first buffer of the level below the start
+          HIPCHK(pprs_k::pool_copy_off(d, lv - 1, level_n(lv - 1), vbuf,
+                                       (const long long*)(dpack + il.o0), ds, cnt, c->stream));
+          top = lv;
+        } else {
+          HIPCHK(pprs_k::pool_copy(d, spec.stage_level, level_n(spec.stage_level), spec.stage,
+                                   spec.stage_stride, (const int*)(dpack + il.stage), ds, cnt,
+                                   c->stream));
+          top = spec.stage_level;
+        }
+        for (int l = top; l > lv; --l)
+          HIPCHK(pprs_k::pool_restrict(d, l, level_n(l - 1), ds, cnt, c->stream));
       }
     }
     // 2. step every slot G times
@@ -1129,8 +1172,10 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
     // 3. poll: retire finished slots, release their dependents
     HIPCHK(hipMemcpyAsync(st.data(), hd.state, sizeof(SlotState) * S, hipMemcpyDeviceToHost,
                           c->stream));
-    HIPCHK(hipMemcpyAsync(nodes.data(), hd.node_count, sizeof(long long) * WK_COUNT * S,
-                          hipMemcpyDeviceToHost, c->stream));
+    // the per-kind node counts feed the kernel timing figures only
+    if (c->timing)
+      HIPCHK(hipMemcpyAsync(nodes.data(), hd.node_count, sizeof(long long) * WK_COUNT * S,
+                            hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     if (c->timing) STCHK(tk_collect(c));
     std::vector<int> fin;
@@ -1142,7 +1187,8 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
       // a probe's non-finite energy only decides its judge; it does not fail the call
       bool probe = op.eval_only || op.stop_level() < op.L;
       if (flags_or) *flags_or |= probe ? (st[s].flags & ~PPRS_FLAG_NAN) : st[s].flags;
-      for (int k = 0; k < WK_COUNT; ++k) c->nodes_acc[k] += nodes[(size_t)s * WK_COUNT + k];
+      if (c->timing)
+        for (int k = 0; k < WK_COUNT; ++k) c->nodes_acc[k] += nodes[(size_t)s * WK_COUNT + k];
       for (int l = st[s].coarsest; l <= op.stop_level(); ++l) {
         long long nn = (long long)level_n(l) * level_n(l);
         if (node_steps) *node_steps += nn * st[s].iters[l - st[s].coarsest];
@@ -1167,24 +1213,21 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
         if (--remaining[q] == 0) ready.push(q);
       ++done_ops;
     }
-    // copy the finished results out (grouped by finest level) before their slots are reused
+    // the finished results' lists (grouped by finest level) open the next upload; their slots
+    // are free for the registrations that upload starts (pool_finish runs before pool_assign)
     for (int Lv = m0min; Lv <= Lmax && !fin.empty(); ++Lv) {
       int cnt = 0;
-      int* fs = h_idx.data() + 3 * S;
-      long long* fo = h_off.data() + 2 * S;
       for (int s : fin)
         if (ops[slot_op[s]].stop_level() == Lv) {
-          fs[cnt] = s;
-          fo[cnt] = ver_off[ops[slot_op[s]].out];
+          lst[cnt] = s;
+          lst_o0[cnt] = ver_off[ops[slot_op[s]].out];
           ++cnt;
         }
       if (cnt == 0) continue;
-      HIPCHK(hipMemcpyAsync(didx + 3 * S, fs, sizeof(int) * cnt, hipMemcpyHostToDevice,
-                            c->stream));
-      HIPCHK(hipMemcpyAsync(doff + 2 * S, fo, sizeof(long long) * cnt, hipMemcpyHostToDevice,
-                            c->stream));
-      HIPCHK(pprs_k::pool_finish(d, Lv, didx + 3 * S, doff + 2 * S, cnt, vbuf, c->stream));
-      HIPCHK(hipStreamSynchronize(c->stream));
+      FinishList f{Lv, cnt, 0, 0};
+      f.slots = put(lst.data(), sizeof(int) * cnt);
+      f.outs = put(lst_o0.data(), sizeof(long long) * cnt);
+      finish_lists.push_back(f);
     }
     for (int s : fin) {
       slot_op[s] = -1;
@@ -1193,6 +1236,12 @@ pprs_status run_pool(pprs_ctx* c, std::vector<PoolOp>& ops, int S, float* vbuf,
     if (done_steps > max_steps)
       return fail(PPRS_ESTATE, "slot pool did not finish within %lld steps", max_steps);
   }
+  // the last poll's results
+  if (pack_over) return fail(PPRS_ESTATE, "pool upload exceeds its %zu bytes", pack_cap);
+  if (pack_used > 0)
+    HIPCHK(hipMemcpyAsync(dpack, hpack.data(), pack_used, hipMemcpyHostToDevice, c->stream));
+  pack_used = 0;
+  STCHK(launch_finish());
   HIPCHK(hipStreamSynchronize(c->stream));
   if (c->log) {
     double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
@@ -1282,14 +1331,14 @@ pprs_status run_program(const ScanProg& sp, int M, int ver0, Reg reg,
 // count its pool takes and the slot layout (in hd). Mirrors run_series_set for one series.
 struct SeriesWs {
   FrameBytes frames{};
-  size_t elems = 0, pool_idx = 0, pool_off = 0, pool_states = 0, tmp = 0;
+  size_t elems = 0, pool_pack = 0, tmp = 0;
   SlotBytes slots{};
   int n_slots = 0;
   bool any = false;  // N > 1: the call allocates anything at all
   size_t total() const {
     if (!any) return 0;
     return frames.frames + frames.frame_off + frames.rsum + frames.fr_part + frames.fr_ms +
-           frames.tcoef + elems + pool_idx + pool_off + pool_states + tmp + slots.state + slots.ubuf +
+           frames.tcoef + elems + pool_pack + tmp + slots.state + slots.ubuf +
            slots.dbuf + slots.gbuf + slots.zbuf + slots.partial + slots.nodecount +
            slots.coef + slots.list_slots + slots.list_off + slots.lists + slots.desc +
            slots.opidx;
@@ -1314,9 +1363,7 @@ pprs_status series_workspace(int N, int L, int m0, const pprs_params* p, int poo
   w.slots = slot_layout(hd, slots, L, m0, true);
   int S = std::max(1, std::min(slots, M + n_ops));
   w.n_slots = slots;
-  w.pool_idx = sizeof(int) * 4 * (size_t)S;
-  w.pool_off = sizeof(long long) * 3 * (size_t)S;
-  w.pool_states = sizeof(SlotState) * (size_t)S;
+  w.pool_pack = pool_pack_bytes(S);
   w.tmp = sizeof(long long) * M;
   return PPRS_OK;
 }
@@ -1496,9 +1543,7 @@ pprs_status pprs_reserve_workspace(pprs_ctx* c, int N, int H, int W, const pprs_
   STCHK(ensure(c->fr_ms, w.frames.fr_ms));
   STCHK(ensure(c->tcoef, w.frames.tcoef));
   STCHK(ensure(c->elems, w.elems));
-  STCHK(ensure(c->pool_idx, w.pool_idx));
-  STCHK(ensure(c->pool_off, w.pool_off));
-  STCHK(ensure(c->pool_states, w.pool_states));
+  STCHK(ensure(c->pool_pack, w.pool_pack));
   STCHK(ensure(c->tmp, w.tmp));
   STCHK(ensure_slots(c, w.n_slots, L, m0, params->beta));
   return PPRS_OK;
