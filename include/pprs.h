@@ -262,7 +262,7 @@ typedef struct {
   int grid_grad;     /* workgroups of the gradient kernel (default 8192) */
   int grid_smooth;   /* workgroups of the metric-solve kernels (default 8192) */
   int grid_prolong;  /* unused: the prolongations run inside the gradient launch */
-  int tile_grad;     /* gradient tile shape: 0 = default (64x16), 1 = 64x8, 2 = 128x4,
+  int tile_grad;     /* gradient tile shape: 0 = default (64x8), 1 = 64x8, 2 = 128x4,
                         3 = 64x16, 4 = 32x16 nodes */
   int smooth_lines;  /* columns per workgroup of the column solves: 8, 16 (default) or 32 */
   int ladder_rungs;  /* step sizes evaluated per line-search pass: 1, 2, 3, 5 or 7; 0 = one

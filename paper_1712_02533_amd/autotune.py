@@ -17,7 +17,7 @@ import time
 
 CANDIDATES = {
     "ladder_rungs": [2, 1],
-    "tile_grad": [0, 4, 1, 2],
+    "tile_grad": [0, 3, 4, 2],
     "smooth_lines": [32, 8, 16],
     "pool_group": [16, 32, 8],
     "grid_grad": [8192, 4096, 2048],
