@@ -7,9 +7,11 @@
 //   L1 2->64 stride 2 (64^2)   L2 64->128 stride 2 (32^2)   L3 128->256 stride 2 (16^2)
 //   L4 [up2(L3), L2] 384->128 (32^2)   L5 [up2(L4), L1] 192->64 (64^2)
 //   L6 [up2(L5), input] 66->2 (128^2, linear)
-// Activations are NHWC. A convolution is im2col + an MFMA GEMM (v_mfma_f32_16x16x32_bf16);
-// its weights are [Cout][Kp] with k = (dy * 3 + dx) * Cin + ci, Kp = 9 Cin rounded up to 32
-// (L1 to 64), padded with zeros. L6 (2 output channels) uses direct FP32 kernels.
+// Activations are NHWC. Weights are [Cout][Kp] with k = (dy * 3 + dx) * Cin + ci, Kp = 9 Cin
+// rounded up to 32 (L1 to 64), padded with zeros. L2-L5 run as fused implicit-GEMM
+// convolutions on MFMAs (v_mfma_f32_16x16x32_bf16); L1 (2 input channels) and L6 (2 output
+// channels, its upsampled input folded into the weights) as direct FP32 kernels. The backward
+// pass uses im2col + MFMA GEMMs for the weight gradients.
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 #include <ctype.h>
@@ -380,16 +382,6 @@ __global__ void k_upcat_bwd(const float* __restrict__ dU, int C1, int C2, int Bn
   }
 }
 
-// out_bf16[m][n] = relu(Z[m][n] + bias[n]) (N columns).
-__global__ void k_bias_relu(const float* __restrict__ Z, const float* __restrict__ bias,
-                            long long M, int N, bf16* __restrict__ out) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < M * N;
-       i += (long long)gridDim.x * blockDim.x) {
-    float v = Z[i] + bias[i % N];
-    out[i] = (bf16)(v > 0.f ? v : 0.f);
-  }
-}
-
 // dZ = dA * (A > 0) as bf16 (A is the layer's ReLU output).
 __global__ void k_relu_bwd(const float* __restrict__ dA, const bf16* __restrict__ A,
                            long long count, bf16* __restrict__ dZ) {
@@ -444,51 +436,147 @@ __global__ void k_f32_to_bf16(const float* __restrict__ x, long long count,
 // Last layer (66 -> 2 channels, stride 1), FP32 direct kernels. W6 is [2][9][66] fp32 (from the
 // bf16 copy), bias b6[2].
 
-// Last layer read straight from its sources: input channels 0..63 are the 2x upsampled L5
-// output a5 [B][64][64][64], channels 64, 65 the network input x0 [B][128][128][2]; the
-// 66 x 9 x 2 weights sit in LDS. One thread per output pixel, 16-byte loads of a5.
+// Last layer read straight from its sources. Channels 0..63 are the nearest 2x upsampling of
+// the L5 output a5 [B][64][64][64]: output pixel (2Y + py, 2X + px) sees through its 3x3 taps
+// only the 2 x 2 source pixels (Y - 1 + py + i, X - 1 + px + j), i, j in {0, 1} (tap rows
+// {0} and {1, 2} land on source rows Y - 1 and Y when py = 0, {0, 1} and {2} on Y and Y + 1
+// when py = 1; columns alike), so the taps that land on one source pixel are summed into the
+// folded weights W6f [parity py px][i][j][output][64] (k_w6_prep): 4 source pixels of 64
+// channels instead of 9. Channels 64, 65 are the network input x0 [B][128][128][2] (9 taps,
+// weights W6 [2][9][66]). One workgroup per (sample, parity, 4 source rows of 64), so a wave's
+// weights are uniform; 16-byte loads of a5.
 __global__ void __launch_bounds__(256) k_l6_fused(const bf16* __restrict__ a5,
                                                   const bf16* __restrict__ x0,
                                                   const float* __restrict__ W6,
+                                                  const float* __restrict__ W6f,
                                                   const float* __restrict__ b6, int Bn,
                                                   float* __restrict__ Y) {
   constexpr int C = 66;
-  __shared__ float w[2 * 9 * C];
-  for (int i = threadIdx.x; i < 2 * 9 * C; i += blockDim.x) w[i] = W6[i];
-  __syncthreads();
-  long long total = (long long)Bn * 128 * 128;
-  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < total;
-       p += (long long)gridDim.x * blockDim.x) {
-    int x = (int)(p & 127), y = (int)((p >> 7) & 127), b = (int)(p >> 14);
+  const int nblk = Bn * 64;
+  for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int b = blk >> 6, par = (blk >> 4) & 3, py = par >> 1, px = par & 1;
+    const int ys = (blk & 15) * 4 + (threadIdx.x >> 6), xs = threadIdx.x & 63;
+    const int y = 2 * ys + py, x = 2 * xs + px;
     float s0 = b6[0], s1 = b6[1];
-    for (int tap = 0; tap < 9; ++tap) {
-      int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
-      if (yy < 0 || yy >= 128 || xx < 0 || xx >= 128) continue;
-      const uint4* u = (const uint4*)(a5 + (((size_t)b * 64 + (yy >> 1)) * 64 + (xx >> 1)) * 64);
-      const float* w0 = w + tap * C;
-      const float* w1 = w + 9 * C + tap * C;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        uint4 v = u[q];
-        unsigned int h[4] = {v.x, v.y, v.z, v.w};
+    for (int i = 0; i < 2; ++i) {
+      const int sy = ys - 1 + py + i;
+      if (sy < 0 || sy >= 64) continue;  // uniform over the wave (one source row)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          float lo = __uint_as_float(h[i] << 16), hi = __uint_as_float(h[i] & 0xffff0000u);
-          s0 = fmaf(w0[8 * q + 2 * i], lo, s0);
-          s1 = fmaf(w1[8 * q + 2 * i], lo, s1);
-          s0 = fmaf(w0[8 * q + 2 * i + 1], hi, s0);
-          s1 = fmaf(w1[8 * q + 2 * i + 1], hi, s1);
+      for (int j = 0; j < 2; ++j) {
+        const int sx = xs - 1 + px + j;
+        const bool ok = sx >= 0 && sx < 64;
+        const uint4* u = (const uint4*)(a5 + (((size_t)b * 64 + sy) * 64 + (ok ? sx : 0)) * 64);
+        const float* w0 = W6f + (((par * 2 + i) * 2 + j) * 2) * 64;
+        const float* w1 = w0 + 64;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          uint4 v = ok ? u[q] : make_uint4(0u, 0u, 0u, 0u);
+          unsigned int h[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            float lo = __uint_as_float(h[k] << 16), hi = __uint_as_float(h[k] & 0xffff0000u);
+            s0 = fmaf(w0[8 * q + 2 * k], lo, s0);
+            s1 = fmaf(w1[8 * q + 2 * k], lo, s1);
+            s0 = fmaf(w0[8 * q + 2 * k + 1], hi, s0);
+            s1 = fmaf(w1[8 * q + 2 * k + 1], hi, s1);
+          }
         }
       }
-      const bf16* xi = x0 + (((size_t)b * 128 + yy) * 128 + xx) * 2;
-      float f0 = (float)xi[0], f1 = (float)xi[1];
-      s0 = fmaf(w0[64], f0, s0);
-      s1 = fmaf(w1[64], f0, s1);
-      s0 = fmaf(w0[65], f1, s0);
-      s1 = fmaf(w1[65], f1, s1);
     }
-    Y[p * 2] = s0;
-    Y[p * 2 + 1] = s1;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+      if (yy < 0 || yy >= 128 || xx < 0 || xx >= 128) continue;
+      const bf16* xi = x0 + (((size_t)b * 128 + yy) * 128 + xx) * 2;
+      const float f0 = (float)xi[0], f1 = (float)xi[1];
+      s0 = fmaf(W6[tap * C + 64], f0, s0);
+      s1 = fmaf(W6[9 * C + tap * C + 64], f0, s1);
+      s0 = fmaf(W6[tap * C + 65], f1, s0);
+      s1 = fmaf(W6[9 * C + tap * C + 65], f1, s1);
+    }
+    const size_t o = (((size_t)b * 128 + y) * 128 + x) * 2;
+    Y[o] = s0;
+    Y[o + 1] = s1;
+  }
+}
+
+// FP32 copies of the last layer's weights from the BF16 copy: W6 [2][9][66] (the backward
+// pass's) and the folded W6f of k_l6_fused, each entry the sum, in tap order, of the taps that
+// land on its source pixel. One workgroup.
+__global__ void __launch_bounds__(256) k_w6_prep(const bf16* __restrict__ wb6,
+                                                 float* __restrict__ W6,
+                                                 float* __restrict__ W6f) {
+  constexpr int C = 66;
+  for (int k = threadIdx.x; k < 2 * 9 * C; k += blockDim.x) W6[k] = (float)wb6[k];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 4 * 2 * 2 * 2 * 64; e += blockDim.x) {
+    const int c = e & 63, o = (e >> 6) & 1, j = (e >> 7) & 1, i = (e >> 8) & 1, par = e >> 9;
+    const int py = par >> 1, px = par & 1;
+    // tap rows (columns) landing on source row (column) offset i (j) for parity py (px)
+    const int r0 = py == 0 ? (i == 0 ? 0 : 1) : (i == 0 ? 0 : 2);
+    const int r1 = py == 0 ? (i == 0 ? 0 : 2) : (i == 0 ? 1 : 2);
+    const int c0 = px == 0 ? (j == 0 ? 0 : 1) : (j == 0 ? 0 : 2);
+    const int c1 = px == 0 ? (j == 0 ? 0 : 2) : (j == 0 ? 1 : 2);
+    float acc = 0.f;
+    for (int ty = r0; ty <= r1; ++ty)
+      for (int tx = c0; tx <= c1; ++tx) acc += W6[o * 9 * C + (ty * 3 + tx) * C + c];
+    W6f[e] = acc;
+  }
+}
+
+// First layer (2 -> 64 channels, stride 2, 128^2 -> 64^2) straight from the input x0
+// [B][128][128][2]: one thread per output pixel holds its 18 inputs (k = tap * 2 + c); the
+// weights (FP32 from the BF16 copy, [k][64]) and the bias sit in LDS, read four channels at a
+// time at one address per wave; FP32 sums in k order, then bias and ReLU; the 64 BF16 outputs
+// leave as eight 16-byte stores (NHWC).
+__global__ void __launch_bounds__(256) k_l1_direct(const bf16* __restrict__ x0,
+                                                   const bf16* __restrict__ W, int Kp,
+                                                   const float* __restrict__ bias, int Bn,
+                                                   bf16* __restrict__ out) {
+  __shared__ __attribute__((aligned(16))) float ws[18][64];
+  __shared__ __attribute__((aligned(16))) float bs[64];
+  for (int e = threadIdx.x; e < 18 * 64; e += blockDim.x) {
+    const int co = e / 18, k = e - co * 18;
+    ws[k][co] = (float)W[co * Kp + k];
+  }
+  if (threadIdx.x < 64) bs[threadIdx.x] = bias[threadIdx.x];
+  __syncthreads();
+  const long long total = (long long)Bn * 64 * 64;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < total;
+       p += (long long)gridDim.x * blockDim.x) {
+    const int ox = (int)(p & 63), oy = (int)((p >> 6) & 63);
+    const long long b = p >> 12;
+    float in[18];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int iy = 2 * oy + tap / 3 - 1, ix = 2 * ox + tap % 3 - 1;
+      const bool ok = iy >= 0 && iy < 128 && ix >= 0 && ix < 128;
+      unsigned int v = ok ? *(const unsigned int*)(x0 + ((b * 128 + iy) * 128 + ix) * 2) : 0u;
+      in[2 * tap] = __uint_as_float(v << 16);
+      in[2 * tap + 1] = __uint_as_float(v & 0xffff0000u);
+    }
+    uint2* dst = (uint2*)(out + p * 64);
+#pragma unroll 1
+    for (int g = 0; g < 16; ++g) {  // output channels 4g .. 4g + 3
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < 18; ++k) {
+        const f32x4 w = *(const f32x4*)&ws[k][4 * g];
+        acc[0] = fmaf(w[0], in[k], acc[0]);
+        acc[1] = fmaf(w[1], in[k], acc[1]);
+        acc[2] = fmaf(w[2], in[k], acc[2]);
+        acc[3] = fmaf(w[3], in[k], acc[3]);
+      }
+      const f32x4 bb = *(const f32x4*)&bs[4 * g];
+      unsigned int h[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float v = acc[r] + bb[r];
+        h[r] = __builtin_bit_cast(unsigned short, (bf16)(v > 0.f ? v : 0.f));
+      }
+      dst[g] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+    }
   }
 }
 
@@ -706,7 +794,7 @@ struct Model {
   bf16 *x0 = nullptr, *a[5] = {nullptr}, *u4 = nullptr, *u5 = nullptr, *u6 = nullptr,
        *col = nullptr, *dzb = nullptr;
   float *z = nullptr, *y = nullptr, *dy = nullptr, *dcol = nullptr, *du = nullptr,
-        *da[5] = {nullptr}, *part = nullptr, *w6 = nullptr;
+        *da[5] = {nullptr}, *part = nullptr, *w6 = nullptr, *w6f = nullptr;
   double* lpart = nullptr;
   size_t part_floats = 0;
 };
@@ -872,13 +960,10 @@ static pprs_status forward(Model& M, const float* x, int B, bool train) {
   long long P128 = (long long)B * 128 * 128;
   hipLaunchKernelGGL(k_f32_to_bf16, dim3(grid1d(P128 * 2)), dim3(kBlock), 0, st, x, P128 * 2, M.x0);
   {
-    // L1 (2 input channels): im2col + GEMM
+    // L1 (2 input channels): a direct kernel (18 products per output channel)
     const Layer& y = M.L[0];
     long long pix = (long long)B * y.hout * y.hout;
-    hipLaunchKernelGGL(k_im2col, dim3(grid1d(pix * y.kp)), dim3(kBlock), 0, st, M.x0, B, y.hin, y.hin, y.cin, y.stride, y.kp, M.col);
-    pprs_status s = gemm(M, false, false, M.col, y.kp, M.wb + y.woff, y.kp, M.z, y.cout, (int)pix, y.cout, y.kp, 1);
-    if (s != PPRS_OK) return s;
-    hipLaunchKernelGGL(k_bias_relu, dim3(grid1d(pix * y.cout)), dim3(kBlock), 0, st, M.z, M.w + y.boff, pix, y.cout, M.a[0]);
+    hipLaunchKernelGGL(k_l1_direct, dim3(grid1d(pix)), dim3(kBlock), 0, st, M.x0, M.wb + y.woff, y.kp, M.w + y.boff, B, M.a[0]);
   }
   for (int l = 1; l < 5; ++l) {
     pprs_status s = conv_fused(M, l, B);
@@ -893,7 +978,7 @@ static pprs_status forward(Model& M, const float* x, int B, bool train) {
   const Layer& y6 = M.L[5];
   if (train)
     hipLaunchKernelGGL(k_upcat, dim3(grid1d(P128 * 66)), dim3(kBlock), 0, st, M.a[4], 64, M.x0, 2, B, 128, 128, M.u6);
-  hipLaunchKernelGGL(k_l6_fused, dim3(grid1d(P128)), dim3(kBlock), 0, st, M.a[4], M.x0, M.w6, M.w + y6.boff, B, M.y);
+  hipLaunchKernelGGL(k_l6_fused, dim3(B * 64), dim3(kBlock), 0, st, M.a[4], M.x0, M.w6, M.w6f, M.w + y6.boff, B, M.y);
   CHK(hipGetLastError());
   return PPRS_OK;
 }
@@ -901,16 +986,8 @@ static pprs_status forward(Model& M, const float* x, int B, bool train) {
 // fp32 view of the L6 weights from the bf16 copy (so every layer computes with bf16 weights).
 static pprs_status refresh_w6(Model& M) {
   const Layer& y6 = M.L[5];
-  std::vector<uint16_t> hb((size_t)y6.cout * y6.kp);
-  CHK(hipMemcpyAsync(hb.data(), M.wb + y6.woff, hb.size() * 2, hipMemcpyDeviceToHost, M.stream));
-  CHK(hipStreamSynchronize(M.stream));
-  std::vector<float> hf(hb.size());
-  for (size_t i = 0; i < hb.size(); ++i) {
-    uint32_t u = (uint32_t)hb[i] << 16;
-    memcpy(&hf[i], &u, 4);
-  }
-  CHK(hipMemcpyAsync(M.w6, hf.data(), hf.size() * 4, hipMemcpyHostToDevice, M.stream));
-  CHK(hipStreamSynchronize(M.stream));
+  hipLaunchKernelGGL(k_w6_prep, dim3(1), dim3(kBlock), 0, M.stream, M.wb + y6.woff, M.w6, M.w6f);
+  CHK(hipGetLastError());
   return PPRS_OK;
 }
 
@@ -1201,6 +1278,7 @@ pprs_status pprs_cnn_create(pprs_cnn** out, int device, void* stream, unsigned l
   if (e == hipSuccess) e = hipMalloc(&M.g, sizeof(float) * M.n_params);
   if (e == hipSuccess) e = hipMalloc(&M.wb, sizeof(bf16) * M.n_params);
   if (e == hipSuccess) e = hipMalloc(&M.w6, sizeof(float) * M.L[5].cout * M.L[5].kp);
+  if (e == hipSuccess) e = hipMalloc(&M.w6f, sizeof(float) * 4 * 2 * 2 * 2 * 64);
   if (e != hipSuccess) {
     delete c;
     return cfail(PPRS_ENOMEM, "cnn allocation failed");
@@ -1215,8 +1293,8 @@ void pprs_cnn_destroy(pprs_cnn* c) {
   Model& M = c->M;
   (void)hipSetDevice(M.device);
   (void)hipStreamSynchronize(M.stream);
-  void* ptrs[] = {M.w, M.m, M.v, M.g, M.wb, M.w6, M.x0, M.a[0], M.a[1], M.a[2], M.a[3], M.a[4],
-                  M.u4, M.u5, M.u6, M.col, M.dzb, M.z, M.y, M.dy, M.dcol, M.du, M.da[0],
+  void* ptrs[] = {M.w, M.m, M.v, M.g, M.wb, M.w6, M.w6f, M.x0, M.a[0], M.a[1], M.a[2], M.a[3],
+                  M.a[4], M.u4, M.u5, M.u6, M.col, M.dzb, M.z, M.y, M.dy, M.dcol, M.du, M.da[0],
                   M.da[1], M.da[2], M.da[3], M.da[4], M.part, M.lpart, M.wflip};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
