@@ -580,51 +580,79 @@ __global__ void __launch_bounds__(256) k_l1_direct(const bf16* __restrict__ x0,
   }
 }
 
-// dU[b][y][x][c] = sum over taps of W6[o][tap][c] dY at the output whose patch holds (y, x).
-__global__ void k_l6_bwd_data(const float* __restrict__ dY, const float* __restrict__ W6,
-                              int Bn, int H, int Wd, int C, float* __restrict__ dU) {
-  long long total = (long long)Bn * H * Wd * C;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-       i += (long long)gridDim.x * blockDim.x) {
-    int c = (int)(i % C);
-    long long p = i / C;
-    int x = (int)(p % Wd), y = (int)((p / Wd) % H), b = (int)(p / ((long long)Wd * H));
+// Data gradient of the last layer for its upsampled input, straight onto the L5 output grid
+// (the adjoint of k_l6_fused's folded product, which also sums the four upsampled copies):
+// source pixel (Y, X) feeds the outputs (2 Ys + py, 2 Xs + px) with Ys = Y + 1 - py - i and
+// Xs = X + 1 - px - j through W6f[py px][i][j][o][c] (the output rows 2Y - 1 .. 2Y + 2 and the
+// columns alike, 2 outputs each). One wave per source pixel, one lane per channel: the dY
+// values of a wave are the same for every lane; the weights sit in LDS.
+__global__ void __launch_bounds__(256) k_l6_bwd_a5(const float* __restrict__ dY,
+                                                   const float* __restrict__ W6f, int Bn,
+                                                   float* __restrict__ dA5) {
+  __shared__ float w[4 * 2 * 2 * 2 * 64];
+  for (int e = threadIdx.x; e < 4 * 2 * 2 * 2 * 64; e += blockDim.x) w[e] = W6f[e];
+  __syncthreads();
+  const int c = threadIdx.x & 63;
+  const long long npix = (long long)Bn * 64 * 64;
+  const long long step = ((long long)gridDim.x * blockDim.x) >> 6;
+  for (long long p = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6; p < npix;
+       p += step) {
+    const int X = (int)(p & 63), Y = (int)((p >> 6) & 63);
+    const long long b = p >> 12;
     float s = 0.f;
-    for (int tap = 0; tap < 9; ++tap) {
-      int oy = y + 1 - tap / 3, ox = x + 1 - tap % 3;
-      if (oy < 0 || oy >= H || ox < 0 || ox >= Wd) continue;
-      const float* g = dY + (((size_t)b * H + oy) * Wd + ox) * 2;
-      s = fmaf(W6[tap * C + c], g[0], s);
-      s = fmaf(W6[9 * C + tap * C + c], g[1], s);
-    }
-    dU[i] = s;
+#pragma unroll
+    for (int py = 0; py < 2; ++py)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int y = 2 * (Y + 1 - py - i) + py;
+        if (y < 0 || y >= 128) continue;
+#pragma unroll
+        for (int px = 0; px < 2; ++px)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const int x = 2 * (X + 1 - px - j) + px;
+            if (x < 0 || x >= 128) continue;
+            const float* g = dY + ((b * 128 + y) * 128 + x) * 2;
+            const float* wp = w + ((((py * 2 + px) * 2 + i) * 2 + j) * 2) * 64 + c;
+            s = fmaf(wp[0], g[0], s);
+            s = fmaf(wp[64], g[1], s);
+          }
+      }
+    dA5[p * 64 + c] = s;
   }
 }
 
-
 // L6 weight and bias gradients by tiles: one block per 16x16 tile of output positions of one
-// image. The tile's 18x18 halo of U (zero outside the image, C channels) and its dY are staged
-// in LDS; each thread sums, over the tile's 256 positions in order, dY(p, o) U(p + tap, c) for
-// both outputs o of its (tap, c) pairs, or dY(p, o) for the bias. Per-block partials
+// 128 x 128 image. The tile's 18x18 halo of the layer input U (zero outside the image: channels
+// 0..63 the 2x upsampled L5 output a5 [B][64][64][64], read through the halving of the
+// position; 64, 65 the network input x0 [B][128][128][2]) and its dY are staged in LDS; each
+// thread sums, over the tile's 256 positions in order, dY(p, o) U(p + tap, c) for both
+// outputs o of its (tap, c) pairs, or dY(p, o) for the bias. Per-block partials
 // [block][2 * 9 * C + 2] (weights o-major as in the layer, then the two biases), summed over
-// blocks in a fixed order by k_colsum_final. H and Wd are multiples of 16; C == L6C.
+// blocks in a fixed order by k_colsum_final. C == L6C.
 constexpr int L6T = 16, L6H = L6T + 2, L6C = 66;
 __global__ void __launch_bounds__(256) k_l6_bwd_w_tile(const float* __restrict__ dY,
-                                                       const bf16* __restrict__ U, int H, int Wd,
+                                                       const bf16* __restrict__ a5,
+                                                       const bf16* __restrict__ x0,
                                                        float* __restrict__ part) {
+  constexpr int H = 128, Wd = 128;
   __shared__ bf16 sU[L6H * L6H * L6C];
   __shared__ float2 sY[L6T * L6T];
   const int tx_n = Wd / L6T, per_img = tx_n * (H / L6T);
   const int b = blockIdx.x / per_img, tt = blockIdx.x % per_img;
-  const int y0 = (tt / tx_n) * L6T, x0 = (tt % tx_n) * L6T;
+  const int ty0 = (tt / tx_n) * L6T, tx0 = (tt % tx_n) * L6T;
   for (int i = threadIdx.x; i < L6H * L6H * L6C; i += blockDim.x) {
     int c = i % L6C, pix = i / L6C;
-    int y = y0 + pix / L6H - 1, x = x0 + pix % L6H - 1;
+    int y = ty0 + pix / L6H - 1, x = tx0 + pix % L6H - 1;
     bool in = y >= 0 && y < H && x >= 0 && x < Wd;
-    sU[i] = in ? U[(((size_t)b * H + y) * Wd + x) * L6C + c] : (bf16)0.f;
+    bf16 v = (bf16)0.f;
+    if (in)
+      v = c < 64 ? a5[(((size_t)b * 64 + (y >> 1)) * 64 + (x >> 1)) * 64 + c]
+                 : x0[(((size_t)b * H + y) * Wd + x) * 2 + (c - 64)];
+    sU[i] = v;
   }
   for (int p = threadIdx.x; p < L6T * L6T; p += blockDim.x) {
-    size_t q = ((size_t)b * H + y0 + p / L6T) * Wd + x0 + p % L6T;
+    size_t q = ((size_t)b * H + ty0 + p / L6T) * Wd + tx0 + p % L6T;
     sY[p] = make_float2(dY[2 * q], dY[2 * q + 1]);
   }
   __syncthreads();
@@ -791,7 +819,7 @@ struct Model {
   long long step = 0;
   int cap_b = 0;
   // activations and workspaces (sized for cap_b)
-  bf16 *x0 = nullptr, *a[5] = {nullptr}, *u4 = nullptr, *u5 = nullptr, *u6 = nullptr,
+  bf16 *x0 = nullptr, *a[5] = {nullptr}, *u4 = nullptr, *u5 = nullptr,
        *col = nullptr, *dzb = nullptr;
   float *z = nullptr, *y = nullptr, *dy = nullptr, *dcol = nullptr, *du = nullptr,
         *da[5] = {nullptr}, *part = nullptr, *w6 = nullptr, *w6f = nullptr;
@@ -878,7 +906,7 @@ static void define_layers(Model& M) {
 
 static pprs_status alloc_batch(Model& M, int B) {
   if (B <= M.cap_b) return PPRS_OK;
-  void* ptrs[] = {M.x0, M.a[0], M.a[1], M.a[2], M.a[3], M.a[4], M.u4, M.u5, M.u6, M.col, M.dzb,
+  void* ptrs[] = {M.x0, M.a[0], M.a[1], M.a[2], M.a[3], M.a[4], M.u4, M.u5, M.col, M.dzb,
                   M.z, M.y, M.dy, M.dcol, M.du, M.da[0], M.da[1], M.da[2], M.da[3], M.da[4],
                   M.part, M.lpart, M.wflip};
   for (void* p : ptrs)
@@ -899,7 +927,6 @@ static pprs_status alloc_batch(Model& M, int B) {
   CHK(hipMalloc(&M.a[4], sizeof(bf16) * P64 * 64));
   CHK(hipMalloc(&M.u4, sizeof(bf16) * P32 * 384));
   CHK(hipMalloc(&M.u5, sizeof(bf16) * P64 * 192));
-  CHK(hipMalloc(&M.u6, sizeof(bf16) * P128 * 66));
   long long wf = 0;
   for (int l = 3; l < 5; ++l) wf = std::max(wf, (long long)M.L[l].cin * 9 * M.L[l].cout);
   CHK(hipMalloc(&M.wflip, sizeof(bf16) * wf));
@@ -976,8 +1003,6 @@ static pprs_status forward(Model& M, const float* x, int B, bool train) {
   }
   // L6
   const Layer& y6 = M.L[5];
-  if (train)
-    hipLaunchKernelGGL(k_upcat, dim3(grid1d(P128 * 66)), dim3(kBlock), 0, st, M.a[4], 64, M.x0, 2, B, 128, 128, M.u6);
   hipLaunchKernelGGL(k_l6_fused, dim3(B * 64), dim3(kBlock), 0, st, M.a[4], M.x0, M.w6, M.w6f, M.w + y6.boff, B, M.y);
   CHK(hipGetLastError());
   return PPRS_OK;
@@ -1006,12 +1031,11 @@ static pprs_status backward(Model& M, const float* target, int B, int margin, do
   const Layer& y6 = M.L[5];
   {
     int nw = 2 * 9 * 66 + 2, chunks = B * (128 / L6T) * (128 / L6T);
-    hipLaunchKernelGGL(k_l6_bwd_w_tile, dim3(chunks), dim3(256), 0, st, M.dy, M.u6, 128, 128, M.part);
+    hipLaunchKernelGGL(k_l6_bwd_w_tile, dim3(chunks), dim3(256), 0, st, M.dy, M.a[4], M.x0, M.part);
     // weights [2][9*66] then bias [2] are contiguous at woff: columns 0..nw-1 map to them
     hipLaunchKernelGGL(k_colsum_final, dim3(nw), dim3(kBlock), 0, st, M.part, nw, chunks, M.g + y6.woff);
-    hipLaunchKernelGGL(k_l6_bwd_data, dim3(grid1d(P128 * 66)), dim3(kBlock), 0, st, M.dy, M.w6, B, 128, 128, 66, M.du);
-    // split dU6 into d a[4] (upsampled part); the input part needs no gradient
-    hipLaunchKernelGGL(k_upcat_bwd, dim3(grid1d(P128 / 4 * 64)), dim3(kBlock), 0, st, M.du, 64, 2, B, 128, 128, M.da[4], (float*)nullptr, 0);
+    // d a[4] through the folded weights (the input part needs no gradient)
+    hipLaunchKernelGGL(k_l6_bwd_a5, dim3(grid1d(P128 / 4 * 64)), dim3(kBlock), 0, st, M.dy, M.w6f, B, M.da[4]);
   }
   CHK(hipGetLastError());
   // L5 .. L1
@@ -1294,7 +1318,7 @@ void pprs_cnn_destroy(pprs_cnn* c) {
   (void)hipSetDevice(M.device);
   (void)hipStreamSynchronize(M.stream);
   void* ptrs[] = {M.w, M.m, M.v, M.g, M.wb, M.w6, M.w6f, M.x0, M.a[0], M.a[1], M.a[2], M.a[3],
-                  M.a[4], M.u4, M.u5, M.u6, M.col, M.dzb, M.z, M.y, M.dy, M.dcol, M.du, M.da[0],
+                  M.a[4], M.u4, M.u5, M.col, M.dzb, M.z, M.y, M.dy, M.dcol, M.du, M.da[0],
                   M.da[1], M.da[2], M.da[3], M.da[4], M.part, M.lpart, M.wflip};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
