@@ -123,11 +123,18 @@ constexpr int CV_BM = 128, CV_BK = 64, CV_LD = CV_BK + 8;
 
 // DGRAD: the same product for a data gradient (input dZ, weights flipped and transposed):
 // no bias or ReLU, FP32 output (`out` is then a float*).
-template <int BN, bool UP, bool DGRAD = false>
+// FOLD (with UP): the upsampled source is read at its own resolution. Output pixel
+// (2Y + py, 2X + px) sees through its 3x3 taps only the 2 x 2 source pixels
+// (Y - 1 + py + i, X - 1 + px + j), so the taps landing on one source pixel are summed into
+// folded weights, one matrix per output parity (k_fold_weights: [4][Cout][Kp'], k' = (2i + j) C0
+// + c for the upsampled part, then 4 C0 + tap C1 + c for the skip part, Kp' = 4 C0 + 9 C1).
+// The pixels of a 128-row tile share one parity: m = ((parity B + b) (H/2) + Y) (H/2) + X.
+template <int BN, bool UP, bool DGRAD = false, bool FOLD = false>
 __global__ void __launch_bounds__(256, 2) k_conv_fwd(
     const bf16* __restrict__ src0, int C0, const bf16* __restrict__ src1, int C1, int Hin,
     int stride, const bf16* __restrict__ Wt, int Kp, const float* __restrict__ bias, int Cout,
     void* __restrict__ out_) {
+  static_assert(!FOLD || (UP && !DGRAD), "folding is for the upsampling layers' forward");
   constexpr int WN = BN / 2;          // columns per wave
   constexpr int TN = WN / 16;         // 16-wide MFMA tiles per wave along n
   constexpr int B_PIECES = BN * 8 / 256;
@@ -135,39 +142,74 @@ __global__ void __launch_bounds__(256, 2) k_conv_fwd(
   __shared__ __attribute__((aligned(16))) bf16 sB[2][BN * CV_LD];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int Cin = C0 + C1, Hout = Hin / stride;
-  const int K = 9 * Cin, nchunks = K / CV_BK;
-  const long long m0 = (long long)blockIdx.x * CV_BM;
+  const int K = FOLD ? 4 * C0 + 9 * C1 : 9 * Cin, nchunks = K / CV_BK;
   const int n0 = blockIdx.y * BN;
   const int Hs0 = UP ? Hin / 2 : Hin;
-  // this thread's 4 A rows (pixels) and its 16-byte piece within a 64-wide chunk
+  // FOLD: the tile's parity and its pixels' half-resolution coordinates
+  const long long tiles_per_par = FOLD ? (long long)gridDim.x / 4 : 1;
+  const int par = FOLD ? (int)(blockIdx.x / tiles_per_par) : 0;
+  const int py = par >> 1, px = par & 1;
+  const long long m0 = FOLD ? (blockIdx.x - par * tiles_per_par) * CV_BM
+                            : (long long)blockIdx.x * CV_BM;
+  if (FOLD) Wt += (size_t)par * Cout * Kp;
+  // this thread's 4 A rows (pixels) and its 16-byte piece within a 64-wide chunk; FOLD: the
+  // rows hold (b, Y, X) on the half-resolution grid
   const int a_piece = tid & 7;
+  const int Hm = FOLD ? Hout / 2 : Hout;
   int a_b[4], a_oy[4], a_ox[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     long long m = m0 + (tid >> 3) + 32 * r;
-    a_ox[r] = (int)(m % Hout);
-    a_oy[r] = (int)((m / Hout) % Hout);
-    a_b[r] = (int)(m / ((long long)Hout * Hout));
+    a_ox[r] = (int)(m % Hm);
+    a_oy[r] = (int)((m / Hm) % Hm);
+    a_b[r] = (int)(m / ((long long)Hm * Hm));
   }
   uint4 ra[4], rb[B_PIECES];
   auto fetch = [&](int chunk) {
     int k0 = chunk * CV_BK;
-    int tap = k0 / Cin, c0 = k0 - tap * Cin;
-    int dy = tap / 3 - 1, dx = tap % 3 - 1;
-    bool first = c0 < C0;
+    bool first;
+    int dy, dx, c0;
+    if (FOLD) {
+      first = k0 < 4 * C0;
+      if (first) {
+        int ij = k0 / C0;
+        c0 = k0 - ij * C0;
+        dy = (ij >> 1) - 1 + py;  // source row offset from Y
+        dx = (ij & 1) - 1 + px;
+      } else {
+        int r = k0 - 4 * C0, tap = r / C1;
+        c0 = C0 + (r - tap * C1);
+        dy = tap / 3 - 1;
+        dx = tap % 3 - 1;
+      }
+    } else {
+      int tap = k0 / Cin;
+      c0 = k0 - tap * Cin;
+      dy = tap / 3 - 1;
+      dx = tap % 3 - 1;
+      first = c0 < C0;
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      int iy = a_oy[r] * stride + dy, ix = a_ox[r] * stride + dx;
       uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (iy >= 0 && iy < Hin && ix >= 0 && ix < Hin) {
-        const bf16* p;
-        if (first) {
-          int sy = UP ? iy >> 1 : iy, sx = UP ? ix >> 1 : ix;
-          p = src0 + (((size_t)a_b[r] * Hs0 + sy) * Hs0 + sx) * C0 + c0;
-        } else {
-          p = src1 + (((size_t)a_b[r] * Hin + iy) * Hin + ix) * C1 + (c0 - C0);
+      if (FOLD && first) {
+        int sy = a_oy[r] + dy, sx = a_ox[r] + dx;
+        if (sy >= 0 && sy < Hs0 && sx >= 0 && sx < Hs0)
+          v = *(const uint4*)(src0 + (((size_t)a_b[r] * Hs0 + sy) * Hs0 + sx) * C0 + c0 +
+                              a_piece * 8);
+      } else {
+        int oy = FOLD ? 2 * a_oy[r] + py : a_oy[r], ox = FOLD ? 2 * a_ox[r] + px : a_ox[r];
+        int iy = oy * stride + dy, ix = ox * stride + dx;
+        if (iy >= 0 && iy < Hin && ix >= 0 && ix < Hin) {
+          const bf16* p;
+          if (first) {
+            int sy = UP ? iy >> 1 : iy, sx = UP ? ix >> 1 : ix;
+            p = src0 + (((size_t)a_b[r] * Hs0 + sy) * Hs0 + sx) * C0 + c0;
+          } else {
+            p = src1 + (((size_t)a_b[r] * Hin + iy) * Hin + ix) * C1 + (c0 - C0);
+          }
+          v = *(const uint4*)(p + a_piece * 8);
         }
-        v = *(const uint4*)(p + a_piece * 8);
       }
       ra[r] = v;
     }
@@ -228,12 +270,49 @@ __global__ void __launch_bounds__(256, 2) k_conv_fwd(
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         long long row = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+        if (FOLD) {  // (b, Y, X) -> the output pixel (b, 2Y + py, 2X + px)
+          long long X = row % Hm, t = row / Hm, Y = t % Hm, bb = t / Hm;
+          row = (bb * Hout + 2 * Y + py) * Hout + 2 * X + px;
+        }
         float v = acc[i][j][r] + bv;
         if (DGRAD)
           ((float*)out_)[row * Cout + col] = v;
         else
           ((bf16*)out_)[row * Cout + col] = (bf16)(v > 0.f ? v : 0.f);
       }
+  }
+}
+
+// Folded weights of an upsampling layer (see k_conv_fwd's FOLD): Wf[par][co][k'] from the
+// layer's W[co][k] (k = tap Cin + c): for the upsampled part the sum, over the taps landing on
+// source offset (i, j) for parity par, of W[co][tap Cin + c] (FP32, taps in order, rounded to
+// BF16 once); the skip part copied.
+__global__ void k_fold_weights(const bf16* __restrict__ W, int Cout, int C0, int C1, int Kp,
+                               bf16* __restrict__ Wf) {
+  const int Cin = C0 + C1, Kf = 4 * C0 + 9 * C1;
+  const long long total = 4LL * Cout * Kf;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(e % Kf);
+    const long long t = e / Kf;
+    const int co = (int)(t % Cout), par = (int)(t / Cout);
+    const bf16* w = W + (size_t)co * Kp;
+    if (k < 4 * C0) {
+      const int ij = k / C0, c = k - ij * C0, i = ij >> 1, j = ij & 1;
+      const int py = par >> 1, px = par & 1;
+      // tap rows (columns) landing on source row (column) offset i (j) for parity py (px)
+      const int r0 = py == 0 ? (i == 0 ? 0 : 1) : (i == 0 ? 0 : 2);
+      const int r1 = py == 0 ? (i == 0 ? 0 : 2) : (i == 0 ? 1 : 2);
+      const int c0 = px == 0 ? (j == 0 ? 0 : 1) : (j == 0 ? 0 : 2);
+      const int c1 = px == 0 ? (j == 0 ? 0 : 2) : (j == 0 ? 1 : 2);
+      float acc = 0.f;
+      for (int ty = r0; ty <= r1; ++ty)
+        for (int tx = c0; tx <= c1; ++tx) acc += (float)w[(ty * 3 + tx) * Cin + c];
+      Wf[e] = (bf16)acc;
+    } else {
+      const int r = k - 4 * C0, tap = r / C1, c = r - tap * C1;
+      Wf[e] = w[tap * Cin + C0 + c];
+    }
   }
 }
 
@@ -816,6 +895,7 @@ struct Model {
   float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;  // fp32 master, Adam, grad
   bf16* wb = nullptr;                                            // bf16 copy of w
   bf16* wflip = nullptr;  // flipped, transposed weights of a decoder layer (its data gradient)
+  bf16* wfold[2] = {nullptr, nullptr};  // folded weights of the upsampling layers L4, L5
   long long step = 0;
   int cap_b = 0;
   // activations and workspaces (sized for cap_b)
@@ -968,14 +1048,20 @@ static pprs_status conv_fused(Model& M, int l, int B) {
   dim3 grid((unsigned)(pix / CV_BM), y.cout / bn);
   const bf16* w = M.wb + y.woff;
   const float* b = M.w + y.boff;
-  if (bn == 128 && up)
-    hipLaunchKernelGGL((k_conv_fwd<128, true>), grid, dim3(256), 0, M.stream, s0, c0, s1, c1, y.hin, y.stride, w, y.kp, b, y.cout, M.a[l]);
-  else if (bn == 128)
+  if (up) {
+    // folded upsampling: per output parity, 4 C0 + 9 C1 deep (pixels of one parity per tile)
+    const int kf = 4 * c0 + 9 * c1;
+    if ((pix / 4) % CV_BM) return cfail(PPRS_EINVAL, "layer %d does not fit the folded convolution", l + 1);
+    const bf16* wf = M.wfold[l - 3];
+    if (bn == 128)
+      hipLaunchKernelGGL((k_conv_fwd<128, true, false, true>), grid, dim3(256), 0, M.stream, s0, c0, s1, c1, y.hin, y.stride, wf, kf, b, y.cout, M.a[l]);
+    else
+      hipLaunchKernelGGL((k_conv_fwd<64, true, false, true>), grid, dim3(256), 0, M.stream, s0, c0, s1, c1, y.hin, y.stride, wf, kf, b, y.cout, M.a[l]);
+  } else if (bn == 128) {
     hipLaunchKernelGGL((k_conv_fwd<128, false>), grid, dim3(256), 0, M.stream, s0, c0, s1, c1, y.hin, y.stride, w, y.kp, b, y.cout, M.a[l]);
-  else if (up)
-    hipLaunchKernelGGL((k_conv_fwd<64, true>), grid, dim3(256), 0, M.stream, s0, c0, s1, c1, y.hin, y.stride, w, y.kp, b, y.cout, M.a[l]);
-  else
+  } else {
     hipLaunchKernelGGL((k_conv_fwd<64, false>), grid, dim3(256), 0, M.stream, s0, c0, s1, c1, y.hin, y.stride, w, y.kp, b, y.cout, M.a[l]);
+  }
   CHK(hipGetLastError());
   return PPRS_OK;
 }
@@ -1009,9 +1095,16 @@ static pprs_status forward(Model& M, const float* x, int B, bool train) {
 }
 
 // fp32 view of the L6 weights from the bf16 copy (so every layer computes with bf16 weights).
-static pprs_status refresh_w6(Model& M) {
+// Weight copies derived from the BF16 weights, remade whenever they change: L6's FP32 copies
+// and the folded weights of the upsampling layers L4 and L5.
+static pprs_status refresh_derived(Model& M) {
   const Layer& y6 = M.L[5];
   hipLaunchKernelGGL(k_w6_prep, dim3(1), dim3(kBlock), 0, M.stream, M.wb + y6.woff, M.w6, M.w6f);
+  for (int l = 3; l < 5; ++l) {
+    const Layer& y = M.L[l];
+    const int c0 = l == 3 ? 256 : 128, c1 = y.cin - c0;
+    hipLaunchKernelGGL(k_fold_weights, dim3(grid1d(4LL * y.cout * (4 * c0 + 9 * c1))), dim3(kBlock), 0, M.stream, M.wb + y.woff, y.cout, c0, c1, y.kp, M.wfold[l - 3]);
+  }
   CHK(hipGetLastError());
   return PPRS_OK;
 }
@@ -1303,6 +1396,10 @@ pprs_status pprs_cnn_create(pprs_cnn** out, int device, void* stream, unsigned l
   if (e == hipSuccess) e = hipMalloc(&M.wb, sizeof(bf16) * M.n_params);
   if (e == hipSuccess) e = hipMalloc(&M.w6, sizeof(float) * M.L[5].cout * M.L[5].kp);
   if (e == hipSuccess) e = hipMalloc(&M.w6f, sizeof(float) * 4 * 2 * 2 * 2 * 64);
+  for (int l = 3; l < 5 && e == hipSuccess; ++l) {
+    const int c0 = l == 3 ? 256 : 128, c1 = M.L[l].cin - c0;
+    e = hipMalloc(&M.wfold[l - 3], sizeof(bf16) * 4 * M.L[l].cout * (4 * c0 + 9 * c1));
+  }
   if (e != hipSuccess) {
     delete c;
     return cfail(PPRS_ENOMEM, "cnn allocation failed");
@@ -1317,7 +1414,8 @@ void pprs_cnn_destroy(pprs_cnn* c) {
   Model& M = c->M;
   (void)hipSetDevice(M.device);
   (void)hipStreamSynchronize(M.stream);
-  void* ptrs[] = {M.w, M.m, M.v, M.g, M.wb, M.w6, M.w6f, M.x0, M.a[0], M.a[1], M.a[2], M.a[3],
+  void* ptrs[] = {M.w, M.m, M.v, M.g, M.wb, M.w6, M.w6f, M.wfold[0], M.wfold[1], M.x0, M.a[0],
+                  M.a[1], M.a[2], M.a[3],
                   M.a[4], M.u4, M.u5, M.col, M.dzb, M.z, M.y, M.dy, M.dcol, M.du, M.da[0],
                   M.da[1], M.da[2], M.da[3], M.da[4], M.part, M.lpart, M.wflip};
   for (void* p : ptrs)
@@ -1338,7 +1436,7 @@ pprs_status pprs_cnn_set_params(pprs_cnn* c, const float* host, size_t count) {
   hipLaunchKernelGGL(k_f32_to_bf16, dim3(grid1d(count)), dim3(kBlock), 0, M.stream, M.w, (long long)count, M.wb);
   CHK(hipGetLastError());
   M.step = 0;
-  return refresh_w6(M);
+  return refresh_derived(M);
 }
 
 pprs_status pprs_cnn_load(pprs_cnn* c, const void* blob, size_t bytes) {
@@ -1427,7 +1525,7 @@ pprs_status pprs_cnn_train_step(pprs_cnn* c, const float* x, const float* target
   float c1 = 1.f - powf(b1, (float)M.step), c2 = 1.f - powf(b2, (float)M.step);
   hipLaunchKernelGGL(k_adam, dim3(grid1d(M.n_params)), dim3(kBlock), 0, M.stream, M.w, M.m, M.v, M.g, M.n_params, lr, b1, b2, 1e-8f, c1, c2, M.wb);
   CHK(hipGetLastError());
-  return refresh_w6(M);
+  return refresh_derived(M);
 }
 
 }  // extern "C"
