@@ -522,8 +522,10 @@ __global__ void k_f32_to_bf16(const float* __restrict__ x, long long count,
 // when py = 1; columns alike), so the taps that land on one source pixel are summed into the
 // folded weights W6f [parity py px][i][j][output][64] (k_w6_prep): 4 source pixels of 64
 // channels instead of 9. Channels 64, 65 are the network input x0 [B][128][128][2] (9 taps,
-// weights W6 [2][9][66]). One workgroup per (sample, parity, 4 source rows of 64), so a wave's
-// weights are uniform; 16-byte loads of a5.
+// weights W6 [2][9][66]). Eight lanes share an output pixel, lane g taking channels 8g .. 8g + 7
+// (one 16-byte piece of each source pixel, so a source pixel is one 128-byte line per 8 lanes)
+// and x0 tap g (and tap 8 on lane 0); the 8 partial sums are then added across the lanes.
+// One workgroup per (sample, parity, 32 source pixels of a row): a wave's parity is uniform.
 __global__ void __launch_bounds__(256) k_l6_fused(const bf16* __restrict__ a5,
                                                   const bf16* __restrict__ x0,
                                                   const float* __restrict__ W6,
@@ -531,52 +533,71 @@ __global__ void __launch_bounds__(256) k_l6_fused(const bf16* __restrict__ a5,
                                                   const float* __restrict__ b6, int Bn,
                                                   float* __restrict__ Y) {
   constexpr int C = 66;
-  const int nblk = Bn * 64;
+  __shared__ __attribute__((aligned(16))) float wf[4 * 2 * 2 * 2 * 64];
+  for (int e = threadIdx.x; e < 4 * 2 * 2 * 2 * 64; e += blockDim.x) wf[e] = W6f[e];
+  __syncthreads();
+  const int g = threadIdx.x & 7;  // channel group
+  const int nblk = Bn * 4 * 64 * 2;  // (sample, parity, source row, half row)
   for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-    const int b = blk >> 6, par = (blk >> 4) & 3, py = par >> 1, px = par & 1;
-    const int ys = (blk & 15) * 4 + (threadIdx.x >> 6), xs = threadIdx.x & 63;
+    const int half = blk & 1, ys = (blk >> 1) & 63, par = (blk >> 7) & 3, b = blk >> 9;
+    const int py = par >> 1, px = par & 1;
+    const int xs = half * 32 + (threadIdx.x >> 3);
     const int y = 2 * ys + py, x = 2 * xs + px;
-    float s0 = b6[0], s1 = b6[1];
+    float s0 = g == 0 ? b6[0] : 0.f, s1 = g == 0 ? b6[1] : 0.f;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int sy = ys - 1 + py + i;
-      if (sy < 0 || sy >= 64) continue;  // uniform over the wave (one source row)
+      if (sy < 0 || sy >= 64) continue;  // uniform over the workgroup (one source row)
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int sx = xs - 1 + px + j;
         const bool ok = sx >= 0 && sx < 64;
-        const uint4* u = (const uint4*)(a5 + (((size_t)b * 64 + sy) * 64 + (ok ? sx : 0)) * 64);
-        const float* w0 = W6f + (((par * 2 + i) * 2 + j) * 2) * 64;
-        const float* w1 = w0 + 64;
+        uint4 v = ok ? *(const uint4*)(a5 + (((size_t)b * 64 + sy) * 64 + sx) * 64 + 8 * g)
+                     : make_uint4(0u, 0u, 0u, 0u);
+        const float* w0 = wf + (((par * 2 + i) * 2 + j) * 2) * 64 + 8 * g;
+        const f32x4 wa = *(const f32x4*)w0, wb = *(const f32x4*)(w0 + 4);
+        const f32x4 wc = *(const f32x4*)(w0 + 64), wd = *(const f32x4*)(w0 + 68);
+        const unsigned int h[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          uint4 v = ok ? u[q] : make_uint4(0u, 0u, 0u, 0u);
-          unsigned int h[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            float lo = __uint_as_float(h[k] << 16), hi = __uint_as_float(h[k] & 0xffff0000u);
-            s0 = fmaf(w0[8 * q + 2 * k], lo, s0);
-            s1 = fmaf(w1[8 * q + 2 * k], lo, s1);
-            s0 = fmaf(w0[8 * q + 2 * k + 1], hi, s0);
-            s1 = fmaf(w1[8 * q + 2 * k + 1], hi, s1);
-          }
+        for (int k = 0; k < 4; ++k) {
+          const float lo = __uint_as_float(h[k] << 16), hi = __uint_as_float(h[k] & 0xffff0000u);
+          const float w0lo = k < 2 ? wa[2 * k] : wb[2 * k - 4];
+          const float w0hi = k < 2 ? wa[2 * k + 1] : wb[2 * k - 3];
+          const float w1lo = k < 2 ? wc[2 * k] : wd[2 * k - 4];
+          const float w1hi = k < 2 ? wc[2 * k + 1] : wd[2 * k - 3];
+          s0 = fmaf(w0lo, lo, s0);
+          s1 = fmaf(w1lo, lo, s1);
+          s0 = fmaf(w0hi, hi, s0);
+          s1 = fmaf(w1hi, hi, s1);
         }
       }
     }
+    // x0 channels: lane g takes tap g, lane 0 also tap 8
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
+    for (int t = 0; t < 2; ++t) {
+      const int tap = t == 0 ? g : 8;
+      if (t == 1 && g != 0) break;
       const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
-      if (yy < 0 || yy >= 128 || xx < 0 || xx >= 128) continue;
-      const bf16* xi = x0 + (((size_t)b * 128 + yy) * 128 + xx) * 2;
-      const float f0 = (float)xi[0], f1 = (float)xi[1];
-      s0 = fmaf(W6[tap * C + 64], f0, s0);
-      s1 = fmaf(W6[9 * C + tap * C + 64], f0, s1);
-      s0 = fmaf(W6[tap * C + 65], f1, s0);
-      s1 = fmaf(W6[9 * C + tap * C + 65], f1, s1);
+      if (yy >= 0 && yy < 128 && xx >= 0 && xx < 128) {
+        const unsigned int v = *(const unsigned int*)(x0 + (((size_t)b * 128 + yy) * 128 + xx) * 2);
+        const float f0 = __uint_as_float(v << 16), f1 = __uint_as_float(v & 0xffff0000u);
+        s0 = fmaf(W6[tap * C + 64], f0, s0);
+        s1 = fmaf(W6[9 * C + tap * C + 64], f0, s1);
+        s0 = fmaf(W6[tap * C + 65], f1, s0);
+        s1 = fmaf(W6[9 * C + tap * C + 65], f1, s1);
+      }
     }
-    const size_t o = (((size_t)b * 128 + y) * 128 + x) * 2;
-    Y[o] = s0;
-    Y[o + 1] = s1;
+    // the 8 channel groups' partial sums (lanes 8p .. 8p + 7), fixed order
+#pragma unroll
+    for (int m = 1; m < 8; m <<= 1) {
+      s0 += __shfl_xor(s0, m, 64);
+      s1 += __shfl_xor(s1, m, 64);
+    }
+    if (g == 0) {
+      const size_t o = (((size_t)b * 128 + y) * 128 + x) * 2;
+      Y[o] = s0;
+      Y[o + 1] = s1;
+    }
   }
 }
 
@@ -676,8 +697,10 @@ __global__ void __launch_bounds__(256) k_l6_bwd_a5(const float* __restrict__ dY,
   const long long step = ((long long)gridDim.x * blockDim.x) >> 6;
   for (long long p = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6; p < npix;
        p += step) {
-    const int X = (int)(p & 63), Y = (int)((p >> 6) & 63);
-    const long long b = p >> 12;
+    // one source pixel per wave: its index in scalar registers, so the dY reads are scalar
+    const int pu = __builtin_amdgcn_readfirstlane((int)p);
+    const int X = pu & 63, Y = (pu >> 6) & 63;
+    const long long b = pu >> 12;
     float s = 0.f;
 #pragma unroll
     for (int py = 0; py < 2; ++py)
@@ -1089,7 +1112,7 @@ static pprs_status forward(Model& M, const float* x, int B, bool train) {
   }
   // L6
   const Layer& y6 = M.L[5];
-  hipLaunchKernelGGL(k_l6_fused, dim3(B * 64), dim3(kBlock), 0, st, M.a[4], M.x0, M.w6, M.w6f, M.w + y6.boff, B, M.y);
+  hipLaunchKernelGGL(k_l6_fused, dim3(std::min(B * 512, 16384)), dim3(kBlock), 0, st, M.a[4], M.x0, M.w6, M.w6f, M.w + y6.boff, B, M.y);
   CHK(hipGetLastError());
   return PPRS_OK;
 }
