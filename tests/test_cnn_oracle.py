@@ -92,3 +92,35 @@ def test_bf16_rounding():
     assert r[0] == 1.0 and r[1] == 1.0  # halfway to even
     assert r[2] == np.float32(1.0078125)
     assert r[3] == np.float32(-3.140625)
+
+
+def test_upsampled_convolution_folds_onto_the_source_grid():
+    """The reading the network kernels use for the layers after a 2x nearest upsampling (L4,
+    L5, L6): output pixel (2Y + py, 2X + px) of a 3x3 convolution (padding 1) of the upsampled
+    map sees only the source pixels (Y - 1 + py + i, X - 1 + px + j), i, j in {0, 1}, with the
+    taps landing on one source pixel summed (tap rows {0}, {1, 2} for py = 0 and {0, 1}, {2}
+    for py = 1; columns alike). Checked in FP64 against upsample-then-convolve with torch."""
+    rng = np.random.default_rng(7)
+    B, C_in, C_out, S = 2, 5, 3, 6
+    src = torch.tensor(rng.standard_normal((B, C_in, S, S)), dtype=torch.float64)
+    w = torch.tensor(rng.standard_normal((C_out, C_in, 3, 3)), dtype=torch.float64)
+    ref = torch.nn.functional.conv2d(torch.nn.functional.interpolate(src, scale_factor=2,
+                                                                     mode="nearest"),
+                                     w, padding=1)
+    groups = {0: ([0], [1, 2]), 1: ([0, 1], [2])}   # tap rows (columns) per offset i (j)
+    out = torch.zeros_like(ref)
+    pad = torch.nn.functional.pad(src, (1, 1, 1, 1))   # source offsets -1 .. +1
+    for py in (0, 1):
+        for px in (0, 1):
+            wf = torch.zeros((C_out, C_in, 2, 2), dtype=torch.float64)
+            for i in (0, 1):
+                for j in (0, 1):
+                    for ty in groups[py][i]:
+                        for tx in groups[px][j]:
+                            wf[:, :, i, j] += w[:, :, ty, tx]
+            # source pixel (Y - 1 + py + i) sits at row Y + py + i of the padded map
+            part = torch.nn.functional.conv2d(pad[:, :, py:py + S + 1, px:px + S + 1], wf)
+            out[:, :, py::2, px::2] = part
+    # everywhere, the border rows and columns included: the taps that leave the upsampled map
+    # (its zero padding) are exactly the source pixels outside the source map
+    assert (out - ref).abs().max().item() < 1e-12
