@@ -2070,8 +2070,9 @@ template <int MODE, int NC>
 __global__ void __launch_bounds__(BLOCK) k_rigid_energy(BatchDesc* D) {
   constexpr int NXN = ET_X + 1, NYN = ET_Y + 1, NN = NXN * NYN;
   constexpr int NV = 3 * NC + 3;
+  constexpr int KG = NV < BLOCK / 16 ? NV : BLOCK / 16;
   __shared__ float s_r[NN];
-  __shared__ double s_red[(BLOCK / 64) * NV];
+  __shared__ double s_stage[KG * (BLOCK / 2)];  // the partial sums' reduction stage
   __shared__ int s_pos;
   const int kind = MODE ? WK_LADDER : WK_EVAL;
   ItemCursor c;
@@ -2116,10 +2117,11 @@ __global__ void __launch_bounds__(BLOCK) k_rigid_energy(BatchDesc* D) {
       }
     }
     __syncthreads();
-    double acc[NV];
+    // per-thread FP32 sums over the thread's elements of the tile (at most
+    // ET_X * ET_Y / BLOCK), converted to FP64 once per tile
+    float es[3 * NC];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    float w = 0.25f / ((float)(n - 1) * (float)(n - 1));
+    for (int k = 0; k < 3 * NC; ++k) es[k] = 0.f;
     for (int e = threadIdx.x; e < ET_X * ET_Y; e += BLOCK) {
       int ey = e / ET_X, ex = e % ET_X;
       int a = e0y + ey, b = e0x + ex;
@@ -2129,9 +2131,6 @@ __global__ void __launch_bounds__(BLOCK) k_rigid_energy(BatchDesc* D) {
       float ndx[NC], ndy[NC];
 #pragma unroll
       for (int j = 0; j < NC; ++j) rigid_node_offset(mp[j], a, b, ndx[j], ndy[j]);
-      float es[3 * NC];
-#pragma unroll
-      for (int k = 0; k < 3 * NC; ++k) es[k] = 0.f;
 #pragma unroll 1
       for (int p = 0; p < 2; ++p) {
 #pragma unroll 1
@@ -2146,19 +2145,19 @@ __global__ void __launch_bounds__(BLOCK) k_rigid_energy(BatchDesc* D) {
             float ty = eta + (ndy[j] + fmaf(sn, xi, cm1 * eta));
             float tv = sample_bil<false>(T, n, b, tx, a, ty, inv_h, nullptr, nullptr);
             es[3 * j + 0] += tv;
-            es[3 * j + 1] += tv * tv;
-            es[3 * j + 2] += tv * rq;
+            es[3 * j + 1] = fmaf(tv, tv, es[3 * j + 1]);
+            es[3 * j + 2] = fmaf(tv, rq, es[3 * j + 2]);
           }
         }
       }
+    }
+    double acc[NV];
+    const double w = 0.25 / ((double)(n - 1) * (double)(n - 1));
 #pragma unroll
-      for (int k = 0; k < 3 * NC; ++k) acc[k] += (double)(w * es[k]);
-    }
-    block_sum<NV>(acc, s_red);
-    if (threadIdx.x == 0) {
-      double* pr = slot_partial(D, s, kind, t);
-      for (int k = 0; k < NV; ++k) pr[k] = acc[k];
-    }
+    for (int k = 0; k < 3 * NC; ++k) acc[k] = w * (double)es[k];
+#pragma unroll
+    for (int k = 3 * NC; k < NV; ++k) acc[k] = 0.0;
+    block_sum_store<NV>(acc, s_stage, slot_partial(D, s, kind, t));
   }
 }
 
