@@ -23,7 +23,6 @@
 #define FLAG_NONCONV 1
 #define FLAG_NAN 2
 
-__constant__ float c_gp[2] = {0.21132486540518711775f, 0.78867513459481288225f};
 
 // ------------------------------------------------------------------------------------------
 // Helpers
@@ -2131,11 +2130,11 @@ __global__ void __launch_bounds__(BLOCK) k_rigid_energy(BatchDesc* D) {
       float ndx[NC], ndy[NC];
 #pragma unroll
       for (int j = 0; j < NC; ++j) rigid_node_offset(mp[j], a, b, ndx[j], ndy[j]);
-#pragma unroll 1
+#pragma unroll
       for (int p = 0; p < 2; ++p) {
-#pragma unroll 1
+#pragma unroll
         for (int q = 0; q < 2; ++q) {
-          float xi = c_gp[q], eta = c_gp[p];
+          const float xi = q ? kGP1 : kGP0, eta = p ? kGP1 : kGP0;
           float p0 = (1.f - xi) * (1.f - eta), p1 = xi * (1.f - eta), p2 = (1.f - xi) * eta, p3 = xi * eta;
           float rq = p0 * rr[0] + p1 * rr[1] + p2 * rr[2] + p3 * rr[3];
 #pragma unroll
@@ -2165,7 +2164,7 @@ __global__ void __launch_bounds__(BLOCK) k_rigid_energy(BatchDesc* D) {
 __global__ void __launch_bounds__(BLOCK) k_rigid_grad(BatchDesc* D) {
   constexpr int NXN = ET_X + 1, NYN = ET_Y + 1, NN = NXN * NYN;
   __shared__ float s_r[NN];
-  __shared__ double s_red[(BLOCK / 64) * 3];
+  __shared__ double s_stage[3 * (BLOCK / 2)];  // the partial sums' reduction stage
   __shared__ int s_pos;
   ItemCursor c;
   if (!cursor_begin(D, WK_GRAD, c, &s_pos)) return;
@@ -2205,7 +2204,8 @@ __global__ void __launch_bounds__(BLOCK) k_rigid_grad(BatchDesc* D) {
       }
     }
     __syncthreads();
-    double acc[3] = {0.0, 0.0, 0.0};
+    // per-thread FP32 sums over the thread's elements of the tile, converted to FP64 once
+    float ga = 0.f, g0 = 0.f, g1 = 0.f;
     for (int e = threadIdx.x; e < ET_X * ET_Y; e += BLOCK) {
       int ey = e / ET_X, ex = e % ET_X;
       int a = e0y + ey, b = e0x + ex;
@@ -2214,12 +2214,11 @@ __global__ void __launch_bounds__(BLOCK) k_rigid_grad(BatchDesc* D) {
       float rr[4] = {s_r[k00], s_r[k00 + 1], s_r[k00 + NXN], s_r[k00 + NXN + 1]};
       float ndx, ndy;
       rigid_node_offset(mp, a, b, ndx, ndy);
-      float ga = 0.f, g0 = 0.f, g1 = 0.f;
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-          float xi = c_gp[q], eta = c_gp[p];
+          const float xi = q ? kGP1 : kGP0, eta = p ? kGP1 : kGP0;
           float p0 = (1.f - xi) * (1.f - eta), p1 = xi * (1.f - eta), p2 = (1.f - xi) * eta, p3 = xi * eta;
           float rq = p0 * rr[0] + p1 * rr[1] + p2 * rr[2] + p3 * rr[3];
           float tx = xi + (ndx + fmaf(cm1, xi, -sn * eta));
@@ -2235,15 +2234,9 @@ __global__ void __launch_bounds__(BLOCK) k_rigid_grad(BatchDesc* D) {
           g1 += f * gy;
         }
       }
-      acc[0] += (double)ga;
-      acc[1] += (double)g0;
-      acc[2] += (double)g1;
     }
-    block_sum<3>(acc, s_red);
-    if (threadIdx.x == 0) {
-      double* pr = slot_partial(D, s, WK_GRAD, t);
-      for (int k = 0; k < 3; ++k) pr[k] = acc[k];
-    }
+    const double acc[3] = {(double)ga, (double)g0, (double)g1};
+    block_sum_store<3>(acc, s_stage, slot_partial(D, s, WK_GRAD, t));
   }
 }
 
