@@ -2086,7 +2086,8 @@ __global__ void __launch_bounds__(BLOCK) k_rigid_energy(BatchDesc* D) {
     int l = (ph == PH_PROLONG) ? stp->level + 1 : stp->level;
     int n = lvl_n(l);
     const float* R = uni(D->pyr + D->frame_off[(size_t)stp->ref * PPRS_MAXL + l]);
-    const float* T = uni(D->pyr + D->frame_off[(size_t)stp->tmpl * PPRS_MAXL + l]);
+    const float* TC = uni(D->tcoef + 4 * D->frame_off[(size_t)stp->tmpl * PPRS_MAXL + l]);
+    const unsigned n16 = (unsigned)n << 4;
     double top = MODE ? stp->top : 0.0;
     RigidMap mp[NC];
 #pragma unroll
@@ -2095,7 +2096,6 @@ __global__ void __launch_bounds__(BLOCK) k_rigid_energy(BatchDesc* D) {
       mp[j] = rigid_map(stp->rp[0] - tj * stp->rd[0], stp->rp[1] - tj * stp->rd[1],
                         stp->rp[2] - tj * stp->rd[2], n);
     }
-    float inv_h = (float)(n - 1);
     int ntx = (n - 1 + ET_X - 1) / ET_X;
     int e0x = (t % ntx) * ET_X, e0y = (t / ntx) * ET_Y;
     __syncthreads();
@@ -2130,6 +2130,10 @@ __global__ void __launch_bounds__(BLOCK) k_rigid_energy(BatchDesc* D) {
       float ndx[NC], ndy[NC];
 #pragma unroll
       for (int j = 0; j < NC; ++j) rigid_node_offset(mp[j], a, b, ndx[j], ndy[j]);
+      // the element's cell in the clamp bounds and the byte offset of its first node's record
+      const float lox = (float)(-b), hix = (float)(n - 1 - b);
+      const float loy = (float)(-a), hiy = (float)(n - 1 - a);
+      const unsigned base16 = (unsigned)mad24(a, n, b) << 4;
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
 #pragma unroll
@@ -2142,7 +2146,7 @@ __global__ void __launch_bounds__(BLOCK) k_rigid_energy(BatchDesc* D) {
             float cm1 = (float)mp[j].cm1, sn = (float)mp[j].s;
             float tx = xi + (ndx[j] + fmaf(cm1, xi, -sn * eta));
             float ty = eta + (ndy[j] + fmaf(sn, xi, cm1 * eta));
-            float tv = sample_bil<false>(T, n, b, tx, a, ty, inv_h, nullptr, nullptr);
+            float tv = sample_cells(TC, n16, base16, lox, hix, loy, hiy, tx, ty);
             es[3 * j + 0] += tv;
             es[3 * j + 1] = fmaf(tv, tv, es[3 * j + 1]);
             es[3 * j + 2] = fmaf(tv, rq, es[3 * j + 2]);
