@@ -7,8 +7,6 @@ namespace pprs_k {
 hipError_t plan(BatchDesc* d, hipStream_t st);
 // nc: step sizes per line-search pass (1, 2, 3, 5 or 7; ladder_rungs_ok)
 bool ladder_rungs_ok(int nc);
-hipError_t energy(BatchDesc* d, int mode, int nc, int grid, hipStream_t st);
-hipError_t energy_fin(BatchDesc* d, int mode, int nc, int grid, hipStream_t st);
 // start energies (eval list) and line-search passes (ladder list) of a step in one launch,
 // and their finalisers
 hipError_t energy_step(BatchDesc* d, int nc, int grid, hipStream_t st);
@@ -62,7 +60,8 @@ hipError_t from_nodes_idx(const float* vbuf, const long long* offs, int n, float
                           long long d_plane, int elems, float scale, hipStream_t st);
 // rigid variant: energy passes (mode 0 start, 1 line search with nc steps), gradient, its
 // per-slot finaliser (the energy finalisers are energy_fin's)
-hipError_t rigid_energy(BatchDesc* d, int mode, int nc, int grid, hipStream_t st);
+// start energies (eval list) and line-search passes (ladder list) of the rigid slots, one launch
+hipError_t rigid_energy_step(BatchDesc* d, int nc, int grid, hipStream_t st);
 hipError_t rigid_grad(BatchDesc* d, int grid, hipStream_t st);
 hipError_t rigid_grad_fin(BatchDesc* d, int grid, hipStream_t st);
 // avg[H][W] = mean over i of frames[i] sampled at x + u[i](x) (pixels, clamped, bilinear)

@@ -5,7 +5,8 @@
 //   k_plan     - builds per-kind item lists from the slot phases (one workgroup)
 //   k_grad     - applies the accepted step and computes the gradient G; in the same launch,
 //                the bilinear prolongation of a finished level's u to the next level
-//   k_energy   - energy at a set of step sizes (line-search pass) or at the current u
+//   k_energy_step - energies at the step sizes of a line-search pass, and the start energy
+//                of a level, in one launch
 //   k_smooth   - metric solve d = (S1^-1 (x) S1^-1) G, one direction per launch
 //   k_*_fin    - per-slot finalisers, launched after a pass: sum the pass's FP64 tile partials
 //                in tile order and advance the slot's state (the kernel boundary orders them
@@ -718,8 +719,9 @@ __device__ __forceinline__ void energy_finalize(BatchDesc* D, SlotState* stp, Sl
 // Staged nodes of an element tile (ET_X x ET_Y elements).
 #define ET_NN ((ET_X + 1) * (ET_Y + 1))
 
-// One energy item: element tile t of slot s (MODE and NC as k_energy's). The LDS arrays are
-// the caller's (s_dx, s_dy unused in MODE 0).
+// One energy item: element tile t of slot s (MODE 0: the start energy of a level; MODE 1: a
+// line-search pass at NC step sizes). The LDS arrays are the caller's (s_dx, s_dy unused in
+// MODE 0).
 template <int MODE, int NC>
 __device__ __forceinline__ void energy_item(BatchDesc* D, int s, int t, float* s_ux, float* s_uy,
                                             float* s_dx, float* s_dy, float* s_r,
@@ -862,22 +864,6 @@ struct EnergyLds {
   __device__ float* field(int i) { return reinterpret_cast<float*>(buf) + i * ET_NN; }
 };
 
-template <int MODE, int NC>
-__global__ void __launch_bounds__(BLOCK, LB_ENERGY) k_energy(BatchDesc* D) {
-  __shared__ EnergyLds<MODE ? 5 : 3, 3 * NC + 3> L;
-  float *s_ux = L.field(0), *s_uy = L.field(1), *s_r = L.field(2);
-  float *s_dx = MODE ? L.field(3) : nullptr, *s_dy = MODE ? L.field(4) : nullptr;
-  __shared__ int s_pos;
-  const int kind = MODE ? WK_LADDER : WK_EVAL;
-  ItemCursor c;
-  if (!cursor_begin(D, kind, c, &s_pos)) return;
-  for (; c.item < c.end; ++c.item) {
-    int s, t;
-    cursor_slot(D, kind, c, s, t);
-    energy_item<MODE, NC>(D, s, t, s_ux, s_uy, s_dx, s_dy, s_r, L.buf);
-  }
-}
-
 // The energy passes of a step in one launch: the start energies of the slots that begin a
 // level (the eval list) and the line-search passes (the ladder list), one item space made of
 // the two lists in that order. The two slot sets are disjoint (the plan gives a slot that
@@ -934,16 +920,6 @@ __device__ __forceinline__ void energy_fin_slot(BatchDesc* D, int pos, double* s
     energy_finalize<MODE, NC>(D, stp, st, s, l, lvl_n(l), ph, MODE ? st.top : 0.0, tot);
   }
   __syncthreads();
-}
-
-template <int MODE, int NC>
-__global__ void __launch_bounds__(BLOCK) k_energy_fin(BatchDesc* D) {
-  constexpr int NV = 3 * NC + 3;
-  __shared__ double s_red[(BLOCK / 64) * NV];
-  const int kind = MODE ? WK_LADDER : WK_EVAL;
-  const WorkList wl = D->lists[kind];
-  for (int pos = blockIdx.x; pos < wl.n_slots; pos += gridDim.x)
-    energy_fin_slot<MODE, NC>(D, pos, s_red);
 }
 
 // Finalisers of k_energy_step: the eval list's slots, then the ladder list's.
@@ -2034,7 +2010,7 @@ __global__ void __launch_bounds__(BLOCK) k_from_nodes_idx(const float* vbuf,
 // Rigid variant (definition of a rigid transformation): phi(x) = R(alpha) x + t with the three
 // parameters in SlotState::rp, rotation about the domain origin as printed. A quadrature point
 // q (in cells) maps to R(alpha) q + t / h. No field is stored: the energy passes and the
-// gradient pass are reductions over the level's elements (same tiles as k_energy). The energy
+// gradient pass are reductions over the level's elements (the field energy pass's tiles). The energy
 // is -NCC (no regulariser); the parameter gradient is
 //   dE/dp_k = sum_q f_q grad T(phi(q)) . dphi/dp_k(q),   dphi/dalpha = R'(alpha) q, dphi/dt = I,
 // f_q as in the gradient kernel; steepest descent in the parameters.
@@ -2063,26 +2039,19 @@ __device__ __forceinline__ void rigid_node_offset(const RigidMap& m, int a, int 
 }
 
 // Energy of the rigid parameters (MODE 0: at rp for slots starting a level; MODE 1: at
-// rp - tau_j rd for the NC steps of a line-search pass). Partials as k_energy's, the three
-// regulariser columns zero.
+// rp - tau_j rd for the NC steps of a line-search pass), one element tile. Partials as the
+// field energy pass's, the three regulariser columns zero.
 template <int MODE, int NC>
-__global__ void __launch_bounds__(BLOCK) k_rigid_energy(BatchDesc* D) {
+__device__ __forceinline__ void rigid_energy_item(BatchDesc* D, int s, int t, float* s_r,
+                                                  double* s_stage) {
   constexpr int NXN = ET_X + 1, NYN = ET_Y + 1, NN = NXN * NYN;
   constexpr int NV = 3 * NC + 3;
-  constexpr int KG = NV < BLOCK / 16 ? NV : BLOCK / 16;
-  __shared__ float s_r[NN];
-  __shared__ double s_stage[KG * (BLOCK / 2)];  // the partial sums' reduction stage
-  __shared__ int s_pos;
   const int kind = MODE ? WK_LADDER : WK_EVAL;
-  ItemCursor c;
-  if (!cursor_begin(D, kind, c, &s_pos)) return;
-  for (; c.item < c.end; ++c.item) {
-    int s, t;
-    cursor_slot(D, kind, c, s, t);
+  {
     const SlotState* stp = D->state + s;
     int ph = stp->phase;
-    if (MODE == 0 && !(ph == PH_INIT || ph == PH_PROLONG)) continue;
-    if (MODE == 1 && ph != PH_LADDER) continue;
+    if (MODE == 0 && !(ph == PH_INIT || ph == PH_PROLONG)) return;
+    if (MODE == 1 && ph != PH_LADDER) return;
     int l = (ph == PH_PROLONG) ? stp->level + 1 : stp->level;
     int n = lvl_n(l);
     const float* R = uni(D->pyr + D->frame_off[(size_t)stp->ref * PPRS_MAXL + l]);
@@ -2161,6 +2130,38 @@ __global__ void __launch_bounds__(BLOCK) k_rigid_energy(BatchDesc* D) {
 #pragma unroll
     for (int k = 3 * NC; k < NV; ++k) acc[k] = 0.0;
     block_sum_store<NV>(acc, s_stage, slot_partial(D, s, kind, t));
+  }
+}
+
+// The rigid energy passes of a step in one launch: the start energies of the slots that begin a
+// level (the eval list) and the line-search passes (the ladder list), one item space made of
+// the two lists in that order (disjoint slot sets, as for the fields' k_energy_step).
+template <int NC>
+__global__ void __launch_bounds__(BLOCK) k_rigid_energy_step(BatchDesc* D) {
+  constexpr int NXN = ET_X + 1, NYN = ET_Y + 1, NN = NXN * NYN;
+  constexpr int NV = 3 * NC + 3, KG = NV < BLOCK / 16 ? NV : BLOCK / 16;
+  __shared__ float s_r[NN];
+  __shared__ double s_stage[KG * (BLOCK / 2)];  // the partial sums' reduction stage
+  __shared__ int s_pos;
+  const int ne = D->lists[WK_EVAL].total, nl = D->lists[WK_LADDER].total;
+  const int total = ne + nl;
+  if (total <= 0) return;
+  int chunk = (total + gridDim.x - 1) / gridDim.x;
+  int b0 = blockIdx.x * chunk, b1 = min(b0 + chunk, total);
+  ItemCursor c;
+  if (b0 < ne && cursor_range(D, WK_EVAL, b0, min(b1, ne), c, &s_pos)) {
+    for (; c.item < c.end; ++c.item) {
+      int s, t;
+      cursor_slot(D, WK_EVAL, c, s, t);
+      rigid_energy_item<0, 1>(D, s, t, s_r, s_stage);
+    }
+  }
+  if (b1 > ne && cursor_range(D, WK_LADDER, max(b0, ne) - ne, b1 - ne, c, &s_pos)) {
+    for (; c.item < c.end; ++c.item) {
+      int s, t;
+      cursor_slot(D, WK_LADDER, c, s, t);
+      rigid_energy_item<1, NC>(D, s, t, s_r, s_stage);
+    }
   }
 }
 
@@ -2353,21 +2354,6 @@ hipError_t plan(BatchDesc* d, hipStream_t st) {
   return hipGetLastError();
 }
 bool ladder_rungs_ok(int nc) { return nc == 1 || nc == 2 || nc == 3 || nc == 5 || nc == 7; }
-hipError_t energy(BatchDesc* d, int mode, int nc, int grid, hipStream_t st) {
-  if (mode == 0) {
-    hipLaunchKernelGGL((k_energy<0, 1>), dim3(grid), dim3(BLOCK), 0, st, d);
-  } else {
-    switch (nc) {
-      case 1: hipLaunchKernelGGL((k_energy<1, 1>), dim3(grid), dim3(BLOCK), 0, st, d); break;
-      case 2: hipLaunchKernelGGL((k_energy<1, 2>), dim3(grid), dim3(BLOCK), 0, st, d); break;
-      case 3: hipLaunchKernelGGL((k_energy<1, 3>), dim3(grid), dim3(BLOCK), 0, st, d); break;
-      case 5: hipLaunchKernelGGL((k_energy<1, 5>), dim3(grid), dim3(BLOCK), 0, st, d); break;
-      case 7: hipLaunchKernelGGL((k_energy<1, 7>), dim3(grid), dim3(BLOCK), 0, st, d); break;
-      default: return hipErrorInvalidValue;
-    }
-  }
-  return hipGetLastError();
-}
 hipError_t energy_step(BatchDesc* d, int nc, int grid, hipStream_t st) {
   switch (nc) {
     case 1: hipLaunchKernelGGL((k_energy_step<1>), dim3(grid), dim3(BLOCK), 0, st, d); break;
@@ -2387,21 +2373,6 @@ hipError_t energy_step_fin(BatchDesc* d, int nc, int grid, hipStream_t st) {
     case 5: hipLaunchKernelGGL((k_energy_step_fin<5>), dim3(grid), dim3(BLOCK), 0, st, d); break;
     case 7: hipLaunchKernelGGL((k_energy_step_fin<7>), dim3(grid), dim3(BLOCK), 0, st, d); break;
     default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-hipError_t energy_fin(BatchDesc* d, int mode, int nc, int grid, hipStream_t st) {
-  if (mode == 0) {
-    hipLaunchKernelGGL((k_energy_fin<0, 1>), dim3(grid), dim3(BLOCK), 0, st, d);
-  } else {
-    switch (nc) {
-      case 1: hipLaunchKernelGGL((k_energy_fin<1, 1>), dim3(grid), dim3(BLOCK), 0, st, d); break;
-      case 2: hipLaunchKernelGGL((k_energy_fin<1, 2>), dim3(grid), dim3(BLOCK), 0, st, d); break;
-      case 3: hipLaunchKernelGGL((k_energy_fin<1, 3>), dim3(grid), dim3(BLOCK), 0, st, d); break;
-      case 5: hipLaunchKernelGGL((k_energy_fin<1, 5>), dim3(grid), dim3(BLOCK), 0, st, d); break;
-      case 7: hipLaunchKernelGGL((k_energy_fin<1, 7>), dim3(grid), dim3(BLOCK), 0, st, d); break;
-      default: return hipErrorInvalidValue;
-    }
   }
   return hipGetLastError();
 }
@@ -2569,18 +2540,14 @@ hipError_t from_nodes_idx(const float* vbuf, const long long* offs, int n, float
   return hipGetLastError();
 }
 
-hipError_t rigid_energy(BatchDesc* d, int mode, int nc, int grid, hipStream_t st) {
-  if (mode == 0) {
-    hipLaunchKernelGGL((k_rigid_energy<0, 1>), dim3(grid), dim3(BLOCK), 0, st, d);
-  } else {
-    switch (nc) {
-      case 1: hipLaunchKernelGGL((k_rigid_energy<1, 1>), dim3(grid), dim3(BLOCK), 0, st, d); break;
-      case 2: hipLaunchKernelGGL((k_rigid_energy<1, 2>), dim3(grid), dim3(BLOCK), 0, st, d); break;
-      case 3: hipLaunchKernelGGL((k_rigid_energy<1, 3>), dim3(grid), dim3(BLOCK), 0, st, d); break;
-      case 5: hipLaunchKernelGGL((k_rigid_energy<1, 5>), dim3(grid), dim3(BLOCK), 0, st, d); break;
-      case 7: hipLaunchKernelGGL((k_rigid_energy<1, 7>), dim3(grid), dim3(BLOCK), 0, st, d); break;
-      default: return hipErrorInvalidValue;
-    }
+hipError_t rigid_energy_step(BatchDesc* d, int nc, int grid, hipStream_t st) {
+  switch (nc) {
+    case 1: hipLaunchKernelGGL((k_rigid_energy_step<1>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    case 2: hipLaunchKernelGGL((k_rigid_energy_step<2>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    case 3: hipLaunchKernelGGL((k_rigid_energy_step<3>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    case 5: hipLaunchKernelGGL((k_rigid_energy_step<5>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    case 7: hipLaunchKernelGGL((k_rigid_energy_step<7>), dim3(grid), dim3(BLOCK), 0, st, d); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

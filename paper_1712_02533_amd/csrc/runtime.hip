@@ -617,16 +617,17 @@ pprs_status launch_step(pprs_ctx* c, BatchDesc* d, int nc) {
 enum InitKind { INIT_IDENTITY = 0, INIT_COMPOSE = 1, INIT_GIVEN = 2, INIT_PREPARED = 3,
                 INIT_RESUME = 4 };
 
-// One step of the rigid variant: start energies of slots that begin a level, the parameter
-// gradient with its finaliser, one line-search pass (the energy finalisers are shared).
+// One step of the rigid variant: the parameter gradient with its finaliser, then in one launch
+// the start energies of the slots that begin a level and the line-search passes (a slot that
+// begins a level iterates from the next step on, as the plan lists it), and the finaliser the
+// field path uses.
 pprs_status launch_step_rigid(pprs_ctx* c, BatchDesc* d, int nc) {
   TIMED(TK_PLAN, pprs_k::plan(d, c->stream));
-  TIMED(TK_EVAL, pprs_k::rigid_energy(d, 0, 1, c->grid_energy, c->stream));
-  TIMED(TK_FIN, pprs_k::energy_fin(d, 0, 1, kGridFin, c->stream));
   TIMED(TK_GRAD, pprs_k::rigid_grad(d, c->grid_grad, c->stream));
   TIMED(TK_FIN, pprs_k::rigid_grad_fin(d, kGridFin, c->stream));
-  TIMED(TK_LADDER, pprs_k::rigid_energy(d, 1, nc, c->grid_energy, c->stream));
-  TIMED(TK_FIN, pprs_k::energy_fin(d, 1, nc, kGridFin, c->stream));
+  // start energies of the slots that begin a level and the line-search passes, one launch
+  TIMED(TK_LADDER, pprs_k::rigid_energy_step(d, nc, c->grid_energy, c->stream));
+  TIMED(TK_FIN, pprs_k::energy_step_fin(d, nc, kGridFin, c->stream));
   return PPRS_OK;
 }
 
