@@ -328,17 +328,33 @@ __device__ __forceinline__ int kind_items(const BatchDesc* D, int kind, int l) {
 // ------------------------------------------------------------------------------------------
 // Work distribution: workgroup b handles the contiguous item range
 // [b * chunk, min((b+1) * chunk, total)); item -> (list position, local index).
+// XGROUP > 0 (one item per workgroup only): workgroups go to the 8 XCDs in turn, each XCD with
+// its own L2, so items are placed XGROUP consecutive ones to an XCD instead: workgroup
+// b = 8 j + x takes item (j / XGROUP) 8 XGROUP + x XGROUP + j mod XGROUP, a permutation of
+// [0, gridDim.x) when gridDim.x is a multiple of 8 XGROUP. Neighbouring items that read two
+// halves of the same 128-byte lines then fetch them into one L2.
 
 struct ItemCursor {
   int item, end, pos;
 };
 
+template <int XGROUP>
+__device__ __forceinline__ int placed_block(int chunk) {
+  int b = blockIdx.x;
+  if (XGROUP > 0 && chunk == 1 && gridDim.x % (8 * XGROUP) == 0) {
+    int x = b & 7, j = b >> 3;
+    b = (j / XGROUP) * (8 * XGROUP) + x * XGROUP + j % XGROUP;
+  }
+  return b;
+}
+
+template <int XGROUP = 0>
 __device__ bool cursor_begin(const BatchDesc* D, int kind, ItemCursor& c, int* s_pos) {
   const WorkList wl = D->lists[kind];
   int total = wl.total;
   if (total <= 0) return false;
   int chunk = (total + gridDim.x - 1) / gridDim.x;
-  c.item = blockIdx.x * chunk;
+  c.item = placed_block<XGROUP>(chunk) * chunk;
   c.end = min(c.item + chunk, total);
   if (c.item >= c.end) return false;
   if (threadIdx.x == 0) {
@@ -878,7 +894,7 @@ __global__ void __launch_bounds__(BLOCK, LB_ENERGY) k_energy_step(BatchDesc* D) 
   const int total = ne + nl;
   if (total <= 0) return;
   int chunk = (total + gridDim.x - 1) / gridDim.x;
-  int b0 = blockIdx.x * chunk, b1 = min(b0 + chunk, total);
+  int b0 = placed_block<16>(chunk) * chunk, b1 = min(b0 + chunk, total);
   ItemCursor c;
   if (b0 < ne && cursor_range(D, WK_EVAL, b0, min(b1, ne), c, &s_pos)) {
     for (; c.item < c.end; ++c.item) {
@@ -1120,7 +1136,7 @@ __global__ void __launch_bounds__(BLOCK, LB_GRAD) k_grad(BatchDesc* D) {
   const int total = ng + np;
   if (total <= 0) return;
   int chunk = (total + gridDim.x - 1) / gridDim.x;
-  int b0 = blockIdx.x * chunk, b1 = min(b0 + chunk, total);
+  int b0 = placed_block<16>(chunk) * chunk, b1 = min(b0 + chunk, total);
   ItemCursor c;
   if (b0 < ng && cursor_range(D, WK_GRAD, b0, min(b1, ng), c, &s_pos)) {
     for (; c.item < c.end; ++c.item) {
@@ -1433,7 +1449,9 @@ __global__ void __launch_bounds__(BLOCK, DIR ? LB_SMX : LB_SMOOTH) k_smooth(Batc
   __shared__ int s_pos;
   const int kind = DIR ? WK_SMX : WK_SMY;
   ItemCursor c;
-  if (!cursor_begin(D, kind, c, &s_pos)) return;
+  // column strips: a strip of 16 lines reads and writes one half of each 128-byte line, its
+  // neighbour the other half
+  if (!cursor_begin<DIR ? 0 : 16>(D, kind, c, &s_pos)) return;
   for (; c.item < c.end; ++c.item) {
     int s, t;
     cursor_slot(D, kind, c, s, t);
