@@ -462,7 +462,10 @@ def test_series_graph_replay_matches_eager_launches():
 
 def test_launch_shape_does_not_change_results():
     """Grid sizes only spread tiles over workgroups and the gradient tile shape only regroups
-    the same per-node sums: any shape gives the same bits."""
+    the same per-node sums: any shape gives the same bits. The default grids (multiples of 128
+    workgroups, one item each) place 16 consecutive items on one XCD in the gradient, energy
+    and column-solve launches; the odd grids here keep the plain placement, so the comparison
+    also covers that permutation."""
     torch = _torch()
     import paper_1712_02533_amd as P
     s = make_series(SeriesSpec(8, 128, 4.0, 1.0, 10.0, 23))
