@@ -429,9 +429,9 @@ __device__ __forceinline__ void sum_partials(const BatchDesc* D, int s, int kind
 }
 
 // ------------------------------------------------------------------------------------------
-// Planning kernel: one workgroup of 1024 threads.
+// Planning kernel: one workgroup of PLAN_T threads, a slot per thread and round.
 
-#define PLAN_T 256
+#define PLAN_T 512
 #define PLAN_V (2 * WK_COUNT)
 template <int NT>
 struct PlanLds {
