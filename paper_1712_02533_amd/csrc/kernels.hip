@@ -409,9 +409,11 @@ __device__ __forceinline__ double* slot_partial(const BatchDesc* D, int s, int k
 
 // Fixed-order sum of NV columns over n_items partial records; result in thread 0's out[].
 // (Compile-time NV keeps out[] in registers; a record's NV loads are issued together.)
+// partials_local: each thread's share (records threadIdx.x, + BLOCK, ...); sum_partials: that
+// and the block reduction.
 template <int NV>
-__device__ __forceinline__ void sum_partials(const BatchDesc* D, int s, int kind, int n_items,
-                                             double (&out)[NV], double* scratch, bool max_last) {
+__device__ __forceinline__ void partials_local(const BatchDesc* D, int s, int kind, int n_items,
+                                               double (&out)[NV], bool max_last) {
 #pragma unroll
   for (int k = 0; k < NV; ++k) out[k] = 0.0;
   for (int it = threadIdx.x; it < n_items; it += BLOCK) {
@@ -425,6 +427,11 @@ __device__ __forceinline__ void sum_partials(const BatchDesc* D, int s, int kind
       else out[k] += x[k];
     }
   }
+}
+template <int NV>
+__device__ __forceinline__ void sum_partials(const BatchDesc* D, int s, int kind, int n_items,
+                                             double (&out)[NV], double* scratch, bool max_last) {
+  partials_local<NV>(D, s, kind, n_items, out, max_last);
   block_sum<NV>(out, scratch, max_last);
 }
 
@@ -611,15 +618,48 @@ __device__ __forceinline__ void ke_apply(const float u[4], float out[4]) {
 // Per element tile: quadrature sums S1 = sum w T, S2 = sum w T^2, S3 = sum w R~ T for each
 // step size, and the Dirichlet terms u^T K u, d^T K u, d^T K d via element matrices.
 
+// The finaliser's operands in global memory outside the slot's head: the reference's
+// quadrature sum on the level, the slot's node counters, its probe flag and the pass count of
+// its level, and the run's parameters. Thread 0 loads them before the block reduction, so that
+// their latency overlaps it instead of following it load after load (a read after the first
+// store would otherwise wait for it); only the slot's own finaliser writes them within a launch.
+struct FinOperands {
+  double rsum;
+  long long nodes_kind, nodes_prol;
+  int eval_only, passes;
+  double sigma, tau_min_rel, eps;
+  int iter_max, rigid;
+  unsigned char* dlog;
+};
+template <int MODE>
+__device__ __forceinline__ void load_fin_operands(const BatchDesc* D, const SlotState* stp,
+                                                  const SlotState& st, int s, int l,
+                                                  FinOperands& fo) {
+  const int kind = MODE ? WK_LADDER : WK_EVAL;
+  const long long* nc_s = D->node_count + (size_t)s * WK_COUNT;
+  fo.rsum = D->rsum[(size_t)st.ref * PPRS_MAXL + l];
+  fo.nodes_kind = nc_s[kind];
+  fo.nodes_prol = MODE ? 0 : nc_s[WK_PROLONG];
+  fo.eval_only = MODE ? 0 : stp->eval_only;
+  fo.passes = MODE ? stp->passes[st.level - st.coarsest] : 0;
+  fo.sigma = D->sigma;
+  fo.tau_min_rel = D->tau_min_rel;
+  fo.eps = D->eps;
+  fo.iter_max = D->iter_max;
+  fo.rigid = D->rigid;
+  fo.dlog = D->dlog;
+}
+
 // Works on a register copy of the slot's scalar fields (loaded together up front, stored back
 // at the end): every read of global state would otherwise wait behind the previous store.
 template <int MODE, int NC>
 __device__ __forceinline__ void energy_finalize(BatchDesc* D, SlotState* stp, SlotState& st,
                                                 int s, int l, int n, int ph, double top,
-                                                const double (&tot)[3 * NC + 3]) {
+                                                const double (&tot)[3 * NC + 3],
+                                                const FinOperands& fo) {
   const int kind = MODE ? WK_LADDER : WK_EVAL;
   int K = D->ladder_k;
-  double rs = D->rsum[(size_t)st.ref * PPRS_MAXL + l];
+  double rs = fo.rsum;
   double e_j[NC], ncc_j[NC], m_j[NC], sg_j[NC];
   for (int j = 0; j < NC; ++j) {
     double m = tot[3 * j], var = tot[3 * j + 1] - m * m;
@@ -633,8 +673,8 @@ __device__ __forceinline__ void energy_finalize(BatchDesc* D, SlotState* stp, Sl
     sg_j[j] = sg;
   }
   long long* nc_s = D->node_count + (size_t)s * WK_COUNT;
-  nc_s[kind] += (long long)n * n;
-  if (MODE == 0 && ph == PH_PROLONG) nc_s[WK_PROLONG] += (long long)n * n;
+  nc_s[kind] = fo.nodes_kind + (long long)n * n;
+  if (MODE == 0 && ph == PH_PROLONG) nc_s[WK_PROLONG] = fo.nodes_prol + (long long)n * n;
   if (MODE == 0) {
     if (ph == PH_PROLONG) {
       st.level = l;
@@ -650,7 +690,7 @@ __device__ __forceinline__ void energy_finalize(BatchDesc* D, SlotState* stp, Sl
     if (!isfinite(st.E)) {
       st.flags |= FLAG_NAN;
       st.phase = PH_DONE;
-    } else if (D->iter_max <= 0 || stp->eval_only) {
+    } else if (fo.iter_max <= 0 || fo.eval_only) {
       level_done(st);
     } else {
       st.phase = PH_GRAD;
@@ -661,11 +701,12 @@ __device__ __forceinline__ void energy_finalize(BatchDesc* D, SlotState* stp, Sl
     // is not started. Walking the steps in order with that rule gives the same accepted step
     // and group count for any NC (NC is a launch-shape choice).
     const int G = 2 * K + 1;
-    const double tmin = D->tau_min_rel * st.tau_max;
+    const double tmin = fo.tau_min_rel * st.tau_max;
     int li = st.level - st.coarsest;
     int r = st.rung;
     int acc_j = -1;
     bool stop = false;
+    int passes = fo.passes;
     for (int j = 0; j < NC; ++j, ++r) {
       double tj = ldexp(top, -j);
       if (r == G) {
@@ -675,16 +716,17 @@ __device__ __forceinline__ void energy_finalize(BatchDesc* D, SlotState* stp, Sl
           break;
         }
       }
-      if (r == 0) stp->passes[li]++;
-      if (e_j[j] <= st.E - D->sigma * tj * st.gtd) {
+      if (r == 0) passes++;
+      if (e_j[j] <= st.E - fo.sigma * tj * st.gtd) {
         acc_j = j;
         break;
       }
     }
+    if (passes != fo.passes) stp->passes[li] = passes;
     if (acc_j >= 0) {
       double tj = ldexp(top, -acc_j);
       double dec = st.E - e_j[acc_j];
-      if (D->dlog) {
+      if (fo.dlog) {
         // ladder position of the accepted step: tj = top0 2^-J, top0 the iteration's first
         // step (powers of two apart, so the exponents differ by exactly J)
         int pos = st.iter;
@@ -699,7 +741,7 @@ __device__ __forceinline__ void energy_finalize(BatchDesc* D, SlotState* stp, Sl
       st.ncc = ncc_j[acc_j];
       st.mean = m_j[acc_j];
       st.sigma = sg_j[acc_j];
-      if (D->rigid) {
+      if (fo.rigid) {
         for (int k = 0; k < 3; ++k) st.rp[k] -= tj * st.rd[k];  // parameters move at once
       } else {
         st.tau_pend = tj;  // applied to u by the next gradient pass
@@ -707,9 +749,9 @@ __device__ __forceinline__ void energy_finalize(BatchDesc* D, SlotState* stp, Sl
       st.tau_prev = tj;
       st.iter++;
       stp->iters[li] = st.iter;
-      if (dec < D->eps) {
+      if (dec < fo.eps) {
         level_done(st);
-      } else if (st.iter >= D->iter_max) {
+      } else if (st.iter >= fo.iter_max) {
         st.flags |= FLAG_NONCONV;
         level_done(st);
       } else {
@@ -928,13 +970,15 @@ __device__ __forceinline__ void energy_fin_slot(BatchDesc* D, int pos, double* s
   SlotState st;
   load_head(st, *stp);  // in flight with the partial loads
   double tot[NV];
-  sum_partials<NV>(D, s, kind, n_items, tot, s_red, false);
+  partials_local<NV>(D, s, kind, n_items, tot, false);
   const int ph = st.phase;
   bool live = MODE == 0 ? (ph == PH_INIT || ph == PH_PROLONG) : ph == PH_LADDER;
-  if (live && threadIdx.x == 0) {
-    int l = (ph == PH_PROLONG) ? st.level + 1 : st.level;
-    energy_finalize<MODE, NC>(D, stp, st, s, l, lvl_n(l), ph, MODE ? st.top : 0.0, tot);
-  }
+  const int l = (ph == PH_PROLONG) ? st.level + 1 : st.level;
+  FinOperands fo;
+  if (live && threadIdx.x == 0) load_fin_operands<MODE>(D, stp, st, s, l, fo);
+  block_sum<NV>(tot, s_red, false);
+  if (live && threadIdx.x == 0)
+    energy_finalize<MODE, NC>(D, stp, st, s, l, lvl_n(l), ph, MODE ? st.top : 0.0, tot, fo);
   __syncthreads();
 }
 
@@ -1634,14 +1678,29 @@ __global__ void __launch_bounds__(BLOCK) k_smooth_fin(BatchDesc* D) {
     SlotState st;
     load_head(st, *stp);  // in flight with the partial loads
     double tot[2];
-    sum_partials<2>(D, s, WK_SMX, off[pos + 1] - off[pos], tot, s_red, true);
+    partials_local<2>(D, s, WK_SMX, off[pos + 1] - off[pos], tot, true);
+    // the node counters (only this workgroup writes them) and the run's parameters load while
+    // the partials reduce, instead of after the first store
+    long long* nc_s = D->node_count + (size_t)s * WK_COUNT;
+    long long nodes[3];
+    double step_cap, tau_min_rel;
+    int ladder_k, halo;
+    if (threadIdx.x == 0) {
+      nodes[0] = nc_s[WK_GRAD];
+      nodes[1] = nc_s[WK_SMY];
+      nodes[2] = nc_s[WK_SMX];
+      step_cap = D->step_cap;
+      tau_min_rel = D->tau_min_rel;
+      ladder_k = D->ladder_k;
+      halo = D->smooth_halo;
+    }
+    block_sum<2>(tot, s_red, true);
     if (threadIdx.x == 0) {
       int l = st.level;
       int n = lvl_n(l);
-      long long* nc_s = D->node_count + (size_t)s * WK_COUNT;
-      nc_s[WK_GRAD] += (long long)n * n;
-      if (!D->smooth_halo) nc_s[WK_SMY] += (long long)n * n;
-      nc_s[WK_SMX] += (long long)n * n;
+      nc_s[WK_GRAD] = nodes[0] + (long long)n * n;
+      if (!halo) nc_s[WK_SMY] = nodes[1] + (long long)n * n;
+      nc_s[WK_SMX] = nodes[2] + (long long)n * n;
       st.ub ^= 1;          // the gradient kernel wrote u - tau_pend d to the other buffer
       st.tau_pend = 0.0;
       st.gtd = tot[0];
@@ -1650,11 +1709,11 @@ __global__ void __launch_bounds__(BLOCK) k_smooth_fin(BatchDesc* D) {
         level_done(st);
       } else {
         double h = 1.0 / (n - 1);
-        st.tau_max = D->step_cap * h / st.dmax;
-        st.top = fmin(ldexp(st.tau_prev, D->ladder_k), st.tau_max);
+        st.tau_max = step_cap * h / st.dmax;
+        st.top = fmin(ldexp(st.tau_prev, ladder_k), st.tau_max);
         st.rung = 0;
         // a line search whose first step is already below tau_min_rel * tau_max is not begun
-        if (st.top < D->tau_min_rel * st.tau_max) level_done(st);
+        if (st.top < tau_min_rel * st.tau_max) level_done(st);
         else st.phase = PH_LADDER;
       }
       store_head(*stp, st);
